@@ -1,0 +1,182 @@
+/*
+ * rpot -- retarded Lorenz-gauge potentials of many sub-domains on MI355X (gfx950).
+ *
+ * The library evaluates, at every time step l, the induced 4-potential
+ * P = (v, Ax, Ay, Az) on every grid point of every sub-domain from the stored
+ * history of the 4-vector sources S = (q rho, q Jx/c, q Jy/c, q Jz/c) of every
+ * sub-domain (Eq. "4v potential" and its multi-domain sum, Sec. II), as the
+ * discrete lag sum of Eq. "retardation space-time sampled lorentz four vector
+ * potential" (Sec. III):
+ *
+ *   P(r_k, l dt) = sum_n [ P_n(r_k, 0) + sum_{k' in d_n} sum_{m} G_m[k,k'] dS(r_k', (l-m) dt) ]
+ *
+ * with the sampled Green's function G_m[k,k'] = h^3 T(m dt - R/c)/R of Eq.
+ * "retardation space-time sampled green interpolation", T the triangle basis
+ * T(x) = max(0, 1 - |x|/dt), dS = S - S(0), and the lag m restricted to the
+ * window the sub-domain sizes and distances allow (Sec. IV, "Computational
+ * Complexity Analysis").  The spatial sums are zero-padded FFT convolutions,
+ * one per lag and (target, source) pair; the source spectra are kept in a ring
+ * buffer in device memory (the retained history of Sec. IV).
+ *
+ * The component index is opaque to the library: every component of P is the
+ * same functional of the same component of S.
+ *
+ * Conventions shared by every entry point:
+ *  - Every entry point returns rp_status (RP_OK = 0) and never throws.  On
+ *    failure rp_last_error(plan) describes the error (rp_last_error(NULL) for a
+ *    failed rp_plan_domains).
+ *  - Grids: sub-domain n has dims[n] = (Nx, Ny, Nz) points, spacing h shared by
+ *    all sub-domains, and origins[n] = the position (bohr) of its point (0,0,0);
+ *    point (i,j,k) sits at origin + h (i,j,k).  Arrays are [4][Nx][Ny][Nz],
+ *    z fastest, component-major.
+ *  - Sub-domains must not overlap: two sub-domains of one system closer than one
+ *    grid cell (minimal point distance < h) give RP_ERR_GEOMETRY (Sec. III:
+ *    the method assumes non-overlapping sub-domains).
+ *  - Steps are 0, 1, 2, ... consecutively.  rp_push_sources(l) must precede
+ *    rp_retarded_step(l); anything else gives RP_ERR_STATE.
+ *  - All device work is enqueued asynchronously on the plan's HIP stream; the
+ *    step path makes no host synchronisation.
+ *  - Ownership: the caller owns every device buffer it passes (sources,
+ *    outputs, the bound workspace) and keeps the workspace alive until
+ *    rp_plan_destroy.  The library owns only its small host-side plan and never
+ *    frees caller memory.  Sources are read before the enqueued work of the
+ *    call completes; the caller may reuse them once that work has completed.
+ *  - A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef RPOT_H
+#define RPOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rp_plan_s *rp_plan;
+
+typedef enum {
+    RP_OK = 0,
+    RP_ERR_ARG = 1,         /* bad argument (null pointer, size, enum)            */
+    RP_ERR_GEOMETRY = 2,    /* overlapping or touching sub-domains                */
+    RP_ERR_NOMEM = 3,       /* workspace too small / host allocation failed       */
+    RP_ERR_STATE = 4,       /* call out of order (step sequence, unbound plan)    */
+    RP_ERR_DEVICE = 5,      /* a HIP call failed                                  */
+    RP_ERR_UNSUPPORTED = 6  /* valid request outside what this build supports     */
+} rp_status;
+
+typedef enum {
+    RP_FP64 = 0,            /* FP64 sources, FFTs, history and accumulation        */
+    RP_FP32 = 1,            /* FP32 sources, FFTs, history and accumulation        */
+    RP_FP32_RING_FP16 = 2,  /* FP32, history spectra stored as scaled FP16          */
+    RP_FP32_RING_BF16 = 3   /* FP32, history spectra stored as scaled BF16          */
+} rp_precision;
+
+/*
+ * Plan the multi-domain evaluation (host only; makes no HIP call).
+ *
+ * n_dom      number of sub-domains (>= 1).
+ * dims       [n_dom][3] grid points per axis (each >= 1).
+ * origins    [n_dom][3] position of grid point (0,0,0), bohr.
+ * system_id  [n_dom] or NULL.  Sub-domains with different ids are independent
+ *            systems batched in one plan: no pair across systems is formed.
+ *            NULL puts every sub-domain in one system.
+ * h, dt, c   grid step, time step and speed of light (atomic units); c may be
+ *            +INFINITY (instantaneous Coulomb coupling, the Hartree limit).
+ * prec       arithmetic and history storage (rp_precision).
+ * hip_stream hipStream_t on which every device call of this plan is enqueued;
+ *            NULL is the null stream.
+ *
+ * For every ordered pair (s <- n) of one system the lag window is
+ * [floor(Rmin/(c dt)), ceil(Rmax/(c dt))] with Rmin/Rmax the smallest/largest
+ * distance between their grid points (Sec. IV: only lags allowed by the
+ * sub-domain sizes and distances contribute); the ring of source n keeps
+ * max_s ceil(Rmax(s,n)/(c dt)) + 1 past spectra.
+ * The self cell needs h sqrt(3)/2 < c dt (RP_ERR_UNSUPPORTED otherwise).
+ */
+rp_status rp_plan_domains(rp_plan *out, int32_t n_dom, const int32_t *dims,
+                          const double *origins, const int32_t *system_id,
+                          double h, double dt, double c, rp_precision prec,
+                          void *hip_stream);
+
+/* Device workspace the plan needs, in bytes (host only). */
+rp_status rp_workspace_bytes(rp_plan plan, size_t *bytes);
+
+/*
+ * Bind caller-allocated device memory of at least rp_workspace_bytes bytes
+ * (256-byte aligned).  Uploads the plan's tables, zeroes the history and
+ * resets the step sequence to 0.  May synchronise the stream.
+ */
+rp_status rp_bind_workspace(rp_plan plan, void *dev_ptr, size_t bytes);
+
+/*
+ * Generate the sampled Green's-function spectra of every (target, source, lag)
+ * triple in FP64 (Eq. "retardation space-time sampled green interpolation",
+ * with h^3 as the quadrature weight and the exact self-cell integral for the
+ * singular point, whose treatment the paper delegates to a smoothed Green's
+ * function) and store them in the plan's precision.  Synchronises the stream.
+ */
+rp_status rp_set_green_kernels(rp_plan plan);
+
+/*
+ * Ingest the sources of step `step` for every sub-domain.
+ * src[n] is a device pointer to [4][Nx][Ny][Nz] values, double for RP_FP64 and
+ * float otherwise.  Step 0 is the ground state S(0): it is kept, and the static
+ * potential P(0) (the ground-state term of Eq. "multi domain TDCDFT lorenz
+ * space-time sampled simplify 1") is computed from it in FP64.  A step l >= 1
+ * stores the spectrum of dS(l) = S(l) - S(0) in the history ring.
+ */
+rp_status rp_push_sources(rp_plan plan, int64_t step, const void *const *src);
+
+/*
+ * Evaluate P at step `step` on every sub-domain.  out[n] is a device pointer to
+ * [4][Nx][Ny][Nz] values (same type as the sources) that receives
+ * (v, Ax, Ay, Az) = P(0) + the lag sum over every source sub-domain.
+ */
+rp_status rp_retarded_step(rp_plan plan, int64_t step, void *const *out);
+
+/*
+ * Planned window of the ordered pair (target s <- source n): lags [m_lo, m_hi]
+ * (-1, -1 if the pair is not formed), the FFT pad of their system, and the ring
+ * depth of source n.  Any output pointer may be NULL.
+ */
+rp_status rp_plan_info(rp_plan plan, int32_t s, int32_t n, int32_t *m_lo,
+                       int32_t *m_hi, int32_t pad[3], int32_t *depth);
+
+/* Counts and per-step byte figures of a plan (for reporting). */
+typedef struct {
+    int64_t n_triples;        /* (target, source, lag) triples per step            */
+    int64_t n_spectra;        /* stored Green spectra (reversed pairs share one)   */
+    int64_t n_entries;        /* (source, lag) ring reads per step                 */
+    int64_t points;           /* target grid points (updates per step)             */
+    double lagsum_bytes;      /* minimal HBM bytes of one lag-sum launch           */
+    double ring_bytes;        /* history ring                                      */
+    double spectra_bytes;     /* Green spectra                                     */
+    double fft_bytes_fwd;     /* minimal bytes of the forward FFT passes per step  */
+    double fft_bytes_inv;     /* minimal bytes of the inverse FFT passes per step  */
+} rp_stats;
+
+rp_status rp_plan_stats(rp_plan plan, rp_stats *out);
+
+/*
+ * Profiling of the lag-sum launch (reporting only).  While enabled, every
+ * rp_retarded_step brackets its lag-sum kernel with HIP events recorded on the
+ * plan's stream.  rp_lagsum_time waits for the last recorded event, returns the
+ * summed kernel time (ms) and the number of launches recorded since the last
+ * query, and starts a new count.
+ */
+rp_status rp_profile_lagsum(rp_plan plan, int32_t enable);
+rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
+
+/* Release the host plan (the workspace stays the caller's). */
+rp_status rp_plan_destroy(rp_plan plan);
+
+/* Description of the last error of `plan` (or of the last failed plan creation
+ * when plan is NULL).  The string lives until the next call on the plan. */
+const char *rp_last_error(rp_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPOT_H */

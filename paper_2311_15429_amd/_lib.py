@@ -1,0 +1,71 @@
+"""ctypes declarations of the C-ABI in include/rpot.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librpot.so")
+
+RP_OK = 0
+STATUS = {0: "RP_OK", 1: "RP_ERR_ARG", 2: "RP_ERR_GEOMETRY", 3: "RP_ERR_NOMEM",
+          4: "RP_ERR_STATE", 5: "RP_ERR_DEVICE", 6: "RP_ERR_UNSUPPORTED"}
+PRECISION = {"fp64": 0, "fp32": 1, "fp32_ring_fp16": 2, "fp32_ring_bf16": 3}
+
+EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_set_green_kernels",
+           "rp_push_sources", "rp_retarded_step", "rp_plan_info", "rp_plan_stats",
+           "rp_profile_lagsum", "rp_lagsum_time", "rp_plan_destroy", "rp_last_error"]
+
+
+class RpotError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class RpStats(ctypes.Structure):
+    _fields_ = [("n_triples", ctypes.c_int64), ("n_spectra", ctypes.c_int64),
+                ("n_entries", ctypes.c_int64), ("points", ctypes.c_int64),
+                ("lagsum_bytes", ctypes.c_double), ("ring_bytes", ctypes.c_double),
+                ("spectra_bytes", ctypes.c_double), ("fft_bytes_fwd", ctypes.c_double),
+                ("fft_bytes_inv", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def load():
+    """Load librpot.so; raise if it has not been built (there is no fallback)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2311_15429_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    P = ctypes.POINTER
+    lib.rp_plan_domains.argtypes = [P(vp), i32, P(i32), P(ctypes.c_double), P(i32), ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_int, vp]
+    lib.rp_workspace_bytes.argtypes = [vp, P(sz)]
+    lib.rp_bind_workspace.argtypes = [vp, vp, sz]
+    lib.rp_set_green_kernels.argtypes = [vp]
+    lib.rp_push_sources.argtypes = [vp, i64, P(vp)]
+    lib.rp_retarded_step.argtypes = [vp, i64, P(vp)]
+    lib.rp_plan_info.argtypes = [vp, i32, i32, P(i32), P(i32), P(i32), P(i32)]
+    lib.rp_plan_stats.argtypes = [vp, P(RpStats)]
+    lib.rp_profile_lagsum.argtypes = [vp, i32]
+    lib.rp_lagsum_time.argtypes = [vp, P(ctypes.c_double), P(i64)]
+    lib.rp_plan_destroy.argtypes = [vp]
+    lib.rp_last_error.argtypes = [vp]
+    lib.rp_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS[:-1]:
+        getattr(lib, name).restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def check(lib, plan, code):
+    if code != RP_OK:
+        msg = lib.rp_last_error(plan)
+        raise RpotError(code, msg.decode() if msg else "")

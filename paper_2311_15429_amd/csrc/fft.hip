@@ -1,0 +1,470 @@
+// LDS-staged mixed-radix (4, 2, 3) FFT passes for gfx950.
+//
+// The 3-D transforms of the method (Sec. IV: a 3-D FFT of every time slice of
+// the zero-padded sources, and the inverse on the target domain) are split into
+// one pass per axis.  A pass block stages a tile of whole lines in LDS, runs a
+// self-sorting (Stockham) FFT over all of them in place, and writes back; the
+// tile is read and written along the contiguous direction of global memory.
+// Zero padding is pruned on input (only n_in points are read) and the crop on
+// output (only n_out points are written).  Intermediate 3-D arrays keep the
+// four components interleaved ([..][4]) so every pass moves 32/64-byte runs.
+#include "rpot_internal.hpp"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+namespace rpot {
+
+template <typename T>
+struct Lds;
+template <>
+struct Lds<float> {
+    static constexpr int E = 4096;   // complex elements staged per block (32 KiB)
+};
+template <>
+struct Lds<double> {
+    static constexpr int E = 2048;   // 32 KiB
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+// multiply by sgn * i
+template <typename T>
+__device__ __forceinline__ Cx<T> mul_i(Cx<T> a, int sgn) {
+    return sgn > 0 ? Cx<T>{-a.y, a.x} : Cx<T>{a.y, -a.x};
+}
+
+// In-place FFT of L lines of length P held in LDS (row-major [L][P]).
+// dir = -1: sum_j x_j exp(-2 pi i jk/P);  dir = +1: exp(+2 pi i jk/P).
+template <typename T, int NT, int BMAX>
+__device__ void lds_fft(Cx<T> *buf, int P, int L, int dir, const Cx<T> *__restrict__ tw,
+                        const RadixPlan &rp) {
+    const int tid = threadIdx.x;
+    int p = 1;
+    for (int st = 0; st < rp.n; ++st) {
+        const int R = rp.r[st];
+        const int nq = P / R;
+        const int nbf = L * nq;
+        const int tws = P / (p * R);
+        Cx<T> v[BMAX][4];
+#pragma unroll
+        for (int it = 0; it < BMAX; ++it) {
+            const int b = tid + it * NT;
+            if (b < nbf) {
+                const int li = b / nq;
+                const int i = b - li * nq;
+                const int k = i % p;
+                const Cx<T> *row = buf + li * P;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r < R) v[it][r] = row[i + r * nq];
+#pragma unroll
+                for (int r = 1; r < 4; ++r) {
+                    if (r < R && k != 0) {
+                        Cx<T> w = tw[r * k * tws];
+                        if (dir > 0) w.y = -w.y;
+                        v[it][r] = cmul(v[it][r], w);
+                    }
+                }
+                if (R == 4) {
+                    const Cx<T> t0 = cadd(v[it][0], v[it][2]);
+                    const Cx<T> t1 = csub(v[it][0], v[it][2]);
+                    const Cx<T> t2 = cadd(v[it][1], v[it][3]);
+                    const Cx<T> t3 = mul_i(csub(v[it][1], v[it][3]), dir);
+                    v[it][0] = cadd(t0, t2);
+                    v[it][2] = csub(t0, t2);
+                    v[it][1] = cadd(t1, t3);
+                    v[it][3] = csub(t1, t3);
+                } else if (R == 2) {
+                    const Cx<T> t0 = v[it][0];
+                    v[it][0] = cadd(t0, v[it][1]);
+                    v[it][1] = csub(t0, v[it][1]);
+                } else {  // R == 3
+                    const T s3 = T(0.86602540378443864676372317075294);
+                    const Cx<T> s = cadd(v[it][1], v[it][2]);
+                    const Cx<T> d = csub(v[it][1], v[it][2]);
+                    const Cx<T> m = {v[it][0].x - T(0.5) * s.x, v[it][0].y - T(0.5) * s.y};
+                    const Cx<T> e = mul_i(Cx<T>{s3 * d.x, s3 * d.y}, dir);
+                    v[it][0] = cadd(v[it][0], s);
+                    v[it][1] = cadd(m, e);
+                    v[it][2] = csub(m, e);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < BMAX; ++it) {
+            const int b = tid + it * NT;
+            if (b < nbf) {
+                const int li = b / nq;
+                const int i = b - li * nq;
+                const int k = i % p;
+                const int j = (i - k) * R + k;
+                Cx<T> *row = buf + li * P;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r < R) row[j + r * p] = v[it][r];
+            }
+        }
+        __syncthreads();
+        p *= R;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Output conversion for the generic pass.
+template <typename T, int FMT>
+struct Store;
+template <typename T>
+struct Store<T, RING_F64> {
+    __device__ static void put(void *base, int64_t idx, Cx<T> v, float) {
+        reinterpret_cast<Cx<double> *>(base)[idx] = Cx<double>{double(v.x), double(v.y)};
+    }
+};
+template <typename T>
+struct Store<T, RING_F32> {
+    __device__ static void put(void *base, int64_t idx, Cx<T> v, float) {
+        reinterpret_cast<Cx<float> *>(base)[idx] = Cx<float>{float(v.x), float(v.y)};
+    }
+};
+template <typename T>
+struct Store<T, RING_F16> {
+    __device__ static void put(void *base, int64_t idx, Cx<T> v, float inv_scale) {
+        reinterpret_cast<__half2 *>(base)[idx] =
+            __halves2half2(__float2half_rn(float(v.x) * inv_scale), __float2half_rn(float(v.y) * inv_scale));
+    }
+};
+template <typename T>
+struct Store<T, RING_BF16> {
+    __device__ static void put(void *base, int64_t idx, Cx<T> v, float inv_scale) {
+        __hip_bfloat162 r;
+        r.x = __float2bfloat16(float(v.x) * inv_scale);
+        r.y = __float2bfloat16(float(v.y) * inv_scale);
+        reinterpret_cast<__hip_bfloat162 *>(base)[idx] = r;
+    }
+};
+
+template <typename T, int FMT>
+__global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
+    constexpr int E = Lds<T>::E;
+    constexpr int NT = kFftThreads;
+    constexpr int BMAX = (E / 2 + NT - 1) / NT;
+    __shared__ Cx<T> buf[E];
+    const LineJob &job = a.jobs[blockIdx.y];
+    const int P = a.P;
+    const int L = E / P;
+    const int line0 = blockIdx.x * L;
+    const int nl = min(L, a.lines - line0);
+    const Cx<T> *__restrict__ in = reinterpret_cast<const Cx<T> *>(job.in);
+
+    const bool jfast_in = (a.in_j == 1);
+    for (int e = threadIdx.x; e < L * P; e += NT) {
+        int li, j;
+        if (jfast_in) {
+            li = e / P;
+            j = e - li * P;
+        } else {
+            j = e / L;
+            li = e - j * L;
+        }
+        Cx<T> v = {T(0), T(0)};
+        if (li < nl && j < a.n_in) {
+            const int line = line0 + li;
+            const int outer = line / a.n_inner;
+            const int inner = line - outer * a.n_inner;
+            v = in[outer * a.in_outer + inner * a.in_inner + int64_t(j) * a.in_j];
+        }
+        buf[li * P + j] = v;
+    }
+    __syncthreads();
+    lds_fft<T, NT, BMAX>(buf, P, L, a.dir, reinterpret_cast<const Cx<T> *>(a.tw), a.rp);
+
+    void *obase = job.out;
+    const float *qs = job.qscale;
+    if (a.step) {
+        const int64_t slot = (*a.step) % job.depth;
+        if (job.slot_stride) {
+            constexpr int esz = (FMT == RING_F64) ? 16 : ((FMT == RING_F32) ? 8 : 4);
+            obase = reinterpret_cast<char *>(obase) + slot * job.slot_stride * esz;
+        }
+        if (qs) qs += slot * 4;
+    }
+    const bool jfast_out = (a.out_j == 1);
+    const int nout = a.n_out;
+    for (int e = threadIdx.x; e < L * nout; e += NT) {
+        int li, j;
+        if (jfast_out) {
+            li = e / nout;
+            j = e - li * nout;
+        } else {
+            j = e / L;
+            li = e - j * L;
+        }
+        if (li < nl) {
+            const int line = line0 + li;
+            const int outer = line / a.n_inner;
+            const int inner = line - outer * a.n_inner;
+            float inv_scale = 1.0f;
+            // the component is the fastest batch index (inner mod 4)
+            if (FMT == RING_F16 || FMT == RING_BF16) inv_scale = 1.0f / qs[inner & 3];
+            Store<T, FMT>::put(obase, outer * a.out_outer + inner * a.out_inner + int64_t(j) * a.out_j,
+                               buf[li * P + j], inv_scale);
+        }
+    }
+}
+
+void launch_line_pass(const LinePass &a, int prec64, hipStream_t st) {
+    const int E = prec64 ? Lds<double>::E : Lds<float>::E;
+    const int L = E / a.P;
+    dim3 grid((a.lines + L - 1) / L, a.n_jobs);
+    if (prec64) {
+        if (a.out_fmt == RING_F64)
+            hipLaunchKernelGGL((k_line_pass<double, RING_F64>), grid, dim3(kFftThreads), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_line_pass<double, RING_F32>), grid, dim3(kFftThreads), 0, st, a);
+    } else {
+        switch (a.out_fmt) {
+        case RING_F64:
+            hipLaunchKernelGGL((k_line_pass<float, RING_F64>), grid, dim3(kFftThreads), 0, st, a);
+            break;
+        case RING_F16:
+            hipLaunchKernelGGL((k_line_pass<float, RING_F16>), grid, dim3(kFftThreads), 0, st, a);
+            break;
+        case RING_BF16:
+            hipLaunchKernelGGL((k_line_pass<float, RING_BF16>), grid, dim3(kFftThreads), 0, st, a);
+            break;
+        default:
+            hipLaunchKernelGGL((k_line_pass<float, RING_F32>), grid, dim3(kFftThreads), 0, st, a);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Complex lines per block of the z passes: a multiple of 4 (the four
+// components of a position pair).
+template <typename T>
+__host__ __device__ inline int zfwd_lpb(int P) { return (Lds<T>::E / P) & ~3; }
+
+// Sampled Green's function of one lag (modes 1 and 2 of ZFwd), FP64.
+__device__ __forceinline__ int kernel_disp(int q, int P, int Ns, int Nn, bool &valid) {
+    if (q < Ns) return q;
+    if (q > P - Nn) return q - P;
+    valid = false;
+    return 0;
+}
+
+__device__ __forceinline__ double green_value(const ZFwd &a, const ZFwdJob &job, int qx, int qy, int qz) {
+    bool valid = true;
+    const int dx = kernel_disp(qx, a.Px, job.Ns[0], job.Nn[0], valid);
+    const int dy = kernel_disp(qy, a.Py, job.Ns[1], job.Nn[1], valid);
+    const int dz = kernel_disp(qz, a.Pz, job.Ns[2], job.Nn[2], valid);
+    if (!valid) return 0.0;
+    if (job.self && dx == 0 && dy == 0 && dz == 0) {
+        if (a.mode == 2) return a.w_static * a.scale;
+        return (job.m == 0 ? a.w_self0 : (job.m == 1 ? a.w_self1 : 0.0)) * a.scale;
+    }
+    const double X = job.off[0] + a.h * dx;
+    const double Y = job.off[1] + a.h * dy;
+    const double Z = job.off[2] + a.h * dz;
+    const double R = sqrt(X * X + Y * Y + Z * Z);
+    const double h3 = a.h * a.h * a.h;
+    if (a.mode == 2) return h3 / R * a.scale;
+    // T(m dt - R/c) with T(x) = max(0, 1 - |x|/dt), in units of dt
+    const double x = double(job.m) - R * a.inv_cdt;
+    const double tv = 1.0 - fabs(x);
+    return tv > 0.0 ? h3 * tv / R * a.scale : 0.0;
+}
+
+// Two real lines of the SAME component are packed into one complex line
+// (neighbouring (x, y) positions for sources, neighbouring y for the Green's
+// function), so the rounding crosstalk of the packing never mixes the large
+// scalar-potential source into the much smaller vector-potential ones.
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
+    constexpr int E = Lds<T>::E;
+    constexpr int NT = kFftThreads;
+    constexpr int BMAX = (E / 2 + NT - 1) / NT;
+    __shared__ Cx<T> buf[E];
+    __shared__ float red[4][NT / 64];
+    const ZFwdJob &job = a.jobs[blockIdx.y];
+    const int P = a.Pz;
+    const int L = zfwd_lpb<T>(P);
+    const int line0 = blockIdx.x * L;
+    const int npos = a.Nx * a.Ny;
+    const int nlines = (a.mode == 0) ? 4 * ((npos + 1) / 2) : a.Px * (a.Py / 2);
+    const int nl = min(L, nlines - line0);
+
+    float mx[4] = {0.f, 0.f, 0.f, 0.f};
+    if (a.mode == 0) {
+        // complex line c = pair * 4 + mu holds positions 2 pair (re) and 2 pair + 1 (im)
+        const T *__restrict__ S = reinterpret_cast<const T *>(job.src);
+        const T *__restrict__ S0 = reinterpret_cast<const T *>(job.s0);
+        const int64_t npts = int64_t(npos) * a.Nz;
+        for (int e = threadIdx.x; e < L * P; e += NT) {
+            const int li = e / P;
+            const int z = e - li * P;
+            Cx<T> v = {T(0), T(0)};
+            if (li < nl && z < a.Nz) {
+                const int c = line0 + li;
+                const int mu = c & 3;
+                const int pa = (c >> 2) * 2;
+                const int64_t oa = mu * npts + int64_t(pa) * a.Nz + z;
+                v.x = S0 ? S[oa] - S0[oa] : S[oa];
+                if (pa + 1 < npos) {
+                    const int64_t ob = oa + a.Nz;
+                    v.y = S0 ? S[ob] - S0[ob] : S[ob];
+                }
+                mx[mu] = fmaxf(mx[mu], fmaxf(fabsf(float(v.x)), fabsf(float(v.y))));
+            }
+            buf[li * P + z] = v;
+        }
+    } else {
+        for (int e = threadIdx.x; e < L * P; e += NT) {
+            const int li = e / P;
+            const int z = e - li * P;
+            Cx<T> v = {T(0), T(0)};
+            if (li < nl) {
+                const int line = line0 + li;
+                const int qx = line / (a.Py / 2);
+                const int qy = 2 * (line - qx * (a.Py / 2));
+                v.x = T(green_value(a, job, qx, qy, z));
+                v.y = T(green_value(a, job, qx, qy + 1, z));
+            }
+            buf[li * P + z] = v;
+        }
+    }
+    if (a.mode == 0 && job.zmax) {
+        for (int c = 0; c < 4; ++c) {
+            float v = mx[c];
+            for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+            if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = v;
+        }
+    }
+    __syncthreads();
+    if (a.mode == 0 && job.zmax && threadIdx.x < 4) {
+        float v = 0.f;
+        for (int w = 0; w < NT / 64; ++w) v = fmaxf(v, red[threadIdx.x][w]);
+        job.zmax[blockIdx.x * 4 + threadIdx.x] = v;
+    }
+    lds_fft<T, NT, BMAX>(buf, P, L, -1, reinterpret_cast<const Cx<T> *>(a.tw), a.rp);
+
+    // unpack: X_re = (Z_k + conj Z_-k)/2,  X_im = (Z_k - conj Z_-k)/(2i)
+    const int Hz = a.Hz;
+    Cx<T> *__restrict__ out = reinterpret_cast<Cx<T> *>(job.out);
+    if (a.mode == 0) {
+        const int pos0 = (line0 >> 2) * 2;
+        const int np = min(2 * ((nl + 3) >> 2), npos - pos0);
+        for (int e = threadIdx.x; e < np * Hz * 4; e += NT) {
+            const int mu = e & 3;
+            const int k = (e >> 2) % Hz;
+            const int pl = (e >> 2) / Hz;
+            const int li = (pl >> 1) * 4 + mu;
+            const Cx<T> zk = buf[li * P + k];
+            const Cx<T> zm = buf[li * P + ((P - k) % P)];
+            Cx<T> r;
+            if ((pl & 1) == 0) r = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+            else r = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+            out[(int64_t(pos0 + pl) * Hz + k) * 4 + mu] = r;
+        }
+    } else {
+        for (int e = threadIdx.x; e < 2 * nl * Hz; e += NT) {
+            const int k = e % Hz;
+            const int rl = e / Hz;
+            const int li = rl >> 1;
+            const Cx<T> zk = buf[li * P + k];
+            const Cx<T> zm = buf[li * P + ((P - k) % P)];
+            Cx<T> r;
+            if ((rl & 1) == 0) r = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+            else r = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
+            out[int64_t(2 * line0 + rl) * Hz + k] = r;
+        }
+    }
+}
+
+int zfwd_lines_per_block(int Pz, int prec64) {
+    return prec64 ? zfwd_lpb<double>(Pz) : zfwd_lpb<float>(Pz);
+}
+
+void launch_zfwd(const ZFwd &a, int prec64, hipStream_t st) {
+    const int L = zfwd_lines_per_block(a.Pz, prec64);
+    const int nlines = (a.mode == 0) ? 4 * ((a.Nx * a.Ny + 1) / 2) : a.Px * (a.Py / 2);
+    dim3 grid((nlines + L - 1) / L, a.n_jobs);
+    if (prec64) hipLaunchKernelGGL(k_zfwd<double>, grid, dim3(kFftThreads), 0, st, a);
+    else hipLaunchKernelGGL(k_zfwd<float>, grid, dim3(kFftThreads), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// Complex-to-real z pass with crop and static add.  Complex line
+// c = pair * 4 + mu carries positions 2 pair (real part) and 2 pair + 1
+// (imaginary part) of component mu.
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
+    constexpr int E = Lds<T>::E;
+    constexpr int NT = kFftThreads;
+    constexpr int BMAX = (E / 2 + NT - 1) / NT;
+    __shared__ Cx<T> buf[E];
+    const ZInvJob &job = a.jobs[blockIdx.y];
+    const int P = a.Pz;
+    const int Hz = a.Hz;
+    const int L = zfwd_lpb<T>(P);
+    const int line0 = blockIdx.x * L;
+    const int npos = a.Nx * a.Ny;
+    const int nlines = 4 * ((npos + 1) / 2);
+    const int nl = min(L, nlines - line0);
+    const Cx<T> *__restrict__ in = reinterpret_cast<const Cx<T> *>(job.in);
+    const int pos0 = (line0 >> 2) * 2;
+
+    // Z_k = X_a(k) + i X_b(k) and Z_{P-k} = conj X_a(k) + i conj X_b(k)
+    for (int e = threadIdx.x; e < (L / 4) * Hz * 4; e += NT) {
+        const int mu = e & 3;
+        const int k = (e >> 2) % Hz;
+        const int ppl = (e >> 2) / Hz;
+        const int li = ppl * 4 + mu;
+        Cx<T> xa = {T(0), T(0)}, xb = {T(0), T(0)};
+        if (li < nl) {
+            const int pa = pos0 + 2 * ppl;
+            xa = in[(int64_t(pa) * Hz + k) * 4 + mu];
+            if (pa + 1 < npos) xb = in[(int64_t(pa + 1) * Hz + k) * 4 + mu];
+        }
+        if (k == 0 || 2 * k == P) {
+            buf[li * P + k] = Cx<T>{xa.x, xb.x};
+        } else {
+            buf[li * P + k] = Cx<T>{xa.x - xb.y, xa.y + xb.x};
+            buf[li * P + (P - k)] = Cx<T>{xa.x + xb.y, xb.x - xa.y};
+        }
+    }
+    __syncthreads();
+    lds_fft<T, NT, BMAX>(buf, P, L, +1, reinterpret_cast<const Cx<T> *>(a.tw), a.rp);
+
+    T *__restrict__ out = reinterpret_cast<T *>(job.out);
+    const T *__restrict__ add = reinterpret_cast<const T *>(job.add);
+    const int np = min(2 * ((nl + 3) >> 2), npos - pos0);
+    const int64_t npts = int64_t(npos) * a.Nz;
+    for (int e = threadIdx.x; e < 4 * np * a.Nz; e += NT) {
+        const int z = e % a.Nz;
+        const int r = e / a.Nz;
+        const int pl = r % np;
+        const int mu = r / np;
+        const Cx<T> v = buf[((pl >> 1) * 4 + mu) * P + z];
+        const int64_t o = mu * npts + int64_t(pos0 + pl) * a.Nz + z;
+        T val = (pl & 1) ? v.y : v.x;
+        if (add) val += add[o];
+        out[o] = val;
+    }
+}
+
+void launch_zinv(const ZInv &a, int prec64, hipStream_t st) {
+    const int L = zfwd_lines_per_block(a.Pz, prec64);
+    const int nlines = 4 * ((a.Nx * a.Ny + 1) / 2);
+    dim3 grid((nlines + L - 1) / L, a.n_jobs);
+    if (prec64) hipLaunchKernelGGL(k_zinv<double>, grid, dim3(kFftThreads), 0, st, a);
+    else hipLaunchKernelGGL(k_zinv<float>, grid, dim3(kFftThreads), 0, st, a);
+}
+
+}  // namespace rpot

@@ -1,0 +1,1035 @@
+// Host runtime: planning (lag windows, FFT pads, ring depths, Green-spectrum
+// table, lag-sum schedule), workspace layout, and the C-ABI entry points.
+//
+// The plan follows the paper's multi-domain scheme (Secs. II-IV): every
+// ordered pair (target s <- source n) of one system couples through the lags
+// its point distances allow; each source keeps the spectra of its past
+// source differences in a ring as deep as its longest lag; a step is the
+// forward transform of the new sources, the lag sum in the frequency domain,
+// and the inverse transform cropped to each target.
+#include "rpot.h"
+#include "rpot_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace rpot;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Error {
+    rp_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(rp_status c, const std::string &m) { throw Error{c, m}; }
+
+#define HIP_OK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) fail(RP_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kGroupMax = 8;      // targets per lag-sum thread
+constexpr int kK2Tile = 256;      // frequencies per lag-sum block
+constexpr int kGreenChunk = kMaxJobs;
+constexpr int kMaxPad = 512;     // z passes stage >= 4 lines of the pad in 32 KiB of LDS
+constexpr size_t kAlign = 256;
+
+// Smallest even 2^a 3^b >= n.
+int smooth_even(int n) {
+    for (int m = std::max(n, 2);; ++m) {
+        if (m & 1) continue;
+        int r = m;
+        while (r % 2 == 0) r /= 2;
+        while (r % 3 == 0) r /= 3;
+        if (r == 1) return m;
+    }
+}
+
+RadixPlan make_radix(int P) {
+    RadixPlan rp{};
+    int n = P;
+    while (n % 4 == 0) { rp.r[rp.n++] = 4; n /= 4; }
+    while (n % 2 == 0) { rp.r[rp.n++] = 2; n /= 2; }
+    while (n % 3 == 0) { rp.r[rp.n++] = 3; n /= 3; }
+    if (n != 1) fail(RP_ERR_UNSUPPORTED, "FFT length is not 2^a 3^b");
+    return rp;
+}
+
+struct DomainP {
+    int N[3];
+    double o[3];
+    int sys;
+    int64_t npts;
+    int depth = 1;
+    int zblocks = 0;
+    size_t off_ring = 0, off_scales = 0, off_zmax = 0, off_s0 = 0, off_p0 = 0, off_acc = 0;
+    size_t off_t1 = 0, off_t2 = 0, off_s0hat = 0;
+};
+
+struct SystemP {
+    std::vector<int> doms;
+    int P[3];
+    int Hz;
+    int64_t C;
+    int64_t spec_base = 0;   // complex elements
+    int64_t n_spec = 0;
+};
+
+struct PairP {
+    int m_lo = -1, m_hi = -1;
+    double rmin = 0, rmax = 0;
+    int64_t spec0 = -1;      // spectrum index (within the system) of lag m_lo
+    bool conj = false;
+};
+
+struct ClassP {
+    int N[3];
+    int P[3];
+    int Hz;
+    int64_t C;
+    std::vector<int> doms;
+};
+
+}  // namespace
+
+struct rp_plan_s {
+    int n_dom = 0;
+    double h = 0, dt = 0, c = 0;
+    rp_precision prec = RP_FP64;
+    hipStream_t stream = nullptr;
+    bool p64 = true;
+    int ring_fmt = RING_F64;
+    size_t tsz = 8, csz = 16, ring_esz = 16, spec_csz = 16;
+    double w_self0 = 0, w_self1 = 0, w_static = 0;
+
+    std::vector<DomainP> dom;
+    std::vector<SystemP> sys;
+    std::vector<PairP> pair;   // [s * n_dom + n]
+    std::vector<ClassP> cls;
+
+    std::vector<K2Group> groups;
+    std::vector<K2Entry> entries;
+    std::vector<K2Item> items;
+    std::vector<DomDev> domdev;
+    int tg = 1;
+
+    std::map<int, size_t> tw64, tw32;   // FFT length -> byte offset of its twiddles
+    size_t off_state = 0, off_items = 0, off_groups = 0, off_entries = 0, off_domdev = 0;
+    size_t off_spec = 0, off_gtmp = 0, off_accd = 0, off_gstat = 0, off_t1d = 0, off_t2d = 0;
+    size_t off_s0d = 0, off_p0d = 0;
+    size_t ws_bytes = 0;
+    char *ws = nullptr;
+
+    bool profile = false;
+    std::vector<hipEvent_t> events;   // begin/end pairs of recorded lag-sum launches
+    size_t n_recorded = 0;
+
+    bool green_ready = false;
+    int64_t next_step = 0;
+    bool pushed = false;
+    std::string err;
+    rp_stats stats{};
+
+    template <typename P = void>
+    P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
+    const PairP &pr(int s, int n) const { return pair[size_t(s) * n_dom + n]; }
+    PairP &pr(int s, int n) { return pair[size_t(s) * n_dom + n]; }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Planning
+
+// Smallest and largest |r - r'| between the grid points of target s and source
+// n: per axis the displacement takes the values o_s - o_n + h d,
+// d = -(N_n - 1) .. N_s - 1, and the axes are independent.
+void pair_distance(const DomainP &s, const DomainP &n, double h, double &rmin, double &rmax) {
+    double mn2 = 0, mx2 = 0;
+    for (int a = 0; a < 3; ++a) {
+        const double base = s.o[a] - n.o[a];
+        const double lo = base - h * (n.N[a] - 1), hi = base + h * (s.N[a] - 1);
+        double mn;
+        if (lo <= 0 && hi >= 0) {
+            // closest attainable value to zero
+            const double d0 = std::floor(-base / h);
+            mn = std::fabs(base + h * d0);
+            for (double d = d0 - 1; d <= d0 + 2; d += 1) {
+                if (d < -(n.N[a] - 1) || d > s.N[a] - 1) continue;
+                mn = std::min(mn, std::fabs(base + h * d));
+            }
+        } else {
+            mn = std::min(std::fabs(lo), std::fabs(hi));
+        }
+        const double mx = std::max(std::fabs(lo), std::fabs(hi));
+        mn2 += mn * mn;
+        mx2 += mx * mx;
+    }
+    rmin = std::sqrt(mn2);
+    rmax = std::sqrt(mx2);
+}
+
+void plan_build(rp_plan p, const int32_t *dims, const double *origins, const int32_t *system_id) {
+    const int nd = p->n_dom;
+    p->dom.resize(nd);
+    std::map<int32_t, int> sys_index;
+    for (int i = 0; i < nd; ++i) {
+        DomainP &d = p->dom[i];
+        for (int a = 0; a < 3; ++a) {
+            d.N[a] = dims[3 * i + a];
+            d.o[a] = origins[3 * i + a];
+            if (d.N[a] < 1) fail(RP_ERR_ARG, "dims must be >= 1");
+            if (!std::isfinite(d.o[a])) fail(RP_ERR_ARG, "origins must be finite");
+        }
+        d.npts = int64_t(d.N[0]) * d.N[1] * d.N[2];
+        const int32_t id = system_id ? system_id[i] : 0;
+        auto it = sys_index.find(id);
+        if (it == sys_index.end()) {
+            it = sys_index.emplace(id, int(p->sys.size())).first;
+            p->sys.emplace_back();
+        }
+        d.sys = it->second;
+        p->sys[d.sys].doms.push_back(i);
+    }
+
+    // pads: every pair of a system is a linear convolution of length N_s + N_n - 1
+    for (SystemP &S : p->sys) {
+        for (int a = 0; a < 3; ++a) {
+            int mx = 1;
+            for (int i : S.doms) mx = std::max(mx, p->dom[i].N[a]);
+            S.P[a] = smooth_even(2 * mx - 1);
+            if (S.P[a] > kMaxPad) fail(RP_ERR_UNSUPPORTED, "FFT pad above 512 points");
+        }
+        S.Hz = S.P[2] / 2 + 1;
+        S.C = int64_t(S.P[0]) * S.P[1] * S.Hz;
+    }
+
+    // windows
+    const double cdt = p->c * p->dt;
+    const bool finite_c = std::isfinite(p->c);
+    p->pair.assign(size_t(nd) * nd, PairP{});
+    for (const SystemP &S : p->sys) {
+        for (int s : S.doms) {
+            for (int n : S.doms) {
+                PairP &q = p->pr(s, n);
+                pair_distance(p->dom[s], p->dom[n], p->h, q.rmin, q.rmax);
+                if (s != n && q.rmin < p->h * (1.0 - 1e-12)) {
+                    char buf[160];
+                    std::snprintf(buf, sizeof buf,
+                                  "sub-domains %d and %d are closer than one grid step (%.6g < h)", s, n, q.rmin);
+                    fail(RP_ERR_GEOMETRY, buf);
+                }
+                if (finite_c) {
+                    const double x = q.rmin / cdt, y = q.rmax / cdt;
+                    // guard that only widens the window under rounding
+                    q.m_lo = int(std::max(0.0, std::floor(x - 1e-9 * std::max(1.0, x))));
+                    q.m_hi = int(std::ceil(y + 1e-9 * std::max(1.0, y)));
+                    if (s == n) q.m_hi = std::max(q.m_hi, 1);   // the self cell reaches lag 1
+                } else {
+                    q.m_lo = q.m_hi = 0;
+                }
+            }
+        }
+    }
+    for (int n = 0; n < nd; ++n) {
+        int mh = 0;
+        for (int s : p->sys[p->dom[n].sys].doms) mh = std::max(mh, p->pr(s, n).m_hi);
+        p->dom[n].depth = mh + 1;
+    }
+
+    // Green spectra: one set per unordered pair; the reversed pair uses the
+    // complex conjugate (its real-space kernel is the mirror image).
+    int64_t spec_base = 0;
+    for (SystemP &S : p->sys) {
+        S.spec_base = spec_base;
+        int64_t cnt = 0;
+        for (size_t a = 0; a < S.doms.size(); ++a) {
+            for (size_t b = a; b < S.doms.size(); ++b) {
+                const int s = S.doms[a], n = S.doms[b];
+                PairP &q = p->pr(s, n);
+                q.spec0 = cnt;
+                q.conj = false;
+                cnt += q.m_hi - q.m_lo + 1;
+                if (s != n) {
+                    PairP &r = p->pr(n, s);
+                    r.spec0 = q.spec0;
+                    r.conj = true;
+                }
+            }
+        }
+        S.n_spec = cnt;
+        spec_base += cnt * S.C;
+    }
+
+    // lag-sum schedule
+    int max_members = 1;
+    for (size_t si = 0; si < p->sys.size(); ++si) {
+        const SystemP &S = p->sys[si];
+        for (size_t g0 = 0; g0 < S.doms.size(); g0 += kGroupMax) {
+            K2Group G{};
+            G.C = S.C;
+            G.spec_base = S.spec_base;
+            G.n_members = int(std::min<size_t>(kGroupMax, S.doms.size() - g0));
+            for (int t = 0; t < G.n_members; ++t) G.member[t] = S.doms[g0 + t];
+            max_members = std::max(max_members, G.n_members);
+            G.entry_begin = int(p->entries.size());
+            for (int n : S.doms) {
+                std::vector<int> ms;
+                for (int t = 0; t < G.n_members; ++t) {
+                    const PairP &q = p->pr(G.member[t], n);
+                    for (int m = q.m_lo; m <= q.m_hi; ++m) ms.push_back(m);
+                }
+                std::sort(ms.begin(), ms.end());
+                ms.erase(std::unique(ms.begin(), ms.end()), ms.end());
+                for (int m : ms) {
+                    K2Entry E{};
+                    E.src = n;
+                    E.m = m;
+                    for (int t = 0; t < G.n_members; ++t) {
+                        const PairP &q = p->pr(G.member[t], n);
+                        if (m < q.m_lo || m > q.m_hi) continue;
+                        E.mask |= 1u << t;
+                        if (q.conj) E.conj |= 1u << t;
+                        E.spec[t] = int32_t(q.spec0 + (m - q.m_lo));
+                    }
+                    p->entries.push_back(E);
+                }
+            }
+            G.entry_end = int(p->entries.size());
+            const int gi = int(p->groups.size());
+            p->groups.push_back(G);
+            for (int64_t k0 = 0; k0 < S.C; k0 += kK2Tile) p->items.push_back(K2Item{gi, int32_t(k0)});
+        }
+    }
+    p->tg = max_members <= 1 ? 1 : (max_members <= 2 ? 2 : (max_members <= 4 ? 4 : 8));
+    if (p->entries.size() > size_t(INT32_MAX) || p->items.size() > size_t(INT32_MAX))
+        fail(RP_ERR_UNSUPPORTED, "schedule too large");
+
+    // shape classes (same dims and pads) for batched FFT launches
+    for (int i = 0; i < nd; ++i) {
+        const DomainP &d = p->dom[i];
+        const SystemP &S = p->sys[d.sys];
+        int found = -1;
+        for (size_t c = 0; c < p->cls.size(); ++c) {
+            const ClassP &K = p->cls[c];
+            if (std::equal(K.N, K.N + 3, d.N) && std::equal(K.P, K.P + 3, S.P)) found = int(c);
+        }
+        if (found < 0) {
+            ClassP K{};
+            std::copy(d.N, d.N + 3, K.N);
+            std::copy(S.P, S.P + 3, K.P);
+            K.Hz = S.Hz;
+            K.C = S.C;
+            p->cls.push_back(K);
+            found = int(p->cls.size()) - 1;
+        }
+        p->cls[found].doms.push_back(i);
+        const int lpb = zfwd_lines_per_block(S.P[2], p->p64);
+        p->dom[i].zblocks = (4 * ((d.N[0] * d.N[1] + 1) / 2) + lpb - 1) / lpb;
+    }
+}
+
+void plan_layout(rp_plan p) {
+    size_t off = 0;
+    auto alloc = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + kAlign - 1) / kAlign * kAlign;
+        return o;
+    };
+    p->off_state = alloc(64);
+    p->off_items = alloc(p->items.size() * sizeof(K2Item));
+    p->off_groups = alloc(p->groups.size() * sizeof(K2Group));
+    p->off_entries = alloc(std::max<size_t>(1, p->entries.size()) * sizeof(K2Entry));
+    p->off_domdev = alloc(p->dom.size() * sizeof(DomDev));
+    for (const SystemP &S : p->sys) {
+        for (int a = 0; a < 3; ++a) {
+            if (!p->tw64.count(S.P[a])) {
+                p->tw64[S.P[a]] = alloc(size_t(S.P[a]) * 16);
+                p->tw32[S.P[a]] = alloc(size_t(S.P[a]) * 8);
+            }
+        }
+    }
+    int64_t spec_elems = 0;
+    for (const SystemP &S : p->sys) spec_elems += S.n_spec * S.C;
+    p->off_spec = alloc(size_t(spec_elems) * p->spec_csz);
+
+    const bool quant = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
+    size_t max_gtmp = 0, max_C = 0, max_t1 = 0, max_t2 = 0, max_pts = 0;
+    for (DomainP &d : p->dom) {
+        const SystemP &S = p->sys[d.sys];
+        const size_t t1 = size_t(d.N[0]) * d.N[1] * S.Hz * 4;
+        const size_t t2 = size_t(d.N[0]) * S.P[1] * S.Hz * 4;
+        d.off_ring = alloc(size_t(d.depth) * S.C * 4 * p->ring_esz);
+        d.off_scales = quant ? alloc(size_t(d.depth) * 4 * sizeof(float)) : 0;
+        d.off_zmax = quant ? alloc(size_t(d.zblocks) * 4 * sizeof(float)) : 0;
+        d.off_s0 = alloc(size_t(4) * d.npts * p->tsz);
+        d.off_p0 = alloc(size_t(4) * d.npts * p->tsz);
+        d.off_acc = alloc(size_t(S.C) * 4 * p->csz);
+        d.off_t1 = alloc(t1 * p->csz);
+        d.off_t2 = alloc(t2 * p->csz);
+        d.off_s0hat = alloc(size_t(S.C) * 4 * 16);
+        max_gtmp = std::max(max_gtmp, size_t(S.P[0]) * S.P[1] * S.Hz);
+        max_C = std::max(max_C, size_t(S.C));
+        max_t1 = std::max(max_t1, t1);
+        max_t2 = std::max(max_t2, t2);
+        max_pts = std::max(max_pts, size_t(d.npts));
+    }
+    p->off_gtmp = alloc(size_t(kGreenChunk) * max_gtmp * 16);
+    p->off_accd = alloc(max_C * 4 * 16);
+    p->off_gstat = alloc(max_C * 16);
+    p->off_t1d = alloc(max_t1 * 16);
+    p->off_t2d = alloc(max_t2 * 16);
+    p->off_s0d = alloc(4 * max_pts * 8);
+    p->off_p0d = alloc(4 * max_pts * 8);
+    p->ws_bytes = off;
+
+    // device-side tables
+    p->domdev.resize(p->dom.size());
+    for (size_t i = 0; i < p->dom.size(); ++i) {
+        const DomainP &d = p->dom[i];
+        DomDev &D = p->domdev[i];
+        // offsets in elements relative to the first ring / accumulator / scale
+        D.ring_off = int64_t((d.off_ring - p->dom[0].off_ring) / (4 * p->ring_esz)) * 4;
+        D.acc_off = int64_t((d.off_acc - p->dom[0].off_acc) / p->csz);
+        D.scale_off = quant ? int64_t((d.off_scales - p->dom[0].off_scales) / sizeof(float)) : 0;
+        D.depth = d.depth;
+        D.pad = 0;
+    }
+}
+
+void plan_stats(rp_plan p) {
+    rp_stats &st = p->stats;
+    st = rp_stats{};
+    for (const SystemP &S : p->sys)
+        for (int s : S.doms)
+            for (int n : S.doms) st.n_triples += p->pr(s, n).m_hi - p->pr(s, n).m_lo + 1;
+    for (const SystemP &S : p->sys) st.n_spectra += S.n_spec;
+    st.n_entries = int64_t(p->entries.size());
+    for (const DomainP &d : p->dom) st.points += d.npts;
+    double bytes = 0;
+    for (const K2Group &G : p->groups) {
+        double per_k = 0;
+        for (int e = G.entry_begin; e < G.entry_end; ++e) {
+            const K2Entry &E = p->entries[e];
+            per_k += 4.0 * p->ring_esz + double(__builtin_popcount(E.mask)) * p->spec_csz;
+        }
+        per_k += double(G.n_members) * 4 * p->csz;   // accumulator write
+        bytes += per_k * double(G.C);
+    }
+    st.lagsum_bytes = bytes;
+    for (const DomainP &d : p->dom) st.ring_bytes += double(d.depth) * p->sys[d.sys].C * 4 * p->ring_esz;
+    for (const SystemP &S : p->sys) st.spectra_bytes += double(S.n_spec) * S.C * p->spec_csz;
+    for (const DomainP &d : p->dom) {
+        const SystemP &S = p->sys[d.sys];
+        const double t1 = double(d.N[0]) * d.N[1] * S.Hz * 4 * p->csz;
+        const double t2 = double(d.N[0]) * S.P[1] * S.Hz * 4 * p->csz;
+        const double ring = double(S.C) * 4 * p->ring_esz;
+        const double acc = double(S.C) * 4 * p->csz;
+        const double real = double(d.npts) * 4 * p->tsz;
+        st.fft_bytes_fwd += 2 * real + t1 + t1 + t2 + t2 + ring;
+        st.fft_bytes_inv += acc + t2 + t2 + t1 + t1 + 2 * real;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+
+void check_launch() {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) fail(RP_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+const void *tw_ptr(rp_plan p, int P, bool dbl) { return p->ws + (dbl ? p->tw64.at(P) : p->tw32.at(P)); }
+
+LinePass line_pass(rp_plan p, int P, bool dbl, int dir) {
+    LinePass a{};
+    a.P = P;
+    a.dir = dir;
+    a.tw = tw_ptr(p, P, dbl);
+    a.rp = make_radix(P);
+    a.out_fmt = dbl ? RING_F64 : RING_F32;
+    return a;
+}
+
+// Forward y pass [Nx][Ny][Hz][4] -> [Nx][Py][Hz][4].
+LinePass fwd_y(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl) {
+    LinePass a = line_pass(p, P[1], dbl, -1);
+    a.n_in = N[1];
+    a.n_out = P[1];
+    a.lines = N[0] * Hz * 4;
+    a.n_inner = Hz * 4;
+    a.in_j = Hz * 4;
+    a.in_inner = 1;
+    a.in_outer = int64_t(N[1]) * Hz * 4;
+    a.out_j = Hz * 4;
+    a.out_inner = 1;
+    a.out_outer = int64_t(P[1]) * Hz * 4;
+    return a;
+}
+
+// Forward x pass [Nx][Py][Hz][4] -> [Px][Py][Hz][4].
+LinePass fwd_x(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl) {
+    LinePass a = line_pass(p, P[0], dbl, -1);
+    a.n_in = N[0];
+    a.n_out = P[0];
+    a.lines = P[1] * Hz * 4;
+    a.n_inner = P[1] * Hz * 4;
+    a.in_j = int64_t(P[1]) * Hz * 4;
+    a.in_inner = 1;
+    a.out_j = int64_t(P[1]) * Hz * 4;
+    a.out_inner = 1;
+    return a;
+}
+
+// Inverse x pass [Px][Py][Hz][4] -> [Nx][Py][Hz][4] (crop).
+LinePass inv_x(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl) {
+    LinePass a = line_pass(p, P[0], dbl, +1);
+    a.n_in = P[0];
+    a.n_out = N[0];
+    a.lines = P[1] * Hz * 4;
+    a.n_inner = P[1] * Hz * 4;
+    a.in_j = int64_t(P[1]) * Hz * 4;
+    a.in_inner = 1;
+    a.out_j = int64_t(P[1]) * Hz * 4;
+    a.out_inner = 1;
+    return a;
+}
+
+// Inverse y pass [Nx][Py][Hz][4] -> [Nx][Ny][Hz][4] (crop).
+LinePass inv_y(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl) {
+    LinePass a = line_pass(p, P[1], dbl, +1);
+    a.n_in = P[1];
+    a.n_out = N[1];
+    a.lines = N[0] * Hz * 4;
+    a.n_inner = Hz * 4;
+    a.in_j = Hz * 4;
+    a.in_inner = 1;
+    a.in_outer = int64_t(P[1]) * Hz * 4;
+    a.out_j = Hz * 4;
+    a.out_inner = 1;
+    a.out_outer = int64_t(N[1]) * Hz * 4;
+    return a;
+}
+
+ZFwd zfwd_common(rp_plan p, int mode, const int N[3], const int P[3], int Hz, bool dbl) {
+    ZFwd a{};
+    a.mode = mode;
+    a.Nx = N[0];
+    a.Ny = N[1];
+    a.Nz = N[2];
+    a.Px = P[0];
+    a.Py = P[1];
+    a.Pz = P[2];
+    a.Hz = Hz;
+    a.h = p->h;
+    a.inv_cdt = std::isfinite(p->c) ? 1.0 / (p->c * p->dt) : 0.0;
+    a.scale = 1.0 / (double(P[0]) * P[1] * P[2]);
+    a.w_self0 = p->w_self0;
+    a.w_self1 = p->w_self1;
+    a.w_static = p->w_static;
+    a.tw = tw_ptr(p, P[2], dbl);
+    a.rp = make_radix(P[2]);
+    return a;
+}
+
+// FP64 spectrum (one component, [Px][Py][Hz]) of the Green's function of pair
+// (s <- n): lag m (mode 1) or instantaneous (mode 2), written with out_fmt.
+void green_spectra(rp_plan p, int s, int n, int mode, int m0, int count, void *const *outs, int out_fmt) {
+    const DomainP &ds = p->dom[s], &dn = p->dom[n];
+    const SystemP &S = p->sys[ds.sys];
+    const size_t gstride = size_t(S.P[0]) * S.P[1] * S.Hz * 16;
+    ZFwd z = zfwd_common(p, mode, ds.N, S.P, S.Hz, true);
+    z.n_jobs = count;
+    for (int j = 0; j < count; ++j) {
+        ZFwdJob &J = z.jobs[j];
+        J.out = p->ws + p->off_gtmp + j * gstride;
+        for (int a = 0; a < 3; ++a) {
+            J.off[a] = ds.o[a] - dn.o[a];
+            J.Ns[a] = ds.N[a];
+            J.Nn[a] = dn.N[a];
+        }
+        J.m = m0 + j;
+        J.self = (s == n);
+    }
+    launch_zfwd(z, 1, p->stream);
+    check_launch();
+
+    LinePass y = line_pass(p, S.P[1], true, -1);
+    y.n_in = y.n_out = S.P[1];
+    y.lines = S.P[0] * S.Hz;
+    y.n_inner = S.Hz;
+    y.in_j = y.out_j = S.Hz;
+    y.in_inner = y.out_inner = 1;
+    y.in_outer = y.out_outer = int64_t(S.P[1]) * S.Hz;
+    y.n_jobs = count;
+    for (int j = 0; j < count; ++j) y.jobs[j].in = y.jobs[j].out = p->ws + p->off_gtmp + j * gstride;
+    launch_line_pass(y, 1, p->stream);
+    check_launch();
+
+    LinePass x = line_pass(p, S.P[0], true, -1);
+    x.n_in = x.n_out = S.P[0];
+    x.lines = x.n_inner = S.P[1] * S.Hz;
+    x.in_j = x.out_j = int64_t(S.P[1]) * S.Hz;
+    x.in_inner = x.out_inner = 1;
+    x.out_fmt = out_fmt;
+    x.n_jobs = count;
+    for (int j = 0; j < count; ++j) {
+        x.jobs[j].in = p->ws + p->off_gtmp + j * gstride;
+        x.jobs[j].out = outs[j];
+    }
+    launch_line_pass(x, 1, p->stream);
+    check_launch();
+}
+
+void do_bind(rp_plan p, void *dev, size_t bytes) {
+    if (!dev) fail(RP_ERR_ARG, "workspace pointer is null");
+    if (reinterpret_cast<uintptr_t>(dev) % kAlign) fail(RP_ERR_ARG, "workspace must be 256-byte aligned");
+    if (bytes < p->ws_bytes) fail(RP_ERR_NOMEM, "workspace smaller than rp_workspace_bytes");
+    p->ws = static_cast<char *>(dev);
+    hipStream_t st = p->stream;
+    HIP_OK(hipMemcpyAsync(p->ws + p->off_items, p->items.data(), p->items.size() * sizeof(K2Item),
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(p->ws + p->off_groups, p->groups.data(), p->groups.size() * sizeof(K2Group),
+                          hipMemcpyHostToDevice, st));
+    if (!p->entries.empty())
+        HIP_OK(hipMemcpyAsync(p->ws + p->off_entries, p->entries.data(), p->entries.size() * sizeof(K2Entry),
+                              hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(p->ws + p->off_domdev, p->domdev.data(), p->domdev.size() * sizeof(DomDev),
+                          hipMemcpyHostToDevice, st));
+    // twiddles exp(-2 pi i j / P), evaluated in FP64 on the host
+    std::vector<Cx<double>> t64;
+    std::vector<Cx<float>> t32;
+    for (const auto &kv : p->tw64) {
+        const int P = kv.first;
+        t64.resize(P);
+        t32.resize(P);
+        for (int j = 0; j < P; ++j) {
+            const double ang = -2.0 * M_PI * double(j) / double(P);
+            t64[j] = {std::cos(ang), std::sin(ang)};
+            t32[j] = {float(t64[j].x), float(t64[j].y)};
+        }
+        HIP_OK(hipMemcpyAsync(p->ws + kv.second, t64.data(), P * 16, hipMemcpyHostToDevice, st));
+        HIP_OK(hipMemcpyAsync(p->ws + p->tw32.at(P), t32.data(), P * 8, hipMemcpyHostToDevice, st));
+        HIP_OK(hipStreamSynchronize(st));   // host buffers are reused
+    }
+    launch_fill_zero(p->ws + p->off_state, 64, st);
+    for (const DomainP &d : p->dom) {
+        launch_fill_zero(p->ws + d.off_ring, size_t(d.depth) * p->sys[d.sys].C * 4 * p->ring_esz, st);
+        if (d.off_scales) launch_fill_zero(p->ws + d.off_scales, (size_t(d.depth) * 16 + 15) / 16 * 16, st);
+    }
+    check_launch();
+    HIP_OK(hipStreamSynchronize(st));
+    p->green_ready = false;
+    p->next_step = 0;
+    p->pushed = false;
+}
+
+void do_green(rp_plan p) {
+    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    const int fmt = p->p64 ? RING_F64 : RING_F32;
+    for (const SystemP &S : p->sys) {
+        for (size_t a = 0; a < S.doms.size(); ++a) {
+            for (size_t b = a; b < S.doms.size(); ++b) {
+                const int s = S.doms[a], n = S.doms[b];
+                const PairP &q = p->pr(s, n);
+                for (int m0 = q.m_lo; m0 <= q.m_hi; m0 += kGreenChunk) {
+                    const int cnt = std::min(kGreenChunk, q.m_hi - m0 + 1);
+                    void *outs[kGreenChunk];
+                    for (int j = 0; j < cnt; ++j)
+                        outs[j] = p->ws + p->off_spec +
+                                  size_t(S.spec_base + (q.spec0 + (m0 + j - q.m_lo)) * S.C) * p->spec_csz;
+                    green_spectra(p, s, n, 1, m0, cnt, outs, fmt);
+                }
+            }
+        }
+    }
+    HIP_OK(hipStreamSynchronize(p->stream));
+    p->green_ready = true;
+}
+
+// Static potential P(0) of every domain in FP64: the instantaneous Coulomb
+// sum of S(0) with the self-cell integral, by the same padded FFT convolution.
+void do_static(rp_plan p, const void *const *src) {
+    hipStream_t st = p->stream;
+    for (const SystemP &S : p->sys) {
+        for (int n : S.doms) {
+            const DomainP &d = p->dom[n];
+            const void *s64 = src[n];
+            if (!p->p64) {
+                launch_convert(p->ws + p->off_s0d, 1, src[n], 0, 4 * d.npts, st);
+                s64 = p->ws + p->off_s0d;
+            }
+            ZFwd z = zfwd_common(p, 0, d.N, S.P, S.Hz, true);
+            z.n_jobs = 1;
+            z.jobs[0].src = s64;
+            z.jobs[0].s0 = nullptr;
+            z.jobs[0].out = p->ws + p->off_t1d;
+            launch_zfwd(z, 1, st);
+            LinePass y = fwd_y(p, d.N, S.P, S.Hz, true);
+            y.n_jobs = 1;
+            y.jobs[0].in = p->ws + p->off_t1d;
+            y.jobs[0].out = p->ws + p->off_t2d;
+            launch_line_pass(y, 1, st);
+            LinePass x = fwd_x(p, d.N, S.P, S.Hz, true);
+            x.n_jobs = 1;
+            x.jobs[0].in = p->ws + p->off_t2d;
+            x.jobs[0].out = p->ws + d.off_s0hat;
+            launch_line_pass(x, 1, st);
+            check_launch();
+        }
+        for (int s : S.doms) {
+            const DomainP &d = p->dom[s];
+            launch_fill_zero(p->ws + p->off_accd, size_t(S.C) * 4 * 16, st);
+            for (int n : S.doms) {
+                void *outs[1] = {p->ws + p->off_gstat};
+                green_spectra(p, s, n, 2, 0, 1, outs, RING_F64);
+                launch_static_mac(p->ws + p->off_accd, p->ws + p->off_gstat, p->ws + p->dom[n].off_s0hat, S.C, st);
+            }
+            LinePass x = inv_x(p, d.N, S.P, S.Hz, true);
+            x.n_jobs = 1;
+            x.jobs[0].in = p->ws + p->off_accd;
+            x.jobs[0].out = p->ws + p->off_t2d;
+            launch_line_pass(x, 1, st);
+            LinePass y = inv_y(p, d.N, S.P, S.Hz, true);
+            y.n_jobs = 1;
+            y.jobs[0].in = p->ws + p->off_t2d;
+            y.jobs[0].out = p->ws + p->off_t1d;
+            launch_line_pass(y, 1, st);
+            ZInv zi{};
+            zi.Nx = d.N[0];
+            zi.Ny = d.N[1];
+            zi.Nz = d.N[2];
+            zi.Pz = S.P[2];
+            zi.Hz = S.Hz;
+            zi.tw = tw_ptr(p, S.P[2], true);
+            zi.rp = make_radix(S.P[2]);
+            zi.n_jobs = 1;
+            zi.jobs[0].in = p->ws + p->off_t1d;
+            zi.jobs[0].out = p->ws + p->off_p0d;
+            zi.jobs[0].add = nullptr;
+            launch_zinv(zi, 1, st);
+            launch_convert(p->ws + d.off_p0, p->p64, p->ws + p->off_p0d, 1, 4 * d.npts, st);
+            check_launch();
+        }
+    }
+}
+
+void do_push(rp_plan p, int64_t step, const void *const *src) {
+    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
+    if (!src) fail(RP_ERR_ARG, "src is null");
+    if (step != p->next_step || p->pushed) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "rp_push_sources(%lld) out of order (expected step %lld%s)",
+                      (long long)step, (long long)p->next_step, p->pushed ? ", already pushed" : "");
+        fail(RP_ERR_STATE, buf);
+    }
+    for (int n = 0; n < p->n_dom; ++n)
+        if (!src[n]) fail(RP_ERR_ARG, "a source pointer is null");
+    hipStream_t st = p->stream;
+    if (step == 0) {
+        for (int n = 0; n < p->n_dom; ++n)
+            launch_convert(p->ws + p->dom[n].off_s0, p->p64, src[n], p->p64, 4 * p->dom[n].npts, st);
+        do_static(p, src);
+    } else {
+        const bool quant = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
+        const int64_t *dstep = p->at<int64_t>(p->off_state);
+        for (const ClassP &K : p->cls) {
+            for (size_t j0 = 0; j0 < K.doms.size(); j0 += kMaxJobs) {
+                const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
+                ZFwd z = zfwd_common(p, 0, K.N, K.P, K.Hz, p->p64);
+                LinePass y = fwd_y(p, K.N, K.P, K.Hz, p->p64);
+                LinePass x = fwd_x(p, K.N, K.P, K.Hz, p->p64);
+                x.out_fmt = p->ring_fmt;
+                x.step = dstep;
+                ScaleArgs sa{};
+                sa.step = dstep;
+                z.n_jobs = y.n_jobs = x.n_jobs = cnt;
+                sa.n_jobs = quant ? cnt : 0;
+                for (int j = 0; j < cnt; ++j) {
+                    const int n = K.doms[j0 + j];
+                    const DomainP &d = p->dom[n];
+                    z.jobs[j].src = src[n];
+                    z.jobs[j].s0 = p->ws + d.off_s0;
+                    z.jobs[j].out = p->ws + d.off_t1;
+                    z.jobs[j].zmax = quant ? p->at<float>(d.off_zmax) : nullptr;
+                    y.jobs[j].in = p->ws + d.off_t1;
+                    y.jobs[j].out = p->ws + d.off_t2;
+                    x.jobs[j].in = p->ws + d.off_t2;
+                    x.jobs[j].out = p->ws + d.off_ring;
+                    x.jobs[j].slot_stride = K.C * 4;
+                    x.jobs[j].depth = d.depth;
+                    x.jobs[j].qscale = quant ? p->at<float>(d.off_scales) : nullptr;
+                    if (quant) {
+                        sa.jobs[j].zmax = p->at<float>(d.off_zmax);
+                        sa.jobs[j].scales = p->at<float>(d.off_scales);
+                        sa.jobs[j].nblk = d.zblocks;
+                        sa.jobs[j].depth = d.depth;
+                        sa.jobs[j].npts = double(d.npts);
+                    }
+                }
+                launch_zfwd(z, p->p64, st);
+                launch_ring_scale(sa, st);
+                launch_line_pass(y, p->p64, st);
+                launch_line_pass(x, p->p64, st);
+                check_launch();
+            }
+        }
+    }
+    check_launch();
+    p->pushed = true;
+}
+
+void do_step(rp_plan p, int64_t step, void *const *out) {
+    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    if (!out) fail(RP_ERR_ARG, "out is null");
+    if (step != p->next_step || !p->pushed) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "rp_retarded_step(%lld) out of order (expected step %lld%s)",
+                      (long long)step, (long long)p->next_step, p->pushed ? "" : ", sources not pushed");
+        fail(RP_ERR_STATE, buf);
+    }
+    for (int n = 0; n < p->n_dom; ++n)
+        if (!out[n]) fail(RP_ERR_ARG, "an output pointer is null");
+    hipStream_t st = p->stream;
+    K2Args k{};
+    k.items = p->at<K2Item>(p->off_items);
+    k.groups = p->at<K2Group>(p->off_groups);
+    k.entries = p->at<K2Entry>(p->off_entries);
+    k.doms = p->at<DomDev>(p->off_domdev);
+    k.spectra = p->ws + p->off_spec;
+    k.ring = p->ws + p->dom[0].off_ring;
+    k.scales = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16) ? p->at<float>(p->dom[0].off_scales) : nullptr;
+    k.acc = p->ws + p->dom[0].off_acc;
+    k.step = p->at<int64_t>(p->off_state);
+    k.n_items = int(p->items.size());
+    if (p->profile) {
+        if (p->events.size() < 2 * (p->n_recorded + 1)) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t ev;
+                HIP_OK(hipEventCreate(&ev));
+                p->events.push_back(ev);
+            }
+        }
+        HIP_OK(hipEventRecord(p->events[2 * p->n_recorded], st));
+    }
+    launch_lagsum(k, p->p64, p->ring_fmt, p->tg, st);
+    check_launch();
+    if (p->profile) {
+        HIP_OK(hipEventRecord(p->events[2 * p->n_recorded + 1], st));
+        p->n_recorded += 1;
+    }
+    for (const ClassP &K : p->cls) {
+        for (size_t j0 = 0; j0 < K.doms.size(); j0 += kMaxJobs) {
+            const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
+            LinePass x = inv_x(p, K.N, K.P, K.Hz, p->p64);
+            LinePass y = inv_y(p, K.N, K.P, K.Hz, p->p64);
+            ZInv zi{};
+            zi.Nx = K.N[0];
+            zi.Ny = K.N[1];
+            zi.Nz = K.N[2];
+            zi.Pz = K.P[2];
+            zi.Hz = K.Hz;
+            zi.tw = tw_ptr(p, K.P[2], p->p64);
+            zi.rp = make_radix(K.P[2]);
+            x.n_jobs = y.n_jobs = zi.n_jobs = cnt;
+            for (int j = 0; j < cnt; ++j) {
+                const int s = K.doms[j0 + j];
+                const DomainP &d = p->dom[s];
+                x.jobs[j].in = p->ws + d.off_acc;
+                x.jobs[j].out = p->ws + d.off_t2;
+                y.jobs[j].in = p->ws + d.off_t2;
+                y.jobs[j].out = p->ws + d.off_t1;
+                zi.jobs[j].in = p->ws + d.off_t1;
+                zi.jobs[j].out = out[s];
+                zi.jobs[j].add = p->ws + d.off_p0;
+            }
+            launch_line_pass(x, p->p64, st);
+            launch_line_pass(y, p->p64, st);
+            launch_zinv(zi, p->p64, st);
+            check_launch();
+        }
+    }
+    launch_advance_step(p->at<int64_t>(p->off_state), st);
+    check_launch();
+    p->next_step += 1;
+    p->pushed = false;
+}
+
+template <typename F>
+rp_status guarded(rp_plan p, F &&f) {
+    if (!p) return RP_ERR_ARG;
+    try {
+        p->err.clear();
+        f();
+        return RP_OK;
+    } catch (const Error &e) {
+        p->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        p->err = "host allocation failed";
+        return RP_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        p->err = e.what();
+        return RP_ERR_ARG;
+    } catch (...) {
+        p->err = "unknown error";
+        return RP_ERR_ARG;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+rp_status rp_plan_domains(rp_plan *out, int32_t n_dom, const int32_t *dims, const double *origins,
+                          const int32_t *system_id, double h, double dt, double c, rp_precision prec,
+                          void *hip_stream) {
+    if (!out) {
+        g_create_error = "out is null";
+        return RP_ERR_ARG;
+    }
+    *out = nullptr;
+    rp_plan p = nullptr;
+    try {
+        if (n_dom < 1 || !dims || !origins) fail(RP_ERR_ARG, "n_dom >= 1 and non-null dims/origins required");
+        if (!(h > 0) || !std::isfinite(h)) fail(RP_ERR_ARG, "h must be positive and finite");
+        if (!(dt > 0) || !std::isfinite(dt)) fail(RP_ERR_ARG, "dt must be positive and finite");
+        if (!(c > 0)) fail(RP_ERR_ARG, "c must be positive (or +INFINITY)");
+        if (prec < RP_FP64 || prec > RP_FP32_RING_BF16) fail(RP_ERR_ARG, "unknown precision");
+        p = new rp_plan_s();
+        p->n_dom = n_dom;
+        p->h = h;
+        p->dt = dt;
+        p->c = c;
+        p->prec = prec;
+        p->stream = static_cast<hipStream_t>(hip_stream);
+        p->p64 = (prec == RP_FP64);
+        p->ring_fmt = prec == RP_FP64 ? RING_F64
+                      : prec == RP_FP32  ? RING_F32
+                      : prec == RP_FP32_RING_FP16 ? RING_F16 : RING_BF16;
+        p->tsz = p->p64 ? 8 : 4;
+        p->csz = p->p64 ? 16 : 8;
+        p->spec_csz = p->csz;
+        p->ring_esz = p->ring_fmt == RING_F64 ? 16 : (p->ring_fmt == RING_F32 ? 8 : 4);
+        // self cell: the exact integral of T(m dt - |u|/c)/|u| over the cell of
+        // side h around the point; C1 = int_{[-1/2,1/2]^3} d^3u/|u| = 3 ln(2 + sqrt 3) - pi/2
+        const double C1 = 3.0 * std::log(2.0 + std::sqrt(3.0)) - M_PI / 2.0;
+        p->w_static = h * h * C1;
+        if (std::isfinite(c)) {
+            if (h * std::sqrt(3.0) / 2.0 >= c * dt)
+                fail(RP_ERR_UNSUPPORTED, "self cell needs h*sqrt(3)/2 < c*dt");
+            p->w_self0 = h * h * C1 - h * h * h / (c * dt);
+            p->w_self1 = h * h * h / (c * dt);
+        } else {
+            p->w_self0 = h * h * C1;
+            p->w_self1 = 0.0;
+        }
+        plan_build(p, dims, origins, system_id);
+        plan_layout(p);
+        plan_stats(p);
+        *out = p;
+        return RP_OK;
+    } catch (const Error &e) {
+        g_create_error = e.msg;
+        delete p;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_create_error = "host allocation failed";
+        delete p;
+        return RP_ERR_NOMEM;
+    } catch (...) {
+        g_create_error = "unknown error";
+        delete p;
+        return RP_ERR_ARG;
+    }
+}
+
+rp_status rp_workspace_bytes(rp_plan plan, size_t *bytes) {
+    return guarded(plan, [&] {
+        if (!bytes) fail(RP_ERR_ARG, "bytes is null");
+        *bytes = plan->ws_bytes;
+    });
+}
+
+rp_status rp_bind_workspace(rp_plan plan, void *dev_ptr, size_t bytes) {
+    return guarded(plan, [&] { do_bind(plan, dev_ptr, bytes); });
+}
+
+rp_status rp_set_green_kernels(rp_plan plan) {
+    return guarded(plan, [&] { do_green(plan); });
+}
+
+rp_status rp_push_sources(rp_plan plan, int64_t step, const void *const *src) {
+    return guarded(plan, [&] { do_push(plan, step, src); });
+}
+
+rp_status rp_retarded_step(rp_plan plan, int64_t step, void *const *out) {
+    return guarded(plan, [&] { do_step(plan, step, out); });
+}
+
+rp_status rp_plan_info(rp_plan plan, int32_t s, int32_t n, int32_t *m_lo, int32_t *m_hi, int32_t pad[3],
+                       int32_t *depth) {
+    return guarded(plan, [&] {
+        if (s < 0 || n < 0 || s >= plan->n_dom || n >= plan->n_dom) fail(RP_ERR_ARG, "domain index out of range");
+        const PairP &q = plan->pr(s, n);
+        if (m_lo) *m_lo = q.m_lo;
+        if (m_hi) *m_hi = q.m_hi;
+        if (pad)
+            for (int a = 0; a < 3; ++a) pad[a] = plan->sys[plan->dom[s].sys].P[a];
+        if (depth) *depth = plan->dom[n].depth;
+    });
+}
+
+rp_status rp_plan_stats(rp_plan plan, rp_stats *out) {
+    return guarded(plan, [&] {
+        if (!out) fail(RP_ERR_ARG, "out is null");
+        *out = plan->stats;
+    });
+}
+
+rp_status rp_profile_lagsum(rp_plan plan, int32_t enable) {
+    return guarded(plan, [&] { plan->profile = (enable != 0); });
+}
+
+rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches) {
+    return guarded(plan, [&] {
+        double tot = 0.0;
+        if (plan->n_recorded) {
+            HIP_OK(hipEventSynchronize(plan->events[2 * plan->n_recorded - 1]));
+            for (size_t i = 0; i < plan->n_recorded; ++i) {
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, plan->events[2 * i], plan->events[2 * i + 1]));
+                tot += ms;
+            }
+        }
+        if (total_ms) *total_ms = tot;
+        if (launches) *launches = int64_t(plan->n_recorded);
+        plan->n_recorded = 0;
+    });
+}
+
+rp_status rp_plan_destroy(rp_plan plan) {
+    if (!plan) return RP_ERR_ARG;
+    for (hipEvent_t ev : plan->events) (void)hipEventDestroy(ev);
+    delete plan;
+    return RP_OK;
+}
+
+const char *rp_last_error(rp_plan plan) {
+    if (!plan) return g_create_error.c_str();
+    return plan->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace rpot {
+
+template <typename T>
+struct Cx {
+    T x, y;
+};
+
+// Mixed-radix factorisation of an FFT length (radices 4, 2, 3).
+struct RadixPlan {
+    int n;
+    int r[16];
+};
+
+constexpr int kMaxJobs = 16;
+constexpr int kFftThreads = 256;
+
+// Ring storage formats of the source-spectrum history.
+enum RingFmt : int { RING_F64 = 0, RING_F32 = 1, RING_F16 = 2, RING_BF16 = 3 };
+
+// ---------------------------------------------------------------------------
+// Generic strided line FFT (complex to complex).  A line is addressed as
+//   base + outer * s_outer + inner * s_inner + j * s_j   (element = one complex)
+// with line = outer * n_inner + inner.  Only the first n_in points of a line
+// are read (the rest are zero) and only the first n_out are written.
+struct LineJob {
+    const void *in;
+    void *out;
+    const float *qscale;   // ring quantisation: scales [depth][4] of the domain, else null
+    int64_t slot_stride;   // ring output: elements per slot (0: out is used as is)
+    int32_t depth;         // ring output: slots; the slot is (*step) mod depth
+    int32_t pad_;
+};
+
+struct LinePass {
+    int P, n_in, n_out;
+    int lines, n_inner;
+    int64_t in_j, in_inner, in_outer;
+    int64_t out_j, out_inner, out_outer;
+    int dir;               // -1 forward, +1 inverse
+    int out_fmt;           // RingFmt of the output (F64/F32 = plain complex)
+    const void *tw;        // twiddles exp(-2 pi i j / P), j < P
+    const int64_t *step;   // device step counter (ring output), else null
+    RadixPlan rp;
+    int n_jobs;
+    LineJob jobs[kMaxJobs];
+};
+
+// ---------------------------------------------------------------------------
+// Real-to-complex z pass.
+//  mode 0: sources.  Line (x, y) of component mu is dS = S - S0 along z
+//          (Nz points, zero-padded to Pz); output [Nx][Ny][Hz][4] interleaved.
+//  mode 1: Green's function of lag m for the pair (s <- n) generated on the
+//          fly on the full Px x Py x Pz grid; output [Px][Py][Hz].
+//  mode 2: as mode 1 with the instantaneous (static) kernel h^3/R.
+struct ZFwdJob {
+    const void *src;       // mode 0: S  [4][Nx][Ny][Nz]
+    const void *s0;        // mode 0: S0 [4][Nx][Ny][Nz] (null: transform S itself)
+    void *out;
+    float *zmax;           // mode 0: per-block max |dS| per component, or null
+    double off[3];         // modes 1/2: o_s - o_n
+    int Ns[3], Nn[3];      // modes 1/2: target / source dims
+    int m;                 // mode 1: lag
+    int self;              // modes 1/2: s == n
+};
+
+struct ZFwd {
+    int mode;
+    int Nx, Ny, Nz;        // mode 0 dims (common to every job of a launch)
+    int Px, Py, Pz, Hz;
+    double h, inv_cdt, scale;      // inv_cdt = 1/(c dt) (0 for c = inf); scale = 1/(Px Py Pz)
+    double w_self0, w_self1, w_static;
+    const void *tw;
+    RadixPlan rp;
+    int n_jobs;
+    ZFwdJob jobs[kMaxJobs];
+};
+
+// Complex-to-real z pass with crop: input [Nx][Ny][Hz][4], output
+// out[mu][x][y][z] = IFFT(...)[z] (+ add[mu][x][y][z]) for z < Nz.
+struct ZInvJob {
+    const void *in;
+    void *out;
+    const void *add;       // static potential, or null
+};
+
+struct ZInv {
+    int Nx, Ny, Nz;
+    int Pz, Hz;
+    const void *tw;
+    RadixPlan rp;
+    int n_jobs;
+    ZInvJob jobs[kMaxJobs];
+};
+
+// ---------------------------------------------------------------------------
+// Lag-sum multiply-accumulate.
+struct K2Entry {
+    int32_t src;           // source domain (global index)
+    int32_t m;             // lag
+    uint32_t mask;         // group members fed by this (source, lag)
+    uint32_t conj;         // members that use the conjugate of the stored spectrum
+    int32_t spec[8];       // spectrum index (within the system) per member
+};
+
+struct K2Group {
+    int64_t C;             // spectrum length of the system
+    int64_t spec_base;     // element offset of the system's spectra
+    int32_t entry_begin, entry_end;
+    int32_t n_members;
+    int32_t member[8];     // global target domain index per member
+};
+
+struct K2Item {
+    int32_t group;
+    int32_t k0;
+};
+
+struct DomDev {
+    int64_t ring_off;      // element offset (complex) of the domain's ring
+    int64_t acc_off;       // element offset (complex) of the domain's accumulator
+    int64_t scale_off;     // float offset of the ring's scales [depth][4]
+    int32_t depth;
+    int32_t pad;
+};
+
+struct K2Args {
+    const K2Item *items;
+    const K2Group *groups;
+    const K2Entry *entries;
+    const DomDev *doms;
+    const void *spectra;
+    const void *ring;
+    const float *scales;
+    void *acc;
+    const int64_t *step;   // device step counter
+    int n_items;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files).
+void launch_line_pass(const LinePass &a, int prec64, hipStream_t st);
+void launch_zfwd(const ZFwd &a, int prec64, hipStream_t st);
+void launch_zinv(const ZInv &a, int prec64, hipStream_t st);
+int zfwd_lines_per_block(int Pz, int prec64);
+void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, hipStream_t st);
+// Per-snapshot ring scales: for each job, scales[(step mod depth)*4 + mu] =
+// 2^(e-15) with npts * max_blocks zmax[b][mu] <= 2^e (1 when the max is 0).
+struct ScaleJob {
+    const float *zmax;
+    float *scales;
+    int32_t nblk;
+    int32_t depth;
+    double npts;
+};
+struct ScaleArgs {
+    const int64_t *step;
+    int n_jobs;
+    ScaleJob jobs[kMaxJobs];
+};
+void launch_ring_scale(const ScaleArgs &a, hipStream_t st);
+void launch_static_mac(void *acc, const void *g, const void *s, int64_t C, hipStream_t st);
+void launch_convert(void *dst, int dst64, const void *src, int src64, int64_t n, hipStream_t st);
+void launch_fill_zero(void *dst, size_t bytes, hipStream_t st);
+void launch_advance_step(int64_t *step, hipStream_t st);
+
+}  // namespace rpot

@@ -1,0 +1,148 @@
+"""Python face of the retarded-potential library: the same calls as the C-ABI
+(include/rpot.h), with torch tensors supplying device memory and the stream.
+
+No arithmetic of the method happens here: every step runs in the HIP kernels
+of librpot.so, and a missing library is an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from . import _lib
+
+
+class Plan:
+    """A planned multi-domain evaluation (rp_plan_domains).
+
+    dims [n][3] and origins [n][3] (bohr) describe the sub-domain grids, h/dt/c
+    the grid step, time step and speed of light (c may be math.inf).
+    precision: "fp64", "fp32", "fp32_ring_fp16" or "fp32_ring_bf16".
+    """
+
+    def __init__(self, dims, origins, h, dt, c, precision="fp32", system_id=None, stream=None):
+        self._lib = _lib.load()
+        dims = np.ascontiguousarray(dims, dtype=np.int32).reshape(-1, 3)
+        origins = np.ascontiguousarray(origins, dtype=np.float64).reshape(-1, 3)
+        if dims.shape != origins.shape:
+            raise ValueError("dims and origins must both be [n][3]")
+        self.n_dom = dims.shape[0]
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        self.precision = precision
+        if precision not in _lib.PRECISION:
+            raise ValueError(f"unknown precision {precision!r}")
+        sid = None
+        if system_id is not None:
+            sid = np.ascontiguousarray(system_id, dtype=np.int32)
+            if sid.shape != (self.n_dom,):
+                raise ValueError("system_id must have one entry per domain")
+        self._stream_obj = stream
+        stream_ptr = None
+        if stream is not None:
+            stream_ptr = ctypes.c_void_p(int(stream.cuda_stream))
+        handle = ctypes.c_void_p()
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        code = self._lib.rp_plan_domains(
+            ctypes.byref(handle), self.n_dom, dims.ctypes.data_as(i32p),
+            origins.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            sid.ctypes.data_as(i32p) if sid is not None else None,
+            float(h), float(dt), float(c), _lib.PRECISION[precision], stream_ptr)
+        _lib.check(self._lib, None, code)
+        self._h = handle
+        self._ws = None
+
+    # -- host-side queries ---------------------------------------------------
+    @property
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _lib.check(self._lib, self._h, self._lib.rp_workspace_bytes(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def info(self, s, n):
+        lo, hi, depth = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        pad = (ctypes.c_int32 * 3)()
+        _lib.check(self._lib, self._h, self._lib.rp_plan_info(
+            self._h, int(s), int(n), ctypes.byref(lo), ctypes.byref(hi), pad, ctypes.byref(depth)))
+        return int(lo.value), int(hi.value), tuple(int(v) for v in pad), int(depth.value)
+
+    def stats(self) -> dict:
+        st = _lib.RpStats()
+        _lib.check(self._lib, self._h, self._lib.rp_plan_stats(self._h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in _lib.RpStats._fields_}
+
+    # -- device calls --------------------------------------------------------
+    @property
+    def dtype(self):
+        import torch
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def bind(self, workspace=None, device="cuda"):
+        """Bind a workspace (a uint8 CUDA tensor of at least workspace_bytes);
+        allocates one with torch when none is given."""
+        import torch
+        nbytes = self.workspace_bytes
+        if workspace is None:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        if workspace.device.type != "cuda" or workspace.dtype != torch.uint8:
+            raise ValueError("workspace must be a uint8 CUDA tensor")
+        ptr = workspace.data_ptr()
+        off = (-ptr) % 256
+        if workspace.numel() - off < nbytes:
+            raise ValueError("workspace too small")
+        self._ws = workspace
+        _lib.check(self._lib, self._h, self._lib.rp_bind_workspace(
+            self._h, ctypes.c_void_p(ptr + off), ctypes.c_size_t(workspace.numel() - off)))
+        return workspace
+
+    def set_green_kernels(self):
+        _lib.check(self._lib, self._h, self._lib.rp_set_green_kernels(self._h))
+
+    def _ptrs(self, tensors):
+        import torch
+        if len(tensors) != self.n_dom:
+            raise ValueError(f"expected {self.n_dom} tensors")
+        for t, d in zip(tensors, self.dims):
+            if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+                raise ValueError("tensors must be CUDA tensors")
+            if t.dtype != self.dtype:
+                raise ValueError(f"tensors must be {self.dtype}")
+            if tuple(t.shape) != (4, *d) or not t.is_contiguous():
+                raise ValueError(f"tensor must be contiguous with shape {(4, *d)}")
+        return (ctypes.c_void_p * self.n_dom)(*[t.data_ptr() for t in tensors])
+
+    def push_sources(self, step, sources):
+        arr = self._ptrs(sources)
+        _lib.check(self._lib, self._h, self._lib.rp_push_sources(self._h, int(step), arr))
+
+    def retarded_step(self, step, outputs):
+        arr = self._ptrs(outputs)
+        _lib.check(self._lib, self._h, self._lib.rp_retarded_step(self._h, int(step), arr))
+
+    def profile_lagsum(self, enable=True):
+        _lib.check(self._lib, self._h, self._lib.rp_profile_lagsum(self._h, int(bool(enable))))
+
+    def lagsum_time(self):
+        """(summed lag-sum kernel ms, launches) since the last query."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _lib.check(self._lib, self._h, self._lib.rp_lagsum_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.rp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_for_system(system, precision="fp32", stream=None):
+    """Plan for a synthetic system description (dims, origins, h, dt, c, ids)."""
+    return Plan(system.dims, system.origins, system.h, system.dt,
+                system.c if math.isfinite(system.c) else math.inf,
+                precision=precision, system_id=system.system_id, stream=stream)

@@ -165,6 +165,9 @@ def sample_sources(system: System, steps, factors=None) -> list:
         B = factors[i] if factors is not None else spatial_factors(dom, system.h, system.c)
         A = time_factors(dom, system.dt, steps)
         nt = B.shape[0]
+        if nt == 0:
+            out.append(np.zeros((len(steps), 4, dom.n_points)))
+            continue
         out.append((A @ B.reshape(nt, -1)).reshape(len(steps), 4, -1))
     return out
 

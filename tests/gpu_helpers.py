@@ -1,0 +1,82 @@
+"""Drivers shared by the GPU tests: run the HIP path through the C-ABI binding
+on seeded inputs and compare with the oracle."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+from synth.sources import spatial_factors, time_factors
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(system, precision, samples, collect=None):
+    """Push samples[n][l] ([L+1][4][N] FP64) for l = 0..L and step.
+
+    Returns {l: [dom][4][N] FP64 numpy} for l in `collect` (default: all)."""
+    import torch
+    from paper_2311_15429_amd import plan_for_system
+    stream = torch.cuda.current_stream()
+    p = plan_for_system(system, precision, stream=stream)
+    p.bind()
+    p.set_green_kernels()
+    dt = p.dtype
+    outs = [torch.empty((4,) + d, dtype=dt, device="cuda") for d in p.dims]
+    L = samples[0].shape[0] - 1
+    collect = set(range(L + 1)) if collect is None else set(collect)
+    res = {}
+    for l in range(L + 1):
+        src = [torch.from_numpy(np.ascontiguousarray(samples[n][l]).reshape((4,) + p.dims[n])).to("cuda", dt)
+               for n in range(p.n_dom)]
+        p.push_sources(l, src)
+        p.retarded_step(l, outs)
+        if l in collect:
+            res[l] = [o.double().cpu().numpy().reshape(4, -1) for o in outs]
+    torch.cuda.synchronize()
+    p.close()
+    return res
+
+
+def rel_err(got, ref):
+    """Per component: max over every point of every domain of |got - ref|
+    divided by max |ref| (the error definition used for every parity bar)."""
+    g = np.concatenate([np.asarray(x).reshape(4, -1) for x in got], axis=1)
+    r = np.concatenate([np.asarray(x).reshape(4, -1) for x in ref], axis=1)
+    return np.max(np.abs(g - r), axis=1) / np.maximum(np.max(np.abs(r), axis=1), 1e-300)
+
+
+class GpuSourceGen:
+    """Per-step sources on the GPU from the separable factors (FP64 matmul,
+    then cast to the path dtype).  The same factors feed the oracle on the CPU."""
+
+    def __init__(self, system, dtype):
+        import torch
+        self.system = system
+        self.dtype = dtype
+        self.B = []
+        for d in system.domains:
+            b = spatial_factors(d, system.h, system.c)
+            self.B.append(torch.from_numpy(b.reshape(b.shape[0], -1)).to("cuda"))
+
+    def step(self, l):
+        import torch
+        out = []
+        for d, B in zip(self.system.domains, self.B):
+            A = torch.from_numpy(time_factors(d, self.system.dt, [l])).to("cuda")
+            out.append((A @ B).reshape((4,) + tuple(d.dims)).to(self.dtype).contiguous())
+        return out
+
+
+def cpu_sample_fn(system):
+    B = [spatial_factors(d, system.h, system.c) for d in system.domains]
+
+    def fn(n, j0, j1):
+        A = time_factors(system.domains[n], system.dt, np.arange(j0, j1 + 1))
+        nt = B[n].shape[0]
+        return (A @ B[n].reshape(nt, -1)).reshape(j1 - j0 + 1, 4, -1)
+
+    return fn

@@ -1,0 +1,139 @@
+"""Host-side checks of the C-ABI library: it loads, exports every declared
+symbol, and plans windows, pads and depths correctly (no GPU needed: planning
+makes no HIP call)."""
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_15429_amd import Plan, RpotError, load
+from synth import sources as sy
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+C_AU = 137.036
+
+
+def test_library_exports_every_declared_symbol():
+    lib = load()
+    header = open(os.path.join(ROOT, "include", "rpot.h")).read()
+    names = set(re.findall(r"^(?:rp_status|const char \*)\s*(rp_[a-z_]+)\s*\(", header, re.M))
+    assert {"rp_plan_domains", "rp_set_green_kernels", "rp_push_sources", "rp_retarded_step"} <= names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_config1_windows_pads_depth():
+    s = sy.config1(1)
+    p = Plan(s.dims, s.origins, s.h, s.dt, s.c, precision="fp64")
+    assert p.info(0, 0)[:2] == (0, 5) and p.info(1, 1)[:2] == (0, 5)
+    assert p.info(0, 1)[:2] == (8, 15) and p.info(1, 0)[:2] == (8, 15)
+    _, _, pad, depth = p.info(0, 1)
+    assert pad == (32, 32, 32) and depth == 16
+    st = p.stats()
+    assert st["n_triples"] == 28
+    assert st["n_spectra"] == 6 + 6 + 8           # reversed pair shares its spectra
+    assert st["points"] == 2 * 16 ** 3
+    assert st["lagsum_bytes"] > 0 and p.workspace_bytes > 0
+
+
+def _bruteforce_window(dt, dn, h, c, dt_):
+    pt = sy.grid_points(dt, h)
+    pn = sy.grid_points(dn, h)
+    R = np.linalg.norm(pt[:, None, :] - pn[None, :, :], axis=2)
+    x = R / (c * dt_)
+    return int(np.floor(x.min())), int(np.ceil(x.max()))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_windows_match_bruteforce(seed):
+    rng = np.random.default_rng(seed)
+    h, dt = 0.5, 0.02
+    doms = []
+    for i in range(3):
+        dims = tuple(int(v) for v in rng.integers(1, 6, size=3))
+        doms.append(sy.Domain(dims, np.array([9.0 * i, rng.uniform(-3, 3), rng.uniform(-3, 3)])))
+    p = Plan([d.dims for d in doms], [d.origin for d in doms], h, dt, C_AU, precision="fp32")
+    for s in range(3):
+        for n in range(3):
+            lo, hi, _, _ = p.info(s, n)
+            blo, bhi = _bruteforce_window(doms[s], doms[n], h, C_AU, dt)
+            if s == n:
+                assert lo == 0 and hi == max(bhi, 1)
+            else:
+                assert lo == blo and hi == bhi
+            rmin, rmax = oracle.box_distance_range(doms[s], doms[n], h)
+            assert lo <= rmin / (C_AU * dt) and hi >= rmax / (C_AU * dt)
+    for n in range(3):
+        assert p.info(0, n)[3] == max(p.info(s, n)[1] for s in range(3)) + 1
+
+
+def test_pads_are_even_smooth_and_cover_linear_convolution():
+    p = Plan([(20, 9, 20), (24, 8, 26), (12, 6, 14)],
+             [(0, 0, 0), (15, 3, -2), (-3, 12, 8)], 0.5, 0.02, C_AU)
+    pad = p.info(0, 1)[2]
+    assert pad == (48, 18, 54)
+
+
+def test_hartree_limit_plans_single_lag():
+    s = sy.config1(1)
+    p = Plan(s.dims, s.origins, s.h, s.dt, math.inf, precision="fp64")
+    for a in range(2):
+        for b in range(2):
+            assert p.info(a, b)[:2] == (0, 0)
+
+
+def test_systems_are_independent():
+    dims = [(4, 4, 4)] * 4
+    origins = [(0, 0, 0), (10, 0, 0), (0, 0, 0), (10, 0, 0)]   # overlap only across systems
+    p = Plan(dims, origins, 0.5, 0.02, C_AU, system_id=[0, 0, 1, 1])
+    assert p.info(0, 2)[:2] == (-1, -1)
+    assert p.info(0, 1)[0] >= 0 and p.info(2, 3)[0] >= 0
+
+
+def test_error_paths():
+    with pytest.raises(RpotError) as e:
+        Plan([(4, 4, 4), (4, 4, 4)], [(0, 0, 0), (1.0, 0, 0)], 0.5, 0.02, C_AU)
+    assert e.value.status == "RP_ERR_GEOMETRY"
+    with pytest.raises(RpotError) as e:
+        Plan(np.zeros((0, 3)), np.zeros((0, 3)), 0.5, 0.02, C_AU)
+    assert e.value.status == "RP_ERR_ARG"
+    with pytest.raises(RpotError) as e:
+        Plan([(4, 4, 4)], [(0, 0, 0)], 0.5, 0.001, C_AU)       # h sqrt3/2 >= c dt
+    assert e.value.status == "RP_ERR_UNSUPPORTED"
+    with pytest.raises(RpotError) as e:
+        Plan([(0, 4, 4)], [(0, 0, 0)], 0.5, 0.02, C_AU)
+    assert e.value.status == "RP_ERR_ARG"
+    with pytest.raises(RpotError) as e:
+        Plan([(300, 4, 4)], [(0, 0, 0)], 0.5, 0.02, C_AU)       # pad above 512
+    assert e.value.status == "RP_ERR_UNSUPPORTED"
+    p = Plan([(4, 4, 4)], [(0, 0, 0)], 0.5, 0.02, C_AU)
+    lib = load()
+    assert lib.rp_set_green_kernels(p._h) == 4               # RP_ERR_STATE: not bound
+    assert b"not bound" in lib.rp_last_error(p._h)
+    assert lib.rp_push_sources(p._h, 0, None) == 4
+
+
+def test_paper_run_windows_do_not_grow_with_distance():
+    """Two C12H4-sized domains (the paper's 20x20x50 a.u. boxes at h = 0.4,
+    dt = 1 as): the multi-domain cost (lag window of the cross pair) does not
+    grow with their distance, while the history depth follows d/(c dt)."""
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_runs.json")))["c12h4_dimer"]
+    h = g["h_au"]
+    dt = g["dt_as"] * 1e-18 / json.load(open(os.path.join(ROOT, "tests", "golden", "paper_runs.json")))[
+        "atomic_unit_of_time_s"]
+    n = [int(round(b / h)) for b in g["box_au"]]
+    widths, depths = [], []
+    for d in (g["d_sweep_au"][0] + 10, g["d_au"][0], 1000.0, g["d_au"][1]):
+        o2 = np.zeros(3)
+        o2[g["separation_axis"]] = d
+        p = Plan([n, n], [(0, 0, 0), o2], h, dt, C_AU)
+        lo, hi, pad, depth = p.info(0, 1)
+        widths.append(hi - lo + 1)
+        depths.append(depth)
+        assert pad == (108, 108, 256)
+    assert max(widths) == widths[0] and min(widths) >= 0.5 * widths[0]
+    assert depths[-1] > 1300 and depths[0] < 100

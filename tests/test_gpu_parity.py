@@ -1,0 +1,152 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Error per step and component: max over every point of every domain of
+|P_gpu - P_oracle| / max |P_oracle|.  Bars: 1e-10 in FP64, 2e-5 in FP32.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import log, rel_err, run_gpu
+from oracle_helpers import Charge, centred
+from synth import sources as sy
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FP64_TOL = 1e-10
+FP32_TOL = 2e-5
+
+
+def _samples(system, L):
+    return sy.sample_sources(system, range(L + 1))
+
+
+def _check(system, precision, L, tol, steps=None):
+    S = _samples(system, L)
+    steps = list(range(L + 1)) if steps is None else steps
+    log(f"[{system.name}] {precision}: GPU run of {L + 1} steps")
+    got = run_gpu(system, precision, S, collect=steps)
+    log(f"[{system.name}] oracle on {len(steps)} steps")
+    ref = oracle.potential_full(system, S, steps)
+    worst = 0.0
+    for i, l in enumerate(steps):
+        e = rel_err(got[l], ref[i])
+        worst = max(worst, float(e.max()))
+        assert np.all(e <= tol), (l, e)
+    log(f"[{system.name}] {precision}: worst rel err {worst:.3e}")
+    return got, ref
+
+
+def test_config1_fp64_every_step():
+    """2 x 16^3, h = 0.5, 30 bohr apart, dt = 0.02, 40 steps, FP64 <= 1e-10."""
+    _check(sy.config1(1), "fp64", 40, FP64_TOL)
+
+
+def test_config1_fp32_every_step():
+    _check(sy.config1(2), "fp32", 40, FP32_TOL)
+
+
+def _uneven_system(seed=4):
+    rng = np.random.default_rng(seed)
+    h = 0.5
+    doms = [sy.Domain((20, 9, 20), np.array([0.0, 0.0, 0.0])),
+            sy.Domain((24, 8, 26), np.array([15.0, 3.0, -2.0])),
+            sy.Domain((12, 6, 14), np.array([-3.0, 12.0, 8.0]))]
+    for d in doms:
+        lo = d.origin
+        hi = d.origin + h * (np.array(d.dims) - 1)
+        for _ in range(2):
+            d.charges.append(sy.Charge("pair", rng.uniform(0.8, 1.5), rng.uniform(lo, hi), rng.uniform(lo, hi),
+                                       ("cos", rng.uniform(0.1, 1), rng.uniform(0.1, 0.5), rng.uniform(0, 6.28))))
+    return sy.System(h, 0.02, sy.C_AU, doms, name="uneven 3 domains (pads 48x18x54)")
+
+
+def test_uneven_domains_radix3_ragged_fp32():
+    """Three domains of different shapes: pads (48, 18, 54) use radix 2, 3, 4;
+    the spectrum length 48*18*28 ends in a partial lag-sum tile."""
+    _check(_uneven_system(), "fp32", 24, FP32_TOL)
+
+
+def test_uneven_domains_fp64():
+    _check(_uneven_system(5), "fp64", 16, FP64_TOL)
+
+
+def test_hartree_limit_c_infinite_fp64():
+    s = sy.config1(3)
+    s.c = math.inf
+    s.name = "config1 geometry, c = inf"
+    _check(s, "fp64", 6, FP64_TOL)
+
+
+def test_degenerate_shapes_fp64():
+    """A 1-point domain, a flat (1 x 5 x 7) domain and a line, all coupled."""
+    h = 0.5
+    doms = [sy.Domain((1, 1, 1), np.array([0.0, 0.0, 0.0])),
+            sy.Domain((1, 5, 7), np.array([4.0, -1.0, 0.5])),
+            sy.Domain((6, 1, 1), np.array([-5.0, 2.0, 1.0]))]
+    rng = np.random.default_rng(9)
+    for d in doms:
+        d.charges.append(sy.Charge("single", 0.9, d.origin + rng.uniform(-0.3, 0.3, 3), None,
+                                   ("cos", 0.7, 0.4, 0.2)))
+    s = sy.System(h, 0.02, sy.C_AU, doms, name="degenerate shapes")
+    _check(s, "fp64", 10, FP64_TOL)
+
+
+def test_batched_systems_are_independent_fp64():
+    """Two systems in one plan equal two separate oracle runs."""
+    a = sy.config1(4)
+    b = _uneven_system(6)
+    both = sy.System(0.5, 0.02, sy.C_AU, a.domains + b.domains, system_id=[0, 0, 1, 1, 1],
+                     name="two systems")
+    L = 12
+    S = _samples(both, L)
+    got = run_gpu(both, "fp64", S)
+    ra = oracle.potential_full(a, S[:2], range(L + 1))
+    rb = oracle.potential_full(b, S[2:], range(L + 1))
+    for l in range(L + 1):
+        assert np.all(rel_err(got[l][:2], ra[l]) <= FP64_TOL)
+        assert np.all(rel_err(got[l][2:], rb[l]) <= FP64_TOL)
+
+
+def test_causality_exact_on_gpu():
+    """Sources only in domain A: domain B keeps exactly its static potential
+    until light from A can arrive, then changes."""
+    h, dt = 0.5, 0.02
+    A = centred((0, 0, 0), 8, h)
+    A.charges.append(Charge("pair", 0.9, np.array([0.5, 0.2, -0.3]), np.array([-0.6, -0.1, 0.4]),
+                            ("cos", 0.8, 0.4, 1.1)))
+    B = centred((25.0, 3.0, 0.0), 6, h)
+    s = sy.System(h, dt, sy.C_AU, [A, B], name="causality")
+    rmin, _ = oracle.box_distance_range(B, A, h)
+    x = rmin / (sy.C_AU * dt)
+    L = int(math.floor(x)) + 3
+    got = run_gpu(s, "fp64", _samples(s, L))
+    for l in range(L + 1):
+        same = np.array_equal(got[l][1], got[0][1])
+        assert same == (l <= math.floor(x)), l
+
+
+def test_time_shift_invariance_bitwise_fp64():
+    """Delaying every source by t0 steps delays the output exactly (bitwise)."""
+    s = sy.config1(5)
+    L, t0 = 20, 7
+    S = _samples(s, L)
+    Sd = [np.concatenate([np.repeat(x[:1], t0, axis=0), x], axis=0) for x in S]
+    a = run_gpu(s, "fp64", S)
+    b = run_gpu(s, "fp64", Sd)
+    for l in range(L + 1):
+        for n in range(2):
+            assert np.array_equal(a[l][n], b[l + t0][n]), (l, n)
+
+
+def test_deterministic_reruns_fp32():
+    s = _uneven_system(7)
+    S = _samples(s, 8)
+    a = run_gpu(s, "fp32", S)
+    b = run_gpu(s, "fp32", S)
+    for l in a:
+        for x, y in zip(a[l], b[l]):
+            assert np.array_equal(x, y)
