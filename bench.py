@@ -125,6 +125,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lagsum-unroll", type=int, default=None, choices=[1, 2, 4])
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -141,6 +144,8 @@ def main():
     workload = "8 sub-domains of 64^3 points, h=0.3 bohr, 400-bohr box, dt=0.01, FFT pad 128^3"
     stream = torch.cuda.current_stream()
     plan = plan_for_system(system, args.precision, stream=stream)
+    if args.lagsum_unroll:
+        plan.set_tuning("lagsum_unroll", args.lagsum_unroll)
     st = plan.stats()
     log(f"plan: triples/step {st['n_triples']}, spectra {st['n_spectra']}, ring reads/step {st['n_entries']}, "
         f"workspace {plan.workspace_bytes / 1e9:.1f} GB, lag-sum bytes/launch {st['lagsum_bytes'] / 1e9:.2f} GB")
@@ -178,6 +183,15 @@ def main():
     if not all(bool(torch.isfinite(o).all()) for o in outs):
         raise RuntimeError("non-finite output")
 
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del a, b
+
     ms_step = 1e3 * el / K
     updates = st["points"] * K / el
     lag_avg_s = lag_ms / launches / 1e3
@@ -206,7 +220,8 @@ def main():
         "config": {"workload": workload, "precision": args.precision, "sub_domains": 8, "grid": [64, 64, 64],
                    "h_bohr": 0.3, "dt_au": 0.01, "c_au": 137.036, "seed": args.seed,
                    "triples_per_step": st["n_triples"], "ring_reads_per_step": st["n_entries"],
-                   "green_setup_s": round(t_green, 3)},
+                   "green_setup_s": round(t_green, 3),
+                   "lagsum_unroll": plan.get_tuning("lagsum_unroll")},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -168,6 +168,16 @@ rp_status rp_plan_stats(rp_plan plan, rp_stats *out);
 rp_status rp_profile_lagsum(rp_plan plan, int32_t enable);
 rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
 
+/*
+ * Tuning knobs (schedule choices that never change results beyond rounding
+ * order; every value is valid for every plan).
+ *   RP_TUNE_LAGSUM_UNROLL  (source, lag) entries whose loads one lag-sum
+ *                          thread issues before accumulating: 1, 2 or 4.
+ */
+enum { RP_TUNE_LAGSUM_UNROLL = 1 };
+rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value);
+rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value);
+
 /* Release the host plan (the workspace stays the caller's). */
 rp_status rp_plan_destroy(rp_plan plan);
 

@@ -95,7 +95,63 @@ __device__ __forceinline__ Cx<double> load_spec(const Cx<double> *p) {
     return {v.x, v.y};
 }
 
+// Everything one (source, lag) entry contributes to a thread: the ring
+// snapshot of the source at that lag and the Green spectrum of every group
+// member fed by it.
+template <typename T, int TG>
+struct EntryData {
+    Cx<T> x[4];
+    Cx<T> g[TG];
+    uint32_t mask;
+};
+
 template <typename T, int FMT, int TG>
+__device__ __forceinline__ void load_entry(const K2Args &a, const K2Entry &en, int64_t l, int64_t C, int64_t k,
+                                           const Cx<T> *__restrict__ spec, EntryData<T, TG> &d) {
+    const DomDev &dd = a.doms[en.src];
+    int64_t slot = (l - en.m) % dd.depth;
+    if (slot < 0) slot += dd.depth;
+    float sc[4] = {1.f, 1.f, 1.f, 1.f};
+    if (FMT == RING_F16 || FMT == RING_BF16) {
+        const float *s = a.scales + dd.scale_off + slot * 4;
+        sc[0] = s[0];
+        sc[1] = s[1];
+        sc[2] = s[2];
+        sc[3] = s[3];
+    }
+    RingLoad<T, FMT>::get(a.ring, dd.ring_off + (slot * C + k) * 4, sc, d.x);
+    d.mask = en.mask;
+    const uint32_t cj = en.conj;
+#pragma unroll
+    for (int t = 0; t < TG; ++t) {
+        if (en.mask & (1u << t)) {
+            d.g[t] = load_spec(spec + int64_t(en.spec[t]) * C);
+            if (cj & (1u << t)) d.g[t].y = -d.g[t].y;
+        }
+    }
+}
+
+template <typename T, int TG>
+__device__ __forceinline__ void mac_entry(const EntryData<T, TG> &d, Cx<T> (&acc)[TG][4]) {
+#pragma unroll
+    for (int t = 0; t < TG; ++t) {
+        if (d.mask & (1u << t)) {
+            const Cx<T> gv = d.g[t];
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) {
+                acc[t][mu].x = fma(gv.x, d.x[mu].x, acc[t][mu].x);
+                acc[t][mu].x = fma(-gv.y, d.x[mu].y, acc[t][mu].x);
+                acc[t][mu].y = fma(gv.x, d.x[mu].y, acc[t][mu].y);
+                acc[t][mu].y = fma(gv.y, d.x[mu].x, acc[t][mu].y);
+            }
+        }
+    }
+}
+
+// U entries are loaded before any of them is accumulated, so a wave keeps U
+// entries' worth of loads in flight (the kernel is bound by memory-level
+// parallelism, not by arithmetic).
+template <typename T, int FMT, int TG, int U>
 __global__ __launch_bounds__(256) void k_lagsum(K2Args a) {
     const K2Item item = a.items[blockIdx.x];
     const K2Group &g = a.groups[item.group];
@@ -111,37 +167,20 @@ __global__ __launch_bounds__(256) void k_lagsum(K2Args a) {
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) acc[t][mu] = {T(0), T(0)};
 
-    for (int e = g.entry_begin; e < g.entry_end; ++e) {
-        const K2Entry &en = a.entries[e];
-        const DomDev &dd = a.doms[en.src];
-        int64_t slot = (l - en.m) % dd.depth;
-        if (slot < 0) slot += dd.depth;
-        float sc[4] = {1.f, 1.f, 1.f, 1.f};
-        if (FMT == RING_F16 || FMT == RING_BF16) {
-            const float *s = a.scales + dd.scale_off + slot * 4;
-            sc[0] = s[0];
-            sc[1] = s[1];
-            sc[2] = s[2];
-            sc[3] = s[3];
-        }
-        Cx<T> x[4];
-        RingLoad<T, FMT>::get(a.ring, dd.ring_off + (slot * C + k) * 4, sc, x);
-        const uint32_t mask = en.mask, cj = en.conj;
+    int e = g.entry_begin;
+    for (; e + U <= g.entry_end; e += U) {
+        EntryData<T, TG> d[U];
 #pragma unroll
-        for (int t = 0; t < TG; ++t) {
-            if (mask & (1u << t)) {
-                Cx<T> gv = load_spec(spec + int64_t(en.spec[t]) * C);
-                if (cj & (1u << t)) gv.y = -gv.y;
+        for (int u = 0; u < U; ++u) load_entry<T, FMT, TG>(a, a.entries[e + u], l, C, k, spec, d[u]);
 #pragma unroll
-                for (int mu = 0; mu < 4; ++mu) {
-                    acc[t][mu].x = fma(gv.x, x[mu].x, acc[t][mu].x);
-                    acc[t][mu].x = fma(-gv.y, x[mu].y, acc[t][mu].x);
-                    acc[t][mu].y = fma(gv.x, x[mu].y, acc[t][mu].y);
-                    acc[t][mu].y = fma(gv.y, x[mu].x, acc[t][mu].y);
-                }
-            }
-        }
+        for (int u = 0; u < U; ++u) mac_entry<T, TG>(d[u], acc);
     }
+    for (; e < g.entry_end; ++e) {
+        EntryData<T, TG> d;
+        load_entry<T, FMT, TG>(a, a.entries[e], l, C, k, spec, d);
+        mac_entry<T, TG>(d, acc);
+    }
+
     Cx<T> *__restrict__ out = reinterpret_cast<Cx<T> *>(a.acc);
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
@@ -153,27 +192,36 @@ __global__ __launch_bounds__(256) void k_lagsum(K2Args a) {
     }
 }
 
-template <typename T, int FMT>
-static void launch_tg(const K2Args &a, int tg, hipStream_t st) {
+template <typename T, int FMT, int TG>
+static void launch_u(const K2Args &a, int unroll, hipStream_t st) {
     dim3 grid(a.n_items), block(256);
-    switch (tg) {
-    case 1: hipLaunchKernelGGL((k_lagsum<T, FMT, 1>), grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_lagsum<T, FMT, 2>), grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_lagsum<T, FMT, 4>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_lagsum<T, FMT, 8>), grid, block, 0, st, a); break;
+    switch (unroll) {
+    case 1: hipLaunchKernelGGL((k_lagsum<T, FMT, TG, 1>), grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_lagsum<T, FMT, TG, 4>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_lagsum<T, FMT, TG, 2>), grid, block, 0, st, a); break;
     }
 }
 
-void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, hipStream_t st) {
+template <typename T, int FMT>
+static void launch_tg(const K2Args &a, int tg, int unroll, hipStream_t st) {
+    switch (tg) {
+    case 1: launch_u<T, FMT, 1>(a, unroll, st); break;
+    case 2: launch_u<T, FMT, 2>(a, unroll, st); break;
+    case 4: launch_u<T, FMT, 4>(a, unroll, st); break;
+    default: launch_u<T, FMT, 8>(a, unroll, st); break;
+    }
+}
+
+void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, int unroll, hipStream_t st) {
     if (a.n_items == 0) return;
     if (prec64) {
-        launch_tg<double, RING_F64>(a, tg, st);
+        launch_tg<double, RING_F64>(a, tg, unroll, st);
     } else if (ring_fmt == RING_F16) {
-        launch_tg<float, RING_F16>(a, tg, st);
+        launch_tg<float, RING_F16>(a, tg, unroll, st);
     } else if (ring_fmt == RING_BF16) {
-        launch_tg<float, RING_BF16>(a, tg, st);
+        launch_tg<float, RING_BF16>(a, tg, unroll, st);
     } else {
-        launch_tg<float, RING_F32>(a, tg, st);
+        launch_tg<float, RING_F32>(a, tg, unroll, st);
     }
 }
 

@@ -123,6 +123,7 @@ struct rp_plan_s {
     std::vector<K2Item> items;
     std::vector<DomDev> domdev;
     int tg = 1;
+    int k2_unroll = 2;   // entries whose loads a lag-sum thread issues together
 
     std::map<int, size_t> tw64, tw32;   // FFT length -> byte offset of its twiddles
     size_t off_state = 0, off_items = 0, off_groups = 0, off_entries = 0, off_domdev = 0;
@@ -824,7 +825,7 @@ void do_step(rp_plan p, int64_t step, void *const *out) {
         }
         HIP_OK(hipEventRecord(p->events[2 * p->n_recorded], st));
     }
-    launch_lagsum(k, p->p64, p->ring_fmt, p->tg, st);
+    launch_lagsum(k, p->p64, p->ring_fmt, p->tg, p->k2_unroll, st);
     check_launch();
     if (p->profile) {
         HIP_OK(hipEventRecord(p->events[2 * p->n_recorded + 1], st));
@@ -1017,6 +1018,29 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches) {
         if (total_ms) *total_ms = tot;
         if (launches) *launches = int64_t(plan->n_recorded);
         plan->n_recorded = 0;
+    });
+}
+
+rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value) {
+    return guarded(plan, [&] {
+        switch (knob) {
+        case RP_TUNE_LAGSUM_UNROLL:
+            if (value != 1 && value != 2 && value != 4) fail(RP_ERR_ARG, "lag-sum unroll must be 1, 2 or 4");
+            plan->k2_unroll = value;
+            break;
+        default:
+            fail(RP_ERR_ARG, "unknown tuning knob");
+        }
+    });
+}
+
+rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value) {
+    return guarded(plan, [&] {
+        if (!value) fail(RP_ERR_ARG, "value is null");
+        switch (knob) {
+        case RP_TUNE_LAGSUM_UNROLL: *value = plan->k2_unroll; break;
+        default: fail(RP_ERR_ARG, "unknown tuning knob");
+        }
     });
 }
 

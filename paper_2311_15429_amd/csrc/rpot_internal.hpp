@@ -149,7 +149,7 @@ void launch_line_pass(const LinePass &a, int prec64, hipStream_t st);
 void launch_zfwd(const ZFwd &a, int prec64, hipStream_t st);
 void launch_zinv(const ZInv &a, int prec64, hipStream_t st);
 int zfwd_lines_per_block(int Pz, int prec64);
-void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, hipStream_t st);
+void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, int unroll, hipStream_t st);
 // Per-snapshot ring scales: for each job, scales[(step mod depth)*4 + mu] =
 // 2^(e-15) with npts * max_blocks zmax[b][mu] <= 2^e (1 when the max is 0).
 struct ScaleJob {

@@ -129,6 +129,14 @@ class Plan:
         _lib.check(self._lib, self._h, self._lib.rp_lagsum_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
 
+    def set_tuning(self, knob, value):
+        _lib.check(self._lib, self._h, self._lib.rp_set_tuning(self._h, _lib.TUNE[knob], int(value)))
+
+    def get_tuning(self, knob):
+        v = ctypes.c_int32()
+        _lib.check(self._lib, self._h, self._lib.rp_get_tuning(self._h, _lib.TUNE[knob], ctypes.byref(v)))
+        return int(v.value)
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.rp_plan_destroy(self._h)
