@@ -187,12 +187,10 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
 
     void *obase = job.out;
     const float *qs = job.qscale;
-    if (a.step) {
-        const int64_t slot = (*a.step) % job.depth;
-        if (job.slot_stride) {
-            constexpr int esz = (FMT == RING_F64) ? 16 : ((FMT == RING_F32) ? 8 : 4);
-            obase = reinterpret_cast<char *>(obase) + slot * job.slot_stride * esz;
-        }
+    if (job.head) {
+        const int64_t slot = *job.head;
+        constexpr int esz = (FMT == RING_F64) ? 16 : ((FMT == RING_F32) ? 8 : 4);
+        obase = reinterpret_cast<char *>(obase) + slot * job.slot_stride * esz;
         if (qs) qs += slot * 4;
     }
     const bool jfast_out = (a.out_j == 1);
@@ -213,8 +211,13 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
             float inv_scale = 1.0f;
             // the component is the fastest batch index (inner mod 4)
             if (FMT == RING_F16 || FMT == RING_BF16) inv_scale = 1.0f / qs[inner & 3];
-            Store<T, FMT>::put(obase, outer * a.out_outer + inner * a.out_inner + int64_t(j) * a.out_j,
-                               buf[li * P + j], inv_scale);
+            int64_t idx = outer * a.out_outer + inner * a.out_inner + int64_t(j) * a.out_j;
+            if (job.tile_stride) {
+                const int64_t kk = idx / a.tile_comp;
+                const int64_t c = idx - kk * a.tile_comp;
+                idx = (kk / kTile) * job.tile_stride + (kk % kTile) * a.tile_comp + c;
+            }
+            Store<T, FMT>::put(obase, idx, buf[li * P + j], inv_scale);
         }
     }
 }

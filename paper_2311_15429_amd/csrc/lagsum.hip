@@ -31,35 +31,54 @@ typedef unsigned nu4 __attribute__((ext_vector_type(4)));
 template <typename T, int FMT>
 struct RingLoad;
 
+// All lag-sum loads are raw buffer loads: the resource (base address and
+// size of one tile row of a ring snapshot or of a Green spectrum) is uniform
+// and lives in scalar registers, the per-lane byte offset is loop-invariant.
+// No vector register is rewritten between the loads of one entry, and every
+// access is bounds-checked by the hardware against the row size.
+typedef unsigned nu2 __attribute__((ext_vector_type(2)));
+constexpr int kRsrcWord3 = 0x00020000;   // gfx9-family buffer descriptor word 3
+constexpr int kLoadAux = 0;              // cache policy bits of the loads
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const char *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(base), (short)0, bytes, kRsrcWord3);
+}
+
+__device__ __forceinline__ nu4 ld128(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(nu4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kLoadAux));
+}
+__device__ __forceinline__ nu2 ld64(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(nu2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kLoadAux));
+}
+
 template <>
 struct RingLoad<double, RING_F64> {
-    __device__ static void get(const void *ring, int64_t idx, const float *, Cx<double> (&x)[4]) {
-        const nd4 *p = reinterpret_cast<const nd4 *>(reinterpret_cast<const Cx<double> *>(ring) + idx);
-        const nd4 a = __builtin_nontemporal_load(p);
-        const nd4 b = __builtin_nontemporal_load(p + 1);
-        x[0] = {a.x, a.y};
-        x[1] = {a.z, a.w};
-        x[2] = {b.x, b.y};
-        x[3] = {b.z, b.w};
+    static constexpr int row_bytes = kTile * 4 * 16;
+    __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *, Cx<double> (&x)[4]) {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const nu4 v = ld128(r, lane * 64 + mu * 16);
+            x[mu] = {__builtin_bit_cast(double, nu2{v.x, v.y}), __builtin_bit_cast(double, nu2{v.z, v.w})};
+        }
     }
 };
 template <>
 struct RingLoad<float, RING_F32> {
-    __device__ static void get(const void *ring, int64_t idx, const float *, Cx<float> (&x)[4]) {
-        const nf4 *p = reinterpret_cast<const nf4 *>(reinterpret_cast<const Cx<float> *>(ring) + idx);
-        const nf4 a = __builtin_nontemporal_load(p);
-        const nf4 b = __builtin_nontemporal_load(p + 1);
-        x[0] = {a.x, a.y};
-        x[1] = {a.z, a.w};
-        x[2] = {b.x, b.y};
-        x[3] = {b.z, b.w};
+    static constexpr int row_bytes = kTile * 4 * 8;
+    __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *, Cx<float> (&x)[4]) {
+        const nu4 a = ld128(r, lane * 32);
+        const nu4 b = ld128(r, lane * 32 + 16);
+        x[0] = {__uint_as_float(a.x), __uint_as_float(a.y)};
+        x[1] = {__uint_as_float(a.z), __uint_as_float(a.w)};
+        x[2] = {__uint_as_float(b.x), __uint_as_float(b.y)};
+        x[3] = {__uint_as_float(b.z), __uint_as_float(b.w)};
     }
 };
 template <>
 struct RingLoad<float, RING_F16> {
-    __device__ static void get(const void *ring, int64_t idx, const float *sc, Cx<float> (&x)[4]) {
-        const nu4 *p = reinterpret_cast<const nu4 *>(reinterpret_cast<const __half2 *>(ring) + idx);
-        const nu4 v = __builtin_nontemporal_load(p);
+    static constexpr int row_bytes = kTile * 4 * 4;
+    __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *sc, Cx<float> (&x)[4]) {
+        const nu4 v = ld128(r, lane * 16);
         const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
@@ -72,9 +91,9 @@ struct RingLoad<float, RING_F16> {
 };
 template <>
 struct RingLoad<float, RING_BF16> {
-    __device__ static void get(const void *ring, int64_t idx, const float *sc, Cx<float> (&x)[4]) {
-        const nu4 *p = reinterpret_cast<const nu4 *>(reinterpret_cast<const unsigned *>(ring) + idx);
-        const nu4 v = __builtin_nontemporal_load(p);
+    static constexpr int row_bytes = kTile * 4 * 4;
+    __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *sc, Cx<float> (&x)[4]) {
+        const nu4 v = ld128(r, lane * 16);
         const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
@@ -86,80 +105,87 @@ struct RingLoad<float, RING_BF16> {
     }
 };
 
-__device__ __forceinline__ Cx<float> load_spec(const Cx<float> *p) {
-    const nf2 v = __builtin_nontemporal_load(reinterpret_cast<const nf2 *>(p));
-    return {v.x, v.y};
+template <typename T>
+__device__ __forceinline__ Cx<T> load_spec(__amdgpu_buffer_rsrc_t r, int lane);
+template <>
+__device__ __forceinline__ Cx<float> load_spec<float>(__amdgpu_buffer_rsrc_t r, int lane) {
+    const nu2 v = ld64(r, lane * 8);
+    return {__uint_as_float(v.x), __uint_as_float(v.y)};
 }
-__device__ __forceinline__ Cx<double> load_spec(const Cx<double> *p) {
-    const nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2 *>(p));
-    return {v.x, v.y};
-}
-
-// Everything one (source, lag) entry contributes to a thread: the ring
-// snapshot of the source at that lag and the Green spectrum of every group
-// member fed by it.
-template <typename T, int TG>
-struct EntryData {
-    Cx<T> x[4];
-    Cx<T> g[TG];
-    uint32_t mask;
-};
-
-template <typename T, int FMT, int TG>
-__device__ __forceinline__ void load_entry(const K2Args &a, const K2Entry &en, int64_t l, int64_t C, int64_t k,
-                                           const Cx<T> *__restrict__ spec, EntryData<T, TG> &d) {
-    const DomDev &dd = a.doms[en.src];
-    int64_t slot = (l - en.m) % dd.depth;
-    if (slot < 0) slot += dd.depth;
-    float sc[4] = {1.f, 1.f, 1.f, 1.f};
-    if (FMT == RING_F16 || FMT == RING_BF16) {
-        const float *s = a.scales + dd.scale_off + slot * 4;
-        sc[0] = s[0];
-        sc[1] = s[1];
-        sc[2] = s[2];
-        sc[3] = s[3];
-    }
-    RingLoad<T, FMT>::get(a.ring, dd.ring_off + (slot * C + k) * 4, sc, d.x);
-    d.mask = en.mask;
-    const uint32_t cj = en.conj;
-#pragma unroll
-    for (int t = 0; t < TG; ++t) {
-        if (en.mask & (1u << t)) {
-            d.g[t] = load_spec(spec + int64_t(en.spec[t]) * C);
-            if (cj & (1u << t)) d.g[t].y = -d.g[t].y;
-        }
-    }
+template <>
+__device__ __forceinline__ Cx<double> load_spec<double>(__amdgpu_buffer_rsrc_t r, int lane) {
+    const nu4 v = ld128(r, lane * 16);
+    return {__builtin_bit_cast(double, nu2{v.x, v.y}), __builtin_bit_cast(double, nu2{v.z, v.w})};
 }
 
 template <typename T, int TG>
-__device__ __forceinline__ void mac_entry(const EntryData<T, TG> &d, Cx<T> (&acc)[TG][4]) {
+__device__ __forceinline__ void mac_entry(Cx<T> (&acc)[TG][4], uint32_t mask, uint32_t conj, const Cx<T> (&g)[TG],
+                                          const Cx<T> (&x)[4]) {
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
-        if (d.mask & (1u << t)) {
-            const Cx<T> gv = d.g[t];
+        if (mask & (1u << t)) {
+            const T gx = g[t].x;
+            const T gy = ((conj >> t) & 1u) ? -g[t].y : g[t].y;
 #pragma unroll
             for (int mu = 0; mu < 4; ++mu) {
-                acc[t][mu].x = fma(gv.x, d.x[mu].x, acc[t][mu].x);
-                acc[t][mu].x = fma(-gv.y, d.x[mu].y, acc[t][mu].x);
-                acc[t][mu].y = fma(gv.x, d.x[mu].y, acc[t][mu].y);
-                acc[t][mu].y = fma(gv.y, d.x[mu].x, acc[t][mu].y);
+                acc[t][mu].x = fma(gx, x[mu].x, acc[t][mu].x);
+                acc[t][mu].x = fma(-gy, x[mu].y, acc[t][mu].x);
+                acc[t][mu].y = fma(gx, x[mu].y, acc[t][mu].y);
+                acc[t][mu].y = fma(gy, x[mu].x, acc[t][mu].y);
             }
         }
     }
 }
 
-// U entries are loaded before any of them is accumulated, so a wave keeps U
-// entries' worth of loads in flight (the kernel is bound by memory-level
-// parallelism, not by arithmetic).
+template <int FMT>
+struct RingEsz {
+    static constexpr int v = (FMT == RING_F64) ? 16 : ((FMT == RING_F32) ? 8 : 4);
+};
+
+// The lag sum walks, for every source of the group, the lags m of the union of
+// the members' windows [m_lo(t,n), m_hi(t,n)].  Storage is tile-major (one
+// block = one frequency tile), so for fixed source and member the ring row and
+// the spectrum row of lag m + 1 sit next to those of lag m:
+//   ring row     = ring(n) + (tile * depth + slot(m)) * row,  slot(m) = (head(n) - m) mod depth
+//   spectrum row = spec + (row0 + tile * w + m) * row
+// All of it is uniform and advanced on the scalar unit; the lane offset is a
+// fixed vector register.  U consecutive lags are loaded before any of them is
+// accumulated.
+template <typename T, int FMT, int TG>
+__device__ __forceinline__ uint32_t load_lag(const K2Args &a, const char *ring_tile, int32_t slot, int64_t scale_off,
+                                             const char *spec, const int32_t (&r)[TG], uint32_t mk, int m, int lane,
+                                             Cx<T> (&x)[4], Cx<T> (&gv)[TG]) {
+    constexpr int64_t ring_row = int64_t(kTile) * 4 * RingEsz<FMT>::v;
+    constexpr int64_t spec_row = int64_t(kTile) * int64_t(sizeof(Cx<T>));
+    if (mk) {
+        float sc[4] = {1.f, 1.f, 1.f, 1.f};
+        if (FMT == RING_F16 || FMT == RING_BF16) {
+            const float *s4 = a.scales + scale_off + int64_t(slot) * 4;
+            sc[0] = s4[0];
+            sc[1] = s4[1];
+            sc[2] = s4[2];
+            sc[3] = s4[3];
+        }
+        RingLoad<T, FMT>::get(row_rsrc(ring_tile + slot * ring_row, int(ring_row)), lane, sc, x);
+#pragma unroll
+        for (int t = 0; t < TG; ++t)
+            if (mk & (1u << t)) gv[t] = load_spec<T>(row_rsrc(spec + int64_t(r[t] + m) * spec_row, int(spec_row)), lane);
+    }
+    return mk;
+}
+
 template <typename T, int FMT, int TG, int U>
 __global__ __launch_bounds__(256) void k_lagsum(K2Args a) {
+    constexpr int esz = RingEsz<FMT>::v;
+    constexpr int64_t ring_row = int64_t(kTile) * 4 * esz;
     const K2Item item = a.items[blockIdx.x];
     const K2Group &g = a.groups[item.group];
-    const int64_t C = g.C;
-    const int64_t k = int64_t(item.k0) + threadIdx.x;
-    if (k >= C) return;
-    const int64_t l = *a.step;
-    const Cx<T> *__restrict__ spec = reinterpret_cast<const Cx<T> *>(a.spectra) + g.spec_base + k;
+    const int lane = threadIdx.x;
+    const int64_t k = int64_t(item.k0) + lane;
+    if (k >= g.C) return;
+    const int32_t tile = item.k0 / kTile;
+    const char *spec = reinterpret_cast<const char *>(a.spectra) + g.spec_base * int64_t(sizeof(Cx<T>));
+    const char *ring = reinterpret_cast<const char *>(a.ring);
 
     Cx<T> acc[TG][4];
 #pragma unroll
@@ -167,18 +193,46 @@ __global__ __launch_bounds__(256) void k_lagsum(K2Args a) {
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) acc[t][mu] = {T(0), T(0)};
 
-    int e = g.entry_begin;
-    for (; e + U <= g.entry_end; e += U) {
-        EntryData<T, TG> d[U];
+    for (int si = g.src_begin; si < g.src_end; ++si) {
+        const K2Src &R = a.srcs[si];
+        const int m_min = R.m_min, m_max = R.m_max, depth = R.depth;
+        if (m_max < m_min) continue;
+        const uint32_t conj = R.conj;
+        const uint32_t *masks = a.masks + R.mask_off - m_min;
+        int32_t r[TG];
 #pragma unroll
-        for (int u = 0; u < U; ++u) load_entry<T, FMT, TG>(a, a.entries[e + u], l, C, k, spec, d[u]);
+        for (int t = 0; t < TG; ++t) {
+            const K2Pair &Q = a.pairs[si * 8 + t];
+            r[t] = Q.row0 + tile * Q.w;
+        }
+        const char *ring_tile = ring + (R.ring_off * esz + int64_t(tile) * depth * ring_row);
+        int64_t scale_off = 0;
+        if (FMT == RING_F16 || FMT == RING_BF16) scale_off = a.doms[R.n].scale_off;
+        int32_t slot = a.head[R.n] - m_min;
+        if (slot < 0) slot += depth;
+
+        int m = m_min;
+        for (; m + U - 1 <= m_max; m += U) {
+            Cx<T> x[U][4];
+            Cx<T> gv[U][TG];
+            uint32_t mask[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) mac_entry<T, TG>(d[u], acc);
-    }
-    for (; e < g.entry_end; ++e) {
-        EntryData<T, TG> d;
-        load_entry<T, FMT, TG>(a, a.entries[e], l, C, k, spec, d);
-        mac_entry<T, TG>(d, acc);
+            for (int u = 0; u < U; ++u) {
+                mask[u] = load_lag<T, FMT, TG>(a, ring_tile, slot, scale_off, spec, r, masks[m + u], m + u, lane,
+                                               x[u], gv[u]);
+                slot = (slot == 0) ? depth - 1 : slot - 1;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (mask[u]) mac_entry<T, TG>(acc, mask[u], conj, gv[u], x[u]);
+        }
+        for (; m <= m_max; ++m) {
+            Cx<T> x[4];
+            Cx<T> gv[TG];
+            const uint32_t mk = load_lag<T, FMT, TG>(a, ring_tile, slot, scale_off, spec, r, masks[m], m, lane, x, gv);
+            if (mk) mac_entry<T, TG>(acc, mk, conj, gv, x);
+            slot = (slot == 0) ? depth - 1 : slot - 1;
+        }
     }
 
     Cx<T> *__restrict__ out = reinterpret_cast<Cx<T> *>(a.acc);
@@ -241,8 +295,7 @@ __global__ void k_ring_scale(ScaleArgs a) {
             frexp(bound, &e);              // bound <= 2^e
             s = ldexpf(1.0f, e - 15);      // |value| / s <= 2^15 < FP16 max
         }
-        const int64_t slot = (*a.step) % j.depth;
-        j.scales[slot * 4 + mu] = s;
+        j.scales[int64_t(*j.head) * 4 + mu] = s;
     }
 }
 
@@ -308,12 +361,16 @@ void launch_fill_zero(void *dst, size_t bytes, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_zero, dim3(unsigned(nb)), dim3(256), 0, st, reinterpret_cast<uint4 *>(dst), n16);
 }
 
-__global__ void k_advance_step(int64_t *step) {
+__global__ void k_advance_step(int64_t *step, int32_t *head, const DomDev *doms, int n_dom) {
+    for (int i = threadIdx.x; i < n_dom; i += blockDim.x) {
+        const int32_t h = head[i] + 1;
+        head[i] = (h == doms[i].depth) ? 0 : h;
+    }
     if (threadIdx.x == 0) *step += 1;
 }
 
-void launch_advance_step(int64_t *step, hipStream_t st) {
-    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(64), 0, st, step);
+void launch_advance_step(int64_t *step, int32_t *head, const DomDev *doms, int n_dom, hipStream_t st) {
+    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(256), 0, st, step, head, doms, n_dom);
 }
 
 }  // namespace rpot

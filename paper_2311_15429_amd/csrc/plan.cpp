@@ -40,7 +40,6 @@ struct Error {
     } while (0)
 
 constexpr int kGroupMax = 8;      // targets per lag-sum thread
-constexpr int kK2Tile = 256;      // frequencies per lag-sum block
 constexpr int kGreenChunk = kMaxJobs;
 constexpr int kMaxPad = 512;     // z passes stage >= 4 lines of the pad in 32 KiB of LDS
 constexpr size_t kAlign = 256;
@@ -82,14 +81,17 @@ struct SystemP {
     int P[3];
     int Hz;
     int64_t C;
+    int64_t Cpad;            // C rounded up to whole frequency tiles
     int64_t spec_base = 0;   // complex elements
-    int64_t n_spec = 0;
+    int64_t n_spec = 0;      // stored spectra (one per lag of every unordered pair)
+    int64_t spec_elems = 0;  // their storage, tile-major per pair
 };
 
 struct PairP {
     int m_lo = -1, m_hi = -1;
     double rmin = 0, rmax = 0;
-    int64_t spec0 = -1;      // spectrum index (within the system) of lag m_lo
+    int64_t spec0 = -1;      // element offset (within the system) of the pair's spectra,
+                             // stored [tile][lag][kTile]
     bool conj = false;
 };
 
@@ -120,13 +122,17 @@ struct rp_plan_s {
 
     std::vector<K2Group> groups;
     std::vector<K2Entry> entries;
+    std::vector<K2Src> srcs;
+    std::vector<K2Pair> pairs;
+    std::vector<uint32_t> masks;
     std::vector<K2Item> items;
     std::vector<DomDev> domdev;
     int tg = 1;
-    int k2_unroll = 2;   // entries whose loads a lag-sum thread issues together
+    int k2_unroll = 1;   // entries whose loads a lag-sum thread issues together
 
     std::map<int, size_t> tw64, tw32;   // FFT length -> byte offset of its twiddles
-    size_t off_state = 0, off_items = 0, off_groups = 0, off_entries = 0, off_domdev = 0;
+    size_t off_state = 0, off_head = 0, off_items = 0, off_groups = 0, off_entries = 0, off_domdev = 0;
+    size_t off_srcs = 0, off_pairs = 0, off_masks = 0;
     size_t off_spec = 0, off_gtmp = 0, off_accd = 0, off_gstat = 0, off_t1d = 0, off_t2d = 0;
     size_t off_s0d = 0, off_p0d = 0;
     size_t ws_bytes = 0;
@@ -214,6 +220,7 @@ void plan_build(rp_plan p, const int32_t *dims, const double *origins, const int
         }
         S.Hz = S.P[2] / 2 + 1;
         S.C = int64_t(S.P[0]) * S.P[1] * S.Hz;
+        S.Cpad = (S.C + kTile - 1) / kTile * kTile;
     }
 
     // windows
@@ -254,14 +261,15 @@ void plan_build(rp_plan p, const int32_t *dims, const double *origins, const int
     int64_t spec_base = 0;
     for (SystemP &S : p->sys) {
         S.spec_base = spec_base;
-        int64_t cnt = 0;
+        int64_t cnt = 0, nsp = 0;
         for (size_t a = 0; a < S.doms.size(); ++a) {
             for (size_t b = a; b < S.doms.size(); ++b) {
                 const int s = S.doms[a], n = S.doms[b];
                 PairP &q = p->pr(s, n);
                 q.spec0 = cnt;
                 q.conj = false;
-                cnt += q.m_hi - q.m_lo + 1;
+                cnt += int64_t(q.m_hi - q.m_lo + 1) * S.Cpad;
+                nsp += q.m_hi - q.m_lo + 1;
                 if (s != n) {
                     PairP &r = p->pr(n, s);
                     r.spec0 = q.spec0;
@@ -269,8 +277,10 @@ void plan_build(rp_plan p, const int32_t *dims, const double *origins, const int
                 }
             }
         }
-        S.n_spec = cnt;
-        spec_base += cnt * S.C;
+        S.n_spec = nsp;
+        S.spec_elems = cnt;
+        spec_base += cnt;
+        if (cnt / kTile > int64_t(INT32_MAX)) fail(RP_ERR_UNSUPPORTED, "Green spectra table too large");
     }
 
     // lag-sum schedule
@@ -285,7 +295,34 @@ void plan_build(rp_plan p, const int32_t *dims, const double *origins, const int
             for (int t = 0; t < G.n_members; ++t) G.member[t] = S.doms[g0 + t];
             max_members = std::max(max_members, G.n_members);
             G.entry_begin = int(p->entries.size());
+            G.src_begin = int(p->srcs.size());
             for (int n : S.doms) {
+                K2Src R{};
+                R.n = n;
+                R.m_min = INT32_MAX;
+                R.m_max = -1;
+                for (int t = 0; t < kGroupMax; ++t) {
+                    K2Pair Q{};
+                    if (t < G.n_members) {
+                        const PairP &q = p->pr(G.member[t], n);
+                        Q.row0 = int32_t(q.spec0 / kTile) - q.m_lo;
+                        Q.w = q.m_hi - q.m_lo + 1;
+                        if (q.conj) R.conj |= 1u << t;
+                        R.m_min = std::min(R.m_min, q.m_lo);
+                        R.m_max = std::max(R.m_max, q.m_hi);
+                    }
+                    p->pairs.push_back(Q);
+                }
+                R.mask_off = int32_t(p->masks.size());
+                for (int m = R.m_min; m <= R.m_max; ++m) {
+                    uint32_t mk = 0;
+                    for (int t = 0; t < G.n_members; ++t) {
+                        const PairP &q = p->pr(G.member[t], n);
+                        if (m >= q.m_lo && m <= q.m_hi) mk |= 1u << t;
+                    }
+                    p->masks.push_back(mk);
+                }
+                p->srcs.push_back(R);
                 std::vector<int> ms;
                 for (int t = 0; t < G.n_members; ++t) {
                     const PairP &q = p->pr(G.member[t], n);
@@ -302,15 +339,17 @@ void plan_build(rp_plan p, const int32_t *dims, const double *origins, const int
                         if (m < q.m_lo || m > q.m_hi) continue;
                         E.mask |= 1u << t;
                         if (q.conj) E.conj |= 1u << t;
-                        E.spec[t] = int32_t(q.spec0 + (m - q.m_lo));
+                        E.spec_tile[t] = int32_t(q.spec0 / kTile + (m - q.m_lo));
+                        E.spec_w[t] = q.m_hi - q.m_lo + 1;
                     }
                     p->entries.push_back(E);
                 }
             }
             G.entry_end = int(p->entries.size());
+            G.src_end = int(p->srcs.size());
             const int gi = int(p->groups.size());
             p->groups.push_back(G);
-            for (int64_t k0 = 0; k0 < S.C; k0 += kK2Tile) p->items.push_back(K2Item{gi, int32_t(k0)});
+            for (int64_t k0 = 0; k0 < S.C; k0 += kTile) p->items.push_back(K2Item{gi, int32_t(k0)});
         }
     }
     p->tg = max_members <= 1 ? 1 : (max_members <= 2 ? 2 : (max_members <= 4 ? 4 : 8));
@@ -349,10 +388,14 @@ void plan_layout(rp_plan p) {
         return o;
     };
     p->off_state = alloc(64);
+    p->off_head = alloc(p->dom.size() * sizeof(int32_t));
     p->off_items = alloc(p->items.size() * sizeof(K2Item));
     p->off_groups = alloc(p->groups.size() * sizeof(K2Group));
     p->off_entries = alloc(std::max<size_t>(1, p->entries.size()) * sizeof(K2Entry));
     p->off_domdev = alloc(p->dom.size() * sizeof(DomDev));
+    p->off_srcs = alloc(p->srcs.size() * sizeof(K2Src));
+    p->off_pairs = alloc(p->pairs.size() * sizeof(K2Pair));
+    p->off_masks = alloc(std::max<size_t>(1, p->masks.size()) * sizeof(uint32_t));
     for (const SystemP &S : p->sys) {
         for (int a = 0; a < 3; ++a) {
             if (!p->tw64.count(S.P[a])) {
@@ -362,7 +405,7 @@ void plan_layout(rp_plan p) {
         }
     }
     int64_t spec_elems = 0;
-    for (const SystemP &S : p->sys) spec_elems += S.n_spec * S.C;
+    for (const SystemP &S : p->sys) spec_elems += S.spec_elems;
     p->off_spec = alloc(size_t(spec_elems) * p->spec_csz);
 
     const bool quant = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
@@ -371,7 +414,7 @@ void plan_layout(rp_plan p) {
         const SystemP &S = p->sys[d.sys];
         const size_t t1 = size_t(d.N[0]) * d.N[1] * S.Hz * 4;
         const size_t t2 = size_t(d.N[0]) * S.P[1] * S.Hz * 4;
-        d.off_ring = alloc(size_t(d.depth) * S.C * 4 * p->ring_esz);
+        d.off_ring = alloc(size_t(d.depth) * S.Cpad * 4 * p->ring_esz);
         d.off_scales = quant ? alloc(size_t(d.depth) * 4 * sizeof(float)) : 0;
         d.off_zmax = quant ? alloc(size_t(d.zblocks) * 4 * sizeof(float)) : 0;
         d.off_s0 = alloc(size_t(4) * d.npts * p->tsz);
@@ -407,6 +450,14 @@ void plan_layout(rp_plan p) {
         D.depth = d.depth;
         D.pad = 0;
     }
+    for (K2Entry &E : p->entries) {
+        E.ring_off = p->domdev[E.src].ring_off;
+        E.depth = p->domdev[E.src].depth;
+    }
+    for (K2Src &R : p->srcs) {
+        R.ring_off = p->domdev[R.n].ring_off;
+        R.depth = p->domdev[R.n].depth;
+    }
 }
 
 void plan_stats(rp_plan p) {
@@ -429,8 +480,8 @@ void plan_stats(rp_plan p) {
         bytes += per_k * double(G.C);
     }
     st.lagsum_bytes = bytes;
-    for (const DomainP &d : p->dom) st.ring_bytes += double(d.depth) * p->sys[d.sys].C * 4 * p->ring_esz;
-    for (const SystemP &S : p->sys) st.spectra_bytes += double(S.n_spec) * S.C * p->spec_csz;
+    for (const DomainP &d : p->dom) st.ring_bytes += double(d.depth) * p->sys[d.sys].Cpad * 4 * p->ring_esz;
+    for (const SystemP &S : p->sys) st.spectra_bytes += double(S.spec_elems) * p->spec_csz;
     for (const DomainP &d : p->dom) {
         const SystemP &S = p->sys[d.sys];
         const double t1 = double(d.N[0]) * d.N[1] * S.Hz * 4 * p->csz;
@@ -546,7 +597,8 @@ ZFwd zfwd_common(rp_plan p, int mode, const int N[3], const int P[3], int Hz, bo
 
 // FP64 spectrum (one component, [Px][Py][Hz]) of the Green's function of pair
 // (s <- n): lag m (mode 1) or instantaneous (mode 2), written with out_fmt.
-void green_spectra(rp_plan p, int s, int n, int mode, int m0, int count, void *const *outs, int out_fmt) {
+void green_spectra(rp_plan p, int s, int n, int mode, int m0, int count, void *const *outs, int out_fmt,
+                   int64_t tile_stride) {
     const DomainP &ds = p->dom[s], &dn = p->dom[n];
     const SystemP &S = p->sys[ds.sys];
     const size_t gstride = size_t(S.P[0]) * S.P[1] * S.Hz * 16;
@@ -584,10 +636,12 @@ void green_spectra(rp_plan p, int s, int n, int mode, int m0, int count, void *c
     x.in_j = x.out_j = int64_t(S.P[1]) * S.Hz;
     x.in_inner = x.out_inner = 1;
     x.out_fmt = out_fmt;
+    x.tile_comp = 1;
     x.n_jobs = count;
     for (int j = 0; j < count; ++j) {
         x.jobs[j].in = p->ws + p->off_gtmp + j * gstride;
         x.jobs[j].out = outs[j];
+        x.jobs[j].tile_stride = tile_stride;
     }
     launch_line_pass(x, 1, p->stream);
     check_launch();
@@ -608,6 +662,13 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
                               hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(p->ws + p->off_domdev, p->domdev.data(), p->domdev.size() * sizeof(DomDev),
                           hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(p->ws + p->off_srcs, p->srcs.data(), p->srcs.size() * sizeof(K2Src),
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(p->ws + p->off_pairs, p->pairs.data(), p->pairs.size() * sizeof(K2Pair),
+                          hipMemcpyHostToDevice, st));
+    if (!p->masks.empty())
+        HIP_OK(hipMemcpyAsync(p->ws + p->off_masks, p->masks.data(), p->masks.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, st));
     // twiddles exp(-2 pi i j / P), evaluated in FP64 on the host
     std::vector<Cx<double>> t64;
     std::vector<Cx<float>> t32;
@@ -625,8 +686,9 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
         HIP_OK(hipStreamSynchronize(st));   // host buffers are reused
     }
     launch_fill_zero(p->ws + p->off_state, 64, st);
+    launch_fill_zero(p->ws + p->off_head, (p->dom.size() * sizeof(int32_t) + 15) / 16 * 16, st);
     for (const DomainP &d : p->dom) {
-        launch_fill_zero(p->ws + d.off_ring, size_t(d.depth) * p->sys[d.sys].C * 4 * p->ring_esz, st);
+        launch_fill_zero(p->ws + d.off_ring, size_t(d.depth) * p->sys[d.sys].Cpad * 4 * p->ring_esz, st);
         if (d.off_scales) launch_fill_zero(p->ws + d.off_scales, (size_t(d.depth) * 16 + 15) / 16 * 16, st);
     }
     check_launch();
@@ -647,10 +709,11 @@ void do_green(rp_plan p) {
                 for (int m0 = q.m_lo; m0 <= q.m_hi; m0 += kGreenChunk) {
                     const int cnt = std::min(kGreenChunk, q.m_hi - m0 + 1);
                     void *outs[kGreenChunk];
+                    const int64_t W = q.m_hi - q.m_lo + 1;
                     for (int j = 0; j < cnt; ++j)
                         outs[j] = p->ws + p->off_spec +
-                                  size_t(S.spec_base + (q.spec0 + (m0 + j - q.m_lo)) * S.C) * p->spec_csz;
-                    green_spectra(p, s, n, 1, m0, cnt, outs, fmt);
+                                  size_t(S.spec_base + q.spec0 + int64_t(m0 + j - q.m_lo) * kTile) * p->spec_csz;
+                    green_spectra(p, s, n, 1, m0, cnt, outs, fmt, W * kTile);
                 }
             }
         }
@@ -694,7 +757,7 @@ void do_static(rp_plan p, const void *const *src) {
             launch_fill_zero(p->ws + p->off_accd, size_t(S.C) * 4 * 16, st);
             for (int n : S.doms) {
                 void *outs[1] = {p->ws + p->off_gstat};
-                green_spectra(p, s, n, 2, 0, 1, outs, RING_F64);
+                green_spectra(p, s, n, 2, 0, 1, outs, RING_F64, 0);
                 launch_static_mac(p->ws + p->off_accd, p->ws + p->off_gstat, p->ws + p->dom[n].off_s0hat, S.C, st);
             }
             LinePass x = inv_x(p, d.N, S.P, S.Hz, true);
@@ -745,7 +808,7 @@ void do_push(rp_plan p, int64_t step, const void *const *src) {
         do_static(p, src);
     } else {
         const bool quant = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
-        const int64_t *dstep = p->at<int64_t>(p->off_state);
+        const int32_t *dhead = p->at<int32_t>(p->off_head);
         for (const ClassP &K : p->cls) {
             for (size_t j0 = 0; j0 < K.doms.size(); j0 += kMaxJobs) {
                 const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
@@ -753,9 +816,8 @@ void do_push(rp_plan p, int64_t step, const void *const *src) {
                 LinePass y = fwd_y(p, K.N, K.P, K.Hz, p->p64);
                 LinePass x = fwd_x(p, K.N, K.P, K.Hz, p->p64);
                 x.out_fmt = p->ring_fmt;
-                x.step = dstep;
+                x.tile_comp = 4;
                 ScaleArgs sa{};
-                sa.step = dstep;
                 z.n_jobs = y.n_jobs = x.n_jobs = cnt;
                 sa.n_jobs = quant ? cnt : 0;
                 for (int j = 0; j < cnt; ++j) {
@@ -769,14 +831,15 @@ void do_push(rp_plan p, int64_t step, const void *const *src) {
                     y.jobs[j].out = p->ws + d.off_t2;
                     x.jobs[j].in = p->ws + d.off_t2;
                     x.jobs[j].out = p->ws + d.off_ring;
-                    x.jobs[j].slot_stride = K.C * 4;
-                    x.jobs[j].depth = d.depth;
+                    x.jobs[j].head = dhead + n;
+                    x.jobs[j].slot_stride = int64_t(kTile) * 4;
+                    x.jobs[j].tile_stride = int64_t(d.depth) * kTile * 4;
                     x.jobs[j].qscale = quant ? p->at<float>(d.off_scales) : nullptr;
                     if (quant) {
                         sa.jobs[j].zmax = p->at<float>(d.off_zmax);
                         sa.jobs[j].scales = p->at<float>(d.off_scales);
                         sa.jobs[j].nblk = d.zblocks;
-                        sa.jobs[j].depth = d.depth;
+                        sa.jobs[j].head = dhead + n;
                         sa.jobs[j].npts = double(d.npts);
                     }
                 }
@@ -808,13 +871,17 @@ void do_step(rp_plan p, int64_t step, void *const *out) {
     k.items = p->at<K2Item>(p->off_items);
     k.groups = p->at<K2Group>(p->off_groups);
     k.entries = p->at<K2Entry>(p->off_entries);
+    k.srcs = p->at<K2Src>(p->off_srcs);
+    k.pairs = p->at<K2Pair>(p->off_pairs);
+    k.masks = p->at<uint32_t>(p->off_masks);
     k.doms = p->at<DomDev>(p->off_domdev);
     k.spectra = p->ws + p->off_spec;
     k.ring = p->ws + p->dom[0].off_ring;
     k.scales = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16) ? p->at<float>(p->dom[0].off_scales) : nullptr;
     k.acc = p->ws + p->dom[0].off_acc;
-    k.step = p->at<int64_t>(p->off_state);
+    k.head = p->at<int32_t>(p->off_head);
     k.n_items = int(p->items.size());
+    k.n_dom = p->n_dom;
     if (p->profile) {
         if (p->events.size() < 2 * (p->n_recorded + 1)) {
             for (int i = 0; i < 2; ++i) {
@@ -862,7 +929,8 @@ void do_step(rp_plan p, int64_t step, void *const *out) {
             check_launch();
         }
     }
-    launch_advance_step(p->at<int64_t>(p->off_state), st);
+    launch_advance_step(p->at<int64_t>(p->off_state), p->at<int32_t>(p->off_head), p->at<DomDev>(p->off_domdev),
+                        p->n_dom, st);
     check_launch();
     p->next_step += 1;
     p->pushed = false;
@@ -924,6 +992,9 @@ rp_status rp_plan_domains(rp_plan *out, int32_t n_dom, const int32_t *dims, cons
         p->csz = p->p64 ? 16 : 8;
         p->spec_csz = p->csz;
         p->ring_esz = p->ring_fmt == RING_F64 ? 16 : (p->ring_fmt == RING_F32 ? 8 : 4);
+        // default lag-sum batching (measured on MI355X, 8 x 64^3): two lags
+        // per batch for the FP32 ring, one for the narrower rings and FP64
+        p->k2_unroll = (p->ring_fmt == RING_F32) ? 2 : 1;
         // self cell: the exact integral of T(m dt - |u|/c)/|u| over the cell of
         // side h around the point; C1 = int_{[-1/2,1/2]^3} d^3u/|u| = 3 ln(2 + sqrt 3) - pi/2
         const double C1 = 3.0 * std::log(2.0 + std::sqrt(3.0)) - M_PI / 2.0;

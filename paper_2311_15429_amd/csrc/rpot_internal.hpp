@@ -20,6 +20,10 @@ struct RadixPlan {
 
 constexpr int kMaxJobs = 16;
 constexpr int kFftThreads = 256;
+// Frequencies per lag-sum block.  The history ring and the Green spectra are
+// stored tile-major ([tile][slot or lag][kTile][...]) so that one block streams
+// contiguous memory across consecutive lags.
+constexpr int kTile = 256;
 
 // Ring storage formats of the source-spectrum history.
 enum RingFmt : int { RING_F64 = 0, RING_F32 = 1, RING_F16 = 2, RING_BF16 = 3 };
@@ -33,9 +37,9 @@ struct LineJob {
     const void *in;
     void *out;
     const float *qscale;   // ring quantisation: scales [depth][4] of the domain, else null
-    int64_t slot_stride;   // ring output: elements per slot (0: out is used as is)
-    int32_t depth;         // ring output: slots; the slot is (*step) mod depth
-    int32_t pad_;
+    const int32_t *head;   // ring output: current slot of the domain's ring, else null
+    int64_t slot_stride;   // ring output: elements per slot
+    int64_t tile_stride;   // tiled output: elements per frequency tile (0: linear output)
 };
 
 struct LinePass {
@@ -45,8 +49,10 @@ struct LinePass {
     int64_t out_j, out_inner, out_outer;
     int dir;               // -1 forward, +1 inverse
     int out_fmt;           // RingFmt of the output (F64/F32 = plain complex)
+    int tile_comp;         // tiled output: interleaved components per frequency
+                           // (linear index e = k * tile_comp + c is stored at
+                           //  (k / kTile) * tile_stride + (k % kTile) * tile_comp + c)
     const void *tw;        // twiddles exp(-2 pi i j / P), j < P
-    const int64_t *step;   // device step counter (ring output), else null
     RadixPlan rp;
     int n_jobs;
     LineJob jobs[kMaxJobs];
@@ -106,13 +112,36 @@ struct K2Entry {
     int32_t m;             // lag
     uint32_t mask;         // group members fed by this (source, lag)
     uint32_t conj;         // members that use the conjugate of the stored spectrum
-    int32_t spec[8];       // spectrum index (within the system) per member
+    int64_t ring_off;      // the source's ring (complex elements from the first ring)
+    int32_t depth;         // the source's ring depth
+    int32_t pad_;
+    int32_t spec_tile[8];  // per member: (pair base + lag * kTile) / kTile within the system
+    int32_t spec_w[8];     // per member: lags of the pair (spectrum tile stride / kTile)
+};
+
+// Per (group, source): the lag range covered by any member and the ring.
+struct K2Src {
+    int32_t n;             // source domain (global index)
+    int32_t m_min, m_max;  // union of the members' lag windows for this source
+    int32_t depth;         // the source's ring depth
+    int64_t ring_off;      // the source's ring (complex elements from the first ring)
+    uint32_t conj;         // members that use the conjugate of the stored spectra
+    int32_t mask_off;      // masks[mask_off + m - m_min]: members whose window holds lag m
+};
+
+// Per (group, source, member): where the pair's spectra sit.  They are stored
+// [tile][lag][kTile]; the row (kTile complex values) of lag m in tile `tile`
+// is row0 + tile * w + m (relative to the system's spectra).
+struct K2Pair {
+    int32_t row0;          // (pair base) / kTile - m_lo
+    int32_t w;             // lags of the pair
 };
 
 struct K2Group {
     int64_t C;             // spectrum length of the system
     int64_t spec_base;     // element offset of the system's spectra
     int32_t entry_begin, entry_end;
+    int32_t src_begin, src_end;   // K2Src records; K2Pair records at [src * 8 + member]
     int32_t n_members;
     int32_t member[8];     // global target domain index per member
 };
@@ -123,7 +152,7 @@ struct K2Item {
 };
 
 struct DomDev {
-    int64_t ring_off;      // element offset (complex) of the domain's ring
+    int64_t ring_off;      // element offset (complex) of the domain's ring [tile][slot][kTile][4]
     int64_t acc_off;       // element offset (complex) of the domain's accumulator
     int64_t scale_off;     // float offset of the ring's scales [depth][4]
     int32_t depth;
@@ -134,13 +163,17 @@ struct K2Args {
     const K2Item *items;
     const K2Group *groups;
     const K2Entry *entries;
+    const K2Src *srcs;
+    const K2Pair *pairs;
+    const uint32_t *masks;
     const DomDev *doms;
     const void *spectra;
     const void *ring;
     const float *scales;
     void *acc;
-    const int64_t *step;   // device step counter
+    const int32_t *head;   // [n_dom] current ring slot of every domain (step mod depth)
     int n_items;
+    int n_dom;
 };
 
 // ---------------------------------------------------------------------------
@@ -150,17 +183,17 @@ void launch_zfwd(const ZFwd &a, int prec64, hipStream_t st);
 void launch_zinv(const ZInv &a, int prec64, hipStream_t st);
 int zfwd_lines_per_block(int Pz, int prec64);
 void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, int unroll, hipStream_t st);
-// Per-snapshot ring scales: for each job, scales[(step mod depth)*4 + mu] =
+// Per-snapshot ring scales: for each job, scales[head*4 + mu] =
 // 2^(e-15) with npts * max_blocks zmax[b][mu] <= 2^e (1 when the max is 0).
 struct ScaleJob {
     const float *zmax;
     float *scales;
+    const int32_t *head;   // current ring slot of the domain
     int32_t nblk;
-    int32_t depth;
+    int32_t pad_;
     double npts;
 };
 struct ScaleArgs {
-    const int64_t *step;
     int n_jobs;
     ScaleJob jobs[kMaxJobs];
 };
@@ -168,6 +201,7 @@ void launch_ring_scale(const ScaleArgs &a, hipStream_t st);
 void launch_static_mac(void *acc, const void *g, const void *s, int64_t C, hipStream_t st);
 void launch_convert(void *dst, int dst64, const void *src, int src64, int64_t n, hipStream_t st);
 void launch_fill_zero(void *dst, size_t bytes, hipStream_t st);
-void launch_advance_step(int64_t *step, hipStream_t st);
+// step += 1 and every domain's ring head moves one slot (mod its depth).
+void launch_advance_step(int64_t *step, int32_t *head, const DomDev *doms, int n_dom, hipStream_t st);
 
 }  // namespace rpot
