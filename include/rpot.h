@@ -171,12 +171,41 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
 /*
  * Tuning knobs (schedule choices that never change results beyond rounding
  * order; every value is valid for every plan).
- *   RP_TUNE_LAGSUM_UNROLL  (source, lag) entries whose loads one lag-sum
- *                          thread issues before accumulating: 1, 2 or 4.
+ *   RP_TUNE_LAGSUM_UNROLL      lags whose loads one lag-sum thread issues
+ *                              before accumulating: 1, 2 or 4.
+ *   RP_TUNE_LAGSUM_PERSISTENT  1: one persistent lag-sum launch sized to the
+ *                              device drains the work list (system group x
+ *                              frequency tile, longest first) through a device
+ *                              counter; 0: one block per work item.
+ * Setting a knob discards a captured step (rp_capture_step).
  */
-enum { RP_TUNE_LAGSUM_UNROLL = 1 };
+enum { RP_TUNE_LAGSUM_UNROLL = 1, RP_TUNE_LAGSUM_PERSISTENT = 2 };
 rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value);
 rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value);
+
+/*
+ * Autotuner: times every lag-sum schedule (unroll x persistent) `iters` times
+ * on the bound plan (after rp_set_green_kernels; only accumulator scratch is
+ * written, the step sequence is untouched), keeps the fastest and returns it
+ * with its mean kernel time.  Synchronises the stream.  Output pointers may be
+ * NULL.  Discards a captured step.
+ */
+rp_status rp_autotune(rp_plan plan, int32_t iters, int32_t *unroll, int32_t *persistent,
+                      double *lagsum_ms);
+
+/*
+ * Graph-captured step (batched systems are one graph launch per step).
+ * rp_capture_step records one whole step -- ingest of src, lag sum, inverse
+ * and crop into out, advance of the step -- for these fixed device buffers
+ * (same layout as rp_push_sources / rp_retarded_step) into a HIP graph owned
+ * by the plan; it enqueues no work.  rp_launch_step(plan, step) replays it on
+ * the plan's stream as step `step` (>= 1, in sequence; step 0 must have been
+ * done by rp_push_sources / rp_retarded_step): the caller writes the step's
+ * sources into the captured src buffers before the launch.  Replays and the
+ * eager calls may be interleaved as long as the steps stay in sequence.
+ */
+rp_status rp_capture_step(rp_plan plan, const void *const *src, void *const *out);
+rp_status rp_launch_step(rp_plan plan, int64_t step);
 
 /* Release the host plan (the workspace stays the caller's). */
 rp_status rp_plan_destroy(rp_plan plan);

@@ -15,8 +15,8 @@ PRECISION = {"fp64": 0, "fp32": 1, "fp32_ring_fp16": 2, "fp32_ring_bf16": 3}
 EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_set_green_kernels",
            "rp_push_sources", "rp_retarded_step", "rp_plan_info", "rp_plan_stats",
            "rp_profile_lagsum", "rp_lagsum_time", "rp_set_tuning", "rp_get_tuning",
-           "rp_plan_destroy", "rp_last_error"]
-TUNE = {"lagsum_unroll": 1}
+           "rp_autotune", "rp_capture_step", "rp_launch_step", "rp_plan_destroy", "rp_last_error"]
+TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2}
 
 
 class RpotError(RuntimeError):
@@ -60,6 +60,9 @@ def load():
     lib.rp_lagsum_time.argtypes = [vp, P(ctypes.c_double), P(i64)]
     lib.rp_set_tuning.argtypes = [vp, i32, i32]
     lib.rp_get_tuning.argtypes = [vp, i32, P(i32)]
+    lib.rp_autotune.argtypes = [vp, i32, P(i32), P(i32), P(ctypes.c_double)]
+    lib.rp_capture_step.argtypes = [vp, P(vp), P(vp)]
+    lib.rp_launch_step.argtypes = [vp, i64]
     lib.rp_plan_destroy.argtypes = [vp]
     lib.rp_last_error.argtypes = [vp]
     lib.rp_last_error.restype = ctypes.c_char_p

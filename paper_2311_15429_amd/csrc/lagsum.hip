@@ -19,6 +19,7 @@
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace rpot {
 
@@ -175,10 +176,10 @@ __device__ __forceinline__ uint32_t load_lag(const K2Args &a, const char *ring_t
 }
 
 template <typename T, int FMT, int TG, int U>
-__global__ __launch_bounds__(256) void k_lagsum(K2Args a) {
+__device__ __forceinline__ void lagsum_item(const K2Args &a, int item_index) {
     constexpr int esz = RingEsz<FMT>::v;
     constexpr int64_t ring_row = int64_t(kTile) * 4 * esz;
-    const K2Item item = a.items[blockIdx.x];
+    const K2Item item = a.items[item_index];
     const K2Group &g = a.groups[item.group];
     const int lane = threadIdx.x;
     const int64_t k = int64_t(item.k0) + lane;
@@ -246,37 +247,101 @@ __global__ __launch_bounds__(256) void k_lagsum(K2Args a) {
     }
 }
 
+// PERSIST = false: one block per work item (system group x frequency tile).
+// PERSIST = true: a grid sized to the resident capacity drains the item list
+// through a device counter (zeroed before the launch); every block leaves the
+// loop once the counter passes the item count.  The items are ordered by
+// decreasing cost, so uneven systems balance across the chip.
+template <typename T, int FMT, int TG, int U, bool PERSIST>
+__global__ __launch_bounds__(256) void k_lagsum(K2Args a) {
+    if (!PERSIST) {
+        lagsum_item<T, FMT, TG, U>(a, blockIdx.x);
+        return;
+    }
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= a.n_items) break;
+        lagsum_item<T, FMT, TG, U>(a, it);
+    }
+}
+
+__global__ void k_zero_counter(int *c) {
+    if (threadIdx.x == 0) *c = 0;
+}
+
+template <typename T, int FMT, int TG, int U>
+static void launch_p(const K2Args &a, int grid_persist, hipStream_t st) {
+    if (grid_persist > 0) {
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, st, a.counter);
+        hipLaunchKernelGGL((k_lagsum<T, FMT, TG, U, true>), dim3(std::min(grid_persist, a.n_items)), dim3(256), 0,
+                           st, a);
+    } else {
+        hipLaunchKernelGGL((k_lagsum<T, FMT, TG, U, false>), dim3(a.n_items), dim3(256), 0, st, a);
+    }
+}
+
 template <typename T, int FMT, int TG>
-static void launch_u(const K2Args &a, int unroll, hipStream_t st) {
-    dim3 grid(a.n_items), block(256);
+static void launch_u(const K2Args &a, int unroll, int grid_persist, hipStream_t st) {
     switch (unroll) {
-    case 1: hipLaunchKernelGGL((k_lagsum<T, FMT, TG, 1>), grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_lagsum<T, FMT, TG, 4>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_lagsum<T, FMT, TG, 2>), grid, block, 0, st, a); break;
+    case 1: launch_p<T, FMT, TG, 1>(a, grid_persist, st); break;
+    case 4: launch_p<T, FMT, TG, 4>(a, grid_persist, st); break;
+    default: launch_p<T, FMT, TG, 2>(a, grid_persist, st); break;
     }
 }
 
 template <typename T, int FMT>
-static void launch_tg(const K2Args &a, int tg, int unroll, hipStream_t st) {
+static void launch_tg(const K2Args &a, int tg, int unroll, int grid_persist, hipStream_t st) {
     switch (tg) {
-    case 1: launch_u<T, FMT, 1>(a, unroll, st); break;
-    case 2: launch_u<T, FMT, 2>(a, unroll, st); break;
-    case 4: launch_u<T, FMT, 4>(a, unroll, st); break;
-    default: launch_u<T, FMT, 8>(a, unroll, st); break;
+    case 1: launch_u<T, FMT, 1>(a, unroll, grid_persist, st); break;
+    case 2: launch_u<T, FMT, 2>(a, unroll, grid_persist, st); break;
+    case 4: launch_u<T, FMT, 4>(a, unroll, grid_persist, st); break;
+    default: launch_u<T, FMT, 8>(a, unroll, grid_persist, st); break;
     }
 }
 
-void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, int unroll, hipStream_t st) {
+void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, int unroll, int grid_persist,
+                   hipStream_t st) {
     if (a.n_items == 0) return;
     if (prec64) {
-        launch_tg<double, RING_F64>(a, tg, unroll, st);
+        launch_tg<double, RING_F64>(a, tg, unroll, grid_persist, st);
     } else if (ring_fmt == RING_F16) {
-        launch_tg<float, RING_F16>(a, tg, unroll, st);
+        launch_tg<float, RING_F16>(a, tg, unroll, grid_persist, st);
     } else if (ring_fmt == RING_BF16) {
-        launch_tg<float, RING_BF16>(a, tg, unroll, st);
+        launch_tg<float, RING_BF16>(a, tg, unroll, grid_persist, st);
     } else {
-        launch_tg<float, RING_F32>(a, tg, unroll, st);
+        launch_tg<float, RING_F32>(a, tg, unroll, grid_persist, st);
     }
+}
+
+int lagsum_blocks_per_cu(int prec64, int ring_fmt, int tg, int unroll) {
+    // resident blocks of the persistent lag-sum kernel per compute unit
+    int n = 0;
+    const void *f = nullptr;
+#define RPOT_K2_FN(T, F, G, U) reinterpret_cast<const void *>(&k_lagsum<T, F, G, U, true>)
+    auto pick_u = [&](auto tgc) {
+        constexpr int G = decltype(tgc)::value;
+        if (prec64) f = unroll == 1 ? RPOT_K2_FN(double, RING_F64, G, 1)
+                        : unroll == 4 ? RPOT_K2_FN(double, RING_F64, G, 4) : RPOT_K2_FN(double, RING_F64, G, 2);
+        else if (ring_fmt == RING_F16) f = unroll == 1 ? RPOT_K2_FN(float, RING_F16, G, 1)
+                        : unroll == 4 ? RPOT_K2_FN(float, RING_F16, G, 4) : RPOT_K2_FN(float, RING_F16, G, 2);
+        else if (ring_fmt == RING_BF16) f = unroll == 1 ? RPOT_K2_FN(float, RING_BF16, G, 1)
+                        : unroll == 4 ? RPOT_K2_FN(float, RING_BF16, G, 4) : RPOT_K2_FN(float, RING_BF16, G, 2);
+        else f = unroll == 1 ? RPOT_K2_FN(float, RING_F32, G, 1)
+                 : unroll == 4 ? RPOT_K2_FN(float, RING_F32, G, 4) : RPOT_K2_FN(float, RING_F32, G, 2);
+    };
+#undef RPOT_K2_FN
+    switch (tg) {
+    case 1: pick_u(std::integral_constant<int, 1>{}); break;
+    case 2: pick_u(std::integral_constant<int, 2>{}); break;
+    case 4: pick_u(std::integral_constant<int, 4>{}); break;
+    default: pick_u(std::integral_constant<int, 8>{}); break;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess || n < 1) n = 1;
+    return n;
 }
 
 // ---------------------------------------------------------------------------

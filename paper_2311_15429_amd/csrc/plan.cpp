@@ -128,11 +128,16 @@ struct rp_plan_s {
     std::vector<K2Item> items;
     std::vector<DomDev> domdev;
     int tg = 1;
-    int k2_unroll = 1;   // entries whose loads a lag-sum thread issues together
+    int k2_unroll = 1;   // lags whose loads a lag-sum thread issues together
+    int k2_persist = 0;  // persistent lag-sum launch (work counter) instead of one block per item
+    int n_cu = 0;        // compute units of the bound device
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
 
     std::map<int, size_t> tw64, tw32;   // FFT length -> byte offset of its twiddles
     size_t off_state = 0, off_head = 0, off_items = 0, off_groups = 0, off_entries = 0, off_domdev = 0;
-    size_t off_srcs = 0, off_pairs = 0, off_masks = 0;
+    size_t off_srcs = 0, off_pairs = 0, off_masks = 0, off_counter = 0;
     size_t off_spec = 0, off_gtmp = 0, off_accd = 0, off_gstat = 0, off_t1d = 0, off_t2d = 0;
     size_t off_s0d = 0, off_p0d = 0;
     size_t ws_bytes = 0;
@@ -353,6 +358,16 @@ void plan_build(rp_plan p, const int32_t *dims, const double *origins, const int
         }
     }
     p->tg = max_members <= 1 ? 1 : (max_members <= 2 ? 2 : (max_members <= 4 ? 4 : 8));
+    // longest work first (for the persistent launch): a group's tile costs its
+    // ring reads plus its spectrum reads
+    std::vector<double> gcost(p->groups.size(), 0.0);
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        const K2Group &G = p->groups[gi];
+        for (int e = G.entry_begin; e < G.entry_end; ++e)
+            gcost[gi] += 4.0 + double(__builtin_popcount(p->entries[e].mask));
+    }
+    std::stable_sort(p->items.begin(), p->items.end(),
+                     [&](const K2Item &x, const K2Item &y) { return gcost[x.group] > gcost[y.group]; });
     if (p->entries.size() > size_t(INT32_MAX) || p->items.size() > size_t(INT32_MAX))
         fail(RP_ERR_UNSUPPORTED, "schedule too large");
 
@@ -389,6 +404,7 @@ void plan_layout(rp_plan p) {
     };
     p->off_state = alloc(64);
     p->off_head = alloc(p->dom.size() * sizeof(int32_t));
+    p->off_counter = alloc(16);
     p->off_items = alloc(p->items.size() * sizeof(K2Item));
     p->off_groups = alloc(p->groups.size() * sizeof(K2Group));
     p->off_entries = alloc(std::max<size_t>(1, p->entries.size()) * sizeof(K2Entry));
@@ -647,6 +663,13 @@ void green_spectra(rp_plan p, int s, int n, int mode, int m0, int count, void *c
     check_launch();
 }
 
+void release_graph(rp_plan p) {
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+}
+
 void do_bind(rp_plan p, void *dev, size_t bytes) {
     if (!dev) fail(RP_ERR_ARG, "workspace pointer is null");
     if (reinterpret_cast<uintptr_t>(dev) % kAlign) fail(RP_ERR_ARG, "workspace must be 256-byte aligned");
@@ -687,6 +710,12 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
     }
     launch_fill_zero(p->ws + p->off_state, 64, st);
     launch_fill_zero(p->ws + p->off_head, (p->dom.size() * sizeof(int32_t) + 15) / 16 * 16, st);
+    launch_fill_zero(p->ws + p->off_counter, 16, st);
+    {
+        int dev = 0;
+        HIP_OK(hipGetDevice(&dev));
+        HIP_OK(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
     for (const DomainP &d : p->dom) {
         launch_fill_zero(p->ws + d.off_ring, size_t(d.depth) * p->sys[d.sys].Cpad * 4 * p->ring_esz, st);
         if (d.off_scales) launch_fill_zero(p->ws + d.off_scales, (size_t(d.depth) * 16 + 15) / 16 * 16, st);
@@ -696,6 +725,7 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
     p->green_ready = false;
     p->next_step = 0;
     p->pushed = false;
+    release_graph(p);
 }
 
 void do_green(rp_plan p) {
@@ -789,84 +819,56 @@ void do_static(rp_plan p, const void *const *src) {
     }
 }
 
-void do_push(rp_plan p, int64_t step, const void *const *src) {
-    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
-    if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
-    if (!src) fail(RP_ERR_ARG, "src is null");
-    if (step != p->next_step || p->pushed) {
-        char buf[128];
-        std::snprintf(buf, sizeof buf, "rp_push_sources(%lld) out of order (expected step %lld%s)",
-                      (long long)step, (long long)p->next_step, p->pushed ? ", already pushed" : "");
-        fail(RP_ERR_STATE, buf);
-    }
-    for (int n = 0; n < p->n_dom; ++n)
-        if (!src[n]) fail(RP_ERR_ARG, "a source pointer is null");
-    hipStream_t st = p->stream;
-    if (step == 0) {
-        for (int n = 0; n < p->n_dom; ++n)
-            launch_convert(p->ws + p->dom[n].off_s0, p->p64, src[n], p->p64, 4 * p->dom[n].npts, st);
-        do_static(p, src);
-    } else {
-        const bool quant = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
-        const int32_t *dhead = p->at<int32_t>(p->off_head);
-        for (const ClassP &K : p->cls) {
-            for (size_t j0 = 0; j0 < K.doms.size(); j0 += kMaxJobs) {
-                const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
-                ZFwd z = zfwd_common(p, 0, K.N, K.P, K.Hz, p->p64);
-                LinePass y = fwd_y(p, K.N, K.P, K.Hz, p->p64);
-                LinePass x = fwd_x(p, K.N, K.P, K.Hz, p->p64);
-                x.out_fmt = p->ring_fmt;
-                x.tile_comp = 4;
-                ScaleArgs sa{};
-                z.n_jobs = y.n_jobs = x.n_jobs = cnt;
-                sa.n_jobs = quant ? cnt : 0;
-                for (int j = 0; j < cnt; ++j) {
-                    const int n = K.doms[j0 + j];
-                    const DomainP &d = p->dom[n];
-                    z.jobs[j].src = src[n];
-                    z.jobs[j].s0 = p->ws + d.off_s0;
-                    z.jobs[j].out = p->ws + d.off_t1;
-                    z.jobs[j].zmax = quant ? p->at<float>(d.off_zmax) : nullptr;
-                    y.jobs[j].in = p->ws + d.off_t1;
-                    y.jobs[j].out = p->ws + d.off_t2;
-                    x.jobs[j].in = p->ws + d.off_t2;
-                    x.jobs[j].out = p->ws + d.off_ring;
-                    x.jobs[j].head = dhead + n;
-                    x.jobs[j].slot_stride = int64_t(kTile) * 4;
-                    x.jobs[j].tile_stride = int64_t(d.depth) * kTile * 4;
-                    x.jobs[j].qscale = quant ? p->at<float>(d.off_scales) : nullptr;
-                    if (quant) {
-                        sa.jobs[j].zmax = p->at<float>(d.off_zmax);
-                        sa.jobs[j].scales = p->at<float>(d.off_scales);
-                        sa.jobs[j].nblk = d.zblocks;
-                        sa.jobs[j].head = dhead + n;
-                        sa.jobs[j].npts = double(d.npts);
-                    }
+// Forward transform of dS(l) = S(l) - S(0) of every domain into the slot of
+// its ring given by the device-side head (no host-side step dependence, so
+// the same launches are valid inside a captured graph).
+void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
+    const bool quant = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
+    const int32_t *dhead = p->at<int32_t>(p->off_head);
+    for (const ClassP &K : p->cls) {
+        for (size_t j0 = 0; j0 < K.doms.size(); j0 += kMaxJobs) {
+            const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
+            ZFwd z = zfwd_common(p, 0, K.N, K.P, K.Hz, p->p64);
+            LinePass y = fwd_y(p, K.N, K.P, K.Hz, p->p64);
+            LinePass x = fwd_x(p, K.N, K.P, K.Hz, p->p64);
+            x.out_fmt = p->ring_fmt;
+            x.tile_comp = 4;
+            ScaleArgs sa{};
+            z.n_jobs = y.n_jobs = x.n_jobs = cnt;
+            sa.n_jobs = quant ? cnt : 0;
+            for (int j = 0; j < cnt; ++j) {
+                const int n = K.doms[j0 + j];
+                const DomainP &d = p->dom[n];
+                z.jobs[j].src = src[n];
+                z.jobs[j].s0 = p->ws + d.off_s0;
+                z.jobs[j].out = p->ws + d.off_t1;
+                z.jobs[j].zmax = quant ? p->at<float>(d.off_zmax) : nullptr;
+                y.jobs[j].in = p->ws + d.off_t1;
+                y.jobs[j].out = p->ws + d.off_t2;
+                x.jobs[j].in = p->ws + d.off_t2;
+                x.jobs[j].out = p->ws + d.off_ring;
+                x.jobs[j].head = dhead + n;
+                x.jobs[j].slot_stride = int64_t(kTile) * 4;
+                x.jobs[j].tile_stride = int64_t(d.depth) * kTile * 4;
+                x.jobs[j].qscale = quant ? p->at<float>(d.off_scales) : nullptr;
+                if (quant) {
+                    sa.jobs[j].zmax = p->at<float>(d.off_zmax);
+                    sa.jobs[j].scales = p->at<float>(d.off_scales);
+                    sa.jobs[j].nblk = d.zblocks;
+                    sa.jobs[j].head = dhead + n;
+                    sa.jobs[j].npts = double(d.npts);
                 }
-                launch_zfwd(z, p->p64, st);
-                launch_ring_scale(sa, st);
-                launch_line_pass(y, p->p64, st);
-                launch_line_pass(x, p->p64, st);
-                check_launch();
             }
+            launch_zfwd(z, p->p64, st);
+            launch_ring_scale(sa, st);
+            launch_line_pass(y, p->p64, st);
+            launch_line_pass(x, p->p64, st);
+            check_launch();
         }
     }
-    check_launch();
-    p->pushed = true;
 }
 
-void do_step(rp_plan p, int64_t step, void *const *out) {
-    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
-    if (!out) fail(RP_ERR_ARG, "out is null");
-    if (step != p->next_step || !p->pushed) {
-        char buf[128];
-        std::snprintf(buf, sizeof buf, "rp_retarded_step(%lld) out of order (expected step %lld%s)",
-                      (long long)step, (long long)p->next_step, p->pushed ? "" : ", sources not pushed");
-        fail(RP_ERR_STATE, buf);
-    }
-    for (int n = 0; n < p->n_dom; ++n)
-        if (!out[n]) fail(RP_ERR_ARG, "an output pointer is null");
-    hipStream_t st = p->stream;
+K2Args lagsum_args(rp_plan p) {
     K2Args k{};
     k.items = p->at<K2Item>(p->off_items);
     k.groups = p->at<K2Group>(p->off_groups);
@@ -880,24 +882,21 @@ void do_step(rp_plan p, int64_t step, void *const *out) {
     k.scales = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16) ? p->at<float>(p->dom[0].off_scales) : nullptr;
     k.acc = p->ws + p->dom[0].off_acc;
     k.head = p->at<int32_t>(p->off_head);
+    k.counter = p->at<int>(p->off_counter);
     k.n_items = int(p->items.size());
     k.n_dom = p->n_dom;
-    if (p->profile) {
-        if (p->events.size() < 2 * (p->n_recorded + 1)) {
-            for (int i = 0; i < 2; ++i) {
-                hipEvent_t ev;
-                HIP_OK(hipEventCreate(&ev));
-                p->events.push_back(ev);
-            }
-        }
-        HIP_OK(hipEventRecord(p->events[2 * p->n_recorded], st));
-    }
-    launch_lagsum(k, p->p64, p->ring_fmt, p->tg, p->k2_unroll, st);
+    return k;
+}
+
+void enqueue_lagsum(rp_plan p, hipStream_t st, int unroll, int persist) {
+    const int grid = persist ? p->n_cu * lagsum_blocks_per_cu(p->p64, p->ring_fmt, p->tg, unroll) : 0;
+    launch_lagsum(lagsum_args(p), p->p64, p->ring_fmt, p->tg, unroll, grid, st);
     check_launch();
-    if (p->profile) {
-        HIP_OK(hipEventRecord(p->events[2 * p->n_recorded + 1], st));
-        p->n_recorded += 1;
-    }
+}
+
+// Inverse transform of every target's accumulated spectrum, crop to the
+// domain, add P(0), write the caller's output; then advance the step.
+void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st) {
     for (const ClassP &K : p->cls) {
         for (size_t j0 = 0; j0 < K.doms.size(); j0 += kMaxJobs) {
             const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
@@ -932,8 +931,144 @@ void do_step(rp_plan p, int64_t step, void *const *out) {
     launch_advance_step(p->at<int64_t>(p->off_state), p->at<int32_t>(p->off_head), p->at<DomDev>(p->off_domdev),
                         p->n_dom, st);
     check_launch();
+}
+
+void check_ptrs(rp_plan p, const void *const *ptrs, const char *what) {
+    if (!ptrs) fail(RP_ERR_ARG, std::string(what) + " is null");
+    for (int n = 0; n < p->n_dom; ++n)
+        if (!ptrs[n]) fail(RP_ERR_ARG, std::string("a ") + what + " pointer is null");
+}
+
+void do_push(rp_plan p, int64_t step, const void *const *src) {
+    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
+    check_ptrs(p, src, "src");
+    if (step != p->next_step || p->pushed) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "rp_push_sources(%lld) out of order (expected step %lld%s)",
+                      (long long)step, (long long)p->next_step, p->pushed ? ", already pushed" : "");
+        fail(RP_ERR_STATE, buf);
+    }
+    hipStream_t st = p->stream;
+    if (step == 0) {
+        for (int n = 0; n < p->n_dom; ++n)
+            launch_convert(p->ws + p->dom[n].off_s0, p->p64, src[n], p->p64, 4 * p->dom[n].npts, st);
+        do_static(p, src);
+    } else {
+        enqueue_ingest(p, src, st);
+    }
+    check_launch();
+    p->pushed = true;
+}
+
+void do_step(rp_plan p, int64_t step, void *const *out) {
+    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    check_ptrs(p, out, "out");
+    if (step != p->next_step || !p->pushed) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "rp_retarded_step(%lld) out of order (expected step %lld%s)",
+                      (long long)step, (long long)p->next_step, p->pushed ? "" : ", sources not pushed");
+        fail(RP_ERR_STATE, buf);
+    }
+    hipStream_t st = p->stream;
+    if (p->profile) {
+        if (p->events.size() < 2 * (p->n_recorded + 1)) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t ev;
+                HIP_OK(hipEventCreate(&ev));
+                p->events.push_back(ev);
+            }
+        }
+        HIP_OK(hipEventRecord(p->events[2 * p->n_recorded], st));
+    }
+    enqueue_lagsum(p, st, p->k2_unroll, p->k2_persist);
+    if (p->profile) {
+        HIP_OK(hipEventRecord(p->events[2 * p->n_recorded + 1], st));
+        p->n_recorded += 1;
+    }
+    enqueue_inverse(p, out, st);
     p->next_step += 1;
     p->pushed = false;
+}
+
+// Record one whole step (ingest + lag sum + inverse + advance) for fixed
+// source and output buffers as a HIP graph.
+void do_capture(rp_plan p, const void *const *src, void *const *out) {
+    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
+    check_ptrs(p, src, "src");
+    check_ptrs(p, out, "out");
+    release_graph(p);
+    if (!p->capture_stream) HIP_OK(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = p->capture_stream;
+    HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue_ingest(p, src, cs);
+        enqueue_lagsum(p, cs, p->k2_unroll, p->k2_persist);
+        enqueue_inverse(p, out, cs);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    HIP_OK(hipStreamEndCapture(cs, &p->graph));
+    HIP_OK(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+}
+
+void do_launch_graph(rp_plan p, int64_t step) {
+    if (!p->graph_exec) fail(RP_ERR_STATE, "no captured step (rp_capture_step)");
+    if (step < 1 || step != p->next_step || p->pushed) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "rp_launch_step(%lld) out of order (expected step %lld >= 1)",
+                      (long long)step, (long long)p->next_step);
+        fail(RP_ERR_STATE, buf);
+    }
+    HIP_OK(hipGraphLaunch(p->graph_exec, p->stream));
+    p->next_step += 1;
+}
+
+// Time every lag-sum schedule on the bound plan (its current ring and
+// spectra; only the accumulator scratch is written) and keep the fastest.
+void do_autotune(rp_plan p, int iters, int32_t *best_unroll, int32_t *best_persist, double *best_ms) {
+    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
+    if (iters < 1) fail(RP_ERR_ARG, "iters must be >= 1");
+    hipStream_t st = p->stream;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    double best = 1e300;
+    int bu = p->k2_unroll, bp = p->k2_persist;
+    try {
+        for (int persist = 0; persist <= 1; ++persist) {
+            for (int unroll : {1, 2, 4}) {
+                enqueue_lagsum(p, st, unroll, persist);   // warm-up
+                HIP_OK(hipEventRecord(e0, st));
+                for (int i = 0; i < iters; ++i) enqueue_lagsum(p, st, unroll, persist);
+                HIP_OK(hipEventRecord(e1, st));
+                HIP_OK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms / iters < best) {
+                    best = ms / iters;
+                    bu = unroll;
+                    bp = persist;
+                }
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->k2_unroll = bu;
+    p->k2_persist = bp;
+    if (best_unroll) *best_unroll = bu;
+    if (best_persist) *best_persist = bp;
+    if (best_ms) *best_ms = best;
 }
 
 template <typename F>
@@ -1099,9 +1234,14 @@ rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value) {
             if (value != 1 && value != 2 && value != 4) fail(RP_ERR_ARG, "lag-sum unroll must be 1, 2 or 4");
             plan->k2_unroll = value;
             break;
+        case RP_TUNE_LAGSUM_PERSISTENT:
+            if (value != 0 && value != 1) fail(RP_ERR_ARG, "persistent must be 0 or 1");
+            plan->k2_persist = value;
+            break;
         default:
             fail(RP_ERR_ARG, "unknown tuning knob");
         }
+        release_graph(plan);   // a captured step holds the old schedule
     });
 }
 
@@ -1110,14 +1250,32 @@ rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value) {
         if (!value) fail(RP_ERR_ARG, "value is null");
         switch (knob) {
         case RP_TUNE_LAGSUM_UNROLL: *value = plan->k2_unroll; break;
+        case RP_TUNE_LAGSUM_PERSISTENT: *value = plan->k2_persist; break;
         default: fail(RP_ERR_ARG, "unknown tuning knob");
         }
     });
 }
 
+rp_status rp_autotune(rp_plan plan, int32_t iters, int32_t *unroll, int32_t *persistent, double *lagsum_ms) {
+    return guarded(plan, [&] {
+        do_autotune(plan, iters, unroll, persistent, lagsum_ms);
+        release_graph(plan);
+    });
+}
+
+rp_status rp_capture_step(rp_plan plan, const void *const *src, void *const *out) {
+    return guarded(plan, [&] { do_capture(plan, src, out); });
+}
+
+rp_status rp_launch_step(rp_plan plan, int64_t step) {
+    return guarded(plan, [&] { do_launch_graph(plan, step); });
+}
+
 rp_status rp_plan_destroy(rp_plan plan) {
     if (!plan) return RP_ERR_ARG;
     for (hipEvent_t ev : plan->events) (void)hipEventDestroy(ev);
+    release_graph(plan);
+    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
     delete plan;
     return RP_OK;
 }

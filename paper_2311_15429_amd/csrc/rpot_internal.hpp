@@ -172,6 +172,7 @@ struct K2Args {
     const float *scales;
     void *acc;
     const int32_t *head;   // [n_dom] current ring slot of every domain (step mod depth)
+    int *counter;          // persistent launch: next work item
     int n_items;
     int n_dom;
 };
@@ -182,7 +183,11 @@ void launch_line_pass(const LinePass &a, int prec64, hipStream_t st);
 void launch_zfwd(const ZFwd &a, int prec64, hipStream_t st);
 void launch_zinv(const ZInv &a, int prec64, hipStream_t st);
 int zfwd_lines_per_block(int Pz, int prec64);
-void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, int unroll, hipStream_t st);
+// grid_persist > 0: persistent launch with that many blocks (capped at the
+// item count); 0: one block per item.
+void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, int unroll, int grid_persist,
+                   hipStream_t st);
+int lagsum_blocks_per_cu(int prec64, int ring_fmt, int tg, int unroll);
 // Per-snapshot ring scales: for each job, scales[head*4 + mu] =
 // 2^(e-15) with npts * max_blocks zmax[b][mu] <= 2^e (1 when the max is 0).
 struct ScaleJob {

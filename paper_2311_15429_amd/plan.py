@@ -137,6 +137,25 @@ class Plan:
         _lib.check(self._lib, self._h, self._lib.rp_get_tuning(self._h, _lib.TUNE[knob], ctypes.byref(v)))
         return int(v.value)
 
+    def autotune(self, iters=3):
+        """Time every lag-sum schedule on this bound plan and keep the fastest.
+        Returns {"lagsum_unroll", "lagsum_persistent", "lagsum_ms"}."""
+        u, pe, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _lib.check(self._lib, self._h, self._lib.rp_autotune(self._h, int(iters), ctypes.byref(u),
+                                                             ctypes.byref(pe), ctypes.byref(ms)))
+        return {"lagsum_unroll": int(u.value), "lagsum_persistent": int(pe.value), "lagsum_ms": float(ms.value)}
+
+    def capture_step(self, sources, outputs):
+        """Record one whole step for these fixed buffers as a HIP graph."""
+        s_arr = self._ptrs(sources)
+        o_arr = self._ptrs(outputs)
+        self._graph_bufs = (list(sources), list(outputs))
+        _lib.check(self._lib, self._h, self._lib.rp_capture_step(self._h, s_arr, o_arr))
+
+    def launch_step(self, step):
+        """Replay the captured step as step `step`."""
+        _lib.check(self._lib, self._h, self._lib.rp_launch_step(self._h, int(step)))
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.rp_plan_destroy(self._h)
