@@ -207,6 +207,34 @@ rp_status rp_autotune(rp_plan plan, int32_t iters, int32_t *unroll, int32_t *per
 rp_status rp_capture_step(rp_plan plan, const void *const *src, void *const *out);
 rp_status rp_launch_step(rp_plan plan, int64_t step);
 
+/*
+ * Small fully connected network of the far-pair surrogate (training and
+ * inference run in this library's kernels):
+ *   h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3,
+ *   loss = sum (y - t)^2 / (2 batch n_out).
+ * Parameters: one flat FP32 vector [W1 (n_in x H), b1 (H), W2 (H x H), b2 (H),
+ * W3 (H x n_out), b3 (n_out)], row-major.  x, t, y are row-major
+ * [batch][n_in] / [batch][n_out] FP32 device arrays; batch <= max_batch.
+ * All calls are asynchronous on the stream given at creation; loss and grad
+ * outputs are device pointers.  The caller initialises the parameters
+ * (rp_mlp_set_params, which also restarts the optimiser).
+ */
+typedef struct rp_mlp_s *rp_mlp;
+rp_status rp_mlp_create(rp_mlp *out, int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t max_batch,
+                        void *hip_stream);
+rp_status rp_mlp_workspace_bytes(rp_mlp mlp, size_t *bytes);
+rp_status rp_mlp_bind(rp_mlp mlp, void *dev_ptr, size_t bytes);
+rp_status rp_mlp_n_params(rp_mlp mlp, int64_t *n);
+rp_status rp_mlp_set_params(rp_mlp mlp, const float *params);
+rp_status rp_mlp_get_params(rp_mlp mlp, float *params);
+rp_status rp_mlp_forward(rp_mlp mlp, const float *x, int32_t batch, float *y);
+/* loss (1 float) and the gradient of every parameter (flat, as the parameters) */
+rp_status rp_mlp_loss_grad(rp_mlp mlp, const float *x, const float *t, int32_t batch, float *loss, float *grad);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch; loss of the batch before the step */
+rp_status rp_mlp_train_step(rp_mlp mlp, const float *x, const float *t, int32_t batch, float lr, float *loss);
+rp_status rp_mlp_destroy(rp_mlp mlp);
+const char *rp_mlp_last_error(rp_mlp mlp);
+
 /* Release the host plan (the workspace stays the caller's). */
 rp_status rp_plan_destroy(rp_plan plan);
 

@@ -15,7 +15,10 @@ PRECISION = {"fp64": 0, "fp32": 1, "fp32_ring_fp16": 2, "fp32_ring_bf16": 3}
 EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_set_green_kernels",
            "rp_push_sources", "rp_retarded_step", "rp_plan_info", "rp_plan_stats",
            "rp_profile_lagsum", "rp_lagsum_time", "rp_set_tuning", "rp_get_tuning",
-           "rp_autotune", "rp_capture_step", "rp_launch_step", "rp_plan_destroy", "rp_last_error"]
+           "rp_autotune", "rp_capture_step", "rp_launch_step", "rp_mlp_create", "rp_mlp_workspace_bytes",
+           "rp_mlp_bind", "rp_mlp_n_params", "rp_mlp_set_params", "rp_mlp_get_params", "rp_mlp_forward",
+           "rp_mlp_loss_grad", "rp_mlp_train_step", "rp_mlp_destroy", "rp_plan_destroy", "rp_last_error",
+           "rp_mlp_last_error"]
 TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2}
 
 
@@ -66,8 +69,21 @@ def load():
     lib.rp_plan_destroy.argtypes = [vp]
     lib.rp_last_error.argtypes = [vp]
     lib.rp_last_error.restype = ctypes.c_char_p
-    for name in EXPORTS[:-1]:
-        getattr(lib, name).restype = ctypes.c_int
+    lib.rp_mlp_create.argtypes = [P(vp), i32, i32, i32, i32, vp]
+    lib.rp_mlp_workspace_bytes.argtypes = [vp, P(sz)]
+    lib.rp_mlp_bind.argtypes = [vp, vp, sz]
+    lib.rp_mlp_n_params.argtypes = [vp, P(i64)]
+    lib.rp_mlp_set_params.argtypes = [vp, vp]
+    lib.rp_mlp_get_params.argtypes = [vp, vp]
+    lib.rp_mlp_forward.argtypes = [vp, vp, i32, vp]
+    lib.rp_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, vp]
+    lib.rp_mlp_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp]
+    lib.rp_mlp_destroy.argtypes = [vp]
+    lib.rp_mlp_last_error.argtypes = [vp]
+    lib.rp_mlp_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("rp_last_error", "rp_mlp_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
 
@@ -75,4 +91,10 @@ def load():
 def check(lib, plan, code):
     if code != RP_OK:
         msg = lib.rp_last_error(plan)
+        raise RpotError(code, msg.decode() if msg else "")
+
+
+def check_mlp(lib, mlp, code):
+    if code != RP_OK:
+        msg = lib.rp_mlp_last_error(mlp)
         raise RpotError(code, msg.decode() if msg else "")

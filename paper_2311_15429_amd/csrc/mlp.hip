@@ -1,0 +1,393 @@
+// Small fully connected network for the far-pair surrogate: training and
+// inference kernels and their C-ABI (rp_mlp_*).
+//
+//   h1 = tanh(x W1 + b1),  h2 = tanh(h1 W2 + b2),  y = h2 W3 + b3
+//   loss = sum (y - t)^2 / (2 B n_out)
+//
+// Parameters are one flat FP32 vector [W1 (n_in x H), b1 (H), W2 (H x H),
+// b2 (H), W3 (H x n_out), b3 (n_out)], row-major, in the bound workspace.
+// Matrix products run in one LDS-tiled FP32 kernel (64 x 64 output tile,
+// 16-deep K slices, 4 x 4 outputs per thread) with strided operands, so the
+// transposed products of the backward pass need no copies.
+#include "rpot.h"
+#include "rpot_internal.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+namespace rpot {
+
+namespace {
+
+constexpr int kGT = 64;   // output tile
+constexpr int kGK = 16;   // K slice
+
+struct GemmArgs {
+    const float *A;        // A(i, k) = A[i * sa0 + k * sa1]
+    const float *B;        // B(k, j) = B[k * sb0 + j * sb1]
+    float *C;              // C(i, j) = C[i * ldc + j]
+    const float *bias;     // + bias[j] (or null)
+    int64_t sa0, sa1, sb0, sb1, ldc;
+    int M, N, K;
+    int act;               // 0 none, 1 tanh
+    float beta;            // C = beta * C + A B
+};
+
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+    __shared__ float As[kGK][kGT + 4];
+    __shared__ float Bs[kGK][kGT + 4];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int i0 = blockIdx.y * kGT, j0 = blockIdx.x * kGT;
+    float acc[4][4] = {};
+    for (int k0 = 0; k0 < g.K; k0 += kGK) {
+        for (int e = threadIdx.x; e < kGK * kGT; e += 256) {
+            const int kk = e / kGT, ii = e % kGT;
+            const int i = i0 + ii, k = k0 + kk;
+            As[kk][ii] = (i < g.M && k < g.K) ? g.A[i * g.sa0 + k * g.sa1] : 0.f;
+            const int j = j0 + ii;
+            Bs[kk][ii] = (j < g.N && k < g.K) ? g.B[k * g.sb0 + j * g.sb1] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGK; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = i0 + ty * 4 + r;
+        if (i >= g.M) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int j = j0 + tx * 4 + c;
+            if (j >= g.N) continue;
+            float v = acc[r][c];
+            if (g.bias) v += g.bias[j];
+            if (g.beta != 0.f) v += g.beta * g.C[int64_t(i) * g.ldc + j];
+            if (g.act == 1) v = tanhf(v);
+            g.C[int64_t(i) * g.ldc + j] = v;
+        }
+    }
+}
+
+void gemm(hipStream_t st, const float *A, int64_t sa0, int64_t sa1, const float *B, int64_t sb0, int64_t sb1,
+          float *C, int64_t ldc, int M, int N, int K, const float *bias, int act, float beta) {
+    GemmArgs g{A, B, C, bias, sa0, sa1, sb0, sb1, ldc, M, N, K, act, beta};
+    dim3 grid((N + kGT - 1) / kGT, (M + kGT - 1) / kGT);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+}
+
+// dy = (y - t) / (B n_out); loss partial sums per block
+__global__ void k_mse_grad(const float *y, const float *t, float *dy, int64_t n, float inv, float *part) {
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        const float d = y[i] - t[i];
+        dy[i] = d * inv;
+        s += d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// loss = sum(part) * scale (one block)
+__global__ void k_sum_parts(const float *part, int n, float scale, float *loss) {
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] * scale;
+}
+
+// dz = dh * (1 - h^2)  (tanh derivative), in place on dh
+__global__ void k_tanh_back(float *dh, const float *h, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+        dh[i] *= 1.f - h[i] * h[i];
+}
+
+// db[j] = sum_i dz[i][j]
+__global__ void k_colsum(const float *dz, int rows, int cols, float *db) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= cols) return;
+    float s = 0.f;
+    for (int i = 0; i < rows; ++i) s += dz[int64_t(i) * cols + j];
+    db[j] = s;
+}
+
+__global__ void k_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    }
+}
+
+__global__ void k_copy_f32(float *dst, const float *src, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) dst[i] = src[i];
+}
+
+int nblocks(int64_t n) { return int(std::min<int64_t>((n + 255) / 256, 4096)); }
+
+}  // namespace
+}  // namespace rpot
+
+using namespace rpot;
+
+struct rp_mlp_s {
+    int n_in = 0, H = 0, n_out = 0, max_batch = 0;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t n_params = 0;
+    size_t off_w = 0, off_g = 0, off_m = 0, off_v = 0, off_h1 = 0, off_h2 = 0, off_y = 0, off_dy = 0, off_d2 = 0,
+           off_d1 = 0, off_part = 0;
+    int64_t step = 0;
+    std::string err;
+    float *W1() { return f(off_w); }
+    float *b1() { return W1() + int64_t(n_in) * H; }
+    float *W2() { return b1() + H; }
+    float *b2() { return W2() + int64_t(H) * H; }
+    float *W3() { return b2() + H; }
+    float *b3() { return W3() + int64_t(H) * n_out; }
+    float *f(size_t off) { return reinterpret_cast<float *>(ws + off); }
+};
+
+namespace {
+
+struct MErr {
+    rp_status code;
+    std::string msg;
+};
+
+[[noreturn]] void mfail(rp_status c, const std::string &m) { throw MErr{c, m}; }
+
+thread_local std::string g_mlp_create_error;
+
+template <typename F>
+rp_status mguard(rp_mlp m, F &&fn) {
+    if (!m) return RP_ERR_ARG;
+    try {
+        m->err.clear();
+        fn();
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) mfail(RP_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+        return RP_OK;
+    } catch (const MErr &e) {
+        m->err = e.msg;
+        return e.code;
+    } catch (...) {
+        m->err = "unknown error";
+        return RP_ERR_ARG;
+    }
+}
+
+void need_bound(rp_mlp m) {
+    if (!m->ws) mfail(RP_ERR_STATE, "workspace not bound");
+}
+
+void check_batch(rp_mlp m, int batch) {
+    if (batch < 1 || batch > m->max_batch) mfail(RP_ERR_ARG, "batch outside [1, max_batch]");
+}
+
+void forward(rp_mlp m, const float *x, int B, float *y) {
+    hipStream_t st = m->stream;
+    const int H = m->H;
+    gemm(st, x, m->n_in, 1, m->W1(), H, 1, m->f(m->off_h1), H, B, H, m->n_in, m->b1(), 1, 0.f);
+    gemm(st, m->f(m->off_h1), H, 1, m->W2(), H, 1, m->f(m->off_h2), H, B, H, H, m->b2(), 1, 0.f);
+    gemm(st, m->f(m->off_h2), H, 1, m->W3(), m->n_out, 1, y, m->n_out, B, m->n_out, H, m->b3(), 0, 0.f);
+}
+
+// Loss into *loss_dev and the gradient of every parameter into grad (flat).
+void loss_grad(rp_mlp m, const float *x, const float *t, int B, float *loss_dev, float *grad) {
+    hipStream_t st = m->stream;
+    const int H = m->H, no = m->n_out, ni = m->n_in;
+    float *y = m->f(m->off_y), *dy = m->f(m->off_dy), *h1 = m->f(m->off_h1), *h2 = m->f(m->off_h2);
+    float *d2 = m->f(m->off_d2), *d1 = m->f(m->off_d1);
+    forward(m, x, B, y);
+    const int64_t ny = int64_t(B) * no;
+    const int nb = std::min(nblocks(ny), 256);
+    hipLaunchKernelGGL(k_mse_grad, dim3(nb), dim3(256), 0, st, y, t, dy, ny, 1.f / float(ny), m->f(m->off_part));
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, m->f(m->off_part), nb, 0.5f / float(ny), loss_dev);
+    float *gW1 = grad, *gb1 = gW1 + int64_t(ni) * H, *gW2 = gb1 + H, *gb2 = gW2 + int64_t(H) * H;
+    float *gW3 = gb2 + H, *gb3 = gW3 + int64_t(H) * no;
+    // layer 3: gW3 = h2^T dy, gb3 = colsum dy, d2 = dy W3^T
+    gemm(st, h2, 1, H, dy, no, 1, gW3, no, H, no, B, nullptr, 0, 0.f);
+    hipLaunchKernelGGL(k_colsum, dim3((no + 255) / 256), dim3(256), 0, st, dy, B, no, gb3);
+    gemm(st, dy, no, 1, m->W3(), 1, no, d2, H, B, H, no, nullptr, 0, 0.f);
+    hipLaunchKernelGGL(k_tanh_back, dim3(nblocks(int64_t(B) * H)), dim3(256), 0, st, d2, h2, int64_t(B) * H);
+    // layer 2
+    gemm(st, h1, 1, H, d2, H, 1, gW2, H, H, H, B, nullptr, 0, 0.f);
+    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, d2, B, H, gb2);
+    gemm(st, d2, H, 1, m->W2(), 1, H, d1, H, B, H, H, nullptr, 0, 0.f);
+    hipLaunchKernelGGL(k_tanh_back, dim3(nblocks(int64_t(B) * H)), dim3(256), 0, st, d1, h1, int64_t(B) * H);
+    // layer 1
+    gemm(st, x, 1, ni, d1, H, 1, gW1, H, ni, H, B, nullptr, 0, 0.f);
+    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, d1, B, H, gb1);
+}
+
+}  // namespace
+
+extern "C" {
+
+rp_status rp_mlp_create(rp_mlp *out, int32_t n_in, int32_t n_hidden, int32_t n_out, int32_t max_batch,
+                        void *hip_stream) {
+    if (!out) {
+        g_mlp_create_error = "out is null";
+        return RP_ERR_ARG;
+    }
+    *out = nullptr;
+    if (n_in < 1 || n_hidden < 1 || n_out < 1 || max_batch < 1) {
+        g_mlp_create_error = "sizes must be >= 1";
+        return RP_ERR_ARG;
+    }
+    rp_mlp m = new (std::nothrow) rp_mlp_s();
+    if (!m) return RP_ERR_NOMEM;
+    m->n_in = n_in;
+    m->H = n_hidden;
+    m->n_out = n_out;
+    m->max_batch = max_batch;
+    m->stream = static_cast<hipStream_t>(hip_stream);
+    m->n_params = int64_t(n_in) * n_hidden + n_hidden + int64_t(n_hidden) * n_hidden + n_hidden +
+                  int64_t(n_hidden) * n_out + n_out;
+    size_t off = 0;
+    auto alloc = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const size_t P = size_t(m->n_params) * 4, BH = size_t(max_batch) * n_hidden * 4, BO = size_t(max_batch) * n_out * 4;
+    m->off_w = alloc(P);
+    m->off_g = alloc(P);
+    m->off_m = alloc(P);
+    m->off_v = alloc(P);
+    m->off_h1 = alloc(BH);
+    m->off_h2 = alloc(BH);
+    m->off_y = alloc(BO);
+    m->off_dy = alloc(BO);
+    m->off_d2 = alloc(BH);
+    m->off_d1 = alloc(BH);
+    m->off_part = alloc(256 * 4 + 16);
+    m->ws_bytes = off;
+    *out = m;
+    return RP_OK;
+}
+
+rp_status rp_mlp_workspace_bytes(rp_mlp m, size_t *bytes) {
+    return mguard(m, [&] {
+        if (!bytes) mfail(RP_ERR_ARG, "bytes is null");
+        *bytes = m->ws_bytes;
+    });
+}
+
+rp_status rp_mlp_n_params(rp_mlp m, int64_t *n) {
+    return mguard(m, [&] {
+        if (!n) mfail(RP_ERR_ARG, "n is null");
+        *n = m->n_params;
+    });
+}
+
+rp_status rp_mlp_bind(rp_mlp m, void *dev, size_t bytes) {
+    return mguard(m, [&] {
+        if (!dev || reinterpret_cast<uintptr_t>(dev) % 256) mfail(RP_ERR_ARG, "workspace must be 256-byte aligned");
+        if (bytes < m->ws_bytes) mfail(RP_ERR_NOMEM, "workspace smaller than rp_mlp_workspace_bytes");
+        m->ws = static_cast<char *>(dev);
+        // every region is 256-byte aligned and padded, so whole 16-byte words fit
+        launch_fill_zero(m->ws + m->off_m, (size_t(m->n_params) * 4 + 15) / 16 * 16, m->stream);
+        launch_fill_zero(m->ws + m->off_v, (size_t(m->n_params) * 4 + 15) / 16 * 16, m->stream);
+        m->step = 0;
+    });
+}
+
+rp_status rp_mlp_set_params(rp_mlp m, const float *params) {
+    return mguard(m, [&] {
+        need_bound(m);
+        if (!params) mfail(RP_ERR_ARG, "params is null");
+        hipLaunchKernelGGL(k_copy_f32, dim3(nblocks(m->n_params)), dim3(256), 0, m->stream, m->f(m->off_w), params,
+                           m->n_params);
+        // restart the optimiser moments with new parameters
+        launch_fill_zero(m->ws + m->off_m, (size_t(m->n_params) * 4 + 15) / 16 * 16, m->stream);
+        launch_fill_zero(m->ws + m->off_v, (size_t(m->n_params) * 4 + 15) / 16 * 16, m->stream);
+        m->step = 0;
+    });
+}
+
+rp_status rp_mlp_get_params(rp_mlp m, float *params) {
+    return mguard(m, [&] {
+        need_bound(m);
+        if (!params) mfail(RP_ERR_ARG, "params is null");
+        hipLaunchKernelGGL(k_copy_f32, dim3(nblocks(m->n_params)), dim3(256), 0, m->stream, params, m->f(m->off_w),
+                           m->n_params);
+    });
+}
+
+rp_status rp_mlp_forward(rp_mlp m, const float *x, int32_t batch, float *y) {
+    return mguard(m, [&] {
+        need_bound(m);
+        check_batch(m, batch);
+        if (!x || !y) mfail(RP_ERR_ARG, "null pointer");
+        forward(m, x, batch, y);
+    });
+}
+
+rp_status rp_mlp_loss_grad(rp_mlp m, const float *x, const float *t, int32_t batch, float *loss, float *grad) {
+    return mguard(m, [&] {
+        need_bound(m);
+        check_batch(m, batch);
+        if (!x || !t || !loss || !grad) mfail(RP_ERR_ARG, "null pointer");
+        loss_grad(m, x, t, batch, loss, grad);
+    });
+}
+
+rp_status rp_mlp_train_step(rp_mlp m, const float *x, const float *t, int32_t batch, float lr, float *loss) {
+    return mguard(m, [&] {
+        need_bound(m);
+        check_batch(m, batch);
+        if (!x || !t || !loss) mfail(RP_ERR_ARG, "null pointer");
+        if (!(lr > 0.f)) mfail(RP_ERR_ARG, "lr must be positive");
+        loss_grad(m, x, t, batch, loss, m->f(m->off_g));
+        m->step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.f / (1.f - std::pow(b1, float(m->step)));
+        const float c2 = 1.f / (1.f - std::pow(b2, float(m->step)));
+        hipLaunchKernelGGL(k_adam, dim3(nblocks(m->n_params)), dim3(256), 0, m->stream, m->f(m->off_w),
+                           m->f(m->off_g), m->f(m->off_m), m->f(m->off_v), m->n_params, lr, b1, b2, 1e-8f, c1, c2);
+    });
+}
+
+rp_status rp_mlp_destroy(rp_mlp m) {
+    if (!m) return RP_ERR_ARG;
+    delete m;
+    return RP_OK;
+}
+
+const char *rp_mlp_last_error(rp_mlp m) {
+    if (!m) return g_mlp_create_error.c_str();
+    return m->err.c_str();
+}
+
+}  // extern "C"
