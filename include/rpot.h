@@ -235,6 +235,76 @@ rp_status rp_mlp_train_step(rp_mlp mlp, const float *x, const float *t, int32_t 
 rp_status rp_mlp_destroy(rp_mlp mlp);
 const char *rp_mlp_last_error(rp_mlp mlp);
 
+/*
+ * Learned far-pair surrogate (an extension: the paper's closing section points
+ * at a multipole approximation of the retarded potentials of far sub-domains
+ * as a further speed-up; here the far coupling is learned from the plain
+ * method's pair responses).
+ *
+ * A pair (target s <- source n, s != n, one system) is far when the distance
+ * of the box centres |c_s - c_n| exceeds far_factor times the larger of the
+ * two box diagonals.  Far pairs leave the plain lag sum.  Every source of a far
+ * pair keeps a ring of 22 moments of dS = S - S(0) about its centre, weight h^3:
+ *   q = sum dS_0, p_i = sum dS_0 x_i, Q_ij = sum dS_0 x_i x_j (xx yy zz xy xz yz),
+ *   J_i = sum dS_{1+i}, K_ij = sum dS_{1+i} x_j.
+ * The network input of a far pair at step l is, for the n_lags lags
+ * m = m_c - n_lags/2 + j (m_c = round(|c_s - c_n| / (c dt))), the moments of
+ * step l - m (zero for l - m <= 0) rotated into the pair frame (rows e1 along
+ * c_s - c_n, e2, e3) and multiplied by in_scale[22], followed by two geometry
+ * values (10 dbar / |c_s - c_n| with dbar the mean box diagonal of the plan,
+ * and |c_s - c_n| / (c dt) - m_c): n_in = 22 n_lags + 2.  Its 80 outputs y,
+ * times out_scale[80] / |c_s - c_n|, are the coefficients a[mu][b] of the pair's
+ * potential component mu (frame components for A) in the tensor-Legendre basis
+ * P_i P_j P_k (i + j + k <= 3, lexicographic (i, j, k)) of
+ * u = R (r - c_s) / ell, ell = the target's largest half side.  The library maps
+ * them to the target box basis (box coordinates in [-1, 1]) and adds the field
+ * of the target's active far pairs to its output in rp_retarded_step (and in a
+ * captured step).
+ *
+ * Audit sources keep the plain history of all their pairs (ring and spectra):
+ * their far pairs are judged against the plain pair sum, may fall back to it,
+ * and give the plain pair responses that train the network.
+ *
+ * rp_surrogate_configure  before rp_workspace_bytes / rp_bind_workspace
+ *     (RP_ERR_STATE after).  far_factor <= 0 switches the surrogate off.
+ *     Needs a finite c, a precision other than RP_FP64, 1 <= n_lags <= 1024, and
+ *     at least 4 points per axis on every far-pair target (RP_ERR_UNSUPPORTED).
+ *     audit: n_audit source domains (host array, may be NULL when n_audit = 0).
+ *     Re-plans ring depths, spectra, schedules and the workspace size.
+ * rp_surrogate_info   counts: far pairs, audited far pairs, n_in, n_out (80).
+ * rp_surrogate_pairs  host arrays [n_far] (any may be NULL): target, source,
+ *     centre distance, audited flag, fallen-back flag, in far-pair order.
+ * rp_surrogate_attach the network used by every later step (NULL detaches:
+ *     far pairs then contribute nothing).  in_scale [22], out_scale [80] are host
+ *     arrays.  The network must have n_in inputs, 80 outputs and max_batch >= the
+ *     far-pair count, stay alive while attached, and not run on another stream
+ *     during a step.  Discards a captured step.
+ * rp_surrogate_features  device [n_far][n_in] FP32: the network inputs of the
+ *     last completed step.
+ * rp_surrogate_pair_response  for the audited far pairs (in the order of
+ *     rp_surrogate_pairs restricted to audited pairs) at the last completed step:
+ *     the plain pair field F (the lag sum over that pair alone, inverse
+ *     transformed and cropped), its least-squares coefficients a[mu][b] in the
+ *     network's frame basis (device [n_aud][80]) and resid (device [n_aud][8]):
+ *     max |F_mu - fit_mu| for mu < 4, then max |F_mu|.
+ * rp_surrogate_judge  judges every active audited far pair of the last
+ *     completed step: a pair whose error max_r |F_mu - surrogate_mu| exceeds
+ *     tol * max_r |out_s,mu| / (active far pairs of s) in any component falls
+ *     back to the plain lag sum from the next step on, and its term in out (the
+ *     outputs of that step, corrected in place) is replaced by F.  Returns the
+ *     number of pairs that fell back and the largest error/budget ratio over the
+ *     judged pairs.  Synchronises the stream.  A captured step stays valid.
+ */
+rp_status rp_surrogate_configure(rp_plan plan, double far_factor, int32_t n_lags, const int32_t *audit,
+                                 int32_t n_audit);
+rp_status rp_surrogate_info(rp_plan plan, int32_t *n_far, int32_t *n_audited, int32_t *n_in, int32_t *n_out);
+rp_status rp_surrogate_pairs(rp_plan plan, int32_t *target, int32_t *source, double *dist, int32_t *audited,
+                             int32_t *fallen_back);
+rp_status rp_surrogate_attach(rp_plan plan, rp_mlp mlp, const float *in_scale, const float *out_scale);
+rp_status rp_surrogate_features(rp_plan plan, float *x);
+rp_status rp_surrogate_pair_response(rp_plan plan, float *coef, float *resid);
+rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t *n_fallback, double *worst);
+
 /* Release the host plan (the workspace stays the caller's). */
 rp_status rp_plan_destroy(rp_plan plan);
 

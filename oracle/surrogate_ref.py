@@ -1,0 +1,161 @@
+"""FP64 reference of the fixed (not learned) parts of the far-pair surrogate.
+
+Test infrastructure: only tests/, the smoke check and the bench's CPU baseline
+use this module.  It shares no code with the HIP path.
+
+The paper ends by naming a multipole approximation of far sub-domains' retarded
+potentials as a further speed-up (Sec. V, conclusion).  The surrogate learns
+that far coupling; what it computes besides the network is defined here from
+first principles:
+
+* moments of dS = S(t) - S(0) of a source domain about its box centre c, with
+  the quadrature weight h^3 of the discrete lag sum (Sec. III): charge q,
+  dipole p, second moment Q (xx yy zz xy xz yz), current monopole J and current
+  first moment K_ij = sum dS_{1+i} x_j;
+* the pair frame: e1 along c_target - c_source, e2 the unit part of a reference
+  axis (z, or x when e1 is within 25.8 degrees of z) orthogonal to e1,
+  e3 = e1 x e2;
+* the network input of a pair at step l: moments of steps l - m for the lags
+  m = m_c - n_lags/2 + j, rotated into the frame (vectors R v, tensors R T R^T),
+  then (10 dbar / |d|, |d|/(c dt) - m_c);
+* the cubic tensor-Legendre basis P_i(x) P_j(y) P_k(z), i + j + k <= 3, and the
+  least-squares coefficients of a field on the target grid in the frame
+  variables u = R (r - c_target) / ell (A components taken in the frame).
+
+Parity of the learned output itself is unpinned: it is an approximation,
+judged against the plain lag sum and the direct sum at sampled points.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+DEGREES = [(i, j, k) for i in range(4) for j in range(4) for k in range(4) if i + j + k <= 3]
+N_FEAT = 22
+N_GEO = 2
+
+
+def grid_points(dom, h):
+    axes = [dom.origin[a] + h * np.arange(dom.dims[a]) for a in range(3)]
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def box_centre(dom, h):
+    return np.asarray(dom.origin, dtype=np.float64) + 0.5 * h * (np.asarray(dom.dims) - 1)
+
+
+def box_diagonal(dom, h):
+    return float(np.linalg.norm(h * (np.asarray(dom.dims) - 1)))
+
+
+def moments(dS, dom, h):
+    """The 22 moments of dS [4][N] about the domain's centre (FP64)."""
+    r = grid_points(dom, h) - box_centre(dom, h)[None, :]
+    w = h ** 3
+    rho, J = dS[0], dS[1:4]
+    out = np.zeros(N_FEAT)
+    out[0] = w * rho.sum()
+    out[1:4] = w * (rho[:, None] * r).sum(axis=0)
+    second = w * np.einsum("n,ni,nj->ij", rho, r, r)
+    out[4:10] = [second[0, 0], second[1, 1], second[2, 2], second[0, 1], second[0, 2], second[1, 2]]
+    out[10:13] = w * J.sum(axis=1)
+    out[13:22] = (w * J @ r).ravel()            # K[i][j] = sum J_i x_j
+    return out
+
+
+def frame(d):
+    """Rows e1, e2, e3 of the pair frame for d = c_target - c_source."""
+    d = np.asarray(d, dtype=np.float64)
+    e1 = d / np.linalg.norm(d)
+    ref = np.array([1.0, 0.0, 0.0]) if abs(e1[2]) > 0.9 else np.array([0.0, 0.0, 1.0])
+    e2 = ref - (ref @ e1) * e1
+    e2 /= np.linalg.norm(e2)
+    return np.stack([e1, e2, np.cross(e1, e2)])
+
+
+def rotate(m, R):
+    """Moments m [22] expressed in the frame with axes R (rows)."""
+    out = np.zeros(N_FEAT)
+    out[0] = m[0]
+    out[1:4] = R @ m[1:4]
+    Q = np.array([[m[4], m[7], m[8]], [m[7], m[5], m[9]], [m[8], m[9], m[6]]])
+    Qr = R @ Q @ R.T
+    out[4:10] = [Qr[0, 0], Qr[1, 1], Qr[2, 2], Qr[0, 1], Qr[0, 2], Qr[1, 2]]
+    out[10:13] = R @ m[10:13]
+    out[13:22] = (R @ m[13:22].reshape(3, 3) @ R.T).ravel()
+    return out
+
+
+def pair_geometry(system, s, n):
+    """(d = c_s - c_n, |d|, m_c, frac) of the pair target s <- source n."""
+    h = system.h
+    d = box_centre(system.domains[s], h) - box_centre(system.domains[n], h)
+    dist = float(np.linalg.norm(d))
+    x = dist / (system.c * system.dt)
+    m_c = int(math.floor(x + 0.5))
+    return d, dist, m_c, x - m_c
+
+
+def features(system, samples, s, n, l, n_lags):
+    """Network input of pair (s <- n) at step l; samples[n][t] = S(t) [4][N]."""
+    h = system.h
+    d, dist, m_c, frac = pair_geometry(system, s, n)
+    R = frame(d)
+    dom = system.domains[n]
+    x = np.zeros(n_lags * N_FEAT + N_GEO)
+    for j in range(n_lags):
+        m = m_c - n_lags // 2 + j
+        t = l - m
+        if t > 0 and m >= 0:
+            x[j * N_FEAT:(j + 1) * N_FEAT] = rotate(moments(samples[n][t] - samples[n][0], dom, h), R)
+    dbar = np.mean([box_diagonal(dm, h) for dm in system.domains])
+    x[n_lags * N_FEAT] = 10.0 * dbar / dist
+    x[n_lags * N_FEAT + 1] = frac
+    return x
+
+
+def legendre(x):
+    x = np.asarray(x, dtype=np.float64)
+    return [np.ones_like(x), x, 0.5 * (3 * x * x - 1), 0.5 * x * (5 * x * x - 3)]
+
+
+def basis(u):
+    """[npts][20] basis values at points u [npts][3]."""
+    px, py, pz = legendre(u[:, 0]), legendre(u[:, 1]), legendre(u[:, 2])
+    return np.stack([px[i] * py[j] * pz[k] for i, j, k in DEGREES], axis=1)
+
+
+def frame_coords(system, s, R):
+    dom = system.domains[s]
+    h = system.h
+    ell = 0.5 * h * (max(dom.dims) - 1)
+    r = grid_points(dom, h) - box_centre(dom, h)[None, :]
+    return (r @ R.T) / ell
+
+
+def box_coords(dom):
+    axes = [np.linspace(-1.0, 1.0, n) for n in dom.dims]
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def frame_fit(system, s, n, F):
+    """Least-squares frame coefficients a [4][20] of a field F [4][N_s] on
+    target s for the pair (s <- n); the A part is taken in frame components."""
+    d, _, _, _ = pair_geometry(system, s, n)
+    R = frame(d)
+    B = basis(frame_coords(system, s, R))
+    G = np.vstack([F[0][None, :], R @ F[1:4]])
+    coef, *_ = np.linalg.lstsq(B, G.T, rcond=None)
+    return coef.T
+
+
+def frame_synth(system, s, n, a):
+    """Field [4][N_s] of frame coefficients a [4][20] (inverse of frame_fit)."""
+    d, _, _, _ = pair_geometry(system, s, n)
+    R = frame(d)
+    B = basis(frame_coords(system, s, R))
+    G = (B @ a.T).T
+    return np.vstack([G[0][None, :], R.T @ G[1:4]])

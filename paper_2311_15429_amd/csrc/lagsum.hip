@@ -426,16 +426,18 @@ void launch_fill_zero(void *dst, size_t bytes, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_zero, dim3(unsigned(nb)), dim3(256), 0, st, reinterpret_cast<uint4 *>(dst), n16);
 }
 
-__global__ void k_advance_step(int64_t *step, int32_t *head, const DomDev *doms, int n_dom) {
+__global__ void k_advance_step(int64_t *step, int32_t *head, int32_t *prev, const DomDev *doms, int n_dom) {
     for (int i = threadIdx.x; i < n_dom; i += blockDim.x) {
-        const int32_t h = head[i] + 1;
-        head[i] = (h == doms[i].depth) ? 0 : h;
+        const int32_t h = head[i];
+        prev[i] = h;
+        head[i] = (h + 1 == doms[i].depth) ? 0 : h + 1;
     }
     if (threadIdx.x == 0) *step += 1;
 }
 
-void launch_advance_step(int64_t *step, int32_t *head, const DomDev *doms, int n_dom, hipStream_t st) {
-    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(256), 0, st, step, head, doms, n_dom);
+void launch_advance_step(int64_t *step, int32_t *head, int32_t *prev, const DomDev *doms, int n_dom,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(256), 0, st, step, head, prev, doms, n_dom);
 }
 
 }  // namespace rpot

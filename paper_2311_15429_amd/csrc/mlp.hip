@@ -214,8 +214,7 @@ void check_batch(rp_mlp m, int batch) {
     if (batch < 1 || batch > m->max_batch) mfail(RP_ERR_ARG, "batch outside [1, max_batch]");
 }
 
-void forward(rp_mlp m, const float *x, int B, float *y) {
-    hipStream_t st = m->stream;
+void forward(rp_mlp m, const float *x, int B, float *y, hipStream_t st) {
     const int H = m->H;
     gemm(st, x, m->n_in, 1, m->W1(), H, 1, m->f(m->off_h1), H, B, H, m->n_in, m->b1(), 1, 0.f);
     gemm(st, m->f(m->off_h1), H, 1, m->W2(), H, 1, m->f(m->off_h2), H, B, H, H, m->b2(), 1, 0.f);
@@ -228,7 +227,7 @@ void loss_grad(rp_mlp m, const float *x, const float *t, int B, float *loss_dev,
     const int H = m->H, no = m->n_out, ni = m->n_in;
     float *y = m->f(m->off_y), *dy = m->f(m->off_dy), *h1 = m->f(m->off_h1), *h2 = m->f(m->off_h2);
     float *d2 = m->f(m->off_d2), *d1 = m->f(m->off_d1);
-    forward(m, x, B, y);
+    forward(m, x, B, y, st);
     const int64_t ny = int64_t(B) * no;
     const int nb = std::min(nblocks(ny), 256);
     hipLaunchKernelGGL(k_mse_grad, dim3(nb), dim3(256), 0, st, y, t, dy, ny, 1.f / float(ny), m->f(m->off_part));
@@ -251,6 +250,20 @@ void loss_grad(rp_mlp m, const float *x, const float *t, int B, float *loss_dev,
 }
 
 }  // namespace
+
+namespace rpot {
+
+bool mlp_dims(rp_mlp m, int *n_in, int *n_out, int *max_batch) {
+    if (!m || !m->ws) return false;
+    *n_in = m->n_in;
+    *n_out = m->n_out;
+    *max_batch = m->max_batch;
+    return true;
+}
+
+void mlp_forward_on(rp_mlp m, const float *x, int batch, float *y, hipStream_t st) { forward(m, x, batch, y, st); }
+
+}  // namespace rpot
 
 extern "C" {
 
@@ -350,7 +363,7 @@ rp_status rp_mlp_forward(rp_mlp m, const float *x, int32_t batch, float *y) {
         need_bound(m);
         check_batch(m, batch);
         if (!x || !y) mfail(RP_ERR_ARG, "null pointer");
-        forward(m, x, batch, y);
+        forward(m, x, batch, y, m->stream);
     });
 }
 

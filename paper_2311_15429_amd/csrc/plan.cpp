@@ -7,42 +7,21 @@
 // source differences in a ring as deep as its longest lag; a step is the
 // forward transform of the new sources, the lag sum in the frequency domain,
 // and the inverse transform cropped to each target.
-#include "rpot.h"
-#include "rpot_internal.hpp"
+#include "plan_internal.hpp"
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <exception>
-#include <map>
 #include <new>
-#include <string>
-#include <vector>
 
 using namespace rpot;
 
+namespace rpot_host {
+
 namespace {
-
 thread_local std::string g_create_error;
-
-struct Error {
-    rp_status code;
-    std::string msg;
-};
-
-[[noreturn]] void fail(rp_status c, const std::string &m) { throw Error{c, m}; }
-
-#define HIP_OK(expr)                                                                               \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) fail(RP_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-constexpr int kGroupMax = 8;      // targets per lag-sum thread
-constexpr int kGreenChunk = kMaxJobs;
-constexpr int kMaxPad = 512;     // z passes stage >= 4 lines of the pad in 32 KiB of LDS
-constexpr size_t kAlign = 256;
 
 // Smallest even 2^a 3^b >= n.
 int smooth_even(int n) {
@@ -54,6 +33,7 @@ int smooth_even(int n) {
         if (r == 1) return m;
     }
 }
+}  // namespace
 
 RadixPlan make_radix(int P) {
     RadixPlan rp{};
@@ -64,102 +44,6 @@ RadixPlan make_radix(int P) {
     if (n != 1) fail(RP_ERR_UNSUPPORTED, "FFT length is not 2^a 3^b");
     return rp;
 }
-
-struct DomainP {
-    int N[3];
-    double o[3];
-    int sys;
-    int64_t npts;
-    int depth = 1;
-    int zblocks = 0;
-    size_t off_ring = 0, off_scales = 0, off_zmax = 0, off_s0 = 0, off_p0 = 0, off_acc = 0;
-    size_t off_t1 = 0, off_t2 = 0, off_s0hat = 0;
-};
-
-struct SystemP {
-    std::vector<int> doms;
-    int P[3];
-    int Hz;
-    int64_t C;
-    int64_t Cpad;            // C rounded up to whole frequency tiles
-    int64_t spec_base = 0;   // complex elements
-    int64_t n_spec = 0;      // stored spectra (one per lag of every unordered pair)
-    int64_t spec_elems = 0;  // their storage, tile-major per pair
-};
-
-struct PairP {
-    int m_lo = -1, m_hi = -1;
-    double rmin = 0, rmax = 0;
-    int64_t spec0 = -1;      // element offset (within the system) of the pair's spectra,
-                             // stored [tile][lag][kTile]
-    bool conj = false;
-};
-
-struct ClassP {
-    int N[3];
-    int P[3];
-    int Hz;
-    int64_t C;
-    std::vector<int> doms;
-};
-
-}  // namespace
-
-struct rp_plan_s {
-    int n_dom = 0;
-    double h = 0, dt = 0, c = 0;
-    rp_precision prec = RP_FP64;
-    hipStream_t stream = nullptr;
-    bool p64 = true;
-    int ring_fmt = RING_F64;
-    size_t tsz = 8, csz = 16, ring_esz = 16, spec_csz = 16;
-    double w_self0 = 0, w_self1 = 0, w_static = 0;
-
-    std::vector<DomainP> dom;
-    std::vector<SystemP> sys;
-    std::vector<PairP> pair;   // [s * n_dom + n]
-    std::vector<ClassP> cls;
-
-    std::vector<K2Group> groups;
-    std::vector<K2Entry> entries;
-    std::vector<K2Src> srcs;
-    std::vector<K2Pair> pairs;
-    std::vector<uint32_t> masks;
-    std::vector<K2Item> items;
-    std::vector<DomDev> domdev;
-    int tg = 1;
-    int k2_unroll = 1;   // lags whose loads a lag-sum thread issues together
-    int k2_persist = 0;  // persistent lag-sum launch (work counter) instead of one block per item
-    int n_cu = 0;        // compute units of the bound device
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    hipStream_t capture_stream = nullptr;
-
-    std::map<int, size_t> tw64, tw32;   // FFT length -> byte offset of its twiddles
-    size_t off_state = 0, off_head = 0, off_items = 0, off_groups = 0, off_entries = 0, off_domdev = 0;
-    size_t off_srcs = 0, off_pairs = 0, off_masks = 0, off_counter = 0;
-    size_t off_spec = 0, off_gtmp = 0, off_accd = 0, off_gstat = 0, off_t1d = 0, off_t2d = 0;
-    size_t off_s0d = 0, off_p0d = 0;
-    size_t ws_bytes = 0;
-    char *ws = nullptr;
-
-    bool profile = false;
-    std::vector<hipEvent_t> events;   // begin/end pairs of recorded lag-sum launches
-    size_t n_recorded = 0;
-
-    bool green_ready = false;
-    int64_t next_step = 0;
-    bool pushed = false;
-    std::string err;
-    rp_stats stats{};
-
-    template <typename P = void>
-    P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
-    const PairP &pr(int s, int n) const { return pair[size_t(s) * n_dom + n]; }
-    PairP &pr(int s, int n) { return pair[size_t(s) * n_dom + n]; }
-};
-
-namespace {
 
 // ---------------------------------------------------------------------------
 // Planning
@@ -192,7 +76,8 @@ void pair_distance(const DomainP &s, const DomainP &n, double h, double &rmin, d
     rmax = std::sqrt(mx2);
 }
 
-void plan_build(rp_plan p, const int32_t *dims, const double *origins, const int32_t *system_id) {
+// Domains, systems, FFT pads, lag windows and shape classes.
+void plan_geometry(rp_plan p, const int32_t *dims, const double *origins, const int32_t *system_id) {
     const int nd = p->n_dom;
     p->dom.resize(nd);
     std::map<int32_t, int> sys_index;
@@ -255,121 +140,6 @@ void plan_build(rp_plan p, const int32_t *dims, const double *origins, const int
             }
         }
     }
-    for (int n = 0; n < nd; ++n) {
-        int mh = 0;
-        for (int s : p->sys[p->dom[n].sys].doms) mh = std::max(mh, p->pr(s, n).m_hi);
-        p->dom[n].depth = mh + 1;
-    }
-
-    // Green spectra: one set per unordered pair; the reversed pair uses the
-    // complex conjugate (its real-space kernel is the mirror image).
-    int64_t spec_base = 0;
-    for (SystemP &S : p->sys) {
-        S.spec_base = spec_base;
-        int64_t cnt = 0, nsp = 0;
-        for (size_t a = 0; a < S.doms.size(); ++a) {
-            for (size_t b = a; b < S.doms.size(); ++b) {
-                const int s = S.doms[a], n = S.doms[b];
-                PairP &q = p->pr(s, n);
-                q.spec0 = cnt;
-                q.conj = false;
-                cnt += int64_t(q.m_hi - q.m_lo + 1) * S.Cpad;
-                nsp += q.m_hi - q.m_lo + 1;
-                if (s != n) {
-                    PairP &r = p->pr(n, s);
-                    r.spec0 = q.spec0;
-                    r.conj = true;
-                }
-            }
-        }
-        S.n_spec = nsp;
-        S.spec_elems = cnt;
-        spec_base += cnt;
-        if (cnt / kTile > int64_t(INT32_MAX)) fail(RP_ERR_UNSUPPORTED, "Green spectra table too large");
-    }
-
-    // lag-sum schedule
-    int max_members = 1;
-    for (size_t si = 0; si < p->sys.size(); ++si) {
-        const SystemP &S = p->sys[si];
-        for (size_t g0 = 0; g0 < S.doms.size(); g0 += kGroupMax) {
-            K2Group G{};
-            G.C = S.C;
-            G.spec_base = S.spec_base;
-            G.n_members = int(std::min<size_t>(kGroupMax, S.doms.size() - g0));
-            for (int t = 0; t < G.n_members; ++t) G.member[t] = S.doms[g0 + t];
-            max_members = std::max(max_members, G.n_members);
-            G.entry_begin = int(p->entries.size());
-            G.src_begin = int(p->srcs.size());
-            for (int n : S.doms) {
-                K2Src R{};
-                R.n = n;
-                R.m_min = INT32_MAX;
-                R.m_max = -1;
-                for (int t = 0; t < kGroupMax; ++t) {
-                    K2Pair Q{};
-                    if (t < G.n_members) {
-                        const PairP &q = p->pr(G.member[t], n);
-                        Q.row0 = int32_t(q.spec0 / kTile) - q.m_lo;
-                        Q.w = q.m_hi - q.m_lo + 1;
-                        if (q.conj) R.conj |= 1u << t;
-                        R.m_min = std::min(R.m_min, q.m_lo);
-                        R.m_max = std::max(R.m_max, q.m_hi);
-                    }
-                    p->pairs.push_back(Q);
-                }
-                R.mask_off = int32_t(p->masks.size());
-                for (int m = R.m_min; m <= R.m_max; ++m) {
-                    uint32_t mk = 0;
-                    for (int t = 0; t < G.n_members; ++t) {
-                        const PairP &q = p->pr(G.member[t], n);
-                        if (m >= q.m_lo && m <= q.m_hi) mk |= 1u << t;
-                    }
-                    p->masks.push_back(mk);
-                }
-                p->srcs.push_back(R);
-                std::vector<int> ms;
-                for (int t = 0; t < G.n_members; ++t) {
-                    const PairP &q = p->pr(G.member[t], n);
-                    for (int m = q.m_lo; m <= q.m_hi; ++m) ms.push_back(m);
-                }
-                std::sort(ms.begin(), ms.end());
-                ms.erase(std::unique(ms.begin(), ms.end()), ms.end());
-                for (int m : ms) {
-                    K2Entry E{};
-                    E.src = n;
-                    E.m = m;
-                    for (int t = 0; t < G.n_members; ++t) {
-                        const PairP &q = p->pr(G.member[t], n);
-                        if (m < q.m_lo || m > q.m_hi) continue;
-                        E.mask |= 1u << t;
-                        if (q.conj) E.conj |= 1u << t;
-                        E.spec_tile[t] = int32_t(q.spec0 / kTile + (m - q.m_lo));
-                        E.spec_w[t] = q.m_hi - q.m_lo + 1;
-                    }
-                    p->entries.push_back(E);
-                }
-            }
-            G.entry_end = int(p->entries.size());
-            G.src_end = int(p->srcs.size());
-            const int gi = int(p->groups.size());
-            p->groups.push_back(G);
-            for (int64_t k0 = 0; k0 < S.C; k0 += kTile) p->items.push_back(K2Item{gi, int32_t(k0)});
-        }
-    }
-    p->tg = max_members <= 1 ? 1 : (max_members <= 2 ? 2 : (max_members <= 4 ? 4 : 8));
-    // longest work first (for the persistent launch): a group's tile costs its
-    // ring reads plus its spectrum reads
-    std::vector<double> gcost(p->groups.size(), 0.0);
-    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
-        const K2Group &G = p->groups[gi];
-        for (int e = G.entry_begin; e < G.entry_end; ++e)
-            gcost[gi] += 4.0 + double(__builtin_popcount(p->entries[e].mask));
-    }
-    std::stable_sort(p->items.begin(), p->items.end(),
-                     [&](const K2Item &x, const K2Item &y) { return gcost[x.group] > gcost[y.group]; });
-    if (p->entries.size() > size_t(INT32_MAX) || p->items.size() > size_t(INT32_MAX))
-        fail(RP_ERR_UNSUPPORTED, "schedule too large");
 
     // shape classes (same dims and pads) for batched FFT launches
     for (int i = 0; i < nd; ++i) {
@@ -390,8 +160,220 @@ void plan_build(rp_plan p, const int32_t *dims, const double *origins, const int
             found = int(p->cls.size()) - 1;
         }
         p->cls[found].doms.push_back(i);
+        p->dom[i].cls = found;
         const int lpb = zfwd_lines_per_block(S.P[2], p->p64);
         p->dom[i].zblocks = (4 * ((d.N[0] * d.N[1] + 1) / 2) + lpb - 1) / lpb;
+    }
+}
+
+// A pair whose plain lag sum may run: every near pair, and a far pair whose
+// source keeps its history (it can be judged and can fall back).
+bool keeps_history(rp_plan p, int s, int n) {
+    const SurrogateH &S = p->sur;
+    if (!S.on) return true;
+    const int f = S.far_index[size_t(s) * p->n_dom + n];
+    return f < 0 || S.pairs[f].audited;
+}
+
+// A pair summed by the plain lag sum at every step.
+bool plain_pair(rp_plan p, int s, int n) {
+    const SurrogateH &S = p->sur;
+    if (!S.on) return true;
+    const int f = S.far_index[size_t(s) * p->n_dom + n];
+    return f < 0 || S.pairs[f].plain;
+}
+
+// Lag-sum schedule of the members (accumulator slots of system si): groups of
+// up to 8 members, and per group the sources any member takes with the union
+// of their windows.
+void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables &T) {
+    const SystemP &S = p->sys[si];
+    for (size_t g0 = 0; g0 < members.size(); g0 += kGroupMax) {
+        K2Group G{};
+        G.C = S.C;
+        G.spec_base = S.spec_base;
+        G.n_members = int(std::min<size_t>(kGroupMax, members.size() - g0));
+        const K2Member *mb = members.data() + g0;
+        for (int t = 0; t < G.n_members; ++t) G.member[t] = mb[t].slot;
+        G.entry_begin = int(T.entries.size());
+        G.src_begin = int(T.srcs.size());
+        for (int n : S.doms) {
+            uint32_t takes = 0;
+            for (int t = 0; t < G.n_members; ++t)
+                if (std::find(mb[t].srcs.begin(), mb[t].srcs.end(), n) != mb[t].srcs.end()) takes |= 1u << t;
+            if (!takes) continue;
+            K2Src R{};
+            R.n = n;
+            R.m_min = INT32_MAX;
+            R.m_max = -1;
+            for (int t = 0; t < kGroupMax; ++t) {
+                K2Pair Q{};
+                if ((takes >> t) & 1u) {
+                    const PairP &q = p->pr(mb[t].s, n);
+                    if (q.spec0 < 0) fail(RP_ERR_STATE, "internal: lag sum over a pair without spectra");
+                    Q.row0 = int32_t(q.spec0 / kTile) - q.m_lo;
+                    Q.w = q.m_hi - q.m_lo + 1;
+                    if (q.conj) R.conj |= 1u << t;
+                    R.m_min = std::min(R.m_min, q.m_lo);
+                    R.m_max = std::max(R.m_max, q.m_hi);
+                }
+                T.pairs.push_back(Q);
+            }
+            R.mask_off = int32_t(T.masks.size());
+            for (int m = R.m_min; m <= R.m_max; ++m) {
+                uint32_t mk = 0;
+                for (int t = 0; t < G.n_members; ++t) {
+                    if (!((takes >> t) & 1u)) continue;
+                    const PairP &q = p->pr(mb[t].s, n);
+                    if (m >= q.m_lo && m <= q.m_hi) mk |= 1u << t;
+                }
+                T.masks.push_back(mk);
+            }
+            T.srcs.push_back(R);
+            for (int m = R.m_min; m <= R.m_max; ++m) {
+                K2Entry E{};
+                E.src = n;
+                E.m = m;
+                for (int t = 0; t < G.n_members; ++t) {
+                    if (!((takes >> t) & 1u)) continue;
+                    const PairP &q = p->pr(mb[t].s, n);
+                    if (m < q.m_lo || m > q.m_hi) continue;
+                    E.mask |= 1u << t;
+                    if (q.conj) E.conj |= 1u << t;
+                    E.spec_tile[t] = int32_t(q.spec0 / kTile + (m - q.m_lo));
+                    E.spec_w[t] = q.m_hi - q.m_lo + 1;
+                }
+                if (E.mask) T.entries.push_back(E);
+            }
+        }
+        G.entry_end = int(T.entries.size());
+        G.src_end = int(T.srcs.size());
+        const int gi = int(T.groups.size());
+        T.groups.push_back(G);
+        for (int64_t k0 = 0; k0 < S.C; k0 += kTile) T.items.push_back(K2Item{gi, int32_t(k0)});
+    }
+}
+
+// Template width of the schedule, work order and size checks.
+void finish_k2(rp_plan p, K2Tables &T) {
+    int max_members = 1;
+    for (const K2Group &G : T.groups) max_members = std::max(max_members, G.n_members);
+    T.tg = max_members <= 1 ? 1 : (max_members <= 2 ? 2 : (max_members <= 4 ? 4 : 8));
+    // longest work first (for the persistent launch): a group's tile costs its
+    // ring reads plus its spectrum reads
+    std::vector<double> gcost(T.groups.size(), 0.0);
+    for (size_t gi = 0; gi < T.groups.size(); ++gi) {
+        const K2Group &G = T.groups[gi];
+        for (int e = G.entry_begin; e < G.entry_end; ++e)
+            gcost[gi] += 4.0 + double(__builtin_popcount(T.entries[e].mask));
+    }
+    std::stable_sort(T.items.begin(), T.items.end(),
+                     [&](const K2Item &x, const K2Item &y) { return gcost[x.group] > gcost[y.group]; });
+    if (T.entries.size() > size_t(INT32_MAX) || T.items.size() > size_t(INT32_MAX) ||
+        T.masks.size() > size_t(INT32_MAX))
+        fail(RP_ERR_UNSUPPORTED, "schedule too large");
+    // ring offsets and depths (known once the layout exists)
+    if (!p->domdev.empty()) {
+        for (K2Entry &E : T.entries) {
+            E.ring_off = p->domdev[E.src].ring_off;
+            E.depth = p->domdev[E.src].depth;
+        }
+        for (K2Src &R : T.srcs) {
+            R.ring_off = p->domdev[R.n].ring_off;
+            R.depth = p->domdev[R.n].depth;
+        }
+    }
+}
+
+// The plain lag sum of every domain over its plain pairs.
+void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int)) {
+    T = K2Tables{};
+    for (size_t si = 0; si < p->sys.size(); ++si) {
+        std::vector<K2Member> members;
+        for (int s : p->sys[si].doms) {
+            K2Member M{s, s, {}};
+            for (int n : p->sys[si].doms)
+                if (pred(p, s, n)) M.srcs.push_back(n);
+            members.push_back(std::move(M));
+        }
+        build_k2(p, int(si), members, T);
+    }
+    finish_k2(p, T);
+}
+
+// Ring depths, stored Green spectra and the lag-sum schedules.
+void plan_tables(rp_plan p) {
+    const int nd = p->n_dom;
+    for (int n = 0; n < nd; ++n) {
+        int mh = 0;
+        for (int s : p->sys[p->dom[n].sys].doms)
+            if (keeps_history(p, s, n)) mh = std::max(mh, p->pr(s, n).m_hi);
+        p->dom[n].depth = mh + 1;
+    }
+
+    // Green spectra: one set per unordered pair; the reversed pair uses the
+    // complex conjugate (its real-space kernel is the mirror image).  Pairs
+    // that never run the plain lag sum in either direction store none.
+    int64_t spec_base = 0;
+    for (SystemP &S : p->sys) {
+        S.spec_base = spec_base;
+        int64_t cnt = 0, nsp = 0;
+        for (size_t a = 0; a < S.doms.size(); ++a) {
+            for (size_t b = a; b < S.doms.size(); ++b) {
+                const int s = S.doms[a], n = S.doms[b];
+                PairP &q = p->pr(s, n);
+                PairP &r = p->pr(n, s);
+                q.spec0 = r.spec0 = -1;
+                if (!keeps_history(p, s, n) && !keeps_history(p, n, s)) continue;
+                q.spec0 = cnt;
+                q.conj = false;
+                cnt += int64_t(q.m_hi - q.m_lo + 1) * S.Cpad;
+                nsp += q.m_hi - q.m_lo + 1;
+                if (s != n) {
+                    r.spec0 = q.spec0;
+                    r.conj = true;
+                }
+            }
+        }
+        S.n_spec = nsp;
+        S.spec_elems = cnt;
+        spec_base += cnt;
+        if (cnt / kTile > int64_t(INT32_MAX)) fail(RP_ERR_UNSUPPORTED, "Green spectra table too large");
+    }
+
+    main_k2(p, p->k2, plain_pair);
+    // room for the largest schedule a fallback can reach
+    K2Tables cap;
+    main_k2(p, cap, keeps_history);
+    K2Dev &D = p->k2_dev;
+    D.cap_items = std::max(cap.items.size(), p->k2.items.size());
+    D.cap_groups = std::max(cap.groups.size(), p->k2.groups.size());
+    D.cap_entries = std::max(cap.entries.size(), p->k2.entries.size());
+    D.cap_srcs = std::max(cap.srcs.size(), p->k2.srcs.size());
+    D.cap_pairs = std::max(cap.pairs.size(), p->k2.pairs.size());
+    D.cap_masks = std::max(cap.masks.size(), p->k2.masks.size());
+
+    // judge schedule of the surrogate: one slot per audited far pair
+    SurrogateH &U = p->sur;
+    U.judge = K2Tables{};
+    if (U.on && !U.aud.empty()) {
+        for (size_t si = 0; si < p->sys.size(); ++si) {
+            std::vector<K2Member> members;
+            for (size_t v = 0; v < U.aud.size(); ++v) {
+                const FarPairH &F = U.pairs[U.aud[v]];
+                if (p->dom[F.s].sys != int(si)) continue;
+                members.push_back(K2Member{nd + int(v), F.s, {F.n}});
+            }
+            build_k2(p, int(si), members, U.judge);
+        }
+        finish_k2(p, U.judge);
+        K2Dev &J = U.judge_dev;
+        J.cap_items = U.judge.items.size();
+        J.cap_groups = U.judge.groups.size();
+        J.cap_entries = U.judge.entries.size();
+        J.cap_srcs = U.judge.srcs.size();
+        J.cap_pairs = U.judge.pairs.size();
+        J.cap_masks = U.judge.masks.size();
     }
 }
 
@@ -402,16 +384,24 @@ void plan_layout(rp_plan p) {
         off += (bytes + kAlign - 1) / kAlign * kAlign;
         return o;
     };
+    auto alloc_k2 = [&](K2Dev &D) {
+        D.items = alloc(std::max<size_t>(1, D.cap_items) * sizeof(K2Item));
+        D.groups = alloc(std::max<size_t>(1, D.cap_groups) * sizeof(K2Group));
+        D.entries = alloc(std::max<size_t>(1, D.cap_entries) * sizeof(K2Entry));
+        D.srcs = alloc(std::max<size_t>(1, D.cap_srcs) * sizeof(K2Src));
+        D.pairs = alloc(std::max<size_t>(1, D.cap_pairs) * sizeof(K2Pair));
+        D.masks = alloc(std::max<size_t>(1, D.cap_masks) * sizeof(uint32_t));
+    };
+    const size_t n_slots = p->dom.size() + (p->sur.on ? p->sur.aud.size() : 0);
+    p->tw64.clear();
+    p->tw32.clear();
     p->off_state = alloc(64);
     p->off_head = alloc(p->dom.size() * sizeof(int32_t));
+    p->off_prev_head = alloc(p->dom.size() * sizeof(int32_t));
     p->off_counter = alloc(16);
-    p->off_items = alloc(p->items.size() * sizeof(K2Item));
-    p->off_groups = alloc(p->groups.size() * sizeof(K2Group));
-    p->off_entries = alloc(std::max<size_t>(1, p->entries.size()) * sizeof(K2Entry));
-    p->off_domdev = alloc(p->dom.size() * sizeof(DomDev));
-    p->off_srcs = alloc(p->srcs.size() * sizeof(K2Src));
-    p->off_pairs = alloc(p->pairs.size() * sizeof(K2Pair));
-    p->off_masks = alloc(std::max<size_t>(1, p->masks.size()) * sizeof(uint32_t));
+    alloc_k2(p->k2_dev);
+    if (p->sur.on) alloc_k2(p->sur.judge_dev);
+    p->off_domdev = alloc(n_slots * sizeof(DomDev));
     for (const SystemP &S : p->sys) {
         for (int a = 0; a < 3; ++a) {
             if (!p->tw64.count(S.P[a])) {
@@ -452,10 +442,11 @@ void plan_layout(rp_plan p) {
     p->off_t2d = alloc(max_t2 * 16);
     p->off_s0d = alloc(4 * max_pts * 8);
     p->off_p0d = alloc(4 * max_pts * 8);
+    if (p->sur.on) sur_layout(p, off);
     p->ws_bytes = off;
 
     // device-side tables
-    p->domdev.resize(p->dom.size());
+    p->domdev.assign(n_slots, DomDev{});
     for (size_t i = 0; i < p->dom.size(); ++i) {
         const DomainP &d = p->dom[i];
         DomDev &D = p->domdev[i];
@@ -466,14 +457,30 @@ void plan_layout(rp_plan p) {
         D.depth = d.depth;
         D.pad = 0;
     }
-    for (K2Entry &E : p->entries) {
-        E.ring_off = p->domdev[E.src].ring_off;
-        E.depth = p->domdev[E.src].depth;
+    if (p->sur.on) {
+        // judge slots: accumulators of the audited far pairs, [slot][C][4]
+        for (size_t v = 0; v < p->sur.aud.size(); ++v) {
+            DomDev &D = p->domdev[p->dom.size() + v];
+            D.acc_off = int64_t((p->sur.jacc_off[v] - p->dom[0].off_acc) / p->csz);
+            D.depth = 1;
+        }
     }
-    for (K2Src &R : p->srcs) {
-        R.ring_off = p->domdev[R.n].ring_off;
-        R.depth = p->domdev[R.n].depth;
+    finish_k2(p, p->k2);
+    if (p->sur.on) finish_k2(p, p->sur.judge);
+}
+
+double k2_bytes(rp_plan p, const K2Tables &T) {
+    double bytes = 0;
+    for (const K2Group &G : T.groups) {
+        double per_k = 0;
+        for (int e = G.entry_begin; e < G.entry_end; ++e) {
+            const K2Entry &E = T.entries[e];
+            per_k += 4.0 * p->ring_esz + double(__builtin_popcount(E.mask)) * p->spec_csz;
+        }
+        per_k += double(G.n_members) * 4 * p->csz;   // accumulator write
+        bytes += per_k * double(G.C);
     }
+    return bytes;
 }
 
 void plan_stats(rp_plan p) {
@@ -481,21 +488,12 @@ void plan_stats(rp_plan p) {
     st = rp_stats{};
     for (const SystemP &S : p->sys)
         for (int s : S.doms)
-            for (int n : S.doms) st.n_triples += p->pr(s, n).m_hi - p->pr(s, n).m_lo + 1;
+            for (int n : S.doms)
+                if (plain_pair(p, s, n)) st.n_triples += p->pr(s, n).m_hi - p->pr(s, n).m_lo + 1;
     for (const SystemP &S : p->sys) st.n_spectra += S.n_spec;
-    st.n_entries = int64_t(p->entries.size());
+    st.n_entries = int64_t(p->k2.entries.size());
     for (const DomainP &d : p->dom) st.points += d.npts;
-    double bytes = 0;
-    for (const K2Group &G : p->groups) {
-        double per_k = 0;
-        for (int e = G.entry_begin; e < G.entry_end; ++e) {
-            const K2Entry &E = p->entries[e];
-            per_k += 4.0 * p->ring_esz + double(__builtin_popcount(E.mask)) * p->spec_csz;
-        }
-        per_k += double(G.n_members) * 4 * p->csz;   // accumulator write
-        bytes += per_k * double(G.C);
-    }
-    st.lagsum_bytes = bytes;
+    st.lagsum_bytes = k2_bytes(p, p->k2);
     for (const DomainP &d : p->dom) st.ring_bytes += double(d.depth) * p->sys[d.sys].Cpad * 4 * p->ring_esz;
     for (const SystemP &S : p->sys) st.spectra_bytes += double(S.spec_elems) * p->spec_csz;
     for (const DomainP &d : p->dom) {
@@ -663,6 +661,23 @@ void green_spectra(rp_plan p, int s, int n, int mode, int m0, int count, void *c
     check_launch();
 }
 
+// Copy a lag-sum schedule into its device tables (asynchronous on st; the
+// host vectors must stay unchanged until the copy has completed).
+void upload_k2(rp_plan p, const K2Tables &T, const K2Dev &D, hipStream_t st) {
+    if (T.items.size() > D.cap_items || T.groups.size() > D.cap_groups || T.entries.size() > D.cap_entries ||
+        T.srcs.size() > D.cap_srcs || T.pairs.size() > D.cap_pairs || T.masks.size() > D.cap_masks)
+        fail(RP_ERR_STATE, "internal: lag-sum schedule exceeds its device tables");
+    auto up = [&](size_t off, const void *src, size_t bytes) {
+        if (bytes) HIP_OK(hipMemcpyAsync(p->ws + off, src, bytes, hipMemcpyHostToDevice, st));
+    };
+    up(D.items, T.items.data(), T.items.size() * sizeof(K2Item));
+    up(D.groups, T.groups.data(), T.groups.size() * sizeof(K2Group));
+    up(D.entries, T.entries.data(), T.entries.size() * sizeof(K2Entry));
+    up(D.srcs, T.srcs.data(), T.srcs.size() * sizeof(K2Src));
+    up(D.pairs, T.pairs.data(), T.pairs.size() * sizeof(K2Pair));
+    up(D.masks, T.masks.data(), T.masks.size() * sizeof(uint32_t));
+}
+
 void release_graph(rp_plan p) {
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -676,22 +691,10 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
     if (bytes < p->ws_bytes) fail(RP_ERR_NOMEM, "workspace smaller than rp_workspace_bytes");
     p->ws = static_cast<char *>(dev);
     hipStream_t st = p->stream;
-    HIP_OK(hipMemcpyAsync(p->ws + p->off_items, p->items.data(), p->items.size() * sizeof(K2Item),
-                          hipMemcpyHostToDevice, st));
-    HIP_OK(hipMemcpyAsync(p->ws + p->off_groups, p->groups.data(), p->groups.size() * sizeof(K2Group),
-                          hipMemcpyHostToDevice, st));
-    if (!p->entries.empty())
-        HIP_OK(hipMemcpyAsync(p->ws + p->off_entries, p->entries.data(), p->entries.size() * sizeof(K2Entry),
-                              hipMemcpyHostToDevice, st));
+    upload_k2(p, p->k2, p->k2_dev, st);
+    if (p->sur.on) upload_k2(p, p->sur.judge, p->sur.judge_dev, st);
     HIP_OK(hipMemcpyAsync(p->ws + p->off_domdev, p->domdev.data(), p->domdev.size() * sizeof(DomDev),
                           hipMemcpyHostToDevice, st));
-    HIP_OK(hipMemcpyAsync(p->ws + p->off_srcs, p->srcs.data(), p->srcs.size() * sizeof(K2Src),
-                          hipMemcpyHostToDevice, st));
-    HIP_OK(hipMemcpyAsync(p->ws + p->off_pairs, p->pairs.data(), p->pairs.size() * sizeof(K2Pair),
-                          hipMemcpyHostToDevice, st));
-    if (!p->masks.empty())
-        HIP_OK(hipMemcpyAsync(p->ws + p->off_masks, p->masks.data(), p->masks.size() * sizeof(uint32_t),
-                              hipMemcpyHostToDevice, st));
     // twiddles exp(-2 pi i j / P), evaluated in FP64 on the host
     std::vector<Cx<double>> t64;
     std::vector<Cx<float>> t32;
@@ -710,6 +713,7 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
     }
     launch_fill_zero(p->ws + p->off_state, 64, st);
     launch_fill_zero(p->ws + p->off_head, (p->dom.size() * sizeof(int32_t) + 15) / 16 * 16, st);
+    launch_fill_zero(p->ws + p->off_prev_head, (p->dom.size() * sizeof(int32_t) + 15) / 16 * 16, st);
     launch_fill_zero(p->ws + p->off_counter, 16, st);
     {
         int dev = 0;
@@ -720,6 +724,7 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
         launch_fill_zero(p->ws + d.off_ring, size_t(d.depth) * p->sys[d.sys].Cpad * 4 * p->ring_esz, st);
         if (d.off_scales) launch_fill_zero(p->ws + d.off_scales, (size_t(d.depth) * 16 + 15) / 16 * 16, st);
     }
+    if (p->sur.on) sur_bind(p);
     check_launch();
     HIP_OK(hipStreamSynchronize(st));
     p->green_ready = false;
@@ -736,6 +741,7 @@ void do_green(rp_plan p) {
             for (size_t b = a; b < S.doms.size(); ++b) {
                 const int s = S.doms[a], n = S.doms[b];
                 const PairP &q = p->pr(s, n);
+                if (q.spec0 < 0) continue;   // far pair without plain history
                 for (int m0 = q.m_lo; m0 <= q.m_hi; m0 += kGreenChunk) {
                     const int cnt = std::min(kGreenChunk, q.m_hi - m0 + 1);
                     void *outs[kGreenChunk];
@@ -868,30 +874,35 @@ void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
     }
 }
 
-K2Args lagsum_args(rp_plan p) {
+K2Args k2_args(rp_plan p, const K2Tables &T, const K2Dev &D, const int32_t *head) {
     K2Args k{};
-    k.items = p->at<K2Item>(p->off_items);
-    k.groups = p->at<K2Group>(p->off_groups);
-    k.entries = p->at<K2Entry>(p->off_entries);
-    k.srcs = p->at<K2Src>(p->off_srcs);
-    k.pairs = p->at<K2Pair>(p->off_pairs);
-    k.masks = p->at<uint32_t>(p->off_masks);
+    k.items = p->at<K2Item>(D.items);
+    k.groups = p->at<K2Group>(D.groups);
+    k.entries = p->at<K2Entry>(D.entries);
+    k.srcs = p->at<K2Src>(D.srcs);
+    k.pairs = p->at<K2Pair>(D.pairs);
+    k.masks = p->at<uint32_t>(D.masks);
     k.doms = p->at<DomDev>(p->off_domdev);
     k.spectra = p->ws + p->off_spec;
     k.ring = p->ws + p->dom[0].off_ring;
     k.scales = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16) ? p->at<float>(p->dom[0].off_scales) : nullptr;
     k.acc = p->ws + p->dom[0].off_acc;
-    k.head = p->at<int32_t>(p->off_head);
+    k.head = head;
     k.counter = p->at<int>(p->off_counter);
-    k.n_items = int(p->items.size());
+    k.n_items = int(T.items.size());
     k.n_dom = p->n_dom;
     return k;
 }
 
-void enqueue_lagsum(rp_plan p, hipStream_t st, int unroll, int persist) {
-    const int grid = persist ? p->n_cu * lagsum_blocks_per_cu(p->p64, p->ring_fmt, p->tg, unroll) : 0;
-    launch_lagsum(lagsum_args(p), p->p64, p->ring_fmt, p->tg, unroll, grid, st);
+void enqueue_k2(rp_plan p, const K2Args &a, int tg, hipStream_t st, int unroll, int persist) {
+    if (a.n_items == 0) return;
+    const int grid = persist ? p->n_cu * lagsum_blocks_per_cu(p->p64, p->ring_fmt, tg, unroll) : 0;
+    launch_lagsum(a, p->p64, p->ring_fmt, tg, unroll, grid, st);
     check_launch();
+}
+
+void enqueue_lagsum(rp_plan p, hipStream_t st, int unroll, int persist) {
+    enqueue_k2(p, k2_args(p, p->k2, p->k2_dev, p->at<int32_t>(p->off_head)), p->k2.tg, st, unroll, persist);
 }
 
 // Inverse transform of every target's accumulated spectrum, crop to the
@@ -928,8 +939,14 @@ void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st) {
             check_launch();
         }
     }
-    launch_advance_step(p->at<int64_t>(p->off_state), p->at<int32_t>(p->off_head), p->at<DomDev>(p->off_domdev),
-                        p->n_dom, st);
+}
+
+// Surrogate far-pair terms (when a network is attached), then step += 1 and
+// every ring head moves on (the previous heads are kept for the judge).
+void enqueue_finish(rp_plan p, void *const *out, hipStream_t st) {
+    if (p->sur.on) sur_enqueue_infer(p, out, st);
+    launch_advance_step(p->at<int64_t>(p->off_state), p->at<int32_t>(p->off_head), p->at<int32_t>(p->off_prev_head),
+                        p->at<DomDev>(p->off_domdev), p->n_dom, st);
     check_launch();
 }
 
@@ -956,6 +973,7 @@ void do_push(rp_plan p, int64_t step, const void *const *src) {
         do_static(p, src);
     } else {
         enqueue_ingest(p, src, st);
+        if (p->sur.on) sur_enqueue_moments(p, src, st);
     }
     check_launch();
     p->pushed = true;
@@ -987,6 +1005,7 @@ void do_step(rp_plan p, int64_t step, void *const *out) {
         p->n_recorded += 1;
     }
     enqueue_inverse(p, out, st);
+    enqueue_finish(p, out, st);
     p->next_step += 1;
     p->pushed = false;
 }
@@ -1004,8 +1023,10 @@ void do_capture(rp_plan p, const void *const *src, void *const *out) {
     HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     try {
         enqueue_ingest(p, src, cs);
+        if (p->sur.on) sur_enqueue_moments(p, src, cs);
         enqueue_lagsum(p, cs, p->k2_unroll, p->k2_persist);
         enqueue_inverse(p, out, cs);
+        enqueue_finish(p, out, cs);
     } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(cs, &g);
@@ -1093,7 +1114,9 @@ rp_status guarded(rp_plan p, F &&f) {
     }
 }
 
-}  // namespace
+}  // namespace rpot_host
+
+using namespace rpot_host;
 
 extern "C" {
 
@@ -1143,7 +1166,8 @@ rp_status rp_plan_domains(rp_plan *out, int32_t n_dom, const int32_t *dims, cons
             p->w_self0 = h * h * C1;
             p->w_self1 = 0.0;
         }
-        plan_build(p, dims, origins, system_id);
+        plan_geometry(p, dims, origins, system_id);
+        plan_tables(p);
         plan_layout(p);
         plan_stats(p);
         *out = p;
@@ -1269,6 +1293,52 @@ rp_status rp_capture_step(rp_plan plan, const void *const *src, void *const *out
 
 rp_status rp_launch_step(rp_plan plan, int64_t step) {
     return guarded(plan, [&] { do_launch_graph(plan, step); });
+}
+
+rp_status rp_surrogate_configure(rp_plan plan, double far_factor, int32_t n_lags, const int32_t *audit,
+                                 int32_t n_audit) {
+    return guarded(plan, [&] { sur_configure(plan, far_factor, n_lags, audit, n_audit); });
+}
+
+rp_status rp_surrogate_info(rp_plan plan, int32_t *n_far, int32_t *n_audited, int32_t *n_in, int32_t *n_out) {
+    return guarded(plan, [&] {
+        const SurrogateH &U = plan->sur;
+        if (n_far) *n_far = int32_t(U.pairs.size());
+        if (n_audited) *n_audited = int32_t(U.aud.size());
+        if (n_in) *n_in = U.on ? U.n_in : 0;
+        if (n_out) *n_out = U.on ? kNOut : 0;
+    });
+}
+
+rp_status rp_surrogate_pairs(rp_plan plan, int32_t *target, int32_t *source, double *dist, int32_t *audited,
+                             int32_t *fallen_back) {
+    return guarded(plan, [&] {
+        const SurrogateH &U = plan->sur;
+        for (size_t f = 0; f < U.pairs.size(); ++f) {
+            const FarPairH &F = U.pairs[f];
+            if (target) target[f] = F.s;
+            if (source) source[f] = F.n;
+            if (dist) dist[f] = F.dist;
+            if (audited) audited[f] = F.audited ? 1 : 0;
+            if (fallen_back) fallen_back[f] = F.plain ? 1 : 0;
+        }
+    });
+}
+
+rp_status rp_surrogate_attach(rp_plan plan, rp_mlp mlp, const float *in_scale, const float *out_scale) {
+    return guarded(plan, [&] { sur_attach(plan, mlp, in_scale, out_scale); });
+}
+
+rp_status rp_surrogate_features(rp_plan plan, float *x) {
+    return guarded(plan, [&] { sur_features(plan, x); });
+}
+
+rp_status rp_surrogate_pair_response(rp_plan plan, float *coef, float *resid) {
+    return guarded(plan, [&] { sur_pair_response(plan, coef, resid); });
+}
+
+rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t *n_fallback, double *worst) {
+    return guarded(plan, [&] { sur_judge(plan, out, tol, n_fallback, worst); });
 }
 
 rp_status rp_plan_destroy(rp_plan plan) {

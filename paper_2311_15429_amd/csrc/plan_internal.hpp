@@ -1,0 +1,228 @@
+// Host-side plan state shared by the runtime (plan.cpp) and the far-pair
+// surrogate (surrogate.cpp).  Not part of the C ABI.
+#pragma once
+
+#include "rpot.h"
+#include "rpot_internal.hpp"
+
+#include <map>
+#include <string>
+#include <vector>
+
+namespace rpot_host {
+
+using namespace rpot;
+
+struct Error {
+    rp_status code;
+    std::string msg;
+};
+
+[[noreturn]] inline void fail(rp_status c, const std::string &m) { throw Error{c, m}; }
+
+#define HIP_OK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) fail(RP_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kGroupMax = 8;      // targets per lag-sum thread
+constexpr int kGreenChunk = kMaxJobs;
+constexpr int kMaxPad = 512;      // z passes stage >= 4 lines of the pad in 32 KiB of LDS
+constexpr size_t kAlign = 256;
+
+struct DomainP {
+    int N[3];
+    double o[3];
+    int sys;
+    int64_t npts;
+    int depth = 1;
+    int zblocks = 0;
+    int cls = 0;
+    size_t off_ring = 0, off_scales = 0, off_zmax = 0, off_s0 = 0, off_p0 = 0, off_acc = 0;
+    size_t off_t1 = 0, off_t2 = 0, off_s0hat = 0;
+};
+
+struct SystemP {
+    std::vector<int> doms;
+    int P[3];
+    int Hz;
+    int64_t C;
+    int64_t Cpad;            // C rounded up to whole frequency tiles
+    int64_t spec_base = 0;   // complex elements
+    int64_t n_spec = 0;      // stored spectra (one per lag of every unordered pair)
+    int64_t spec_elems = 0;  // their storage, tile-major per pair
+};
+
+struct PairP {
+    int m_lo = -1, m_hi = -1;
+    double rmin = 0, rmax = 0;
+    int64_t spec0 = -1;      // element offset (within the system) of the pair's spectra,
+                             // stored [tile][lag][kTile]; -1 when not stored
+    bool conj = false;
+};
+
+struct ClassP {
+    int N[3];
+    int P[3];
+    int Hz;
+    int64_t C;
+    std::vector<int> doms;
+};
+
+// One lag-sum schedule: groups of up to 8 accumulator slots of one system,
+// their (source, lag) walk, and the work items (group x frequency tile).
+struct K2Tables {
+    std::vector<K2Group> groups;
+    std::vector<K2Entry> entries;
+    std::vector<K2Src> srcs;
+    std::vector<K2Pair> pairs;
+    std::vector<uint32_t> masks;
+    std::vector<K2Item> items;
+    int tg = 1;
+};
+
+// Device copy of a schedule, with room for the largest schedule the plan can
+// switch to (the surrogate's fallback adds pairs to the plain lag sum).
+struct K2Dev {
+    size_t items = 0, groups = 0, entries = 0, srcs = 0, pairs = 0, masks = 0;
+    size_t cap_items = 0, cap_groups = 0, cap_entries = 0, cap_srcs = 0, cap_pairs = 0, cap_masks = 0;
+};
+
+// A lag-sum accumulator slot: slot index into the DomDev table (a domain, or
+// a judge slot past the domains), the target domain whose pairs it sums, and
+// the sources it takes.
+struct K2Member {
+    int slot;
+    int s;
+    std::vector<int> srcs;
+};
+
+// Far-pair surrogate state (host).
+struct FarPairH {
+    int s = 0, n = 0;        // target, source
+    double dist = 0;         // |c_s - c_n|
+    int m_c = 0;             // round(dist / (c dt))
+    double frac = 0;         // dist / (c dt) - m_c
+    bool audited = false;    // the source keeps the plain history of this pair
+    bool plain = false;      // fallen back: summed by the plain lag sum
+    double rot[9] = {};      // frame axes (rows)
+};
+
+struct SurrogateH {
+    bool on = false;
+    double far_factor = 0;
+    int n_lags = 0;
+    int n_in = 0;
+    std::vector<char> audit;       // per domain
+    std::vector<int> far_index;    // [s * n_dom + n] -> far pair index, or -1
+    std::vector<FarPairH> pairs;
+    std::vector<int> src_slot;     // per domain: moment ring index, or -1
+    std::vector<int> src_doms;     // moment ring index -> domain
+    int mom_depth = 1;
+    std::vector<int> aud;          // far pair indices with an audited source (judge order)
+    std::vector<int> aud_row;      // judge slot -> row among audited pairs in far-pair order
+    std::vector<float> mats;       // [n_far][2][kNBasis^2]: frame -> box, box -> frame
+    std::vector<int> far_cls;      // target shape classes of far pairs
+    std::map<int, size_t> off_Q;   // class -> LS dual basis [kNBasis][npts]
+    K2Tables judge;
+    K2Dev judge_dev;
+    int n_chunks = 1;              // moment partial sums per source
+    size_t off_mom = 0, off_mpart = 0, off_fpairs = 0, off_x = 0, off_y = 0, off_pc = 0, off_coef = 0;
+    size_t off_order = 0, off_tbeg = 0, off_mats = 0, off_inscale = 0, off_outscale = 0;
+    size_t off_jacc = 0, off_jt1 = 0, off_jt2 = 0, off_jF = 0, off_jcoef = 0, off_jres = 0;
+    size_t off_budget = 0, off_fail = 0, off_aud = 0, off_jcb = 0;
+    size_t jt1_elems = 0, jt2_elems = 0, jF_elems = 0;
+    std::vector<size_t> jacc_off;  // judge slot -> byte offset of its accumulator
+    std::vector<int> synth_targets;  // domains that are the target of a far pair
+    std::vector<int32_t> h_order, h_tbeg;   // active far pairs by target (CSR)
+    rp_mlp mlp = nullptr;
+    bool attached = false;
+};
+
+}  // namespace rpot_host
+
+struct rp_plan_s {
+    int n_dom = 0;
+    double h = 0, dt = 0, c = 0;
+    rp_precision prec = RP_FP64;
+    hipStream_t stream = nullptr;
+    bool p64 = true;
+    int ring_fmt = rpot::RING_F64;
+    size_t tsz = 8, csz = 16, ring_esz = 16, spec_csz = 16;
+    double w_self0 = 0, w_self1 = 0, w_static = 0;
+
+    std::vector<rpot_host::DomainP> dom;
+    std::vector<rpot_host::SystemP> sys;
+    std::vector<rpot_host::PairP> pair;   // [s * n_dom + n]
+    std::vector<rpot_host::ClassP> cls;
+
+    rpot_host::K2Tables k2;               // the plain lag sum of every step
+    rpot_host::K2Dev k2_dev;
+    std::vector<rpot::DomDev> domdev;     // domains, then judge slots
+    int k2_unroll = 1;   // lags whose loads a lag-sum thread issues together
+    int k2_persist = 0;  // persistent lag-sum launch (work counter) instead of one block per item
+    int n_cu = 0;        // compute units of the bound device
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+
+    std::map<int, size_t> tw64, tw32;   // FFT length -> byte offset of its twiddles
+    size_t off_state = 0, off_head = 0, off_prev_head = 0, off_domdev = 0, off_counter = 0;
+    size_t off_spec = 0, off_gtmp = 0, off_accd = 0, off_gstat = 0, off_t1d = 0, off_t2d = 0;
+    size_t off_s0d = 0, off_p0d = 0;
+    size_t ws_bytes = 0;
+    char *ws = nullptr;
+
+    bool profile = false;
+    std::vector<hipEvent_t> events;   // begin/end pairs of recorded lag-sum launches
+    size_t n_recorded = 0;
+
+    bool green_ready = false;
+    int64_t next_step = 0;
+    bool pushed = false;
+    std::string err;
+    rp_stats stats{};
+
+    rpot_host::SurrogateH sur;
+
+    template <typename P = void>
+    P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
+    const rpot_host::PairP &pr(int s, int n) const { return pair[size_t(s) * n_dom + n]; }
+    rpot_host::PairP &pr(int s, int n) { return pair[size_t(s) * n_dom + n]; }
+};
+
+namespace rpot_host {
+
+// plan.cpp
+void check_launch();
+RadixPlan make_radix(int P);
+const void *tw_ptr(rp_plan p, int P, bool dbl);
+LinePass inv_x(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl);
+LinePass inv_y(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl);
+void build_k2(rp_plan p, int sys, const std::vector<K2Member> &members, K2Tables &T);
+void finish_k2(rp_plan p, K2Tables &T);
+void plan_tables(rp_plan p);
+void plan_layout(rp_plan p);
+void plan_stats(rp_plan p);
+void release_graph(rp_plan p);
+void upload_k2(rp_plan p, const K2Tables &T, const K2Dev &D, hipStream_t st);
+K2Args k2_args(rp_plan p, const K2Tables &T, const K2Dev &D, const int32_t *head);
+void enqueue_k2(rp_plan p, const K2Args &a, int tg, hipStream_t st, int unroll, int persist);
+bool keeps_history(rp_plan p, int s, int n);
+bool plain_pair(rp_plan p, int s, int n);
+
+// surrogate.cpp
+void sur_classify(rp_plan p);                 // after the windows, before plan_tables
+void sur_layout(rp_plan p, size_t &off);      // workspace for the surrogate
+void sur_bind(rp_plan p);                     // uploads after bind
+void sur_enqueue_moments(rp_plan p, const void *const *src, hipStream_t st);
+void sur_enqueue_infer(rp_plan p, void *const *out, hipStream_t st);
+void sur_configure(rp_plan p, double far_factor, int n_lags, const int32_t *audit, int n_audit);
+void sur_attach(rp_plan p, rp_mlp mlp, const float *in_scale, const float *out_scale);
+void sur_features(rp_plan p, float *x);
+void sur_pair_response(rp_plan p, float *coef, float *resid);
+void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, double *worst);
+void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int));
+
+}  // namespace rpot_host

@@ -5,6 +5,8 @@
 #include <cstddef>
 #include <cstdint>
 
+typedef struct rp_mlp_s *rp_mlp;
+
 namespace rpot {
 
 template <typename T>
@@ -206,7 +208,151 @@ void launch_ring_scale(const ScaleArgs &a, hipStream_t st);
 void launch_static_mac(void *acc, const void *g, const void *s, int64_t C, hipStream_t st);
 void launch_convert(void *dst, int dst64, const void *src, int src64, int64_t n, hipStream_t st);
 void launch_fill_zero(void *dst, size_t bytes, hipStream_t st);
-// step += 1 and every domain's ring head moves one slot (mod its depth).
-void launch_advance_step(int64_t *step, int32_t *head, const DomDev *doms, int n_dom, hipStream_t st);
+// step += 1 and every domain's ring head moves one slot (mod its depth); the
+// heads before the move are kept in prev.
+void launch_advance_step(int64_t *step, int32_t *head, int32_t *prev, const DomDev *doms, int n_dom, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Far-pair surrogate.
+//
+// Moments of dS = S(l) - S(0) of a source about its centre (weight h^3), in
+// ring order:
+//   0 q = sum dS_0;  1..3 p_i = sum dS_0 x_i;  4..9 Q = sum dS_0 x_i x_j for
+//   (xx, yy, zz, xy, xz, yz);  10..12 J_i = sum dS_{1+i};
+//   13..21 K_ij = sum dS_{1+i} x_j (row-major i, j).
+constexpr int kNFeat = 22;
+constexpr int kFeatStride = 24;   // floats per moment-ring slot
+constexpr int kNBasis = 20;       // tensor-Legendre functions of total degree <= 3
+constexpr int kNOut = 4 * kNBasis;
+constexpr int kNGeo = 2;          // geometry features of a pair
+constexpr int kMomChunks = 64;    // partial sums per source
+
+struct MomentJob {
+    const float *src;      // S(l) [4][Nx][Ny][Nz]
+    const float *s0;       // S(0)
+    float *ring;           // the source's moment ring [depth][kFeatStride]
+    float *partial;        // the source's partial sums [kMomChunks][kNFeat]
+    int N[3];
+    float o[3];            // position of point (0,0,0) relative to the domain centre
+};
+struct MomentArgs {
+    float h;
+    double h3;
+    int depth;
+    const int64_t *step;
+    int n_jobs;
+    MomentJob jobs[kMaxJobs];
+};
+
+// A far pair (target s <- source n) on the device.  rot holds the frame axes
+// as rows: e1 along c_s - c_n, e2 and e3 completing a right-handed frame.
+struct FarPair {
+    int32_t s, n;
+    int32_t m_c;           // centre lag round(|c_s - c_n| / (c dt))
+    int32_t src_slot;      // moment ring of the source
+    float rot[9];
+    float inv_d;           // 1 / |c_s - c_n|
+    float geo[kNGeo];      // (r_ref / |c_s - c_n|, |c_s - c_n| / (c dt) - m_c)
+};
+struct FeatArgs {
+    const FarPair *pairs;
+    const float *moments;  // [n_src][depth][kFeatStride]
+    const float *in_scale; // [kNFeat]
+    float *x;              // [n_pairs][n_in]
+    const int64_t *step;
+    int64_t step_adj;      // the features are those of step *step + step_adj
+    int depth;
+    int n_lags;
+    int n_in;
+    int n_pairs;
+};
+// Coefficient maps between the network's frame basis and the target box basis:
+//  dir 0: out = M (R^T-mixed (in * scale * inv_d))   (frame -> box)
+//  dir 1: out = R-mixed (Minv in)                    (box -> frame)
+// mats = [n_far][2][kNBasis * kNBasis] (M, Minv), row r uses pair index[r]
+// (or r when index is null).
+struct XformArgs {
+    const FarPair *pairs;
+    const float *mats;
+    const float *in;
+    float *out;
+    const float *scale;    // [kNOut], dir 0 only
+    const int32_t *index;
+    int dir;
+    int n;
+};
+// coef[s] = sum of pc[order[i]] over i in [tgt_begin[s], tgt_begin[s + 1])
+struct CoefArgs {
+    const float *pc;
+    const int32_t *order;
+    const int32_t *tgt_begin;
+    float *coef;
+    int n_targets;
+};
+struct SynthJob {
+    const float *coef;     // [4][kNBasis]
+    float *out;            // [4][Nx][Ny][Nz], += sum_b coef[mu][b] B_b
+    int N[3];
+};
+struct SynthArgs {
+    int n_jobs;
+    SynthJob jobs[kMaxJobs];
+};
+// Least-squares coefficients coef = Q F (Q: [kNBasis][npts]) and residuals
+// resid[mu] = max |F_mu - sum_b c[mu][b] B_b|, resid[4 + mu] = max |F_mu|
+// with c = coef_in (or the fitted coef when coef_in is null).
+struct ProjJob {
+    const float *F;        // [4][npts]
+    const float *Q;
+    const float *coef_in;
+    float *coef;
+    float *resid;
+    int N[3];
+    int64_t npts;
+};
+struct ProjArgs {
+    int n_jobs;
+    ProjJob jobs[kMaxJobs];
+};
+// budget[mu] = scale * max |out_mu|
+struct BudgetJob {
+    const float *out;
+    float *budget;
+    int64_t npts;
+    float scale;
+};
+struct BudgetArgs {
+    int n_jobs;
+    BudgetJob jobs[kMaxJobs];
+};
+// Judge correction: a pair that is active and whose residual exceeds the
+// budget in any component has out += F - sum_b pc B_b and fail = 1.
+struct CorrJob {
+    const float *F;
+    const float *pc;
+    const float *resid;
+    const float *budget;
+    float *out;
+    int32_t *fail;
+    int N[3];
+    int active;
+};
+struct CorrArgs {
+    int n_jobs;
+    int64_t max_pts;
+    CorrJob jobs[kMaxJobs];
+};
+void launch_moments(const MomentArgs &a, hipStream_t st);
+void launch_features(const FeatArgs &a, hipStream_t st);
+void launch_xform(const XformArgs &a, hipStream_t st);
+void launch_coef_sum(const CoefArgs &a, hipStream_t st);
+void launch_synthesize(const SynthArgs &a, hipStream_t st);
+void launch_project(const ProjArgs &a, bool fit, hipStream_t st);
+void launch_budget(const BudgetArgs &a, hipStream_t st);
+void launch_correct(const CorrArgs &a, hipStream_t st);
+
+// Network forward pass of the surrogate on a given stream (mlp.hip).
+bool mlp_dims(rp_mlp m, int *n_in, int *n_out, int *max_batch);
+void mlp_forward_on(rp_mlp m, const float *x, int batch, float *y, hipStream_t st);
 
 }  // namespace rpot

@@ -1,0 +1,692 @@
+// Host side of the learned far-pair surrogate: pair classification, frames
+// and basis maps, workspace, the per-step moment and inference launches, the
+// plain pair responses that train and judge the network, and the fallback.
+//
+// A pair (s <- n) is far when its centre distance exceeds far_factor times
+// the larger of the two box diagonals.  Far pairs leave the plain lag sum;
+// their sources keep only a ring of moments, not of spectra, unless they are
+// audit sources: those keep the plain history of all their pairs, so their
+// far pairs can be judged against the plain sum and can fall back to it.
+#include "plan_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+using namespace rpot;
+
+namespace rpot_host {
+
+namespace {
+
+const int kDeg[kNBasis][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 0, 3}, {0, 1, 0}, {0, 1, 1}, {0, 1, 2},
+                              {0, 2, 0}, {0, 2, 1}, {0, 3, 0}, {1, 0, 0}, {1, 0, 1}, {1, 0, 2}, {1, 1, 0},
+                              {1, 1, 1}, {1, 2, 0}, {2, 0, 0}, {2, 0, 1}, {2, 1, 0}, {3, 0, 0}};
+
+void legendre(double x, double (&p)[4]) {
+    p[0] = 1.0;
+    p[1] = x;
+    p[2] = 0.5 * (3.0 * x * x - 1.0);
+    p[3] = 0.5 * x * (5.0 * x * x - 3.0);
+}
+
+void basis_row(const double (&x)[3], double *B) {
+    double px[4], py[4], pz[4];
+    legendre(x[0], px);
+    legendre(x[1], py);
+    legendre(x[2], pz);
+    for (int b = 0; b < kNBasis; ++b) B[b] = px[kDeg[b][0]] * py[kDeg[b][1]] * pz[kDeg[b][2]];
+}
+
+// Inverse of the symmetric positive definite n x n matrix G (Cholesky).
+std::vector<double> spd_inverse(std::vector<double> G, int n) {
+    std::vector<double> L(size_t(n) * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double d = G[size_t(j) * n + j];
+        for (int k = 0; k < j; ++k) d -= L[size_t(j) * n + k] * L[size_t(j) * n + k];
+        if (!(d > 0)) fail(RP_ERR_UNSUPPORTED, "surrogate basis is singular on this grid");
+        L[size_t(j) * n + j] = std::sqrt(d);
+        for (int i = j + 1; i < n; ++i) {
+            double v = G[size_t(i) * n + j];
+            for (int k = 0; k < j; ++k) v -= L[size_t(i) * n + k] * L[size_t(j) * n + k];
+            L[size_t(i) * n + j] = v / L[size_t(j) * n + j];
+        }
+    }
+    std::vector<double> inv(size_t(n) * n, 0.0);
+    for (int c = 0; c < n; ++c) {
+        std::vector<double> y(n, 0.0);
+        for (int i = 0; i < n; ++i) {   // L y = e_c
+            double v = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= L[size_t(i) * n + k] * y[k];
+            y[i] = v / L[size_t(i) * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {   // L^T x = y
+            double v = y[i];
+            for (int k = i + 1; k < n; ++k) v -= L[size_t(k) * n + i] * inv[size_t(k) * n + c];
+            inv[size_t(i) * n + c] = v / L[size_t(i) * n + i];
+        }
+    }
+    return inv;
+}
+
+// X = argmin |A X - Y| for A [m][kNBasis], Y [m][kNBasis] (normal equations).
+std::vector<double> lsq20(const std::vector<double> &A, const std::vector<double> &Y, int m) {
+    const int n = kNBasis;
+    std::vector<double> G(size_t(n) * n, 0.0), R(size_t(n) * n, 0.0);
+    for (int r = 0; r < m; ++r)
+        for (int i = 0; i < n; ++i) {
+            for (int j = 0; j < n; ++j) {
+                G[size_t(i) * n + j] += A[size_t(r) * n + i] * A[size_t(r) * n + j];
+                R[size_t(i) * n + j] += A[size_t(r) * n + i] * Y[size_t(r) * n + j];
+            }
+        }
+    const std::vector<double> Gi = spd_inverse(G, n);
+    std::vector<double> X(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) X[size_t(i) * n + j] += Gi[size_t(i) * n + k] * R[size_t(k) * n + j];
+    return X;
+}
+
+double centre(rp_plan p, int i, int a) { return p->dom[i].o[a] + 0.5 * p->h * (p->dom[i].N[a] - 1); }
+
+double diagonal(rp_plan p, int i) {
+    double d2 = 0;
+    for (int a = 0; a < 3; ++a) {
+        const double e = p->h * (p->dom[i].N[a] - 1);
+        d2 += e * e;
+    }
+    return std::sqrt(d2);
+}
+
+// Right-handed frame with e1 along d (rows of R).
+void make_frame(const double (&d)[3], double (&R)[9]) {
+    const double L = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double e1[3] = {d[0] / L, d[1] / L, d[2] / L};
+    double a[3] = {0, 0, 1};
+    if (std::fabs(e1[2]) > 0.9) a[0] = 1, a[2] = 0;
+    const double ad = a[0] * e1[0] + a[1] * e1[1] + a[2] * e1[2];
+    double e2[3] = {a[0] - ad * e1[0], a[1] - ad * e1[1], a[2] - ad * e1[2]};
+    const double n2 = std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+    for (double &v : e2) v /= n2;
+    const double e3[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    for (int i = 0; i < 3; ++i) {
+        R[i] = e1[i];
+        R[3 + i] = e2[i];
+        R[6 + i] = e3[i];
+    }
+}
+
+// Basis maps of a far pair.  The network's frame basis is the same
+// tensor-Legendre set in u = R (r - c_s) / ell (ell = the target's largest
+// half side); both sets span the polynomials of total degree <= 3, so the
+// maps are exact: M takes frame coefficients to box coefficients, Minv back.
+void pair_maps(rp_plan p, const FarPairH &F, float *M, float *Minv) {
+    const DomainP &t = p->dom[F.s];
+    double hw[3], ell = 0;
+    for (int a = 0; a < 3; ++a) {
+        hw[a] = 0.5 * p->h * (t.N[a] - 1);
+        ell = std::max(ell, hw[a]);
+    }
+    const double nodes[4] = {-1.0, -1.0 / 3.0, 1.0 / 3.0, 1.0};
+    const int m = 64;
+    std::vector<double> Bb(size_t(m) * kNBasis), Bf(size_t(m) * kNBasis);
+    int r = 0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            for (int k = 0; k < 4; ++k, ++r) {
+                const double xi[3] = {nodes[i], nodes[j], nodes[k]};
+                basis_row(xi, &Bb[size_t(r) * kNBasis]);
+                const double d[3] = {xi[0] * hw[0], xi[1] * hw[1], xi[2] * hw[2]};
+                double u[3];
+                for (int a = 0; a < 3; ++a)
+                    u[a] = (F.rot[3 * a] * d[0] + F.rot[3 * a + 1] * d[1] + F.rot[3 * a + 2] * d[2]) / ell;
+                basis_row(u, &Bf[size_t(r) * kNBasis]);
+            }
+    const std::vector<double> X = lsq20(Bb, Bf, m), Xi = lsq20(Bf, Bb, m);
+    for (int i = 0; i < kNBasis * kNBasis; ++i) {
+        M[i] = float(X[i]);
+        Minv[i] = float(Xi[i]);
+    }
+}
+
+// LS dual basis of an N-grid box: Q = (B^T B)^-1 B^T, [kNBasis][npts].
+std::vector<float> dual_basis(const int (&N)[3]) {
+    const int64_t npts = int64_t(N[0]) * N[1] * N[2];
+    std::vector<double> B(size_t(npts) * kNBasis);
+    std::vector<double> G(kNBasis * kNBasis, 0.0);
+    for (int64_t i = 0; i < npts; ++i) {
+        const int iz = int(i % N[2]), iy = int((i / N[2]) % N[1]), ix = int(i / (int64_t(N[2]) * N[1]));
+        const double x[3] = {2.0 * ix / (N[0] - 1) - 1.0, 2.0 * iy / (N[1] - 1) - 1.0, 2.0 * iz / (N[2] - 1) - 1.0};
+        double *row = &B[size_t(i) * kNBasis];
+        basis_row(x, row);
+        for (int a = 0; a < kNBasis; ++a)
+            for (int b = 0; b < kNBasis; ++b) G[a * kNBasis + b] += row[a] * row[b];
+    }
+    const std::vector<double> Gi = spd_inverse(G, kNBasis);
+    std::vector<float> Q(size_t(kNBasis) * npts);
+    for (int64_t i = 0; i < npts; ++i)
+        for (int a = 0; a < kNBasis; ++a) {
+            double v = 0;
+            for (int b = 0; b < kNBasis; ++b) v += Gi[a * kNBasis + b] * B[size_t(i) * kNBasis + b];
+            Q[size_t(a) * npts + i] = float(v);
+        }
+    return Q;
+}
+
+void upload_csr(rp_plan p, hipStream_t st) {
+    SurrogateH &U = p->sur;
+    const int nd = p->n_dom;
+    U.h_order.clear();
+    U.h_tbeg.assign(nd + 1, 0);
+    std::vector<std::vector<int32_t>> by_t(nd);
+    for (size_t f = 0; f < U.pairs.size(); ++f)
+        if (!U.pairs[f].plain) by_t[U.pairs[f].s].push_back(int32_t(f));
+    for (int s = 0; s < nd; ++s) {
+        U.h_tbeg[s] = int32_t(U.h_order.size());
+        U.h_order.insert(U.h_order.end(), by_t[s].begin(), by_t[s].end());
+    }
+    U.h_tbeg[nd] = int32_t(U.h_order.size());
+    if (!U.h_order.empty())
+        HIP_OK(hipMemcpyAsync(p->ws + U.off_order, U.h_order.data(), U.h_order.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(p->ws + U.off_tbeg, U.h_tbeg.data(), U.h_tbeg.size() * 4, hipMemcpyHostToDevice, st));
+}
+
+int active_far(rp_plan p, int s) {
+    int n = 0;
+    for (const FarPairH &F : p->sur.pairs) n += (F.s == s && !F.plain);
+    return n;
+}
+
+// Plain pair fields of the audited far pairs at the last completed step: the
+// judge lag sum (ring heads of that step), then per batch of up to kMaxJobs
+// pairs with one target shape the inverse transform and crop into the judge
+// field buffers; fn(batch, count) is called after each batch is enqueued.
+template <typename Fn>
+void judge_fields(rp_plan p, hipStream_t st, Fn &&fn) {
+    SurrogateH &U = p->sur;
+    enqueue_k2(p, k2_args(p, U.judge, U.judge_dev, p->at<int32_t>(p->off_prev_head)), U.judge.tg, st, p->k2_unroll,
+               0);
+    for (int c : U.far_cls) {
+        const ClassP &K = p->cls[c];
+        std::vector<int> vs;
+        for (size_t v = 0; v < U.aud.size(); ++v)
+            if (p->dom[U.pairs[U.aud[v]].s].cls == c) vs.push_back(int(v));
+        for (size_t j0 = 0; j0 < vs.size(); j0 += kMaxJobs) {
+            const int cnt = int(std::min<size_t>(kMaxJobs, vs.size() - j0));
+            LinePass x = inv_x(p, K.N, K.P, K.Hz, false);
+            LinePass y = inv_y(p, K.N, K.P, K.Hz, false);
+            ZInv zi{};
+            zi.Nx = K.N[0];
+            zi.Ny = K.N[1];
+            zi.Nz = K.N[2];
+            zi.Pz = K.P[2];
+            zi.Hz = K.Hz;
+            zi.tw = tw_ptr(p, K.P[2], false);
+            zi.rp = make_radix(K.P[2]);
+            x.n_jobs = y.n_jobs = zi.n_jobs = cnt;
+            for (int j = 0; j < cnt; ++j) {
+                const int v = vs[j0 + j];
+                char *t1 = p->ws + U.off_jt1 + size_t(j) * U.jt1_elems * p->csz;
+                char *t2 = p->ws + U.off_jt2 + size_t(j) * U.jt2_elems * p->csz;
+                x.jobs[j].in = p->ws + U.jacc_off[v];
+                x.jobs[j].out = t2;
+                y.jobs[j].in = t2;
+                y.jobs[j].out = t1;
+                zi.jobs[j].in = t1;
+                zi.jobs[j].out = p->ws + U.off_jF + size_t(j) * U.jF_elems * 4;
+                zi.jobs[j].add = nullptr;
+            }
+            launch_line_pass(x, 0, st);
+            launch_line_pass(y, 0, st);
+            launch_zinv(zi, 0, st);
+            check_launch();
+            fn(&vs[j0], cnt);
+        }
+    }
+}
+
+float *jfield(rp_plan p, int j) { return p->at<float>(p->sur.off_jF + size_t(j) * p->sur.jF_elems * 4); }
+
+void need_ready(rp_plan p) {
+    if (!p->sur.on) fail(RP_ERR_STATE, "surrogate not configured (rp_surrogate_configure)");
+    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    if (p->next_step < 1 || p->pushed) fail(RP_ERR_STATE, "no completed step to evaluate");
+}
+
+}  // namespace
+
+void sur_classify(rp_plan p) {
+    SurrogateH &U = p->sur;
+    const int nd = p->n_dom;
+    U.pairs.clear();
+    U.far_index.assign(size_t(nd) * nd, -1);
+    U.src_slot.assign(nd, -1);
+    U.src_doms.clear();
+    U.aud.clear();
+    U.aud_row.clear();
+    U.mats.clear();
+    U.far_cls.clear();
+    U.synth_targets.clear();
+    if (!U.on) return;
+    const double cdt = p->c * p->dt;
+    for (const SystemP &S : p->sys) {
+        for (int s : S.doms) {
+            for (int n : S.doms) {
+                if (s == n) continue;
+                double d[3], d2 = 0;
+                for (int a = 0; a < 3; ++a) {
+                    d[a] = centre(p, s, a) - centre(p, n, a);
+                    d2 += d[a] * d[a];
+                }
+                const double dist = std::sqrt(d2);
+                if (!(dist > U.far_factor * std::max(diagonal(p, s), diagonal(p, n)))) continue;
+                for (int a = 0; a < 3; ++a)
+                    if (p->dom[s].N[a] < 4)
+                        fail(RP_ERR_UNSUPPORTED, "a far-pair target needs at least 4 points per axis");
+                FarPairH F;
+                F.s = s;
+                F.n = n;
+                F.dist = dist;
+                F.m_c = int(std::lround(dist / cdt));
+                F.frac = dist / cdt - F.m_c;
+                F.audited = U.audit[n] != 0;
+                make_frame(d, F.rot);
+                U.far_index[size_t(s) * nd + n] = int(U.pairs.size());
+                U.pairs.push_back(F);
+            }
+        }
+    }
+    U.mom_depth = 1;
+    for (const FarPairH &F : U.pairs) {
+        if (U.src_slot[F.n] < 0) {
+            U.src_slot[F.n] = int(U.src_doms.size());
+            U.src_doms.push_back(F.n);
+        }
+        U.mom_depth = std::max(U.mom_depth, F.m_c - U.n_lags / 2 + U.n_lags);
+        if (F.audited) U.aud.push_back(int(&F - U.pairs.data()));
+        const int c = p->dom[F.s].cls;
+        if (std::find(U.far_cls.begin(), U.far_cls.end(), c) == U.far_cls.end()) U.far_cls.push_back(c);
+        if (std::find(U.synth_targets.begin(), U.synth_targets.end(), F.s) == U.synth_targets.end())
+            U.synth_targets.push_back(F.s);
+    }
+    // judge order: by system, then source (shared ring reads), then target
+    std::stable_sort(U.aud.begin(), U.aud.end(), [&](int a, int b) {
+        const FarPairH &A = U.pairs[a], &B = U.pairs[b];
+        const int sa = p->dom[A.s].sys, sb = p->dom[B.s].sys;
+        if (sa != sb) return sa < sb;
+        if (A.n != B.n) return A.n < B.n;
+        return A.s < B.s;
+    });
+    U.aud_row.assign(U.aud.size(), 0);
+    for (size_t v = 0; v < U.aud.size(); ++v)
+        for (int f = 0; f < U.aud[v]; ++f) U.aud_row[v] += U.pairs[f].audited ? 1 : 0;
+    U.mats.resize(U.pairs.size() * 2 * kNBasis * kNBasis);
+    for (size_t f = 0; f < U.pairs.size(); ++f)
+        pair_maps(p, U.pairs[f], &U.mats[f * 2 * kNBasis * kNBasis], &U.mats[(f * 2 + 1) * kNBasis * kNBasis]);
+}
+
+void sur_layout(rp_plan p, size_t &off) {
+    auto alloc = [&](size_t bytes) {
+        const size_t o = off;
+        off += (std::max<size_t>(bytes, 1) + kAlign - 1) / kAlign * kAlign;
+        return o;
+    };
+    SurrogateH &U = p->sur;
+    const size_t nf = U.pairs.size(), na = U.aud.size(), ns = U.src_doms.size(), nd = p->dom.size();
+    U.off_mom = alloc(ns * U.mom_depth * kFeatStride * 4);
+    U.off_mpart = alloc(ns * kMomChunks * kNFeat * 4);
+    U.off_fpairs = alloc(nf * sizeof(FarPair));
+    U.off_x = alloc(nf * U.n_in * 4);
+    U.off_y = alloc(nf * kNOut * 4);
+    U.off_pc = alloc(nf * kNOut * 4);
+    U.off_coef = alloc(nd * kNOut * 4);
+    U.off_order = alloc(nf * 4);
+    U.off_tbeg = alloc((nd + 1) * 4);
+    U.off_mats = alloc(nf * 2 * kNBasis * kNBasis * 4);
+    U.off_inscale = alloc(kNFeat * 4);
+    U.off_outscale = alloc(kNOut * 4);
+    U.off_Q.clear();
+    U.jt1_elems = U.jt2_elems = U.jF_elems = 0;
+    for (int c : U.far_cls) {
+        const ClassP &K = p->cls[c];
+        const size_t npts = size_t(K.N[0]) * K.N[1] * K.N[2];
+        U.off_Q[c] = alloc(kNBasis * npts * 4);
+        U.jt1_elems = std::max(U.jt1_elems, size_t(K.N[0]) * K.N[1] * K.Hz * 4);
+        U.jt2_elems = std::max(U.jt2_elems, size_t(K.N[0]) * K.P[1] * K.Hz * 4);
+        U.jF_elems = std::max(U.jF_elems, 4 * npts);
+    }
+    size_t jacc = 0;
+    U.jacc_off.assign(na, 0);
+    for (size_t v = 0; v < na; ++v) jacc += size_t(p->sys[p->dom[U.pairs[U.aud[v]].s].sys].C) * 4 * p->csz;
+    U.off_jacc = alloc(jacc);
+    size_t o = U.off_jacc;
+    for (size_t v = 0; v < na; ++v) {
+        U.jacc_off[v] = o;
+        o += size_t(p->sys[p->dom[U.pairs[U.aud[v]].s].sys].C) * 4 * p->csz;
+    }
+    const size_t nj = std::min<size_t>(kMaxJobs, std::max<size_t>(na, 1));
+    U.off_jt1 = alloc(nj * U.jt1_elems * p->csz);
+    U.off_jt2 = alloc(nj * U.jt2_elems * p->csz);
+    U.off_jF = alloc(nj * U.jF_elems * 4);
+    U.off_jcb = alloc(kMaxJobs * kNOut * 4);
+    U.off_jres = alloc(na * 8 * 4);
+    U.off_budget = alloc(nd * 4 * 4);
+    U.off_fail = alloc(na * 4);
+    U.off_aud = alloc(na * 4);
+}
+
+void sur_bind(rp_plan p) {
+    SurrogateH &U = p->sur;
+    hipStream_t st = p->stream;
+    std::vector<FarPair> fp(U.pairs.size());
+    double dbar = 0;
+    for (int i = 0; i < p->n_dom; ++i) dbar += diagonal(p, i) / p->n_dom;
+    for (size_t f = 0; f < U.pairs.size(); ++f) {
+        const FarPairH &F = U.pairs[f];
+        FarPair &D = fp[f];
+        D.s = F.s;
+        D.n = F.n;
+        D.m_c = F.m_c;
+        D.src_slot = U.src_slot[F.n];
+        for (int i = 0; i < 9; ++i) D.rot[i] = float(F.rot[i]);
+        D.inv_d = float(1.0 / F.dist);
+        D.geo[0] = float(10.0 * dbar / F.dist);
+        D.geo[1] = float(F.frac);
+    }
+    std::vector<int32_t> aud(U.aud.begin(), U.aud.end());
+    std::vector<float> ones(kNOut, 1.0f);
+    if (!fp.empty()) {
+        HIP_OK(hipMemcpy(p->ws + U.off_fpairs, fp.data(), fp.size() * sizeof(FarPair), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(p->ws + U.off_mats, U.mats.data(), U.mats.size() * 4, hipMemcpyHostToDevice));
+    }
+    if (!aud.empty()) HIP_OK(hipMemcpy(p->ws + U.off_aud, aud.data(), aud.size() * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(p->ws + U.off_inscale, ones.data(), kNFeat * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(p->ws + U.off_outscale, ones.data(), kNOut * 4, hipMemcpyHostToDevice));
+    for (const auto &kv : U.off_Q) {
+        const std::vector<float> Q = dual_basis(p->cls[kv.first].N);
+        HIP_OK(hipMemcpy(p->ws + kv.second, Q.data(), Q.size() * 4, hipMemcpyHostToDevice));
+    }
+    for (FarPairH &F : U.pairs) F.plain = false;
+    upload_csr(p, st);
+    if (!U.src_doms.empty())   // ns * depth * 96 bytes: a multiple of 16
+        launch_fill_zero(p->ws + U.off_mom, U.src_doms.size() * U.mom_depth * kFeatStride * 4, st);
+    launch_fill_zero(p->ws + U.off_coef, (p->dom.size() * kNOut * 4 + 15) / 16 * 16, st);
+    check_launch();
+    HIP_OK(hipStreamSynchronize(st));
+}
+
+void sur_enqueue_moments(rp_plan p, const void *const *src, hipStream_t st) {
+    SurrogateH &U = p->sur;
+    const size_t ns = U.src_doms.size();
+    for (size_t j0 = 0; j0 < ns; j0 += kMaxJobs) {
+        MomentArgs a{};
+        a.h = float(p->h);
+        a.h3 = p->h * p->h * p->h;
+        a.depth = U.mom_depth;
+        a.step = p->at<int64_t>(p->off_state);
+        a.n_jobs = int(std::min<size_t>(kMaxJobs, ns - j0));
+        for (int j = 0; j < a.n_jobs; ++j) {
+            const int slot = int(j0) + j, n = U.src_doms[slot];
+            const DomainP &d = p->dom[n];
+            MomentJob &J = a.jobs[j];
+            J.src = static_cast<const float *>(src[n]);
+            J.s0 = p->at<float>(d.off_s0);
+            J.ring = p->at<float>(U.off_mom) + size_t(slot) * U.mom_depth * kFeatStride;
+            J.partial = p->at<float>(U.off_mpart) + size_t(slot) * kMomChunks * kNFeat;
+            for (int c = 0; c < 3; ++c) {
+                J.N[c] = d.N[c];
+                J.o[c] = float(d.o[c] - centre(p, n, c));
+            }
+        }
+        launch_moments(a, st);
+        check_launch();
+    }
+}
+
+FeatArgs feat_args(rp_plan p, float *x, int64_t adj) {
+    SurrogateH &U = p->sur;
+    FeatArgs f{};
+    f.pairs = p->at<FarPair>(U.off_fpairs);
+    f.moments = p->at<float>(U.off_mom);
+    f.in_scale = p->at<float>(U.off_inscale);
+    f.x = x;
+    f.step = p->at<int64_t>(p->off_state);
+    f.step_adj = adj;
+    f.depth = U.mom_depth;
+    f.n_lags = U.n_lags;
+    f.n_in = U.n_in;
+    f.n_pairs = int(U.pairs.size());
+    return f;
+}
+
+// Inference of every far pair at the current step and the synthesis of the
+// active pairs' fields into the targets' outputs.
+void sur_enqueue_infer(rp_plan p, void *const *out, hipStream_t st) {
+    SurrogateH &U = p->sur;
+    const int nf = int(U.pairs.size());
+    if (!U.attached || nf == 0) return;
+    launch_features(feat_args(p, p->at<float>(U.off_x), 0), st);
+    mlp_forward_on(U.mlp, p->at<float>(U.off_x), nf, p->at<float>(U.off_y), st);
+    XformArgs xa{};
+    xa.pairs = p->at<FarPair>(U.off_fpairs);
+    xa.mats = p->at<float>(U.off_mats);
+    xa.in = p->at<float>(U.off_y);
+    xa.out = p->at<float>(U.off_pc);
+    xa.scale = p->at<float>(U.off_outscale);
+    xa.dir = 0;
+    xa.n = nf;
+    launch_xform(xa, st);
+    CoefArgs ca{};
+    ca.pc = p->at<float>(U.off_pc);
+    ca.order = p->at<int32_t>(U.off_order);
+    ca.tgt_begin = p->at<int32_t>(U.off_tbeg);
+    ca.coef = p->at<float>(U.off_coef);
+    ca.n_targets = p->n_dom;
+    launch_coef_sum(ca, st);
+    for (size_t j0 = 0; j0 < U.synth_targets.size(); j0 += kMaxJobs) {
+        SynthArgs sa{};
+        sa.n_jobs = int(std::min<size_t>(kMaxJobs, U.synth_targets.size() - j0));
+        for (int j = 0; j < sa.n_jobs; ++j) {
+            const int s = U.synth_targets[j0 + j];
+            sa.jobs[j].coef = p->at<float>(U.off_coef) + size_t(s) * kNOut;
+            sa.jobs[j].out = static_cast<float *>(out[s]);
+            for (int c = 0; c < 3; ++c) sa.jobs[j].N[c] = p->dom[s].N[c];
+        }
+        launch_synthesize(sa, st);
+    }
+    check_launch();
+}
+
+// ---------------------------------------------------------------------------
+// Entry points (called from the C ABI in plan.cpp's guard)
+
+void sur_configure(rp_plan p, double far_factor, int n_lags, const int32_t *audit, int n_audit) {
+    if (p->ws) fail(RP_ERR_STATE, "configure the surrogate before rp_bind_workspace");
+    SurrogateH &U = p->sur;
+    if (far_factor <= 0) {
+        U = SurrogateH{};
+    } else {
+        if (!std::isfinite(far_factor)) fail(RP_ERR_ARG, "far_factor must be finite");
+        if (p->p64) fail(RP_ERR_UNSUPPORTED, "the surrogate runs with FP32 outputs (not RP_FP64)");
+        if (!std::isfinite(p->c)) fail(RP_ERR_UNSUPPORTED, "the surrogate needs a finite c");
+        if (n_lags < 1 || n_lags > 1024) fail(RP_ERR_ARG, "n_lags must be in [1, 1024]");
+        if (n_audit < 0 || (n_audit > 0 && !audit)) fail(RP_ERR_ARG, "bad audit list");
+        std::vector<char> aud(p->n_dom, 0);
+        for (int i = 0; i < n_audit; ++i) {
+            if (audit[i] < 0 || audit[i] >= p->n_dom) fail(RP_ERR_ARG, "audit source out of range");
+            aud[audit[i]] = 1;
+        }
+        U = SurrogateH{};
+        U.on = true;
+        U.far_factor = far_factor;
+        U.n_lags = n_lags;
+        U.n_in = n_lags * kNFeat + kNGeo;
+        U.audit = aud;
+    }
+    sur_classify(p);
+    plan_tables(p);
+    plan_layout(p);
+    plan_stats(p);
+}
+
+void sur_attach(rp_plan p, rp_mlp mlp, const float *in_scale, const float *out_scale) {
+    SurrogateH &U = p->sur;
+    if (!U.on) fail(RP_ERR_STATE, "surrogate not configured (rp_surrogate_configure)");
+    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    release_graph(p);
+    if (!mlp) {
+        U.mlp = nullptr;
+        U.attached = false;
+        return;
+    }
+    int ni = 0, no = 0, mb = 0;
+    if (!mlp_dims(mlp, &ni, &no, &mb)) fail(RP_ERR_STATE, "network workspace not bound");
+    if (ni != U.n_in || no != kNOut) fail(RP_ERR_ARG, "network shape does not match the surrogate (n_in, 80)");
+    if (mb < int(U.pairs.size())) fail(RP_ERR_ARG, "network max_batch below the number of far pairs");
+    if (!in_scale || !out_scale) fail(RP_ERR_ARG, "scales are null");
+    HIP_OK(hipStreamSynchronize(p->stream));
+    HIP_OK(hipMemcpy(p->ws + U.off_inscale, in_scale, kNFeat * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(p->ws + U.off_outscale, out_scale, kNOut * 4, hipMemcpyHostToDevice));
+    U.mlp = mlp;
+    U.attached = true;
+}
+
+void sur_features(rp_plan p, float *x) {
+    need_ready(p);
+    if (!x) fail(RP_ERR_ARG, "x is null");
+    launch_features(feat_args(p, x, -1), p->stream);
+    check_launch();
+}
+
+void sur_pair_response(rp_plan p, float *coef, float *resid) {
+    need_ready(p);
+    SurrogateH &U = p->sur;
+    if (!coef || !resid) fail(RP_ERR_ARG, "null output");
+    if (U.aud.empty()) return;
+    hipStream_t st = p->stream;
+    judge_fields(p, st, [&](const int *vs, int cnt) {
+        ProjArgs pa{};
+        pa.n_jobs = cnt;
+        for (int j = 0; j < cnt; ++j) {
+            const int v = vs[j];
+            const DomainP &t = p->dom[U.pairs[U.aud[v]].s];
+            ProjJob &J = pa.jobs[j];
+            J.F = jfield(p, j);
+            J.Q = p->at<float>(U.off_Q.at(t.cls));
+            J.coef_in = nullptr;
+            J.coef = p->at<float>(U.off_jcb) + size_t(j) * kNOut;
+            J.resid = resid + size_t(U.aud_row[v]) * 8;
+            for (int c = 0; c < 3; ++c) J.N[c] = t.N[c];
+            J.npts = t.npts;
+        }
+        launch_project(pa, true, st);
+        for (int j = 0; j < cnt; ++j) {
+            XformArgs xa{};
+            xa.pairs = p->at<FarPair>(U.off_fpairs);
+            xa.mats = p->at<float>(U.off_mats);
+            xa.in = p->at<float>(U.off_jcb) + size_t(j) * kNOut;
+            xa.out = coef + size_t(U.aud_row[vs[j]]) * kNOut;
+            xa.index = p->at<int32_t>(U.off_aud) + vs[j];
+            xa.dir = 1;
+            xa.n = 1;
+            launch_xform(xa, st);
+        }
+        check_launch();
+    });
+}
+
+void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, double *worst) {
+    need_ready(p);
+    SurrogateH &U = p->sur;
+    if (!U.attached) fail(RP_ERR_STATE, "no network attached (rp_surrogate_attach)");
+    if (!out) fail(RP_ERR_ARG, "out is null");
+    for (int n = 0; n < p->n_dom; ++n)
+        if (!out[n]) fail(RP_ERR_ARG, "an out pointer is null");
+    if (!(tol > 0)) fail(RP_ERR_ARG, "tol must be positive");
+    hipStream_t st = p->stream;
+    const int na = int(U.aud.size());
+    int fell = 0;
+    double w = 0.0;
+    if (na > 0) {
+        // per-target budgets: tol * max |P_s| / (active far pairs of s)
+        std::vector<int> ts;
+        for (int s : U.synth_targets)
+            if (active_far(p, s) > 0) ts.push_back(s);
+        for (size_t j0 = 0; j0 < ts.size(); j0 += kMaxJobs) {
+            BudgetArgs ba{};
+            ba.n_jobs = int(std::min<size_t>(kMaxJobs, ts.size() - j0));
+            for (int j = 0; j < ba.n_jobs; ++j) {
+                const int s = ts[j0 + j];
+                ba.jobs[j].out = static_cast<const float *>(out[s]);
+                ba.jobs[j].budget = p->at<float>(U.off_budget) + size_t(s) * 4;
+                ba.jobs[j].npts = p->dom[s].npts;
+                ba.jobs[j].scale = float(tol / active_far(p, s));
+            }
+            launch_budget(ba, st);
+        }
+        launch_fill_zero(p->ws + U.off_fail, (size_t(na) * 4 + 15) / 16 * 16, st);
+        judge_fields(p, st, [&](const int *vs, int cnt) {
+            ProjArgs pa{};
+            CorrArgs ca{};
+            pa.n_jobs = ca.n_jobs = cnt;
+            for (int j = 0; j < cnt; ++j) {
+                const int v = vs[j], f = U.aud[v];
+                const FarPairH &F = U.pairs[f];
+                const DomainP &t = p->dom[F.s];
+                ProjJob &J = pa.jobs[j];
+                J.F = jfield(p, j);
+                J.Q = nullptr;
+                J.coef_in = p->at<float>(U.off_pc) + size_t(f) * kNOut;
+                J.coef = p->at<float>(U.off_jcb) + size_t(j) * kNOut;
+                J.resid = p->at<float>(U.off_jres) + size_t(v) * 8;
+                for (int c = 0; c < 3; ++c) J.N[c] = t.N[c];
+                J.npts = t.npts;
+                CorrJob &C = ca.jobs[j];
+                C.F = J.F;
+                C.pc = J.coef_in;
+                C.resid = J.resid;
+                C.budget = p->at<float>(U.off_budget) + size_t(F.s) * 4;
+                C.out = static_cast<float *>(out[F.s]);
+                C.fail = p->at<int32_t>(U.off_fail) + v;
+                for (int c = 0; c < 3; ++c) C.N[c] = t.N[c];
+                C.active = F.plain ? 0 : 1;
+                ca.max_pts = std::max<int64_t>(ca.max_pts, t.npts);
+            }
+            launch_project(pa, false, st);
+            launch_correct(ca, st);
+            check_launch();
+        });
+        std::vector<int32_t> flags(na);
+        std::vector<float> res(size_t(na) * 8), bud(size_t(p->n_dom) * 4);
+        HIP_OK(hipStreamSynchronize(st));
+        HIP_OK(hipMemcpy(flags.data(), p->ws + U.off_fail, size_t(na) * 4, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(res.data(), p->ws + U.off_jres, res.size() * 4, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(bud.data(), p->ws + U.off_budget, bud.size() * 4, hipMemcpyDeviceToHost));
+        for (int v = 0; v < na; ++v) {
+            FarPairH &F = U.pairs[U.aud[v]];
+            if (F.plain) continue;
+            for (int mu = 0; mu < 4; ++mu) {
+                const double b = bud[size_t(F.s) * 4 + mu];
+                const double r = res[size_t(v) * 8 + mu];
+                w = std::max(w, b > 0 ? r / b : (r > 0 ? INFINITY : 0.0));
+            }
+            if (flags[v]) {
+                F.plain = true;
+                ++fell;
+            }
+        }
+        if (fell) {
+            main_k2(p, p->k2, plain_pair);
+            upload_k2(p, p->k2, p->k2_dev, st);
+            upload_csr(p, st);
+            HIP_OK(hipStreamSynchronize(st));
+            plan_stats(p);
+        }
+    }
+    if (n_fallback) *n_fallback = fell;
+    if (worst) *worst = w;
+}
+
+}  // namespace rpot_host

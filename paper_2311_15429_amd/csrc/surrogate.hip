@@ -1,0 +1,396 @@
+// Kernels of the learned far-pair surrogate.
+//
+// The paper closes by pointing at a multipole approximation of the retarded
+// potentials of far sub-domains as a further speed-up (Sec. V).  Here that far
+// coupling is learned: for a far pair (target s <- source n) a small network
+// maps the recent history of the source's low-order moments, rotated into a
+// frame aligned with the pair, to the coefficients of the pair's potential in
+// a cubic polynomial basis on the target box.  The kernels below compute the
+// moments, gather the network inputs, map the outputs back to the box basis,
+// add the synthesised field to the targets, and judge the surrogate against
+// the plain pair sum (least-squares fit, residuals, correction).
+//
+// Box basis: B_b(x, y, z) = P_i(x) P_j(y) P_k(z), i + j + k <= 3 (20 functions,
+// Legendre polynomials P, box coordinates mapped to [-1, 1]).
+#include "rpot_internal.hpp"
+
+namespace rpot {
+
+__device__ __forceinline__ void legendre4(float x, float (&p)[4]) {
+    p[0] = 1.f;
+    p[1] = x;
+    p[2] = 0.5f * (3.f * x * x - 1.f);
+    p[3] = 0.5f * x * (5.f * x * x - 3.f);
+}
+
+// basis index -> degrees along x, y, z (lexicographic, total degree <= 3)
+__constant__ int8_t kBasisDeg[kNBasis][3] = {
+    {0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 0, 3}, {0, 1, 0}, {0, 1, 1}, {0, 1, 2}, {0, 2, 0}, {0, 2, 1}, {0, 3, 0},
+    {1, 0, 0}, {1, 0, 1}, {1, 0, 2}, {1, 1, 0}, {1, 1, 1}, {1, 2, 0}, {2, 0, 0}, {2, 0, 1}, {2, 1, 0}, {3, 0, 0}};
+
+__device__ __forceinline__ float box_coord(int i, int n) { return n > 1 ? 2.f * float(i) / float(n - 1) - 1.f : 0.f; }
+
+// The 20 basis values at grid point i of an N[0] x N[1] x N[2] box.
+__device__ __forceinline__ void basis_at(int64_t i, const int (&N)[3], float (&B)[kNBasis]) {
+    const int iz = int(i % N[2]);
+    const int iy = int((i / N[2]) % N[1]);
+    const int ix = int(i / (int64_t(N[2]) * N[1]));
+    float px[4], py[4], pz[4];
+    legendre4(box_coord(ix, N[0]), px);
+    legendre4(box_coord(iy, N[1]), py);
+    legendre4(box_coord(iz, N[2]), pz);
+#pragma unroll
+    for (int b = 0; b < kNBasis; ++b) B[b] = px[kBasisDeg[b][0]] * py[kBasisDeg[b][1]] * pz[kBasisDeg[b][2]];
+}
+
+template <int NT>
+__device__ __forceinline__ float block_sum(float v, float *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <int NT>
+__device__ __forceinline__ float block_max(float v, float *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Moments.  Grid (kMomChunks, jobs): each block reduces a strided share of the
+// points into partial[chunk][kNFeat]; a second launch sums the chunks in a
+// fixed order (deterministic) into the ring slot of the current step.
+__global__ __launch_bounds__(256) void k_moments_partial(MomentArgs a) {
+    const MomentJob &j = a.jobs[blockIdx.y];
+    const int64_t npts = int64_t(j.N[0]) * j.N[1] * j.N[2];
+    float acc[kNFeat];
+#pragma unroll
+    for (int q = 0; q < kNFeat; ++q) acc[q] = 0.f;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < npts; i += int64_t(gridDim.x) * 256) {
+        const int iz = int(i % j.N[2]);
+        const int iy = int((i / j.N[2]) % j.N[1]);
+        const int ix = int(i / (int64_t(j.N[2]) * j.N[1]));
+        const float r[3] = {j.o[0] + a.h * float(ix), j.o[1] + a.h * float(iy), j.o[2] + a.h * float(iz)};
+        float d[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) d[mu] = j.src[mu * npts + i] - j.s0[mu * npts + i];
+        acc[0] += d[0];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[1 + c] = fmaf(d[0], r[c], acc[1 + c]);
+        acc[4] = fmaf(d[0] * r[0], r[0], acc[4]);
+        acc[5] = fmaf(d[0] * r[1], r[1], acc[5]);
+        acc[6] = fmaf(d[0] * r[2], r[2], acc[6]);
+        acc[7] = fmaf(d[0] * r[0], r[1], acc[7]);
+        acc[8] = fmaf(d[0] * r[0], r[2], acc[8]);
+        acc[9] = fmaf(d[0] * r[1], r[2], acc[9]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[10 + c] += d[1 + c];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) acc[13 + 3 * c + e] = fmaf(d[1 + c], r[e], acc[13 + 3 * c + e]);
+        }
+    }
+    __shared__ float red[256];
+#pragma unroll 1
+    for (int q = 0; q < kNFeat; ++q) {
+        const float v = block_sum<256>(acc[q], red);
+        if (threadIdx.x == 0) j.partial[blockIdx.x * kNFeat + q] = v;
+    }
+}
+
+__global__ void k_moments_final(MomentArgs a) {
+    const MomentJob &j = a.jobs[blockIdx.x];
+    const int q = threadIdx.x;
+    if (q >= kNFeat) return;
+    double s = 0.0;
+    for (int c = 0; c < kMomChunks; ++c) s += double(j.partial[c * kNFeat + q]);
+    const int64_t slot = (*a.step) % a.depth;
+    j.ring[slot * kFeatStride + q] = float(s * a.h3);
+}
+
+// ---------------------------------------------------------------------------
+// Network inputs of every far pair: the source's moments at lags
+// m = m_c - n_lags/2 + j (j < n_lags), i.e. of steps t = l - m, rotated into
+// the pair's frame and scaled, then the pair's geometry.  Steps t <= 0 have
+// dS = 0.  Block: one pair; thread: one lag.
+__global__ __launch_bounds__(128) void k_features(FeatArgs a) {
+    const FarPair &fp = a.pairs[blockIdx.x];
+    const int64_t l = *a.step + a.step_adj;
+    float *x = a.x + int64_t(blockIdx.x) * a.n_in;
+    const float *ring = a.moments + int64_t(fp.src_slot) * a.depth * kFeatStride;
+    float R[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = fp.rot[i];
+    for (int jl = threadIdx.x; jl < a.n_lags; jl += blockDim.x) {
+        const int64_t m = int64_t(fp.m_c) - a.n_lags / 2 + jl;
+        const int64_t t = l - m;
+        float f[kNFeat];
+        if (t > 0 && m >= 0) {
+            const float *v = ring + (t % a.depth) * kFeatStride;
+#pragma unroll
+            for (int q = 0; q < kNFeat; ++q) f[q] = v[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < kNFeat; ++q) f[q] = 0.f;
+        }
+        const float Q[3][3] = {{f[4], f[7], f[8]}, {f[7], f[5], f[9]}, {f[8], f[9], f[6]}};
+        float g[kNFeat];
+        g[0] = f[0];
+#pragma unroll
+        for (int A = 0; A < 3; ++A) {
+            g[1 + A] = R[3 * A] * f[1] + R[3 * A + 1] * f[2] + R[3 * A + 2] * f[3];
+            g[10 + A] = R[3 * A] * f[10] + R[3 * A + 1] * f[11] + R[3 * A + 2] * f[12];
+        }
+        // rank-2 tensors: T' = R T R^T
+        float RQ[3][3], RK[3][3];
+#pragma unroll
+        for (int A = 0; A < 3; ++A)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                RQ[A][c] = R[3 * A] * Q[0][c] + R[3 * A + 1] * Q[1][c] + R[3 * A + 2] * Q[2][c];
+                RK[A][c] = R[3 * A] * f[13 + c] + R[3 * A + 1] * f[16 + c] + R[3 * A + 2] * f[19 + c];
+            }
+        float Qp[3][3];
+#pragma unroll
+        for (int A = 0; A < 3; ++A)
+#pragma unroll
+            for (int B = 0; B < 3; ++B) {
+                Qp[A][B] = RQ[A][0] * R[3 * B] + RQ[A][1] * R[3 * B + 1] + RQ[A][2] * R[3 * B + 2];
+                g[13 + 3 * A + B] = RK[A][0] * R[3 * B] + RK[A][1] * R[3 * B + 1] + RK[A][2] * R[3 * B + 2];
+            }
+        g[4] = Qp[0][0];
+        g[5] = Qp[1][1];
+        g[6] = Qp[2][2];
+        g[7] = Qp[0][1];
+        g[8] = Qp[0][2];
+        g[9] = Qp[1][2];
+#pragma unroll
+        for (int q = 0; q < kNFeat; ++q) x[jl * kNFeat + q] = g[q] * a.in_scale[q];
+    }
+    if (threadIdx.x < kNGeo) x[a.n_lags * kNFeat + threadIdx.x] = fp.geo[threadIdx.x];
+}
+
+// Coefficient maps (see XformArgs).  Block: one row; thread: one output.
+__global__ __launch_bounds__(128) void k_xform(XformArgs a) {
+    const int row = blockIdx.x;
+    const int f = a.index ? a.index[row] : row;
+    const FarPair &fp = a.pairs[f];
+    const float *M = a.mats + (int64_t(f) * 2 + a.dir) * kNBasis * kNBasis;
+    __shared__ float v[kNOut], w[kNOut];
+    const int t = threadIdx.x;
+    if (t < kNOut) {
+        const float x = a.in[int64_t(row) * kNOut + t];
+        v[t] = (a.dir == 0) ? x * a.scale[t] * fp.inv_d : x;
+    }
+    __syncthreads();
+    const int mu = t / kNBasis, b = t - (t / kNBasis) * kNBasis;
+    if (a.dir == 0) {
+        // vector part back to the global axes: A_i = sum_j R[j][i] A'_j
+        if (t < kNOut) {
+            float y = v[t];
+            if (mu > 0) {
+                const int i = mu - 1;
+                y = fp.rot[i] * v[kNBasis + b] + fp.rot[3 + i] * v[2 * kNBasis + b] + fp.rot[6 + i] * v[3 * kNBasis + b];
+            }
+            w[t] = y;
+        }
+        __syncthreads();
+        if (t < kNOut) {
+            float y = 0.f;
+            for (int c = 0; c < kNBasis; ++c) y = fmaf(M[b * kNBasis + c], w[mu * kNBasis + c], y);
+            a.out[int64_t(row) * kNOut + t] = y;
+        }
+    } else {
+        if (t < kNOut) {
+            float y = 0.f;
+            for (int c = 0; c < kNBasis; ++c) y = fmaf(M[b * kNBasis + c], v[mu * kNBasis + c], y);
+            w[t] = y;
+        }
+        __syncthreads();
+        if (t < kNOut) {
+            float y = w[t];
+            if (mu > 0) {
+                const int j = mu - 1;
+                y = fp.rot[3 * j] * w[kNBasis + b] + fp.rot[3 * j + 1] * w[2 * kNBasis + b] +
+                    fp.rot[3 * j + 2] * w[3 * kNBasis + b];
+            }
+            a.out[int64_t(row) * kNOut + t] = y;
+        }
+    }
+}
+
+// Per target: the sum of its active far pairs' box coefficients (fixed order).
+__global__ void k_coef_sum(CoefArgs a) {
+    const int s = blockIdx.x;
+    const int k = threadIdx.x;
+    if (k >= kNOut) return;
+    float acc = 0.f;
+    for (int i = a.tgt_begin[s]; i < a.tgt_begin[s + 1]; ++i) acc += a.pc[int64_t(a.order[i]) * kNOut + k];
+    a.coef[int64_t(s) * kNOut + k] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_synthesize(SynthArgs a) {
+    const SynthJob &j = a.jobs[blockIdx.y];
+    const int64_t npts = int64_t(j.N[0]) * j.N[1] * j.N[2];
+    __shared__ float c[kNOut];
+    if (threadIdx.x < kNOut) c[threadIdx.x] = j.coef[threadIdx.x];
+    __syncthreads();
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < npts; i += int64_t(gridDim.x) * 256) {
+        float B[kNBasis];
+        basis_at(i, j.N, B);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            float v = 0.f;
+#pragma unroll
+            for (int b = 0; b < kNBasis; ++b) v = fmaf(c[mu * kNBasis + b], B[b], v);
+            j.out[mu * npts + i] += v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Judge: least-squares projection (block per (basis function, job)).
+__global__ __launch_bounds__(256) void k_project(ProjArgs a) {
+    const ProjJob &j = a.jobs[blockIdx.y];
+    const int b = blockIdx.x;
+    const float *q = j.Q + int64_t(b) * j.npts;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t i = threadIdx.x; i < j.npts; i += 256) {
+        const float w = q[i];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) acc[mu] = fmaf(w, j.F[mu * j.npts + i], acc[mu]);
+    }
+    __shared__ float red[256];
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        const float v = block_sum<256>(acc[mu], red);
+        if (threadIdx.x == 0) j.coef[mu * kNBasis + b] = v;
+    }
+}
+
+// Residual of F against the basis expansion with coefficients c (block per job).
+__global__ __launch_bounds__(256) void k_residual(ProjArgs a) {
+    const ProjJob &j = a.jobs[blockIdx.x];
+    const float *cin = j.coef_in ? j.coef_in : j.coef;
+    __shared__ float c[kNOut];
+    if (threadIdx.x < kNOut) c[threadIdx.x] = cin[threadIdx.x];
+    __syncthreads();
+    float r[4] = {0.f, 0.f, 0.f, 0.f}, fm[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t i = threadIdx.x; i < j.npts; i += 256) {
+        float B[kNBasis];
+        basis_at(i, j.N, B);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            float v = 0.f;
+#pragma unroll
+            for (int b = 0; b < kNBasis; ++b) v = fmaf(c[mu * kNBasis + b], B[b], v);
+            const float F = j.F[mu * j.npts + i];
+            r[mu] = fmaxf(r[mu], fabsf(F - v));
+            fm[mu] = fmaxf(fm[mu], fabsf(F));
+        }
+    }
+    __shared__ float red[256];
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        const float x = block_max<256>(r[mu], red);
+        const float y = block_max<256>(fm[mu], red);
+        if (threadIdx.x == 0) {
+            j.resid[mu] = x;
+            j.resid[4 + mu] = y;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_budget(BudgetArgs a) {
+    const BudgetJob &j = a.jobs[blockIdx.x];
+    __shared__ float red[256];
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        float m = 0.f;
+        for (int64_t i = threadIdx.x; i < j.npts; i += 256) m = fmaxf(m, fabsf(j.out[mu * j.npts + i]));
+        m = block_max<256>(m, red);
+        if (threadIdx.x == 0) j.budget[mu] = j.scale * m;
+    }
+}
+
+// Grid over points; every thread walks the jobs in order, so jobs that share
+// a target never write the same element concurrently.
+__global__ __launch_bounds__(256) void k_correct(CorrArgs a) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    for (int jj = 0; jj < a.n_jobs; ++jj) {
+        const CorrJob &j = a.jobs[jj];
+        bool bad = false;
+        if (j.active)
+            for (int mu = 0; mu < 4; ++mu) bad |= j.resid[mu] > j.budget[mu];
+        if (i == 0) j.fail[0] = bad ? 1 : 0;
+        const int64_t npts = int64_t(j.N[0]) * j.N[1] * j.N[2];
+        if (!bad || i >= npts) continue;
+        float B[kNBasis];
+        basis_at(i, j.N, B);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            float v = 0.f;
+#pragma unroll
+            for (int b = 0; b < kNBasis; ++b) v = fmaf(j.pc[mu * kNBasis + b], B[b], v);
+            j.out[mu * npts + i] += j.F[mu * npts + i] - v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+void launch_moments(const MomentArgs &a, hipStream_t st) {
+    if (a.n_jobs == 0) return;
+    hipLaunchKernelGGL(k_moments_partial, dim3(kMomChunks, a.n_jobs), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_moments_final, dim3(a.n_jobs), dim3(64), 0, st, a);
+}
+
+void launch_features(const FeatArgs &a, hipStream_t st) {
+    if (a.n_pairs == 0) return;
+    hipLaunchKernelGGL(k_features, dim3(a.n_pairs), dim3(128), 0, st, a);
+}
+
+void launch_xform(const XformArgs &a, hipStream_t st) {
+    if (a.n == 0) return;
+    hipLaunchKernelGGL(k_xform, dim3(a.n), dim3(128), 0, st, a);
+}
+
+void launch_coef_sum(const CoefArgs &a, hipStream_t st) {
+    if (a.n_targets == 0) return;
+    hipLaunchKernelGGL(k_coef_sum, dim3(a.n_targets), dim3(128), 0, st, a);
+}
+
+void launch_synthesize(const SynthArgs &a, hipStream_t st) {
+    if (a.n_jobs == 0) return;
+    hipLaunchKernelGGL(k_synthesize, dim3(128, a.n_jobs), dim3(256), 0, st, a);
+}
+
+void launch_project(const ProjArgs &a, bool fit, hipStream_t st) {
+    if (a.n_jobs == 0) return;
+    if (fit) hipLaunchKernelGGL(k_project, dim3(kNBasis, a.n_jobs), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_residual, dim3(a.n_jobs), dim3(256), 0, st, a);
+}
+
+void launch_budget(const BudgetArgs &a, hipStream_t st) {
+    if (a.n_jobs == 0) return;
+    hipLaunchKernelGGL(k_budget, dim3(a.n_jobs), dim3(256), 0, st, a);
+}
+
+void launch_correct(const CorrArgs &a, hipStream_t st) {
+    if (a.n_jobs == 0 || a.max_pts == 0) return;
+    hipLaunchKernelGGL(k_correct, dim3(unsigned((a.max_pts + 255) / 256)), dim3(256), 0, st, a);
+}
+
+}  // namespace rpot

@@ -156,6 +156,76 @@ class Plan:
         """Replay the captured step as step `step`."""
         _lib.check(self._lib, self._h, self._lib.rp_launch_step(self._h, int(step)))
 
+    # -- far-pair surrogate --------------------------------------------------
+    def surrogate_configure(self, far_factor, n_lags=64, audit=()):
+        """Far pairs (centre distance > far_factor x the larger box diagonal)
+        leave the plain lag sum; `audit` sources keep their plain history.
+        Call before bind(); far_factor <= 0 switches the surrogate off."""
+        aud = np.ascontiguousarray(list(audit), dtype=np.int32)
+        ptr = aud.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if aud.size else None
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_configure(
+            self._h, float(far_factor), int(n_lags), ptr, int(aud.size)))
+
+    def surrogate_info(self) -> dict:
+        v = [ctypes.c_int32() for _ in range(4)]
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_info(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("n_far", "n_audited", "n_in", "n_out"), (int(x.value) for x in v)))
+
+    def surrogate_pairs(self) -> dict:
+        n = self.surrogate_info()["n_far"]
+        t, s, a, f = (np.zeros(max(n, 1), np.int32) for _ in range(4))
+        d = np.zeros(max(n, 1), np.float64)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_pairs(
+            self._h, t.ctypes.data_as(i32p), s.ctypes.data_as(i32p),
+            d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.ctypes.data_as(i32p), f.ctypes.data_as(i32p)))
+        return {"target": t[:n], "source": s[:n], "dist": d[:n], "audited": a[:n].astype(bool),
+                "fallen_back": f[:n].astype(bool)}
+
+    def surrogate_attach(self, mlp, in_scale=None, out_scale=None):
+        """Use `mlp` (an Mlp, or None to detach) for the far pairs of every later step."""
+        fp = ctypes.POINTER(ctypes.c_float)
+        if mlp is None:
+            _lib.check(self._lib, self._h, self._lib.rp_surrogate_attach(self._h, None, None, None))
+            self._mlp = None
+            return
+        ins = np.ascontiguousarray(in_scale, dtype=np.float32)
+        outs = np.ascontiguousarray(out_scale, dtype=np.float32)
+        if ins.shape != (22,) or outs.shape != (80,):
+            raise ValueError("in_scale must have 22 and out_scale 80 entries")
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_attach(
+            self._h, mlp._h, ins.ctypes.data_as(fp), outs.ctypes.data_as(fp)))
+        self._mlp = mlp
+
+    def surrogate_features(self, out=None):
+        """Network inputs [n_far][n_in] (FP32, device) of the last completed step."""
+        import torch
+        info = self.surrogate_info()
+        x = out if out is not None else torch.empty((info["n_far"], info["n_in"]), dtype=torch.float32,
+                                                     device="cuda")
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_features(self._h, ctypes.c_void_p(x.data_ptr())))
+        return x
+
+    def surrogate_pair_response(self):
+        """Plain pair responses of the audited far pairs at the last completed
+        step: (frame coefficients [n_aud][80], residuals [n_aud][8]) on the device."""
+        import torch
+        na = self.surrogate_info()["n_audited"]
+        coef = torch.zeros((max(na, 1), 80), dtype=torch.float32, device="cuda")
+        resid = torch.zeros((max(na, 1), 8), dtype=torch.float32, device="cuda")
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_pair_response(
+            self._h, ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(resid.data_ptr())))
+        return coef[:na], resid[:na]
+
+    def surrogate_judge(self, outputs, tol):
+        """Judge the active audited far pairs of the last step against the plain
+        sum; returns (pairs that fell back, largest error / budget)."""
+        arr = self._ptrs(outputs)
+        nf, worst = ctypes.c_int32(), ctypes.c_double()
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_judge(self._h, arr, float(tol), ctypes.byref(nf),
+                                                                    ctypes.byref(worst)))
+        return int(nf.value), float(worst.value)
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.rp_plan_destroy(self._h)

@@ -1,0 +1,206 @@
+"""Far-pair surrogate on the GPU, through the C-ABI: network inputs and plain
+pair responses against the FP64 oracle, far pairs left out when no network is
+attached, the judge's fallback to the plain lag sum, and graph replay."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import surrogate_ref as sr
+from oracle.ref import contrib, self_cell_c1
+from gpu_helpers import GpuSourceGen, log, rel_err
+from synth import sources as sy
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N_LAGS = 16
+FAR = 3.0
+
+
+def far_system(seed=0, n=8, h=0.5):
+    """Five 8^3 boxes: a close pair (0, 1) and three boxes 40-70 bohr away."""
+    rng = np.random.default_rng(seed)
+    cents = [(0, 0, 0), (8, 0, 0), (40, 5, -3), (-10, 45, 12), (25, -30, 50)]
+    doms = []
+    for c in cents:
+        d = sy.Domain((n, n, n), np.array(c, float) - 0.5 * (n - 1) * h)
+        lo, hi = d.origin, d.origin + h * (n - 1)
+        for _ in range(2):
+            d.charges.append(sy.Charge("pair", rng.uniform(0.8, 1.2), rng.uniform(lo, hi), rng.uniform(lo, hi),
+                                       ("cos", rng.uniform(0.3, 1.0), rng.uniform(0.5, 2.0), rng.uniform(0, 6.3))))
+        doms.append(d)
+    return sy.System(h, 0.02, sy.C_AU, doms)
+
+
+def make_plan(system, audit=None, precision="fp32"):
+    from paper_2311_15429_amd import plan_for_system
+    p = plan_for_system(system, precision, stream=torch.cuda.current_stream())
+    p.surrogate_configure(FAR, n_lags=N_LAGS, audit=range(len(system.domains)) if audit is None else audit)
+    p.bind()
+    p.set_green_kernels()
+    return p
+
+
+def run(p, gen, L, outs=None, each=None):
+    outs = outs or [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in p.dims]
+    for l in range(L + 1):
+        p.push_sources(l, gen.step(l))
+        p.retarded_step(l, outs)
+        if each:
+            each(l, outs)
+    return outs
+
+
+def pair_field(system, S, s, n, l):
+    """Oracle: dynamic contribution [4][N_s] of source n to target s at step l."""
+    h = system.h
+    pts = sr.grid_points(system.domains[s], h)
+    out = np.zeros((len(pts), 4))
+    hist = S[n]
+    contrib(pts, None, system.domains[n], h, hist[1:], 1, hist.shape[0] - 1, hist[0], l * system.dt, system.dt,
+            system.c, True, self_cell_c1(), out)
+    return out.T.copy()
+
+
+def test_features_match_oracle():
+    system = far_system(1)
+    L = 40
+    S = sy.sample_sources(system, range(L + 1))
+    p = make_plan(system)
+    run(p, GpuSourceGen(system, torch.float32), L)
+    x = p.surrogate_features().double().cpu().numpy()
+    pairs = p.surrogate_pairs()
+    worst = 0.0
+    for f, (s, n) in enumerate(zip(pairs["target"], pairs["source"])):
+        want = sr.features(system, S, int(s), int(n), L, N_LAGS)
+        mom = slice(0, N_LAGS * 22)
+        scale = np.max(np.abs(want[mom]))
+        assert scale > 0
+        e = np.max(np.abs(x[f, mom] - want[mom])) / scale
+        worst = max(worst, e)
+        assert np.allclose(x[f, -2:], want[-2:], rtol=1e-6, atol=1e-7)
+    assert worst < 2e-5, worst
+    log(f"features: {len(pairs['target'])} far pairs, worst rel err {worst:.2e}")
+    p.close()
+
+
+def test_pair_response_matches_oracle():
+    system = far_system(2)
+    L = 36
+    S = sy.sample_sources(system, range(L + 1))
+    p = make_plan(system)
+    run(p, GpuSourceGen(system, torch.float32), L)
+    coef, resid = p.surrogate_pair_response()
+    coef, resid = coef.double().cpu().numpy(), resid.double().cpu().numpy()
+    pairs = p.surrogate_pairs()
+    aud = np.nonzero(pairs["audited"])[0]
+    worst = 0.0
+    for v, f in enumerate(aud):
+        s, n = int(pairs["target"][f]), int(pairs["source"][f])
+        F = pair_field(system, S, s, n, L)
+        a = sr.frame_fit(system, s, n, F)
+        G = sr.frame_synth(system, s, n, a)
+        e = np.max(np.abs(coef[v] - a.ravel())) / np.max(np.abs(a))
+        worst = max(worst, e)
+        fmax = np.max(np.abs(F), axis=1)
+        assert np.allclose(resid[v, 4:], fmax, rtol=1e-4, atol=1e-6 * fmax.max())
+        fit = np.max(np.abs(F - G), axis=1)
+        assert np.all(np.abs(resid[v, :4] - fit) <= 1e-4 * fmax.max() + 1e-3 * fit)
+    assert worst < 1e-4, worst
+    log(f"pair responses: {len(aud)} audited pairs, worst coefficient rel err {worst:.2e}")
+    p.close()
+
+
+def test_far_pairs_dropped_without_network():
+    """No network attached: the output is the full result minus the far pairs'
+    dynamic terms (their static terms stay)."""
+    system = far_system(3)
+    L = 30
+    S = sy.sample_sources(system, range(L + 1))
+    p = make_plan(system, audit=[])
+    outs = run(p, GpuSourceGen(system, torch.float32), L)
+    got = [o.double().cpu().numpy().reshape(4, -1) for o in outs]
+    ref = oracle.potential_full(system, S, [L])[0]
+    pairs = p.surrogate_pairs()
+    for s, n in zip(pairs["target"], pairs["source"]):
+        ref[int(s)] = ref[int(s)] - pair_field(system, S, int(s), int(n), L)
+    e = rel_err(got, ref)
+    assert np.all(e <= 2e-5), e
+    p.close()
+
+
+def _random_mlp(n_in, n_far, scale=0.05, seed=0):
+    from paper_2311_15429_amd.mlp import Mlp
+    m = Mlp(n_in, 32, 80, max(n_far, 1))
+    g = torch.Generator().manual_seed(seed)
+    m.set_params(torch.randn(m.n_params, generator=g) * scale)
+    return m
+
+
+def test_judge_falls_back_and_then_matches_the_plain_method():
+    system = far_system(4)
+    L, Lj = 34, 24
+    S = sy.sample_sources(system, range(L + 1))
+    p = make_plan(system)
+    info = p.surrogate_info()
+    mlp = _random_mlp(info["n_in"], info["n_far"])
+    p.surrogate_attach(mlp, np.full(22, 1.0, np.float32), np.full(80, 1e-3, np.float32))
+    gen = GpuSourceGen(system, torch.float32)
+    outs = [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in p.dims]
+    got = {}
+    for l in range(L + 1):
+        p.push_sources(l, gen.step(l))
+        p.retarded_step(l, outs)
+        if l == Lj - 1:
+            nf, worst = p.surrogate_judge(outs, 1e3)       # loose: nobody falls back
+            assert nf == 0 and 0 < worst < 1
+        if l == Lj:
+            nf, worst = p.surrogate_judge(outs, 1e-6)      # tight: every audited pair falls back
+            assert nf == info["n_far"] and worst > 1
+            assert p.surrogate_pairs()["fallen_back"].all()
+        if l >= Lj:
+            got[l] = [o.double().cpu().numpy().reshape(4, -1) for o in outs]
+    ref = oracle.potential_full(system, S, sorted(got))
+    for (l, g), r in zip(sorted(got.items()), ref):
+        e = rel_err(g, r)
+        assert np.all(e <= 2e-5), (l, e)
+    log(f"judge: {info['n_far']} pairs fell back; steps {Lj}..{L} match the oracle")
+    p.surrogate_attach(None)
+    p.close()
+    mlp.close()
+
+
+def test_graph_replay_with_surrogate_is_bitwise_identical():
+    system = far_system(5)
+    L = 20
+    gen = GpuSourceGen(system, torch.float32)
+    res = []
+    for capture in (False, True):
+        p = make_plan(system, audit=[2])
+        info = p.surrogate_info()
+        mlp = _random_mlp(info["n_in"], info["n_far"], seed=7)
+        p.surrogate_attach(mlp, np.full(22, 0.5, np.float32), np.full(80, 1e-3, np.float32))
+        outs = [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in p.dims]
+        buf = [torch.empty_like(o) for o in outs]
+        p.push_sources(0, gen.step(0))
+        p.retarded_step(0, outs)
+        if capture:
+            p.capture_step(buf, outs)
+        seq = []
+        for l in range(1, L + 1):
+            if capture:
+                for b, x in zip(buf, gen.step(l)):
+                    b.copy_(x)
+                p.launch_step(l)
+            else:
+                p.push_sources(l, gen.step(l))
+                p.retarded_step(l, outs)
+            torch.cuda.synchronize()
+            seq.append([o.cpu().numpy().copy() for o in outs])
+        res.append(seq)
+        p.surrogate_attach(None)
+        p.close()
+        mlp.close()
+    for a, b in zip(*res):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)

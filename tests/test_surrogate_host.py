@@ -1,0 +1,111 @@
+"""Host-side planning of the far-pair surrogate through the C-ABI (no GPU):
+far-pair classification, ring depths, stored spectra, lag-sum bytes, the
+network input size and the error paths."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import surrogate_ref as sr
+from synth import sources as sy
+
+pytest.importorskip("paper_2311_15429_amd")
+from paper_2311_15429_amd import Plan, RpotError, plan_for_system  # noqa: E402
+
+
+def _system(n=8, h=0.5):
+    """Five 8^3 boxes: a close pair (0, 1) and three far boxes."""
+    cents = [(0, 0, 0), (8, 0, 0), (40, 5, -3), (-10, 45, 12), (25, -30, 50)]
+    doms = [sy.Domain((n, n, n), np.array(c, float) - 0.5 * (n - 1) * h) for c in cents]
+    return sy.System(h, 0.02, sy.C_AU, doms)
+
+
+def _expected_far(system, factor):
+    h = system.h
+    far = set()
+    for s, ds in enumerate(system.domains):
+        for m, dn in enumerate(system.domains):
+            if s == m:
+                continue
+            d = np.linalg.norm(sr.box_centre(ds, h) - sr.box_centre(dn, h))
+            if d > factor * max(sr.box_diagonal(ds, h), sr.box_diagonal(dn, h)):
+                far.add((s, m))
+    return far
+
+
+def test_classification_depths_and_bytes():
+    system = _system()
+    plain = plan_for_system(system, "fp32")
+    base = plain.stats()
+    depth_plain = [plain.info(0, n)[3] for n in range(5)]
+    p = plan_for_system(system, "fp32")
+    p.surrogate_configure(3.0, n_lags=16, audit=[2])
+    info = p.surrogate_info()
+    far = _expected_far(system, 3.0)
+    assert info["n_far"] == len(far) > 0
+    assert info["n_in"] == 16 * 22 + 2 and info["n_out"] == 80
+    pairs = p.surrogate_pairs()
+    got = set(zip(pairs["target"].tolist(), pairs["source"].tolist()))
+    assert got == far
+    assert info["n_audited"] == sum(1 for (s, n) in far if n == 2)
+    assert np.array_equal(pairs["audited"], pairs["source"] == 2)
+    assert not pairs["fallen_back"].any()
+    for t, n, d in zip(pairs["target"], pairs["source"], pairs["dist"]):
+        want = np.linalg.norm(sr.box_centre(system.domains[t], system.h) - sr.box_centre(system.domains[n], system.h))
+        assert abs(d - want) < 1e-12
+    # depth: a non-audited source keeps only what its near pairs need
+    for n in range(5):
+        lo_hi = [p.info(s, n)[:2] for s in range(5) if (s, n) not in far or n == 2]
+        assert p.info(0, n)[3] == max(hi for _, hi in lo_hi) + 1
+        assert p.info(0, n)[3] <= depth_plain[n]
+    assert p.info(0, 2)[3] == depth_plain[2]
+    st = p.stats()
+    assert st["lagsum_bytes"] < base["lagsum_bytes"]
+    assert st["spectra_bytes"] < base["spectra_bytes"]
+    assert st["ring_bytes"] < base["ring_bytes"]
+    # switching off restores the plain plan
+    p.surrogate_configure(0.0)
+    assert p.surrogate_info()["n_far"] == 0
+    assert p.stats()["lagsum_bytes"] == base["lagsum_bytes"]
+    assert [p.info(0, n)[3] for n in range(5)] == depth_plain
+    p.close()
+    plain.close()
+
+
+def test_error_paths():
+    system = _system()
+    p64 = plan_for_system(system, "fp64")
+    with pytest.raises(RpotError) as e:
+        p64.surrogate_configure(3.0)
+    assert e.value.status == "RP_ERR_UNSUPPORTED"
+    p = plan_for_system(system, "fp32")
+    for kw, status in [(dict(n_lags=0), "RP_ERR_ARG"), (dict(n_lags=2000), "RP_ERR_ARG"),
+                       (dict(audit=[7]), "RP_ERR_ARG")]:
+        with pytest.raises(RpotError) as e:
+            p.surrogate_configure(3.0, **kw)
+        assert e.value.status == status
+    with pytest.raises(RpotError) as e:
+        p.surrogate_configure(math.inf)
+    assert e.value.status == "RP_ERR_ARG"
+    # a far target thinner than 4 points per axis cannot carry the cubic basis
+    thin = sy.System(0.5, 0.02, sy.C_AU, [sy.Domain((8, 8, 3), np.zeros(3)),
+                                          sy.Domain((8, 8, 8), np.array([60.0, 0, 0]))])
+    pt = plan_for_system(thin, "fp32")
+    with pytest.raises(RpotError) as e:
+        pt.surrogate_configure(3.0)
+    assert e.value.status == "RP_ERR_UNSUPPORTED"
+    inf = Plan(system.dims, system.origins, system.h, system.dt, math.inf, precision="fp32")
+    with pytest.raises(RpotError) as e:
+        inf.surrogate_configure(3.0)
+    assert e.value.status == "RP_ERR_UNSUPPORTED"
+    for q in (p64, p, pt, inf):
+        q.close()
+
+
+def test_calls_before_bind_report_state():
+    p = plan_for_system(_system(), "fp32")
+    p.surrogate_configure(3.0, n_lags=8, audit=[0, 1, 2, 3, 4])
+    lib = p._lib
+    assert lib.rp_surrogate_features(p._h, None) != 0
+    assert b"not bound" in lib.rp_last_error(p._h) or b"null" in lib.rp_last_error(p._h)
+    p.close()

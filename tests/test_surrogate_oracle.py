@@ -1,0 +1,122 @@
+"""Pins of the surrogate oracle (oracle/surrogate_ref.py) against closed forms
+and invariants: Gaussian moments, charge conservation between the charge and
+current moments, frame orthonormality, rotation invariants, and exact
+reproduction of cubic fields by the least-squares basis fit."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import surrogate_ref as sr
+from synth import sources as sy
+
+
+def _gauss(pts, a, s):
+    d2 = np.sum((pts - a[None, :]) ** 2, axis=1)
+    return (math.pi * s * s) ** -1.5 * np.exp(-d2 / (s * s))
+
+
+def test_gaussian_moments_closed_form():
+    """Normalised Gaussian of width s at a: q = 1, p = a - c,
+    Q = (a - c)(a - c)^T + s^2/2 I; a current v g gives J = v, K = v (a - c)^T."""
+    h, s = 0.25, 0.6
+    dom = sy.Domain((32, 32, 32), np.array([1.0, -2.0, 0.5]))
+    c = sr.box_centre(dom, h)
+    a = c + np.array([0.7, -0.4, 0.9])
+    pts = sr.grid_points(dom, h)
+    g = _gauss(pts, a, s)
+    v = np.array([0.3, -1.1, 0.6])
+    dS = np.vstack([g[None, :], v[:, None] * g[None, :]])
+    m = sr.moments(dS, dom, h)
+    r = a - c
+    Q = np.outer(r, r) + 0.5 * s * s * np.eye(3)
+    want = np.concatenate([[1.0], r, [Q[0, 0], Q[1, 1], Q[2, 2], Q[0, 1], Q[0, 2], Q[1, 2]], v,
+                           np.outer(v, r).ravel()])
+    assert np.max(np.abs(m - want)) < 1e-9
+
+
+def test_current_moment_is_the_dipole_rate():
+    """Charge conservation of the synthetic pair sources: c * J = dp/dt."""
+    h, dt = 0.3, 0.01
+    dom = sy.Domain((40, 40, 40), np.zeros(3))
+    rng = np.random.default_rng(3)
+    lo, hi = np.full(3, 4.0), np.full(3, 7.7)
+    for _ in range(3):
+        dom.charges.append(sy.Charge("pair", rng.uniform(0.8, 1.2), rng.uniform(lo, hi), rng.uniform(lo, hi),
+                                     ("cos", rng.uniform(0.3, 1.0), rng.uniform(0.1, 0.5), rng.uniform(0, 6.3))))
+    system = sy.System(h, dt, sy.C_AU, [dom])
+    l = 50
+    S = sy.sample_sources(system, [0, l - 1, l, l + 1])[0]
+    m = [sr.moments(S[k] - S[0], dom, h) for k in range(4)]
+    dp = (m[3][1:4] - m[1][1:4]) / (2 * dt)
+    cJ = sy.C_AU * sr.moments(S[2], dom, h)[10:13]     # J(l) itself, not J(l) - J(0)
+    assert np.max(np.abs(dp - cJ)) < 2e-4 * np.max(np.abs(cJ))
+    assert abs(m[2][0]) < 1e-9 * np.max(np.abs(m[2][1:4]))        # neutral pairs
+
+
+@pytest.mark.parametrize("d", [(3.0, -1.0, 2.0), (0.1, 0.2, 5.0), (-4.0, 0.0, 0.0), (0.0, 0.0, -2.0)])
+def test_frame_is_right_handed_orthonormal(d):
+    R = sr.frame(d)
+    assert np.allclose(R @ R.T, np.eye(3), atol=1e-14)
+    assert abs(np.linalg.det(R) - 1.0) < 1e-14
+    assert np.allclose(R[0], np.asarray(d) / np.linalg.norm(d), atol=1e-15)
+
+
+def test_rotation_invariants():
+    rng = np.random.default_rng(5)
+    m = rng.normal(size=22)
+    R = sr.frame(rng.normal(size=3))
+    r = sr.rotate(m, R)
+    Q = np.array([[m[4], m[7], m[8]], [m[7], m[5], m[9]], [m[8], m[9], m[6]]])
+    Qr = np.array([[r[4], r[7], r[8]], [r[7], r[5], r[9]], [r[8], r[9], r[6]]])
+    assert r[0] == m[0]
+    assert abs(np.linalg.norm(r[1:4]) - np.linalg.norm(m[1:4])) < 1e-13
+    assert abs(r[1] - m[1:4] @ R[0]) < 1e-13
+    assert abs(np.trace(Qr) - np.trace(Q)) < 1e-13
+    assert abs(np.linalg.norm(Qr) - np.linalg.norm(Q)) < 1e-13
+    assert np.allclose(np.linalg.eigvalsh(Qr), np.linalg.eigvalsh(Q), atol=1e-13)
+    assert abs(np.linalg.norm(r[13:22]) - np.linalg.norm(m[13:22])) < 1e-13
+    # K's antisymmetric part (the magnetic moment) rotates as a vector
+    K, Kr = m[13:22].reshape(3, 3), r[13:22].reshape(3, 3)
+    w = np.array([K[1, 2] - K[2, 1], K[2, 0] - K[0, 2], K[0, 1] - K[1, 0]])
+    wr = np.array([Kr[1, 2] - Kr[2, 1], Kr[2, 0] - Kr[0, 2], Kr[0, 1] - Kr[1, 0]])
+    assert np.allclose(wr, R @ w, atol=1e-13)
+
+
+def _two_box_system(n=(9, 7, 8)):
+    h = 0.4
+    a = sy.Domain(n, np.array([0.0, 0.0, 0.0]))
+    b = sy.Domain((6, 6, 6), np.array([60.0, -35.0, 20.0]))
+    return sy.System(h, 0.02, sy.C_AU, [a, b])
+
+
+def test_frame_fit_reproduces_cubic_fields():
+    """Any field that is a polynomial of total degree <= 3 in position is fitted
+    exactly (the frame basis spans that space on a non-degenerate box), for the
+    scalar and, in frame components, the vector part."""
+    system = _two_box_system()
+    rng = np.random.default_rng(11)
+    pts = sr.grid_points(system.domains[0], system.h)
+    x = (pts - pts.mean(axis=0)) / 2.0
+    mono = [x[:, 0] ** i * x[:, 1] ** j * x[:, 2] ** k for i, j, k in sr.DEGREES]
+    F = np.stack([sum(rng.normal() * f for f in mono) for _ in range(4)])
+    a = sr.frame_fit(system, 0, 1, F)
+    G = sr.frame_synth(system, 0, 1, a)
+    assert np.max(np.abs(G - F)) < 1e-10 * np.max(np.abs(F))
+    # a quartic term is outside the space
+    F4 = F + (x[:, 0] ** 2 * x[:, 1] * x[:, 2])[None, :]
+    G4 = sr.frame_synth(system, 0, 1, sr.frame_fit(system, 0, 1, F4))
+    assert np.max(np.abs(G4 - F4)) > 1e-3
+
+
+def test_features_before_arrival_are_zero_and_geometry_is_exact():
+    system = _two_box_system()
+    L = 8
+    S = sy.sample_sources(system, range(L + 1))
+    _, dist, m_c, frac = sr.pair_geometry(system, 0, 1)
+    assert m_c > L + 16
+    x = sr.features(system, S, 0, 1, L, 16)
+    assert np.all(x[:16 * 22] == 0)
+    assert abs(x[-1] - frac) < 1e-15 and abs(frac) <= 0.5
+    dbar = np.mean([sr.box_diagonal(d, system.h) for d in system.domains])
+    assert abs(x[-2] - 10 * dbar / dist) < 1e-15
