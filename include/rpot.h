@@ -209,11 +209,11 @@ rp_status rp_launch_step(rp_plan plan, int64_t step);
 
 /*
  * Small fully connected network of the far-pair surrogate (training and
- * inference run in this library's kernels):
- *   h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3,
+ * inference run in this library's kernels), two tanh layers and a linear skip:
+ *   h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3 + x Ws,
  *   loss = sum (y - t)^2 / (2 batch n_out).
  * Parameters: one flat FP32 vector [W1 (n_in x H), b1 (H), W2 (H x H), b2 (H),
- * W3 (H x n_out), b3 (n_out)], row-major.  x, t, y are row-major
+ * W3 (H x n_out), b3 (n_out), Ws (n_in x n_out)], row-major.  x, t, y are row-major
  * [batch][n_in] / [batch][n_out] FP32 device arrays; batch <= max_batch.
  * All calls are asynchronous on the stream given at creation; loss and grad
  * outputs are device pointers.  The caller initialises the parameters
@@ -247,12 +247,16 @@ const char *rp_mlp_last_error(rp_mlp mlp);
  * pair keeps a ring of 22 moments of dS = S - S(0) about its centre, weight h^3:
  *   q = sum dS_0, p_i = sum dS_0 x_i, Q_ij = sum dS_0 x_i x_j (xx yy zz xy xz yz),
  *   J_i = sum dS_{1+i}, K_ij = sum dS_{1+i} x_j.
- * The network input of a far pair at step l is, for the n_lags lags
- * m = m_c - n_lags/2 + j (m_c = round(|c_s - c_n| / (c dt))), the moments of
- * step l - m (zero for l - m <= 0) rotated into the pair frame (rows e1 along
- * c_s - c_n, e2, e3) and multiplied by in_scale[22], followed by two geometry
- * values (10 dbar / |c_s - c_n| with dbar the mean box diagonal of the plan,
- * and |c_s - c_n| / (c dt) - m_c): n_in = 22 n_lags + 2.  Its 80 outputs y,
+ * The network input of a far pair at step l is built from H[j][k], the
+ * moments of step l - m for the n_lags lags m = m_c - n_lags/2 + j
+ * (m_c = round(|c_s - c_n| / (c dt)); zero for l - m <= 0) rotated into the
+ * pair frame (rows e1 along c_s - c_n, e2, e3) and multiplied by in_scale[k],
+ * and the pair's geometry g = 10 dbar / |c_s - c_n| (dbar the mean box
+ * diagonal of the plan) and f = |c_s - c_n| / (c dt) - m_c: six blocks
+ * H, g H, f H, g f H, g^2 H, f^2 H (each [n_lags][22]), then g and f:
+ * n_in = 132 n_lags + 2.  (The far coupling is linear in the history with
+ * weights that vary smoothly with g and f; the blocks let the network's
+ * linear skip carry it.)  Its 80 outputs y,
  * times out_scale[80] / |c_s - c_n|, are the coefficients a[mu][b] of the pair's
  * potential component mu (frame components for A) in the tensor-Legendre basis
  * P_i P_j P_k (i + j + k <= 3, lexicographic (i, j, k)) of
@@ -289,7 +293,9 @@ const char *rp_mlp_last_error(rp_mlp mlp);
  *     max |F_mu - fit_mu| for mu < 4, then max |F_mu|.
  * rp_surrogate_judge  judges every active audited far pair of the last
  *     completed step: a pair whose error max_r |F_mu - surrogate_mu| exceeds
- *     tol * max_r |out_s,mu| / (active far pairs of s) in any component falls
+ *     tol * M_mu / (active far pairs of s), M_mu = max |out_mu| over every point
+ *     of the target's system (the norm of the relative error per component),
+ *     in any component falls
  *     back to the plain lag sum from the next step on, and its term in out (the
  *     outputs of that step, corrected in place) is replaced by F.  Returns the
  *     number of pairs that fell back and the largest error/budget ratio over the

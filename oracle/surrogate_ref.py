@@ -15,9 +15,10 @@ first principles:
 * the pair frame: e1 along c_target - c_source, e2 the unit part of a reference
   axis (z, or x when e1 is within 25.8 degrees of z) orthogonal to e1,
   e3 = e1 x e2;
-* the network input of a pair at step l: moments of steps l - m for the lags
-  m = m_c - n_lags/2 + j, rotated into the frame (vectors R v, tensors R T R^T),
-  then (10 dbar / |d|, |d|/(c dt) - m_c);
+* the network input of a pair at step l: H = moments of steps l - m for the
+  lags m = m_c - n_lags/2 + j, rotated into the frame (vectors R v, tensors
+  R T R^T); with g = 10 dbar / |d| and f = |d|/(c dt) - m_c the six blocks
+  H, g H, f H, g f H, g^2 H, f^2 H, then g and f;
 * the cubic tensor-Legendre basis P_i(x) P_j(y) P_k(z), i + j + k <= 3, and the
   least-squares coefficients of a field on the target grid in the frame
   variables u = R (r - c_target) / ell (A components taken in the frame).
@@ -34,6 +35,7 @@ import numpy as np
 DEGREES = [(i, j, k) for i in range(4) for j in range(4) for k in range(4) if i + j + k <= 3]
 N_FEAT = 22
 N_GEO = 2
+N_BLOCKS = 6
 
 
 def grid_points(dom, h):
@@ -104,16 +106,16 @@ def features(system, samples, s, n, l, n_lags):
     d, dist, m_c, frac = pair_geometry(system, s, n)
     R = frame(d)
     dom = system.domains[n]
-    x = np.zeros(n_lags * N_FEAT + N_GEO)
+    H = np.zeros((n_lags, N_FEAT))
     for j in range(n_lags):
         m = m_c - n_lags // 2 + j
         t = l - m
         if t > 0 and m >= 0:
-            x[j * N_FEAT:(j + 1) * N_FEAT] = rotate(moments(samples[n][t] - samples[n][0], dom, h), R)
+            H[j] = rotate(moments(samples[n][t] - samples[n][0], dom, h), R)
     dbar = np.mean([box_diagonal(dm, h) for dm in system.domains])
-    x[n_lags * N_FEAT] = 10.0 * dbar / dist
-    x[n_lags * N_FEAT + 1] = frac
-    return x
+    g, f = 10.0 * dbar / dist, frac
+    blocks = [H, g * H, f * H, g * f * H, g * g * H, f * f * H]
+    return np.concatenate([b.ravel() for b in blocks] + [[g, f]])
 
 
 def legendre(x):

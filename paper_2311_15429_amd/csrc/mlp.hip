@@ -1,17 +1,20 @@
 // Small fully connected network for the far-pair surrogate: training and
 // inference kernels and their C-ABI (rp_mlp_*).
 //
-//   h1 = tanh(x W1 + b1),  h2 = tanh(h1 W2 + b2),  y = h2 W3 + b3
+//   h1 = tanh(x W1 + b1),  h2 = tanh(h1 W2 + b2),  y = h2 W3 + b3 + x Ws
 //   loss = sum (y - t)^2 / (2 B n_out)
 //
-// Parameters are one flat FP32 vector [W1 (n_in x H), b1 (H), W2 (H x H),
-// b2 (H), W3 (H x n_out), b3 (n_out)], row-major, in the bound workspace.
+// The linear skip x Ws carries the part of the map that is linear in the
+// inputs; the two tanh layers learn the rest.  Parameters are one flat FP32
+// vector [W1 (n_in x H), b1 (H), W2 (H x H), b2 (H), W3 (H x n_out),
+// b3 (n_out), Ws (n_in x n_out)], row-major, in the bound workspace.
 // Matrix products run in one LDS-tiled FP32 kernel (64 x 64 output tile,
 // 16-deep K slices, 4 x 4 outputs per thread) with strided operands, so the
 // transposed products of the backward pass need no copies.
 #include "rpot.h"
 #include "rpot_internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -23,6 +26,7 @@ namespace {
 
 constexpr int kGT = 64;   // output tile
 constexpr int kGK = 16;   // K slice
+constexpr int kMaxSplit = 16;   // K splits of a product with few output tiles
 
 struct GemmArgs {
     const float *A;        // A(i, k) = A[i * sa0 + k * sa1]
@@ -33,6 +37,8 @@ struct GemmArgs {
     int M, N, K;
     int act;               // 0 none, 1 tanh
     float beta;            // C = beta * C + A B
+    int ks;                // split-K: K columns per split (blockIdx.z), 0 = no split
+    float *part;           // split-K: raw partial products [split][M][N]
 };
 
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
@@ -40,14 +46,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     __shared__ float Bs[kGK][kGT + 4];
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int i0 = blockIdx.y * kGT, j0 = blockIdx.x * kGT;
+    const int kb = g.ks ? int(blockIdx.z) * g.ks : 0;
+    const int ke = g.ks ? min(g.K, kb + g.ks) : g.K;
     float acc[4][4] = {};
-    for (int k0 = 0; k0 < g.K; k0 += kGK) {
+    for (int k0 = kb; k0 < ke; k0 += kGK) {
         for (int e = threadIdx.x; e < kGK * kGT; e += 256) {
             const int kk = e / kGT, ii = e % kGT;
             const int i = i0 + ii, k = k0 + kk;
-            As[kk][ii] = (i < g.M && k < g.K) ? g.A[i * g.sa0 + k * g.sa1] : 0.f;
+            As[kk][ii] = (i < g.M && k < ke) ? g.A[i * g.sa0 + k * g.sa1] : 0.f;
             const int j = j0 + ii;
-            Bs[kk][ii] = (j < g.N && k < g.K) ? g.B[k * g.sb0 + j * g.sb1] : 0.f;
+            Bs[kk][ii] = (j < g.N && k < ke) ? g.B[k * g.sb0 + j * g.sb1] : 0.f;
         }
         __syncthreads();
 #pragma unroll
@@ -72,6 +80,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         for (int c = 0; c < 4; ++c) {
             const int j = j0 + tx * 4 + c;
             if (j >= g.N) continue;
+            if (g.part) {
+                g.part[(int64_t(blockIdx.z) * g.M + i) * g.N + j] = acc[r][c];
+                continue;
+            }
             float v = acc[r][c];
             if (g.bias) v += g.bias[j];
             if (g.beta != 0.f) v += g.beta * g.C[int64_t(i) * g.ldc + j];
@@ -81,11 +93,42 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     }
 }
 
+// C = act(beta C + sum over splits of part + bias), fixed summation order
+__global__ void k_splitk_reduce(GemmArgs g, int splits) {
+    const int64_t n = int64_t(g.M) * g.N;
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) {
+        const int i = int(e / g.N), j = int(e - int64_t(i) * g.N);
+        float v = 0.f;
+        for (int z = 0; z < splits; ++z) v += g.part[int64_t(z) * n + e];
+        if (g.bias) v += g.bias[j];
+        if (g.beta != 0.f) v += g.beta * g.C[int64_t(i) * g.ldc + j];
+        if (g.act == 1) v = tanhf(v);
+        g.C[int64_t(i) * g.ldc + j] = v;
+    }
+}
+
+// C (M x N) = act(beta C + A B + bias).  With split_buf (room for
+// kMaxSplit x M x N floats) a product with few output tiles and a long K is
+// split along K over blockIdx.z, then reduced.
 void gemm(hipStream_t st, const float *A, int64_t sa0, int64_t sa1, const float *B, int64_t sb0, int64_t sb1,
-          float *C, int64_t ldc, int M, int N, int K, const float *bias, int act, float beta) {
-    GemmArgs g{A, B, C, bias, sa0, sa1, sb0, sb1, ldc, M, N, K, act, beta};
-    dim3 grid((N + kGT - 1) / kGT, (M + kGT - 1) / kGT);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+          float *C, int64_t ldc, int M, int N, int K, const float *bias, int act, float beta,
+          float *split_buf = nullptr) {
+    GemmArgs g{A, B, C, bias, sa0, sa1, sb0, sb1, ldc, M, N, K, act, beta, 0, nullptr};
+    const int gx = (N + kGT - 1) / kGT, gy = (M + kGT - 1) / kGT;
+    int splits = 1;
+    if (split_buf) splits = std::min({kMaxSplit, std::max(1, 1024 / (gx * gy)), std::max(1, K / 256)});
+    if (splits <= 1) {
+        hipLaunchKernelGGL(k_gemm, dim3(gx, gy), dim3(256), 0, st, g);
+        return;
+    }
+    g.ks = ((K + splits - 1) / splits + kGK - 1) / kGK * kGK;
+    splits = (K + g.ks - 1) / g.ks;
+    g.part = split_buf;
+    hipLaunchKernelGGL(k_gemm, dim3(gx, gy, splits), dim3(256), 0, st, g);
+    g.part = split_buf;
+    const int64_t n = int64_t(M) * N;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(unsigned(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256), 0, st, g,
+                       splits);
 }
 
 // dy = (y - t) / (B n_out); loss partial sums per block
@@ -165,7 +208,7 @@ struct rp_mlp_s {
     size_t ws_bytes = 0;
     int64_t n_params = 0;
     size_t off_w = 0, off_g = 0, off_m = 0, off_v = 0, off_h1 = 0, off_h2 = 0, off_y = 0, off_dy = 0, off_d2 = 0,
-           off_d1 = 0, off_part = 0;
+           off_d1 = 0, off_part = 0, off_split = 0;
     int64_t step = 0;
     std::string err;
     float *W1() { return f(off_w); }
@@ -174,6 +217,7 @@ struct rp_mlp_s {
     float *b2() { return W2() + int64_t(H) * H; }
     float *W3() { return b2() + H; }
     float *b3() { return W3() + int64_t(H) * n_out; }
+    float *Ws() { return b3() + n_out; }
     float *f(size_t off) { return reinterpret_cast<float *>(ws + off); }
 };
 
@@ -216,9 +260,11 @@ void check_batch(rp_mlp m, int batch) {
 
 void forward(rp_mlp m, const float *x, int B, float *y, hipStream_t st) {
     const int H = m->H;
-    gemm(st, x, m->n_in, 1, m->W1(), H, 1, m->f(m->off_h1), H, B, H, m->n_in, m->b1(), 1, 0.f);
+    float *sp = m->f(m->off_split);
+    gemm(st, x, m->n_in, 1, m->W1(), H, 1, m->f(m->off_h1), H, B, H, m->n_in, m->b1(), 1, 0.f, sp);
     gemm(st, m->f(m->off_h1), H, 1, m->W2(), H, 1, m->f(m->off_h2), H, B, H, H, m->b2(), 1, 0.f);
     gemm(st, m->f(m->off_h2), H, 1, m->W3(), m->n_out, 1, y, m->n_out, B, m->n_out, H, m->b3(), 0, 0.f);
+    gemm(st, x, m->n_in, 1, m->Ws(), m->n_out, 1, y, m->n_out, B, m->n_out, m->n_in, nullptr, 0, 1.f, sp);
 }
 
 // Loss into *loss_dev and the gradient of every parameter into grad (flat).
@@ -233,7 +279,9 @@ void loss_grad(rp_mlp m, const float *x, const float *t, int B, float *loss_dev,
     hipLaunchKernelGGL(k_mse_grad, dim3(nb), dim3(256), 0, st, y, t, dy, ny, 1.f / float(ny), m->f(m->off_part));
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, m->f(m->off_part), nb, 0.5f / float(ny), loss_dev);
     float *gW1 = grad, *gb1 = gW1 + int64_t(ni) * H, *gW2 = gb1 + H, *gb2 = gW2 + int64_t(H) * H;
-    float *gW3 = gb2 + H, *gb3 = gW3 + int64_t(H) * no;
+    float *gW3 = gb2 + H, *gb3 = gW3 + int64_t(H) * no, *gWs = gb3 + no;
+    // skip: gWs = x^T dy
+    gemm(st, x, 1, ni, dy, no, 1, gWs, no, ni, no, B, nullptr, 0, 0.f);
     // layer 3: gW3 = h2^T dy, gb3 = colsum dy, d2 = dy W3^T
     gemm(st, h2, 1, H, dy, no, 1, gW3, no, H, no, B, nullptr, 0, 0.f);
     hipLaunchKernelGGL(k_colsum, dim3((no + 255) / 256), dim3(256), 0, st, dy, B, no, gb3);
@@ -286,7 +334,7 @@ rp_status rp_mlp_create(rp_mlp *out, int32_t n_in, int32_t n_hidden, int32_t n_o
     m->max_batch = max_batch;
     m->stream = static_cast<hipStream_t>(hip_stream);
     m->n_params = int64_t(n_in) * n_hidden + n_hidden + int64_t(n_hidden) * n_hidden + n_hidden +
-                  int64_t(n_hidden) * n_out + n_out;
+                  int64_t(n_hidden) * n_out + n_out + int64_t(n_in) * n_out;
     size_t off = 0;
     auto alloc = [&](size_t bytes) {
         const size_t o = off;
@@ -305,6 +353,7 @@ rp_status rp_mlp_create(rp_mlp *out, int32_t n_in, int32_t n_hidden, int32_t n_o
     m->off_d2 = alloc(BH);
     m->off_d1 = alloc(BH);
     m->off_part = alloc(256 * 4 + 16);
+    m->off_split = alloc(size_t(kMaxSplit) * max_batch * std::max(n_hidden, n_out) * 4);
     m->ws_bytes = off;
     *out = m;
     return RP_OK;

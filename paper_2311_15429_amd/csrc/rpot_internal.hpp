@@ -225,6 +225,7 @@ constexpr int kFeatStride = 24;   // floats per moment-ring slot
 constexpr int kNBasis = 20;       // tensor-Legendre functions of total degree <= 3
 constexpr int kNOut = 4 * kNBasis;
 constexpr int kNGeo = 2;          // geometry features of a pair
+constexpr int kNBlocks = 6;       // history blocks H, gH, fH, gfH, g^2 H, f^2 H
 constexpr int kMomChunks = 64;    // partial sums per source
 
 struct MomentJob {

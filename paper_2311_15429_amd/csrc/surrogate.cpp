@@ -522,7 +522,7 @@ void sur_configure(rp_plan p, double far_factor, int n_lags, const int32_t *audi
         U.on = true;
         U.far_factor = far_factor;
         U.n_lags = n_lags;
-        U.n_in = n_lags * kNFeat + kNGeo;
+        U.n_in = kNBlocks * n_lags * kNFeat + kNGeo;
         U.audit = aud;
     }
     sur_classify(p);
@@ -610,22 +610,37 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
     int fell = 0;
     double w = 0.0;
     if (na > 0) {
-        // per-target budgets: tol * max |P_s| / (active far pairs of s)
-        std::vector<int> ts;
-        for (int s : U.synth_targets)
-            if (active_far(p, s) > 0) ts.push_back(s);
-        for (size_t j0 = 0; j0 < ts.size(); j0 += kMaxJobs) {
+        // per-pair budget: tol * (max |P_mu| over the target's system) / (active far pairs of the target),
+        // so that by the triangle inequality the system's error stays within tol per component
+        std::vector<int> all(p->n_dom);
+        for (int i = 0; i < p->n_dom; ++i) all[i] = i;
+        for (size_t j0 = 0; j0 < all.size(); j0 += kMaxJobs) {
             BudgetArgs ba{};
-            ba.n_jobs = int(std::min<size_t>(kMaxJobs, ts.size() - j0));
+            ba.n_jobs = int(std::min<size_t>(kMaxJobs, all.size() - j0));
             for (int j = 0; j < ba.n_jobs; ++j) {
-                const int s = ts[j0 + j];
+                const int s = all[j0 + j];
                 ba.jobs[j].out = static_cast<const float *>(out[s]);
                 ba.jobs[j].budget = p->at<float>(U.off_budget) + size_t(s) * 4;
                 ba.jobs[j].npts = p->dom[s].npts;
-                ba.jobs[j].scale = float(tol / active_far(p, s));
+                ba.jobs[j].scale = 1.0f;
             }
             launch_budget(ba, st);
         }
+        check_launch();
+        std::vector<float> amax(size_t(p->n_dom) * 4), bud(size_t(p->n_dom) * 4, 0.f);
+        HIP_OK(hipStreamSynchronize(st));
+        HIP_OK(hipMemcpy(amax.data(), p->ws + U.off_budget, amax.size() * 4, hipMemcpyDeviceToHost));
+        std::vector<float> smax(p->sys.size() * 4, 0.f);
+        for (int i = 0; i < p->n_dom; ++i)
+            for (int mu = 0; mu < 4; ++mu)
+                smax[size_t(p->dom[i].sys) * 4 + mu] = std::max(smax[size_t(p->dom[i].sys) * 4 + mu], amax[size_t(i) * 4 + mu]);
+        for (int s : U.synth_targets) {
+            const int na_s = active_far(p, s);
+            if (na_s == 0) continue;
+            for (int mu = 0; mu < 4; ++mu)
+                bud[size_t(s) * 4 + mu] = float(tol * smax[size_t(p->dom[s].sys) * 4 + mu] / na_s);
+        }
+        HIP_OK(hipMemcpy(p->ws + U.off_budget, bud.data(), bud.size() * 4, hipMemcpyHostToDevice));
         launch_fill_zero(p->ws + U.off_fail, (size_t(na) * 4 + 15) / 16 * 16, st);
         judge_fields(p, st, [&](const int *vs, int cnt) {
             ProjArgs pa{};
@@ -659,11 +674,10 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
             check_launch();
         });
         std::vector<int32_t> flags(na);
-        std::vector<float> res(size_t(na) * 8), bud(size_t(p->n_dom) * 4);
+        std::vector<float> res(size_t(na) * 8);
         HIP_OK(hipStreamSynchronize(st));
         HIP_OK(hipMemcpy(flags.data(), p->ws + U.off_fail, size_t(na) * 4, hipMemcpyDeviceToHost));
         HIP_OK(hipMemcpy(res.data(), p->ws + U.off_jres, res.size() * 4, hipMemcpyDeviceToHost));
-        HIP_OK(hipMemcpy(bud.data(), p->ws + U.off_budget, bud.size() * 4, hipMemcpyDeviceToHost));
         for (int v = 0; v < na; ++v) {
             FarPairH &F = U.pairs[U.aud[v]];
             if (F.plain) continue;

@@ -124,8 +124,9 @@ __global__ void k_moments_final(MomentArgs a) {
 // ---------------------------------------------------------------------------
 // Network inputs of every far pair: the source's moments at lags
 // m = m_c - n_lags/2 + j (j < n_lags), i.e. of steps t = l - m, rotated into
-// the pair's frame and scaled, then the pair's geometry.  Steps t <= 0 have
-// dS = 0.  Block: one pair; thread: one lag.
+// the pair's frame and scaled (H), written as the six blocks H, g H, f H,
+// g f H, g^2 H, f^2 H with the pair's geometry g, f, then g and f.  Steps
+// t <= 0 have dS = 0.  Block: one pair; thread: one lag.
 __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
     const FarPair &fp = a.pairs[blockIdx.x];
     const int64_t l = *a.step + a.step_adj;
@@ -134,6 +135,9 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
     float R[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) R[i] = fp.rot[i];
+    const float g = fp.geo[0], fr = fp.geo[1];
+    const float mult[kNBlocks] = {1.f, g, fr, g * fr, g * g, fr * fr};
+    const int64_t nh = int64_t(a.n_lags) * kNFeat;
     for (int jl = threadIdx.x; jl < a.n_lags; jl += blockDim.x) {
         const int64_t m = int64_t(fp.m_c) - a.n_lags / 2 + jl;
         const int64_t t = l - m;
@@ -147,12 +151,12 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
             for (int q = 0; q < kNFeat; ++q) f[q] = 0.f;
         }
         const float Q[3][3] = {{f[4], f[7], f[8]}, {f[7], f[5], f[9]}, {f[8], f[9], f[6]}};
-        float g[kNFeat];
-        g[0] = f[0];
+        float gq[kNFeat];
+        gq[0] = f[0];
 #pragma unroll
         for (int A = 0; A < 3; ++A) {
-            g[1 + A] = R[3 * A] * f[1] + R[3 * A + 1] * f[2] + R[3 * A + 2] * f[3];
-            g[10 + A] = R[3 * A] * f[10] + R[3 * A + 1] * f[11] + R[3 * A + 2] * f[12];
+            gq[1 + A] = R[3 * A] * f[1] + R[3 * A + 1] * f[2] + R[3 * A + 2] * f[3];
+            gq[10 + A] = R[3 * A] * f[10] + R[3 * A + 1] * f[11] + R[3 * A + 2] * f[12];
         }
         // rank-2 tensors: T' = R T R^T
         float RQ[3][3], RK[3][3];
@@ -169,18 +173,22 @@ __global__ __launch_bounds__(128) void k_features(FeatArgs a) {
 #pragma unroll
             for (int B = 0; B < 3; ++B) {
                 Qp[A][B] = RQ[A][0] * R[3 * B] + RQ[A][1] * R[3 * B + 1] + RQ[A][2] * R[3 * B + 2];
-                g[13 + 3 * A + B] = RK[A][0] * R[3 * B] + RK[A][1] * R[3 * B + 1] + RK[A][2] * R[3 * B + 2];
+                gq[13 + 3 * A + B] = RK[A][0] * R[3 * B] + RK[A][1] * R[3 * B + 1] + RK[A][2] * R[3 * B + 2];
             }
-        g[4] = Qp[0][0];
-        g[5] = Qp[1][1];
-        g[6] = Qp[2][2];
-        g[7] = Qp[0][1];
-        g[8] = Qp[0][2];
-        g[9] = Qp[1][2];
+        gq[4] = Qp[0][0];
+        gq[5] = Qp[1][1];
+        gq[6] = Qp[2][2];
+        gq[7] = Qp[0][1];
+        gq[8] = Qp[0][2];
+        gq[9] = Qp[1][2];
 #pragma unroll
-        for (int q = 0; q < kNFeat; ++q) x[jl * kNFeat + q] = g[q] * a.in_scale[q];
+        for (int q = 0; q < kNFeat; ++q) {
+            const float v = gq[q] * a.in_scale[q];
+#pragma unroll
+            for (int b = 0; b < kNBlocks; ++b) x[b * nh + jl * kNFeat + q] = mult[b] * v;
+        }
     }
-    if (threadIdx.x < kNGeo) x[a.n_lags * kNFeat + threadIdx.x] = fp.geo[threadIdx.x];
+    if (threadIdx.x < kNGeo) x[kNBlocks * nh + threadIdx.x] = fp.geo[threadIdx.x];
 }
 
 // Coefficient maps (see XformArgs).  Block: one row; thread: one output.

@@ -8,7 +8,8 @@ from . import _lib
 
 
 class Mlp:
-    """n_in -> H -> H -> n_out tanh network with Adam training on the GPU."""
+    """n_in -> H -> H -> n_out tanh network with a linear skip (n_in -> n_out),
+    trained with Adam on the GPU."""
 
     def __init__(self, n_in, n_hidden, n_out, max_batch, stream=None):
         import torch
@@ -83,9 +84,10 @@ class Mlp:
 
 
 def unflatten(flat, n_in, n_hidden, n_out):
-    """Split a flat parameter vector into (W1, b1, W2, b2, W3, b3)."""
-    sizes = [n_in * n_hidden, n_hidden, n_hidden * n_hidden, n_hidden, n_hidden * n_out, n_out]
-    shapes = [(n_in, n_hidden), (n_hidden,), (n_hidden, n_hidden), (n_hidden,), (n_hidden, n_out), (n_out,)]
+    """Split a flat parameter vector into (W1, b1, W2, b2, W3, b3, Ws)."""
+    sizes = [n_in * n_hidden, n_hidden, n_hidden * n_hidden, n_hidden, n_hidden * n_out, n_out, n_in * n_out]
+    shapes = [(n_in, n_hidden), (n_hidden,), (n_hidden, n_hidden), (n_hidden,), (n_hidden, n_out), (n_out,),
+              (n_in, n_out)]
     out, o = [], 0
     for n, sh in zip(sizes, shapes):
         out.append(flat[o:o + n].reshape(sh))

@@ -19,6 +19,7 @@ from .mlp import Mlp
 
 N_FEAT = 22
 N_OUT = 80
+N_BLOCKS = 6   # input blocks H, g H, f H, g f H, g^2 H, f^2 H
 
 
 def collect_pair_responses(plan, sources_at, n_steps, start=1, every=1, outputs=None):
@@ -61,25 +62,27 @@ class TrainedSurrogate:
 
 
 def feature_scales(X, T, n_lags):
-    """Input scale per moment (1 / RMS over samples and lags) and output scale
-    per coefficient (RMS over samples); zero columns get scale 1."""
+    """Input scale per moment (1 / RMS of the unmodulated block H over samples
+    and lags) and one output scale per potential component (RMS over samples
+    and its 20 coefficients), so that the loss weighs coefficient errors by
+    their share of the field error; zero columns get scale 1."""
     import torch
     xm = X[:, :n_lags * N_FEAT].reshape(-1, n_lags, N_FEAT)
     rms_in = torch.sqrt(torch.mean(xm.double() ** 2, dim=(0, 1))).cpu().numpy()
-    rms_out = torch.sqrt(torch.mean(T.double() ** 2, dim=0)).cpu().numpy()
+    rms_out = torch.sqrt(torch.mean(T.double().reshape(-1, 4, N_OUT // 4) ** 2, dim=(0, 2))).cpu().numpy()
     in_scale = np.where(rms_in > 0, 1.0 / np.maximum(rms_in, 1e-300), 1.0).astype(np.float32)
-    out_scale = np.where(rms_out > 0, rms_out, 1.0).astype(np.float32)
+    out_scale = np.repeat(np.where(rms_out > 0, rms_out, 1.0), N_OUT // 4).astype(np.float32)
     return in_scale, out_scale
 
 
 def scale_inputs(X, in_scale, n_lags):
     import torch
     s = torch.ones(X.shape[1], dtype=torch.float32, device=X.device)
-    s[:n_lags * N_FEAT] = torch.as_tensor(np.tile(in_scale, n_lags), device=X.device)
+    s[:N_BLOCKS * n_lags * N_FEAT] = torch.as_tensor(np.tile(in_scale, N_BLOCKS * n_lags), device=X.device)
     return X * s
 
 
-def train_surrogate(X, T, n_lags, hidden=256, iters=4000, batch=256, lr=1e-3, lr_end=1e-5, seed=0,
+def train_surrogate(X, T, n_lags, hidden=256, iters=20000, batch=2048, lr=3e-3, lr_end=1e-5, seed=0,
                     max_batch=None, log_every=0, log=print):
     """Fit the network to (X, T) with Adam on the GPU (cosine learning-rate
     decay from lr to lr_end).  max_batch: the largest inference batch the
@@ -92,9 +95,11 @@ def train_surrogate(X, T, n_lags, hidden=256, iters=4000, batch=256, lr=1e-3, lr
     mlp = Mlp(n_in, hidden, N_OUT, max(batch, max_batch or 0, 1))
     g = torch.Generator(device="cpu").manual_seed(seed)
     parts = []
-    for fan_in, fan_out in ((n_in, hidden), (hidden, hidden), (hidden, N_OUT)):
+    for fan_in, fan_out in ((n_in, hidden), (hidden, hidden)):
         parts.append(torch.randn(fan_in * fan_out, generator=g) * math.sqrt(1.0 / fan_in))
         parts.append(torch.zeros(fan_out))
+    # the output layer and the linear skip start at zero
+    parts += [torch.zeros(hidden * N_OUT), torch.zeros(N_OUT), torch.zeros(n_in * N_OUT)]
     mlp.set_params(torch.cat(parts).float())
     gi = torch.Generator(device="cuda").manual_seed(seed + 1)
     n = Xs.shape[0]
@@ -118,10 +123,9 @@ def relative_rms(sur: TrainedSurrogate, X, T, chunk=4096):
     Xs = scale_inputs(X, sur.in_scale, sur.n_lags)
     osc = torch.as_tensor(sur.out_scale, device=X.device)
     num = den = 0.0
+    chunk = min(chunk, sur.mlp.max_batch)
     for i in range(0, Xs.shape[0], chunk):
         xb = Xs[i:i + chunk].contiguous()
-        if xb.shape[0] > sur.mlp.max_batch:
-            raise ValueError("chunk larger than the network's max_batch")
         y = sur.mlp.forward(xb) * osc
         num += float(torch.sum((y - T[i:i + chunk]) ** 2))
         den += float(torch.sum(T[i:i + chunk] ** 2))

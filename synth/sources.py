@@ -292,13 +292,14 @@ def config4(seed: int = 0, n_systems: int = 64, sizes=(32, 48, 64, 96),
                   name=f"{n_systems} systems, sizes {sizes}, seed={seed}")
 
 
-def config5(seed: int = 0, n_dom: int = 32, n: int = 48, n_pairs: int = 16) -> System:
-    """32 domains of 48^3, h = 0.3, random in a 2000-bohr box, dt = 0.01."""
+def config5(seed: int = 0, n_dom: int = 32, n: int = 48, n_pairs: int = 16, box: float = 2000.0) -> System:
+    """32 domains of 48^3, h = 0.3, random in a 2000-bohr box, dt = 0.01
+    (smaller n_dom, n and box give the same recipe at test size)."""
     rng = np.random.default_rng(seed)
     h = 0.3
     side = (n - 1) * h
-    centres = _place_centres(rng, n_dom, lambda i: side, 2000.0, 20.0, h)
+    centres = _place_centres(rng, n_dom, lambda i: side, box, 20.0, h)
     doms = [_centred_domain(cc, n, h) for cc in centres]
     for d in doms:
         _random_pairs(rng, d, h, n_pairs)
-    return System(h, 0.01, C_AU, doms, name=f"{n_dom}x{n}^3 h=0.3 box=2000 seed={seed}")
+    return System(h, 0.01, C_AU, doms, name=f"{n_dom}x{n}^3 h=0.3 box={box:g} seed={seed}")

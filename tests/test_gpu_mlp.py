@@ -11,7 +11,7 @@ torch = pytest.importorskip("torch")
 def _setup(n_in=70, H=48, n_out=20, B=37, seed=0):
     from paper_2311_15429_amd.mlp import Mlp
     rng = np.random.default_rng(seed)
-    n = n_in * H + H + H * H + H + H * n_out + n_out
+    n = mlp_ref.n_params(n_in, H, n_out)
     w = rng.normal(scale=0.3, size=n)
     x = rng.normal(size=(B, n_in))
     t = rng.normal(size=(B, n_out))
@@ -20,15 +20,18 @@ def _setup(n_in=70, H=48, n_out=20, B=37, seed=0):
     return m, w.astype(np.float32).astype(np.float64), x.astype(np.float32), t.astype(np.float32)
 
 
-def test_forward_matches_reference():
-    m, w, x, t = _setup()
+@pytest.mark.parametrize("n_in", [70, 3000])
+def test_forward_matches_reference(n_in):
+    """n_in = 3000 runs the first layer and the skip as split-K products."""
+    m, w, x, t = _setup(n_in=n_in)
     y = m.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     ref, _ = mlp_ref.forward(w, x.astype(np.float64), m.n_in, m.n_hidden, m.n_out)
     assert np.max(np.abs(y - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
 
 
-def test_gradient_matches_reference():
-    m, w, x, t = _setup(seed=1)
+@pytest.mark.parametrize("n_in", [70, 3000])
+def test_gradient_matches_reference(n_in):
+    m, w, x, t = _setup(n_in=n_in, seed=1)
     loss, g = m.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
     rl, rg = mlp_ref.loss_grad(w, x.astype(np.float64), t.astype(np.float64), m.n_in, m.n_hidden, m.n_out)
     g = g.cpu().numpy()
@@ -36,7 +39,8 @@ def test_gradient_matches_reference():
     assert np.max(np.abs(g - rg)) <= 1e-3 * np.max(np.abs(rg))
     # per block (W1, b1, ...), relative to that block's scale
     o = 0
-    for size in [m.n_in * m.n_hidden, m.n_hidden, m.n_hidden ** 2, m.n_hidden, m.n_hidden * m.n_out, m.n_out]:
+    for size in [m.n_in * m.n_hidden, m.n_hidden, m.n_hidden ** 2, m.n_hidden, m.n_hidden * m.n_out, m.n_out,
+                 m.n_in * m.n_out]:
         blk, rblk = g[o:o + size], rg[o:o + size]
         assert np.max(np.abs(blk - rblk)) <= 1e-3 * np.max(np.abs(rblk)) + 1e-9
         o += size
@@ -48,7 +52,7 @@ def test_training_reduces_loss_on_a_linear_map():
     rng = np.random.default_rng(3)
     n_in, H, n_out, B = 16, 32, 4, 64
     A = rng.normal(size=(n_in, n_out)) / np.sqrt(n_in)
-    n = n_in * H + H + H * H + H + H * n_out + n_out
+    n = mlp_ref.n_params(n_in, H, n_out)
     w0 = rng.normal(scale=1.0 / np.sqrt(H), size=n).astype(np.float32)
     m = Mlp(n_in, H, n_out, max_batch=B, stream=torch.cuda.current_stream())
     m.set_params(torch.from_numpy(w0))

@@ -8,7 +8,7 @@ from oracle import mlp_ref
 def test_reference_gradient_matches_finite_differences():
     rng = np.random.default_rng(0)
     n_in, H, n_out, B = 7, 5, 3, 4
-    n = n_in * H + H + H * H + H + H * n_out + n_out
+    n = mlp_ref.n_params(n_in, H, n_out)
     w = rng.normal(scale=0.5, size=n)
     x = rng.normal(size=(B, n_in))
     t = rng.normal(size=(B, n_out))

@@ -43,7 +43,7 @@ def test_classification_depths_and_bytes():
     info = p.surrogate_info()
     far = _expected_far(system, 3.0)
     assert info["n_far"] == len(far) > 0
-    assert info["n_in"] == 16 * 22 + 2 and info["n_out"] == 80
+    assert info["n_in"] == 6 * 16 * 22 + 2 and info["n_out"] == 80
     pairs = p.surrogate_pairs()
     got = set(zip(pairs["target"].tolist(), pairs["source"].tolist()))
     assert got == far

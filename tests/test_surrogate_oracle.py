@@ -116,7 +116,8 @@ def test_features_before_arrival_are_zero_and_geometry_is_exact():
     _, dist, m_c, frac = sr.pair_geometry(system, 0, 1)
     assert m_c > L + 16
     x = sr.features(system, S, 0, 1, L, 16)
-    assert np.all(x[:16 * 22] == 0)
+    assert x.shape == (6 * 16 * 22 + 2,)
+    assert np.all(x[:6 * 16 * 22] == 0)
     assert abs(x[-1] - frac) < 1e-15 and abs(frac) <= 0.5
     dbar = np.mean([sr.box_diagonal(d, system.h) for d in system.domains])
     assert abs(x[-2] - 10 * dbar / dist) < 1e-15
