@@ -168,6 +168,180 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_surrogate(args):
+    """32 sub-domains of 48^3 in a 2000-bohr box with the learned far-pair
+    surrogate: teacher data from the plain method on other seeds (audit
+    sources only), training in the library's kernels, then the timed run with
+    the judge on sampled steps, and the FP64 oracle at sampled points."""
+    import numpy as np
+    import torch
+    import oracle
+    from oracle import surrogate_ref
+    from paper_2311_15429_amd import plan_for_system
+    from paper_2311_15429_amd import surrogate as S
+    from synth.sources import config5, spatial_factors, time_factors
+
+    FAR, NL, T_STEPS, JUDGE_EVERY, TOL = 10.0, 64, 3000, 100, 1e-4
+    precision = args.precision if args.precision != "fp32" else "fp32_ring_fp16"
+    stream = torch.cuda.current_stream()
+
+    class Gen:
+        """Sources of step l on the GPU from the separable factors."""
+
+        def __init__(self, system):
+            self.system = system
+            self.B = []
+            for d in system.domains:
+                b = spatial_factors(d, system.h, system.c)
+                self.B.append(torch.from_numpy(b.reshape(b.shape[0], -1)).to("cuda", torch.float32))
+
+        def __call__(self, l):
+            out = []
+            for d, B in zip(self.system.domains, self.B):
+                A = torch.from_numpy(time_factors(d, self.system.dt, [l])).to("cuda", torch.float32)
+                out.append((A @ B).reshape((4,) + tuple(d.dims)).contiguous())
+            return out
+
+    # teacher data
+    t0 = time.perf_counter()
+    X, T = [], []
+    for seed in args.teacher_seeds:
+        tsys = config5(seed)
+        p = plan_for_system(tsys, "fp32", stream=stream)
+        p.surrogate_configure(FAR, n_lags=NL, audit=range(args.teacher_audit))
+        log(f"teacher seed {seed}: {p.surrogate_info()}, workspace {p.workspace_bytes / 1e9:.1f} GB")
+        p.bind()
+        p.set_green_kernels()
+        x, t = S.collect_pair_responses(p, Gen(tsys), T_STEPS, start=1, every=3)
+        X.append(x)
+        T.append(t)
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+        log(f"  {x.shape[0]} samples, {time.perf_counter() - t0:.0f} s")
+    X, T = torch.cat(X), torch.cat(T)
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sur = S.train_surrogate(X, T, NL, max_batch=2048, log_every=5000, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    train_rms = S.relative_rms(sur, X, T)
+    n_samples = int(X.shape[0])
+    del X, T
+    torch.cuda.empty_cache()
+    log(f"trained on {n_samples} pair responses in {t_train:.0f} s, train rel rms {train_rms:.2e}")
+
+    # the workload
+    system = config5(args.seed)
+    plain = plan_for_system(system, "fp32")
+    pst = plain.stats()
+    plain.close()
+    plan = plan_for_system(system, precision, stream=stream)
+    plan.surrogate_configure(FAR, n_lags=NL, audit=list(args.audit))
+    info = plan.surrogate_info()
+    st = plan.stats()
+    log(f"surrogate plan: {info}, workspace {plan.workspace_bytes / 1e9:.1f} GB "
+        f"(plain FP32 would need {(pst['ring_bytes'] + pst['spectra_bytes']) / 1e9:.0f} GB of history)")
+    plan.bind()
+    plan.set_green_kernels()
+    plan.surrogate_attach(sur.mlp, sur.in_scale, sur.out_scale)
+    tuned = plan.autotune(iters=3)
+    gen = Gen(system)
+    outs = [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in plan.dims]
+    W, K = args.warmup, args.steps
+    judged = []
+
+    def step(l):
+        plan.push_sources(l, gen(l))
+        plan.retarded_step(l, outs)
+        if l % JUDGE_EVERY == JUDGE_EVERY - 1:
+            judged.append(plan.surrogate_judge(outs, TOL))
+
+    for l in range(W + 1):
+        step(l)
+    # sources of the timed steps in device memory before the timed region
+    src = [gen(l) for l in range(W + 1, W + K + 1)]
+    torch.cuda.synchronize()
+    plan.lagsum_time()
+    plan.profile_lagsum(True)
+    t0 = time.perf_counter()
+    for i, l in enumerate(range(W + 1, W + K + 1)):
+        plan.push_sources(l, src[i])
+        plan.retarded_step(l, outs)
+        if l % JUDGE_EVERY == JUDGE_EVERY - 1:
+            judged.append(plan.surrogate_judge(outs, TOL))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    plan.profile_lagsum(False)
+    lag_ms, launches = plan.lagsum_time()
+    l_end = W + K
+    ms_step = 1e3 * el / K
+    updates = st["points"] * K / el
+    lag_s = lag_ms / launches / 1e3
+    st = plan.stats()                       # after fallbacks
+    achieved = st["lagsum_bytes"] / lag_s / 1e9
+    plain_lag_ms = pst["lagsum_bytes"] / (achieved * 1e9) * 1e3
+    fell = sum(n for n, _ in judged)
+    log(f"step {ms_step:.2f} ms ({updates / 1e6:.1f} M updates/s), lag sum {lag_s * 1e3:.2f} ms at {achieved:.0f} GB/s; "
+        f"plain lag sum alone would be {plain_lag_ms:.1f} ms ({pst['lagsum_bytes'] / 1e9:.0f} GB); "
+        f"judge: {len(judged)} calls, {fell} fallbacks")
+
+    # error vs the FP64 oracle at sampled points of the last step, beside the
+    # same points with the far pairs left out
+    got = [o.double().cpu().numpy().reshape(4, -1) for o in outs]
+    scale = np.max(np.abs(np.concatenate(got, axis=1)), axis=1)
+    pairs = plan.surrogate_pairs()
+    rng = np.random.default_rng(1)
+    targets = rng.choice(len(system.domains), args.oracle_targets, replace=False)
+    B = [spatial_factors(d, system.h, system.c) for d in system.domains]
+
+    def sample_fn(n, j0, j1):
+        A = time_factors(system.domains[n], system.dt, np.arange(j0, j1 + 1))
+        return (A @ B[n].reshape(B[n].shape[0], -1)).reshape(j1 - j0 + 1, 4, -1)
+
+    err_s = np.zeros(4)
+    err_d = np.zeros(4)
+    t0 = time.perf_counter()
+    for s in targets:
+        s = int(s)
+        idx = np.sort(rng.choice(system.domains[s].n_points, args.oracle_points, replace=False))
+        ref = oracle.potential_points(system, s, idx, l_end, sample_fn)
+        err_s = np.maximum(err_s, np.max(np.abs(got[s][:, idx].T - ref), axis=0) / scale)
+        # what leaving the far pairs out would cost at the same points
+        far_src = [int(n) for t_, n in zip(pairs["target"], pairs["source"]) if int(t_) == s]
+        pts = surrogate_ref.grid_points(system.domains[s], system.h)[idx]
+        far_dyn = oracle.potential_at(system, pts, l_end * system.dt, sample_fn, dynamic=True, sources=far_src)
+        err_d = np.maximum(err_d, np.max(np.abs(far_dyn), axis=0) / scale)
+        log(f"  oracle target {s}: {time.perf_counter() - t0:.0f} s")
+    t_oracle = time.perf_counter() - t0
+    log(f"oracle at {len(targets)} x {args.oracle_points} points: rel err {np.array2string(err_s, precision=2)}; "
+        f"far pairs left out would give {np.array2string(err_d, precision=2)} ({t_oracle:.0f} s)")
+
+    line = {"metric": METRIC, "value": updates, "unit": "grid-point updates/s", "n_gpus": 1, "steps": K,
+            "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "32 sub-domains of 48^3 points, h=0.3 bohr, 2000-bohr box, dt=0.01, "
+                                   "learned far-pair surrogate (pairs > 10 box diagonals apart)",
+                       "precision": precision, "far_pairs": info["n_far"], "audited_far_pairs": info["n_audited"],
+                       "judge_every": JUDGE_EVERY, "judge_tol": TOL, "fallbacks": fell,
+                       "rel_err_vs_fp64_oracle_sampled": [float(v) for v in err_s],
+                       "rel_err_far_pairs_left_out_sampled": [float(v) for v in err_d],
+                       "oracle_points": int(len(targets) * args.oracle_points), "step_of_check": l_end,
+                       "plain_fp32_history_bytes": pst["ring_bytes"] + pst["spectra_bytes"],
+                       "plain_fp32_lagsum_bytes": pst["lagsum_bytes"],
+                       "plain_fp32_lagsum_ms_modelled": plain_lag_ms,
+                       "speedup_vs_plain_lagsum_alone_modelled": plain_lag_ms / ms_step,
+                       "teacher_samples": n_samples, "teacher_s": round(t_data, 1), "train_s": round(t_train, 1),
+                       "train_rel_rms": train_rms, "autotune": tuned},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_lagsum",
+                         "kernel_ms": round(lag_s * 1e3, 4), "algorithmic_bytes_per_launch": st["lagsum_bytes"]},
+            "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+    plan.surrogate_attach(None)
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,9 +353,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lagsum-unroll", type=int, default=None, choices=[1, 2, 4])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default lag-sum schedule")
-    ap.add_argument("--workload", default="scale", choices=["scale", "batched"],
+    ap.add_argument("--workload", default="scale", choices=["scale", "batched", "surrogate"],
                     help="scale: 8 x 64^3 (the metric's workload); batched: 64 independent systems "
-                         "(2-8 domains of 16^3/24^3/32^3) in one plan, one graph launch per step")
+                         "(2-8 domains of 16^3/24^3/32^3) in one plan, one graph launch per step; "
+                         "surrogate: 32 x 48^3 in a 2000-bohr box with the learned far-pair surrogate")
+    ap.add_argument("--teacher-seeds", type=int, nargs="+", default=[101, 102, 103])
+    ap.add_argument("--teacher-audit", type=int, default=3, help="audit sources per teacher system")
+    ap.add_argument("--audit", type=int, nargs="*", default=[0, 1], help="audit sources of the timed run")
+    ap.add_argument("--oracle-targets", type=int, default=3)
+    ap.add_argument("--oracle-points", type=int, default=24)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -198,6 +378,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
     system = config2(args.seed)
     workload = "8 sub-domains of 64^3 points, h=0.3 bohr, 400-bohr box, dt=0.01, FFT pad 128^3"
     stream = torch.cuda.current_stream()
