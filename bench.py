@@ -16,7 +16,6 @@ Prints one JSON line.  `--gpus N` with N > 1 is not supported (one GPU).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -50,13 +49,6 @@ def make_sources(system, steps, dtype):
     return out
 
 
-def kernel_source_sha():
-    h = hashlib.sha1()
-    for f in ("lagsum.hip", "rpot_internal.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_2311_15429_amd", "csrc", f), "rb").read())
-    return h.hexdigest()
-
-
 def traffic_from_profiles(workload, precision):
     """HBM bytes per lag-sum launch from the committed counter summary, if it
     was taken on the current kernel source and this workload."""
@@ -67,6 +59,7 @@ def traffic_from_profiles(workload, precision):
         return None
     key = f"{workload}|{precision}"
     ent = rec.get(key)
+    from paper_2311_15429_amd.profiling import kernel_source_sha
     if not ent or ent.get("kernel_source_sha") != kernel_source_sha():
         return None
     return ent.get("traffic_bytes_per_launch")

@@ -7,7 +7,7 @@ __amd_rocclr_copyBuffer dispatch, `bench.py --calib-copy-mib N`), because the
 derived counters need not count every request size.
 
     python -m paper_2311_15429_amd.profiling FETCH.csv WRITE.csv --copy-mib 1024 \
-        --key config2|fp32 --kernel-sha SHA --out profiles/lagsum_traffic.json
+        --key config2|fp32 --out profiles/lagsum_traffic.json
 """
 from __future__ import annotations
 
@@ -17,6 +17,19 @@ import json
 import os
 import sys
 from collections import defaultdict
+
+
+def kernel_source_sha():
+    """Hash of the lag-sum kernel's source: lagsum.hip and the lag-sum tables'
+    declarations.  Counter figures taken on another source are stale."""
+    import hashlib
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha1()
+    h.update(open(os.path.join(here, "lagsum.hip"), "rb").read())
+    hdr = open(os.path.join(here, "rpot_internal.hpp")).read()
+    a, b = hdr.index("// Lag-sum multiply-accumulate."), hdr.index("// Launchers")
+    h.update(hdr[a:b].encode())
+    return h.hexdigest()
 
 
 def _read(path):
@@ -54,7 +67,7 @@ def main():
     ap.add_argument("write_csv")
     ap.add_argument("--copy-mib", type=float, required=True)
     ap.add_argument("--key", required=True)
-    ap.add_argument("--kernel-sha", required=True)
+    ap.add_argument("--kernel-sha", default=None, help="default: the current lag-sum source")
     ap.add_argument("--kernel", default="k_lagsum")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
@@ -62,7 +75,7 @@ def main():
     rec = {}
     if os.path.exists(a.out):
         rec = json.load(open(a.out))
-    rec[a.key] = {"kernel_source_sha": a.kernel_sha, "traffic_bytes_per_launch": f + w,
+    rec[a.key] = {"kernel_source_sha": a.kernel_sha or kernel_source_sha(), "traffic_bytes_per_launch": f + w,
                   "fetch_bytes": f, "write_bytes": w, "fetch_scale": fs, "write_scale": ws,
                   "launches": n}
     json.dump(rec, open(a.out, "w"), indent=1, sort_keys=True)
