@@ -14,14 +14,17 @@ def log(*a):
     sys.stdout.flush()
 
 
-def run_gpu(system, precision, samples, collect=None):
+def run_gpu(system, precision, samples, collect=None, tune=None):
     """Push samples[n][l] ([L+1][4][N] FP64) for l = 0..L and step.
+    tune: {knob: value} set before binding.
 
     Returns {l: [dom][4][N] FP64 numpy} for l in `collect` (default: all)."""
     import torch
     from paper_2311_15429_amd import plan_for_system
     stream = torch.cuda.current_stream()
     p = plan_for_system(system, precision, stream=stream)
+    for k, v in (tune or {}).items():
+        p.set_tuning(k, v)
     p.bind()
     p.set_green_kernels()
     dt = p.dtype

@@ -19,12 +19,14 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _run_sampled(system, precision, steps_out, n_pts, seed=0, unroll=None):
+def _run_sampled(system, precision, steps_out, n_pts, seed=0, unroll=None, tune=None):
     from paper_2311_15429_amd import plan_for_system
     stream = torch.cuda.current_stream()
     plan = plan_for_system(system, precision, stream=stream)
     if unroll is not None:
         plan.set_tuning("lagsum_unroll", unroll)
+    for k, v in (tune or {}).items():
+        plan.set_tuning(k, v)
     plan.bind()
     plan.set_green_kernels()
     gen = GpuSourceGen(system, plan.dtype)
