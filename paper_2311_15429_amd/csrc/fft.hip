@@ -13,6 +13,8 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
+
 namespace rpot {
 
 template <typename T>
@@ -42,24 +44,26 @@ __device__ __forceinline__ Cx<T> mul_i(Cx<T> a, int sgn) {
 
 // In-place FFT of L lines of length P held in LDS (row-major [L][P]).
 // dir = -1: sum_j x_j exp(-2 pi i jk/P);  dir = +1: exp(+2 pi i jk/P).
+// The twiddles tw come from LDS; every division by a stage constant is a
+// multiply-high (RadixPlan::dq, dp).
 template <typename T, int NT, int BMAX>
-__device__ void lds_fft(Cx<T> *buf, int P, int L, int dir, const Cx<T> *__restrict__ tw,
-                        const RadixPlan &rp) {
+__device__ void lds_fft(Cx<T> *buf, int P, int L, int dir, const Cx<T> *tw, const RadixPlan &rp) {
     const int tid = threadIdx.x;
     int p = 1;
     for (int st = 0; st < rp.n; ++st) {
         const int R = rp.r[st];
         const int nq = P / R;
         const int nbf = L * nq;
-        const int tws = P / (p * R);
+        const int tws = rp.tws[st];
+        const FastDiv dq = rp.dq[st], dp = rp.dp[st];
         Cx<T> v[BMAX][4];
 #pragma unroll
         for (int it = 0; it < BMAX; ++it) {
             const int b = tid + it * NT;
             if (b < nbf) {
-                const int li = b / nq;
+                const int li = dq.div(b);
                 const int i = b - li * nq;
-                const int k = i % p;
+                const int k = i - dp.div(i) * p;
                 const Cx<T> *row = buf + li * P;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
@@ -102,9 +106,9 @@ __device__ void lds_fft(Cx<T> *buf, int P, int L, int dir, const Cx<T> *__restri
         for (int it = 0; it < BMAX; ++it) {
             const int b = tid + it * NT;
             if (b < nbf) {
-                const int li = b / nq;
+                const int li = dq.div(b);
                 const int i = b - li * nq;
-                const int k = i % p;
+                const int k = i - dp.div(i) * p;
                 const int j = (i - k) * R + k;
                 Cx<T> *row = buf + li * P;
 #pragma unroll
@@ -156,34 +160,36 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
     constexpr int NT = kFftThreads;
     constexpr int BMAX = (E / 2 + NT - 1) / NT;
     __shared__ Cx<T> buf[E];
+    __shared__ Cx<T> twl[kMaxFft];
     const LineJob &job = a.jobs[blockIdx.y];
     const int P = a.P;
-    const int L = E / P;
+    const int L = a.L;
     const int line0 = blockIdx.x * L;
     const int nl = min(L, a.lines - line0);
     const Cx<T> *__restrict__ in = reinterpret_cast<const Cx<T> *>(job.in);
+    for (int i = threadIdx.x; i < P; i += NT) twl[i] = reinterpret_cast<const Cx<T> *>(a.tw)[i];
 
     const bool jfast_in = (a.in_j == 1);
     for (int e = threadIdx.x; e < L * P; e += NT) {
         int li, j;
         if (jfast_in) {
-            li = e / P;
+            li = a.dP.div(e);
             j = e - li * P;
         } else {
-            j = e / L;
+            j = a.dL.div(e);
             li = e - j * L;
         }
         Cx<T> v = {T(0), T(0)};
         if (li < nl && j < a.n_in) {
             const int line = line0 + li;
-            const int outer = line / a.n_inner;
+            const int outer = a.dinner.div(line);
             const int inner = line - outer * a.n_inner;
             v = in[outer * a.in_outer + inner * a.in_inner + int64_t(j) * a.in_j];
         }
         buf[li * P + j] = v;
     }
     __syncthreads();
-    lds_fft<T, NT, BMAX>(buf, P, L, a.dir, reinterpret_cast<const Cx<T> *>(a.tw), a.rp);
+    lds_fft<T, NT, BMAX>(buf, P, L, a.dir, twl, a.rp);
 
     void *obase = job.out;
     const float *qs = job.qscale;
@@ -198,33 +204,53 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
     for (int e = threadIdx.x; e < L * nout; e += NT) {
         int li, j;
         if (jfast_out) {
-            li = e / nout;
+            li = a.dnout.div(e);
             j = e - li * nout;
         } else {
-            j = e / L;
+            j = a.dL.div(e);
             li = e - j * L;
         }
         if (li < nl) {
             const int line = line0 + li;
-            const int outer = line / a.n_inner;
+            const int outer = a.dinner.div(line);
             const int inner = line - outer * a.n_inner;
             float inv_scale = 1.0f;
             // the component is the fastest batch index (inner mod 4)
             if (FMT == RING_F16 || FMT == RING_BF16) inv_scale = 1.0f / qs[inner & 3];
             int64_t idx = outer * a.out_outer + inner * a.out_inner + int64_t(j) * a.out_j;
             if (job.tile_stride) {
-                const int64_t kk = idx / a.tile_comp;
-                const int64_t c = idx - kk * a.tile_comp;
-                idx = (kk / kTile) * job.tile_stride + (kk % kTile) * a.tile_comp + c;
+                // tile_comp is 1 or 4; one job's indices stay below 2^31
+                const uint32_t u = uint32_t(idx);
+                const uint32_t kk = a.tile_comp == 4 ? (u >> 2) : u;
+                const uint32_t c = u - kk * uint32_t(a.tile_comp);
+                idx = int64_t(kk / kTile) * job.tile_stride + int64_t((kk % kTile) * uint32_t(a.tile_comp) + c);
             }
             Store<T, FMT>::put(obase, idx, buf[li * P + j], inv_scale);
         }
     }
 }
 
-void launch_line_pass(const LinePass &a, int prec64, hipStream_t st) {
+// Stage divisors of a radix plan (host).
+static void fill_stage_divisors(RadixPlan &rp, int P) {
+    int p = 1;
+    for (int st = 0; st < rp.n; ++st) {
+        rp.dq[st] = FastDiv(uint32_t(P / rp.r[st]));
+        rp.dp[st] = FastDiv(uint32_t(p));
+        rp.tws[st] = P / (p * rp.r[st]);
+        p *= rp.r[st];
+    }
+}
+
+void launch_line_pass(const LinePass &a0, int prec64, hipStream_t st) {
+    LinePass a = a0;
     const int E = prec64 ? Lds<double>::E : Lds<float>::E;
     const int L = E / a.P;
+    a.L = L;
+    a.dL = FastDiv(uint32_t(L));
+    a.dP = FastDiv(uint32_t(a.P));
+    a.dinner = FastDiv(uint32_t(a.n_inner));
+    a.dnout = FastDiv(uint32_t(std::max(a.n_out, 1)));
+    fill_stage_divisors(a.rp, a.P);
     dim3 grid((a.lines + L - 1) / L, a.n_jobs);
     if (prec64) {
         if (a.out_fmt == RING_F64)
@@ -294,10 +320,12 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
     constexpr int NT = kFftThreads;
     constexpr int BMAX = (E / 2 + NT - 1) / NT;
     __shared__ Cx<T> buf[E];
+    __shared__ Cx<T> twl[kMaxFft];
     __shared__ float red[4][NT / 64];
     const ZFwdJob &job = a.jobs[blockIdx.y];
     const int P = a.Pz;
     const int L = zfwd_lpb<T>(P);
+    for (int i = threadIdx.x; i < P; i += NT) twl[i] = reinterpret_cast<const Cx<T> *>(a.tw)[i];
     const int line0 = blockIdx.x * L;
     const int npos = a.Nx * a.Ny;
     const int nlines = (a.mode == 0) ? 4 * ((npos + 1) / 2) : a.Px * (a.Py / 2);
@@ -310,7 +338,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         const T *__restrict__ S0 = reinterpret_cast<const T *>(job.s0);
         const int64_t npts = int64_t(npos) * a.Nz;
         for (int e = threadIdx.x; e < L * P; e += NT) {
-            const int li = e / P;
+            const int li = a.dP.div(e);
             const int z = e - li * P;
             Cx<T> v = {T(0), T(0)};
             if (li < nl && z < a.Nz) {
@@ -329,12 +357,12 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         }
     } else {
         for (int e = threadIdx.x; e < L * P; e += NT) {
-            const int li = e / P;
+            const int li = a.dP.div(e);
             const int z = e - li * P;
             Cx<T> v = {T(0), T(0)};
             if (li < nl) {
                 const int line = line0 + li;
-                const int qx = line / (a.Py / 2);
+                const int qx = a.dPy2.div(line);
                 const int qy = 2 * (line - qx * (a.Py / 2));
                 v.x = T(green_value(a, job, qx, qy, z));
                 v.y = T(green_value(a, job, qx, qy + 1, z));
@@ -355,7 +383,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         for (int w = 0; w < NT / 64; ++w) v = fmaxf(v, red[threadIdx.x][w]);
         job.zmax[blockIdx.x * 4 + threadIdx.x] = v;
     }
-    lds_fft<T, NT, BMAX>(buf, P, L, -1, reinterpret_cast<const Cx<T> *>(a.tw), a.rp);
+    lds_fft<T, NT, BMAX>(buf, P, L, -1, twl, a.rp);
 
     // unpack: X_re = (Z_k + conj Z_-k)/2,  X_im = (Z_k - conj Z_-k)/(2i)
     const int Hz = a.Hz;
@@ -365,11 +393,11 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         const int np = min(2 * ((nl + 3) >> 2), npos - pos0);
         for (int e = threadIdx.x; e < np * Hz * 4; e += NT) {
             const int mu = e & 3;
-            const int k = (e >> 2) % Hz;
-            const int pl = (e >> 2) / Hz;
+            const int pl = a.dHz.div(e >> 2);
+            const int k = (e >> 2) - pl * Hz;
             const int li = (pl >> 1) * 4 + mu;
             const Cx<T> zk = buf[li * P + k];
-            const Cx<T> zm = buf[li * P + ((P - k) % P)];
+            const Cx<T> zm = buf[li * P + (k == 0 ? 0 : P - k)];
             Cx<T> r;
             if ((pl & 1) == 0) r = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
             else r = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
@@ -377,11 +405,11 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         }
     } else {
         for (int e = threadIdx.x; e < 2 * nl * Hz; e += NT) {
-            const int k = e % Hz;
-            const int rl = e / Hz;
+            const int rl = a.dHz.div(e);
+            const int k = e - rl * Hz;
             const int li = rl >> 1;
             const Cx<T> zk = buf[li * P + k];
-            const Cx<T> zm = buf[li * P + ((P - k) % P)];
+            const Cx<T> zm = buf[li * P + (k == 0 ? 0 : P - k)];
             Cx<T> r;
             if ((rl & 1) == 0) r = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
             else r = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
@@ -394,7 +422,12 @@ int zfwd_lines_per_block(int Pz, int prec64) {
     return prec64 ? zfwd_lpb<double>(Pz) : zfwd_lpb<float>(Pz);
 }
 
-void launch_zfwd(const ZFwd &a, int prec64, hipStream_t st) {
+void launch_zfwd(const ZFwd &a0, int prec64, hipStream_t st) {
+    ZFwd a = a0;
+    a.dP = FastDiv(uint32_t(a.Pz));
+    a.dHz = FastDiv(uint32_t(a.Hz));
+    a.dPy2 = FastDiv(uint32_t(std::max(a.Py / 2, 1)));
+    fill_stage_divisors(a.rp, a.Pz);
     const int L = zfwd_lines_per_block(a.Pz, prec64);
     const int nlines = (a.mode == 0) ? 4 * ((a.Nx * a.Ny + 1) / 2) : a.Px * (a.Py / 2);
     dim3 grid((nlines + L - 1) / L, a.n_jobs);
@@ -412,9 +445,11 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
     constexpr int NT = kFftThreads;
     constexpr int BMAX = (E / 2 + NT - 1) / NT;
     __shared__ Cx<T> buf[E];
+    __shared__ Cx<T> twl[kMaxFft];
     const ZInvJob &job = a.jobs[blockIdx.y];
     const int P = a.Pz;
     const int Hz = a.Hz;
+    for (int i = threadIdx.x; i < P; i += NT) twl[i] = reinterpret_cast<const Cx<T> *>(a.tw)[i];
     const int L = zfwd_lpb<T>(P);
     const int line0 = blockIdx.x * L;
     const int npos = a.Nx * a.Ny;
@@ -426,8 +461,8 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
     // Z_k = X_a(k) + i X_b(k) and Z_{P-k} = conj X_a(k) + i conj X_b(k)
     for (int e = threadIdx.x; e < (L / 4) * Hz * 4; e += NT) {
         const int mu = e & 3;
-        const int k = (e >> 2) % Hz;
-        const int ppl = (e >> 2) / Hz;
+        const int ppl = a.dHz.div(e >> 2);
+        const int k = (e >> 2) - ppl * Hz;
         const int li = ppl * 4 + mu;
         Cx<T> xa = {T(0), T(0)}, xb = {T(0), T(0)};
         if (li < nl) {
@@ -443,17 +478,25 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
         }
     }
     __syncthreads();
-    lds_fft<T, NT, BMAX>(buf, P, L, +1, reinterpret_cast<const Cx<T> *>(a.tw), a.rp);
+    lds_fft<T, NT, BMAX>(buf, P, L, +1, twl, a.rp);
 
     T *__restrict__ out = reinterpret_cast<T *>(job.out);
     const T *__restrict__ add = reinterpret_cast<const T *>(job.add);
     const int np = min(2 * ((nl + 3) >> 2), npos - pos0);
     const int64_t npts = int64_t(npos) * a.Nz;
+    // np is the block's position count: at most 2 (L / 4); a short block
+    // (the last one) divides by its own count
     for (int e = threadIdx.x; e < 4 * np * a.Nz; e += NT) {
-        const int z = e % a.Nz;
-        const int r = e / a.Nz;
-        const int pl = r % np;
-        const int mu = r / np;
+        const int r = a.dNz.div(e);
+        const int z = e - r * a.Nz;
+        int mu, pl;
+        if (np == 2 * (L >> 2)) {
+            mu = a.dnp.div(r);
+            pl = r - mu * np;
+        } else {
+            mu = r / np;
+            pl = r - mu * np;
+        }
         const Cx<T> v = buf[((pl >> 1) * 4 + mu) * P + z];
         const int64_t o = mu * npts + int64_t(pos0 + pl) * a.Nz + z;
         T val = (pl & 1) ? v.y : v.x;
@@ -462,8 +505,13 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
     }
 }
 
-void launch_zinv(const ZInv &a, int prec64, hipStream_t st) {
+void launch_zinv(const ZInv &a0, int prec64, hipStream_t st) {
+    ZInv a = a0;
     const int L = zfwd_lines_per_block(a.Pz, prec64);
+    a.dHz = FastDiv(uint32_t(a.Hz));
+    a.dNz = FastDiv(uint32_t(a.Nz));
+    a.dnp = FastDiv(uint32_t(std::max(2 * (L >> 2), 1)));
+    fill_stage_divisors(a.rp, a.Pz);
     const int nlines = 4 * ((a.Nx * a.Ny + 1) / 2);
     dim3 grid((nlines + L - 1) / L, a.n_jobs);
     if (prec64) hipLaunchKernelGGL(k_zinv<double>, grid, dim3(kFftThreads), 0, st, a);

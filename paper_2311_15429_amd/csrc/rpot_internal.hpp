@@ -14,10 +14,29 @@ struct Cx {
     T x, y;
 };
 
-// Mixed-radix factorisation of an FFT length (radices 4, 2, 3).
+// Division by a fixed divisor d >= 1 through a multiply-high:
+// n / d = (mulhi(n, mul) + n) >> shift for every n < 2^31.
+struct FastDiv {
+    uint32_t mul = 1, shift = 0;
+    FastDiv() = default;
+    __host__ explicit FastDiv(uint32_t d) {
+        while ((uint64_t(1) << shift) < d) ++shift;
+        mul = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << shift) - d)) / d + 1);
+    }
+    __device__ __forceinline__ int div(int n) const {
+        return int((uint64_t(__umulhi(uint32_t(n), mul)) + uint32_t(n)) >> shift);
+    }
+};
+
+// Mixed-radix factorisation of an FFT length (radices 4, 2, 3), with the
+// per-stage divisors of the Stockham index map (butterflies per line
+// nq = P / r and the stride p of the radices before the stage).
+constexpr int kMaxFft = 512;      // longest FFT
 struct RadixPlan {
     int n;
     int r[16];
+    FastDiv dq[16], dp[16];
+    int tws[16];                  // twiddle stride P / (p r)
 };
 
 constexpr int kMaxJobs = 16;
@@ -47,6 +66,8 @@ struct LineJob {
 struct LinePass {
     int P, n_in, n_out;
     int lines, n_inner;
+    int L;                 // lines per block (set by the launcher)
+    FastDiv dL, dP, dinner, dnout;   // set by the launcher
     int64_t in_j, in_inner, in_outer;
     int64_t out_j, out_inner, out_outer;
     int dir;               // -1 forward, +1 inverse
@@ -82,6 +103,7 @@ struct ZFwd {
     int mode;
     int Nx, Ny, Nz;        // mode 0 dims (common to every job of a launch)
     int Px, Py, Pz, Hz;
+    FastDiv dP, dHz, dPy2; // set by the launcher
     double h, inv_cdt, scale;      // inv_cdt = 1/(c dt) (0 for c = inf); scale = 1/(Px Py Pz)
     double w_self0, w_self1, w_static;
     const void *tw;
@@ -101,6 +123,7 @@ struct ZInvJob {
 struct ZInv {
     int Nx, Ny, Nz;
     int Pz, Hz;
+    FastDiv dHz, dNz, dnp; // set by the launcher (dnp: position pairs per block)
     const void *tw;
     RadixPlan rp;
     int n_jobs;
