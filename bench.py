@@ -161,6 +161,62 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_small(args):
+    """Config 1 in FP64 (2 x 16^3, h = 0.5, 30 bohr apart, dt = 0.02): step
+    latency over 40 steps, beside the oracle's full run of the same steps on
+    the host cores (parity is checked too)."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2311_15429_amd import plan_for_system
+    from synth.sources import config1, sample_sources
+    L = 40
+    system = config1(args.seed if args.seed else 1)
+    S = sample_sources(system, range(L + 1))
+    plan = plan_for_system(system, "fp64", stream=torch.cuda.current_stream())
+    plan.bind()
+    plan.set_green_kernels()
+    src = [[torch.from_numpy(np.ascontiguousarray(S[n][l]).reshape((4,) + plan.dims[n])).to("cuda")
+            for n in range(2)] for l in range(L + 1)]
+    outs = [torch.empty((4,) + d, dtype=torch.float64, device="cuda") for d in plan.dims]
+    times, got = [], None
+    for rep in range(3):
+        if rep:
+            plan.bind()            # restart the step sequence on the same plan
+            plan.set_green_kernels()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for l in range(L + 1):
+            plan.push_sources(l, src[l])
+            plan.retarded_step(l, outs)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    got = [o.cpu().numpy().reshape(4, -1) for o in outs]
+    el = min(times)
+    pts = plan.stats()["points"]
+    t0 = time.perf_counter()
+    ref = oracle.potential_full(system, S, range(L + 1))
+    t_oracle = time.perf_counter() - t0
+    r = np.concatenate(ref[L], axis=1)
+    g = np.concatenate(got, axis=1)
+    err = np.max(np.abs(g - r), axis=1) / np.max(np.abs(r), axis=1)
+    cores = len(os.sched_getaffinity(0))
+    log(f"config 1 FP64: {1e3 * el / (L + 1):.3f} ms/step, {pts * (L + 1) / el / 1e6:.2f} M updates/s; "
+        f"oracle {t_oracle:.1f} s on {cores} cores; rel err at step {L}: {np.array2string(err, precision=2)}")
+    line = {"metric": METRIC, "value": pts * (L + 1) / el, "unit": "grid-point updates/s", "n_gpus": 1,
+            "steps": L + 1, "warmup": 0, "ms_per_step": 1e3 * el / (L + 1), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "2 sub-domains of 16^3 points, h=0.5 bohr, centres 30 bohr apart, dt=0.02, "
+                                   "41 steps (step 0 included), FP64, best of 3 runs",
+                       "rel_err_vs_fp64_oracle_last_step": [float(v) for v in err]},
+            "roofline": None,
+            "cpu_baseline": {"value": pts * (L + 1) / t_oracle, "unit": "grid-point updates/s", "cores": cores,
+                             "kind": "oracle", "sample": f"the full run: {L + 1} steps x {pts} points",
+                             "seconds": t_oracle}}
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
 def bench_surrogate(args):
     """32 sub-domains of 48^3 in a 2000-bohr box with the learned far-pair
     surrogate: teacher data from the plain method on other seeds (audit
@@ -346,10 +402,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lagsum-unroll", type=int, default=None, choices=[1, 2, 4])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default lag-sum schedule")
-    ap.add_argument("--workload", default="scale", choices=["scale", "batched", "surrogate"],
+    ap.add_argument("--workload", default="scale", choices=["scale", "batched", "surrogate", "small"],
                     help="scale: 8 x 64^3 (the metric's workload); batched: 64 independent systems "
                          "(2-8 domains of 16^3/24^3/32^3) in one plan, one graph launch per step; "
-                         "surrogate: 32 x 48^3 in a 2000-bohr box with the learned far-pair surrogate")
+                         "surrogate: 32 x 48^3 in a 2000-bohr box with the learned far-pair surrogate; "
+                         "small: 2 x 16^3 in FP64 beside the oracle's full run")
     ap.add_argument("--teacher-seeds", type=int, nargs="+", default=[101, 102, 103])
     ap.add_argument("--teacher-audit", type=int, default=3, help="audit sources per teacher system")
     ap.add_argument("--audit", type=int, nargs="*", default=[0, 1], help="audit sources of the timed run")
@@ -373,6 +430,8 @@ def main():
         return bench_batched(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    if args.workload == "small":
+        return bench_small(args)
     system = config2(args.seed)
     workload = "8 sub-domains of 64^3 points, h=0.3 bohr, 400-bohr box, dt=0.01, FFT pad 128^3"
     stream = torch.cuda.current_stream()
@@ -460,6 +519,7 @@ def main():
                    "green_setup_s": round(t_green, 3),
                    "lagsum_unroll": plan.get_tuning("lagsum_unroll"),
                    "lagsum_persistent": plan.get_tuning("lagsum_persistent"),
+                   "fft_lds": plan.get_tuning("fft_lds"),
                    "autotuned": tuned is not None},
         "roofline": roof,
         "cpu_baseline": cpu,

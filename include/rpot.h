@@ -177,17 +177,21 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
  *                              device drains the work list (system group x
  *                              frequency tile, longest first) through a device
  *                              counter; 0: one block per work item.
+ *   RP_TUNE_FFT_LDS            complex values an FFT line-pass block stages in
+ *                              LDS (whole lines): 2048, 4096 (default) or 6144
+ *                              in FP32 (half as many in FP64); 0 = default.
  * Setting a knob discards a captured step (rp_capture_step).
  */
-enum { RP_TUNE_LAGSUM_UNROLL = 1, RP_TUNE_LAGSUM_PERSISTENT = 2 };
+enum { RP_TUNE_LAGSUM_UNROLL = 1, RP_TUNE_LAGSUM_PERSISTENT = 2, RP_TUNE_FFT_LDS = 4 };
 rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value);
 rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value);
 
 /*
  * Autotuner: times every lag-sum schedule (unroll x persistent) `iters` times
- * on the bound plan (after rp_set_green_kernels; only accumulator scratch is
- * written, the step sequence is untouched), keeps the fastest and returns it
- * with its mean kernel time.  Synchronises the stream.  Output pointers may be
+ * on the bound plan (after rp_set_green_kernels; only accumulator and FFT
+ * scratch are written, the step sequence is untouched), keeps the fastest and
+ * returns it with its mean kernel time; then times the inverse line passes at
+ * every line-pass tile and keeps the fastest (read it with rp_get_tuning).  Synchronises the stream.  Output pointers may be
  * NULL.  Discards a captured step.
  */
 rp_status rp_autotune(rp_plan plan, int32_t iters, int32_t *unroll, int32_t *persistent,

@@ -20,7 +20,7 @@ EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_set
            "rp_mlp_loss_grad", "rp_mlp_train_step", "rp_mlp_destroy", "rp_plan_destroy", "rp_last_error",
            "rp_mlp_last_error", "rp_surrogate_configure", "rp_surrogate_info", "rp_surrogate_pairs",
            "rp_surrogate_attach", "rp_surrogate_features", "rp_surrogate_pair_response", "rp_surrogate_judge"]
-TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2}
+TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2, "fft_lds": 4}
 
 
 class RpotError(RuntimeError):

@@ -154,9 +154,9 @@ struct Store<T, RING_BF16> {
     }
 };
 
-template <typename T, int FMT>
+template <typename T, int FMT, int E>
 __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
-    constexpr int E = Lds<T>::E;
+    static_assert((E + kMaxFft) * sizeof(Cx<T>) <= 64 * 1024, "line-pass LDS above 64 KiB");
     constexpr int NT = kFftThreads;
     constexpr int BMAX = (E / 2 + NT - 1) / NT;
     __shared__ Cx<T> buf[E];
@@ -241,9 +241,28 @@ static void fill_stage_divisors(RadixPlan &rp, int P) {
     }
 }
 
+template <typename T, int FMT>
+static void launch_line_e(const LinePass &a, dim3 grid, int E, hipStream_t st) {
+    // E is the staged element count of the T path (the FP64 path stages half)
+    switch (E) {
+    case Lds<T>::E / 2: hipLaunchKernelGGL((k_line_pass<T, FMT, Lds<T>::E / 2>), grid, dim3(kFftThreads), 0, st, a); break;
+    case Lds<T>::E * 3 / 2:
+        hipLaunchKernelGGL((k_line_pass<T, FMT, Lds<T>::E * 3 / 2>), grid, dim3(kFftThreads), 0, st, a);
+        break;
+    default: hipLaunchKernelGGL((k_line_pass<T, FMT, Lds<T>::E>), grid, dim3(kFftThreads), 0, st, a); break;
+    }
+}
+
+int line_pass_elems(int lds_elems, int prec64) {
+    const int base = prec64 ? Lds<double>::E : Lds<float>::E;
+    if (lds_elems == 2048) return base / 2;
+    if (lds_elems == 6144) return base * 3 / 2;
+    return base;
+}
+
 void launch_line_pass(const LinePass &a0, int prec64, hipStream_t st) {
     LinePass a = a0;
-    const int E = prec64 ? Lds<double>::E : Lds<float>::E;
+    const int E = line_pass_elems(a.lds_elems, prec64);
     const int L = E / a.P;
     a.L = L;
     a.dL = FastDiv(uint32_t(L));
@@ -253,23 +272,14 @@ void launch_line_pass(const LinePass &a0, int prec64, hipStream_t st) {
     fill_stage_divisors(a.rp, a.P);
     dim3 grid((a.lines + L - 1) / L, a.n_jobs);
     if (prec64) {
-        if (a.out_fmt == RING_F64)
-            hipLaunchKernelGGL((k_line_pass<double, RING_F64>), grid, dim3(kFftThreads), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_line_pass<double, RING_F32>), grid, dim3(kFftThreads), 0, st, a);
+        if (a.out_fmt == RING_F64) launch_line_e<double, RING_F64>(a, grid, E, st);
+        else launch_line_e<double, RING_F32>(a, grid, E, st);
     } else {
         switch (a.out_fmt) {
-        case RING_F64:
-            hipLaunchKernelGGL((k_line_pass<float, RING_F64>), grid, dim3(kFftThreads), 0, st, a);
-            break;
-        case RING_F16:
-            hipLaunchKernelGGL((k_line_pass<float, RING_F16>), grid, dim3(kFftThreads), 0, st, a);
-            break;
-        case RING_BF16:
-            hipLaunchKernelGGL((k_line_pass<float, RING_BF16>), grid, dim3(kFftThreads), 0, st, a);
-            break;
-        default:
-            hipLaunchKernelGGL((k_line_pass<float, RING_F32>), grid, dim3(kFftThreads), 0, st, a);
+        case RING_F64: launch_line_e<float, RING_F64>(a, grid, E, st); break;
+        case RING_F16: launch_line_e<float, RING_F16>(a, grid, E, st); break;
+        case RING_BF16: launch_line_e<float, RING_BF16>(a, grid, E, st); break;
+        default: launch_line_e<float, RING_F32>(a, grid, E, st);
         }
     }
 }

@@ -521,6 +521,7 @@ const void *tw_ptr(rp_plan p, int P, bool dbl) { return p->ws + (dbl ? p->tw64.a
 LinePass line_pass(rp_plan p, int P, bool dbl, int dir) {
     LinePass a{};
     a.P = P;
+    a.lds_elems = p->fft_lds;
     a.dir = dir;
     a.tw = tw_ptr(p, P, dbl);
     a.rp = make_radix(P);
@@ -1049,8 +1050,32 @@ void do_launch_graph(rp_plan p, int64_t step) {
     p->next_step += 1;
 }
 
-// Time every lag-sum schedule on the bound plan (its current ring and
-// spectra; only the accumulator scratch is written) and keep the fastest.
+// The inverse x and y passes of every target (accumulator -> temporaries
+// only): the autotuner's probe of the line-pass tile.
+void enqueue_inverse_xy(rp_plan p, hipStream_t st) {
+    for (const ClassP &K : p->cls) {
+        for (size_t j0 = 0; j0 < K.doms.size(); j0 += kMaxJobs) {
+            const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
+            LinePass x = inv_x(p, K.N, K.P, K.Hz, p->p64);
+            LinePass y = inv_y(p, K.N, K.P, K.Hz, p->p64);
+            x.n_jobs = y.n_jobs = cnt;
+            for (int j = 0; j < cnt; ++j) {
+                const DomainP &d = p->dom[K.doms[j0 + j]];
+                x.jobs[j].in = p->ws + d.off_acc;
+                x.jobs[j].out = p->ws + d.off_t2;
+                y.jobs[j].in = p->ws + d.off_t2;
+                y.jobs[j].out = p->ws + d.off_t1;
+            }
+            launch_line_pass(x, p->p64, st);
+            launch_line_pass(y, p->p64, st);
+            check_launch();
+        }
+    }
+}
+
+// Time every lag-sum schedule and line-pass tile on the bound plan (its
+// current ring and spectra; only the accumulator and FFT temporaries are
+// written) and keep the fastest.
 void do_autotune(rp_plan p, int iters, int32_t *best_unroll, int32_t *best_persist, double *best_ms) {
     if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
     if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
@@ -1083,8 +1108,34 @@ void do_autotune(rp_plan p, int iters, int32_t *best_unroll, int32_t *best_persi
         (void)hipEventDestroy(e1);
         throw;
     }
+    // line-pass tile
+    int bf = p->fft_lds;
+    try {
+        double bt = 1e300;
+        const int saved = p->fft_lds;
+        for (int e : {2048, 4096, 6144}) {
+            p->fft_lds = e;
+            enqueue_inverse_xy(p, st);   // warm-up
+            HIP_OK(hipEventRecord(e0, st));
+            for (int i = 0; i < iters; ++i) enqueue_inverse_xy(p, st);
+            HIP_OK(hipEventRecord(e1, st));
+            HIP_OK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < bt) {
+                bt = ms;
+                bf = e;
+            }
+        }
+        p->fft_lds = saved;
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    p->fft_lds = bf;
     p->k2_unroll = bu;
     p->k2_persist = bp;
     if (best_unroll) *best_unroll = bu;
@@ -1262,6 +1313,11 @@ rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value) {
             if (value != 0 && value != 1) fail(RP_ERR_ARG, "persistent must be 0 or 1");
             plan->k2_persist = value;
             break;
+        case RP_TUNE_FFT_LDS:
+            if (value != 0 && value != 2048 && value != 4096 && value != 6144)
+                fail(RP_ERR_ARG, "line-pass tile must be 0, 2048, 4096 or 6144");
+            plan->fft_lds = value;
+            break;
         default:
             fail(RP_ERR_ARG, "unknown tuning knob");
         }
@@ -1275,6 +1331,7 @@ rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value) {
         switch (knob) {
         case RP_TUNE_LAGSUM_UNROLL: *value = plan->k2_unroll; break;
         case RP_TUNE_LAGSUM_PERSISTENT: *value = plan->k2_persist; break;
+        case RP_TUNE_FFT_LDS: *value = plan->fft_lds ? plan->fft_lds : 4096; break;
         default: fail(RP_ERR_ARG, "unknown tuning knob");
         }
     });

@@ -162,6 +162,7 @@ struct rp_plan_s {
     std::vector<rpot::DomDev> domdev;     // domains, then judge slots
     int k2_unroll = 1;   // lags whose loads a lag-sum thread issues together
     int k2_persist = 0;  // persistent lag-sum launch (work counter) instead of one block per item
+    int fft_lds = 0;     // line-pass tile: complex elements staged per block (0: default)
     int n_cu = 0;        // compute units of the bound device
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

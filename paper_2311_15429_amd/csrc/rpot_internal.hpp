@@ -67,6 +67,8 @@ struct LinePass {
     int P, n_in, n_out;
     int lines, n_inner;
     int L;                 // lines per block (set by the launcher)
+    int lds_elems;         // complex elements staged per block: 0 (default 4096), 2048, 4096 or 6144
+                           // (FP32; half of it in FP64)
     FastDiv dL, dP, dinner, dnout;   // set by the launcher
     int64_t in_j, in_inner, in_outer;
     int64_t out_j, out_inner, out_outer;

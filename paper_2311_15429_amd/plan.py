@@ -29,6 +29,7 @@ class Plan:
         if dims.shape != origins.shape:
             raise ValueError("dims and origins must both be [n][3]")
         self.n_dom = dims.shape[0]
+        self.n_systems = 1 if system_id is None else len(set(int(v) for v in system_id))
         self.dims = [tuple(int(v) for v in d) for d in dims]
         self.precision = precision
         if precision not in _lib.PRECISION:
@@ -137,13 +138,53 @@ class Plan:
         _lib.check(self._lib, self._h, self._lib.rp_get_tuning(self._h, _lib.TUNE[knob], ctypes.byref(v)))
         return int(v.value)
 
-    def autotune(self, iters=3):
-        """Time every lag-sum schedule on this bound plan and keep the fastest.
-        Returns {"lagsum_unroll", "lagsum_persistent", "lagsum_ms"}."""
+    def shape_key(self):
+        """Autotuner cache key: device, precision and the plan's shape classes
+        (grid and FFT pad per domain, with counts) and system count."""
+        import torch
+        classes = {}
+        for n, d in enumerate(self.dims):
+            pad = self.info(n, n)[2]
+            classes[(d, pad)] = classes.get((d, pad), 0) + 1
+        sig = ";".join(f"{d[0]}x{d[1]}x{d[2]}/{p[0]}x{p[1]}x{p[2]}*{c}" for (d, p), c in sorted(classes.items()))
+        return f"{torch.cuda.get_device_name()}|{self.precision}|{sig}|systems={self.n_systems}"
+
+    def autotune(self, iters=3, cache=None):
+        """Time every lag-sum schedule and line-pass tile on this bound plan
+        and keep the fastest.  With `cache` (a JSON file path) a stored choice
+        for the same device and shape classes is applied without timing, and a
+        new choice is stored.  Returns {"lagsum_unroll", "lagsum_persistent",
+        "fft_lds", "lagsum_ms", "cached"}."""
+        import json
+        import os
+        key = self.shape_key() if cache else None
+        if cache and os.path.exists(cache):
+            try:
+                rec = json.load(open(cache)).get(key)
+            except (OSError, ValueError):
+                rec = None
+            if rec:
+                for k in ("lagsum_unroll", "lagsum_persistent", "fft_lds"):
+                    self.set_tuning(k, rec[k])
+                return dict(rec, cached=True)
         u, pe, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         _lib.check(self._lib, self._h, self._lib.rp_autotune(self._h, int(iters), ctypes.byref(u),
                                                              ctypes.byref(pe), ctypes.byref(ms)))
-        return {"lagsum_unroll": int(u.value), "lagsum_persistent": int(pe.value), "lagsum_ms": float(ms.value)}
+        res = {"lagsum_unroll": int(u.value), "lagsum_persistent": int(pe.value),
+               "fft_lds": self.get_tuning("fft_lds"), "lagsum_ms": float(ms.value)}
+        if cache:
+            data = {}
+            if os.path.exists(cache):
+                try:
+                    data = json.load(open(cache))
+                except (OSError, ValueError):
+                    data = {}
+            data[key] = res
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(res, cached=False)
 
     def capture_step(self, sources, outputs):
         """Record one whole step for these fixed buffers as a HIP graph."""

@@ -137,3 +137,15 @@ def test_paper_run_windows_do_not_grow_with_distance():
         assert pad == (108, 108, 256)
     assert max(widths) == widths[0] and min(widths) >= 0.5 * widths[0]
     assert depths[-1] > 1300 and depths[0] < 100
+
+
+def test_fft_tile_knob_host():
+    from paper_2311_15429_amd import RpotError, plan_for_system
+    p = plan_for_system(sy.config1(1), "fp32")
+    assert p.get_tuning("fft_lds") == 4096
+    for v in (2048, 6144, 0):
+        p.set_tuning("fft_lds", v)
+    with pytest.raises(RpotError) as e:
+        p.set_tuning("fft_lds", 1000)
+    assert e.value.status == "RP_ERR_ARG"
+    p.close()

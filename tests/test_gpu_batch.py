@@ -153,8 +153,10 @@ def test_autotune_selects_a_valid_schedule():
     p = _plan(s, "fp32")
     res = p.autotune(iters=2)
     assert res["lagsum_unroll"] in (1, 2, 4) and res["lagsum_persistent"] in (0, 1)
+    assert res["fft_lds"] in (2048, 4096, 6144) and not res["cached"]
     assert res["lagsum_ms"] > 0
     assert p.get_tuning("lagsum_unroll") == res["lagsum_unroll"]
+    assert p.get_tuning("fft_lds") == res["fft_lds"]
     outs = [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in p.dims]
     for l in range(L + 1):
         p.push_sources(l, _src(S, l, p.dims, torch.float32))
@@ -181,3 +183,19 @@ def test_launch_step_requires_capture_and_order():
     p.launch_step(1)
     torch.cuda.synchronize()
     p.close()
+
+
+def test_autotune_cache(tmp_path):
+    """The second plan of the same shapes takes the stored choice."""
+    from test_gpu_parity import _uneven_system
+    cache = str(tmp_path / "tune.json")
+    s = _uneven_system(11)
+    p = _plan(s, "fp32")
+    first = p.autotune(iters=1, cache=cache)
+    p.close()
+    q = _plan(s, "fp32")
+    second = q.autotune(iters=1, cache=cache)
+    assert second["cached"] and not first["cached"]
+    for k in ("lagsum_unroll", "lagsum_persistent", "fft_lds"):
+        assert second[k] == first[k] == q.get_tuning(k)
+    q.close()

@@ -150,3 +150,16 @@ def test_deterministic_reruns_fp32():
     for l in a:
         for x, y in zip(a[l], b[l]):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision,tile", [("fp32", 2048), ("fp32", 6144), ("fp64", 2048), ("fp64", 6144)])
+def test_line_pass_tiles(precision, tile):
+    """Every line-pass tile (lines staged per block) gives the oracle's result
+    on the uneven radix-2/3/4 shapes."""
+    s = _uneven_system(10)
+    L = 12
+    S = _samples(s, L)
+    got = run_gpu(s, precision, S, collect=[L], tune={"fft_lds": tile})
+    ref = oracle.potential_full(s, S, [L])[0]
+    e = rel_err(got[L], ref)
+    assert np.all(e <= (FP64_TOL if precision == "fp64" else FP32_TOL)), e
