@@ -254,7 +254,7 @@ def bench_surrogate(args):
     # teacher data
     t0 = time.perf_counter()
     X, T = [], []
-    for seed in args.teacher_seeds:
+    for seed in (args.teacher_seeds if args.far == "learned" else []):
         tsys = config5(seed)
         p = plan_for_system(tsys, "fp32", stream=stream)
         p.surrogate_configure(FAR, n_lags=NL, audit=range(args.teacher_audit))
@@ -268,17 +268,19 @@ def bench_surrogate(args):
         del p
         torch.cuda.empty_cache()
         log(f"  {x.shape[0]} samples, {time.perf_counter() - t0:.0f} s")
-    X, T = torch.cat(X), torch.cat(T)
-    t_data = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    sur = S.train_surrogate(X, T, NL, max_batch=2048, log_every=5000, log=log)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    train_rms = S.relative_rms(sur, X, T)
-    n_samples = int(X.shape[0])
-    del X, T
-    torch.cuda.empty_cache()
-    log(f"trained on {n_samples} pair responses in {t_train:.0f} s, train rel rms {train_rms:.2e}")
+    sur, n_samples, t_data, t_train, train_rms = None, 0, 0.0, 0.0, None
+    if args.far == "learned":
+        X, T = torch.cat(X), torch.cat(T)
+        t_data = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sur = S.train_surrogate(X, T, NL, max_batch=2048, log_every=5000, log=log)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        train_rms = S.relative_rms(sur, X, T)
+        n_samples = int(X.shape[0])
+        del X, T
+        torch.cuda.empty_cache()
+        log(f"trained on {n_samples} pair responses in {t_train:.0f} s, train rel rms {train_rms:.2e}")
 
     # the workload
     system = config5(args.seed)
@@ -293,7 +295,10 @@ def bench_surrogate(args):
         f"(plain FP32 would need {(pst['ring_bytes'] + pst['spectra_bytes']) / 1e9:.0f} GB of history)")
     plan.bind()
     plan.set_green_kernels()
-    plan.surrogate_attach(sur.mlp, sur.in_scale, sur.out_scale)
+    if sur is not None:
+        plan.surrogate_attach(sur.mlp, sur.in_scale, sur.out_scale)
+    else:
+        plan.surrogate_multipole(True)
     tuned = plan.autotune(iters=3)
     gen = Gen(system)
     outs = [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in plan.dims]
@@ -370,7 +375,9 @@ def bench_surrogate(args):
             "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "32 sub-domains of 48^3 points, h=0.3 bohr, 2000-bohr box, dt=0.01, "
-                                   "learned far-pair surrogate (pairs > 10 box diagonals apart)",
+                                   + ("learned far-pair surrogate" if args.far == "learned"
+                                      else "analytic multipole far-pair terms")
+                                   + " (pairs > 10 box diagonals apart)",
                        "precision": precision, "far_pairs": info["n_far"], "audited_far_pairs": info["n_audited"],
                        "judge_every": JUDGE_EVERY, "judge_tol": TOL, "fallbacks": fell,
                        "rel_err_vs_fp64_oracle_sampled": [float(v) for v in err_s],
@@ -407,6 +414,8 @@ def main():
                          "(2-8 domains of 16^3/24^3/32^3) in one plan, one graph launch per step; "
                          "surrogate: 32 x 48^3 in a 2000-bohr box with the learned far-pair surrogate; "
                          "small: 2 x 16^3 in FP64 beside the oracle's full run")
+    ap.add_argument("--far", default="learned", choices=["learned", "multipole"],
+                    help="surrogate workload: far-pair terms from the trained network or the analytic multipole")
     ap.add_argument("--teacher-seeds", type=int, nargs="+", default=[101, 102, 103])
     ap.add_argument("--teacher-audit", type=int, default=3, help="audit sources per teacher system")
     ap.add_argument("--audit", type=int, nargs="*", default=[0, 1], help="audit sources of the timed run")

@@ -311,6 +311,21 @@ rp_status rp_surrogate_info(rp_plan plan, int32_t *n_far, int32_t *n_audited, in
 rp_status rp_surrogate_pairs(rp_plan plan, int32_t *target, int32_t *source, double *dist, int32_t *audited,
                              int32_t *fallen_back);
 rp_status rp_surrogate_attach(rp_plan plan, rp_mlp mlp, const float *in_scale, const float *out_scale);
+/*
+ * Analytic multipole far-pair terms instead of a network (enable != 0; it
+ * detaches any network; 0 switches them off).  For every far pair the
+ * retarded multipole field of the source is evaluated at a 4 x 4 x 4 node grid
+ * of the target box (box coordinates -1, -1/3, 1/3, 1) and fitted to the box
+ * basis.  With R from the source centre, u = R/|R|, the moments at the retarded
+ * time (cubic interpolation in time, which also gives the time derivatives):
+ *   v   = q/R + u.p/R^2 + u.p'/(cR) + (3 u.Q.u - tr Q)/(2R^3)
+ *         + (3 u.Q'.u - tr Q')/(2cR^2) + u.Q''.u/(2c^2 R),
+ *   A_i = J_i/R + (K u)_i/R^2 + (K' u)_i/(cR).
+ * The multipole approximation of far sub-domains named in Sec. V; it needs no
+ * training.  The judge and fallback work as with a network.  Discards a
+ * captured step.
+ */
+rp_status rp_surrogate_multipole(rp_plan plan, int32_t enable);
 rp_status rp_surrogate_features(rp_plan plan, float *x);
 rp_status rp_surrogate_pair_response(rp_plan plan, float *coef, float *resid);
 rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t *n_fallback, double *worst);

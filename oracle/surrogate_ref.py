@@ -161,3 +161,70 @@ def frame_synth(system, s, n, a):
     B = basis(frame_coords(system, s, R))
     G = (B @ a.T).T
     return np.vstack([G[0][None, :], R.T @ G[1:4]])
+
+
+# ---------------------------------------------------------------------------
+# Analytic multipole field of a far source (the non-learned far-pair path).
+#
+# With R the vector from the source centre to the target point, u = R/|R|,
+# tau = t - |R|/c and the moments f(tau) of dS (dots: time derivatives):
+#   v   = q/R + u.p/R^2 + u.p'/(c R)
+#         + (3 u.Q.u - tr Q)/(2 R^3) + (3 u.Q'.u - tr Q')/(2 c R^2) + u.Q''.u/(2 c^2 R)
+#   A_i = J_i/R + u.K_i/R^2 + u.K_i'/(c R)
+# the retarded Taylor expansion of sum_r' dS(r', t - |R - r'|/c)/|R - r'| to
+# second order in r' (to first order for the current, whose second moments
+# are not kept).  The moments between samples are cubic Lagrange
+# interpolants of the four samples around tau.
+
+def _cubic_weights(u):
+    """Value, first and second derivative weights (per step) at u in [0, 1)
+    for samples at -1, 0, 1, 2."""
+    x = np.array([-1.0, 0.0, 1.0, 2.0])
+    w, d1, d2 = np.zeros(4), np.zeros(4), np.zeros(4)
+    for k in range(4):
+        others = [x[j] for j in range(4) if j != k]
+        den = np.prod([x[k] - o for o in others])
+        # polynomial prod (u - o) / den: value, first and second derivative
+        a, b, c_ = others
+        w[k] = (u - a) * (u - b) * (u - c_) / den
+        d1[k] = ((u - b) * (u - c_) + (u - a) * (u - c_) + (u - a) * (u - b)) / den
+        d2[k] = 2.0 * ((u - a) + (u - b) + (u - c_)) / den
+    return w, d1, d2
+
+
+def multipole_field(system, samples, s, n, l, pts):
+    """v and A [4][len(pts)] of source n at points pts [n][3] and step l."""
+    h, dt, c = system.h, system.dt, system.c
+    dom = system.domains[n]
+    cn = box_centre(dom, h)
+    mom = {}
+
+    def m_at(t):
+        if t <= 0:
+            return np.zeros(N_FEAT)
+        if t not in mom:
+            mom[t] = moments(samples[n][t] - samples[n][0], dom, h)
+        return mom[t]
+
+    out = np.zeros((4, len(pts)))
+    for k, r in enumerate(np.asarray(pts, dtype=np.float64)):
+        Rv = r - cn
+        R = float(np.linalg.norm(Rv))
+        u = Rv / R
+        tau = l - R / (c * dt)
+        a = int(np.floor(tau))
+        w, d1, d2 = _cubic_weights(tau - a)
+        F = np.stack([m_at(a - 1 + j) for j in range(4)])
+        f0, f1, f2 = w @ F, (d1 @ F) / dt, (d2 @ F) / (dt * dt)
+
+        def Qm(f):
+            return np.array([[f[4], f[7], f[8]], [f[7], f[5], f[9]], [f[8], f[9], f[6]]])
+        v = f0[0] / R + u @ f0[1:4] / R ** 2 + u @ f1[1:4] / (c * R)
+        v += (3 * u @ Qm(f0) @ u - np.trace(Qm(f0))) / (2 * R ** 3)
+        v += (3 * u @ Qm(f1) @ u - np.trace(Qm(f1))) / (2 * c * R ** 2)
+        v += (u @ Qm(f2) @ u) / (2 * c * c * R)
+        K0, K1 = f0[13:22].reshape(3, 3), f1[13:22].reshape(3, 3)
+        A = f0[10:13] / R + K0 @ u / R ** 2 + K1 @ u / (c * R)
+        out[0, k] = v
+        out[1:4, k] = A
+    return out

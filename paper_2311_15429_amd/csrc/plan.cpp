@@ -1386,6 +1386,10 @@ rp_status rp_surrogate_attach(rp_plan plan, rp_mlp mlp, const float *in_scale, c
     return guarded(plan, [&] { sur_attach(plan, mlp, in_scale, out_scale); });
 }
 
+rp_status rp_surrogate_multipole(rp_plan plan, int32_t enable) {
+    return guarded(plan, [&] { sur_multipole(plan, enable); });
+}
+
 rp_status rp_surrogate_features(rp_plan plan, float *x) {
     return guarded(plan, [&] { sur_features(plan, x); });
 }

@@ -138,6 +138,8 @@ struct SurrogateH {
     std::vector<int32_t> h_order, h_tbeg;   // active far pairs by target (CSR)
     rp_mlp mlp = nullptr;
     bool attached = false;
+    bool multipole = false;        // analytic multipole far-pair terms instead of the network
+    size_t off_pinv = 0;           // [kNBasis][64] node-to-coefficient fit
 };
 
 }  // namespace rpot_host
@@ -224,6 +226,7 @@ void sur_attach(rp_plan p, rp_mlp mlp, const float *in_scale, const float *out_s
 void sur_features(rp_plan p, float *x);
 void sur_pair_response(rp_plan p, float *coef, float *resid);
 void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, double *worst);
+void sur_multipole(rp_plan p, int enable);
 void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int));
 
 }  // namespace rpot_host

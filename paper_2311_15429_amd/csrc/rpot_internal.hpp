@@ -279,6 +279,8 @@ struct FarPair {
     float rot[9];
     float inv_d;           // 1 / |c_s - c_n|
     float geo[kNGeo];      // (r_ref / |c_s - c_n|, |c_s - c_n| / (c dt) - m_c)
+    float d[3];            // c_s - c_n
+    float hw[3];           // half side of the target box per axis
 };
 struct FeatArgs {
     const FarPair *pairs;
@@ -375,6 +377,21 @@ void launch_coef_sum(const CoefArgs &a, hipStream_t st);
 void launch_synthesize(const SynthArgs &a, hipStream_t st);
 void launch_project(const ProjArgs &a, bool fit, hipStream_t st);
 void launch_budget(const BudgetArgs &a, hipStream_t st);
+// Analytic multipole far-pair terms: the retarded multipole field of every
+// far pair's source at a 4 x 4 x 4 node grid on the target box
+// (xi in {-1, -1/3, 1/3, 1} per axis), fitted to the box basis by pinv
+// ([kNBasis][64]), into pc ([n_pairs][kNOut]).
+struct MultipoleArgs {
+    const FarPair *pairs;
+    const float *moments;  // [n_src][depth][kFeatStride]
+    const float *pinv;
+    float *pc;
+    const int64_t *step;
+    int depth;
+    int n_pairs;
+    float inv_cdt, c, dt;
+};
+void launch_multipole(const MultipoleArgs &a, hipStream_t st);
 void launch_correct(const CorrArgs &a, hipStream_t st);
 
 // Network forward pass of the surrogate on a given stream (mlp.hip).

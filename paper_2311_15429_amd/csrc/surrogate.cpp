@@ -305,6 +305,9 @@ void sur_classify(rp_plan p) {
             U.src_doms.push_back(F.n);
         }
         U.mom_depth = std::max(U.mom_depth, F.m_c - U.n_lags / 2 + U.n_lags);
+        // the multipole path reads up to the farthest node's retarded step plus
+        // the interpolation stencil
+        U.mom_depth = std::max(U.mom_depth, int(std::ceil((F.dist + 0.5 * diagonal(p, F.s)) / cdt)) + 4);
         if (F.audited) U.aud.push_back(int(&F - U.pairs.data()));
         const int c = p->dom[F.s].cls;
         if (std::find(U.far_cls.begin(), U.far_cls.end(), c) == U.far_cls.end()) U.far_cls.push_back(c);
@@ -347,6 +350,7 @@ void sur_layout(rp_plan p, size_t &off) {
     U.off_mats = alloc(nf * 2 * kNBasis * kNBasis * 4);
     U.off_inscale = alloc(kNFeat * 4);
     U.off_outscale = alloc(kNOut * 4);
+    U.off_pinv = alloc(kNBasis * 64 * 4);
     U.off_Q.clear();
     U.jt1_elems = U.jt2_elems = U.jF_elems = 0;
     for (int c : U.far_cls) {
@@ -394,6 +398,10 @@ void sur_bind(rp_plan p) {
         D.inv_d = float(1.0 / F.dist);
         D.geo[0] = float(10.0 * dbar / F.dist);
         D.geo[1] = float(F.frac);
+        for (int a = 0; a < 3; ++a) {
+            D.d[a] = float(centre(p, F.s, a) - centre(p, F.n, a));
+            D.hw[a] = float(0.5 * p->h * (p->dom[F.s].N[a] - 1));
+        }
     }
     std::vector<int32_t> aud(U.aud.begin(), U.aud.end());
     std::vector<float> ones(kNOut, 1.0f);
@@ -404,6 +412,28 @@ void sur_bind(rp_plan p) {
     if (!aud.empty()) HIP_OK(hipMemcpy(p->ws + U.off_aud, aud.data(), aud.size() * 4, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(p->ws + U.off_inscale, ones.data(), kNFeat * 4, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(p->ws + U.off_outscale, ones.data(), kNOut * 4, hipMemcpyHostToDevice));
+    {
+        // node-to-coefficient fit of the multipole path: (B^T B)^-1 B^T on the
+        // 4 x 4 x 4 nodes xi in {-1, -1/3, 1/3, 1}
+        const double nodes[4] = {-1.0, -1.0 / 3.0, 1.0 / 3.0, 1.0};
+        std::vector<double> B(64 * kNBasis), G(kNBasis * kNBasis, 0.0);
+        for (int t = 0; t < 64; ++t) {
+            const double xi[3] = {nodes[t >> 4], nodes[(t >> 2) & 3], nodes[t & 3]};
+            basis_row(xi, &B[size_t(t) * kNBasis]);
+        }
+        for (int t = 0; t < 64; ++t)
+            for (int a = 0; a < kNBasis; ++a)
+                for (int b = 0; b < kNBasis; ++b) G[a * kNBasis + b] += B[t * kNBasis + a] * B[t * kNBasis + b];
+        const std::vector<double> Gi = spd_inverse(G, kNBasis);
+        std::vector<float> pinv(kNBasis * 64);
+        for (int a = 0; a < kNBasis; ++a)
+            for (int t = 0; t < 64; ++t) {
+                double v = 0;
+                for (int b = 0; b < kNBasis; ++b) v += Gi[a * kNBasis + b] * B[t * kNBasis + b];
+                pinv[a * 64 + t] = float(v);
+            }
+        HIP_OK(hipMemcpy(p->ws + U.off_pinv, pinv.data(), pinv.size() * 4, hipMemcpyHostToDevice));
+    }
     for (const auto &kv : U.off_Q) {
         const std::vector<float> Q = dual_basis(p->cls[kv.first].N);
         HIP_OK(hipMemcpy(p->ws + kv.second, Q.data(), Q.size() * 4, hipMemcpyHostToDevice));
@@ -466,18 +496,33 @@ FeatArgs feat_args(rp_plan p, float *x, int64_t adj) {
 void sur_enqueue_infer(rp_plan p, void *const *out, hipStream_t st) {
     SurrogateH &U = p->sur;
     const int nf = int(U.pairs.size());
-    if (!U.attached || nf == 0) return;
-    launch_features(feat_args(p, p->at<float>(U.off_x), 0), st);
-    mlp_forward_on(U.mlp, p->at<float>(U.off_x), nf, p->at<float>(U.off_y), st);
-    XformArgs xa{};
-    xa.pairs = p->at<FarPair>(U.off_fpairs);
-    xa.mats = p->at<float>(U.off_mats);
-    xa.in = p->at<float>(U.off_y);
-    xa.out = p->at<float>(U.off_pc);
-    xa.scale = p->at<float>(U.off_outscale);
-    xa.dir = 0;
-    xa.n = nf;
-    launch_xform(xa, st);
+    if ((!U.attached && !U.multipole) || nf == 0) return;
+    if (U.multipole) {
+        MultipoleArgs ma{};
+        ma.pairs = p->at<FarPair>(U.off_fpairs);
+        ma.moments = p->at<float>(U.off_mom);
+        ma.pinv = p->at<float>(U.off_pinv);
+        ma.pc = p->at<float>(U.off_pc);
+        ma.step = p->at<int64_t>(p->off_state);
+        ma.depth = U.mom_depth;
+        ma.n_pairs = nf;
+        ma.inv_cdt = float(1.0 / (p->c * p->dt));
+        ma.c = float(p->c);
+        ma.dt = float(p->dt);
+        launch_multipole(ma, st);
+    } else {
+        launch_features(feat_args(p, p->at<float>(U.off_x), 0), st);
+        mlp_forward_on(U.mlp, p->at<float>(U.off_x), nf, p->at<float>(U.off_y), st);
+        XformArgs xa{};
+        xa.pairs = p->at<FarPair>(U.off_fpairs);
+        xa.mats = p->at<float>(U.off_mats);
+        xa.in = p->at<float>(U.off_y);
+        xa.out = p->at<float>(U.off_pc);
+        xa.scale = p->at<float>(U.off_outscale);
+        xa.dir = 0;
+        xa.n = nf;
+        launch_xform(xa, st);
+    }
     CoefArgs ca{};
     ca.pc = p->at<float>(U.off_pc);
     ca.order = p->at<int32_t>(U.off_order);
@@ -541,6 +586,7 @@ void sur_attach(rp_plan p, rp_mlp mlp, const float *in_scale, const float *out_s
         U.attached = false;
         return;
     }
+    U.multipole = false;
     int ni = 0, no = 0, mb = 0;
     if (!mlp_dims(mlp, &ni, &no, &mb)) fail(RP_ERR_STATE, "network workspace not bound");
     if (ni != U.n_in || no != kNOut) fail(RP_ERR_ARG, "network shape does not match the surrogate (n_in, 80)");
@@ -551,6 +597,18 @@ void sur_attach(rp_plan p, rp_mlp mlp, const float *in_scale, const float *out_s
     HIP_OK(hipMemcpy(p->ws + U.off_outscale, out_scale, kNOut * 4, hipMemcpyHostToDevice));
     U.mlp = mlp;
     U.attached = true;
+}
+
+void sur_multipole(rp_plan p, int enable) {
+    SurrogateH &U = p->sur;
+    if (!U.on) fail(RP_ERR_STATE, "surrogate not configured (rp_surrogate_configure)");
+    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    release_graph(p);
+    U.multipole = enable != 0;
+    if (U.multipole) {
+        U.mlp = nullptr;
+        U.attached = false;
+    }
 }
 
 void sur_features(rp_plan p, float *x) {
@@ -600,7 +658,8 @@ void sur_pair_response(rp_plan p, float *coef, float *resid) {
 void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, double *worst) {
     need_ready(p);
     SurrogateH &U = p->sur;
-    if (!U.attached) fail(RP_ERR_STATE, "no network attached (rp_surrogate_attach)");
+    if (!U.attached && !U.multipole)
+        fail(RP_ERR_STATE, "no far-pair terms to judge (rp_surrogate_attach or rp_surrogate_multipole)");
     if (!out) fail(RP_ERR_ARG, "out is null");
     for (int n = 0; n < p->n_dom; ++n)
         if (!out[n]) fail(RP_ERR_ARG, "an out pointer is null");

@@ -359,6 +359,85 @@ __global__ __launch_bounds__(256) void k_correct(CorrArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Analytic multipole far-pair terms (see MultipoleArgs).  With R from the
+// source centre to a node, u = R/|R|, tau the retarded step l - |R|/(c dt)
+// and the moments f of dS at tau (cubic Lagrange interpolation of the four
+// ring samples around tau, which also gives the time derivatives):
+//   v   = q/R + u.p/R^2 + u.p'/(cR) + (3 u.Q.u - tr Q)/(2R^3)
+//         + (3 u.Q'.u - tr Q')/(2cR^2) + u.Q''.u/(2c^2 R)
+//   A_i = J_i/R + (K u)_i/R^2 + (K' u)_i/(cR)
+// (the retarded Taylor expansion of the pair's lag sum to second order in the
+// source coordinates, first order for the current).
+__global__ __launch_bounds__(64) void k_multipole(MultipoleArgs a) {
+    const FarPair &fp = a.pairs[blockIdx.x];
+    const int t = threadIdx.x;
+    const int64_t l = *a.step;
+    const float nodes[4] = {-1.f, -1.f / 3.f, 1.f / 3.f, 1.f};
+    const float Rv[3] = {fp.d[0] + nodes[t >> 4] * fp.hw[0], fp.d[1] + nodes[(t >> 2) & 3] * fp.hw[1],
+                         fp.d[2] + nodes[t & 3] * fp.hw[2]};
+    const float R = sqrtf(Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2]);
+    const float u[3] = {Rv[0] / R, Rv[1] / R, Rv[2] / R};
+    const double tau = double(l) - double(R) * a.inv_cdt;
+    const int64_t a0 = int64_t(floor(tau));
+    const float x = float(tau - double(a0));
+    // cubic Lagrange weights for samples at -1, 0, 1, 2 (value, d/dx, d2/dx2)
+    const float w[4] = {-x * (x - 1.f) * (x - 2.f) / 6.f, (x + 1.f) * (x - 1.f) * (x - 2.f) / 2.f,
+                        -(x + 1.f) * x * (x - 2.f) / 2.f, (x + 1.f) * x * (x - 1.f) / 6.f};
+    const float d1[4] = {-(3.f * x * x - 6.f * x + 2.f) / 6.f, (3.f * x * x - 4.f * x - 1.f) / 2.f,
+                         -(3.f * x * x - 2.f * x - 2.f) / 2.f, (3.f * x * x - 1.f) / 6.f};
+    const float d2[4] = {-(6.f * x - 6.f) / 6.f, (6.f * x - 4.f) / 2.f, -(6.f * x - 2.f) / 2.f, (6.f * x) / 6.f};
+    const float *ring = a.moments + int64_t(fp.src_slot) * a.depth * kFeatStride;
+    float f0[kNFeat], f1[kNFeat], f2[kNFeat];
+#pragma unroll
+    for (int q = 0; q < kNFeat; ++q) f0[q] = f1[q] = f2[q] = 0.f;
+    for (int k = 0; k < 4; ++k) {
+        int64_t ts = a0 - 1 + k;
+        if (ts > l) ts = l;   // never for a far pair; keeps the read inside the held history
+        if (ts <= 0) continue;
+        const float *v = ring + (ts % a.depth) * kFeatStride;
+#pragma unroll
+        for (int q = 0; q < kNFeat; ++q) {
+            f0[q] = fmaf(w[k], v[q], f0[q]);
+            f1[q] = fmaf(d1[k], v[q], f1[q]);
+            f2[q] = fmaf(d2[k], v[q], f2[q]);
+        }
+    }
+    const float idt = 1.f / a.dt, ic = 1.f / a.c, iR = 1.f / R;
+    auto quad = [&](const float *f) {   // u.Q.u and tr Q from (xx yy zz xy xz yz)
+        const float uqu = f[4] * u[0] * u[0] + f[5] * u[1] * u[1] + f[6] * u[2] * u[2] +
+                          2.f * (f[7] * u[0] * u[1] + f[8] * u[0] * u[2] + f[9] * u[1] * u[2]);
+        return make_float2(uqu, f[4] + f[5] + f[6]);
+    };
+    const float2 Q0 = quad(f0), Q1 = quad(f1), Q2 = quad(f2);
+    const float up0 = u[0] * f0[1] + u[1] * f0[2] + u[2] * f0[3];
+    const float up1 = (u[0] * f1[1] + u[1] * f1[2] + u[2] * f1[3]) * idt;
+    float v = f0[0] * iR + up0 * iR * iR + up1 * ic * iR;
+    v += (3.f * Q0.x - Q0.y) * 0.5f * iR * iR * iR;
+    v += (3.f * Q1.x - Q1.y) * idt * 0.5f * ic * iR * iR;
+    v += Q2.x * idt * idt * 0.5f * ic * ic * iR;
+    __shared__ float F[4][64];
+    F[0][t] = v;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float Ku0 = f0[13 + 3 * i] * u[0] + f0[14 + 3 * i] * u[1] + f0[15 + 3 * i] * u[2];
+        const float Ku1 = (f1[13 + 3 * i] * u[0] + f1[14 + 3 * i] * u[1] + f1[15 + 3 * i] * u[2]) * idt;
+        F[1 + i][t] = f0[10 + i] * iR + Ku0 * iR * iR + Ku1 * ic * iR;
+    }
+    __syncthreads();
+    for (int o = t; o < kNOut; o += 64) {
+        const int mu = o / kNBasis, b = o - mu * kNBasis;
+        float acc = 0.f;
+        for (int j = 0; j < 64; ++j) acc = fmaf(a.pinv[b * 64 + j], F[mu][j], acc);
+        a.pc[int64_t(blockIdx.x) * kNOut + o] = acc;
+    }
+}
+
+void launch_multipole(const MultipoleArgs &a, hipStream_t st) {
+    if (a.n_pairs == 0) return;
+    hipLaunchKernelGGL(k_multipole, dim3(a.n_pairs), dim3(64), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
 void launch_moments(const MomentArgs &a, hipStream_t st) {
     if (a.n_jobs == 0) return;
     hipLaunchKernelGGL(k_moments_partial, dim3(kMomChunks, a.n_jobs), dim3(256), 0, st, a);

@@ -238,6 +238,12 @@ class Plan:
             self._h, mlp._h, ins.ctypes.data_as(fp), outs.ctypes.data_as(fp)))
         self._mlp = mlp
 
+    def surrogate_multipole(self, enable=True):
+        """Analytic multipole terms for the far pairs instead of a network."""
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_multipole(self._h, int(bool(enable))))
+        if enable:
+            self._mlp = None
+
     def surrogate_features(self, out=None):
         """Network inputs [n_far][n_in] (FP32, device) of the last completed step."""
         import torch

@@ -204,3 +204,53 @@ def test_graph_replay_with_surrogate_is_bitwise_identical():
     for a, b in zip(*res):
         for x, y in zip(a, b):
             assert np.array_equal(x, y)
+
+
+def _box_synth_from_nodes(system, s, F_nodes):
+    """Oracle side of the multipole path: least-squares fit of node values
+    [4][64] on the 4 x 4 x 4 nodes, synthesised on the target grid."""
+    nodes = np.array([-1.0, -1.0 / 3.0, 1.0 / 3.0, 1.0])
+    xi = np.array([[nodes[t >> 4], nodes[(t >> 2) & 3], nodes[t & 3]] for t in range(64)])
+    Bn = sr.basis(xi)
+    coef, *_ = np.linalg.lstsq(Bn, F_nodes.T, rcond=None)
+    return (sr.basis(sr.box_coords(system.domains[s])) @ coef).T
+
+
+def test_multipole_terms_match_the_oracle_formula():
+    system = far_system(7)
+    L = 60
+    S = sy.sample_sources(system, range(L + 1))
+    gen = GpuSourceGen(system, torch.float32)
+    res = {}
+    for mode in ("multipole", "dropped"):
+        p = make_plan(system, audit=[])
+        if mode == "multipole":
+            p.surrogate_multipole(True)
+        outs = run(p, gen, L)
+        res[mode] = [o.double().cpu().numpy().reshape(4, -1) for o in outs]
+        pairs = p.surrogate_pairs()
+        p.close()
+    h = system.h
+    worst = 0.0
+    for s in sorted(set(int(t) for t in pairs["target"])):
+        dom = system.domains[s]
+        hw = 0.5 * h * (np.array(dom.dims) - 1)
+        nodes = np.array([-1.0, -1.0 / 3.0, 1.0 / 3.0, 1.0])
+        xi = np.array([[nodes[t >> 4], nodes[(t >> 2) & 3], nodes[t & 3]] for t in range(64)])
+        pts = sr.box_centre(dom, h) + xi * hw
+        want = np.zeros((4, dom.n_points))
+        for t_, n in zip(pairs["target"], pairs["source"]):
+            if int(t_) == s:
+                want += _box_synth_from_nodes(system, s, sr.multipole_field(system, S, s, int(n), L, pts))
+        got = res["multipole"][s] - res["dropped"][s]
+        scale = np.max(np.abs(want), axis=1)
+        e = np.max(np.abs(got - want), axis=1) / scale
+        worst = max(worst, float(e.max()))
+        assert np.all(e <= 2e-4), (s, e)
+    # and the far terms bring the total close to the direct sum
+    ref = oracle.potential_full(system, S, [L])[0]
+    e_mp = rel_err(res["multipole"], ref)
+    e_dr = rel_err(res["dropped"], ref)
+    log(f"multipole: formula match {worst:.1e}; total rel err {np.array2string(e_mp, precision=2)} "
+        f"vs far pairs left out {np.array2string(e_dr, precision=2)}")
+    assert np.max(e_mp) <= np.max(e_dr) / 10
