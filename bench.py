@@ -398,6 +398,113 @@ def bench_surrogate(args):
     plan.close()
 
 
+def speedup_model(Wp, Lp, dp):
+    """The paper's cost ratio for two W x W x L domains side by side in a
+    W x d x L box (Sec. III, Eq. of the computational complexity ratio), in
+    grid units: retardation steps times N log N per domain pair."""
+    diag = math.sqrt(dp * dp + Lp * Lp + Wp * Wp)
+    small = Wp * Wp * Lp * math.log(Wp * Wp * Lp)
+    big = diag * Wp * dp * Lp * math.log(Wp * dp * Lp)
+    inv = (2 * diag * small - 2 * (dp - 2 * Wp) * small + 2 * math.sqrt(2 * Wp * Wp + Lp * Lp) * small) / big
+    return 1.0 / inv
+
+
+def _time_graph(plan, src_at, W, K):
+    """ms per graph-launched step after W warm-up steps (the sources for
+    step l come from src_at(l), copied into the captured buffers)."""
+    import torch
+    outs = [torch.empty((4,) + d, dtype=plan.dtype, device="cuda") for d in plan.dims]
+    buf = [torch.empty_like(o) for o in outs]
+    plan.push_sources(0, src_at(0))
+    plan.retarded_step(0, outs)
+    plan.capture_step(buf, outs)
+    for l in range(1, W + K + 1):
+        if l == W + 1:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        torch._foreach_copy_(buf, src_at(l))
+        plan.launch_step(l)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / K, outs
+
+
+def bench_sweep(args):
+    """Measured form of the paper's single- vs multi-domain cost comparison
+    (Sec. III, Fig. 3): two W x W x L domains side by side, the box that
+    encloses both W x d x L.  Per d: the step time of the two-domain plan and
+    of the one-domain plan (same sources, zero between the domains), the
+    agreement of the two on the sub-domain points, and the model's ratio."""
+    import numpy as np
+    import torch
+    from paper_2311_15429_amd import plan_for_system
+    from synth.sources import enclosing_domain, wire_pair
+    Wp, Lp = 32, 128
+    both = [72, 96, 128, 160, 192, 224, 256]
+    multi_only = [512, 1024, 2048, 4096]
+    precision = args.precision
+    K = args.steps
+    rows = []
+    stream = torch.cuda.current_stream()
+    for dp in both + multi_only:
+        system = wire_pair(W=Wp, L=Lp, d=dp, n_pairs=8, seed=args.seed)
+        row = {"d_points": dp, "d_over_L": dp / Lp, "d_bohr": round(dp * system.h, 2),
+               "speedup_model": speedup_model(Wp, Lp, dp)}
+        plan = plan_for_system(system, precision, stream=stream)
+        depth = max(plan.info(0, n)[3] for n in range(2))
+        row["multi_lagsum_bytes"] = plan.stats()["lagsum_bytes"]
+        row["multi_ring_depth"] = depth
+        plan.bind()
+        plan.set_green_kernels()
+        W = depth + 2
+        src = make_sources(system, range(W + K + 1), plan.dtype)
+        row["ms_multi"], outs_m = _time_graph(plan, lambda l: src[l], W, K)
+        if dp in both:
+            encl, blocks = enclosing_domain(system)
+            dims = tuple(encl.domains[0].dims)
+            big_src = []
+            for l in range(W + K + 1):
+                big = torch.zeros((4,) + dims, dtype=plan.dtype, device="cuda")
+                for n, b in enumerate(blocks):
+                    big[(slice(None),) + b] = src[l][n]
+                big_src.append([big])
+            sp = plan_for_system(encl, precision, stream=stream)
+            row["single_lagsum_bytes"] = sp.stats()["lagsum_bytes"]
+            sdepth = sp.info(0, 0)[3]
+            sp.bind()
+            sp.set_green_kernels()
+            # the same number of steps, so both end on the same step
+            row["ms_single"], outs_s = _time_graph(sp, lambda l: big_src[l], W, K)
+            big = outs_s[0].double()
+            diff = 0.0
+            for n, b in enumerate(blocks):
+                cut = big[(slice(None),) + b]
+                ref = outs_m[n].double()
+                diff = max(diff, float(torch.max(torch.abs(cut - ref)) / torch.max(torch.abs(ref))))
+            row["rel_diff_single_vs_multi"] = diff
+            row["speedup_measured"] = row["ms_single"] / row["ms_multi"]
+            row["single_ring_depth"] = sdepth
+            sp.close()
+            del sp, outs_s, big_src
+        plan.close()
+        del plan, outs_m, src
+        torch.cuda.empty_cache()
+        log("sweep " + ", ".join(f"{k} {v:.4g}" if isinstance(v, float) else f"{k} {v}" for k, v in row.items()))
+        rows.append(row)
+    last = [r for r in rows if "speedup_measured" in r][-1]
+    ms_m = [r["ms_multi"] for r in rows]
+    line = {"metric": "multi-domain speedup over one enclosing domain (measured step time ratio)",
+            "value": last["speedup_measured"], "unit": "x", "n_gpus": 1, "steps": K, "warmup": "ring depth + 2",
+            "ms_per_step": last["ms_multi"], "higher_is_better": True, "scaling": "strong",
+            "vs_baseline": None, "dtype": {"fp64": "f64"}.get(precision, "f32"), "data": "synthetic",
+            "config": {"workload": f"two {Wp}x{Wp}x{Lp}-point domains side by side along y, h=0.3 bohr, dt=0.01; "
+                                   f"enclosing box {Wp}x d x {Lp}; value at d={last['d_points']} points",
+                       "precision": precision,
+                       "multi_ms_spread_over_d": [min(ms_m), max(ms_m)],
+                       "sweep": rows},
+            "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -409,11 +516,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lagsum-unroll", type=int, default=None, choices=[1, 2, 4])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default lag-sum schedule")
-    ap.add_argument("--workload", default="scale", choices=["scale", "batched", "surrogate", "small"],
+    ap.add_argument("--workload", default="scale", choices=["scale", "batched", "surrogate", "small", "sweep"],
                     help="scale: 8 x 64^3 (the metric's workload); batched: 64 independent systems "
                          "(2-8 domains of 16^3/24^3/32^3) in one plan, one graph launch per step; "
                          "surrogate: 32 x 48^3 in a 2000-bohr box with the learned far-pair surrogate; "
-                         "small: 2 x 16^3 in FP64 beside the oracle's full run")
+                         "small: 2 x 16^3 in FP64 beside the oracle's full run; "
+                         "sweep: two 32x32x128 domains vs the box enclosing both, over the distance")
     ap.add_argument("--far", default="learned", choices=["learned", "multipole"],
                     help="surrogate workload: far-pair terms from the trained network or the analytic multipole")
     ap.add_argument("--teacher-seeds", type=int, nargs="+", default=[101, 102, 103])
@@ -441,6 +549,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "small":
         return bench_small(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
     system = config2(args.seed)
     workload = "8 sub-domains of 64^3 points, h=0.3 bohr, 400-bohr box, dt=0.01, FFT pad 128^3"
     stream = torch.cuda.current_stream()

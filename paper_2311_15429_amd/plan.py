@@ -277,6 +277,7 @@ class Plan:
         if getattr(self, "_h", None):
             self._lib.rp_plan_destroy(self._h)
             self._h = None
+        self._ws = None
 
     def __del__(self):
         try:

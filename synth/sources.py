@@ -303,3 +303,39 @@ def config5(seed: int = 0, n_dom: int = 32, n: int = 48, n_pairs: int = 16, box:
     for d in doms:
         _random_pairs(rng, d, h, n_pairs)
     return System(h, 0.01, C_AU, doms, name=f"{n_dom}x{n}^3 h=0.3 box={box:g} seed={seed}")
+
+
+def wire_pair(W: int = 32, L: int = 128, d: int = 128, h: float = 0.3, dt: float = 0.01,
+              n_pairs: int = 8, seed: int = 0) -> System:
+    """Two elongated W x W x L point domains, long axis z, side by side along y:
+    domain 0 occupies y points [0, W), domain 1 [d - W, d), so the box that
+    encloses both has W x d x L points (the geometry of the paper's cost
+    comparison, Sec. III).  Each domain holds n_pairs seeded charge pairs."""
+    if d < 2 * W:
+        raise ValueError("the domains would overlap: need d >= 2 W")
+    rng = np.random.default_rng(seed)
+    doms = [Domain((W, W, L), np.array([0.0, 0.0, 0.0])),
+            Domain((W, W, L), np.array([0.0, h * (d - W), 0.0]))]
+    for dm in doms:
+        _random_pairs(rng, dm, h, n_pairs)
+    return System(h, dt, C_AU, doms, name=f"wire pair {W}x{W}x{L} d={d} h={h}")
+
+
+def enclosing_domain(system: System):
+    """One domain whose grid holds every point of every domain of `system`
+    (the domains' grids must share the lattice of spacing h).  Returns the
+    one-domain System (no charges: its sources are the sub-domains' sources
+    placed in it, zero elsewhere) and, per sub-domain, the index slices of
+    its block inside the enclosing grid."""
+    h = system.h
+    lo = np.min(system.origins, axis=0)
+    hi = np.max(system.origins + h * (system.dims - 1), axis=0)
+    dims = tuple(int(round(v)) + 1 for v in (hi - lo) / h)
+    blocks = []
+    for dm in system.domains:
+        off = (dm.origin - lo) / h
+        k = np.rint(off).astype(int)
+        if np.max(np.abs(off - k)) > 1e-9:
+            raise ValueError("sub-domain grids are not on one lattice")
+        blocks.append(tuple(slice(int(k[a]), int(k[a]) + dm.dims[a]) for a in range(3)))
+    return System(h, system.dt, system.c, [Domain(dims, lo.copy())], name=f"enclosing {dims}"), blocks

@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 
 from synth import sources as sy
 
@@ -56,3 +57,14 @@ def test_sampling_is_separable_and_seeded():
     # J/c components are small compared with rho (v/c)
     assert np.max(np.abs(a[0][:, 1:])) < 0.05 * np.max(np.abs(a[0][:, 0]))
     assert math.isfinite(float(np.sum(a[1])))
+
+
+def test_wire_pair_and_enclosing_domain():
+    s = sy.wire_pair(W=8, L=24, d=40, h=0.5, dt=0.02, n_pairs=1)
+    encl, blocks = sy.enclosing_domain(s)
+    assert tuple(encl.domains[0].dims) == (8, 40, 24)
+    pts = sy.grid_points(encl.domains[0], s.h).reshape(8, 40, 24, 3)
+    for dm, b in zip(s.domains, blocks):
+        assert np.allclose(pts[b].reshape(-1, 3), sy.grid_points(dm, s.h))
+    with pytest.raises(ValueError):
+        sy.wire_pair(W=8, L=24, d=15)
