@@ -339,3 +339,17 @@ def enclosing_domain(system: System):
             raise ValueError("sub-domain grids are not on one lattice")
         blocks.append(tuple(slice(int(k[a]), int(k[a]) + dm.dims[a]) for a in range(3)))
     return System(h, system.dt, system.c, [Domain(dims, lo.copy())], name=f"enclosing {dims}"), blocks
+
+
+def pair_shapes(dom: Domain, h: float, c: float) -> np.ndarray:
+    """Per charge pair of the domain, its fixed source shape [K][4][N]: the
+    charge part (component 0) and the current part per unit dq/dt (components
+    1-3, divided by c), from the separable factors."""
+    B = spatial_factors(dom, h, c)
+    if any(ch.kind != "pair" for ch in dom.charges):
+        raise ValueError("every charge must be a pair")
+    K = len(dom.charges)
+    out = np.zeros((K, 4, dom.n_points))
+    out[:, 0] = B[0::2, 0]
+    out[:, 1:4] = B[1::2, 1:4]
+    return out
