@@ -330,6 +330,48 @@ rp_status rp_surrogate_features(rp_plan plan, float *x);
 rp_status rp_surrogate_pair_response(rp_plan plan, float *coef, float *resid);
 rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t *n_fallback, double *worst);
 
+/*
+ * Model response of the sources: the steps either side of the potential
+ * evaluation in the propagation loop of Fig. 4, with Lorentz oscillators in
+ * place of the Kohn-Sham dynamics (the current of step l drives the vector
+ * potential of step l + 1, Sec. II).  Oscillator k of domain n has a fixed
+ * shape B [4][N_n] (component 0: charge per unit q; components 1-3: current / c
+ * per unit dq/dt) and the amplitude q.  Sources S = (sum_k q_k B_k[0],
+ * sum_k qdot_k B_k[1..3]).  One rp_osc_step, from the potentials P of step l:
+ *   phi_k = h^3 sum_r B_k[0] v,   psi_k = h^3 sum_r sum_a B_k[1+a] A_a,
+ *   F_k   = -phi_k - (psi_k - psi_k(l-1)) / dt + drive_k e_ext
+ *           (the generalised force of the potentials on the shape; psi(l-1) =
+ *           psi(l) on the first step after bind or rp_osc_set_state),
+ *   qdot  = qdot + dt (kappa F - gamma qdot - omega^2 q),  q = q + dt qdot,
+ * then writes S(l + 1) of the new state.  The state is FP64 on the device.
+ *
+ * rp_osc_create  n_osc [n_dom] oscillators per domain (0..256), params
+ *     [total][4] = omega, gamma, kappa, drive (host, copied; finite, omega and
+ *     gamma >= 0, omega dt < 2 for a stable step; else RP_ERR_ARG).  Takes the
+ *     plan's grids, h, dt and stream; the plan may be destroyed afterwards.
+ * rp_osc_bind  device workspace (256-byte aligned, >= rp_osc_workspace_bytes)
+ *     and basis [n_dom] device pointers to [K_n][4][N_n] shapes in the plan's
+ *     source type (FP64 for RP_FP64, else FP32; NULL where K_n = 0), which the
+ *     caller keeps alive.  Sets q = qdot = 0.  Synchronises the stream.
+ * rp_osc_set_state  host q, qdot [total].  Synchronises the stream.
+ * rp_osc_sources  writes S of the current state into src [n_dom] ([4][N_n]).
+ * rp_osc_step  pot [n_dom]: outputs of rp_retarded_step of step l; e_ext: the
+ *     external field amplitude at l dt; src_next [n_dom]: S(l + 1).
+ *     Asynchronous on the stream, no allocation.
+ * rp_osc_state  host copies [total] of q, qdot and the last phi, psi (any may
+ *     be NULL).  Synchronises the stream.
+ */
+typedef struct rp_osc_s *rp_osc;
+rp_status rp_osc_create(rp_osc *out, rp_plan plan, const int32_t *n_osc, const double *params);
+rp_status rp_osc_workspace_bytes(rp_osc osc, size_t *bytes);
+rp_status rp_osc_bind(rp_osc osc, void *dev_ptr, size_t bytes, const void *const *basis);
+rp_status rp_osc_set_state(rp_osc osc, const double *q, const double *qdot);
+rp_status rp_osc_sources(rp_osc osc, void *const *src);
+rp_status rp_osc_step(rp_osc osc, const void *const *pot, double e_ext, void *const *src_next);
+rp_status rp_osc_state(rp_osc osc, double *q, double *qdot, double *phi, double *psi);
+rp_status rp_osc_destroy(rp_osc osc);
+const char *rp_osc_last_error(rp_osc osc);
+
 /* Release the host plan (the workspace stays the caller's). */
 rp_status rp_plan_destroy(rp_plan plan);
 

@@ -6,6 +6,7 @@ librpot.so behind the C-ABI of include/rpot.h; this package is its ctypes
 binding.
 """
 from .plan import Plan, plan_for_system
+from .coupling import Oscillators
 from ._lib import RpotError, load, LIB_PATH
 
-__all__ = ["Plan", "plan_for_system", "RpotError", "load", "LIB_PATH"]
+__all__ = ["Plan", "plan_for_system", "Oscillators", "RpotError", "load", "LIB_PATH"]

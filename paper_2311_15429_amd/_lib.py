@@ -19,7 +19,9 @@ EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_set
            "rp_mlp_bind", "rp_mlp_n_params", "rp_mlp_set_params", "rp_mlp_get_params", "rp_mlp_forward",
            "rp_mlp_loss_grad", "rp_mlp_train_step", "rp_mlp_destroy", "rp_plan_destroy", "rp_last_error",
            "rp_mlp_last_error", "rp_surrogate_configure", "rp_surrogate_info", "rp_surrogate_pairs",
-           "rp_surrogate_attach", "rp_surrogate_multipole", "rp_surrogate_features", "rp_surrogate_pair_response", "rp_surrogate_judge"]
+           "rp_surrogate_attach", "rp_surrogate_multipole", "rp_surrogate_features", "rp_surrogate_pair_response", "rp_surrogate_judge",
+           "rp_osc_create", "rp_osc_workspace_bytes", "rp_osc_bind", "rp_osc_set_state", "rp_osc_sources",
+           "rp_osc_step", "rp_osc_state", "rp_osc_destroy", "rp_osc_last_error"]
 TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2, "fft_lds": 4}
 
 
@@ -91,8 +93,18 @@ def load():
     lib.rp_surrogate_multipole.argtypes = [vp, i32]
     lib.rp_surrogate_pair_response.argtypes = [vp, vp, vp]
     lib.rp_surrogate_judge.argtypes = [vp, P(vp), ctypes.c_double, P(i32), dp]
+    lib.rp_osc_create.argtypes = [P(vp), vp, P(i32), dp]
+    lib.rp_osc_workspace_bytes.argtypes = [vp, P(sz)]
+    lib.rp_osc_bind.argtypes = [vp, vp, sz, P(vp)]
+    lib.rp_osc_set_state.argtypes = [vp, dp, dp]
+    lib.rp_osc_sources.argtypes = [vp, P(vp)]
+    lib.rp_osc_step.argtypes = [vp, P(vp), ctypes.c_double, P(vp)]
+    lib.rp_osc_state.argtypes = [vp, dp, dp, dp, dp]
+    lib.rp_osc_destroy.argtypes = [vp]
+    lib.rp_osc_last_error.argtypes = [vp]
+    lib.rp_osc_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("rp_last_error", "rp_mlp_last_error"):
+        if name not in ("rp_last_error", "rp_mlp_last_error", "rp_osc_last_error"):
             getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -107,4 +119,10 @@ def check(lib, plan, code):
 def check_mlp(lib, mlp, code):
     if code != RP_OK:
         msg = lib.rp_mlp_last_error(mlp)
+        raise RpotError(code, msg.decode() if msg else "")
+
+
+def check_osc(lib, osc, code):
+    if code != RP_OK:
+        msg = lib.rp_osc_last_error(osc)
         raise RpotError(code, msg.decode() if msg else "")

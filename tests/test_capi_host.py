@@ -149,3 +149,38 @@ def test_fft_tile_knob_host():
         p.set_tuning("fft_lds", 1000)
     assert e.value.status == "RP_ERR_ARG"
     p.close()
+
+
+def test_oscillator_create_checks_arguments():
+    import ctypes
+    from paper_2311_15429_amd import _lib
+    from synth import sources as sy
+    from paper_2311_15429_amd import plan_for_system
+    lib = _lib.load()
+    system = sy.config1()
+    p = plan_for_system(system, "fp32")
+
+    def create(n_osc, params):
+        h = ctypes.c_void_p()
+        k = (ctypes.c_int32 * 2)(*n_osc)
+        P = np.ascontiguousarray(np.asarray(params, np.float64).reshape(-1, 4))
+        code = lib.rp_osc_create(ctypes.byref(h), p._h, k, P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return code, h
+
+    ok = [[2.0, 0.1, 1.0, 0.5]] * 3
+    code, h = create([2, 1], ok)
+    assert code == 0
+    nb = ctypes.c_size_t()
+    assert lib.rp_osc_workspace_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
+    # steps need a bound workspace
+    assert lib.rp_osc_step(h, None, 0.0, None) == 4
+    assert b"not bound" in lib.rp_osc_last_error(h)
+    lib.rp_osc_destroy(h)
+    for n_osc, params in (([300, 0], [[1.0, 0, 1, 0]] * 300),          # too many per domain
+                          ([1, 0], [[1.0 / system.dt * 2.5, 0, 1, 0]]),  # omega dt >= 2: unstable
+                          ([1, 0], [[1.0, -0.1, 1, 0]]),                 # negative damping
+                          ([1, 0], [[float("nan"), 0, 1, 0]])):
+        code, h = create(n_osc, params)
+        assert code == 1 and not h.value, n_osc
+        assert lib.rp_osc_last_error(None)
+    p.close()
