@@ -398,6 +398,84 @@ def bench_surrogate(args):
     plan.close()
 
 
+def bench_coupled(args):
+    """The propagation loop around the path on config 2: each domain's 16
+    charge pairs are Lorentz oscillators driven by the computed potentials
+    (domain 0 also by a sin^2 pulse); per step push the sources, evaluate the
+    potentials, project them on the oscillators, update them and synthesise
+    the next step's sources, all on the GPU with no host round trip."""
+    import numpy as np
+    import torch
+    from paper_2311_15429_amd import Oscillators, plan_for_system
+    from synth.sources import config2, pair_shapes
+    system = config2(args.seed)
+    stream = torch.cuda.current_stream()
+    plan = plan_for_system(system, args.precision, stream=stream)
+    st = plan.stats()
+    plan.bind()
+    plan.set_green_kernels()
+    tuned = None if args.no_autotune else plan.autotune(iters=3)
+    dt_ = plan.dtype
+    rng = np.random.default_rng(args.seed + 7)
+    bases, params = [], []
+    for i, d in enumerate(system.domains):
+        bases.append(torch.from_numpy(pair_shapes(d, system.h, system.c)).to("cuda", dt_).contiguous())
+        k = len(d.charges)
+        p = np.column_stack([rng.uniform(0.5, 5.0, k), np.full(k, 0.05), np.ones(k),
+                             [ch.cp[2] - ch.cm[2] if i == 0 else 0.0 for ch in d.charges]])
+        params.append(p)
+    osc = Oscillators(plan, bases, params)
+    src = [torch.empty((4,) + d, dtype=dt_, device="cuda") for d in plan.dims]
+    nxt = [torch.empty_like(x) for x in src]
+    outs = [torch.empty_like(x) for x in src]
+    T_env, w_d = 20.0, 0.8
+
+    def e_ext(l):
+        t = l * system.dt
+        return math.sin(math.pi * t / T_env) ** 2 * math.sin(w_d * t) if t < T_env else 0.0
+
+    osc.sources(src)
+    W, K = args.warmup, args.steps
+    for l in range(W + K + 1):
+        if l == W + 1:
+            torch.cuda.synchronize()
+            plan.lagsum_time()
+            plan.profile_lagsum(True)
+            t0 = time.perf_counter()
+        plan.push_sources(l, src)
+        plan.retarded_step(l, outs)
+        osc.step(outs, e_ext(l), nxt)
+        src, nxt = nxt, src
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    plan.profile_lagsum(False)
+    lag_ms, launches = plan.lagsum_time()
+    q, qd, phi, psi = osc.state()
+    if not (np.all(np.isfinite(q)) and all(bool(torch.isfinite(o).all()) for o in outs)):
+        raise RuntimeError("non-finite state")
+    n_osc = sum(len(d.charges) for d in system.domains)
+    osc_bytes = sum(2 * b.numel() * b.element_size() for b in bases)
+    ms_step = 1e3 * el / K
+    updates = st["points"] * K / el
+    log(f"coupled loop: step {ms_step:.3f} ms ({updates / 1e6:.2f} M updates/s), lag sum {lag_ms / launches:.3f} ms, "
+        f"{n_osc} oscillators, shape bytes streamed per step {osc_bytes / 1e9:.2f} GB; "
+        f"max |q| domain 0 {np.max(np.abs(q[:16])):.3e}, others {np.max(np.abs(q[16:])):.3e}")
+    line = {"metric": METRIC, "value": updates, "unit": "grid-point updates/s", "n_gpus": 1, "steps": K,
+            "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": {"fp64": "f64"}.get(args.precision, "f32"), "data": "synthetic",
+            "config": {"workload": "8 sub-domains of 64^3 points (config 2 geometry), each charge pair a Lorentz "
+                                   "oscillator driven by the computed potentials; sources of step l+1 from the "
+                                   "potentials of step l on the GPU",
+                       "precision": args.precision, "oscillators": n_osc,
+                       "lagsum_ms": lag_ms / launches, "shape_bytes_per_step": osc_bytes,
+                       "max_abs_q": [float(np.max(np.abs(q[:16]))), float(np.max(np.abs(q[16:])))],
+                       "autotune": tuned},
+            "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+    osc.close()
+    plan.close()
+
+
 def speedup_model(Wp, Lp, dp):
     """The paper's cost ratio for two W x W x L domains side by side in a
     W x d x L box (Sec. III, Eq. of the computational complexity ratio), in
@@ -516,12 +594,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lagsum-unroll", type=int, default=None, choices=[1, 2, 4])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default lag-sum schedule")
-    ap.add_argument("--workload", default="scale", choices=["scale", "batched", "surrogate", "small", "sweep"],
+    ap.add_argument("--workload", default="scale", choices=["scale", "batched", "surrogate", "small", "sweep", "coupled"],
                     help="scale: 8 x 64^3 (the metric's workload); batched: 64 independent systems "
                          "(2-8 domains of 16^3/24^3/32^3) in one plan, one graph launch per step; "
                          "surrogate: 32 x 48^3 in a 2000-bohr box with the learned far-pair surrogate; "
                          "small: 2 x 16^3 in FP64 beside the oracle's full run; "
-                         "sweep: two 32x32x128 domains vs the box enclosing both, over the distance")
+                         "sweep: two 32x32x128 domains vs the box enclosing both, over the distance; "
+                         "coupled: config 2 with oscillator sources driven by the potentials")
     ap.add_argument("--far", default="learned", choices=["learned", "multipole"],
                     help="surrogate workload: far-pair terms from the trained network or the analytic multipole")
     ap.add_argument("--teacher-seeds", type=int, nargs="+", default=[101, 102, 103])
@@ -551,6 +630,8 @@ def main():
         return bench_small(args)
     if args.workload == "sweep":
         return bench_sweep(args)
+    if args.workload == "coupled":
+        return bench_coupled(args)
     system = config2(args.seed)
     workload = "8 sub-domains of 64^3 points, h=0.3 bohr, 400-bohr box, dt=0.01, FFT pad 128^3"
     stream = torch.cuda.current_stream()

@@ -178,8 +178,9 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
  *                              frequency tile, longest first) through a device
  *                              counter; 0: one block per work item.
  *   RP_TUNE_FFT_LDS            complex values an FFT line-pass block stages in
- *                              LDS (whole lines): 2048, 4096 (default) or 6144
- *                              in FP32 (half as many in FP64); 0 = default.
+ *                              LDS (whole lines): 2048, 4096 or 6144 in FP32
+ *                              (half as many in FP64); 0 = default (2048 for
+ *                              FP32 plans, 4096 for FP64 plans).
  * Setting a knob discards a captured step (rp_capture_step).
  */
 enum { RP_TUNE_LAGSUM_UNROLL = 1, RP_TUNE_LAGSUM_PERSISTENT = 2, RP_TUNE_FFT_LDS = 4 };

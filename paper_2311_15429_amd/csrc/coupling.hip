@@ -125,20 +125,23 @@ __global__ void __launch_bounds__(kOscThreads) k_osc_project(OscArgs<T> a) {
     }
 }
 
-// One thread per oscillator: fixed-order sum of its partials, force, update.
+// One wave per oscillator: its partials summed in a fixed order (lane-strided
+// then the wave tree), then the force and the update by lane 0.
 // state: q [n], qdot [n], psi_prev [n], phi [n], psi [n].
-__global__ void k_osc_advance(const OscMeta *meta, const double *params, const double *part, double *state,
-                              int n, double w, double dt, double e_ext, int first) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__global__ void __launch_bounds__(64) k_osc_advance(const OscMeta *meta, const double *params, const double *part,
+                                                    double *state, int n, double w, double dt, double e_ext,
+                                                    int first) {
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
     const OscMeta m = meta[i];
     double phi = 0.0, psi = 0.0;
-    for (int b = 0; b < m.nblk; ++b) {
+    for (int b = lane; b < m.nblk; b += 64) {
         phi += part[2 * (m.part + b)];
         psi += part[2 * (m.part + b) + 1];
     }
-    phi *= w;
-    psi *= w;
+    phi = wave_sum(phi) * w;
+    psi = wave_sum(psi) * w;
+    if (lane != 0) return;
     const double psi_prev = first ? psi : state[2 * n + i];
     const double omega = params[4 * i], gamma = params[4 * i + 1], kappa = params[4 * i + 2],
                  drive = params[4 * i + 3];
@@ -444,7 +447,7 @@ rp_status rp_osc_step(rp_osc o, const void *const *pot, double e_ext, void *cons
         else
             enqueue_project<float>(o, pot);
         if (o->n_osc > 0)
-            hipLaunchKernelGGL(k_osc_advance, dim3((o->n_osc + 255) / 256), dim3(256), 0, o->stream,
+            hipLaunchKernelGGL(k_osc_advance, dim3(o->n_osc), dim3(64), 0, o->stream,
                                reinterpret_cast<const OscMeta *>(o->ws + o->off_meta),
                                reinterpret_cast<const double *>(o->ws + o->off_params),
                                reinterpret_cast<const double *>(o->ws + o->off_part), o->state(), o->n_osc,

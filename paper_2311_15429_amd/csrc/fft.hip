@@ -255,6 +255,9 @@ static void launch_line_e(const LinePass &a, dim3 grid, int E, hipStream_t st) {
 
 int line_pass_elems(int lds_elems, int prec64) {
     const int base = prec64 ? Lds<double>::E : Lds<float>::E;
+    // default: the 16 KiB tile in FP32 (measured fastest on the 128^3 pads),
+    // the 32 KiB tile in FP64
+    if (lds_elems == 0) lds_elems = prec64 ? 4096 : 2048;
     if (lds_elems == 2048) return base / 2;
     if (lds_elems == 6144) return base * 3 / 2;
     return base;

@@ -1331,7 +1331,7 @@ rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value) {
         switch (knob) {
         case RP_TUNE_LAGSUM_UNROLL: *value = plan->k2_unroll; break;
         case RP_TUNE_LAGSUM_PERSISTENT: *value = plan->k2_persist; break;
-        case RP_TUNE_FFT_LDS: *value = plan->fft_lds ? plan->fft_lds : 4096; break;
+        case RP_TUNE_FFT_LDS: *value = plan->fft_lds ? plan->fft_lds : (plan->p64 ? 4096 : 2048); break;
         default: fail(RP_ERR_ARG, "unknown tuning knob");
         }
     });

@@ -142,8 +142,9 @@ def test_paper_run_windows_do_not_grow_with_distance():
 def test_fft_tile_knob_host():
     from paper_2311_15429_amd import RpotError, plan_for_system
     p = plan_for_system(sy.config1(1), "fp32")
-    assert p.get_tuning("fft_lds") == 4096
-    for v in (2048, 6144, 0):
+    assert p.get_tuning("fft_lds") == 2048
+    assert plan_for_system(sy.config1(1), "fp64").get_tuning("fft_lds") == 4096
+    for v in (4096, 6144, 0):
         p.set_tuning("fft_lds", v)
     with pytest.raises(RpotError) as e:
         p.set_tuning("fft_lds", 1000)

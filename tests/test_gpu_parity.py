@@ -152,7 +152,7 @@ def test_deterministic_reruns_fp32():
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("precision,tile", [("fp32", 2048), ("fp32", 6144), ("fp64", 2048), ("fp64", 6144)])
+@pytest.mark.parametrize("precision,tile", [("fp32", 4096), ("fp32", 6144), ("fp64", 2048), ("fp64", 6144)])
 def test_line_pass_tiles(precision, tile):
     """Every line-pass tile (lines staged per block) gives the oracle's result
     on the uneven radix-2/3/4 shapes."""
