@@ -93,6 +93,8 @@ def cpu_baseline(system, target_seconds):
 
     rng = np.random.default_rng(0)
     c1 = oracle.self_cell_c1()
+    from oracle.ref import threads
+    cores = threads()
     npts = 8
     while True:
         idx = np.sort(rng.choice(dom0.n_points, size=npts, replace=False))
@@ -102,11 +104,29 @@ def cpu_baseline(system, target_seconds):
         if el >= 0.5 * target_seconds or npts >= dom0.n_points:
             break
         npts = min(dom0.n_points, int(npts * min(64.0, max(2.0, target_seconds / max(el, 1e-3)))))
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # one thread on a proportionally smaller sample
+    n1 = max(1, npts // max(cores, 1))
+    idx1 = np.sort(rng.choice(dom0.n_points, size=n1, replace=False))
+    threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.potential_points(system, 0, idx1, l, fn, c1=c1)
+        el1 = time.perf_counter() - t0
+    finally:
+        threads(cores)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": npts / el, "unit": "grid-point updates/s", "cores": cores, "kind": "oracle",
             "sample": f"{npts} grid points of domain 0 (all 8 source domains, 2,097,152 source points each "
                       f"update) at step {l}; {el:.1f} s of oracle time",
-            "seconds": el}
+            "seconds": el, "single_thread_value": n1 / el1, "single_thread_sample_points": n1,
+            "cpu_model": model}
 
 
 def bench_batched(args):

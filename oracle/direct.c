@@ -34,6 +34,7 @@
  * h sqrt(3)/2 >= c dt; 3 self cell requested at a time that is not a step.
  */
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 
 static const double *sample_ptr(const double *samples, const double *s0,
@@ -147,4 +148,13 @@ int rpo_contrib(int n_pts, const double *pts, const long *self_idx,
             status = err;
     }
     return status;
+}
+
+/* Threads used by rpo_contrib (timing control only): n >= 1 sets the count,
+ * the return value is the count now in effect. */
+int rpo_threads(int n)
+{
+    if (n >= 1)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

@@ -39,8 +39,15 @@ def load_library():
                                 dp, ctypes.c_double, dp, ctypes.c_long, ctypes.c_long, dp,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_double, dp]
+    lib.rpo_threads.restype = ctypes.c_int
+    lib.rpo_threads.argtypes = [ctypes.c_int]
     _LIB = lib
     return lib
+
+
+def threads(n=0):
+    """Threads of the direct sum: n >= 1 sets the count; returns the count in effect."""
+    return int(load_library().rpo_threads(int(n)))
 
 
 def _dp(a):
