@@ -137,8 +137,10 @@ rp_status rp_retarded_step(rp_plan plan, int64_t step, void *const *out);
 
 /*
  * Planned window of the ordered pair (target s <- source n): lags [m_lo, m_hi]
- * (-1, -1 if the pair is not formed), the FFT pad of their system, and the ring
- * depth of source n.  Any output pointer may be NULL.
+ * (-1, -1 if the pair is not formed), the FFT pad of their system, and the
+ * depth of source n's spectral ring (the lags it holds from 0; with a split
+ * history the later windows sit in rings of their own).  Any output pointer
+ * may be NULL.
  */
 rp_status rp_plan_info(rp_plan plan, int32_t s, int32_t n, int32_t *m_lo,
                        int32_t *m_hi, int32_t pad[3], int32_t *depth);
@@ -154,6 +156,8 @@ typedef struct {
     double spectra_bytes;     /* Green spectra                                     */
     double fft_bytes_fwd;     /* minimal bytes of the forward FFT passes per step  */
     double fft_bytes_inv;     /* minimal bytes of the inverse FFT passes per step  */
+    double history_bytes;     /* real-space source rings of a split history        */
+    int64_t split_rings;      /* extra spectral rings of a split history           */
 } rp_stats;
 
 rp_status rp_plan_stats(rp_plan plan, rp_stats *out);
@@ -239,6 +243,23 @@ rp_status rp_mlp_loss_grad(rp_mlp mlp, const float *x, const float *t, int32_t b
 rp_status rp_mlp_train_step(rp_mlp mlp, const float *x, const float *t, int32_t batch, float lr, float *loss);
 rp_status rp_mlp_destroy(rp_mlp mlp);
 const char *rp_mlp_last_error(rp_mlp mlp);
+
+/*
+ * Split history (the retained history of Sec. IV, kept compact).  A source's
+ * spectral ring holds every lag from 0 to the largest m_hi of its pairs, but
+ * far pairs read only narrow windows of it.  With min_gap > 0 the windows of
+ * a source's pairs are merged where they are less than min_gap lags apart;
+ * every window after the first then gets a spectral ring of its own width,
+ * fed each step by transforming again the sources of `window start` steps
+ * ago, which the source keeps in a real-space ring (source precision,
+ * window start + 1 slots).  A source is split only where the spectra saved
+ * exceed the real-space ring and the extra transform scratch.  Results are
+ * identical to the unsplit plan (the same transforms of the same data).
+ * Before rp_workspace_bytes / rp_bind_workspace (RP_ERR_STATE after);
+ * min_gap <= 0 switches it off.  Not combined with the far-pair surrogate
+ * (RP_ERR_UNSUPPORTED).  Re-plans ring depths, schedules and the workspace.
+ */
+rp_status rp_history_split(rp_plan plan, int32_t min_gap);
 
 /*
  * Learned far-pair surrogate (an extension: the paper's closing section points

@@ -347,9 +347,17 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
     float mx[4] = {0.f, 0.f, 0.f, 0.f};
     if (a.mode == 0) {
         // complex line c = pair * 4 + mu holds positions 2 pair (re) and 2 pair + 1 (im)
-        const T *__restrict__ S = reinterpret_cast<const T *>(job.src);
-        const T *__restrict__ S0 = reinterpret_cast<const T *>(job.s0);
         const int64_t npts = int64_t(npos) * a.Nz;
+        const T *__restrict__ S = reinterpret_cast<const T *>(job.src);
+        if (job.src_head) {
+            // a real-space history ring: the snapshot src_lag steps before the newest
+            int h = (*job.src_head - job.src_lag) % job.src_depth;
+            if (h < 0) h += job.src_depth;
+            S += int64_t(h) * 4 * npts;
+        }
+        const T *__restrict__ S0 = reinterpret_cast<const T *>(job.s0);
+        T *__restrict__ St = nullptr;
+        if (job.store) St = reinterpret_cast<T *>(job.store) + int64_t(*job.store_head) * 4 * npts;
         for (int e = threadIdx.x; e < L * P; e += NT) {
             const int li = a.dP.div(e);
             const int z = e - li * P;
@@ -359,10 +367,14 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
                 const int mu = c & 3;
                 const int pa = (c >> 2) * 2;
                 const int64_t oa = mu * npts + int64_t(pa) * a.Nz + z;
-                v.x = S0 ? S[oa] - S0[oa] : S[oa];
+                const T sa = S[oa];
+                if (St) St[oa] = sa;
+                v.x = S0 ? sa - S0[oa] : sa;
                 if (pa + 1 < npos) {
                     const int64_t ob = oa + a.Nz;
-                    v.y = S0 ? S[ob] - S0[ob] : S[ob];
+                    const T sb = S[ob];
+                    if (St) St[ob] = sb;
+                    v.y = S0 ? sb - S0[ob] : sb;
                 }
                 mx[mu] = fmaxf(mx[mu], fmaxf(fabsf(float(v.x)), fabsf(float(v.y))));
             }
@@ -434,6 +446,8 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
 int zfwd_lines_per_block(int Pz, int prec64) {
     return prec64 ? zfwd_lpb<double>(Pz) : zfwd_lpb<float>(Pz);
 }
+
+static_assert(sizeof(ZFwd) <= 4096, "z-pass kernel arguments above 4 KiB");
 
 void launch_zfwd(const ZFwd &a0, int prec64, hipStream_t st) {
     ZFwd a = a0;

@@ -209,7 +209,8 @@ __device__ __forceinline__ void lagsum_item(const K2Args &a, int item_index) {
         const char *ring_tile = ring + (R.ring_off * esz + int64_t(tile) * depth * ring_row);
         int64_t scale_off = 0;
         if (FMT == RING_F16 || FMT == RING_BF16) scale_off = a.doms[R.n].scale_off;
-        int32_t slot = a.head[R.n] - m_min;
+        // the ring's newest snapshot (at the head) has lag m_base
+        int32_t slot = a.head[R.n] - (m_min - R.m_base);
         if (slot < 0) slot += depth;
 
         int m = m_min;

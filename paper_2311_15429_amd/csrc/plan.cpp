@@ -10,6 +10,7 @@
 #include "plan_internal.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -206,18 +207,17 @@ void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables 
             R.n = n;
             R.m_min = INT32_MAX;
             R.m_max = -1;
+            K2Pair Qs[kGroupMax] = {};
             for (int t = 0; t < kGroupMax; ++t) {
-                K2Pair Q{};
                 if ((takes >> t) & 1u) {
                     const PairP &q = p->pr(mb[t].s, n);
                     if (q.spec0 < 0) fail(RP_ERR_STATE, "internal: lag sum over a pair without spectra");
-                    Q.row0 = int32_t(q.spec0 / kTile) - q.m_lo;
-                    Q.w = q.m_hi - q.m_lo + 1;
+                    Qs[t].row0 = int32_t(q.spec0 / kTile) - q.m_lo;
+                    Qs[t].w = q.m_hi - q.m_lo + 1;
                     if (q.conj) R.conj |= 1u << t;
                     R.m_min = std::min(R.m_min, q.m_lo);
                     R.m_max = std::max(R.m_max, q.m_hi);
                 }
-                T.pairs.push_back(Q);
             }
             R.mask_off = int32_t(T.masks.size());
             for (int m = R.m_min; m <= R.m_max; ++m) {
@@ -229,7 +229,23 @@ void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables 
                 }
                 T.masks.push_back(mk);
             }
-            T.srcs.push_back(R);
+            // one record per ring that holds part of the window: the source's
+            // ring (lags from 0) and its split rings (lags from their start)
+            const DomainP &dn = p->dom[n];
+            std::vector<std::array<int, 3>> rings{{n, 0, dn.depth - 1}};
+            for (int v : dn.vr) rings.push_back({p->vring[v].idx, p->vring[v].lo, p->vring[v].hi});
+            for (const auto &rg : rings) {
+                const int a = std::max(R.m_min, rg[1]), b = std::min(R.m_max, rg[2]);
+                if (a > b) continue;
+                K2Src Rs = R;
+                Rs.n = rg[0];
+                Rs.m_min = a;
+                Rs.m_max = b;
+                Rs.m_base = rg[1];
+                Rs.mask_off = R.mask_off + (a - R.m_min);
+                for (int t = 0; t < kGroupMax; ++t) T.pairs.push_back(Qs[t]);
+                T.srcs.push_back(Rs);
+            }
             for (int m = R.m_min; m <= R.m_max; ++m) {
                 K2Entry E{};
                 E.src = n;
@@ -304,11 +320,59 @@ void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int)) {
 // Ring depths, stored Green spectra and the lag-sum schedules.
 void plan_tables(rp_plan p) {
     const int nd = p->n_dom;
+    p->vring.clear();
+    p->domdev.clear();   // rebuilt by plan_layout for the new ring indices
     for (int n = 0; n < nd; ++n) {
+        DomainP &d = p->dom[n];
+        std::vector<std::pair<int, int>> iv;
+        for (int s : p->sys[d.sys].doms)
+            if (keeps_history(p, s, n)) iv.push_back({p->pr(s, n).m_lo, p->pr(s, n).m_hi});
         int mh = 0;
-        for (int s : p->sys[p->dom[n].sys].doms)
-            if (keeps_history(p, s, n)) mh = std::max(mh, p->pr(s, n).m_hi);
-        p->dom[n].depth = mh + 1;
+        for (const auto &w : iv) mh = std::max(mh, w.second);
+        d.span = mh + 1;
+        d.depth = mh + 1;
+        d.vr.clear();
+        d.d1 = 0;
+        d.t1_idx = -1;
+        if (p->split_gap <= 0 || iv.empty()) continue;
+        // merge the pairs' windows; a gap of split_gap lags or more starts a new ring
+        std::sort(iv.begin(), iv.end());
+        std::vector<std::pair<int, int>> win{{0, iv[0].second}};
+        for (size_t i = 1; i < iv.size(); ++i) {
+            if (iv[i].first - win.back().second - 1 >= p->split_gap) win.push_back(iv[i]);
+            else win.back().second = std::max(win.back().second, iv[i].second);
+        }
+        if (win.size() < 2) continue;
+        // split only where the spectra saved outweigh the real-space ring and
+        // the transform scratch of the extra rings
+        const SystemP &S = p->sys[d.sys];
+        const double spec_slot = double(S.Cpad) * 4 * p->ring_esz;
+        int kept = 0;
+        for (const auto &w : win) kept += w.second - w.first + 1;
+        const double saved = double(d.span - kept) * spec_slot;
+        const double scratch = double(d.N[0]) * (d.N[1] + S.P[1]) * S.Hz * 4 * p->csz;
+        const double cost = double(win.back().first + 1) * 4 * double(d.npts) * p->tsz +
+                            double(win.size() - 1) * scratch;
+        if (saved <= cost) continue;
+        d.depth = win[0].second + 1;
+        d.d1 = win.back().first + 1;
+        for (size_t w = 1; w < win.size(); ++w) {
+            VRingP v;
+            v.n = n;
+            v.lo = win[w].first;
+            v.hi = win[w].second;
+            v.W = v.hi - v.lo + 1;
+            d.vr.push_back(int(p->vring.size()));
+            p->vring.push_back(v);
+        }
+    }
+    // head slots: domains, judge accumulators, split rings, real-space rings
+    {
+        int idx = nd + int(p->sur.on ? p->sur.aud.size() : 0);
+        for (VRingP &v : p->vring) v.idx = idx++;
+        for (DomainP &d : p->dom)
+            if (d.d1 > 0) d.t1_idx = idx++;
+        p->n_heads = idx;
     }
 
     // Green spectra: one set per unordered pair; the reversed pair uses the
@@ -392,12 +456,12 @@ void plan_layout(rp_plan p) {
         D.pairs = alloc(std::max<size_t>(1, D.cap_pairs) * sizeof(K2Pair));
         D.masks = alloc(std::max<size_t>(1, D.cap_masks) * sizeof(uint32_t));
     };
-    const size_t n_slots = p->dom.size() + (p->sur.on ? p->sur.aud.size() : 0);
+    const size_t n_slots = size_t(p->n_heads);
     p->tw64.clear();
     p->tw32.clear();
     p->off_state = alloc(64);
-    p->off_head = alloc(p->dom.size() * sizeof(int32_t));
-    p->off_prev_head = alloc(p->dom.size() * sizeof(int32_t));
+    p->off_head = alloc(n_slots * sizeof(int32_t));
+    p->off_prev_head = alloc(n_slots * sizeof(int32_t));
     p->off_counter = alloc(16);
     alloc_k2(p->k2_dev);
     if (p->sur.on) alloc_k2(p->sur.judge_dev);
@@ -435,6 +499,16 @@ void plan_layout(rp_plan p) {
         max_t2 = std::max(max_t2, t2);
         max_pts = std::max(max_pts, size_t(d.npts));
     }
+    for (VRingP &v : p->vring) {
+        const DomainP &d = p->dom[v.n];
+        const SystemP &S = p->sys[d.sys];
+        v.off_ring = alloc(size_t(v.W) * S.Cpad * 4 * p->ring_esz);
+        v.off_scales = quant ? alloc(size_t(v.W) * 4 * sizeof(float)) : 0;
+        v.off_zmax = quant ? alloc(size_t(d.zblocks) * 4 * sizeof(float)) : 0;
+        v.off_t1 = alloc(size_t(d.N[0]) * d.N[1] * S.Hz * 4 * p->csz);
+        v.off_t2 = alloc(size_t(d.N[0]) * S.P[1] * S.Hz * 4 * p->csz);
+    }
+    for (DomainP &d : p->dom) d.off_hist = d.d1 > 0 ? alloc(size_t(d.d1) * 4 * d.npts * p->tsz) : 0;
     p->off_gtmp = alloc(size_t(kGreenChunk) * max_gtmp * 16);
     p->off_accd = alloc(max_C * 4 * 16);
     p->off_gstat = alloc(max_C * 16);
@@ -457,6 +531,14 @@ void plan_layout(rp_plan p) {
         D.depth = d.depth;
         D.pad = 0;
     }
+    for (const VRingP &v : p->vring) {
+        DomDev &D = p->domdev[v.idx];
+        D.ring_off = int64_t((v.off_ring - p->dom[0].off_ring) / (4 * p->ring_esz)) * 4;
+        D.scale_off = quant ? int64_t((v.off_scales - p->dom[0].off_scales) / sizeof(float)) : 0;
+        D.depth = v.W;
+    }
+    for (const DomainP &d : p->dom)
+        if (d.t1_idx >= 0) p->domdev[d.t1_idx].depth = d.d1;
     if (p->sur.on) {
         // judge slots: accumulators of the audited far pairs, [slot][C][4]
         for (size_t v = 0; v < p->sur.aud.size(); ++v) {
@@ -495,6 +577,9 @@ void plan_stats(rp_plan p) {
     for (const DomainP &d : p->dom) st.points += d.npts;
     st.lagsum_bytes = k2_bytes(p, p->k2);
     for (const DomainP &d : p->dom) st.ring_bytes += double(d.depth) * p->sys[d.sys].Cpad * 4 * p->ring_esz;
+    for (const VRingP &v : p->vring) st.ring_bytes += double(v.W) * p->sys[p->dom[v.n].sys].Cpad * 4 * p->ring_esz;
+    for (const DomainP &d : p->dom) st.history_bytes += double(d.d1) * 4 * double(d.npts) * p->tsz;
+    st.split_rings = int64_t(p->vring.size());
     for (const SystemP &S : p->sys) st.spectra_bytes += double(S.spec_elems) * p->spec_csz;
     for (const DomainP &d : p->dom) {
         const SystemP &S = p->sys[d.sys];
@@ -505,6 +590,8 @@ void plan_stats(rp_plan p) {
         const double real = double(d.npts) * 4 * p->tsz;
         st.fft_bytes_fwd += 2 * real + t1 + t1 + t2 + t2 + ring;
         st.fft_bytes_inv += acc + t2 + t2 + t1 + t1 + 2 * real;
+        // a split history also stores the sources, and transforms them again per extra ring
+        if (d.d1 > 0) st.fft_bytes_fwd += real + double(d.vr.size()) * (2 * real + t1 + t1 + t2 + t2 + ring);
     }
 }
 
@@ -713,8 +800,8 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
         HIP_OK(hipStreamSynchronize(st));   // host buffers are reused
     }
     launch_fill_zero(p->ws + p->off_state, 64, st);
-    launch_fill_zero(p->ws + p->off_head, (p->dom.size() * sizeof(int32_t) + 15) / 16 * 16, st);
-    launch_fill_zero(p->ws + p->off_prev_head, (p->dom.size() * sizeof(int32_t) + 15) / 16 * 16, st);
+    launch_fill_zero(p->ws + p->off_head, (size_t(p->n_heads) * sizeof(int32_t) + 15) / 16 * 16, st);
+    launch_fill_zero(p->ws + p->off_prev_head, (size_t(p->n_heads) * sizeof(int32_t) + 15) / 16 * 16, st);
     launch_fill_zero(p->ws + p->off_counter, 16, st);
     {
         int dev = 0;
@@ -724,6 +811,10 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
     for (const DomainP &d : p->dom) {
         launch_fill_zero(p->ws + d.off_ring, size_t(d.depth) * p->sys[d.sys].Cpad * 4 * p->ring_esz, st);
         if (d.off_scales) launch_fill_zero(p->ws + d.off_scales, (size_t(d.depth) * 16 + 15) / 16 * 16, st);
+    }
+    for (const VRingP &v : p->vring) {
+        launch_fill_zero(p->ws + v.off_ring, size_t(v.W) * p->sys[p->dom[v.n].sys].Cpad * 4 * p->ring_esz, st);
+        if (v.off_scales) launch_fill_zero(p->ws + v.off_scales, (size_t(v.W) * 16 + 15) / 16 * 16, st);
     }
     if (p->sur.on) sur_bind(p);
     check_launch();
@@ -833,8 +924,14 @@ void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
     const bool quant = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
     const int32_t *dhead = p->at<int32_t>(p->off_head);
     for (const ClassP &K : p->cls) {
-        for (size_t j0 = 0; j0 < K.doms.size(); j0 += kMaxJobs) {
-            const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
+        // jobs: every domain of the class (newest sources into its ring, and a
+        // copy into its real-space ring), then every split ring of those
+        // domains (the sources of lo steps ago, from the real-space ring)
+        std::vector<int> jobs(K.doms.begin(), K.doms.end());
+        for (int n : K.doms)
+            for (int v : p->dom[n].vr) jobs.push_back(-1 - v);
+        for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxJobs) {
+            const int cnt = int(std::min<size_t>(kMaxJobs, jobs.size() - j0));
             ZFwd z = zfwd_common(p, 0, K.N, K.P, K.Hz, p->p64);
             LinePass y = fwd_y(p, K.N, K.P, K.Hz, p->p64);
             LinePass x = fwd_x(p, K.N, K.P, K.Hz, p->p64);
@@ -844,25 +941,46 @@ void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
             z.n_jobs = y.n_jobs = x.n_jobs = cnt;
             sa.n_jobs = quant ? cnt : 0;
             for (int j = 0; j < cnt; ++j) {
-                const int n = K.doms[j0 + j];
+                const int code = jobs[j0 + j];
+                const bool split = code < 0;
+                const VRingP *v = split ? &p->vring[size_t(-1 - code)] : nullptr;
+                const int n = split ? v->n : code;
                 const DomainP &d = p->dom[n];
-                z.jobs[j].src = src[n];
+                const int ring_idx = split ? v->idx : n;
+                const int depth = split ? v->W : d.depth;
+                const size_t off_t1 = split ? v->off_t1 : d.off_t1;
+                const size_t off_t2 = split ? v->off_t2 : d.off_t2;
+                const size_t off_ring = split ? v->off_ring : d.off_ring;
+                const size_t off_zmax = split ? v->off_zmax : d.off_zmax;
+                const size_t off_scales = split ? v->off_scales : d.off_scales;
+                if (split) {
+                    z.jobs[j].src = p->ws + d.off_hist;
+                    z.jobs[j].src_head = dhead + d.t1_idx;
+                    z.jobs[j].src_depth = d.d1;
+                    z.jobs[j].src_lag = v->lo;
+                } else {
+                    z.jobs[j].src = src[n];
+                    if (d.d1 > 0) {
+                        z.jobs[j].store = p->ws + d.off_hist;
+                        z.jobs[j].store_head = dhead + d.t1_idx;
+                    }
+                }
                 z.jobs[j].s0 = p->ws + d.off_s0;
-                z.jobs[j].out = p->ws + d.off_t1;
-                z.jobs[j].zmax = quant ? p->at<float>(d.off_zmax) : nullptr;
-                y.jobs[j].in = p->ws + d.off_t1;
-                y.jobs[j].out = p->ws + d.off_t2;
-                x.jobs[j].in = p->ws + d.off_t2;
-                x.jobs[j].out = p->ws + d.off_ring;
-                x.jobs[j].head = dhead + n;
+                z.jobs[j].out = p->ws + off_t1;
+                z.jobs[j].zmax = quant ? p->at<float>(off_zmax) : nullptr;
+                y.jobs[j].in = p->ws + off_t1;
+                y.jobs[j].out = p->ws + off_t2;
+                x.jobs[j].in = p->ws + off_t2;
+                x.jobs[j].out = p->ws + off_ring;
+                x.jobs[j].head = dhead + ring_idx;
                 x.jobs[j].slot_stride = int64_t(kTile) * 4;
-                x.jobs[j].tile_stride = int64_t(d.depth) * kTile * 4;
-                x.jobs[j].qscale = quant ? p->at<float>(d.off_scales) : nullptr;
+                x.jobs[j].tile_stride = int64_t(depth) * kTile * 4;
+                x.jobs[j].qscale = quant ? p->at<float>(off_scales) : nullptr;
                 if (quant) {
-                    sa.jobs[j].zmax = p->at<float>(d.off_zmax);
-                    sa.jobs[j].scales = p->at<float>(d.off_scales);
+                    sa.jobs[j].zmax = p->at<float>(off_zmax);
+                    sa.jobs[j].scales = p->at<float>(off_scales);
                     sa.jobs[j].nblk = d.zblocks;
-                    sa.jobs[j].head = dhead + n;
+                    sa.jobs[j].head = dhead + ring_idx;
                     sa.jobs[j].npts = double(d.npts);
                 }
             }
@@ -947,7 +1065,7 @@ void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st) {
 void enqueue_finish(rp_plan p, void *const *out, hipStream_t st) {
     if (p->sur.on) sur_enqueue_infer(p, out, st);
     launch_advance_step(p->at<int64_t>(p->off_state), p->at<int32_t>(p->off_head), p->at<int32_t>(p->off_prev_head),
-                        p->at<DomDev>(p->off_domdev), p->n_dom, st);
+                        p->at<DomDev>(p->off_domdev), p->n_heads, st);
     check_launch();
 }
 
@@ -969,8 +1087,15 @@ void do_push(rp_plan p, int64_t step, const void *const *src) {
     }
     hipStream_t st = p->stream;
     if (step == 0) {
-        for (int n = 0; n < p->n_dom; ++n)
-            launch_convert(p->ws + p->dom[n].off_s0, p->p64, src[n], p->p64, 4 * p->dom[n].npts, st);
+        for (int n = 0; n < p->n_dom; ++n) {
+            const DomainP &d = p->dom[n];
+            launch_convert(p->ws + d.off_s0, p->p64, src[n], p->p64, 4 * d.npts, st);
+            // the real-space ring starts with S(0) in every slot: sources before
+            // step 0 are S(0)
+            for (int j = 0; j < d.d1; ++j)
+                launch_convert(p->ws + d.off_hist + size_t(j) * 4 * d.npts * p->tsz, p->p64, src[n], p->p64,
+                               4 * d.npts, st);
+        }
         do_static(p, src);
     } else {
         enqueue_ingest(p, src, st);
@@ -1355,6 +1480,18 @@ rp_status rp_launch_step(rp_plan plan, int64_t step) {
 rp_status rp_surrogate_configure(rp_plan plan, double far_factor, int32_t n_lags, const int32_t *audit,
                                  int32_t n_audit) {
     return guarded(plan, [&] { sur_configure(plan, far_factor, n_lags, audit, n_audit); });
+}
+
+rp_status rp_history_split(rp_plan plan, int32_t min_gap) {
+    return guarded(plan, [&] {
+        if (plan->ws) fail(RP_ERR_STATE, "split the history before rp_bind_workspace");
+        if (min_gap > 0 && plan->sur.on) fail(RP_ERR_UNSUPPORTED, "the surrogate and a split history do not combine");
+        plan->split_gap = std::max(0, int(min_gap));
+        plan_tables(plan);
+        plan_layout(plan);
+        plan_stats(plan);
+        release_graph(plan);
+    });
 }
 
 rp_status rp_surrogate_info(rp_plan plan, int32_t *n_far, int32_t *n_audited, int32_t *n_in, int32_t *n_out) {

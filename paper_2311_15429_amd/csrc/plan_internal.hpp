@@ -36,11 +36,25 @@ struct DomainP {
     double o[3];
     int sys;
     int64_t npts;
-    int depth = 1;
+    int depth = 1;           // spectral ring: lags 0 .. depth - 1
+    int span = 1;            // history the pairs need: max m_hi + 1
     int zblocks = 0;
     int cls = 0;
     size_t off_ring = 0, off_scales = 0, off_zmax = 0, off_s0 = 0, off_p0 = 0, off_acc = 0;
     size_t off_t1 = 0, off_t2 = 0, off_s0hat = 0;
+    // split history: later lag windows in their own spectral rings, fed from
+    // a real-space ring of the raw sources (d1 slots; head at slot index t1_idx)
+    std::vector<int> vr;
+    int d1 = 0;
+    int t1_idx = -1;
+    size_t off_hist = 0;
+};
+
+// A later lag window [lo, hi] of source n with its own spectral ring.
+struct VRingP {
+    int n = 0, lo = 0, hi = 0, W = 1;
+    int idx = 0;             // ring / head slot index
+    size_t off_ring = 0, off_scales = 0, off_zmax = 0, off_t1 = 0, off_t2 = 0;
 };
 
 struct SystemP {
@@ -165,6 +179,9 @@ struct rp_plan_s {
     int k2_unroll = 1;   // lags whose loads a lag-sum thread issues together
     int k2_persist = 0;  // persistent lag-sum launch (work counter) instead of one block per item
     int fft_lds = 0;     // line-pass tile: complex elements staged per block (0: default)
+    int split_gap = 0;   // split a source's history at lag gaps of at least this many lags (0: off)
+    std::vector<rpot_host::VRingP> vring;
+    int n_heads = 0;     // ring heads: domains, judge slots, split rings, real-space rings
     int n_cu = 0;        // compute units of the bound device
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

@@ -91,8 +91,12 @@ struct LinePass {
 //          fly on the full Px x Py x Pz grid; output [Px][Py][Hz].
 //  mode 2: as mode 1 with the instantaneous (static) kernel h^3/R.
 struct ZFwdJob {
-    const void *src;       // mode 0: S  [4][Nx][Ny][Nz]
+    const void *src;       // mode 0: S  [4][Nx][Ny][Nz]; with src_head a ring of such arrays
     const void *s0;        // mode 0: S0 [4][Nx][Ny][Nz] (null: transform S itself)
+    const int32_t *src_head;  // mode 0: read slot (*src_head - src_lag) mod src_depth of the src ring
+    void *store;           // mode 0: also copy S into slot *store_head of this ring (or null)
+    const int32_t *store_head;
+    int32_t src_depth, src_lag;
     void *out;
     float *zmax;           // mode 0: per-block max |dS| per component, or null
     double off[3];         // modes 1/2: o_s - o_n
@@ -148,12 +152,13 @@ struct K2Entry {
 
 // Per (group, source): the lag range covered by any member and the ring.
 struct K2Src {
-    int32_t n;             // source domain (global index)
-    int32_t m_min, m_max;  // union of the members' lag windows for this source
-    int32_t depth;         // the source's ring depth
-    int64_t ring_off;      // the source's ring (complex elements from the first ring)
+    int32_t n;             // ring (and head) index: the source domain, or one of its split rings
+    int32_t m_min, m_max;  // union of the members' lag windows for this source (within this ring)
+    int32_t depth;         // the ring's depth
+    int64_t ring_off;      // the ring (complex elements from the first ring)
     uint32_t conj;         // members that use the conjugate of the stored spectra
     int32_t mask_off;      // masks[mask_off + m - m_min]: members whose window holds lag m
+    int32_t m_base;        // lag of the ring's newest snapshot (0, or a split ring's first lag)
 };
 
 // Per (group, source, member): where the pair's spectra sit.  They are stored
@@ -198,7 +203,7 @@ struct K2Args {
     const void *ring;
     const float *scales;
     void *acc;
-    const int32_t *head;   // [n_dom] current ring slot of every domain (step mod depth)
+    const int32_t *head;   // current slot of every ring (step mod depth)
     int *counter;          // persistent launch: next work item
     int n_items;
     int n_dom;

@@ -554,6 +554,7 @@ void sur_configure(rp_plan p, double far_factor, int n_lags, const int32_t *audi
         U = SurrogateH{};
     } else {
         if (!std::isfinite(far_factor)) fail(RP_ERR_ARG, "far_factor must be finite");
+        if (p->split_gap > 0) fail(RP_ERR_UNSUPPORTED, "the surrogate and a split history do not combine");
         if (p->p64) fail(RP_ERR_UNSUPPORTED, "the surrogate runs with FP32 outputs (not RP_FP64)");
         if (!std::isfinite(p->c)) fail(RP_ERR_UNSUPPORTED, "the surrogate needs a finite c");
         if (n_lags < 1 || n_lags > 1024) fail(RP_ERR_ARG, "n_lags must be in [1, 1024]");

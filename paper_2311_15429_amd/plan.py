@@ -198,6 +198,12 @@ class Plan:
         _lib.check(self._lib, self._h, self._lib.rp_launch_step(self._h, int(step)))
 
     # -- far-pair surrogate --------------------------------------------------
+    def history_split(self, min_gap):
+        """Split each source's history at lag gaps of at least min_gap lags
+        (later windows in spectral rings of their own, fed from a real-space
+        ring of the sources).  Call before bind(); min_gap <= 0 switches it off."""
+        _lib.check(self._lib, self._h, self._lib.rp_history_split(self._h, int(min_gap)))
+
     def surrogate_configure(self, far_factor, n_lags=64, audit=()):
         """Far pairs (centre distance > far_factor x the larger box diagonal)
         leave the plain lag sum; `audit` sources keep their plain history.

@@ -14,9 +14,9 @@ def log(*a):
     sys.stdout.flush()
 
 
-def run_gpu(system, precision, samples, collect=None, tune=None):
+def run_gpu(system, precision, samples, collect=None, tune=None, split=0):
     """Push samples[n][l] ([L+1][4][N] FP64) for l = 0..L and step.
-    tune: {knob: value} set before binding.
+    tune: {knob: value} set before binding; split: history split gap (0: off).
 
     Returns {l: [dom][4][N] FP64 numpy} for l in `collect` (default: all)."""
     import torch
@@ -25,6 +25,9 @@ def run_gpu(system, precision, samples, collect=None, tune=None):
     p = plan_for_system(system, precision, stream=stream)
     for k, v in (tune or {}).items():
         p.set_tuning(k, v)
+    if split:
+        p.history_split(split)
+        assert p.stats()["split_rings"] > 0
     p.bind()
     p.set_green_kernels()
     dt = p.dtype

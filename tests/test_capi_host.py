@@ -185,3 +185,47 @@ def test_oscillator_create_checks_arguments():
         assert code == 1 and not h.value, n_osc
         assert lib.rp_osc_last_error(None)
     p.close()
+
+
+def test_history_split_plans_rings_and_keeps_the_lag_sum():
+    """Two domains far apart: the cross window sits far beyond the self window.
+    The split keeps the main ring to the self window, adds one ring per
+    source for the cross window, and reads exactly the same lag-sum bytes."""
+    from paper_2311_15429_amd import RpotError, plan_for_system
+    system = sy.wire_pair(W=8, L=12, d=120, h=0.3, dt=0.01, n_pairs=1)
+    plain = plan_for_system(system, "fp32")
+    p = plan_for_system(system, "fp32")
+    p.history_split(8)
+    a, b = plain.stats(), p.stats()
+    assert b["split_rings"] == 2 and a["split_rings"] == 0
+    assert b["lagsum_bytes"] == a["lagsum_bytes"] and b["n_entries"] == a["n_entries"]
+    assert b["ring_bytes"] < 0.5 * a["ring_bytes"] and b["history_bytes"] > 0 and a["history_bytes"] == 0
+    for n in range(2):
+        self_hi = p.info(n, n)[1]
+        cross_lo, cross_hi = p.info(1 - n, n)[:2]
+        assert cross_lo - self_hi > 8
+        assert p.info(0, n)[3] == self_hi + 1
+        assert plain.info(0, n)[3] == cross_hi + 1
+    # a gap threshold above the gap keeps one ring; 0 switches the split off
+    p.history_split(10 ** 6)
+    assert p.stats()["split_rings"] == 0 and p.stats()["ring_bytes"] == a["ring_bytes"]
+    p.history_split(8)
+    p.history_split(0)
+    assert p.stats() == a
+    # config 1: self [0, 5], cross [8, 15]; a 2-lag gap is below a threshold of 3
+    near = plan_for_system(sy.config1(1), "fp32")
+    assert near.info(0, 0)[:2] == (0, 5) and near.info(1, 0)[:2] == (8, 15)
+    near.history_split(3)
+    assert near.stats()["split_rings"] == 0
+    # not with the far-pair surrogate, in either order
+    p.history_split(8)
+    with pytest.raises(RpotError) as e:
+        p.surrogate_configure(3.0)
+    assert e.value.status == "RP_ERR_UNSUPPORTED"
+    q = plan_for_system(system, "fp32")
+    q.surrogate_configure(3.0)
+    with pytest.raises(RpotError) as e:
+        q.history_split(8)
+    assert e.value.status == "RP_ERR_UNSUPPORTED"
+    for x in (plain, p, near, q):
+        x.close()

@@ -1,0 +1,102 @@
+"""Split history on the GPU: later lag windows in spectral rings of their own,
+fed by transforming again the sources kept in a real-space ring.  The lag sum
+then reads the same spectra in the same order, so every output is bitwise
+identical to the unsplit plan's; and it matches the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import log, rel_err, run_gpu
+from synth import sources as sy
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _pair():
+    """Two 8x8x12 domains 36 bohr apart: self window [0, 4], cross window about [24, 29]."""
+    return sy.wire_pair(W=8, L=12, d=120, h=0.3, dt=0.01, n_pairs=2, seed=4)
+
+
+def _three():
+    """Three uneven domains at 40 and 90 bohr: two far windows per source (those
+    of source 2 touch and merge)."""
+    rng = np.random.default_rng(9)
+    h = 0.3
+    doms = [sy.Domain((8, 8, 12), np.array([0.0, 0, 0])), sy.Domain((10, 6, 9), np.array([40.0, 0, 0])),
+            sy.Domain((7, 7, 7), np.array([0.0, 0, 90.0]))]
+    for d in doms:
+        sy._random_pairs(rng, d, h, 2)
+    return sy.System(h, 0.01, sy.C_AU, doms)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_ring_fp16", "fp32_ring_bf16"])
+def test_split_history_is_bitwise_identical(precision):
+    system = _pair()
+    L = 60
+    S = sy.sample_sources(system, range(L + 1))
+    a = run_gpu(system, precision, S)
+    b = run_gpu(system, precision, S, split=8)
+    for l in a:
+        for x, y in zip(a[l], b[l]):
+            assert np.array_equal(x, y), l
+    log(f"{precision}: split history bitwise identical over {L + 1} steps")
+
+
+def test_split_history_three_domains_matches_oracle_fp64():
+    from paper_2311_15429_amd import plan_for_system
+    system = _three()
+    p = plan_for_system(system, "fp64")
+    p.history_split(4)
+    st = p.stats()
+    assert st["split_rings"] == 5, st["split_rings"]   # source 2: its two far windows touch
+    p.close()
+    L = 80
+    steps = [30, 55, L]
+    S = sy.sample_sources(system, range(L + 1))
+    got = run_gpu(system, "fp64", S, collect=steps, split=4)
+    ref = oracle.potential_full(system, S, steps)
+    plain = run_gpu(system, "fp64", S, collect=steps)
+    for l, r in zip(steps, ref):
+        e = rel_err(got[l], r)
+        log(f"three domains, split, step {l}: rel err {np.array2string(e, precision=2)}")
+        assert np.all(e <= 1e-10), (l, e)
+        for x, y in zip(got[l], plain[l]):
+            assert np.array_equal(x, y)
+
+
+def test_split_history_graph_replay_is_bitwise_identical():
+    from paper_2311_15429_amd import plan_for_system
+    system = _pair()
+    L = 45
+    S = sy.sample_sources(system, range(L + 1))
+    src = [[torch.from_numpy(np.ascontiguousarray(S[n][l]).reshape((4,) + tuple(system.domains[n].dims)))
+            .to("cuda", torch.float32) for n in range(2)] for l in range(L + 1)]
+    res = []
+    for capture in (False, True):
+        p = plan_for_system(system, "fp32", stream=torch.cuda.current_stream())
+        p.history_split(8)
+        p.bind()
+        p.set_green_kernels()
+        outs = [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in p.dims]
+        buf = [torch.empty_like(o) for o in outs]
+        p.push_sources(0, src[0])
+        p.retarded_step(0, outs)
+        if capture:
+            p.capture_step(buf, outs)
+        seq = []
+        for l in range(1, L + 1):
+            if capture:
+                for b, x in zip(buf, src[l]):
+                    b.copy_(x)
+                p.launch_step(l)
+            else:
+                p.push_sources(l, src[l])
+                p.retarded_step(l, outs)
+            torch.cuda.synchronize()
+            seq.append([o.cpu().numpy().copy() for o in outs])
+        res.append(seq)
+        p.close()
+    for a, b in zip(*res):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
