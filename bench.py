@@ -496,6 +496,60 @@ def bench_coupled(args):
     plan.close()
 
 
+def bench_paper(args):
+    """The paper's two-molecule geometry with synthetic sources: two
+    50 x 50 x 125-point boxes (h = 0.4, dt = 1 as) 90 and 7500 bohr apart,
+    each with the history in one spectral ring and split (the far window in
+    a ring of its own, fed from a real-space ring).  Graph-launched steps."""
+    import numpy as np
+    import torch
+    from paper_2311_15429_amd import plan_for_system
+    from synth.sources import paper_pair
+    K, W = args.steps, args.warmup
+    rows = []
+    stream = torch.cuda.current_stream()
+    for d in (90.0, 7500.0):
+        system = paper_pair(d, seed=args.seed)
+        last = None
+        for split in (0, 8):
+            plan = plan_for_system(system, args.precision, stream=stream)
+            if split:
+                plan.history_split(split)
+            st = plan.stats()
+            ws = plan.workspace_bytes
+            plan.bind()
+            plan.set_green_kernels()
+            src = make_sources(system, range(W + K + 1), plan.dtype)
+            ms, outs = _time_graph(plan, lambda l: src[l], W, K)
+            got = [o.cpu() for o in outs]
+            same = None if last is None else all(bool(torch.equal(a, b)) for a, b in zip(last, got))
+            last = got
+            row = {"d_bohr": d, "split": bool(split), "ms_per_step": ms,
+                   "updates_per_s": st["points"] * 1e3 / ms, "workspace_gb": ws / 1e9,
+                   "ring_gb": st["ring_bytes"] / 1e9, "real_history_gb": st["history_bytes"] / 1e9,
+                   "split_rings": st["split_rings"], "ring_depth": plan.info(0, 0)[3],
+                   "cross_window": list(plan.info(1, 0)[:2]), "lagsum_gb": st["lagsum_bytes"] / 1e9}
+            if same is not None:
+                row["bitwise_equal_to_single_ring"] = same
+            log("paper pair " + ", ".join(f"{k} {v:.4g}" if isinstance(v, float) else f"{k} {v}"
+                                          for k, v in row.items()))
+            rows.append(row)
+            plan.close()
+            del plan, outs, src
+            torch.cuda.empty_cache()
+    best = [r for r in rows if r["d_bohr"] == 7500.0 and r["split"]][0]
+    line = {"metric": METRIC, "value": best["updates_per_s"], "unit": "grid-point updates/s", "n_gpus": 1,
+            "steps": K, "warmup": W, "ms_per_step": best["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64"}.get(args.precision, "f32"),
+            "data": "synthetic",
+            "config": {"workload": "the paper's two-molecule geometry: 2 x 50x50x125 points, h=0.4 bohr, "
+                                   "dt=1 as, 90 and 7500 bohr apart, single and split history; value: "
+                                   "7500 bohr, split",
+                       "precision": args.precision, "runs": rows},
+            "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
 def speedup_model(Wp, Lp, dp):
     """The paper's cost ratio for two W x W x L domains side by side in a
     W x d x L box (Sec. III, Eq. of the computational complexity ratio), in
@@ -614,13 +668,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lagsum-unroll", type=int, default=None, choices=[1, 2, 4])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default lag-sum schedule")
-    ap.add_argument("--workload", default="scale", choices=["scale", "batched", "surrogate", "small", "sweep", "coupled"],
+    ap.add_argument("--workload", default="scale", choices=["scale", "batched", "surrogate", "small", "sweep", "coupled", "paper"],
                     help="scale: 8 x 64^3 (the metric's workload); batched: 64 independent systems "
                          "(2-8 domains of 16^3/24^3/32^3) in one plan, one graph launch per step; "
                          "surrogate: 32 x 48^3 in a 2000-bohr box with the learned far-pair surrogate; "
                          "small: 2 x 16^3 in FP64 beside the oracle's full run; "
                          "sweep: two 32x32x128 domains vs the box enclosing both, over the distance; "
-                         "coupled: config 2 with oscillator sources driven by the potentials")
+                         "coupled: config 2 with oscillator sources driven by the potentials; "
+                         "paper: the paper's two-molecule geometry, single and split history")
     ap.add_argument("--far", default="learned", choices=["learned", "multipole"],
                     help="surrogate workload: far-pair terms from the trained network or the analytic multipole")
     ap.add_argument("--teacher-seeds", type=int, nargs="+", default=[101, 102, 103])
@@ -652,6 +707,8 @@ def main():
         return bench_sweep(args)
     if args.workload == "coupled":
         return bench_coupled(args)
+    if args.workload == "paper":
+        return bench_paper(args)
     system = config2(args.seed)
     workload = "8 sub-domains of 64^3 points, h=0.3 bohr, 400-bohr box, dt=0.01, FFT pad 128^3"
     stream = torch.cuda.current_stream()

@@ -353,3 +353,17 @@ def pair_shapes(dom: Domain, h: float, c: float) -> np.ndarray:
     out[:, 0] = B[0::2, 0]
     out[:, 1:4] = B[1::2, 1:4]
     return out
+
+
+def paper_pair(d: float, seed: int = 0, n_pairs: int = 8) -> System:
+    """The paper's two-molecule geometry (Sec. IV): two 20 x 20 x 50 bohr boxes
+    (50 x 50 x 125 points at h = 0.4), long axis z, centres d bohr apart along
+    y, dt = 1 as = 0.04134 a.u.; seeded charge pairs stand in for the molecules."""
+    rng = np.random.default_rng(seed)
+    h, dims = 0.4, (50, 50, 125)
+    half = 0.5 * h * (np.array(dims) - 1)
+    doms = [Domain(dims, np.array(c, float) - half) for c in ((0.0, 0.0, 0.0), (0.0, d, 0.0))]
+    for dm in doms:
+        _random_pairs(rng, dm, h, n_pairs)
+    return System(h, 0.04134, C_AU, doms, name=f"paper pair d={d:g}")
+
