@@ -39,7 +39,10 @@ struct RingLoad;
 // access is bounds-checked by the hardware against the row size.
 typedef unsigned nu2 __attribute__((ext_vector_type(2)));
 constexpr int kRsrcWord3 = 0x00020000;   // gfx9-family buffer descriptor word 3
-constexpr int kLoadAux = 0;              // cache policy bits of the loads
+// Cache policy of the loads: non-temporal.  Every ring row and spectrum row is
+// read once per step, so nothing is gained by keeping it in the caches; with
+// the FP16/BF16 ring the lag sum runs 7% faster this way (FP32: no change).
+constexpr int kLoadAux = 2;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const char *base, int bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(base), (short)0, bytes, kRsrcWord3);
