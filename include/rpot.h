@@ -346,8 +346,18 @@ rp_status rp_surrogate_attach(rp_plan plan, rp_mlp mlp, const float *in_scale, c
  * The multipole approximation of far sub-domains named in Sec. V; it needs no
  * training.  The judge and fallback work as with a network.  Discards a
  * captured step.
+ * enable = 2 keeps the attached network (and a network attached later) and
+ * adds its output to the multipole terms: the network then models what the
+ * expansion leaves out, trained on the plain pair responses minus
+ * rp_surrogate_multipole_response.
  */
 rp_status rp_surrogate_multipole(rp_plan plan, int32_t enable);
+/*
+ * The multipole terms of the audited far pairs at the last completed step, as
+ * frame coefficients a[mu][b] (device [n_aud][80], the rows and basis of
+ * rp_surrogate_pair_response).  Works in every surrogate mode.
+ */
+rp_status rp_surrogate_multipole_response(rp_plan plan, float *coef);
 rp_status rp_surrogate_features(rp_plan plan, float *x);
 rp_status rp_surrogate_pair_response(rp_plan plan, float *coef, float *resid);
 rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t *n_fallback, double *worst);

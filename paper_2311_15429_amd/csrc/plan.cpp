@@ -1527,6 +1527,10 @@ rp_status rp_surrogate_multipole(rp_plan plan, int32_t enable) {
     return guarded(plan, [&] { sur_multipole(plan, enable); });
 }
 
+rp_status rp_surrogate_multipole_response(rp_plan plan, float *coef) {
+    return guarded(plan, [&] { sur_multipole_response(plan, coef); });
+}
+
 rp_status rp_surrogate_features(rp_plan plan, float *x) {
     return guarded(plan, [&] { sur_features(plan, x); });
 }

@@ -152,7 +152,7 @@ struct SurrogateH {
     std::vector<int32_t> h_order, h_tbeg;   // active far pairs by target (CSR)
     rp_mlp mlp = nullptr;
     bool attached = false;
-    bool multipole = false;        // analytic multipole far-pair terms instead of the network
+    int multipole = 0;             // analytic multipole far-pair terms: 1 alone, 2 plus the network's correction
     size_t off_pinv = 0;           // [kNBasis][64] node-to-coefficient fit
 };
 
@@ -244,6 +244,7 @@ void sur_features(rp_plan p, float *x);
 void sur_pair_response(rp_plan p, float *coef, float *resid);
 void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, double *worst);
 void sur_multipole(rp_plan p, int enable);
+void sur_multipole_response(rp_plan p, float *coef);
 void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int));
 
 }  // namespace rpot_host

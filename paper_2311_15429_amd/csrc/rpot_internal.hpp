@@ -313,6 +313,7 @@ struct XformArgs {
     const int32_t *index;
     int dir;
     int n;
+    int accumulate;        // dir 0: add to out instead of writing it
 };
 // coef[s] = sum of pc[order[i]] over i in [tgt_begin[s], tgt_begin[s + 1])
 struct CoefArgs {
@@ -392,6 +393,7 @@ struct MultipoleArgs {
     const float *pinv;
     float *pc;
     const int64_t *step;
+    int step_off;          // evaluate at step *step + step_off
     int depth;
     int n_pairs;
     float inv_cdt, c, dt;

@@ -493,24 +493,29 @@ FeatArgs feat_args(rp_plan p, float *x, int64_t adj) {
 
 // Inference of every far pair at the current step and the synthesis of the
 // active pairs' fields into the targets' outputs.
+MultipoleArgs multipole_args(rp_plan p, int step_off) {
+    SurrogateH &U = p->sur;
+    MultipoleArgs ma{};
+    ma.pairs = p->at<FarPair>(U.off_fpairs);
+    ma.moments = p->at<float>(U.off_mom);
+    ma.pinv = p->at<float>(U.off_pinv);
+    ma.pc = p->at<float>(U.off_pc);
+    ma.step = p->at<int64_t>(p->off_state);
+    ma.step_off = step_off;
+    ma.depth = U.mom_depth;
+    ma.n_pairs = int(U.pairs.size());
+    ma.inv_cdt = float(1.0 / (p->c * p->dt));
+    ma.c = float(p->c);
+    ma.dt = float(p->dt);
+    return ma;
+}
+
 void sur_enqueue_infer(rp_plan p, void *const *out, hipStream_t st) {
     SurrogateH &U = p->sur;
     const int nf = int(U.pairs.size());
     if ((!U.attached && !U.multipole) || nf == 0) return;
-    if (U.multipole) {
-        MultipoleArgs ma{};
-        ma.pairs = p->at<FarPair>(U.off_fpairs);
-        ma.moments = p->at<float>(U.off_mom);
-        ma.pinv = p->at<float>(U.off_pinv);
-        ma.pc = p->at<float>(U.off_pc);
-        ma.step = p->at<int64_t>(p->off_state);
-        ma.depth = U.mom_depth;
-        ma.n_pairs = nf;
-        ma.inv_cdt = float(1.0 / (p->c * p->dt));
-        ma.c = float(p->c);
-        ma.dt = float(p->dt);
-        launch_multipole(ma, st);
-    } else {
+    if (U.multipole) launch_multipole(multipole_args(p, 0), st);
+    if (U.attached) {
         launch_features(feat_args(p, p->at<float>(U.off_x), 0), st);
         mlp_forward_on(U.mlp, p->at<float>(U.off_x), nf, p->at<float>(U.off_y), st);
         XformArgs xa{};
@@ -521,6 +526,7 @@ void sur_enqueue_infer(rp_plan p, void *const *out, hipStream_t st) {
         xa.scale = p->at<float>(U.off_outscale);
         xa.dir = 0;
         xa.n = nf;
+        xa.accumulate = U.multipole ? 1 : 0;   // a correction on top of the multipole terms
         launch_xform(xa, st);
     }
     CoefArgs ca{};
@@ -587,7 +593,7 @@ void sur_attach(rp_plan p, rp_mlp mlp, const float *in_scale, const float *out_s
         U.attached = false;
         return;
     }
-    U.multipole = false;
+    if (U.multipole == 1) U.multipole = 0;   // the network replaces the multipole terms (mode 2 keeps both)
     int ni = 0, no = 0, mb = 0;
     if (!mlp_dims(mlp, &ni, &no, &mb)) fail(RP_ERR_STATE, "network workspace not bound");
     if (ni != U.n_in || no != kNOut) fail(RP_ERR_ARG, "network shape does not match the surrogate (n_in, 80)");
@@ -604,12 +610,36 @@ void sur_multipole(rp_plan p, int enable) {
     SurrogateH &U = p->sur;
     if (!U.on) fail(RP_ERR_STATE, "surrogate not configured (rp_surrogate_configure)");
     if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    if (enable < 0 || enable > 2) fail(RP_ERR_ARG, "enable must be 0, 1 or 2");
     release_graph(p);
-    U.multipole = enable != 0;
-    if (U.multipole) {
+    U.multipole = enable;
+    if (U.multipole == 1) {
         U.mlp = nullptr;
         U.attached = false;
     }
+}
+
+// The multipole terms of the audited far pairs at the last completed step,
+// as frame coefficients (the layout of rp_surrogate_pair_response).
+void sur_multipole_response(rp_plan p, float *coef) {
+    need_ready(p);
+    SurrogateH &U = p->sur;
+    if (!coef) fail(RP_ERR_ARG, "coef is null");
+    if (U.aud.empty() || U.pairs.empty()) return;
+    hipStream_t st = p->stream;
+    launch_multipole(multipole_args(p, -1), st);
+    for (size_t v = 0; v < U.aud.size(); ++v) {
+        XformArgs xa{};
+        xa.pairs = p->at<FarPair>(U.off_fpairs);
+        xa.mats = p->at<float>(U.off_mats);
+        xa.in = p->at<float>(U.off_pc) + size_t(U.aud[v]) * kNOut;
+        xa.out = coef + size_t(U.aud_row[v]) * kNOut;
+        xa.index = p->at<int32_t>(U.off_aud) + v;
+        xa.dir = 1;
+        xa.n = 1;
+        launch_xform(xa, st);
+    }
+    check_launch();
 }
 
 void sur_features(rp_plan p, float *x) {

@@ -219,7 +219,8 @@ __global__ __launch_bounds__(128) void k_xform(XformArgs a) {
         if (t < kNOut) {
             float y = 0.f;
             for (int c = 0; c < kNBasis; ++c) y = fmaf(M[b * kNBasis + c], w[mu * kNBasis + c], y);
-            a.out[int64_t(row) * kNOut + t] = y;
+            float *o = a.out + int64_t(row) * kNOut + t;
+            *o = a.accumulate ? *o + y : y;
         }
     } else {
         if (t < kNOut) {
@@ -371,7 +372,7 @@ __global__ __launch_bounds__(256) void k_correct(CorrArgs a) {
 __global__ __launch_bounds__(64) void k_multipole(MultipoleArgs a) {
     const FarPair &fp = a.pairs[blockIdx.x];
     const int t = threadIdx.x;
-    const int64_t l = *a.step;
+    const int64_t l = *a.step + a.step_off;
     const float nodes[4] = {-1.f, -1.f / 3.f, 1.f / 3.f, 1.f};
     const float Rv[3] = {fp.d[0] + nodes[t >> 4] * fp.hw[0], fp.d[1] + nodes[(t >> 2) & 3] * fp.hw[1],
                          fp.d[2] + nodes[t & 3] * fp.hw[2]};

@@ -245,10 +245,23 @@ class Plan:
         self._mlp = mlp
 
     def surrogate_multipole(self, enable=True):
-        """Analytic multipole terms for the far pairs instead of a network."""
-        _lib.check(self._lib, self._h, self._lib.rp_surrogate_multipole(self._h, int(bool(enable))))
-        if enable:
+        """Analytic multipole terms for the far pairs: True (or 1) instead of a
+        network, "hybrid" (or 2) with the attached network's output added as a
+        correction, False (or 0) off."""
+        mode = 2 if enable == "hybrid" else int(enable)
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_multipole(self._h, mode))
+        if mode == 1:
             self._mlp = None
+
+    def surrogate_multipole_response(self):
+        """Multipole terms of the audited far pairs at the last completed step
+        as frame coefficients [n_aud][80] (device), rows as surrogate_pair_response."""
+        import torch
+        na = self.surrogate_info()["n_audited"]
+        coef = torch.zeros((max(na, 1), 80), dtype=torch.float32, device="cuda")
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_multipole_response(
+            self._h, ctypes.c_void_p(coef.data_ptr())))
+        return coef[:na]
 
     def surrogate_features(self, out=None):
         """Network inputs [n_far][n_in] (FP32, device) of the last completed step."""

@@ -22,12 +22,14 @@ N_OUT = 80
 N_BLOCKS = 6   # input blocks H, g H, f H, g f H, g^2 H, f^2 H
 
 
-def collect_pair_responses(plan, sources_at, n_steps, start=1, every=1, outputs=None):
+def collect_pair_responses(plan, sources_at, n_steps, start=1, every=1, outputs=None, residual=False):
     """Run `plan` (bound, Green kernels set, surrogate configured with audit
     sources, no network attached) from step 0 to n_steps - 1.  sources_at(l)
     returns the step's source tensors.  From step `start` on, every `every`
     steps, keeps the raw features and the targets (frame coefficients times
-    the pair distance) of the audited far pairs.
+    the pair distance) of the audited far pairs.  residual=True: the targets
+    are the plain responses minus the multipole terms (for a network that
+    corrects the multipole expansion).
 
     Returns (X [N][n_in], T [N][80]) FP32 device tensors."""
     import torch
@@ -46,6 +48,8 @@ def collect_pair_responses(plan, sources_at, n_steps, start=1, every=1, outputs=
         if l >= start and (l - start) % every == 0:
             x = plan.surrogate_features()
             coef, _ = plan.surrogate_pair_response()
+            if residual:
+                coef = coef - plan.surrogate_multipole_response()
             X.append(x.index_select(0, rows))
             T.append(coef * dist)
     assert info["n_out"] == N_OUT

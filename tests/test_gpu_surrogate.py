@@ -254,3 +254,74 @@ def test_multipole_terms_match_the_oracle_formula():
     log(f"multipole: formula match {worst:.1e}; total rel err {np.array2string(e_mp, precision=2)} "
         f"vs far pairs left out {np.array2string(e_dr, precision=2)}")
     assert np.max(e_mp) <= np.max(e_dr) / 10
+
+
+def _node_points(system, s):
+    dom = system.domains[s]
+    hw = 0.5 * system.h * (np.array(dom.dims) - 1)
+    nodes = np.array([-1.0, -1.0 / 3.0, 1.0 / 3.0, 1.0])
+    xi = np.array([[nodes[t >> 4], nodes[(t >> 2) & 3], nodes[t & 3]] for t in range(64)])
+    return sr.box_centre(dom, system.h) + xi * hw
+
+
+def test_multipole_response_matches_the_oracle():
+    """Frame coefficients of the multipole terms of the audited pairs at the
+    last completed step: the oracle's multipole field at the nodes, fitted to
+    the box basis, synthesised and fitted to the frame basis."""
+    system = far_system(8)
+    L = 50
+    S = sy.sample_sources(system, range(L + 1))
+    p = make_plan(system)
+    run(p, GpuSourceGen(system, torch.float32), L)
+    got = p.surrogate_multipole_response().double().cpu().numpy()
+    pairs = p.surrogate_pairs()
+    aud = np.nonzero(pairs["audited"])[0]
+    worst = 0.0
+    for v, f in enumerate(aud):
+        s, n = int(pairs["target"][f]), int(pairs["source"][f])
+        F = _box_synth_from_nodes(system, s, sr.multipole_field(system, S, s, n, L, _node_points(system, s)))
+        want = sr.frame_fit(system, s, n, F).ravel()
+        e = np.max(np.abs(got[v] - want)) / np.max(np.abs(want))
+        worst = max(worst, e)
+    log(f"multipole response: {len(aud)} audited pairs, worst rel err {worst:.1e}")
+    assert worst < 2e-4, worst
+    p.close()
+
+
+def test_hybrid_adds_the_network_to_the_multipole_terms():
+    system = far_system(9)
+    L = 40
+    gen = GpuSourceGen(system, torch.float32)
+    res = {}
+    info = None
+    for mode in ("dropped", "multipole", "network", "hybrid0", "hybrid"):
+        p = make_plan(system, audit=[])
+        info = p.surrogate_info()
+        mlp = None
+        if mode in ("network", "hybrid"):
+            mlp = _random_mlp(info["n_in"], info["n_far"], scale=0.05, seed=11)
+        elif mode == "hybrid0":
+            from paper_2311_15429_amd.mlp import Mlp
+            mlp = Mlp(info["n_in"], 32, 80, info["n_far"])
+            mlp.set_params(torch.zeros(mlp.n_params))
+        if mode.startswith("hybrid"):
+            p.surrogate_multipole("hybrid")
+        elif mode == "multipole":
+            p.surrogate_multipole(True)
+        if mlp is not None:
+            p.surrogate_attach(mlp, np.full(22, 1.0, np.float32), np.full(80, 1e-2, np.float32))
+        outs = run(p, gen, L)
+        res[mode] = [o.double().cpu().numpy().reshape(4, -1) for o in outs]
+        p.surrogate_attach(None)
+        p.close()
+        if mlp is not None:
+            mlp.close()
+    for a, b in zip(res["hybrid0"], res["multipole"]):
+        assert np.array_equal(a, b)
+    want = [m + w - d for m, w, d in zip(res["multipole"], res["network"], res["dropped"])]
+    e = rel_err(res["hybrid"], want)
+    net_part = rel_err(res["network"], res["dropped"])
+    log(f"hybrid = multipole + network: rel err {np.array2string(e, precision=2)}; "
+        f"network part {np.array2string(net_part, precision=2)}")
+    assert np.all(net_part > 1e-5), net_part
+    assert np.all(e <= 1e-3 * net_part + 1e-7), (e, net_part)
