@@ -274,14 +274,14 @@ def bench_surrogate(args):
     # teacher data
     t0 = time.perf_counter()
     X, T = [], []
-    for seed in (args.teacher_seeds if args.far == "learned" else []):
+    for seed in (args.teacher_seeds if args.far in ("learned", "hybrid") else []):
         tsys = config5(seed)
         p = plan_for_system(tsys, "fp32", stream=stream)
         p.surrogate_configure(FAR, n_lags=NL, audit=range(args.teacher_audit))
         log(f"teacher seed {seed}: {p.surrogate_info()}, workspace {p.workspace_bytes / 1e9:.1f} GB")
         p.bind()
         p.set_green_kernels()
-        x, t = S.collect_pair_responses(p, Gen(tsys), T_STEPS, start=1, every=3)
+        x, t = S.collect_pair_responses(p, Gen(tsys), T_STEPS, start=1, every=3, residual=args.far == "hybrid")
         X.append(x)
         T.append(t)
         p.close()
@@ -289,7 +289,7 @@ def bench_surrogate(args):
         torch.cuda.empty_cache()
         log(f"  {x.shape[0]} samples, {time.perf_counter() - t0:.0f} s")
     sur, n_samples, t_data, t_train, train_rms = None, 0, 0.0, 0.0, None
-    if args.far == "learned":
+    if args.far in ("learned", "hybrid"):
         X, T = torch.cat(X), torch.cat(T)
         t_data = time.perf_counter() - t0
         t0 = time.perf_counter()
@@ -315,7 +315,10 @@ def bench_surrogate(args):
         f"(plain FP32 would need {(pst['ring_bytes'] + pst['spectra_bytes']) / 1e9:.0f} GB of history)")
     plan.bind()
     plan.set_green_kernels()
-    if sur is not None:
+    if args.far == "hybrid":
+        plan.surrogate_multipole("hybrid")
+        plan.surrogate_attach(sur.mlp, sur.in_scale, sur.out_scale)
+    elif sur is not None:
         plan.surrogate_attach(sur.mlp, sur.in_scale, sur.out_scale)
     else:
         plan.surrogate_multipole(True)
@@ -395,8 +398,9 @@ def bench_surrogate(args):
             "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "32 sub-domains of 48^3 points, h=0.3 bohr, 2000-bohr box, dt=0.01, "
-                                   + ("learned far-pair surrogate" if args.far == "learned"
-                                      else "analytic multipole far-pair terms")
+                                   + {"learned": "learned far-pair surrogate",
+                                      "multipole": "analytic multipole far-pair terms",
+                                      "hybrid": "analytic multipole far-pair terms plus a learned correction"}[args.far]
                                    + " (pairs > 10 box diagonals apart)",
                        "precision": precision, "far_pairs": info["n_far"], "audited_far_pairs": info["n_audited"],
                        "judge_every": JUDGE_EVERY, "judge_tol": TOL, "fallbacks": fell,
@@ -676,8 +680,9 @@ def main():
                          "sweep: two 32x32x128 domains vs the box enclosing both, over the distance; "
                          "coupled: config 2 with oscillator sources driven by the potentials; "
                          "paper: the paper's two-molecule geometry, single and split history")
-    ap.add_argument("--far", default="learned", choices=["learned", "multipole"],
-                    help="surrogate workload: far-pair terms from the trained network or the analytic multipole")
+    ap.add_argument("--far", default="learned", choices=["learned", "multipole", "hybrid"],
+                    help="surrogate workload: far-pair terms from the trained network, the analytic "
+                         "multipole, or the multipole plus a network trained on its residual")
     ap.add_argument("--teacher-seeds", type=int, nargs="+", default=[101, 102, 103])
     ap.add_argument("--teacher-audit", type=int, default=3, help="audit sources per teacher system")
     ap.add_argument("--audit", type=int, nargs="*", default=[0, 1], help="audit sources of the timed run")
