@@ -627,12 +627,16 @@ void sur_multipole_response(rp_plan p, float *coef) {
     if (!coef) fail(RP_ERR_ARG, "coef is null");
     if (U.aud.empty() || U.pairs.empty()) return;
     hipStream_t st = p->stream;
-    launch_multipole(multipole_args(p, -1), st);
+    // into the network-output scratch: the step's own terms (which the judge
+    // corrects with) stay intact
+    MultipoleArgs ma = multipole_args(p, -1);
+    ma.pc = p->at<float>(U.off_y);
+    launch_multipole(ma, st);
     for (size_t v = 0; v < U.aud.size(); ++v) {
         XformArgs xa{};
         xa.pairs = p->at<FarPair>(U.off_fpairs);
         xa.mats = p->at<float>(U.off_mats);
-        xa.in = p->at<float>(U.off_pc) + size_t(U.aud[v]) * kNOut;
+        xa.in = p->at<float>(U.off_y) + size_t(U.aud[v]) * kNOut;
         xa.out = coef + size_t(U.aud_row[v]) * kNOut;
         xa.index = p->at<int32_t>(U.off_aud) + v;
         xa.dir = 1;

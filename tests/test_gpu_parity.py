@@ -163,3 +163,28 @@ def test_line_pass_tiles(precision, tile):
     ref = oracle.potential_full(s, S, [L])[0]
     e = rel_err(got[L], ref)
     assert np.all(e <= (FP64_TOL if precision == "fp64" else FP32_TOL)), e
+
+
+def test_single_domain_fp64():
+    """One sub-domain alone: the self pair only (ragged 12 x 10 x 9 grid)."""
+    rng = np.random.default_rng(21)
+    d = sy.Domain((12, 10, 9), np.array([1.0, -2.0, 0.5]))
+    sy._random_pairs(rng, d, 0.5, 2)
+    _check(sy.System(0.5, 0.02, sy.C_AU, [d], name="single domain"), "fp64", 12, FP64_TOL)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_largest_fft_length(precision, tol):
+    """Two thin 256-point domains: the pads reach 512 along x and z, the
+    largest transform length of the library."""
+    from paper_2311_15429_amd import plan_for_system
+    h = 0.5
+    doms = [sy.Domain((256, 4, 4), np.array([0.0, 0.0, 0.0])), sy.Domain((4, 4, 256), np.array([10.0, 8.0, 0.0]))]
+    rng = np.random.default_rng(22)
+    for d in doms:
+        sy._random_pairs(rng, d, h, 2)
+    s = sy.System(h, 0.02, sy.C_AU, doms, name="pads 512")
+    p = plan_for_system(s, precision)
+    assert tuple(p.info(0, 0)[2]) == (512, 8, 512)
+    p.close()
+    _check(s, precision, 8, tol, steps=[4, 8])

@@ -325,3 +325,29 @@ def test_hybrid_adds_the_network_to_the_multipole_terms():
         f"network part {np.array2string(net_part, precision=2)}")
     assert np.all(net_part > 1e-5), net_part
     assert np.all(e <= 1e-3 * net_part + 1e-7), (e, net_part)
+
+
+def test_multipole_response_leaves_the_judged_step_intact():
+    """The judge corrects a step with that step's own far-pair terms: asking
+    for the multipole response first must not change what it does."""
+    system = far_system(10)
+    L = 30
+    res = []
+    for query in (False, True):
+        gen = GpuSourceGen(system, torch.float32)
+        p = make_plan(system)
+        info = p.surrogate_info()
+        mlp = _random_mlp(info["n_in"], info["n_far"], scale=0.05, seed=3)
+        p.surrogate_multipole("hybrid")
+        p.surrogate_attach(mlp, np.full(22, 1.0, np.float32), np.full(80, 1e-2, np.float32))
+        outs = run(p, gen, L)
+        if query:
+            p.surrogate_multipole_response()
+        nf, _ = p.surrogate_judge(outs, 1e-6)
+        assert nf == info["n_far"]
+        res.append([o.cpu().numpy().copy() for o in outs])
+        p.surrogate_attach(None)
+        p.close()
+        mlp.close()
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
