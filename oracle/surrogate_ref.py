@@ -67,6 +67,28 @@ def moments(dS, dom, h):
     return out
 
 
+# index triples of the 10 distinct third moments, in storage order
+OCT = [(0, 0, 0), (1, 1, 1), (2, 2, 2), (0, 0, 1), (0, 0, 2), (0, 1, 1), (1, 1, 2), (0, 2, 2), (1, 2, 2), (0, 1, 2)]
+# index pairs of the 6 distinct second moments (xx yy zz xy xz yz)
+PAIRS = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+
+
+def higher_moments(dS, dom, h):
+    """The 28 further moments of dS [4][N] used by the analytic far field
+    (weight h^3, about the box centre): the charge's third moments
+    O_ijk = sum dS_0 x_i x_j x_k (10, in OCT order) and the current's second
+    moments N_i,jk = sum dS_{1+i} x_j x_k (3 x 6, PAIRS order)."""
+    r = grid_points(dom, h) - box_centre(dom, h)[None, :]
+    w = h ** 3
+    out = np.zeros(28)
+    for k, (a, b, c) in enumerate(OCT):
+        out[k] = w * np.sum(dS[0] * r[:, a] * r[:, b] * r[:, c])
+    for i in range(3):
+        for k, (a, b) in enumerate(PAIRS):
+            out[10 + 6 * i + k] = w * np.sum(dS[1 + i] * r[:, a] * r[:, b])
+    return out
+
+
 def frame(d):
     """Rows e1, e2, e3 of the pair frame for d = c_target - c_source."""
     d = np.asarray(d, dtype=np.float64)
@@ -166,34 +188,65 @@ def frame_synth(system, s, n, a):
 # ---------------------------------------------------------------------------
 # Analytic multipole field of a far source (the non-learned far-pair path).
 #
-# With R the vector from the source centre to the target point, u = R/|R|,
-# tau = t - |R|/c and the moments f(tau) of dS (dots: time derivatives):
-#   v   = q/R + u.p/R^2 + u.p'/(c R)
-#         + (3 u.Q.u - tr Q)/(2 R^3) + (3 u.Q'.u - tr Q')/(2 c R^2) + u.Q''.u/(2 c^2 R)
-#   A_i = J_i/R + u.K_i/R^2 + u.K_i'/(c R)
-# the retarded Taylor expansion of sum_r' dS(r', t - |R - r'|/c)/|R - r'| to
-# second order in r' (to first order for the current, whose second moments
-# are not kept).  The moments between samples are cubic Lagrange
-# interpolants of the four samples around tau.
+# With R the vector from the source centre to the target point, u = R/|R| and
+# the source shape expanded about the centre, every term of the lag sum is
+# F(t - |R - r'|/c) / |R - r'| with r' the source point.  Its Taylor expansion
+# in r' is sum_n (-1)^n / n! (r'.grad)^n [F(t - R/c) / R], so the moment of
+# order n multiplies the n-th gradient of the radial function
+# g(R) = F(t - R/c)/R, whose R-derivatives are (F^(k): k-th time derivative)
+#   g1 = -F/R^2 - F^(1)/(cR)
+#   g2 = 2F/R^3 + 2F^(1)/(cR^2) + F^(2)/(c^2 R)
+#   g3 = -6F/R^4 - 6F^(1)/(cR^3) - 3F^(2)/(c^2 R^2) - F^(3)/(c^3 R),
+# and the gradients of a radial function are
+#   d_i g = u_i g1,  d_ij g = u_i u_j (g2 - g1/R) + delta_ij g1/R,
+#   d_ijk g = u_i u_j u_k (g3 - 3 g2/R + 3 g1/R^2) + (delta_ij u_k + ...)(g2/R - g1/R^2).
+# Contracting with the charge moments to third order and the current moments
+# to second order gives, with the time derivatives at t - R/c:
+#   v   = q/R + u.p/R^2 + u.p^(1)/(cR)
+#         + (3 u.Q.u - tr Q)/(2R^3) + (3 u.Q^(1).u - tr Q^(1))/(2cR^2) + u.Q^(2).u/(2c^2 R)
+#         + (15 O_uuu - 9 u.trO)/(6R^4) + (15 O^(1)_uuu - 9 u.trO^(1))/(6cR^3)
+#         + (6 O^(2)_uuu - 3 u.trO^(2))/(6c^2 R^2) + O^(3)_uuu/(6c^3 R)
+#   A_i = J_i/R + u.K_i/R^2 + u.K_i^(1)/(cR)
+#         + (3 u.N_i.u - tr N_i)/(2R^3) + (3 u.N_i^(1).u - tr N_i^(1))/(2cR^2)
+#         + u.N_i^(2).u/(2c^2 R)
+# (O_uuu = sum O_ijk u_i u_j u_k, (trO)_k = sum_i O_iik).  The moments between
+# samples are cubic Lagrange interpolants of the four samples around the
+# retarded time; the derivatives are those of the same cubic.
 
 def _cubic_weights(u):
-    """Value, first and second derivative weights (per step) at u in [0, 1)
-    for samples at -1, 0, 1, 2."""
+    """Value and first, second, third derivative weights (per step) at u in
+    [0, 1) for samples at -1, 0, 1, 2."""
     x = np.array([-1.0, 0.0, 1.0, 2.0])
-    w, d1, d2 = np.zeros(4), np.zeros(4), np.zeros(4)
+    w, d1, d2, d3 = np.zeros(4), np.zeros(4), np.zeros(4), np.zeros(4)
     for k in range(4):
         others = [x[j] for j in range(4) if j != k]
         den = np.prod([x[k] - o for o in others])
-        # polynomial prod (u - o) / den: value, first and second derivative
+        # polynomial prod (u - o) / den: value and derivatives
         a, b, c_ = others
         w[k] = (u - a) * (u - b) * (u - c_) / den
         d1[k] = ((u - b) * (u - c_) + (u - a) * (u - c_) + (u - a) * (u - b)) / den
         d2[k] = 2.0 * ((u - a) + (u - b) + (u - c_)) / den
-    return w, d1, d2
+        d3[k] = 6.0 / den
+    return w, d1, d2, d3
 
 
-def multipole_field(system, samples, s, n, l, pts):
-    """v and A [4][len(pts)] of source n at points pts [n][3] and step l."""
+def _sym3(f):
+    """Full 3x3x3 tensor from the 10 distinct third moments (OCT order)."""
+    T = np.zeros((3, 3, 3))
+    for k, (a, b, c) in enumerate(OCT):
+        for idx in {(a, b, c), (a, c, b), (b, a, c), (b, c, a), (c, a, b), (c, b, a)}:
+            T[idx] = f[k]
+    return T
+
+
+def _sym2(f):
+    """Symmetric 3x3 matrix from (xx yy zz xy xz yz)."""
+    return np.array([[f[0], f[3], f[4]], [f[3], f[1], f[5]], [f[4], f[5], f[2]]])
+
+
+def multipole_field(system, samples, s, n, l, pts, order=3):
+    """v and A [4][len(pts)] of source n at points pts [n][3] and step l
+    (order=2: charge to second and current to first order only)."""
     h, dt, c = system.h, system.dt, system.c
     dom = system.domains[n]
     cn = box_centre(dom, h)
@@ -201,9 +254,10 @@ def multipole_field(system, samples, s, n, l, pts):
 
     def m_at(t):
         if t <= 0:
-            return np.zeros(N_FEAT)
+            return np.zeros(N_FEAT + 28)
         if t not in mom:
-            mom[t] = moments(samples[n][t] - samples[n][0], dom, h)
+            d = samples[n][t] - samples[n][0]
+            mom[t] = np.concatenate([moments(d, dom, h), higher_moments(d, dom, h)])
         return mom[t]
 
     out = np.zeros((4, len(pts)))
@@ -213,18 +267,40 @@ def multipole_field(system, samples, s, n, l, pts):
         u = Rv / R
         tau = l - R / (c * dt)
         a = int(np.floor(tau))
-        w, d1, d2 = _cubic_weights(tau - a)
+        w, d1, d2, d3 = _cubic_weights(tau - a)
         F = np.stack([m_at(a - 1 + j) for j in range(4)])
-        f0, f1, f2 = w @ F, (d1 @ F) / dt, (d2 @ F) / (dt * dt)
+        f = [w @ F, (d1 @ F) / dt, (d2 @ F) / dt ** 2, (d3 @ F) / dt ** 3]
+        # the lag sum reads the sources through their linear interpolant (the
+        # triangle basis), which lies on the chords: averaged over the spread of
+        # retarded times across a source it is S + dt^2/12 S''.  The far terms
+        # carry the same bias, so that they model the plain lag sum.
+        f = [f[0] + dt * dt / 12.0 * f[2], f[1] + dt * dt / 12.0 * f[3], f[2], f[3]]
 
-        def Qm(f):
-            return np.array([[f[4], f[7], f[8]], [f[7], f[5], f[9]], [f[8], f[9], f[6]]])
-        v = f0[0] / R + u @ f0[1:4] / R ** 2 + u @ f1[1:4] / (c * R)
-        v += (3 * u @ Qm(f0) @ u - np.trace(Qm(f0))) / (2 * R ** 3)
-        v += (3 * u @ Qm(f1) @ u - np.trace(Qm(f1))) / (2 * c * R ** 2)
-        v += (u @ Qm(f2) @ u) / (2 * c * c * R)
-        K0, K1 = f0[13:22].reshape(3, 3), f1[13:22].reshape(3, 3)
-        A = f0[10:13] / R + K0 @ u / R ** 2 + K1 @ u / (c * R)
+        def Qm(g):
+            return np.array([[g[4], g[7], g[8]], [g[7], g[5], g[9]], [g[8], g[9], g[6]]])
+
+        def oct_terms(g):
+            T = _sym3(g[22:32])
+            return np.einsum("ijk,i,j,k->", T, u, u, u), np.einsum("iik,k->", T, u)
+
+        v = f[0][0] / R + u @ f[0][1:4] / R ** 2 + u @ f[1][1:4] / (c * R)
+        v += (3 * u @ Qm(f[0]) @ u - np.trace(Qm(f[0]))) / (2 * R ** 3)
+        v += (3 * u @ Qm(f[1]) @ u - np.trace(Qm(f[1]))) / (2 * c * R ** 2)
+        v += (u @ Qm(f[2]) @ u) / (2 * c * c * R)
+        K0, K1 = f[0][13:22].reshape(3, 3), f[1][13:22].reshape(3, 3)
+        A = f[0][10:13] / R + K0 @ u / R ** 2 + K1 @ u / (c * R)
+        out[0, k] = v
+        out[1:4, k] = A
+        if order < 3:
+            continue
+        o0, o1, o2, o3 = (oct_terms(g) for g in f)
+        v += (15 * o0[0] - 9 * o0[1]) / (6 * R ** 4) + (15 * o1[0] - 9 * o1[1]) / (6 * c * R ** 3)
+        v += (6 * o2[0] - 3 * o2[1]) / (6 * c * c * R ** 2) + o3[0] / (6 * c ** 3 * R)
+        for i in range(3):
+            N0, N1, N2 = (_sym2(g[32 + 6 * i: 38 + 6 * i]) for g in f[:3])
+            A[i] += (3 * u @ N0 @ u - np.trace(N0)) / (2 * R ** 3)
+            A[i] += (3 * u @ N1 @ u - np.trace(N1)) / (2 * c * R ** 2)
+            A[i] += (u @ N2 @ u) / (2 * c * c * R)
         out[0, k] = v
         out[1:4, k] = A
     return out
