@@ -339,10 +339,16 @@ rp_status rp_surrogate_attach(rp_plan plan, rp_mlp mlp, const float *in_scale, c
  * retarded multipole field of the source is evaluated at a 4 x 4 x 4 node grid
  * of the target box (box coordinates -1, -1/3, 1/3, 1) and fitted to the box
  * basis.  With R from the source centre, u = R/|R|, the moments at the retarded
- * time (cubic interpolation in time, which also gives the time derivatives):
- *   v   = q/R + u.p/R^2 + u.p'/(cR) + (3 u.Q.u - tr Q)/(2R^3)
- *         + (3 u.Q'.u - tr Q')/(2cR^2) + u.Q''.u/(2c^2 R),
- *   A_i = J_i/R + (K u)_i/R^2 + (K' u)_i/(cR).
+ * time (cubic interpolation in time, which also gives the time derivatives
+ * f^(k)), O the charge's third moments and N_i the current's second moments:
+ *   v   = q/R + u.p/R^2 + u.p^(1)/(cR) + (3 u.Q.u - tr Q)/(2R^3)
+ *         + (3 u.Q^(1).u - tr Q^(1))/(2cR^2) + u.Q^(2).u/(2c^2 R)
+ *         + (15 O_uuu - 9 u.trO)/(6R^4) + (15 O^(1)_uuu - 9 u.trO^(1))/(6cR^3)
+ *         + (6 O^(2)_uuu - 3 u.trO^(2))/(6c^2 R^2) + O^(3)_uuu/(6c^3 R),
+ *   A_i = J_i/R + (K u)_i/R^2 + (K^(1) u)_i/(cR) + (3 u.N_i.u - tr N_i)/(2R^3)
+ *         + (3 u.N_i^(1).u - tr N_i^(1))/(2cR^2) + u.N_i^(2).u/(2c^2 R),
+ * each moment and first derivative plus dt^2/12 times its next derivative
+ * (the lag sum reads the sources on the chords between samples).
  * The multipole approximation of far sub-domains named in Sec. V; it needs no
  * training.  The judge and fallback work as with a network.  Discards a
  * captured step.

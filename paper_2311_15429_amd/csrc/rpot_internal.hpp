@@ -250,8 +250,9 @@ void launch_advance_step(int64_t *step, int32_t *head, int32_t *prev, const DomD
 //   0 q = sum dS_0;  1..3 p_i = sum dS_0 x_i;  4..9 Q = sum dS_0 x_i x_j for
 //   (xx, yy, zz, xy, xz, yz);  10..12 J_i = sum dS_{1+i};
 //   13..21 K_ij = sum dS_{1+i} x_j (row-major i, j).
-constexpr int kNFeat = 22;
-constexpr int kFeatStride = 24;   // floats per moment-ring slot
+constexpr int kNFeat = 22;        // moments the network reads (q, p, Q, J, K)
+constexpr int kNMom = 50;         // plus the charge's third and the current's second moments
+constexpr int kFeatStride = 56;   // floats per moment-ring slot
 constexpr int kNBasis = 20;       // tensor-Legendre functions of total degree <= 3
 constexpr int kNOut = 4 * kNBasis;
 constexpr int kNGeo = 2;          // geometry features of a pair
@@ -262,7 +263,7 @@ struct MomentJob {
     const float *src;      // S(l) [4][Nx][Ny][Nz]
     const float *s0;       // S(0)
     float *ring;           // the source's moment ring [depth][kFeatStride]
-    float *partial;        // the source's partial sums [kMomChunks][kNFeat]
+    float *partial;        // the source's partial sums [kMomChunks][kNMom]
     int N[3];
     float o[3];            // position of point (0,0,0) relative to the domain centre
 };

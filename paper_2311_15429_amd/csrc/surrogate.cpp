@@ -339,7 +339,7 @@ void sur_layout(rp_plan p, size_t &off) {
     SurrogateH &U = p->sur;
     const size_t nf = U.pairs.size(), na = U.aud.size(), ns = U.src_doms.size(), nd = p->dom.size();
     U.off_mom = alloc(ns * U.mom_depth * kFeatStride * 4);
-    U.off_mpart = alloc(ns * kMomChunks * kNFeat * 4);
+    U.off_mpart = alloc(ns * kMomChunks * kNMom * 4);
     U.off_fpairs = alloc(nf * sizeof(FarPair));
     U.off_x = alloc(nf * U.n_in * 4);
     U.off_y = alloc(nf * kNOut * 4);
@@ -464,7 +464,7 @@ void sur_enqueue_moments(rp_plan p, const void *const *src, hipStream_t st) {
             J.src = static_cast<const float *>(src[n]);
             J.s0 = p->at<float>(d.off_s0);
             J.ring = p->at<float>(U.off_mom) + size_t(slot) * U.mom_depth * kFeatStride;
-            J.partial = p->at<float>(U.off_mpart) + size_t(slot) * kMomChunks * kNFeat;
+            J.partial = p->at<float>(U.off_mpart) + size_t(slot) * kMomChunks * kNMom;
             for (int c = 0; c < 3; ++c) {
                 J.N[c] = d.N[c];
                 J.o[c] = float(d.o[c] - centre(p, n, c));

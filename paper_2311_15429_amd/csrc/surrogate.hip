@@ -76,9 +76,9 @@ __device__ __forceinline__ float block_max(float v, float *red) {
 __global__ __launch_bounds__(256) void k_moments_partial(MomentArgs a) {
     const MomentJob &j = a.jobs[blockIdx.y];
     const int64_t npts = int64_t(j.N[0]) * j.N[1] * j.N[2];
-    float acc[kNFeat];
+    float acc[kNMom];
 #pragma unroll
-    for (int q = 0; q < kNFeat; ++q) acc[q] = 0.f;
+    for (int q = 0; q < kNMom; ++q) acc[q] = 0.f;
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < npts; i += int64_t(gridDim.x) * 256) {
         const int iz = int(i % j.N[2]);
         const int iy = int((i / j.N[2]) % j.N[1]);
@@ -87,36 +87,59 @@ __global__ __launch_bounds__(256) void k_moments_partial(MomentArgs a) {
         float d[4];
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) d[mu] = j.src[mu * npts + i] - j.s0[mu * npts + i];
+        // second-moment products x_a x_b (xx yy zz xy xz yz)
+        const float rr[6] = {r[0] * r[0], r[1] * r[1], r[2] * r[2], r[0] * r[1], r[0] * r[2], r[1] * r[2]};
         acc[0] += d[0];
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[1 + c] = fmaf(d[0], r[c], acc[1 + c]);
-        acc[4] = fmaf(d[0] * r[0], r[0], acc[4]);
-        acc[5] = fmaf(d[0] * r[1], r[1], acc[5]);
-        acc[6] = fmaf(d[0] * r[2], r[2], acc[6]);
-        acc[7] = fmaf(d[0] * r[0], r[1], acc[7]);
-        acc[8] = fmaf(d[0] * r[0], r[2], acc[8]);
-        acc[9] = fmaf(d[0] * r[1], r[2], acc[9]);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[4 + k] = fmaf(d[0], rr[k], acc[4 + k]);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             acc[10 + c] += d[1 + c];
 #pragma unroll
             for (int e = 0; e < 3; ++e) acc[13 + 3 * c + e] = fmaf(d[1 + c], r[e], acc[13 + 3 * c + e]);
         }
+        // third moments of the charge: xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz
+        const float dr0 = d[0] * r[0], dr1 = d[0] * r[1], dr2 = d[0] * r[2];
+        acc[22] = fmaf(dr0, rr[0], acc[22]);
+        acc[23] = fmaf(dr1, rr[1], acc[23]);
+        acc[24] = fmaf(dr2, rr[2], acc[24]);
+        acc[25] = fmaf(dr1, rr[0], acc[25]);
+        acc[26] = fmaf(dr2, rr[0], acc[26]);
+        acc[27] = fmaf(dr0, rr[1], acc[27]);
+        acc[28] = fmaf(dr2, rr[1], acc[28]);
+        acc[29] = fmaf(dr0, rr[2], acc[29]);
+        acc[30] = fmaf(dr1, rr[2], acc[30]);
+        acc[31] = fmaf(dr0, rr[5], acc[31]);
+        // second moments of the current: N_i,ab
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[32 + 6 * c + k] = fmaf(d[1 + c], rr[k], acc[32 + 6 * c + k]);
     }
-    __shared__ float red[256];
-#pragma unroll 1
-    for (int q = 0; q < kNFeat; ++q) {
-        const float v = block_sum<256>(acc[q], red);
-        if (threadIdx.x == 0) j.partial[blockIdx.x * kNFeat + q] = v;
+    // wave sums, then the four waves in a fixed order
+    __shared__ float red[4][kNMom];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kNMom; ++q) {
+        float v = acc[q];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNMom) {
+        const int q = threadIdx.x;
+        j.partial[blockIdx.x * kNMom + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
     }
 }
 
 __global__ void k_moments_final(MomentArgs a) {
     const MomentJob &j = a.jobs[blockIdx.x];
     const int q = threadIdx.x;
-    if (q >= kNFeat) return;
+    if (q >= kNMom) return;
     double s = 0.0;
-    for (int c = 0; c < kMomChunks; ++c) s += double(j.partial[c * kNFeat + q]);
+    for (int c = 0; c < kMomChunks; ++c) s += double(j.partial[c * kNMom + q]);
     const int64_t slot = (*a.step) % a.depth;
     j.ring[slot * kFeatStride + q] = float(s * a.h3);
 }
@@ -363,12 +386,19 @@ __global__ __launch_bounds__(256) void k_correct(CorrArgs a) {
 // Analytic multipole far-pair terms (see MultipoleArgs).  With R from the
 // source centre to a node, u = R/|R|, tau the retarded step l - |R|/(c dt)
 // and the moments f of dS at tau (cubic Lagrange interpolation of the four
-// ring samples around tau, which also gives the time derivatives):
-//   v   = q/R + u.p/R^2 + u.p'/(cR) + (3 u.Q.u - tr Q)/(2R^3)
-//         + (3 u.Q'.u - tr Q')/(2cR^2) + u.Q''.u/(2c^2 R)
-//   A_i = J_i/R + (K u)_i/R^2 + (K' u)_i/(cR)
-// (the retarded Taylor expansion of the pair's lag sum to second order in the
-// source coordinates, first order for the current).
+// ring samples around tau, which also gives the time derivatives f^(k)):
+//   v   = q/R + u.p/R^2 + u.p^(1)/(cR) + (3 u.Q.u - tr Q)/(2R^3)
+//         + (3 u.Q^(1).u - tr Q^(1))/(2cR^2) + u.Q^(2).u/(2c^2 R)
+//         + (15 O_uuu - 9 u.trO)/(6R^4) + (15 O^(1)_uuu - 9 u.trO^(1))/(6cR^3)
+//         + (6 O^(2)_uuu - 3 u.trO^(2))/(6c^2 R^2) + O^(3)_uuu/(6c^3 R)
+//   A_i = J_i/R + (K u)_i/R^2 + (K^(1) u)_i/(cR) + (3 u.N_i.u - tr N_i)/(2R^3)
+//         + (3 u.N_i^(1).u - tr N_i^(1))/(2cR^2) + u.N_i^(2).u/(2c^2 R)
+// (the retarded Taylor expansion of the pair's lag sum to third order in the
+// source coordinates for the charge, second order for the current; O the
+// charge's third moments, N_i the current's second moments).  The value and
+// first derivative carry + dt^2/12 times the next derivative: the lag sum
+// reads the sources through their linear interpolant in time, whose mean over
+// the spread of retarded times across a source lies that much above them.
 __global__ __launch_bounds__(64) void k_multipole(MultipoleArgs a) {
     const FarPair &fp = a.pairs[blockIdx.x];
     const int t = threadIdx.x;
@@ -381,48 +411,76 @@ __global__ __launch_bounds__(64) void k_multipole(MultipoleArgs a) {
     const double tau = double(l) - double(R) * a.inv_cdt;
     const int64_t a0 = int64_t(floor(tau));
     const float x = float(tau - double(a0));
-    // cubic Lagrange weights for samples at -1, 0, 1, 2 (value, d/dx, d2/dx2)
+    // cubic Lagrange weights for samples at -1, 0, 1, 2 (value, d/dx, d2/dx2, d3/dx3)
     const float w[4] = {-x * (x - 1.f) * (x - 2.f) / 6.f, (x + 1.f) * (x - 1.f) * (x - 2.f) / 2.f,
                         -(x + 1.f) * x * (x - 2.f) / 2.f, (x + 1.f) * x * (x - 1.f) / 6.f};
     const float d1[4] = {-(3.f * x * x - 6.f * x + 2.f) / 6.f, (3.f * x * x - 4.f * x - 1.f) / 2.f,
                          -(3.f * x * x - 2.f * x - 2.f) / 2.f, (3.f * x * x - 1.f) / 6.f};
     const float d2[4] = {-(6.f * x - 6.f) / 6.f, (6.f * x - 4.f) / 2.f, -(6.f * x - 2.f) / 2.f, (6.f * x) / 6.f};
+    const float d3[4] = {-1.f, 3.f, -3.f, 1.f};
     const float *ring = a.moments + int64_t(fp.src_slot) * a.depth * kFeatStride;
-    float f0[kNFeat], f1[kNFeat], f2[kNFeat];
+    float f0[kNMom], f1[kNMom], f2[kNMom], f3[kNMom];
 #pragma unroll
-    for (int q = 0; q < kNFeat; ++q) f0[q] = f1[q] = f2[q] = 0.f;
+    for (int q = 0; q < kNMom; ++q) f0[q] = f1[q] = f2[q] = f3[q] = 0.f;
     for (int k = 0; k < 4; ++k) {
         int64_t ts = a0 - 1 + k;
         if (ts > l) ts = l;   // never for a far pair; keeps the read inside the held history
         if (ts <= 0) continue;
         const float *v = ring + (ts % a.depth) * kFeatStride;
 #pragma unroll
-        for (int q = 0; q < kNFeat; ++q) {
+        for (int q = 0; q < kNMom; ++q) {
             f0[q] = fmaf(w[k], v[q], f0[q]);
             f1[q] = fmaf(d1[k], v[q], f1[q]);
             f2[q] = fmaf(d2[k], v[q], f2[q]);
+            f3[q] = fmaf(d3[k], v[q], f3[q]);
         }
     }
+    // per-step derivatives to per-time ones; the lag sum reads sources on the
+    // chords between samples, whose mean over a source is S + dt^2/12 S''
     const float idt = 1.f / a.dt, ic = 1.f / a.c, iR = 1.f / R;
-    auto quad = [&](const float *f) {   // u.Q.u and tr Q from (xx yy zz xy xz yz)
-        const float uqu = f[4] * u[0] * u[0] + f[5] * u[1] * u[1] + f[6] * u[2] * u[2] +
-                          2.f * (f[7] * u[0] * u[1] + f[8] * u[0] * u[2] + f[9] * u[1] * u[2]);
-        return make_float2(uqu, f[4] + f[5] + f[6]);
+#pragma unroll
+    for (int q = 0; q < kNMom; ++q) {
+        f1[q] *= idt;
+        f2[q] *= idt * idt;
+        f3[q] *= idt * idt * idt;
+        f0[q] = fmaf(a.dt * a.dt * (1.f / 12.f), f2[q], f0[q]);
+        f1[q] = fmaf(a.dt * a.dt * (1.f / 12.f), f3[q], f1[q]);
+    }
+    auto uMu = [&](const float *m) {   // u.M.u from (xx yy zz xy xz yz)
+        return m[0] * u[0] * u[0] + m[1] * u[1] * u[1] + m[2] * u[2] * u[2] +
+               2.f * (m[3] * u[0] * u[1] + m[4] * u[0] * u[2] + m[5] * u[1] * u[2]);
     };
-    const float2 Q0 = quad(f0), Q1 = quad(f1), Q2 = quad(f2);
-    const float up0 = u[0] * f0[1] + u[1] * f0[2] + u[2] * f0[3];
-    const float up1 = (u[0] * f1[1] + u[1] * f1[2] + u[2] * f1[3]) * idt;
-    float v = f0[0] * iR + up0 * iR * iR + up1 * ic * iR;
-    v += (3.f * Q0.x - Q0.y) * 0.5f * iR * iR * iR;
-    v += (3.f * Q1.x - Q1.y) * idt * 0.5f * ic * iR * iR;
-    v += Q2.x * idt * idt * 0.5f * ic * ic * iR;
+    auto octu = [&](const float *o) {  // O_uuu and u.trO from (xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz)
+        const float uuu = o[0] * u[0] * u[0] * u[0] + o[1] * u[1] * u[1] * u[1] + o[2] * u[2] * u[2] * u[2] +
+                          3.f * (o[3] * u[0] * u[0] * u[1] + o[4] * u[0] * u[0] * u[2] + o[5] * u[0] * u[1] * u[1] +
+                                 o[6] * u[1] * u[1] * u[2] + o[7] * u[0] * u[2] * u[2] + o[8] * u[1] * u[2] * u[2]) +
+                          6.f * o[9] * u[0] * u[1] * u[2];
+        const float tr = u[0] * (o[0] + o[5] + o[7]) + u[1] * (o[3] + o[1] + o[8]) + u[2] * (o[4] + o[6] + o[2]);
+        return make_float2(uuu, tr);
+    };
+    const float iR2 = iR * iR, iR3 = iR2 * iR, iR4 = iR2 * iR2;
+    float v = f0[0] * iR;
+    v += (u[0] * f0[1] + u[1] * f0[2] + u[2] * f0[3]) * iR2 + (u[0] * f1[1] + u[1] * f1[2] + u[2] * f1[3]) * ic * iR;
+    v += (3.f * uMu(f0 + 4) - (f0[4] + f0[5] + f0[6])) * 0.5f * iR3;
+    v += (3.f * uMu(f1 + 4) - (f1[4] + f1[5] + f1[6])) * 0.5f * ic * iR2;
+    v += uMu(f2 + 4) * 0.5f * ic * ic * iR;
+    const float2 O0 = octu(f0 + 22), O1 = octu(f1 + 22), O2 = octu(f2 + 22), O3 = octu(f3 + 22);
+    v += (15.f * O0.x - 9.f * O0.y) * (1.f / 6.f) * iR4;
+    v += (15.f * O1.x - 9.f * O1.y) * (1.f / 6.f) * ic * iR3;
+    v += (6.f * O2.x - 3.f * O2.y) * (1.f / 6.f) * ic * ic * iR2;
+    v += O3.x * (1.f / 6.f) * ic * ic * ic * iR;
     __shared__ float F[4][64];
     F[0][t] = v;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const float Ku0 = f0[13 + 3 * i] * u[0] + f0[14 + 3 * i] * u[1] + f0[15 + 3 * i] * u[2];
-        const float Ku1 = (f1[13 + 3 * i] * u[0] + f1[14 + 3 * i] * u[1] + f1[15 + 3 * i] * u[2]) * idt;
-        F[1 + i][t] = f0[10 + i] * iR + Ku0 * iR * iR + Ku1 * ic * iR;
+        const float Ku1 = f1[13 + 3 * i] * u[0] + f1[14 + 3 * i] * u[1] + f1[15 + 3 * i] * u[2];
+        const float *N0 = f0 + 32 + 6 * i, *N1 = f1 + 32 + 6 * i, *N2 = f2 + 32 + 6 * i;
+        float A = f0[10 + i] * iR + Ku0 * iR2 + Ku1 * ic * iR;
+        A += (3.f * uMu(N0) - (N0[0] + N0[1] + N0[2])) * 0.5f * iR3;
+        A += (3.f * uMu(N1) - (N1[0] + N1[1] + N1[2])) * 0.5f * ic * iR2;
+        A += uMu(N2) * 0.5f * ic * ic * iR;
+        F[1 + i][t] = A;
     }
     __syncthreads();
     for (int o = t; o < kNOut; o += 64) {
