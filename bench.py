@@ -322,24 +322,29 @@ def bench_surrogate(args):
         plan.surrogate_attach(sur.mlp, sur.in_scale, sur.out_scale)
     else:
         plan.surrogate_multipole(True)
+    if args.readmit > 0:
+        plan.surrogate_readmit(args.readmit)
     tuned = plan.autotune(iters=3)
     gen = Gen(system)
     outs = [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in plan.dims]
     W, K = args.warmup, args.steps
     judged = []
+    readmitted = []
 
     def step(l):
         plan.push_sources(l, gen(l))
         plan.retarded_step(l, outs)
         if l % JUDGE_EVERY == JUDGE_EVERY - 1:
             judged.append(plan.surrogate_judge(outs, TOL))
+            readmitted.append(plan.last_readmitted)
 
     for l in range(W + 1):
         step(l)
-    if any(n for n, _ in judged):
+    if any(n for n, _ in judged) or any(readmitted):
         # fallbacks changed the lag-sum schedule: tune it again
         tuned = plan.autotune(iters=3)
-        log(f"re-tuned after {sum(n for n, _ in judged)} fallbacks: {tuned}")
+        log(f"re-tuned after {sum(n for n, _ in judged)} fallbacks and {sum(readmitted)} re-admissions: "
+            f"{tuned}")
     # sources of the timed steps in device memory before the timed region
     src = [gen(l) for l in range(W + 1, W + K + 1)]
     torch.cuda.synchronize()
@@ -351,6 +356,7 @@ def bench_surrogate(args):
         plan.retarded_step(l, outs)
         if l % JUDGE_EVERY == JUDGE_EVERY - 1:
             judged.append(plan.surrogate_judge(outs, TOL))
+            readmitted.append(plan.last_readmitted)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     plan.profile_lagsum(False)
@@ -363,9 +369,11 @@ def bench_surrogate(args):
     achieved = st["lagsum_bytes"] / lag_s / 1e9
     plain_lag_ms = pst["lagsum_bytes"] / (achieved * 1e9) * 1e3
     fell = sum(n for n, _ in judged)
+    back = sum(readmitted)
+    plain_now = int(plan.surrogate_pairs()["fallen_back"].sum())
     log(f"step {ms_step:.2f} ms ({updates / 1e6:.1f} M updates/s), lag sum {lag_s * 1e3:.2f} ms at {achieved:.0f} GB/s; "
         f"plain lag sum alone would be {plain_lag_ms:.1f} ms ({pst['lagsum_bytes'] / 1e9:.0f} GB); "
-        f"judge: {len(judged)} calls, {fell} fallbacks")
+        f"judge: {len(judged)} calls, {fell} fallbacks, {back} re-admissions, {plain_now} pairs plain at the end")
 
     # error vs the FP64 oracle at sampled points of the last step, beside the
     # same points with the far pairs left out
@@ -408,6 +416,7 @@ def bench_surrogate(args):
                                    + " (pairs > 10 box diagonals apart)",
                        "precision": precision, "far_pairs": info["n_far"], "audited_far_pairs": info["n_audited"],
                        "judge_every": JUDGE_EVERY, "judge_tol": TOL, "fallbacks": fell,
+                       "readmit_factor": args.readmit, "readmissions": back, "plain_pairs_at_end": plain_now,
                        "rel_err_vs_fp64_oracle_sampled": [float(v) for v in err_s],
                        "rel_err_far_pairs_left_out_sampled": [float(v) for v in err_d],
                        "oracle_points": int(len(targets) * args.oracle_points), "step_of_check": l_end,
@@ -692,6 +701,8 @@ def main():
     ap.add_argument("--teacher-seeds", type=int, nargs="+", default=[101, 102, 103])
     ap.add_argument("--teacher-audit", type=int, default=3, help="audit sources per teacher system")
     ap.add_argument("--audit", type=int, nargs="*", default=[0, 1], help="audit sources of the timed run")
+    ap.add_argument("--readmit", type=float, default=0.5,
+                    help="surrogate workload: re-admission factor of fallen-back pairs (0: never)")
     ap.add_argument("--oracle-targets", type=int, default=3)
     ap.add_argument("--oracle-points", type=int, default=24)
     ap.add_argument("--calib-copy-mib", type=int, default=0,

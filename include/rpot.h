@@ -325,7 +325,15 @@ rp_status rp_history_split(rp_plan plan, int32_t min_gap);
  *     back to the plain lag sum from the next step on, and its term in out (the
  *     outputs of that step, corrected in place) is replaced by F.  Returns the
  *     number of pairs that fell back and the largest error/budget ratio over the
- *     judged pairs.  Synchronises the stream.  A captured step stays valid.
+ *     judged pairs.  With a re-admission factor (rp_surrogate_readmit) a
+ *     fallen-back audited pair whose far-pair terms are within factor x
+ *     tol * M_mu / (active far pairs of s + 1) in every component returns to
+ *     them from the next step on (n_readmitted, may be NULL).  Synchronises the
+ *     stream.  A captured step stays valid.
+ * rp_surrogate_readmit  the re-admission factor (>= 0; 0, the default: a pair
+ *     that falls back stays with the plain lag sum).  A transient, such as the
+ *     light-cone front of a source's switch-on crossing the target box, then
+ *     costs only the judge intervals it spans.
  */
 rp_status rp_surrogate_configure(rp_plan plan, double far_factor, int32_t n_lags, const int32_t *audit,
                                  int32_t n_audit);
@@ -366,7 +374,9 @@ rp_status rp_surrogate_multipole(rp_plan plan, int32_t enable);
 rp_status rp_surrogate_multipole_response(rp_plan plan, float *coef);
 rp_status rp_surrogate_features(rp_plan plan, float *x);
 rp_status rp_surrogate_pair_response(rp_plan plan, float *coef, float *resid);
-rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t *n_fallback, double *worst);
+rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t *n_fallback, double *worst,
+                             int32_t *n_readmitted);
+rp_status rp_surrogate_readmit(rp_plan plan, double factor);
 
 /*
  * Model response of the sources: the steps either side of the potential

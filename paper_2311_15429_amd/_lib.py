@@ -19,7 +19,7 @@ EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_set
            "rp_mlp_bind", "rp_mlp_n_params", "rp_mlp_set_params", "rp_mlp_get_params", "rp_mlp_forward",
            "rp_mlp_loss_grad", "rp_mlp_train_step", "rp_mlp_destroy", "rp_plan_destroy", "rp_last_error",
            "rp_mlp_last_error", "rp_surrogate_configure", "rp_surrogate_info", "rp_surrogate_pairs",
-           "rp_surrogate_attach", "rp_surrogate_multipole", "rp_surrogate_multipole_response", "rp_surrogate_features", "rp_surrogate_pair_response", "rp_surrogate_judge",
+           "rp_surrogate_attach", "rp_surrogate_multipole", "rp_surrogate_multipole_response", "rp_surrogate_features", "rp_surrogate_pair_response", "rp_surrogate_judge", "rp_surrogate_readmit",
            "rp_osc_create", "rp_osc_workspace_bytes", "rp_osc_bind", "rp_osc_set_state", "rp_osc_sources",
            "rp_osc_step", "rp_osc_state", "rp_osc_destroy", "rp_osc_last_error", "rp_history_split"]
 TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2, "fft_lds": 4}
@@ -94,7 +94,8 @@ def load():
     lib.rp_surrogate_multipole.argtypes = [vp, i32]
     lib.rp_surrogate_multipole_response.argtypes = [vp, vp]
     lib.rp_surrogate_pair_response.argtypes = [vp, vp, vp]
-    lib.rp_surrogate_judge.argtypes = [vp, P(vp), ctypes.c_double, P(i32), dp]
+    lib.rp_surrogate_judge.argtypes = [vp, P(vp), ctypes.c_double, P(i32), dp, P(i32)]
+    lib.rp_surrogate_readmit.argtypes = [vp, ctypes.c_double]
     lib.rp_history_split.argtypes = [vp, i32]
     lib.rp_osc_create.argtypes = [P(vp), vp, P(i32), dp]
     lib.rp_osc_workspace_bytes.argtypes = [vp, P(sz)]

@@ -1539,8 +1539,13 @@ rp_status rp_surrogate_pair_response(rp_plan plan, float *coef, float *resid) {
     return guarded(plan, [&] { sur_pair_response(plan, coef, resid); });
 }
 
-rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t *n_fallback, double *worst) {
-    return guarded(plan, [&] { sur_judge(plan, out, tol, n_fallback, worst); });
+rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t *n_fallback, double *worst,
+                             int32_t *n_readmitted) {
+    return guarded(plan, [&] { sur_judge(plan, out, tol, n_fallback, worst, n_readmitted); });
+}
+
+rp_status rp_surrogate_readmit(rp_plan plan, double factor) {
+    return guarded(plan, [&] { sur_readmit(plan, factor); });
 }
 
 rp_status rp_plan_destroy(rp_plan plan) {

@@ -153,6 +153,7 @@ struct SurrogateH {
     rp_mlp mlp = nullptr;
     bool attached = false;
     int multipole = 0;             // analytic multipole far-pair terms: 1 alone, 2 plus the network's correction
+    double readmit = 0;            // a fallen-back pair within readmit x its budget returns (0: never)
     size_t off_pinv = 0;           // [kNBasis][64] node-to-coefficient fit
 };
 
@@ -242,7 +243,8 @@ void sur_configure(rp_plan p, double far_factor, int n_lags, const int32_t *audi
 void sur_attach(rp_plan p, rp_mlp mlp, const float *in_scale, const float *out_scale);
 void sur_features(rp_plan p, float *x);
 void sur_pair_response(rp_plan p, float *coef, float *resid);
-void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, double *worst);
+void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, double *worst, int32_t *n_readmitted);
+void sur_readmit(rp_plan p, double factor);
 void sur_multipole(rp_plan p, int enable);
 void sur_multipole_response(rp_plan p, float *coef);
 void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int));

@@ -690,7 +690,7 @@ void sur_pair_response(rp_plan p, float *coef, float *resid) {
     });
 }
 
-void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, double *worst) {
+void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, double *worst, int32_t *n_readmitted) {
     need_ready(p);
     SurrogateH &U = p->sur;
     if (!U.attached && !U.multipole)
@@ -701,7 +701,7 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
     if (!(tol > 0)) fail(RP_ERR_ARG, "tol must be positive");
     hipStream_t st = p->stream;
     const int na = int(U.aud.size());
-    int fell = 0;
+    int fell = 0, back = 0;
     double w = 0.0;
     if (na > 0) {
         // per-pair budget: tol * (max |P_mu| over the target's system) / (active far pairs of the target),
@@ -772,9 +772,26 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
         HIP_OK(hipStreamSynchronize(st));
         HIP_OK(hipMemcpy(flags.data(), p->ws + U.off_fail, size_t(na) * 4, hipMemcpyDeviceToHost));
         HIP_OK(hipMemcpy(res.data(), p->ws + U.off_jres, res.size() * 4, hipMemcpyDeviceToHost));
+        // active far pairs per target before this judgement (the budgets' count)
+        std::vector<int> n_act(p->n_dom, 0);
+        for (int s : U.synth_targets) n_act[s] = active_far(p, s);
         for (int v = 0; v < na; ++v) {
             FarPairH &F = U.pairs[U.aud[v]];
-            if (F.plain) continue;
+            if (F.plain) {
+                // re-admission: within readmit x the budget the pair would have
+                // as one more active far pair of its target, in every component
+                if (U.readmit <= 0) continue;
+                bool ok = true;
+                for (int mu = 0; mu < 4; ++mu) {
+                    const double b = tol * smax[size_t(p->dom[F.s].sys) * 4 + mu] / (n_act[F.s] + 1);
+                    ok = ok && res[size_t(v) * 8 + mu] <= U.readmit * b;
+                }
+                if (ok) {
+                    F.plain = false;
+                    ++back;
+                }
+                continue;
+            }
             for (int mu = 0; mu < 4; ++mu) {
                 const double b = bud[size_t(F.s) * 4 + mu];
                 const double r = res[size_t(v) * 8 + mu];
@@ -785,7 +802,7 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
                 ++fell;
             }
         }
-        if (fell) {
+        if (fell || back) {
             main_k2(p, p->k2, plain_pair);
             upload_k2(p, p->k2, p->k2_dev, st);
             upload_csr(p, st);
@@ -795,6 +812,14 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
     }
     if (n_fallback) *n_fallback = fell;
     if (worst) *worst = w;
+    if (n_readmitted) *n_readmitted = back;
+}
+
+void sur_readmit(rp_plan p, double factor) {
+    SurrogateH &U = p->sur;
+    if (!U.on) fail(RP_ERR_STATE, "surrogate not configured (rp_surrogate_configure)");
+    if (!(factor >= 0) || !std::isfinite(factor)) fail(RP_ERR_ARG, "factor must be finite and >= 0");
+    U.readmit = factor;
 }
 
 }  // namespace rpot_host

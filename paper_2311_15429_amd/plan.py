@@ -285,12 +285,19 @@ class Plan:
 
     def surrogate_judge(self, outputs, tol):
         """Judge the active audited far pairs of the last step against the plain
-        sum; returns (pairs that fell back, largest error / budget)."""
+        sum; returns (pairs that fell back, largest error / budget).  Pairs
+        re-admitted by the same call are in self.last_readmitted."""
         arr = self._ptrs(outputs)
-        nf, worst = ctypes.c_int32(), ctypes.c_double()
+        nf, worst, back = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
         _lib.check(self._lib, self._h, self._lib.rp_surrogate_judge(self._h, arr, float(tol), ctypes.byref(nf),
-                                                                    ctypes.byref(worst)))
+                                                                    ctypes.byref(worst), ctypes.byref(back)))
+        self.last_readmitted = int(back.value)
         return int(nf.value), float(worst.value)
+
+    def surrogate_readmit(self, factor):
+        """Fallen-back pairs within factor x their budget return to the far-pair
+        terms at the next judgement (0: never)."""
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_readmit(self._h, float(factor)))
 
     def close(self):
         if getattr(self, "_h", None):

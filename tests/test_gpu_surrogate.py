@@ -351,3 +351,38 @@ def test_multipole_response_leaves_the_judged_step_intact():
         mlp.close()
     for a, b in zip(*res):
         assert np.array_equal(a, b)
+
+
+def test_readmission_restores_the_far_terms():
+    """Every audited pair falls back under a tiny tolerance, then returns under
+    a loose one with a re-admission factor: from then on the outputs are those
+    of a run that never fell back, bit for bit."""
+    system = far_system(11)
+    L, Lf, Lb = 60, 42, 47   # after every far field has arrived (farthest pair: 33 lags)
+    res = []
+    for judge in (False, True):
+        gen = GpuSourceGen(system, torch.float32)
+        p = make_plan(system)
+        n_far = p.surrogate_info()["n_far"]
+        p.surrogate_multipole(True)
+        outs = [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in p.dims]
+        seq = {}
+        for l in range(L + 1):
+            p.push_sources(l, gen.step(l))
+            p.retarded_step(l, outs)
+            if judge and l == Lf:
+                nf, _ = p.surrogate_judge(outs, 1e-12)
+                assert nf == n_far and p.last_readmitted == 0
+                assert p.surrogate_pairs()["fallen_back"].all()
+            if judge and l == Lb:
+                p.surrogate_readmit(0.5)
+                nf, _ = p.surrogate_judge(outs, 1e3)
+                assert nf == 0 and p.last_readmitted == n_far
+                assert not p.surrogate_pairs()["fallen_back"].any()
+            if l > Lb:
+                seq[l] = [o.cpu().numpy().copy() for o in outs]
+        res.append(seq)
+        p.close()
+    for l in res[0]:
+        for x, y in zip(res[0][l], res[1][l]):
+            assert np.array_equal(x, y), l
