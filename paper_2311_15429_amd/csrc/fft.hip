@@ -199,6 +199,14 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
         obase = reinterpret_cast<char *>(obase) + slot * job.slot_stride * esz;
         if (qs) qs += slot * 4;
     }
+    // the snapshot's four component scales, inverted once (powers of two: exact)
+    float iq0 = 1.0f, iq1 = 1.0f, iq2 = 1.0f, iq3 = 1.0f;
+    if (FMT == RING_F16 || FMT == RING_BF16) {
+        iq0 = 1.0f / qs[0];
+        iq1 = 1.0f / qs[1];
+        iq2 = 1.0f / qs[2];
+        iq3 = 1.0f / qs[3];
+    }
     const bool jfast_out = (a.out_j == 1);
     const int nout = a.n_out;
     for (int e = threadIdx.x; e < L * nout; e += NT) {
@@ -214,9 +222,9 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
             const int line = line0 + li;
             const int outer = a.dinner.div(line);
             const int inner = line - outer * a.n_inner;
-            float inv_scale = 1.0f;
             // the component is the fastest batch index (inner mod 4)
-            if (FMT == RING_F16 || FMT == RING_BF16) inv_scale = 1.0f / qs[inner & 3];
+            const int comp = inner & 3;
+            const float inv_scale = comp == 0 ? iq0 : (comp == 1 ? iq1 : (comp == 2 ? iq2 : iq3));
             int64_t idx = outer * a.out_outer + inner * a.out_inner + int64_t(j) * a.out_j;
             if (job.tile_stride) {
                 // tile_comp is 1 or 4; one job's indices stay below 2^31
