@@ -158,6 +158,7 @@ typedef struct {
     double fft_bytes_inv;     /* minimal bytes of the inverse FFT passes per step  */
     double history_bytes;     /* real-space source rings of a split history        */
     int64_t split_rings;      /* extra spectral rings of a split history           */
+    int64_t n_classes;        /* shape classes (same grid and FFT pad)             */
 } rp_stats;
 
 rp_status rp_plan_stats(rp_plan plan, rp_stats *out);
@@ -184,11 +185,24 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
  *   RP_TUNE_FFT_LDS            complex values an FFT line-pass block stages in
  *                              LDS (whole lines): 2048, 4096 or 6144 in FP32
  *                              (half as many in FP64); 0 = default (2048 for
- *                              FP32 plans, 4096 for FP64 plans).
+ *                              FP32 plans, 4096 for FP64 plans).  Also per
+ *                              shape class (below).
  * Setting a knob discards a captured step (rp_capture_step).
  */
 enum { RP_TUNE_LAGSUM_UNROLL = 1, RP_TUNE_LAGSUM_PERSISTENT = 2, RP_TUNE_FFT_LDS = 4 };
 rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value);
+/*
+ * Shape classes: sub-domains with the same grid and FFT pad share their
+ * transform launches.  rp_class_info gives class cls (0 <= cls < n_classes of
+ * rp_plan_stats): its grid, pad and number of sub-domains.  The line-pass tile
+ * (RP_TUNE_FFT_LDS, the only per-class knob) may be chosen per class:
+ * rp_set_class_tuning (0: the plan's value), rp_get_class_tuning (the value in
+ * effect).  rp_set_tuning(RP_TUNE_FFT_LDS) resets every class to the plan's
+ * value; rp_autotune chooses a tile per class.
+ */
+rp_status rp_class_info(rp_plan plan, int32_t cls, int32_t dims[3], int32_t pad[3], int32_t *n_domains);
+rp_status rp_set_class_tuning(rp_plan plan, int32_t cls, int32_t knob, int32_t value);
+rp_status rp_get_class_tuning(rp_plan plan, int32_t cls, int32_t knob, int32_t *value);
 rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value);
 
 /*

@@ -580,6 +580,7 @@ void plan_stats(rp_plan p) {
     for (const VRingP &v : p->vring) st.ring_bytes += double(v.W) * p->sys[p->dom[v.n].sys].Cpad * 4 * p->ring_esz;
     for (const DomainP &d : p->dom) st.history_bytes += double(d.d1) * 4 * double(d.npts) * p->tsz;
     st.split_rings = int64_t(p->vring.size());
+    st.n_classes = int64_t(p->cls.size());
     for (const SystemP &S : p->sys) st.spectra_bytes += double(S.spec_elems) * p->spec_csz;
     for (const DomainP &d : p->dom) {
         const SystemP &S = p->sys[d.sys];
@@ -920,6 +921,9 @@ void do_static(rp_plan p, const void *const *src) {
 // Forward transform of dS(l) = S(l) - S(0) of every domain into the slot of
 // its ring given by the device-side head (no host-side step dependence, so
 // the same launches are valid inside a captured graph).
+// Line-pass tile of a shape class: its own choice, else the plan's.
+int cls_lds(rp_plan p, const ClassP &K) { return K.fft_lds ? K.fft_lds : p->fft_lds; }
+
 void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
     const bool quant = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
     const int32_t *dhead = p->at<int32_t>(p->off_head);
@@ -935,6 +939,7 @@ void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
             ZFwd z = zfwd_common(p, 0, K.N, K.P, K.Hz, p->p64);
             LinePass y = fwd_y(p, K.N, K.P, K.Hz, p->p64);
             LinePass x = fwd_x(p, K.N, K.P, K.Hz, p->p64);
+            y.lds_elems = x.lds_elems = cls_lds(p, K);
             x.out_fmt = p->ring_fmt;
             x.tile_comp = 4;
             ScaleArgs sa{};
@@ -1032,6 +1037,7 @@ void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st) {
             const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
             LinePass x = inv_x(p, K.N, K.P, K.Hz, p->p64);
             LinePass y = inv_y(p, K.N, K.P, K.Hz, p->p64);
+            x.lds_elems = y.lds_elems = cls_lds(p, K);
             ZInv zi{};
             zi.Nx = K.N[0];
             zi.Ny = K.N[1];
@@ -1177,12 +1183,15 @@ void do_launch_graph(rp_plan p, int64_t step) {
 
 // The inverse x and y passes of every target (accumulator -> temporaries
 // only): the autotuner's probe of the line-pass tile.
-void enqueue_inverse_xy(rp_plan p, hipStream_t st) {
-    for (const ClassP &K : p->cls) {
+void enqueue_inverse_xy(rp_plan p, hipStream_t st, int only_cls = -1) {
+    for (size_t ci = 0; ci < p->cls.size(); ++ci) {
+        if (only_cls >= 0 && int(ci) != only_cls) continue;
+        const ClassP &K = p->cls[ci];
         for (size_t j0 = 0; j0 < K.doms.size(); j0 += kMaxJobs) {
             const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
             LinePass x = inv_x(p, K.N, K.P, K.Hz, p->p64);
             LinePass y = inv_y(p, K.N, K.P, K.Hz, p->p64);
+            x.lds_elems = y.lds_elems = cls_lds(p, K);
             x.n_jobs = y.n_jobs = cnt;
             for (int j = 0; j < cnt; ++j) {
                 const DomainP &d = p->dom[K.doms[j0 + j]];
@@ -1233,26 +1242,28 @@ void do_autotune(rp_plan p, int iters, int32_t *best_unroll, int32_t *best_persi
         (void)hipEventDestroy(e1);
         throw;
     }
-    // line-pass tile
-    int bf = p->fft_lds;
+    // line-pass tile, per shape class
     try {
-        double bt = 1e300;
-        const int saved = p->fft_lds;
-        for (int e : {2048, 4096, 6144}) {
-            p->fft_lds = e;
-            enqueue_inverse_xy(p, st);   // warm-up
-            HIP_OK(hipEventRecord(e0, st));
-            for (int i = 0; i < iters; ++i) enqueue_inverse_xy(p, st);
-            HIP_OK(hipEventRecord(e1, st));
-            HIP_OK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < bt) {
-                bt = ms;
-                bf = e;
+        for (size_t ci = 0; ci < p->cls.size(); ++ci) {
+            ClassP &K = p->cls[ci];
+            double bt = 1e300;
+            int bf = K.fft_lds;
+            for (int e : {2048, 4096, 6144}) {
+                K.fft_lds = e;
+                enqueue_inverse_xy(p, st, int(ci));   // warm-up
+                HIP_OK(hipEventRecord(e0, st));
+                for (int i = 0; i < iters; ++i) enqueue_inverse_xy(p, st, int(ci));
+                HIP_OK(hipEventRecord(e1, st));
+                HIP_OK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < bt) {
+                    bt = ms;
+                    bf = e;
+                }
             }
+            K.fft_lds = bf;
         }
-        p->fft_lds = saved;
     } catch (...) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -1260,7 +1271,6 @@ void do_autotune(rp_plan p, int iters, int32_t *best_unroll, int32_t *best_persi
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    p->fft_lds = bf;
     p->k2_unroll = bu;
     p->k2_persist = bp;
     if (best_unroll) *best_unroll = bu;
@@ -1442,11 +1452,45 @@ rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value) {
             if (value != 0 && value != 2048 && value != 4096 && value != 6144)
                 fail(RP_ERR_ARG, "line-pass tile must be 0, 2048, 4096 or 6144");
             plan->fft_lds = value;
+            for (ClassP &K : plan->cls) K.fft_lds = 0;   // the plan's value for every class
             break;
         default:
             fail(RP_ERR_ARG, "unknown tuning knob");
         }
         release_graph(plan);   // a captured step holds the old schedule
+    });
+}
+
+rp_status rp_class_info(rp_plan plan, int32_t cls, int32_t dims[3], int32_t pad[3], int32_t *n_domains) {
+    return guarded(plan, [&] {
+        if (cls < 0 || cls >= int(plan->cls.size())) fail(RP_ERR_ARG, "shape class out of range");
+        const ClassP &K = plan->cls[cls];
+        for (int a = 0; a < 3; ++a) {
+            if (dims) dims[a] = K.N[a];
+            if (pad) pad[a] = K.P[a];
+        }
+        if (n_domains) *n_domains = int32_t(K.doms.size());
+    });
+}
+
+rp_status rp_set_class_tuning(rp_plan plan, int32_t cls, int32_t knob, int32_t value) {
+    return guarded(plan, [&] {
+        if (cls < 0 || cls >= int(plan->cls.size())) fail(RP_ERR_ARG, "shape class out of range");
+        if (knob != RP_TUNE_FFT_LDS) fail(RP_ERR_ARG, "only the line-pass tile is chosen per shape class");
+        if (value != 0 && value != 2048 && value != 4096 && value != 6144)
+            fail(RP_ERR_ARG, "line-pass tile must be 0, 2048, 4096 or 6144");
+        plan->cls[cls].fft_lds = value;
+        release_graph(plan);
+    });
+}
+
+rp_status rp_get_class_tuning(rp_plan plan, int32_t cls, int32_t knob, int32_t *value) {
+    return guarded(plan, [&] {
+        if (!value) fail(RP_ERR_ARG, "value is null");
+        if (cls < 0 || cls >= int(plan->cls.size())) fail(RP_ERR_ARG, "shape class out of range");
+        if (knob != RP_TUNE_FFT_LDS) fail(RP_ERR_ARG, "only the line-pass tile is chosen per shape class");
+        const int v = cls_lds(plan, plan->cls[cls]);
+        *value = v ? v : (plan->p64 ? 4096 : 2048);
     });
 }
 

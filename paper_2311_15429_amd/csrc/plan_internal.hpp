@@ -82,6 +82,7 @@ struct ClassP {
     int Hz;
     int64_t C;
     std::vector<int> doms;
+    int fft_lds = 0;         // this class's line-pass tile (0: the plan's)
 };
 
 // One lag-sum schedule: groups of up to 8 accumulator slots of one system,

@@ -138,6 +138,22 @@ class Plan:
         _lib.check(self._lib, self._h, self._lib.rp_get_tuning(self._h, _lib.TUNE[knob], ctypes.byref(v)))
         return int(v.value)
 
+    def classes(self):
+        """Shape classes: [{"dims", "pad", "n_domains", "fft_lds"}] in class order."""
+        n = self.stats()["n_classes"]
+        out = []
+        for c in range(n):
+            dims, pad, nd, v = (ctypes.c_int32 * 3)(), (ctypes.c_int32 * 3)(), ctypes.c_int32(), ctypes.c_int32()
+            _lib.check(self._lib, self._h, self._lib.rp_class_info(self._h, c, dims, pad, ctypes.byref(nd)))
+            _lib.check(self._lib, self._h, self._lib.rp_get_class_tuning(self._h, c, _lib.TUNE["fft_lds"],
+                                                                         ctypes.byref(v)))
+            out.append({"dims": tuple(dims), "pad": tuple(pad), "n_domains": int(nd.value), "fft_lds": int(v.value)})
+        return out
+
+    def set_class_tuning(self, cls, knob, value):
+        """Per-class knob (only "fft_lds"); 0 follows the plan's value."""
+        _lib.check(self._lib, self._h, self._lib.rp_set_class_tuning(self._h, int(cls), _lib.TUNE[knob], int(value)))
+
     def shape_key(self):
         """Autotuner cache key: device, precision and the plan's shape classes
         (grid and FFT pad per domain, with counts) and system count."""
@@ -150,11 +166,12 @@ class Plan:
         return f"{torch.cuda.get_device_name()}|{self.precision}|{sig}|systems={self.n_systems}"
 
     def autotune(self, iters=3, cache=None):
-        """Time every lag-sum schedule and line-pass tile on this bound plan
-        and keep the fastest.  With `cache` (a JSON file path) a stored choice
-        for the same device and shape classes is applied without timing, and a
-        new choice is stored.  Returns {"lagsum_unroll", "lagsum_persistent",
-        "fft_lds", "lagsum_ms", "cached"}."""
+        """Time every lag-sum schedule and, per shape class, every line-pass
+        tile on this bound plan and keep the fastest.  With `cache` (a JSON file
+        path) a stored choice for the same device and shape classes is applied
+        without timing, and a new choice is stored.  Returns {"lagsum_unroll",
+        "lagsum_persistent", "fft_lds" (the plan's), "fft_lds_per_class",
+        "lagsum_ms", "cached"}."""
         import json
         import os
         key = self.shape_key() if cache else None
@@ -166,12 +183,15 @@ class Plan:
             if rec:
                 for k in ("lagsum_unroll", "lagsum_persistent", "fft_lds"):
                     self.set_tuning(k, rec[k])
+                for c, v in enumerate(rec.get("fft_lds_per_class", [])):
+                    self.set_class_tuning(c, "fft_lds", v)
                 return dict(rec, cached=True)
         u, pe, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         _lib.check(self._lib, self._h, self._lib.rp_autotune(self._h, int(iters), ctypes.byref(u),
                                                              ctypes.byref(pe), ctypes.byref(ms)))
         res = {"lagsum_unroll": int(u.value), "lagsum_persistent": int(pe.value),
-               "fft_lds": self.get_tuning("fft_lds"), "lagsum_ms": float(ms.value)}
+               "fft_lds": self.get_tuning("fft_lds"),
+               "fft_lds_per_class": [c["fft_lds"] for c in self.classes()], "lagsum_ms": float(ms.value)}
         if cache:
             data = {}
             if os.path.exists(cache):

@@ -149,6 +149,17 @@ def test_fft_tile_knob_host():
     with pytest.raises(RpotError) as e:
         p.set_tuning("fft_lds", 1000)
     assert e.value.status == "RP_ERR_ARG"
+    # per shape class: config 1 has one class (two 16^3 domains, pad 32^3)
+    cls = p.classes()
+    assert cls == [{"dims": (16, 16, 16), "pad": (32, 32, 32), "n_domains": 2, "fft_lds": 2048}]
+    p.set_class_tuning(0, "fft_lds", 6144)
+    assert p.classes()[0]["fft_lds"] == 6144
+    p.set_tuning("fft_lds", 4096)                  # the plan's value resets every class
+    assert p.classes()[0]["fft_lds"] == 4096
+    for bad in ((1, "fft_lds", 2048), (0, "fft_lds", 1000), (0, "lagsum_unroll", 2)):
+        with pytest.raises(RpotError) as e:
+            p.set_class_tuning(*bad)
+        assert e.value.status == "RP_ERR_ARG"
     p.close()
 
 

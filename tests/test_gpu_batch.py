@@ -157,6 +157,10 @@ def test_autotune_selects_a_valid_schedule():
     assert res["lagsum_ms"] > 0
     assert p.get_tuning("lagsum_unroll") == res["lagsum_unroll"]
     assert p.get_tuning("fft_lds") == res["fft_lds"]
+    # one tile per shape class
+    assert len(res["fft_lds_per_class"]) == len(p.classes())
+    assert all(v in (2048, 4096, 6144) for v in res["fft_lds_per_class"])
+    assert [c["fft_lds"] for c in p.classes()] == res["fft_lds_per_class"]
     outs = [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in p.dims]
     for l in range(L + 1):
         p.push_sources(l, _src(S, l, p.dims, torch.float32))
@@ -199,3 +203,29 @@ def test_autotune_cache(tmp_path):
     for k in ("lagsum_unroll", "lagsum_persistent", "fft_lds"):
         assert second[k] == first[k] == q.get_tuning(k)
     q.close()
+
+
+def test_a_different_line_pass_tile_per_shape_class():
+    """Every shape class of a batched plan with its own line-pass tile: each
+    system still equals its own oracle run."""
+    system = _small_batch(2, 11)
+    L = 10
+    S = sy.sample_sources(system, range(L + 1))
+    p = _plan(system, "fp32")
+    cls = p.classes()
+    assert len(cls) >= 2
+    tiles = [(2048, 4096, 6144)[c % 3] for c in range(len(cls))]
+    for c, v in enumerate(tiles):
+        p.set_class_tuning(c, "fft_lds", v)
+    assert [c["fft_lds"] for c in p.classes()] == tiles
+    outs = [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in p.dims]
+    for l in range(L + 1):
+        p.push_sources(l, _src(S, l, p.dims, torch.float32))
+        p.retarded_step(l, outs)
+    got = [o.double().cpu().numpy().reshape(4, -1) for o in outs]
+    ref = oracle.potential_full(system, S, [L])[0]
+    e = rel_err(got, ref)
+    log(f"per-class tiles {tiles}: rel err {np.array2string(e, precision=2)}")
+    assert np.all(e <= 2e-5), e
+    p.close()
+
