@@ -231,7 +231,17 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
                 const uint32_t u = uint32_t(idx);
                 const uint32_t kk = a.tile_comp == 4 ? (u >> 2) : u;
                 const uint32_t c = u - kk * uint32_t(a.tile_comp);
-                idx = int64_t(kk / kTile) * job.tile_stride + int64_t((kk % kTile) * uint32_t(a.tile_comp) + c);
+                const uint32_t kt = kk % kTile;
+                // within a tile row: FP32 ring [c/2][k][c%2], FP64 ring [c][k],
+                // FP16/BF16 ring [k][c] (one 16-byte lane load of every ring
+                // row then covers a contiguous run); one component: [k]
+                uint32_t w = kt;
+                if (a.tile_comp == 4) {
+                    if (FMT == RING_F32) w = (c >> 1) * (2 * kTile) + kt * 2 + (c & 1);
+                    else if (FMT == RING_F64) w = c * kTile + kt;
+                    else w = kt * 4 + c;
+                }
+                idx = int64_t(kk / kTile) * job.tile_stride + int64_t(w);
             }
             Store<T, FMT>::put(obase, idx, buf[li * P + j], inv_scale);
         }

@@ -61,7 +61,7 @@ struct RingLoad<double, RING_F64> {
     __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *, Cx<double> (&x)[4]) {
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
-            const nu4 v = ld128(r, lane * 64 + mu * 16);
+            const nu4 v = ld128(r, (mu * kTile + lane) * 16);   // row [c][k]
             x[mu] = {__builtin_bit_cast(double, nu2{v.x, v.y}), __builtin_bit_cast(double, nu2{v.z, v.w})};
         }
     }
@@ -70,8 +70,8 @@ template <>
 struct RingLoad<float, RING_F32> {
     static constexpr int row_bytes = kTile * 4 * 8;
     __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *, Cx<float> (&x)[4]) {
-        const nu4 a = ld128(r, lane * 32);
-        const nu4 b = ld128(r, lane * 32 + 16);
+        const nu4 a = ld128(r, lane * 16);                 // row [c/2][k][c%2]
+        const nu4 b = ld128(r, (kTile + lane) * 16);
         x[0] = {__uint_as_float(a.x), __uint_as_float(a.y)};
         x[1] = {__uint_as_float(a.z), __uint_as_float(a.w)};
         x[2] = {__uint_as_float(b.x), __uint_as_float(b.y)};

@@ -74,9 +74,11 @@ struct LinePass {
     int64_t out_j, out_inner, out_outer;
     int dir;               // -1 forward, +1 inverse
     int out_fmt;           // RingFmt of the output (F64/F32 = plain complex)
-    int tile_comp;         // tiled output: interleaved components per frequency
-                           // (linear index e = k * tile_comp + c is stored at
-                           //  (k / kTile) * tile_stride + (k % kTile) * tile_comp + c)
+    int tile_comp;         // tiled output: components per frequency (1 or 4); the
+                           // linear index e = k * tile_comp + c goes to tile
+                           // k / kTile (stride tile_stride), and within it to
+                           // [c/2][k%kTile][c%2] (FP32 ring), [c][k%kTile] (FP64
+                           // ring) or [k%kTile][c] (FP16/BF16 ring, one component)
     const void *tw;        // twiddles exp(-2 pi i j / P), j < P
     RadixPlan rp;
     int n_jobs;
