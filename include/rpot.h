@@ -156,7 +156,8 @@ typedef struct {
     double spectra_bytes;     /* Green spectra                                     */
     double fft_bytes_fwd;     /* minimal bytes of the forward FFT passes per step  */
     double fft_bytes_inv;     /* minimal bytes of the inverse FFT passes per step  */
-    double history_bytes;     /* real-space source rings of a split history        */
+    double history_bytes;     /* real-space source rings of a split history, device
+                                 part (with the host tier: its staging snapshots)  */
     int64_t split_rings;      /* extra spectral rings of a split history           */
     int64_t n_classes;        /* shape classes (same grid and FFT pad)             */
 } rp_stats;
@@ -274,6 +275,35 @@ const char *rp_mlp_last_error(rp_mlp mlp);
  * (RP_ERR_UNSUPPORTED).  Re-plans ring depths, schedules and the workspace.
  */
 rp_status rp_history_split(rp_plan plan, int32_t min_gap);
+
+/*
+ * Host tier of a split history (Sec. IV keeps the retained history on disk;
+ * here the real-space rings move to pinned host memory and stream back one
+ * snapshot per split ring and step).  With enable != 0 the real-space ring of
+ * every split source lives in a caller-owned pinned host buffer
+ * (rp_history_host_bytes; hipHostMalloc or a pinned torch tensor), and the
+ * device keeps only staging snapshots: the newest sources of each split
+ * source and, per split ring, the snapshot the next step transforms again.
+ * The split rule then counts only the staging against the spectra saved.
+ * Each step, after the forward transforms, a second stream of the plan
+ * writes the newest sources to their host slot and fetches the next step's
+ * snapshots (PCIe, about 2 x 4 N x sizeof(source) bytes per split source per
+ * step); the copies overlap the lag sum and the inverse and are joined before
+ * the step ends.  Slots follow the device-side step counter, so captured
+ * steps work.  Results are bitwise identical to the device-resident tier.
+ *   rp_history_host: before rp_workspace_bytes / rp_bind_workspace
+ *     (RP_ERR_STATE after); re-plans like rp_history_split.
+ *   rp_history_host_bytes: host bytes needed (0 when nothing is split).
+ *   rp_bind_history_host: host_ptr 16-byte aligned pinned host memory of at
+ *     least that many bytes (RP_ERR_ARG if it is not pinned, RP_ERR_NOMEM if
+ *     too small); the caller owns it and keeps it alive while the plan runs.
+ *     A no-op when rp_history_host_bytes is 0.  rp_push_sources and
+ *     rp_capture_step fail with RP_ERR_STATE while a needed host buffer is
+ *     unbound.
+ */
+rp_status rp_history_host(rp_plan plan, int32_t enable);
+rp_status rp_history_host_bytes(rp_plan plan, size_t *bytes);
+rp_status rp_bind_history_host(rp_plan plan, void *host_ptr, size_t bytes);
 
 /*
  * Learned far-pair surrogate (an extension: the paper's closing section points

@@ -22,6 +22,7 @@ EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_set
            "rp_surrogate_attach", "rp_surrogate_multipole", "rp_surrogate_multipole_response", "rp_surrogate_features", "rp_surrogate_pair_response", "rp_surrogate_judge", "rp_surrogate_readmit",
            "rp_osc_create", "rp_osc_workspace_bytes", "rp_osc_bind", "rp_osc_set_state", "rp_osc_sources",
            "rp_osc_step", "rp_osc_state", "rp_osc_destroy", "rp_osc_last_error", "rp_history_split",
+           "rp_history_host", "rp_history_host_bytes", "rp_bind_history_host",
            "rp_class_info", "rp_set_class_tuning", "rp_get_class_tuning"]
 TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2, "fft_lds": 4}
 
@@ -98,6 +99,9 @@ def load():
     lib.rp_surrogate_judge.argtypes = [vp, P(vp), ctypes.c_double, P(i32), dp, P(i32)]
     lib.rp_surrogate_readmit.argtypes = [vp, ctypes.c_double]
     lib.rp_history_split.argtypes = [vp, i32]
+    lib.rp_history_host.argtypes = [vp, i32]
+    lib.rp_history_host_bytes.argtypes = [vp, P(ctypes.c_size_t)]
+    lib.rp_bind_history_host.argtypes = [vp, vp, ctypes.c_size_t]
     lib.rp_class_info.argtypes = [vp, i32, P(i32), P(i32), P(i32)]
     lib.rp_set_class_tuning.argtypes = [vp, i32, i32, i32]
     lib.rp_get_class_tuning.argtypes = [vp, i32, i32, P(i32)]

@@ -375,7 +375,8 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         }
         const T *__restrict__ S0 = reinterpret_cast<const T *>(job.s0);
         T *__restrict__ St = nullptr;
-        if (job.store) St = reinterpret_cast<T *>(job.store) + int64_t(*job.store_head) * 4 * npts;
+        if (job.store)
+            St = reinterpret_cast<T *>(job.store) + (job.store_head ? int64_t(*job.store_head) * 4 * npts : 0);
         for (int e = threadIdx.x; e < L * P; e += NT) {
             const int li = a.dP.div(e);
             const int z = e - li * P;

@@ -343,7 +343,8 @@ void plan_tables(rp_plan p) {
             else win.back().second = std::max(win.back().second, iv[i].second);
         }
         if (win.size() < 2) continue;
-        // split only where the spectra saved outweigh the real-space ring and
+        // split only where the spectra saved outweigh the real-space ring (in
+        // device memory; with the host tier only its staging snapshots) and
         // the transform scratch of the extra rings
         const SystemP &S = p->sys[d.sys];
         const double spec_slot = double(S.Cpad) * 4 * p->ring_esz;
@@ -351,8 +352,8 @@ void plan_tables(rp_plan p) {
         for (const auto &w : win) kept += w.second - w.first + 1;
         const double saved = double(d.span - kept) * spec_slot;
         const double scratch = double(d.N[0]) * (d.N[1] + S.P[1]) * S.Hz * 4 * p->csz;
-        const double cost = double(win.back().first + 1) * 4 * double(d.npts) * p->tsz +
-                            double(win.size() - 1) * scratch;
+        const double real_slots = p->hist_host ? double(win.size()) : double(win.back().first + 1);
+        const double cost = real_slots * 4 * double(d.npts) * p->tsz + double(win.size() - 1) * scratch;
         if (saved <= cost) continue;
         d.depth = win[0].second + 1;
         d.d1 = win.back().first + 1;
@@ -507,8 +508,22 @@ void plan_layout(rp_plan p) {
         v.off_zmax = quant ? alloc(size_t(d.zblocks) * 4 * sizeof(float)) : 0;
         v.off_t1 = alloc(size_t(d.N[0]) * d.N[1] * S.Hz * 4 * p->csz);
         v.off_t2 = alloc(size_t(d.N[0]) * S.P[1] * S.Hz * 4 * p->csz);
+        v.off_stage = p->hist_host ? alloc(size_t(4) * d.npts * p->tsz) : 0;
     }
-    for (DomainP &d : p->dom) d.off_hist = d.d1 > 0 ? alloc(size_t(d.d1) * 4 * d.npts * p->tsz) : 0;
+    p->host_bytes = 0;
+    p->host_dev = nullptr;
+    for (DomainP &d : p->dom) {
+        const size_t snap = size_t(4) * d.npts * p->tsz;
+        d.off_hist = d.off_stage = d.host_off = 0;
+        if (d.d1 == 0) continue;
+        if (p->hist_host) {
+            d.off_stage = alloc(snap);
+            d.host_off = p->host_bytes;
+            p->host_bytes += size_t(d.d1) * snap;
+        } else {
+            d.off_hist = alloc(size_t(d.d1) * snap);
+        }
+    }
     p->off_gtmp = alloc(size_t(kGreenChunk) * max_gtmp * 16);
     p->off_accd = alloc(max_C * 4 * 16);
     p->off_gstat = alloc(max_C * 16);
@@ -578,7 +593,8 @@ void plan_stats(rp_plan p) {
     st.lagsum_bytes = k2_bytes(p, p->k2);
     for (const DomainP &d : p->dom) st.ring_bytes += double(d.depth) * p->sys[d.sys].Cpad * 4 * p->ring_esz;
     for (const VRingP &v : p->vring) st.ring_bytes += double(v.W) * p->sys[p->dom[v.n].sys].Cpad * 4 * p->ring_esz;
-    for (const DomainP &d : p->dom) st.history_bytes += double(d.d1) * 4 * double(d.npts) * p->tsz;
+    for (const DomainP &d : p->dom)
+        if (d.d1 > 0) st.history_bytes += double(p->hist_host ? 1 + d.vr.size() : d.d1) * 4 * double(d.npts) * p->tsz;
     st.split_rings = int64_t(p->vring.size());
     st.n_classes = int64_t(p->cls.size());
     for (const SystemP &S : p->sys) st.spectra_bytes += double(S.spec_elems) * p->spec_csz;
@@ -958,14 +974,18 @@ void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
                 const size_t off_ring = split ? v->off_ring : d.off_ring;
                 const size_t off_zmax = split ? v->off_zmax : d.off_zmax;
                 const size_t off_scales = split ? v->off_scales : d.off_scales;
-                if (split) {
+                if (split && p->hist_host) {
+                    z.jobs[j].src = p->ws + v->off_stage;   // fetched from the host ring
+                } else if (split) {
                     z.jobs[j].src = p->ws + d.off_hist;
                     z.jobs[j].src_head = dhead + d.t1_idx;
                     z.jobs[j].src_depth = d.d1;
                     z.jobs[j].src_lag = v->lo;
                 } else {
                     z.jobs[j].src = src[n];
-                    if (d.d1 > 0) {
+                    if (d.d1 > 0 && p->hist_host) {
+                        z.jobs[j].store = p->ws + d.off_stage;   // written to the host ring
+                    } else if (d.d1 > 0) {
                         z.jobs[j].store = p->ws + d.off_hist;
                         z.jobs[j].store_head = dhead + d.t1_idx;
                     }
@@ -1075,6 +1095,68 @@ void enqueue_finish(rp_plan p, void *const *out, hipStream_t st) {
     check_launch();
 }
 
+// Host tier of a split history.  After the forward transforms of step l are
+// queued on st, a second stream writes S(l) from the staging buffer into its
+// host slot and fetches into each split ring's staging buffer the snapshot
+// that step l + 1 transforms again (S(l + 1 - lo), or S(0) before step 0);
+// the copies run under the lag sum and inverse of step l and are joined
+// before the step's ring heads move on (tier_join).  With write_newest false
+// (step 0) only the fetch runs.
+bool tier_active(rp_plan p) { return p->hist_host && p->host_bytes > 0; }
+
+void tier_fork(rp_plan p, hipStream_t st, bool write_newest) {
+    if (!tier_active(p)) return;
+    if (!p->host_dev) fail(RP_ERR_STATE, "the host history is not bound (rp_bind_history_host)");
+    HIP_OK(hipEventRecord(p->tier_fork, st));
+    HIP_OK(hipStreamWaitEvent(p->tier_stream, p->tier_fork, 0));
+    p->tier_open = true;
+    TierArgs out{}, in{};
+    out.step = in.step = p->at<int64_t>(p->off_state);
+    out.head = in.head = p->at<int32_t>(p->off_head);
+    auto flush = [&](TierArgs &a) {
+        launch_tier_copy(a, p->tier_stream);
+        check_launch();
+        a.n_jobs = 0;
+    };
+    for (const DomainP &d : p->dom) {
+        if (d.d1 == 0) continue;
+        const int64_t n16 = int64_t(4) * d.npts * int64_t(p->tsz) / 16;
+        uint4 *ring = reinterpret_cast<uint4 *>(p->host_dev + d.host_off);
+        if (write_newest) {
+            TierJob &j = out.jobs[out.n_jobs++];
+            j = TierJob{};
+            j.src = p->at<uint4>(d.off_stage);
+            j.dst = ring;
+            j.n16 = n16;
+            j.dst_depth = d.d1;
+            j.head_idx = d.t1_idx;
+            if (out.n_jobs == kMaxTierJobs) flush(out);
+        }
+    }
+    flush(out);   // every write lands before a fetch of the same slot (lo = 1)
+    for (const VRingP &v : p->vring) {
+        const DomainP &d = p->dom[v.n];
+        TierJob &j = in.jobs[in.n_jobs++];
+        j = TierJob{};
+        j.src = reinterpret_cast<const uint4 *>(p->host_dev + d.host_off);
+        j.dst = p->at<uint4>(v.off_stage);
+        j.alt = p->at<uint4>(d.off_s0);
+        j.n16 = int64_t(4) * d.npts * int64_t(p->tsz) / 16;
+        j.src_depth = d.d1;
+        j.shift = 1 - v.lo;
+        j.head_idx = d.t1_idx;
+        if (in.n_jobs == kMaxTierJobs) flush(in);
+    }
+    flush(in);
+    HIP_OK(hipEventRecord(p->tier_join, p->tier_stream));
+}
+
+void tier_join(rp_plan p, hipStream_t st) {
+    if (!p->tier_open) return;
+    HIP_OK(hipStreamWaitEvent(st, p->tier_join, 0));
+    p->tier_open = false;
+}
+
 void check_ptrs(rp_plan p, const void *const *ptrs, const char *what) {
     if (!ptrs) fail(RP_ERR_ARG, std::string(what) + " is null");
     for (int n = 0; n < p->n_dom; ++n)
@@ -1085,6 +1167,7 @@ void do_push(rp_plan p, int64_t step, const void *const *src) {
     if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
     if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
     check_ptrs(p, src, "src");
+    if (tier_active(p) && !p->host_dev) fail(RP_ERR_STATE, "the host history is not bound (rp_bind_history_host)");
     if (step != p->next_step || p->pushed) {
         char buf[128];
         std::snprintf(buf, sizeof buf, "rp_push_sources(%lld) out of order (expected step %lld%s)",
@@ -1097,14 +1180,17 @@ void do_push(rp_plan p, int64_t step, const void *const *src) {
             const DomainP &d = p->dom[n];
             launch_convert(p->ws + d.off_s0, p->p64, src[n], p->p64, 4 * d.npts, st);
             // the real-space ring starts with S(0) in every slot: sources before
-            // step 0 are S(0)
-            for (int j = 0; j < d.d1; ++j)
-                launch_convert(p->ws + d.off_hist + size_t(j) * 4 * d.npts * p->tsz, p->p64, src[n], p->p64,
-                               4 * d.npts, st);
+            // step 0 are S(0) (the host tier reads S(0) itself for those)
+            if (!p->hist_host)
+                for (int j = 0; j < d.d1; ++j)
+                    launch_convert(p->ws + d.off_hist + size_t(j) * 4 * d.npts * p->tsz, p->p64, src[n], p->p64,
+                                   4 * d.npts, st);
         }
         do_static(p, src);
+        tier_fork(p, st, false);
     } else {
         enqueue_ingest(p, src, st);
+        tier_fork(p, st, true);
         if (p->sur.on) sur_enqueue_moments(p, src, st);
     }
     check_launch();
@@ -1137,6 +1223,7 @@ void do_step(rp_plan p, int64_t step, void *const *out) {
         p->n_recorded += 1;
     }
     enqueue_inverse(p, out, st);
+    tier_join(p, st);
     enqueue_finish(p, out, st);
     p->next_step += 1;
     p->pushed = false;
@@ -1149,17 +1236,22 @@ void do_capture(rp_plan p, const void *const *src, void *const *out) {
     if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
     check_ptrs(p, src, "src");
     check_ptrs(p, out, "out");
+    if (p->tier_open) fail(RP_ERR_STATE, "capture a step after rp_retarded_step, not between push and step");
+    if (tier_active(p) && !p->host_dev) fail(RP_ERR_STATE, "the host history is not bound (rp_bind_history_host)");
     release_graph(p);
     if (!p->capture_stream) HIP_OK(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
     hipStream_t cs = p->capture_stream;
     HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     try {
         enqueue_ingest(p, src, cs);
+        tier_fork(p, cs, true);
         if (p->sur.on) sur_enqueue_moments(p, src, cs);
         enqueue_lagsum(p, cs, p->k2_unroll, p->k2_persist);
         enqueue_inverse(p, out, cs);
+        tier_join(p, cs);
         enqueue_finish(p, out, cs);
     } catch (...) {
+        p->tier_open = false;
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(cs, &g);
         if (g) (void)hipGraphDestroy(g);
@@ -1538,6 +1630,45 @@ rp_status rp_history_split(rp_plan plan, int32_t min_gap) {
     });
 }
 
+rp_status rp_history_host(rp_plan plan, int32_t enable) {
+    return guarded(plan, [&] {
+        if (plan->ws) fail(RP_ERR_STATE, "choose the host tier before rp_bind_workspace");
+        plan->hist_host = enable != 0;
+        plan_tables(plan);
+        plan_layout(plan);
+        plan_stats(plan);
+        release_graph(plan);
+    });
+}
+
+rp_status rp_history_host_bytes(rp_plan plan, size_t *bytes) {
+    return guarded(plan, [&] {
+        if (!bytes) fail(RP_ERR_ARG, "bytes is null");
+        *bytes = plan->host_bytes;
+    });
+}
+
+rp_status rp_bind_history_host(rp_plan plan, void *host_ptr, size_t bytes) {
+    return guarded(plan, [&] {
+        if (!plan->hist_host) fail(RP_ERR_STATE, "the host tier is off (rp_history_host)");
+        if (plan->host_bytes == 0) return;   // nothing was split: no host ring
+        if (!host_ptr) fail(RP_ERR_ARG, "host buffer is null");
+        if (bytes < plan->host_bytes) fail(RP_ERR_NOMEM, "host buffer smaller than rp_history_host_bytes");
+        if (reinterpret_cast<uintptr_t>(host_ptr) % 16) fail(RP_ERR_ARG, "host buffer must be 16-byte aligned");
+        void *dev = nullptr;
+        if (hipHostGetDevicePointer(&dev, host_ptr, 0) != hipSuccess || !dev) {
+            (void)hipGetLastError();
+            fail(RP_ERR_ARG, "host buffer is not pinned host memory (hipHostMalloc / pin_memory)");
+        }
+        if (plan->tier_stream) HIP_OK(hipStreamSynchronize(plan->tier_stream));
+        if (!plan->tier_stream) HIP_OK(hipStreamCreateWithFlags(&plan->tier_stream, hipStreamNonBlocking));
+        if (!plan->tier_fork) HIP_OK(hipEventCreateWithFlags(&plan->tier_fork, hipEventDisableTiming));
+        if (!plan->tier_join) HIP_OK(hipEventCreateWithFlags(&plan->tier_join, hipEventDisableTiming));
+        plan->host_dev = static_cast<char *>(dev);
+        release_graph(plan);
+    });
+}
+
 rp_status rp_surrogate_info(rp_plan plan, int32_t *n_far, int32_t *n_audited, int32_t *n_in, int32_t *n_out) {
     return guarded(plan, [&] {
         const SurrogateH &U = plan->sur;
@@ -1597,6 +1728,12 @@ rp_status rp_plan_destroy(rp_plan plan) {
     for (hipEvent_t ev : plan->events) (void)hipEventDestroy(ev);
     release_graph(plan);
     if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+    if (plan->tier_stream) {
+        (void)hipStreamSynchronize(plan->tier_stream);
+        (void)hipStreamDestroy(plan->tier_stream);
+    }
+    if (plan->tier_fork) (void)hipEventDestroy(plan->tier_fork);
+    if (plan->tier_join) (void)hipEventDestroy(plan->tier_join);
     delete plan;
     return RP_OK;
 }

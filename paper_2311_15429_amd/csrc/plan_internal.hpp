@@ -48,6 +48,9 @@ struct DomainP {
     int d1 = 0;
     int t1_idx = -1;
     size_t off_hist = 0;
+    // with the host tier: the real-space ring at byte host_off of the pinned
+    // host buffer, and a one-snapshot device staging buffer for the newest sources
+    size_t host_off = 0, off_stage = 0;
 };
 
 // A later lag window [lo, hi] of source n with its own spectral ring.
@@ -55,6 +58,7 @@ struct VRingP {
     int n = 0, lo = 0, hi = 0, W = 1;
     int idx = 0;             // ring / head slot index
     size_t off_ring = 0, off_scales = 0, off_zmax = 0, off_t1 = 0, off_t2 = 0;
+    size_t off_stage = 0;    // host tier: the snapshot the next step transforms again
 };
 
 struct SystemP {
@@ -183,6 +187,13 @@ struct rp_plan_s {
     int fft_lds = 0;     // line-pass tile: complex elements staged per block (0: default)
     int split_gap = 0;   // split a source's history at lag gaps of at least this many lags (0: off)
     std::vector<rpot_host::VRingP> vring;
+    // host tier of a split history: real-space rings in pinned host memory
+    bool hist_host = false;
+    size_t host_bytes = 0;            // pinned host bytes the rings need
+    char *host_dev = nullptr;         // device-visible address of the bound host buffer
+    hipStream_t tier_stream = nullptr;
+    hipEvent_t tier_fork = nullptr, tier_join = nullptr;
+    bool tier_open = false;           // host-tier copies forked and not yet joined
     int n_heads = 0;     // ring heads: domains, judge slots, split rings, real-space rings
     int n_cu = 0;        // compute units of the bound device
     hipGraph_t graph = nullptr;

@@ -97,7 +97,7 @@ struct ZFwdJob {
     const void *s0;        // mode 0: S0 [4][Nx][Ny][Nz] (null: transform S itself)
     const int32_t *src_head;  // mode 0: read slot (*src_head - src_lag) mod src_depth of the src ring
     void *store;           // mode 0: also copy S into slot *store_head of this ring (or null)
-    const int32_t *store_head;
+    const int32_t *store_head;   // slot of the store ring (null: store is one snapshot)
     int32_t src_depth, src_lag;
     void *out;
     float *zmax;           // mode 0: per-block max |dS| per component, or null
@@ -243,6 +243,31 @@ void launch_fill_zero(void *dst, size_t bytes, hipStream_t st);
 // step += 1 and every domain's ring head moves one slot (mod its depth); the
 // heads before the move are kept in prev.
 void launch_advance_step(int64_t *step, int32_t *head, int32_t *prev, const DomDev *doms, int n_dom, hipStream_t st);
+
+// Host tier of a split history: copies of one real-space snapshot between a
+// device staging buffer and a ring in pinned host memory.  Slots are taken
+// from the device-side step counter and ring head, so a captured step replays
+// correctly at every step.  Ring slot: (head[head_idx] + shift) mod depth; a
+// copy with alt reads alt instead while step + shift <= 0 (a snapshot from
+// before step 0, which is S(0)).
+struct TierJob {
+    const uint4 *src;
+    uint4 *dst;
+    const uint4 *alt;
+    int64_t n16;          // 16-byte words per snapshot
+    int32_t src_depth;    // > 0: src is a ring of that many snapshots
+    int32_t dst_depth;    // > 0: dst is a ring of that many snapshots
+    int32_t shift;
+    int32_t head_idx;
+};
+constexpr int kMaxTierJobs = 16;
+struct TierArgs {
+    const int64_t *step;
+    const int32_t *head;
+    int n_jobs;
+    TierJob jobs[kMaxTierJobs];
+};
+void launch_tier_copy(const TierArgs &a, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Far-pair surrogate.

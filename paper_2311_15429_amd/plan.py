@@ -53,6 +53,7 @@ class Plan:
         _lib.check(self._lib, None, code)
         self._h = handle
         self._ws = None
+        self._host_hist = None
 
     # -- host-side queries ---------------------------------------------------
     @property
@@ -79,9 +80,12 @@ class Plan:
         import torch
         return torch.float64 if self.precision == "fp64" else torch.float32
 
-    def bind(self, workspace=None, device="cuda"):
+    def bind(self, workspace=None, device="cuda", host_history=None):
         """Bind a workspace (a uint8 CUDA tensor of at least workspace_bytes);
-        allocates one with torch when none is given."""
+        allocates one with torch when none is given.  With the host tier of a
+        split history (history_host), also binds its pinned host buffer
+        (host_history, a pinned uint8 CPU tensor of at least host_history_bytes;
+        allocated with pin_memory=True when none is given)."""
         import torch
         nbytes = self.workspace_bytes
         if workspace is None:
@@ -92,9 +96,21 @@ class Plan:
         off = (-ptr) % 256
         if workspace.numel() - off < nbytes:
             raise ValueError("workspace too small")
+        hb = self.host_history_bytes
+        if hb:
+            if host_history is None:
+                host_history = torch.empty(hb, dtype=torch.uint8, pin_memory=True)
+            if host_history.device.type != "cpu" or host_history.dtype != torch.uint8:
+                raise ValueError("host_history must be a uint8 CPU tensor")
+            if not host_history.is_pinned():
+                raise ValueError("host_history must be pinned (pin_memory=True)")
         self._ws = workspace
         _lib.check(self._lib, self._h, self._lib.rp_bind_workspace(
             self._h, ctypes.c_void_p(ptr + off), ctypes.c_size_t(workspace.numel() - off)))
+        if hb:
+            self._host_hist = host_history
+            _lib.check(self._lib, self._h, self._lib.rp_bind_history_host(
+                self._h, ctypes.c_void_p(host_history.data_ptr()), ctypes.c_size_t(host_history.numel())))
         return workspace
 
     def set_green_kernels(self):
@@ -224,6 +240,19 @@ class Plan:
         ring of the sources).  Call before bind(); min_gap <= 0 switches it off."""
         _lib.check(self._lib, self._h, self._lib.rp_history_split(self._h, int(min_gap)))
 
+    def history_host(self, enable=True):
+        """Keep the real-space rings of a split history in pinned host memory
+        (streamed back one snapshot per split ring and step on a second
+        stream).  Call before bind()."""
+        _lib.check(self._lib, self._h, self._lib.rp_history_host(self._h, int(bool(enable))))
+
+    @property
+    def host_history_bytes(self):
+        """Pinned host bytes the host tier needs (0 when nothing is split)."""
+        b = ctypes.c_size_t(0)
+        _lib.check(self._lib, self._h, self._lib.rp_history_host_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
     def surrogate_configure(self, far_factor, n_lags=64, audit=()):
         """Far pairs (centre distance > far_factor x the larger box diagonal)
         leave the plain lag sum; `audit` sources keep their plain history.
@@ -324,6 +353,7 @@ class Plan:
             self._lib.rp_plan_destroy(self._h)
             self._h = None
         self._ws = None
+        self._host_hist = None
 
     def __del__(self):
         try:

@@ -14,9 +14,10 @@ def log(*a):
     sys.stdout.flush()
 
 
-def run_gpu(system, precision, samples, collect=None, tune=None, split=0):
+def run_gpu(system, precision, samples, collect=None, tune=None, split=0, host=False):
     """Push samples[n][l] ([L+1][4][N] FP64) for l = 0..L and step.
-    tune: {knob: value} set before binding; split: history split gap (0: off).
+    tune: {knob: value} set before binding; split: history split gap (0: off);
+    host: real-space rings of the split history in pinned host memory.
 
     Returns {l: [dom][4][N] FP64 numpy} for l in `collect` (default: all)."""
     import torch
@@ -27,6 +28,9 @@ def run_gpu(system, precision, samples, collect=None, tune=None, split=0):
         p.set_tuning(k, v)
     if split:
         p.history_split(split)
+        if host:
+            p.history_host(True)
+            assert p.host_history_bytes > 0
         assert p.stats()["split_rings"] > 0
     p.bind()
     p.set_green_kernels()

@@ -1,6 +1,7 @@
 """Host-side checks of the C-ABI library: it loads, exports every declared
 symbol, and plans windows, pads and depths correctly (no GPU needed: planning
 makes no HIP call)."""
+import ctypes
 import json
 import math
 import os
@@ -239,4 +240,55 @@ def test_history_split_plans_rings_and_keeps_the_lag_sum():
         q.history_split(8)
     assert e.value.status == "RP_ERR_UNSUPPORTED"
     for x in (plain, p, near, q):
+        x.close()
+
+
+def test_history_host_tier_plans_host_rings_and_staging():
+    """The host tier moves the real-space rings of a split history to pinned
+    host memory: the device keeps one staging snapshot per split source and
+    one per split ring, the host buffer holds the rings (window start + 1
+    snapshots each), and the lag sum and spectral rings are unchanged.  Since
+    the rings no longer cost device memory, a narrow gap that does not pay
+    with a device-resident ring does pay with the host tier."""
+    from paper_2311_15429_amd import RpotError, plan_for_system, load
+    system = sy.wire_pair(W=8, L=12, d=120, h=0.3, dt=0.01, n_pairs=1)
+    dev = plan_for_system(system, "fp32")
+    dev.history_split(8)
+    p = plan_for_system(system, "fp32")
+    p.history_split(8)
+    assert p.host_history_bytes == 0
+    p.history_host(True)
+    a, b = dev.stats(), p.stats()
+    snap = 4 * int(np.prod(system.domains[0].dims)) * 4
+    assert b["split_rings"] == a["split_rings"] == 2
+    assert b["lagsum_bytes"] == a["lagsum_bytes"] and b["ring_bytes"] == a["ring_bytes"]
+    assert b["history_bytes"] == 2 * 2 * snap            # per source: newest + one split ring
+    assert p.host_history_bytes == a["history_bytes"]   # the rings themselves
+    assert p.host_history_bytes == sum((p.info(1 - n, n)[0] + 1) * snap for n in range(2))
+    assert p.workspace_bytes < dev.workspace_bytes
+    p.history_host(False)
+    assert p.stats() == a and p.host_history_bytes == 0
+    # a one-lag gap: not worth a device-resident ring, worth a host one
+    wide = sy.wire_pair(W=24, L=24, d=100, h=0.3, dt=0.01, n_pairs=1)
+    q = plan_for_system(wide, "fp32")
+    q.history_split(1)
+    assert q.stats()["split_rings"] == 0 and q.host_history_bytes == 0
+    q.history_host(True)
+    assert q.stats()["split_rings"] == 2 and q.host_history_bytes > 0
+    # the host tier alone splits nothing
+    r = plan_for_system(system, "fp32")
+    r.history_host(True)
+    assert r.stats()["split_rings"] == 0 and r.host_history_bytes == 0
+    # binding errors that need no device
+    lib = load()
+    h = p._h
+    assert lib.rp_bind_history_host(h, None, 0) == 4            # tier off: RP_ERR_STATE
+    p.history_host(True)
+    assert lib.rp_bind_history_host(h, None, 1 << 30) == 1      # null: RP_ERR_ARG
+    assert b"null" in lib.rp_last_error(h)
+    buf = ctypes.create_string_buffer(64)
+    assert lib.rp_bind_history_host(h, ctypes.addressof(buf), 64) == 3   # too small: RP_ERR_NOMEM
+    assert lib.rp_history_host_bytes(h, None) == 1
+    assert lib.rp_bind_history_host(r._h, None, 0) == 0         # nothing split: no-op
+    for x in (dev, p, q, r):
         x.close()

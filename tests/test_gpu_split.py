@@ -1,6 +1,7 @@
 """Split history on the GPU: later lag windows in spectral rings of their own,
-fed by transforming again the sources kept in a real-space ring.  The lag sum
-then reads the same spectra in the same order, so every output is bitwise
+fed by transforming again the sources kept in a real-space ring (in device
+memory, or in pinned host memory streamed back each step).  The lag sum then
+reads the same spectra in the same order, so every output is bitwise
 identical to the unsplit plan's; and it matches the FP64 oracle."""
 import numpy as np
 import pytest
@@ -65,7 +66,99 @@ def test_split_history_three_domains_matches_oracle_fp64():
             assert np.array_equal(x, y)
 
 
-def test_split_history_graph_replay_is_bitwise_identical():
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_ring_fp16"])
+def test_host_tier_is_bitwise_identical(precision):
+    system = _pair()
+    L = 60
+    S = sy.sample_sources(system, range(L + 1))
+    a = run_gpu(system, precision, S, split=8)
+    b = run_gpu(system, precision, S, split=8, host=True)
+    for l in a:
+        for x, y in zip(a[l], b[l]):
+            assert np.array_equal(x, y), l
+    log(f"{precision}: host tier bitwise identical to the device tier over {L + 1} steps")
+
+
+def test_host_tier_three_domains_matches_oracle_fp64():
+    """Five split rings over three sources, real-space rings in host memory:
+    the result is the unsplit plan's, bit for bit, and the oracle's."""
+    from paper_2311_15429_amd import plan_for_system
+    system = _three()
+    p = plan_for_system(system, "fp64")
+    p.history_split(4)
+    p.history_host(True)
+    st = p.stats()
+    log(f"three domains, host tier: {st['split_rings']} split rings, host {p.host_history_bytes / 1e6:.2f} MB, "
+        f"device staging {st['history_bytes'] / 1e6:.2f} MB")
+    assert st["split_rings"] == 5
+    p.close()
+    L = 80
+    steps = [30, 55, L]
+    S = sy.sample_sources(system, range(L + 1))
+    got = run_gpu(system, "fp64", S, collect=steps, split=4, host=True)
+    ref = oracle.potential_full(system, S, steps)
+    plain = run_gpu(system, "fp64", S, collect=steps)
+    for l, r in zip(steps, ref):
+        e = rel_err(got[l], r)
+        log(f"three domains, host tier, step {l}: rel err {np.array2string(e, precision=2)}")
+        assert np.all(e <= 1e-10), (l, e)
+        for x, y in zip(got[l], plain[l]):
+            assert np.array_equal(x, y)
+
+
+def test_host_tier_one_lag_gap_is_bitwise_identical():
+    """Self window [0, 9], cross window [11, 23]: a one-lag gap, which only
+    the host tier splits (its rings cost no device memory); the split ring
+    re-transforms the sources of 11 steps ago, fetched from the host."""
+    from paper_2311_15429_amd import plan_for_system
+    system = sy.wire_pair(W=24, L=24, d=100, h=0.3, dt=0.01, n_pairs=2, seed=5)
+    p = plan_for_system(system, "fp32")
+    assert p.info(0, 0)[:2] == (0, 9) and p.info(1, 0)[:2] == (11, 23)
+    p.close()
+    L = 40
+    S = sy.sample_sources(system, range(L + 1))
+    a = run_gpu(system, "fp32", S)
+    b = run_gpu(system, "fp32", S, split=1, host=True)
+    for l in a:
+        for x, y in zip(a[l], b[l]):
+            assert np.array_equal(x, y), l
+    log(f"one-lag gap, host tier: bitwise identical to one ring over {L + 1} steps")
+
+
+def test_host_tier_needs_a_pinned_buffer():
+    import ctypes
+    from paper_2311_15429_amd import RpotError, plan_for_system
+    system = _pair()
+    p = plan_for_system(system, "fp32", stream=torch.cuda.current_stream())
+    p.history_split(8)
+    p.history_host(True)
+    ws = torch.empty(p.workspace_bytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    lib, h = p._lib, p._h
+    assert lib.rp_bind_workspace(h, ctypes.c_void_p(ws.data_ptr() + off), ctypes.c_size_t(ws.numel() - off)) == 0
+    p._ws = ws
+    p.set_green_kernels()
+    src = [torch.zeros((4,) + d, dtype=torch.float32, device="cuda") for d in p.dims]
+    with pytest.raises(RpotError) as e:
+        p.push_sources(0, src)
+    assert e.value.status == "RP_ERR_STATE" and "host history" in str(e.value)
+    pageable = np.zeros(p.host_history_bytes, dtype=np.uint8)
+    assert lib.rp_bind_history_host(h, ctypes.c_void_p(pageable.ctypes.data), ctypes.c_size_t(pageable.size)) == 1
+    assert b"pinned" in lib.rp_last_error(h)
+    with pytest.raises(ValueError):
+        p.bind(host_history=torch.zeros(p.host_history_bytes, dtype=torch.uint8))
+    pinned = torch.empty(p.host_history_bytes, dtype=torch.uint8, pin_memory=True)
+    assert lib.rp_bind_history_host(h, ctypes.c_void_p(pinned.data_ptr()), ctypes.c_size_t(pinned.numel())) == 0
+    p._host_hist = pinned
+    out = [torch.empty_like(x) for x in src]
+    p.push_sources(0, src)
+    p.retarded_step(0, out)
+    torch.cuda.synchronize()
+    p.close()
+
+
+@pytest.mark.parametrize("host", [False, True])
+def test_split_history_graph_replay_is_bitwise_identical(host):
     from paper_2311_15429_amd import plan_for_system
     system = _pair()
     L = 45
@@ -73,9 +166,12 @@ def test_split_history_graph_replay_is_bitwise_identical():
     src = [[torch.from_numpy(np.ascontiguousarray(S[n][l]).reshape((4,) + tuple(system.domains[n].dims)))
             .to("cuda", torch.float32) for n in range(2)] for l in range(L + 1)]
     res = []
-    for capture in (False, True):
+    for capture in ((False, True) if not host else (False, True, "device")):
         p = plan_for_system(system, "fp32", stream=torch.cuda.current_stream())
         p.history_split(8)
+        if host and capture != "device":
+            p.history_host(True)
+        capture = capture is True
         p.bind()
         p.set_green_kernels()
         outs = [torch.empty((4,) + d, dtype=torch.float32, device="cuda") for d in p.dims]
@@ -97,6 +193,7 @@ def test_split_history_graph_replay_is_bitwise_identical():
             seq.append([o.cpu().numpy().copy() for o in outs])
         res.append(seq)
         p.close()
-    for a, b in zip(*res):
-        for x, y in zip(a, b):
-            assert np.array_equal(x, y)
+    for other in res[1:]:
+        for a, b in zip(res[0], other):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
