@@ -1100,8 +1100,11 @@ void enqueue_finish(rp_plan p, void *const *out, hipStream_t st) {
 // host slot and fetches into each split ring's staging buffer the snapshot
 // that step l + 1 transforms again (S(l + 1 - lo), or S(0) before step 0);
 // the copies run under the lag sum and inverse of step l and are joined
-// before the step's ring heads move on (tier_join).  With write_newest false
-// (step 0) only the fetch runs.
+// before the step's ring heads move on (tier_join).  A split ring's window
+// starts at lag 2 or later (the first window starts at 0 and a gap is at
+// least one lag), so no fetch reads the slot written in the same step and
+// all copies of a step go in one launch.  With write_newest false (step 0)
+// only the fetches run.
 bool tier_active(rp_plan p) { return p->hist_host && p->host_bytes > 0; }
 
 void tier_fork(rp_plan p, hipStream_t st, bool write_newest) {
@@ -1110,34 +1113,31 @@ void tier_fork(rp_plan p, hipStream_t st, bool write_newest) {
     HIP_OK(hipEventRecord(p->tier_fork, st));
     HIP_OK(hipStreamWaitEvent(p->tier_stream, p->tier_fork, 0));
     p->tier_open = true;
-    TierArgs out{}, in{};
-    out.step = in.step = p->at<int64_t>(p->off_state);
-    out.head = in.head = p->at<int32_t>(p->off_head);
-    auto flush = [&](TierArgs &a) {
-        launch_tier_copy(a, p->tier_stream);
-        check_launch();
-        a.n_jobs = 0;
+    TierArgs a{};
+    a.step = p->at<int64_t>(p->off_state);
+    a.head = p->at<int32_t>(p->off_head);
+    auto add = [&](const TierJob &j) {
+        a.jobs[a.n_jobs++] = j;
+        if (a.n_jobs == kMaxTierJobs) {
+            launch_tier_copy(a, p->tier_stream);
+            check_launch();
+            a.n_jobs = 0;
+        }
     };
     for (const DomainP &d : p->dom) {
-        if (d.d1 == 0) continue;
-        const int64_t n16 = int64_t(4) * d.npts * int64_t(p->tsz) / 16;
-        uint4 *ring = reinterpret_cast<uint4 *>(p->host_dev + d.host_off);
-        if (write_newest) {
-            TierJob &j = out.jobs[out.n_jobs++];
-            j = TierJob{};
-            j.src = p->at<uint4>(d.off_stage);
-            j.dst = ring;
-            j.n16 = n16;
-            j.dst_depth = d.d1;
-            j.head_idx = d.t1_idx;
-            if (out.n_jobs == kMaxTierJobs) flush(out);
-        }
+        if (d.d1 == 0 || !write_newest) continue;
+        TierJob j{};
+        j.src = p->at<uint4>(d.off_stage);
+        j.dst = reinterpret_cast<uint4 *>(p->host_dev + d.host_off);
+        j.n16 = int64_t(4) * d.npts * int64_t(p->tsz) / 16;
+        j.dst_depth = d.d1;
+        j.head_idx = d.t1_idx;
+        add(j);
     }
-    flush(out);   // every write lands before a fetch of the same slot (lo = 1)
     for (const VRingP &v : p->vring) {
         const DomainP &d = p->dom[v.n];
-        TierJob &j = in.jobs[in.n_jobs++];
-        j = TierJob{};
+        if (v.lo < 2) fail(RP_ERR_STATE, "internal: a split ring starts before lag 2");
+        TierJob j{};
         j.src = reinterpret_cast<const uint4 *>(p->host_dev + d.host_off);
         j.dst = p->at<uint4>(v.off_stage);
         j.alt = p->at<uint4>(d.off_s0);
@@ -1145,9 +1145,12 @@ void tier_fork(rp_plan p, hipStream_t st, bool write_newest) {
         j.src_depth = d.d1;
         j.shift = 1 - v.lo;
         j.head_idx = d.t1_idx;
-        if (in.n_jobs == kMaxTierJobs) flush(in);
+        add(j);
     }
-    flush(in);
+    if (a.n_jobs) {
+        launch_tier_copy(a, p->tier_stream);
+        check_launch();
+    }
     HIP_OK(hipEventRecord(p->tier_join, p->tier_stream));
 }
 
