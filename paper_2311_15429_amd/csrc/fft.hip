@@ -28,6 +28,11 @@ struct Lds<double> {
     static constexpr int E = 2048;   // 32 KiB
 };
 
+// Global reads of a tile go in chunks of kLoadChunk per thread: all loads of
+// a chunk are issued before the first is used, so a wave keeps that many in
+// flight instead of one (the passes are bound by the requests in flight).
+constexpr int kLoadChunk = 8;
+
 template <typename T>
 __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
@@ -42,81 +47,89 @@ __device__ __forceinline__ Cx<T> mul_i(Cx<T> a, int sgn) {
     return sgn > 0 ? Cx<T>{-a.y, a.x} : Cx<T>{a.y, -a.x};
 }
 
+// One Stockham stage of radix R over the L lines in LDS: butterfly b of line
+// li reads x[i + r nq] (i = b mod nq, r < R), multiplies by the twiddles
+// w^(r k) (k = i mod p, p the product of the earlier radices), transforms,
+// and writes x[(i - k) R + k + r p].  Each butterfly's indices are computed
+// once, for the read and the write.
+template <typename T, int NT, int BMAX, int R>
+__device__ __forceinline__ void lds_stage(Cx<T> *buf, int P, int nbf, int nq, int p, int tws, FastDiv dq,
+                                          FastDiv dp, int dir, const Cx<T> *tw) {
+    const int tid = threadIdx.x;
+    Cx<T> v[BMAX][R];
+    int wpos[BMAX];
+#pragma unroll
+    for (int it = 0; it < BMAX; ++it) {
+        const int b = tid + it * NT;
+        wpos[it] = -1;
+        if (b < nbf) {
+            const int li = dq.div(b);
+            const int i = b - li * nq;
+            const int q = dp.div(i);
+            const int k = i - q * p;
+            const Cx<T> *row = buf + li * P;
+            wpos[it] = li * P + q * p * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[it][r] = row[i + r * nq];
+            if (k != 0) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    Cx<T> w = tw[r * k * tws];
+                    w.y = dir > 0 ? -w.y : w.y;
+                    v[it][r] = cmul(v[it][r], w);
+                }
+            }
+            if constexpr (R == 4) {
+                const Cx<T> t0 = cadd(v[it][0], v[it][2]);
+                const Cx<T> t1 = csub(v[it][0], v[it][2]);
+                const Cx<T> t2 = cadd(v[it][1], v[it][3]);
+                const Cx<T> t3 = mul_i(csub(v[it][1], v[it][3]), dir);
+                v[it][0] = cadd(t0, t2);
+                v[it][2] = csub(t0, t2);
+                v[it][1] = cadd(t1, t3);
+                v[it][3] = csub(t1, t3);
+            } else if constexpr (R == 2) {
+                const Cx<T> t0 = v[it][0];
+                v[it][0] = cadd(t0, v[it][1]);
+                v[it][1] = csub(t0, v[it][1]);
+            } else {
+                static_assert(R == 3, "radix 2, 3 or 4");
+                const T s3 = T(0.86602540378443864676372317075294);
+                const Cx<T> s = cadd(v[it][1], v[it][2]);
+                const Cx<T> d = csub(v[it][1], v[it][2]);
+                const Cx<T> m = {v[it][0].x - T(0.5) * s.x, v[it][0].y - T(0.5) * s.y};
+                const Cx<T> e = mul_i(Cx<T>{s3 * d.x, s3 * d.y}, dir);
+                v[it][0] = cadd(v[it][0], s);
+                v[it][1] = cadd(m, e);
+                v[it][2] = csub(m, e);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < BMAX; ++it) {
+        if (wpos[it] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[wpos[it] + r * p] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
 // In-place FFT of L lines of length P held in LDS (row-major [L][P]).
 // dir = -1: sum_j x_j exp(-2 pi i jk/P);  dir = +1: exp(+2 pi i jk/P).
 // The twiddles tw come from LDS; every division by a stage constant is a
 // multiply-high (RadixPlan::dq, dp).
 template <typename T, int NT, int BMAX>
 __device__ void lds_fft(Cx<T> *buf, int P, int L, int dir, const Cx<T> *tw, const RadixPlan &rp) {
-    const int tid = threadIdx.x;
     int p = 1;
     for (int st = 0; st < rp.n; ++st) {
         const int R = rp.r[st];
         const int nq = P / R;
         const int nbf = L * nq;
-        const int tws = rp.tws[st];
-        const FastDiv dq = rp.dq[st], dp = rp.dp[st];
-        Cx<T> v[BMAX][4];
-#pragma unroll
-        for (int it = 0; it < BMAX; ++it) {
-            const int b = tid + it * NT;
-            if (b < nbf) {
-                const int li = dq.div(b);
-                const int i = b - li * nq;
-                const int k = i - dp.div(i) * p;
-                const Cx<T> *row = buf + li * P;
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (r < R) v[it][r] = row[i + r * nq];
-#pragma unroll
-                for (int r = 1; r < 4; ++r) {
-                    if (r < R && k != 0) {
-                        Cx<T> w = tw[r * k * tws];
-                        if (dir > 0) w.y = -w.y;
-                        v[it][r] = cmul(v[it][r], w);
-                    }
-                }
-                if (R == 4) {
-                    const Cx<T> t0 = cadd(v[it][0], v[it][2]);
-                    const Cx<T> t1 = csub(v[it][0], v[it][2]);
-                    const Cx<T> t2 = cadd(v[it][1], v[it][3]);
-                    const Cx<T> t3 = mul_i(csub(v[it][1], v[it][3]), dir);
-                    v[it][0] = cadd(t0, t2);
-                    v[it][2] = csub(t0, t2);
-                    v[it][1] = cadd(t1, t3);
-                    v[it][3] = csub(t1, t3);
-                } else if (R == 2) {
-                    const Cx<T> t0 = v[it][0];
-                    v[it][0] = cadd(t0, v[it][1]);
-                    v[it][1] = csub(t0, v[it][1]);
-                } else {  // R == 3
-                    const T s3 = T(0.86602540378443864676372317075294);
-                    const Cx<T> s = cadd(v[it][1], v[it][2]);
-                    const Cx<T> d = csub(v[it][1], v[it][2]);
-                    const Cx<T> m = {v[it][0].x - T(0.5) * s.x, v[it][0].y - T(0.5) * s.y};
-                    const Cx<T> e = mul_i(Cx<T>{s3 * d.x, s3 * d.y}, dir);
-                    v[it][0] = cadd(v[it][0], s);
-                    v[it][1] = cadd(m, e);
-                    v[it][2] = csub(m, e);
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < BMAX; ++it) {
-            const int b = tid + it * NT;
-            if (b < nbf) {
-                const int li = dq.div(b);
-                const int i = b - li * nq;
-                const int k = i - dp.div(i) * p;
-                const int j = (i - k) * R + k;
-                Cx<T> *row = buf + li * P;
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (r < R) row[j + r * p] = v[it][r];
-            }
-        }
-        __syncthreads();
+        if (R == 4) lds_stage<T, NT, BMAX, 4>(buf, P, nbf, nq, p, rp.tws[st], rp.dq[st], rp.dp[st], dir, tw);
+        else if (R == 2) lds_stage<T, NT, BMAX, 2>(buf, P, nbf, nq, p, rp.tws[st], rp.dq[st], rp.dp[st], dir, tw);
+        else lds_stage<T, NT, BMAX, 3>(buf, P, nbf, nq, p, rp.tws[st], rp.dq[st], rp.dp[st], dir, tw);
         p *= R;
     }
 }
@@ -170,23 +183,39 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
     for (int i = threadIdx.x; i < P; i += NT) twl[i] = reinterpret_cast<const Cx<T> *>(a.tw)[i];
 
     const bool jfast_in = (a.in_j == 1);
-    for (int e = threadIdx.x; e < L * P; e += NT) {
-        int li, j;
-        if (jfast_in) {
-            li = a.dP.div(e);
-            j = e - li * P;
-        } else {
-            j = a.dL.div(e);
-            li = e - j * L;
+    const int LP = L * P;
+    for (int e0 = threadIdx.x; e0 < LP; e0 += NT * kLoadChunk) {
+        Cx<T> v[kLoadChunk];
+        int o[kLoadChunk];
+#pragma unroll
+        for (int u = 0; u < kLoadChunk; ++u) {
+            const int e = e0 + u * NT;
+            int li, j;
+            if (a.in_group > 0) {
+                const int sh = a.in_group >> 1;   // groups of 1, 2 or 4 lines
+                const int t = e >> sh;
+                const int r = a.dP.div(t);
+                j = t - r * P;
+                li = (r << sh) + (e & (a.in_group - 1));
+            } else if (jfast_in) {
+                li = a.dP.div(e);
+                j = e - li * P;
+            } else {
+                j = a.dL.div(e);
+                li = e - j * L;
+            }
+            o[u] = li * P + j;
+            v[u] = {T(0), T(0)};
+            if (e < LP && li < nl && j < a.n_in) {
+                const int line = line0 + li;
+                const int outer = a.dinner.div(line);
+                const int inner = line - outer * a.n_inner;
+                v[u] = in[outer * a.in_outer + inner * a.in_inner + int64_t(j) * a.in_j];
+            }
         }
-        Cx<T> v = {T(0), T(0)};
-        if (li < nl && j < a.n_in) {
-            const int line = line0 + li;
-            const int outer = a.dinner.div(line);
-            const int inner = line - outer * a.n_inner;
-            v = in[outer * a.in_outer + inner * a.in_inner + int64_t(j) * a.in_j];
-        }
-        buf[li * P + j] = v;
+#pragma unroll
+        for (int u = 0; u < kLoadChunk; ++u)
+            if (e0 + u * NT < LP) buf[o[u]] = v[u];
     }
     __syncthreads();
     lds_fft<T, NT, BMAX>(buf, P, L, a.dir, twl, a.rp);
@@ -211,7 +240,13 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
     const int nout = a.n_out;
     for (int e = threadIdx.x; e < L * nout; e += NT) {
         int li, j;
-        if (jfast_out) {
+        if (a.out_group > 0) {
+            const int sh = a.out_group >> 1;   // groups of 1, 2 or 4 lines
+            const int t = e >> sh;
+            const int r = a.dnout.div(t);
+            j = t - r * nout;
+            li = (r << sh) + (e & (a.out_group - 1));
+        } else if (jfast_out) {
             li = a.dnout.div(e);
             j = e - li * nout;
         } else {
@@ -284,7 +319,12 @@ int line_pass_elems(int lds_elems, int prec64) {
 void launch_line_pass(const LinePass &a0, int prec64, hipStream_t st) {
     LinePass a = a0;
     const int E = line_pass_elems(a.lds_elems, prec64);
-    const int L = E / a.P;
+    // grouped orders (groups of 1, 2 or 4 lines) need whole groups of lines in a block
+    int G = std::max(std::max(a.in_group, a.out_group), 1);
+    while (G > 1 && E / a.P < G) G /= 2;
+    a.in_group = std::min(a.in_group, G);
+    a.out_group = std::min(a.out_group, G);
+    const int L = E / a.P - (E / a.P) % G;
     a.L = L;
     a.dL = FastDiv(uint32_t(L));
     a.dP = FastDiv(uint32_t(a.P));
@@ -377,27 +417,51 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         T *__restrict__ St = nullptr;
         if (job.store)
             St = reinterpret_cast<T *>(job.store) + (job.store_head ? int64_t(*job.store_head) * 4 * npts : 0);
-        for (int e = threadIdx.x; e < L * P; e += NT) {
-            const int li = a.dP.div(e);
-            const int z = e - li * P;
-            Cx<T> v = {T(0), T(0)};
-            if (li < nl && z < a.Nz) {
+        const int LP = L * P;
+        for (int e0 = threadIdx.x; e0 < LP; e0 += NT * kLoadChunk) {
+            // position a (real part) and b = a + 1 (imaginary part) of each element
+            T sa[kLoadChunk], sb[kLoadChunk], qa[kLoadChunk], qb[kLoadChunk];
+            int64_t oa[kLoadChunk];
+            bool va[kLoadChunk], vb[kLoadChunk];
+#pragma unroll
+            for (int u = 0; u < kLoadChunk; ++u) {
+                const int e = e0 + u * NT;
+                const int li = a.dP.div(e);
+                const int z = e - li * P;
                 const int c = line0 + li;
-                const int mu = c & 3;
                 const int pa = (c >> 2) * 2;
-                const int64_t oa = mu * npts + int64_t(pa) * a.Nz + z;
-                const T sa = S[oa];
-                if (St) St[oa] = sa;
-                v.x = S0 ? sa - S0[oa] : sa;
-                if (pa + 1 < npos) {
-                    const int64_t ob = oa + a.Nz;
-                    const T sb = S[ob];
-                    if (St) St[ob] = sb;
-                    v.y = S0 ? sb - S0[ob] : sb;
+                va[u] = e < LP && li < nl && z < a.Nz;
+                vb[u] = va[u] && pa + 1 < npos;
+                oa[u] = (c & 3) * npts + int64_t(pa) * a.Nz + z;
+                sa[u] = sb[u] = qa[u] = qb[u] = T(0);
+                if (va[u]) {
+                    sa[u] = S[oa[u]];
+                    if (S0) qa[u] = S0[oa[u]];
                 }
-                mx[mu] = fmaxf(mx[mu], fmaxf(fabsf(float(v.x)), fabsf(float(v.y))));
+                if (vb[u]) {
+                    sb[u] = S[oa[u] + a.Nz];
+                    if (S0) qb[u] = S0[oa[u] + a.Nz];
+                }
             }
-            buf[li * P + z] = v;
+#pragma unroll
+            for (int u = 0; u < kLoadChunk; ++u) {
+                const int e = e0 + u * NT;
+                if (e >= LP) continue;
+                const int li = a.dP.div(e);
+                const int z = e - li * P;
+                Cx<T> v = {T(0), T(0)};
+                if (va[u]) {
+                    if (St) St[oa[u]] = sa[u];
+                    v.x = sa[u] - qa[u];
+                    if (vb[u]) {
+                        if (St) St[oa[u] + a.Nz] = sb[u];
+                        v.y = sb[u] - qb[u];
+                    }
+                    const int mu = (line0 + li) & 3;
+                    mx[mu] = fmaxf(mx[mu], fmaxf(fabsf(float(v.x)), fabsf(float(v.y))));
+                }
+                buf[li * P + z] = v;
+            }
         }
     } else {
         for (int e = threadIdx.x; e < L * P; e += NT) {
@@ -505,22 +569,37 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
     const int pos0 = (line0 >> 2) * 2;
 
     // Z_k = X_a(k) + i X_b(k) and Z_{P-k} = conj X_a(k) + i conj X_b(k)
-    for (int e = threadIdx.x; e < (L / 4) * Hz * 4; e += NT) {
-        const int mu = e & 3;
-        const int ppl = a.dHz.div(e >> 2);
-        const int k = (e >> 2) - ppl * Hz;
-        const int li = ppl * 4 + mu;
-        Cx<T> xa = {T(0), T(0)}, xb = {T(0), T(0)};
-        if (li < nl) {
+    const int nin = (L / 4) * Hz * 4;
+    for (int e0 = threadIdx.x; e0 < nin; e0 += NT * kLoadChunk) {
+        Cx<T> xa[kLoadChunk], xb[kLoadChunk];
+#pragma unroll
+        for (int u = 0; u < kLoadChunk; ++u) {
+            const int e = e0 + u * NT;
+            const int mu = e & 3;
+            const int ppl = a.dHz.div(e >> 2);
+            const int k = (e >> 2) - ppl * Hz;
+            const int li = ppl * 4 + mu;
             const int pa = pos0 + 2 * ppl;
-            xa = in[(int64_t(pa) * Hz + k) * 4 + mu];
-            if (pa + 1 < npos) xb = in[(int64_t(pa + 1) * Hz + k) * 4 + mu];
+            xa[u] = xb[u] = Cx<T>{T(0), T(0)};
+            if (e < nin && li < nl) {
+                xa[u] = in[(int64_t(pa) * Hz + k) * 4 + mu];
+                if (pa + 1 < npos) xb[u] = in[(int64_t(pa + 1) * Hz + k) * 4 + mu];
+            }
         }
-        if (k == 0 || 2 * k == P) {
-            buf[li * P + k] = Cx<T>{xa.x, xb.x};
-        } else {
-            buf[li * P + k] = Cx<T>{xa.x - xb.y, xa.y + xb.x};
-            buf[li * P + (P - k)] = Cx<T>{xa.x + xb.y, xb.x - xa.y};
+#pragma unroll
+        for (int u = 0; u < kLoadChunk; ++u) {
+            const int e = e0 + u * NT;
+            if (e >= nin) continue;
+            const int mu = e & 3;
+            const int ppl = a.dHz.div(e >> 2);
+            const int k = (e >> 2) - ppl * Hz;
+            const int li = ppl * 4 + mu;
+            if (k == 0 || 2 * k == P) {
+                buf[li * P + k] = Cx<T>{xa[u].x, xb[u].x};
+            } else {
+                buf[li * P + k] = Cx<T>{xa[u].x - xb[u].y, xa[u].y + xb[u].x};
+                buf[li * P + (P - k)] = Cx<T>{xa[u].x + xb[u].y, xb[u].x - xa[u].y};
+            }
         }
     }
     __syncthreads();
@@ -532,22 +611,33 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
     const int64_t npts = int64_t(npos) * a.Nz;
     // np is the block's position count: at most 2 (L / 4); a short block
     // (the last one) divides by its own count
-    for (int e = threadIdx.x; e < 4 * np * a.Nz; e += NT) {
-        const int r = a.dNz.div(e);
-        const int z = e - r * a.Nz;
-        int mu, pl;
-        if (np == 2 * (L >> 2)) {
-            mu = a.dnp.div(r);
-            pl = r - mu * np;
-        } else {
-            mu = r / np;
-            pl = r - mu * np;
+    const int nout = 4 * np * a.Nz;
+    const bool full = np == 2 * (L >> 2);
+    for (int e0 = threadIdx.x; e0 < nout; e0 += NT * kLoadChunk) {
+        T ad[kLoadChunk];
+        int64_t o[kLoadChunk];
+        int bi[kLoadChunk];
+        bool odd[kLoadChunk];
+#pragma unroll
+        for (int u = 0; u < kLoadChunk; ++u) {
+            const int e = e0 + u * NT;
+            const int r = a.dNz.div(e);
+            const int z = e - r * a.Nz;
+            const int mu = full ? a.dnp.div(r) : r / np;
+            const int pl = r - mu * np;
+            bi[u] = ((pl >> 1) * 4 + mu) * P + z;
+            odd[u] = (pl & 1) != 0;
+            o[u] = mu * npts + int64_t(pos0 + pl) * a.Nz + z;
+            ad[u] = (add && e < nout) ? add[o[u]] : T(0);
         }
-        const Cx<T> v = buf[((pl >> 1) * 4 + mu) * P + z];
-        const int64_t o = mu * npts + int64_t(pos0 + pl) * a.Nz + z;
-        T val = (pl & 1) ? v.y : v.x;
-        if (add) val += add[o];
-        out[o] = val;
+#pragma unroll
+        for (int u = 0; u < kLoadChunk; ++u) {
+            if (e0 + u * NT >= nout) continue;
+            const Cx<T> v = buf[bi[u]];
+            T val = odd[u] ? v.y : v.x;
+            if (add) val += ad[u];
+            out[o[u]] = val;
+        }
     }
 }
 

@@ -649,30 +649,43 @@ LinePass fwd_y(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl) {
     return a;
 }
 
-// Forward x pass [Nx][Py][Hz][4] -> [Px][Py][Hz][4].
+// Spectra are indexed k = (y Hz + z) Px + x (x fastest): the lag sum is
+// pointwise in k, and this order lets the x passes, the only ones that touch
+// spectra, move whole lines of P x frequencies as contiguous runs.
+
+// Forward x pass [Nx][Py][Hz][4] -> spectrum [C][4], C = Py Hz Px in the order
+// above.  Line (yz, c) = yz * 4 + c; the linear output is written with the
+// four components of a frequency fastest (out_group 4); ring outputs set their
+// own group.
 LinePass fwd_x(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl) {
     LinePass a = line_pass(p, P[0], dbl, -1);
     a.n_in = N[0];
     a.n_out = P[0];
     a.lines = P[1] * Hz * 4;
-    a.n_inner = P[1] * Hz * 4;
+    a.n_inner = 4;
     a.in_j = int64_t(P[1]) * Hz * 4;
+    a.in_outer = 4;
     a.in_inner = 1;
-    a.out_j = int64_t(P[1]) * Hz * 4;
+    a.out_j = 4;
+    a.out_outer = int64_t(P[0]) * 4;
     a.out_inner = 1;
+    a.out_group = 4;
     return a;
 }
 
-// Inverse x pass [Px][Py][Hz][4] -> [Nx][Py][Hz][4] (crop).
+// Inverse x pass spectrum [C][4] -> [Nx][Py][Hz][4] (crop).
 LinePass inv_x(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl) {
     LinePass a = line_pass(p, P[0], dbl, +1);
     a.n_in = P[0];
     a.n_out = N[0];
     a.lines = P[1] * Hz * 4;
-    a.n_inner = P[1] * Hz * 4;
-    a.in_j = int64_t(P[1]) * Hz * 4;
+    a.n_inner = 4;
+    a.in_j = 4;
+    a.in_outer = int64_t(P[0]) * 4;
     a.in_inner = 1;
+    a.in_group = 4;
     a.out_j = int64_t(P[1]) * Hz * 4;
+    a.out_outer = 4;
     a.out_inner = 1;
     return a;
 }
@@ -749,11 +762,14 @@ void green_spectra(rp_plan p, int s, int n, int mode, int m0, int count, void *c
     launch_line_pass(y, 1, p->stream);
     check_launch();
 
+    // spectrum order k = (y Hz + z) Px + x, as for the sources
     LinePass x = line_pass(p, S.P[0], true, -1);
     x.n_in = x.n_out = S.P[0];
     x.lines = x.n_inner = S.P[1] * S.Hz;
-    x.in_j = x.out_j = int64_t(S.P[1]) * S.Hz;
-    x.in_inner = x.out_inner = 1;
+    x.in_j = int64_t(S.P[1]) * S.Hz;
+    x.in_inner = 1;
+    x.out_j = 1;
+    x.out_inner = S.P[0];
     x.out_fmt = out_fmt;
     x.tile_comp = 1;
     x.n_jobs = count;
@@ -958,6 +974,9 @@ void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
             y.lds_elems = x.lds_elems = cls_lds(p, K);
             x.out_fmt = p->ring_fmt;
             x.tile_comp = 4;
+            // lanes in the order of a ring row: [c/2][k][c%2] (FP32), [c][k]
+            // (FP64), [k][c] (FP16/BF16)
+            x.out_group = p->ring_fmt == RING_F32 ? 2 : (p->ring_fmt == RING_F64 ? 1 : 4);
             ScaleArgs sa{};
             z.n_jobs = y.n_jobs = x.n_jobs = cnt;
             sa.n_jobs = quant ? cnt : 0;

@@ -73,6 +73,11 @@ struct LinePass {
     int64_t in_j, in_inner, in_outer;
     int64_t out_j, out_inner, out_outer;
     int dir;               // -1 forward, +1 inverse
+    // element order of the global reads / writes of a block's tile: 0 = the
+    // block's lines fastest (j-fastest when the stride of j is 1); g > 0 =
+    // groups of g consecutive lines fastest, then j, then the groups (g lines
+    // interleaved at stride 1 with j at stride g: one run per group of lines)
+    int in_group, out_group;
     int out_fmt;           // RingFmt of the output (F64/F32 = plain complex)
     int tile_comp;         // tiled output: components per frequency (1 or 4); the
                            // linear index e = k * tile_comp + c goes to tile
