@@ -47,31 +47,74 @@ __device__ __forceinline__ Cx<T> mul_i(Cx<T> a, int sgn) {
     return sgn > 0 ? Cx<T>{-a.y, a.x} : Cx<T>{a.y, -a.x};
 }
 
+// Radix-R butterfly in place (after the twiddles), R = 2, 3 or 4; dir is the
+// sign of the exponent.
+template <typename T, int R>
+__device__ __forceinline__ void butterfly(Cx<T> (&v)[R], int dir) {
+    if constexpr (R == 4) {
+        const Cx<T> t0 = cadd(v[0], v[2]);
+        const Cx<T> t1 = csub(v[0], v[2]);
+        const Cx<T> t2 = cadd(v[1], v[3]);
+        const Cx<T> t3 = mul_i(csub(v[1], v[3]), dir);
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    } else if constexpr (R == 2) {
+        const Cx<T> t0 = v[0];
+        v[0] = cadd(t0, v[1]);
+        v[1] = csub(t0, v[1]);
+    } else {
+        static_assert(R == 3, "radix 2, 3 or 4");
+        const T s3 = T(0.86602540378443864676372317075294);
+        const Cx<T> s = cadd(v[1], v[2]);
+        const Cx<T> d = csub(v[1], v[2]);
+        const Cx<T> m = {v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y};
+        const Cx<T> e = mul_i(Cx<T>{s3 * d.x, s3 * d.y}, dir);
+        v[0] = cadd(v[0], s);
+        v[1] = cadd(m, e);
+        v[2] = csub(m, e);
+    }
+}
+
+// n / D: by the constant D when D > 0, else by the run-time divisor fd.
+template <int D>
+__device__ __forceinline__ int divc(int n, const FastDiv &fd) {
+    if constexpr (D > 0) return int(unsigned(n) / unsigned(D));
+    else return fd.div(n);
+}
+
 // One Stockham stage of radix R over the L lines in LDS: butterfly b of line
 // li reads x[i + r nq] (i = b mod nq, r < R), multiplies by the twiddles
 // w^(r k) (k = i mod p, p the product of the earlier radices), transforms,
 // and writes x[(i - k) R + k + r p].  Each butterfly's indices are computed
-// once, for the read and the write.
-template <typename T, int NT, int BMAX, int R>
-__device__ __forceinline__ void lds_stage(Cx<T> *buf, int P, int nbf, int nq, int p, int tws, FastDiv dq,
-                                          FastDiv dp, int dir, const Cx<T> *tw) {
+// once, for the read and the write.  With NQ, PP, TWS, NBF > 0 the stage
+// constants are compile-time (the transform length is fixed), else the
+// run-time values nq, p, tws, nbf are used.
+template <typename T, int NT, int BMAX, int R, int NQ = 0, int PP = 0, int TWS = 0, int NBF = 0>
+__device__ __forceinline__ void lds_stage(Cx<T> *buf, int P, int nbf_rt, int nq_rt, int p_rt, int tws_rt,
+                                          FastDiv dq, FastDiv dp, int dir, const Cx<T> *tw) {
     const int tid = threadIdx.x;
+    const int nq = NQ ? NQ : nq_rt;
+    const int p = PP ? PP : p_rt;
+    const int tws = TWS ? TWS : tws_rt;
+    const int nbf = NBF ? NBF : nbf_rt;
     Cx<T> v[BMAX][R];
     int wpos[BMAX];
 #pragma unroll
     for (int it = 0; it < BMAX; ++it) {
         const int b = tid + it * NT;
         wpos[it] = -1;
-        if (b < nbf) {
-            const int li = dq.div(b);
+        if ((NBF > 0 && NBF % NT == 0) || b < nbf) {
+            const int li = divc<NQ>(b, dq);
             const int i = b - li * nq;
-            const int q = dp.div(i);
+            const int q = divc<PP>(i, dp);
             const int k = i - q * p;
             const Cx<T> *row = buf + li * P;
             wpos[it] = li * P + q * p * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[it][r] = row[i + r * nq];
-            if (k != 0) {
+            if (PP != 1 && k != 0) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
                     Cx<T> w = tw[r * k * tws];
@@ -79,30 +122,7 @@ __device__ __forceinline__ void lds_stage(Cx<T> *buf, int P, int nbf, int nq, in
                     v[it][r] = cmul(v[it][r], w);
                 }
             }
-            if constexpr (R == 4) {
-                const Cx<T> t0 = cadd(v[it][0], v[it][2]);
-                const Cx<T> t1 = csub(v[it][0], v[it][2]);
-                const Cx<T> t2 = cadd(v[it][1], v[it][3]);
-                const Cx<T> t3 = mul_i(csub(v[it][1], v[it][3]), dir);
-                v[it][0] = cadd(t0, t2);
-                v[it][2] = csub(t0, t2);
-                v[it][1] = cadd(t1, t3);
-                v[it][3] = csub(t1, t3);
-            } else if constexpr (R == 2) {
-                const Cx<T> t0 = v[it][0];
-                v[it][0] = cadd(t0, v[it][1]);
-                v[it][1] = csub(t0, v[it][1]);
-            } else {
-                static_assert(R == 3, "radix 2, 3 or 4");
-                const T s3 = T(0.86602540378443864676372317075294);
-                const Cx<T> s = cadd(v[it][1], v[it][2]);
-                const Cx<T> d = csub(v[it][1], v[it][2]);
-                const Cx<T> m = {v[it][0].x - T(0.5) * s.x, v[it][0].y - T(0.5) * s.y};
-                const Cx<T> e = mul_i(Cx<T>{s3 * d.x, s3 * d.y}, dir);
-                v[it][0] = cadd(v[it][0], s);
-                v[it][1] = cadd(m, e);
-                v[it][2] = csub(m, e);
-            }
+            butterfly<T, R>(v[it], dir);
         }
     }
     __syncthreads();
@@ -131,6 +151,44 @@ __device__ void lds_fft(Cx<T> *buf, int P, int L, int dir, const Cx<T> *tw, cons
         else if (R == 2) lds_stage<T, NT, BMAX, 2>(buf, P, nbf, nq, p, rp.tws[st], rp.dq[st], rp.dp[st], dir, tw);
         else lds_stage<T, NT, BMAX, 3>(buf, P, nbf, nq, p, rp.tws[st], rp.dq[st], rp.dp[st], dir, tw);
         p *= R;
+    }
+}
+
+// The same transform for a length P fixed at compile time (L lines): the
+// radix plan (4s, then a 2, then 3s, as make_radix) unrolls into stages whose
+// index arithmetic is by constants.
+struct RadixList {
+    int n;
+    int r[16];
+};
+__host__ __device__ constexpr RadixList radix_list(int P) {
+    RadixList l{};
+    int m = P;
+    while (m % 4 == 0) { l.r[l.n++] = 4; m /= 4; }
+    while (m % 2 == 0) { l.r[l.n++] = 2; m /= 2; }
+    while (m % 3 == 0) { l.r[l.n++] = 3; m /= 3; }
+    return l;
+}
+__host__ __device__ constexpr int radix_prod(int P, int st) {
+    const RadixList l = radix_list(P);
+    int p = 1;
+    for (int i = 0; i < st; ++i) p *= l.r[i];
+    return p;
+}
+
+template <typename T, int NT, int P, int L, int ST = 0>
+__device__ __forceinline__ void lds_fft_s(Cx<T> *buf, int dir, const Cx<T> *tw) {
+    constexpr RadixList rl = radix_list(P);
+    if constexpr (ST < rl.n) {
+        constexpr int R = rl.r[ST];
+        constexpr int PP = radix_prod(P, ST);
+        constexpr int NQ = P / R;
+        constexpr int NBF = L * NQ;
+        constexpr int TWS = P / (PP * R);
+        constexpr int BM = (NBF + NT - 1) / NT;
+        const FastDiv none;
+        lds_stage<T, NT, BM, R, NQ, PP, TWS, NBF>(buf, P, NBF, NQ, PP, TWS, none, none, dir, tw);
+        lds_fft_s<T, NT, P, L, ST + 1>(buf, dir, tw);
     }
 }
 
@@ -167,16 +225,24 @@ struct Store<T, RING_BF16> {
     }
 };
 
-template <typename T, int FMT, int E>
+// Lines per block of a line pass with a compile-time length P: whole groups
+// of four lines (every grouped order fits).
+__host__ __device__ constexpr int static_lines(int E, int P) { return (E / P) & ~3; }
+
+// PS > 0: the transform length is the compile-time PS (the launcher sets
+// L = static_lines(E, PS)); PS = 0: run-time length and lines per block.
+template <typename T, int FMT, int E, int PS = 0>
 __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
     static_assert((E + kMaxFft) * sizeof(Cx<T>) <= 64 * 1024, "line-pass LDS above 64 KiB");
     constexpr int NT = kFftThreads;
     constexpr int BMAX = (E / 2 + NT - 1) / NT;
+    constexpr int LS = PS ? static_lines(E, PS) : 0;
+    static_assert(PS == 0 || LS >= 4, "fixed-length pass needs four lines per block");
     __shared__ Cx<T> buf[E];
     __shared__ Cx<T> twl[kMaxFft];
     const LineJob &job = a.jobs[blockIdx.y];
-    const int P = a.P;
-    const int L = a.L;
+    const int P = PS ? PS : a.P;
+    const int L = PS ? LS : a.L;
     const int line0 = blockIdx.x * L;
     const int nl = min(L, a.lines - line0);
     const Cx<T> *__restrict__ in = reinterpret_cast<const Cx<T> *>(job.in);
@@ -194,14 +260,14 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
             if (a.in_group > 0) {
                 const int sh = a.in_group >> 1;   // groups of 1, 2 or 4 lines
                 const int t = e >> sh;
-                const int r = a.dP.div(t);
+                const int r = divc<PS>(t, a.dP);
                 j = t - r * P;
                 li = (r << sh) + (e & (a.in_group - 1));
             } else if (jfast_in) {
-                li = a.dP.div(e);
+                li = divc<PS>(e, a.dP);
                 j = e - li * P;
             } else {
-                j = a.dL.div(e);
+                j = divc<LS>(e, a.dL);
                 li = e - j * L;
             }
             o[u] = li * P + j;
@@ -218,7 +284,8 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
             if (e0 + u * NT < LP) buf[o[u]] = v[u];
     }
     __syncthreads();
-    lds_fft<T, NT, BMAX>(buf, P, L, a.dir, twl, a.rp);
+    if constexpr (PS > 0) lds_fft_s<T, NT, PS, LS>(buf, a.dir, twl);
+    else lds_fft<T, NT, BMAX>(buf, P, L, a.dir, twl, a.rp);
 
     void *obase = job.out;
     const float *qs = job.qscale;
@@ -250,7 +317,7 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
             li = a.dnout.div(e);
             j = e - li * nout;
         } else {
-            j = a.dL.div(e);
+            j = divc<LS>(e, a.dL);
             li = e - j * L;
         }
         if (li < nl) {
@@ -306,6 +373,28 @@ static void launch_line_e(const LinePass &a, dim3 grid, int E, hipStream_t st) {
     }
 }
 
+// FP32 passes at the default tile have a compile-time kernel for these
+// transform lengths (the pads of the usual grids); other lengths, FP64 and the
+// other tiles use the run-time kernel.
+template <int FMT, int P0, int... Ps>
+static bool launch_line_static(const LinePass &a, dim3 grid, hipStream_t st) {
+    if (a.P == P0) {
+        hipLaunchKernelGGL((k_line_pass<float, FMT, Lds<float>::E / 2, P0>), grid, dim3(kFftThreads), 0, st, a);
+        return true;
+    }
+    if constexpr (sizeof...(Ps) > 0) return launch_line_static<FMT, Ps...>(a, grid, st);
+    else return false;
+}
+template <int FMT>
+static bool launch_line_static_any(const LinePass &a, dim3 grid, hipStream_t st) {
+    return launch_line_static<FMT, 32, 48, 64, 96, 108, 128, 256>(a, grid, st);
+}
+static bool has_static_len(int P) {
+    for (int q : {32, 48, 64, 96, 108, 128, 256})
+        if (P == q) return true;
+    return false;
+}
+
 int line_pass_elems(int lds_elems, int prec64) {
     const int base = prec64 ? Lds<double>::E : Lds<float>::E;
     // default: the 16 KiB tile in FP32 (measured fastest on the 128^3 pads),
@@ -319,12 +408,13 @@ int line_pass_elems(int lds_elems, int prec64) {
 void launch_line_pass(const LinePass &a0, int prec64, hipStream_t st) {
     LinePass a = a0;
     const int E = line_pass_elems(a.lds_elems, prec64);
+    const bool fixed = !prec64 && E == Lds<float>::E / 2 && a.out_fmt != RING_F64 && has_static_len(a.P);
     // grouped orders (groups of 1, 2 or 4 lines) need whole groups of lines in a block
     int G = std::max(std::max(a.in_group, a.out_group), 1);
     while (G > 1 && E / a.P < G) G /= 2;
     a.in_group = std::min(a.in_group, G);
     a.out_group = std::min(a.out_group, G);
-    const int L = E / a.P - (E / a.P) % G;
+    const int L = fixed ? static_lines(E, a.P) : E / a.P - (E / a.P) % G;
     a.L = L;
     a.dL = FastDiv(uint32_t(L));
     a.dP = FastDiv(uint32_t(a.P));
@@ -335,6 +425,12 @@ void launch_line_pass(const LinePass &a0, int prec64, hipStream_t st) {
     if (prec64) {
         if (a.out_fmt == RING_F64) launch_line_e<double, RING_F64>(a, grid, E, st);
         else launch_line_e<double, RING_F32>(a, grid, E, st);
+    } else if (fixed) {
+        switch (a.out_fmt) {
+        case RING_F16: launch_line_static_any<RING_F16>(a, grid, st); break;
+        case RING_BF16: launch_line_static_any<RING_BF16>(a, grid, st); break;
+        default: launch_line_static_any<RING_F32>(a, grid, st);
+        }
     } else {
         switch (a.out_fmt) {
         case RING_F64: launch_line_e<float, RING_F64>(a, grid, E, st); break;
@@ -349,7 +445,7 @@ void launch_line_pass(const LinePass &a0, int prec64, hipStream_t st) {
 // Complex lines per block of the z passes: a multiple of 4 (the four
 // components of a position pair).
 template <typename T>
-__host__ __device__ inline int zfwd_lpb(int P) { return (Lds<T>::E / P) & ~3; }
+__host__ __device__ constexpr int zfwd_lpb(int P) { return (Lds<T>::E / P) & ~3; }
 
 // Sampled Green's function of one lag (modes 1 and 2 of ZFwd), FP64.
 __device__ __forceinline__ int kernel_disp(int q, int P, int Ns, int Nn, bool &valid) {
@@ -385,17 +481,20 @@ __device__ __forceinline__ double green_value(const ZFwd &a, const ZFwdJob &job,
 // (neighbouring (x, y) positions for sources, neighbouring y for the Green's
 // function), so the rounding crosstalk of the packing never mixes the large
 // scalar-potential source into the much smaller vector-potential ones.
-template <typename T>
+// PS > 0: the z length is the compile-time PS (sources only, mode 0).
+template <typename T, int PS = 0>
 __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
     constexpr int E = Lds<T>::E;
     constexpr int NT = kFftThreads;
     constexpr int BMAX = (E / 2 + NT - 1) / NT;
+    constexpr int LS = PS ? zfwd_lpb<T>(PS) : 0;
+    constexpr int HS = PS ? PS / 2 + 1 : 0;
     __shared__ Cx<T> buf[E];
     __shared__ Cx<T> twl[kMaxFft];
     __shared__ float red[4][NT / 64];
     const ZFwdJob &job = a.jobs[blockIdx.y];
-    const int P = a.Pz;
-    const int L = zfwd_lpb<T>(P);
+    const int P = PS ? PS : a.Pz;
+    const int L = PS ? LS : zfwd_lpb<T>(P);
     for (int i = threadIdx.x; i < P; i += NT) twl[i] = reinterpret_cast<const Cx<T> *>(a.tw)[i];
     const int line0 = blockIdx.x * L;
     const int npos = a.Nx * a.Ny;
@@ -426,7 +525,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
 #pragma unroll
             for (int u = 0; u < kLoadChunk; ++u) {
                 const int e = e0 + u * NT;
-                const int li = a.dP.div(e);
+                const int li = divc<PS>(e, a.dP);
                 const int z = e - li * P;
                 const int c = line0 + li;
                 const int pa = (c >> 2) * 2;
@@ -447,7 +546,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
             for (int u = 0; u < kLoadChunk; ++u) {
                 const int e = e0 + u * NT;
                 if (e >= LP) continue;
-                const int li = a.dP.div(e);
+                const int li = divc<PS>(e, a.dP);
                 const int z = e - li * P;
                 Cx<T> v = {T(0), T(0)};
                 if (va[u]) {
@@ -465,7 +564,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         }
     } else {
         for (int e = threadIdx.x; e < L * P; e += NT) {
-            const int li = a.dP.div(e);
+            const int li = divc<PS>(e, a.dP);
             const int z = e - li * P;
             Cx<T> v = {T(0), T(0)};
             if (li < nl) {
@@ -491,7 +590,8 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         for (int w = 0; w < NT / 64; ++w) v = fmaxf(v, red[threadIdx.x][w]);
         job.zmax[blockIdx.x * 4 + threadIdx.x] = v;
     }
-    lds_fft<T, NT, BMAX>(buf, P, L, -1, twl, a.rp);
+    if constexpr (PS > 0) lds_fft_s<T, NT, PS, LS>(buf, -1, twl);
+    else lds_fft<T, NT, BMAX>(buf, P, L, -1, twl, a.rp);
 
     // unpack: X_re = (Z_k + conj Z_-k)/2,  X_im = (Z_k - conj Z_-k)/(2i)
     const int Hz = a.Hz;
@@ -501,7 +601,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         const int np = min(2 * ((nl + 3) >> 2), npos - pos0);
         for (int e = threadIdx.x; e < np * Hz * 4; e += NT) {
             const int mu = e & 3;
-            const int pl = a.dHz.div(e >> 2);
+            const int pl = divc<HS>(e >> 2, a.dHz);
             const int k = (e >> 2) - pl * Hz;
             const int li = (pl >> 1) * 4 + mu;
             const Cx<T> zk = buf[li * P + k];
@@ -513,7 +613,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         }
     } else {
         for (int e = threadIdx.x; e < 2 * nl * Hz; e += NT) {
-            const int rl = a.dHz.div(e);
+            const int rl = divc<HS>(e, a.dHz);
             const int k = e - rl * Hz;
             const int li = rl >> 1;
             const Cx<T> zk = buf[li * P + k];
@@ -532,6 +632,18 @@ int zfwd_lines_per_block(int Pz, int prec64) {
 
 static_assert(sizeof(ZFwd) <= 4096, "z-pass kernel arguments above 4 KiB");
 
+// FP32 forward z pass of the sources with a compile-time length, for the
+// same lengths as the line passes.
+template <int P0, int... Ps>
+static bool launch_zfwd_static(const ZFwd &a, dim3 grid, hipStream_t st) {
+    if (a.Pz == P0) {
+        hipLaunchKernelGGL((k_zfwd<float, P0>), grid, dim3(kFftThreads), 0, st, a);
+        return true;
+    }
+    if constexpr (sizeof...(Ps) > 0) return launch_zfwd_static<Ps...>(a, grid, st);
+    else return false;
+}
+
 void launch_zfwd(const ZFwd &a0, int prec64, hipStream_t st) {
     ZFwd a = a0;
     a.dP = FastDiv(uint32_t(a.Pz));
@@ -542,25 +654,29 @@ void launch_zfwd(const ZFwd &a0, int prec64, hipStream_t st) {
     const int nlines = (a.mode == 0) ? 4 * ((a.Nx * a.Ny + 1) / 2) : a.Px * (a.Py / 2);
     dim3 grid((nlines + L - 1) / L, a.n_jobs);
     if (prec64) hipLaunchKernelGGL(k_zfwd<double>, grid, dim3(kFftThreads), 0, st, a);
-    else hipLaunchKernelGGL(k_zfwd<float>, grid, dim3(kFftThreads), 0, st, a);
+    else if (a.mode != 0 || !launch_zfwd_static<32, 48, 64, 96, 108, 128, 256>(a, grid, st))
+        hipLaunchKernelGGL(k_zfwd<float>, grid, dim3(kFftThreads), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
 // Complex-to-real z pass with crop and static add.  Complex line
 // c = pair * 4 + mu carries positions 2 pair (real part) and 2 pair + 1
 // (imaginary part) of component mu.
-template <typename T>
+// PS > 0: the z length is the compile-time PS.
+template <typename T, int PS = 0>
 __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
     constexpr int E = Lds<T>::E;
     constexpr int NT = kFftThreads;
     constexpr int BMAX = (E / 2 + NT - 1) / NT;
+    constexpr int LS = PS ? zfwd_lpb<T>(PS) : 0;
+    constexpr int HS = PS ? PS / 2 + 1 : 0;
     __shared__ Cx<T> buf[E];
     __shared__ Cx<T> twl[kMaxFft];
     const ZInvJob &job = a.jobs[blockIdx.y];
-    const int P = a.Pz;
-    const int Hz = a.Hz;
+    const int P = PS ? PS : a.Pz;
+    const int Hz = PS ? HS : a.Hz;
     for (int i = threadIdx.x; i < P; i += NT) twl[i] = reinterpret_cast<const Cx<T> *>(a.tw)[i];
-    const int L = zfwd_lpb<T>(P);
+    const int L = PS ? LS : zfwd_lpb<T>(P);
     const int line0 = blockIdx.x * L;
     const int npos = a.Nx * a.Ny;
     const int nlines = 4 * ((npos + 1) / 2);
@@ -576,7 +692,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
         for (int u = 0; u < kLoadChunk; ++u) {
             const int e = e0 + u * NT;
             const int mu = e & 3;
-            const int ppl = a.dHz.div(e >> 2);
+            const int ppl = divc<HS>(e >> 2, a.dHz);
             const int k = (e >> 2) - ppl * Hz;
             const int li = ppl * 4 + mu;
             const int pa = pos0 + 2 * ppl;
@@ -591,7 +707,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
             const int e = e0 + u * NT;
             if (e >= nin) continue;
             const int mu = e & 3;
-            const int ppl = a.dHz.div(e >> 2);
+            const int ppl = divc<HS>(e >> 2, a.dHz);
             const int k = (e >> 2) - ppl * Hz;
             const int li = ppl * 4 + mu;
             if (k == 0 || 2 * k == P) {
@@ -603,7 +719,8 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
         }
     }
     __syncthreads();
-    lds_fft<T, NT, BMAX>(buf, P, L, +1, twl, a.rp);
+    if constexpr (PS > 0) lds_fft_s<T, NT, PS, LS>(buf, +1, twl);
+    else lds_fft<T, NT, BMAX>(buf, P, L, +1, twl, a.rp);
 
     T *__restrict__ out = reinterpret_cast<T *>(job.out);
     const T *__restrict__ add = reinterpret_cast<const T *>(job.add);
@@ -641,6 +758,17 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
     }
 }
 
+// FP32 inverse z pass with a compile-time length (the line-pass lengths).
+template <int P0, int... Ps>
+static bool launch_zinv_static(const ZInv &a, dim3 grid, hipStream_t st) {
+    if (a.Pz == P0) {
+        hipLaunchKernelGGL((k_zinv<float, P0>), grid, dim3(kFftThreads), 0, st, a);
+        return true;
+    }
+    if constexpr (sizeof...(Ps) > 0) return launch_zinv_static<Ps...>(a, grid, st);
+    else return false;
+}
+
 void launch_zinv(const ZInv &a0, int prec64, hipStream_t st) {
     ZInv a = a0;
     const int L = zfwd_lines_per_block(a.Pz, prec64);
@@ -651,7 +779,8 @@ void launch_zinv(const ZInv &a0, int prec64, hipStream_t st) {
     const int nlines = 4 * ((a.Nx * a.Ny + 1) / 2);
     dim3 grid((nlines + L - 1) / L, a.n_jobs);
     if (prec64) hipLaunchKernelGGL(k_zinv<double>, grid, dim3(kFftThreads), 0, st, a);
-    else hipLaunchKernelGGL(k_zinv<float>, grid, dim3(kFftThreads), 0, st, a);
+    else if (!launch_zinv_static<32, 48, 64, 96, 108, 128, 256>(a, grid, st))
+        hipLaunchKernelGGL(k_zinv<float>, grid, dim3(kFftThreads), 0, st, a);
 }
 
 }  // namespace rpot
