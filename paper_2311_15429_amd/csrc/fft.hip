@@ -373,21 +373,22 @@ static void launch_line_e(const LinePass &a, dim3 grid, int E, hipStream_t st) {
     }
 }
 
-// FP32 passes at the default tile have a compile-time kernel for these
+// FP32 passes at the 2048 and 4096 tiles have a compile-time kernel for these
 // transform lengths (the pads of the usual grids); other lengths, FP64 and the
-// other tiles use the run-time kernel.
-template <int FMT, int P0, int... Ps>
+// 6144 tile use the run-time kernel.
+template <int FMT, int E, int P0, int... Ps>
 static bool launch_line_static(const LinePass &a, dim3 grid, hipStream_t st) {
     if (a.P == P0) {
-        hipLaunchKernelGGL((k_line_pass<float, FMT, Lds<float>::E / 2, P0>), grid, dim3(kFftThreads), 0, st, a);
+        hipLaunchKernelGGL((k_line_pass<float, FMT, E, P0>), grid, dim3(kFftThreads), 0, st, a);
         return true;
     }
-    if constexpr (sizeof...(Ps) > 0) return launch_line_static<FMT, Ps...>(a, grid, st);
+    if constexpr (sizeof...(Ps) > 0) return launch_line_static<FMT, E, Ps...>(a, grid, st);
     else return false;
 }
 template <int FMT>
-static bool launch_line_static_any(const LinePass &a, dim3 grid, hipStream_t st) {
-    return launch_line_static<FMT, 32, 48, 64, 96, 108, 128, 256>(a, grid, st);
+static bool launch_line_static_any(const LinePass &a, int E, dim3 grid, hipStream_t st) {
+    if (E == Lds<float>::E) return launch_line_static<FMT, Lds<float>::E, 32, 48, 64, 96, 108, 128, 256>(a, grid, st);
+    return launch_line_static<FMT, Lds<float>::E / 2, 32, 48, 64, 96, 108, 128, 256>(a, grid, st);
 }
 static bool has_static_len(int P) {
     for (int q : {32, 48, 64, 96, 108, 128, 256})
@@ -408,7 +409,8 @@ int line_pass_elems(int lds_elems, int prec64) {
 void launch_line_pass(const LinePass &a0, int prec64, hipStream_t st) {
     LinePass a = a0;
     const int E = line_pass_elems(a.lds_elems, prec64);
-    const bool fixed = !prec64 && E == Lds<float>::E / 2 && a.out_fmt != RING_F64 && has_static_len(a.P);
+    const bool fixed = !prec64 && (E == Lds<float>::E / 2 || E == Lds<float>::E) && a.out_fmt != RING_F64 &&
+                       has_static_len(a.P);
     // grouped orders (groups of 1, 2 or 4 lines) need whole groups of lines in a block
     int G = std::max(std::max(a.in_group, a.out_group), 1);
     while (G > 1 && E / a.P < G) G /= 2;
@@ -427,9 +429,9 @@ void launch_line_pass(const LinePass &a0, int prec64, hipStream_t st) {
         else launch_line_e<double, RING_F32>(a, grid, E, st);
     } else if (fixed) {
         switch (a.out_fmt) {
-        case RING_F16: launch_line_static_any<RING_F16>(a, grid, st); break;
-        case RING_BF16: launch_line_static_any<RING_BF16>(a, grid, st); break;
-        default: launch_line_static_any<RING_F32>(a, grid, st);
+        case RING_F16: launch_line_static_any<RING_F16>(a, E, grid, st); break;
+        case RING_BF16: launch_line_static_any<RING_BF16>(a, E, grid, st); break;
+        default: launch_line_static_any<RING_F32>(a, E, grid, st);
         }
     } else {
         switch (a.out_fmt) {
