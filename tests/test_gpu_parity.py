@@ -188,3 +188,34 @@ def test_largest_fft_length(precision, tol):
     assert tuple(p.info(0, 0)[2]) == (512, 8, 512)
     p.close()
     _check(s, precision, 8, tol, steps=[4, 8])
+
+
+@pytest.mark.parametrize("dims,pads", [((16, 24, 32), (32, 48, 64)), ((48, 54, 8), (96, 108, 16)),
+                                       ((64, 4, 128), (128, 8, 256))])
+def test_fixed_length_transforms_fp32(dims, pads):
+    """Pads that reach every transform length with a compile-time FP32 kernel
+    (x: 32, 96, 128; y: 48, 108; z: 64, 256) and two without one (8, 16).  At
+    the 2048 and 4096 tiles (compile-time kernels) the result is the oracle's,
+    and it agrees with the run-time kernel of the 6144 tile to FP32 rounding."""
+    from paper_2311_15429_amd import plan_for_system
+    h = 0.5
+    rng = np.random.default_rng(sum(dims))
+    off = np.array([h * dims[0] + 6.0, 2.0, -1.0])
+    doms = [sy.Domain(dims, np.zeros(3)), sy.Domain(dims, off)]
+    for d in doms:
+        sy._random_pairs(rng, d, h, 2)
+    s = sy.System(h, 0.02, sy.C_AU, doms, name=f"pads {pads}")
+    p = plan_for_system(s, "fp32")
+    assert tuple(p.info(0, 0)[2]) == pads
+    p.close()
+    L = 10
+    S = _samples(s, L)
+    runs = {tile: run_gpu(s, "fp32", S, tune={"fft_lds": tile}) for tile in (2048, 4096, 6144)}
+    ref = oracle.potential_full(s, S, [L])[0]
+    for tile in (2048, 4096):
+        e = rel_err(runs[tile][L], ref)
+        log(f"pads {pads}, tile {tile}: rel err vs oracle {np.array2string(e, precision=2)}")
+        assert np.all(e <= FP32_TOL), (tile, e)
+        for l in range(L + 1):
+            d = rel_err(runs[tile][l], runs[6144][l]) if np.any(runs[6144][l][0]) else np.zeros(4)
+            assert np.all(d <= 2e-6), (tile, l, d)
