@@ -84,6 +84,14 @@ __device__ __forceinline__ int divc(int n, const FastDiv &fd) {
     else return fd.div(n);
 }
 
+// Row stride (complex elements) of the lines staged in LDS: odd for lines of
+// 8 points or more, so that lanes walking across lines (same point, next line)
+// fall in different banks instead of all in one.
+__host__ __device__ constexpr int lds_stride(int P) { return P >= 8 ? (P | 1) : P; }
+// Staged elements per block for a tile of E elements: room for the padding
+// (L <= E / 8 lines when P >= 8).
+__host__ __device__ constexpr int lds_room(int E) { return E + E / 8; }
+
 // One Stockham stage of radix R over the L lines in LDS: butterfly b of line
 // li reads x[i + r nq] (i = b mod nq, r < R), multiplies by the twiddles
 // w^(r k) (k = i mod p, p the product of the earlier radices), transforms,
@@ -92,7 +100,7 @@ __device__ __forceinline__ int divc(int n, const FastDiv &fd) {
 // constants are compile-time (the transform length is fixed), else the
 // run-time values nq, p, tws, nbf are used.
 template <typename T, int NT, int BMAX, int R, int NQ = 0, int PP = 0, int TWS = 0, int NBF = 0>
-__device__ __forceinline__ void lds_stage(Cx<T> *buf, int P, int nbf_rt, int nq_rt, int p_rt, int tws_rt,
+__device__ __forceinline__ void lds_stage(Cx<T> *buf, int S, int nbf_rt, int nq_rt, int p_rt, int tws_rt,
                                           FastDiv dq, FastDiv dp, int dir, const Cx<T> *tw) {
     const int tid = threadIdx.x;
     const int nq = NQ ? NQ : nq_rt;
@@ -110,8 +118,8 @@ __device__ __forceinline__ void lds_stage(Cx<T> *buf, int P, int nbf_rt, int nq_
             const int i = b - li * nq;
             const int q = divc<PP>(i, dp);
             const int k = i - q * p;
-            const Cx<T> *row = buf + li * P;
-            wpos[it] = li * P + q * p * R + k;
+            const Cx<T> *row = buf + li * S;
+            wpos[it] = li * S + q * p * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[it][r] = row[i + r * nq];
             if (PP != 1 && k != 0) {
@@ -136,20 +144,20 @@ __device__ __forceinline__ void lds_stage(Cx<T> *buf, int P, int nbf_rt, int nq_
     __syncthreads();
 }
 
-// In-place FFT of L lines of length P held in LDS (row-major [L][P]).
+// In-place FFT of L lines of length P held in LDS (row-major, row stride S).
 // dir = -1: sum_j x_j exp(-2 pi i jk/P);  dir = +1: exp(+2 pi i jk/P).
 // The twiddles tw come from LDS; every division by a stage constant is a
 // multiply-high (RadixPlan::dq, dp).
 template <typename T, int NT, int BMAX>
-__device__ void lds_fft(Cx<T> *buf, int P, int L, int dir, const Cx<T> *tw, const RadixPlan &rp) {
+__device__ void lds_fft(Cx<T> *buf, int P, int S, int L, int dir, const Cx<T> *tw, const RadixPlan &rp) {
     int p = 1;
     for (int st = 0; st < rp.n; ++st) {
         const int R = rp.r[st];
         const int nq = P / R;
         const int nbf = L * nq;
-        if (R == 4) lds_stage<T, NT, BMAX, 4>(buf, P, nbf, nq, p, rp.tws[st], rp.dq[st], rp.dp[st], dir, tw);
-        else if (R == 2) lds_stage<T, NT, BMAX, 2>(buf, P, nbf, nq, p, rp.tws[st], rp.dq[st], rp.dp[st], dir, tw);
-        else lds_stage<T, NT, BMAX, 3>(buf, P, nbf, nq, p, rp.tws[st], rp.dq[st], rp.dp[st], dir, tw);
+        if (R == 4) lds_stage<T, NT, BMAX, 4>(buf, S, nbf, nq, p, rp.tws[st], rp.dq[st], rp.dp[st], dir, tw);
+        else if (R == 2) lds_stage<T, NT, BMAX, 2>(buf, S, nbf, nq, p, rp.tws[st], rp.dq[st], rp.dp[st], dir, tw);
+        else lds_stage<T, NT, BMAX, 3>(buf, S, nbf, nq, p, rp.tws[st], rp.dq[st], rp.dp[st], dir, tw);
         p *= R;
     }
 }
@@ -187,7 +195,7 @@ __device__ __forceinline__ void lds_fft_s(Cx<T> *buf, int dir, const Cx<T> *tw) 
         constexpr int TWS = P / (PP * R);
         constexpr int BM = (NBF + NT - 1) / NT;
         const FastDiv none;
-        lds_stage<T, NT, BM, R, NQ, PP, TWS, NBF>(buf, P, NBF, NQ, PP, TWS, none, none, dir, tw);
+        lds_stage<T, NT, BM, R, NQ, PP, TWS, NBF>(buf, lds_stride(P), NBF, NQ, PP, TWS, none, none, dir, tw);
         lds_fft_s<T, NT, P, L, ST + 1>(buf, dir, tw);
     }
 }
@@ -233,16 +241,19 @@ __host__ __device__ constexpr int static_lines(int E, int P) { return (E / P) & 
 // L = static_lines(E, PS)); PS = 0: run-time length and lines per block.
 template <typename T, int FMT, int E, int PS = 0>
 __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
-    static_assert((E + kMaxFft) * sizeof(Cx<T>) <= 64 * 1024, "line-pass LDS above 64 KiB");
     constexpr int NT = kFftThreads;
     constexpr int BMAX = (E / 2 + NT - 1) / NT;
     constexpr int LS = PS ? static_lines(E, PS) : 0;
     static_assert(PS == 0 || LS >= 4, "fixed-length pass needs four lines per block");
-    __shared__ Cx<T> buf[E];
-    __shared__ Cx<T> twl[kMaxFft];
+    constexpr int NB = PS ? LS * lds_stride(PS) : lds_room(E);
+    constexpr int NTW = PS ? PS : kMaxFft;
+    static_assert((NB + NTW) * sizeof(Cx<T>) <= 64 * 1024, "line-pass LDS above 64 KiB");
+    __shared__ Cx<T> buf[NB];
+    __shared__ Cx<T> twl[NTW];
     const LineJob &job = a.jobs[blockIdx.y];
     const int P = PS ? PS : a.P;
     const int L = PS ? LS : a.L;
+    const int S = lds_stride(P);
     const int line0 = blockIdx.x * L;
     const int nl = min(L, a.lines - line0);
     const Cx<T> *__restrict__ in = reinterpret_cast<const Cx<T> *>(job.in);
@@ -270,7 +281,7 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
                 j = divc<LS>(e, a.dL);
                 li = e - j * L;
             }
-            o[u] = li * P + j;
+            o[u] = li * S + j;
             v[u] = {T(0), T(0)};
             if (e < LP && li < nl && j < a.n_in) {
                 const int line = line0 + li;
@@ -285,7 +296,7 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
     }
     __syncthreads();
     if constexpr (PS > 0) lds_fft_s<T, NT, PS, LS>(buf, a.dir, twl);
-    else lds_fft<T, NT, BMAX>(buf, P, L, a.dir, twl, a.rp);
+    else lds_fft<T, NT, BMAX>(buf, P, S, L, a.dir, twl, a.rp);
 
     void *obase = job.out;
     const float *qs = job.qscale;
@@ -345,7 +356,7 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
                 }
                 idx = int64_t(kk / kTile) * job.tile_stride + int64_t(w);
             }
-            Store<T, FMT>::put(obase, idx, buf[li * P + j], inv_scale);
+            Store<T, FMT>::put(obase, idx, buf[li * S + j], inv_scale);
         }
     }
 }
@@ -491,12 +502,15 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
     constexpr int BMAX = (E / 2 + NT - 1) / NT;
     constexpr int LS = PS ? zfwd_lpb<T>(PS) : 0;
     constexpr int HS = PS ? PS / 2 + 1 : 0;
-    __shared__ Cx<T> buf[E];
-    __shared__ Cx<T> twl[kMaxFft];
+    constexpr int NB = PS ? LS * lds_stride(PS) : lds_room(E);
+    constexpr int NTW = PS ? PS : kMaxFft;
+    __shared__ Cx<T> buf[NB];
+    __shared__ Cx<T> twl[NTW];
     __shared__ float red[4][NT / 64];
     const ZFwdJob &job = a.jobs[blockIdx.y];
     const int P = PS ? PS : a.Pz;
     const int L = PS ? LS : zfwd_lpb<T>(P);
+    const int RS = lds_stride(P);   // LDS row stride
     for (int i = threadIdx.x; i < P; i += NT) twl[i] = reinterpret_cast<const Cx<T> *>(a.tw)[i];
     const int line0 = blockIdx.x * L;
     const int npos = a.Nx * a.Ny;
@@ -561,7 +575,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
                     const int mu = (line0 + li) & 3;
                     mx[mu] = fmaxf(mx[mu], fmaxf(fabsf(float(v.x)), fabsf(float(v.y))));
                 }
-                buf[li * P + z] = v;
+                buf[li * RS + z] = v;
             }
         }
     } else {
@@ -576,7 +590,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
                 v.x = T(green_value(a, job, qx, qy, z));
                 v.y = T(green_value(a, job, qx, qy + 1, z));
             }
-            buf[li * P + z] = v;
+            buf[li * RS + z] = v;
         }
     }
     if (a.mode == 0 && job.zmax) {
@@ -593,7 +607,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
         job.zmax[blockIdx.x * 4 + threadIdx.x] = v;
     }
     if constexpr (PS > 0) lds_fft_s<T, NT, PS, LS>(buf, -1, twl);
-    else lds_fft<T, NT, BMAX>(buf, P, L, -1, twl, a.rp);
+    else lds_fft<T, NT, BMAX>(buf, P, RS, L, -1, twl, a.rp);
 
     // unpack: X_re = (Z_k + conj Z_-k)/2,  X_im = (Z_k - conj Z_-k)/(2i)
     const int Hz = a.Hz;
@@ -606,8 +620,8 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
             const int pl = divc<HS>(e >> 2, a.dHz);
             const int k = (e >> 2) - pl * Hz;
             const int li = (pl >> 1) * 4 + mu;
-            const Cx<T> zk = buf[li * P + k];
-            const Cx<T> zm = buf[li * P + (k == 0 ? 0 : P - k)];
+            const Cx<T> zk = buf[li * RS + k];
+            const Cx<T> zm = buf[li * RS + (k == 0 ? 0 : P - k)];
             Cx<T> r;
             if ((pl & 1) == 0) r = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
             else r = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
@@ -618,8 +632,8 @@ __global__ __launch_bounds__(kFftThreads) void k_zfwd(ZFwd a) {
             const int rl = divc<HS>(e, a.dHz);
             const int k = e - rl * Hz;
             const int li = rl >> 1;
-            const Cx<T> zk = buf[li * P + k];
-            const Cx<T> zm = buf[li * P + (k == 0 ? 0 : P - k)];
+            const Cx<T> zk = buf[li * RS + k];
+            const Cx<T> zm = buf[li * RS + (k == 0 ? 0 : P - k)];
             Cx<T> r;
             if ((rl & 1) == 0) r = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
             else r = {T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x)};
@@ -672,13 +686,16 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
     constexpr int BMAX = (E / 2 + NT - 1) / NT;
     constexpr int LS = PS ? zfwd_lpb<T>(PS) : 0;
     constexpr int HS = PS ? PS / 2 + 1 : 0;
-    __shared__ Cx<T> buf[E];
-    __shared__ Cx<T> twl[kMaxFft];
+    constexpr int NB = PS ? LS * lds_stride(PS) : lds_room(E);
+    constexpr int NTW = PS ? PS : kMaxFft;
+    __shared__ Cx<T> buf[NB];
+    __shared__ Cx<T> twl[NTW];
     const ZInvJob &job = a.jobs[blockIdx.y];
     const int P = PS ? PS : a.Pz;
     const int Hz = PS ? HS : a.Hz;
     for (int i = threadIdx.x; i < P; i += NT) twl[i] = reinterpret_cast<const Cx<T> *>(a.tw)[i];
     const int L = PS ? LS : zfwd_lpb<T>(P);
+    const int S = lds_stride(P);
     const int line0 = blockIdx.x * L;
     const int npos = a.Nx * a.Ny;
     const int nlines = 4 * ((npos + 1) / 2);
@@ -713,16 +730,16 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
             const int k = (e >> 2) - ppl * Hz;
             const int li = ppl * 4 + mu;
             if (k == 0 || 2 * k == P) {
-                buf[li * P + k] = Cx<T>{xa[u].x, xb[u].x};
+                buf[li * S + k] = Cx<T>{xa[u].x, xb[u].x};
             } else {
-                buf[li * P + k] = Cx<T>{xa[u].x - xb[u].y, xa[u].y + xb[u].x};
-                buf[li * P + (P - k)] = Cx<T>{xa[u].x + xb[u].y, xb[u].x - xa[u].y};
+                buf[li * S + k] = Cx<T>{xa[u].x - xb[u].y, xa[u].y + xb[u].x};
+                buf[li * S + (P - k)] = Cx<T>{xa[u].x + xb[u].y, xb[u].x - xa[u].y};
             }
         }
     }
     __syncthreads();
     if constexpr (PS > 0) lds_fft_s<T, NT, PS, LS>(buf, +1, twl);
-    else lds_fft<T, NT, BMAX>(buf, P, L, +1, twl, a.rp);
+    else lds_fft<T, NT, BMAX>(buf, P, S, L, +1, twl, a.rp);
 
     T *__restrict__ out = reinterpret_cast<T *>(job.out);
     const T *__restrict__ add = reinterpret_cast<const T *>(job.add);
@@ -744,7 +761,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zinv(ZInv a) {
             const int z = e - r * a.Nz;
             const int mu = full ? a.dnp.div(r) : r / np;
             const int pl = r - mu * np;
-            bi[u] = ((pl >> 1) * 4 + mu) * P + z;
+            bi[u] = ((pl >> 1) * 4 + mu) * S + z;
             odd[u] = (pl & 1) != 0;
             o[u] = mu * npts + int64_t(pos0 + pl) * a.Nz + z;
             ad[u] = (add && e < nout) ? add[o[u]] : T(0);
