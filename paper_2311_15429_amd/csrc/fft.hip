@@ -239,6 +239,24 @@ __host__ __device__ constexpr int static_lines(int E, int P) { return (E / P) & 
 
 // PS > 0: the transform length is the compile-time PS (the launcher sets
 // L = static_lines(E, PS)); PS = 0: run-time length and lines per block.
+// One scaled FP16 / BF16 complex value as its 32-bit pattern (re low, im high).
+template <int FMT>
+__device__ __forceinline__ uint32_t pack_half2(float x, float y, float s) {
+    if constexpr (FMT == RING_F16) {
+        const __half2 h = __halves2half2(__float2half_rn(x * s), __float2half_rn(y * s));
+        uint32_t u;
+        __builtin_memcpy(&u, &h, 4);
+        return u;
+    } else {
+        __hip_bfloat162 h;
+        h.x = __float2bfloat16(x * s);
+        h.y = __float2bfloat16(y * s);
+        uint32_t u;
+        __builtin_memcpy(&u, &h, 4);
+        return u;
+    }
+}
+
 template <typename T, int FMT, int E, int PS = 0>
 __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
     constexpr int NT = kFftThreads;
@@ -316,6 +334,34 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
     }
     const bool jfast_out = (a.out_j == 1);
     const int nout = a.n_out;
+    if constexpr (FMT == RING_F16 || FMT == RING_BF16) {
+        if (job.tile_stride && a.tile_comp == 4 && a.out_group == 4) {
+            // ring rows [k][c] of 4-byte values: each lane converts the
+            // components c0, c0 + 1 (c0 = 0 or 2) of one frequency and writes
+            // them as one 8-byte store.  Blocks start on whole groups of four
+            // lines (L is a multiple of 4), so line li0 carries component c0.
+            for (int e = threadIdx.x; e < L * nout / 2; e += NT) {
+                const int cp = e & 1;
+                const int t = e >> 1;
+                const int r = a.dnout.div(t);
+                const int j = t - r * nout;
+                const int li0 = r * 4 + cp * 2;
+                if (li0 >= nl) continue;
+                const int line = line0 + li0;
+                const int outer = a.dinner.div(line);
+                const int inner = line - outer * a.n_inner;
+                const uint32_t u = uint32_t(outer * a.out_outer + inner * a.out_inner + int64_t(j) * a.out_j);
+                const uint32_t kk = u >> 2;
+                const int64_t idx = int64_t(kk / kTile) * job.tile_stride + int64_t((kk % kTile) * 4 + (u & 3));
+                const Cx<T> v0 = buf[li0 * S + j];
+                const Cx<T> v1 = buf[(li0 + 1) * S + j];
+                const uint2 w = {pack_half2<FMT>(float(v0.x), float(v0.y), cp ? iq2 : iq0),
+                                 pack_half2<FMT>(float(v1.x), float(v1.y), cp ? iq3 : iq1)};
+                *reinterpret_cast<uint2 *>(reinterpret_cast<char *>(obase) + idx * 4) = w;
+            }
+            return;
+        }
+    }
     for (int e = threadIdx.x; e < L * nout; e += NT) {
         int li, j;
         if (a.out_group > 0) {
