@@ -157,8 +157,8 @@ def test_host_tier_needs_a_pinned_buffer():
     p.close()
 
 
-@pytest.mark.parametrize("host", [False, True])
-def test_split_history_graph_replay_is_bitwise_identical(host):
+@pytest.mark.parametrize("precision,host", [("fp32", False), ("fp32", True), ("fp32_ring_fp16", True)])
+def test_split_history_graph_replay_is_bitwise_identical(precision, host):
     from paper_2311_15429_amd import plan_for_system
     system = _pair()
     L = 45
@@ -167,7 +167,7 @@ def test_split_history_graph_replay_is_bitwise_identical(host):
             .to("cuda", torch.float32) for n in range(2)] for l in range(L + 1)]
     res = []
     for capture in ((False, True) if not host else (False, True, "device")):
-        p = plan_for_system(system, "fp32", stream=torch.cuda.current_stream())
+        p = plan_for_system(system, precision, stream=torch.cuda.current_stream())
         p.history_split(8)
         if host and capture != "device":
             p.history_host(True)
