@@ -8,6 +8,15 @@
 // Zero padding is pruned on input (only n_in points are read) and the crop on
 // output (only n_out points are written).  Intermediate 3-D arrays keep the
 // four components interleaved ([..][4]) so every pass moves 32/64-byte runs.
+//
+// Spectra index frequencies as k = (y Hz + z) Px + x (x fastest): the lag sum
+// is pointwise in k, and this order lets the x passes, the only ones that
+// touch spectra, move whole lines of Px frequencies as contiguous runs.
+// Lines are staged in LDS at an odd row stride, so lanes that walk across
+// lines do not share a bank.  FP32 passes of the usual lengths are compiled
+// for their length (constant radix plan and index arithmetic); the others use
+// the run-time kernel.  FP16/BF16 ring rows are written two components per
+// lane, as one 8-byte store.
 #include "rpot_internal.hpp"
 
 #include <hip/hip_bf16.h>
