@@ -242,6 +242,17 @@ struct Store<T, RING_BF16> {
     }
 };
 
+// Hardware dispatches consecutive blocks round-robin over the 8 XCDs, each
+// with its own L2.  This bijection gives every XCD a contiguous range of
+// block indices, so neighbouring tiles, which share the cache lines at their
+// edges, are fetched through one L2.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_block(int b, int n) {
+    const int x = b % kNumXcd, i = b / kNumXcd;
+    const int q = n / kNumXcd, r = n % kNumXcd;
+    return x * q + min(x, r) + i;
+}
+
 // Lines per block of a line pass with a compile-time length P: whole groups
 // of four lines (every grouped order fits).
 __host__ __device__ constexpr int static_lines(int E, int P) { return (E / P) & ~3; }
@@ -281,7 +292,7 @@ __global__ __launch_bounds__(kFftThreads) void k_line_pass(LinePass a) {
     const int P = PS ? PS : a.P;
     const int L = PS ? LS : a.L;
     const int S = lds_stride(P);
-    const int line0 = blockIdx.x * L;
+    const int line0 = xcd_block(int(blockIdx.x), int(gridDim.x)) * L;
     const int nl = min(L, a.lines - line0);
     const Cx<T> *__restrict__ in = reinterpret_cast<const Cx<T> *>(job.in);
     for (int i = threadIdx.x; i < P; i += NT) twl[i] = reinterpret_cast<const Cx<T> *>(a.tw)[i];
