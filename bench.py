@@ -818,6 +818,15 @@ def main():
             "algorithmic_bytes_per_launch": st["lagsum_bytes"]}
     log(f"step {ms_step:.3f} ms, lag-sum {lag_avg_s * 1e3:.3f} ms ({achieved:.0f} GB/s), "
         f"{updates / 1e6:.2f} M updates/s")
+    # the practical read bandwidth of this device (a plain read stream of 4
+    # GiB through the library's calibration kernel), beside the lag sum
+    from paper_2311_15429_amd.calib import read_stream_gbs
+    rs, rs_cfg = read_stream_gbs()
+    roof["read_stream_gbs"] = round(rs, 1)
+    roof["read_stream_launch"] = {"unroll": rs_cfg[0], "blocks_per_cu": rs_cfg[1]}
+    roof["frac_of_read_stream"] = round(achieved / rs, 4)
+    log(f"read stream: {rs:.0f} GB/s ({rs / HBM_PEAK_GBS:.1%} of peak, unroll {rs_cfg[0]}, "
+        f"{rs_cfg[1]} blocks per CU); the lag sum runs at {achieved / rs:.1%} of it")
 
     cpu = None
     if not args.no_cpu_baseline:

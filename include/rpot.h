@@ -464,6 +464,19 @@ rp_status rp_osc_state(rp_osc osc, double *q, double *qdot, double *phi, double 
 rp_status rp_osc_destroy(rp_osc osc);
 const char *rp_osc_last_error(rp_osc osc);
 
+/* HBM read-stream calibration (no plan): reads `bytes` of device memory at
+ * `buf` once, 16-byte non-temporal loads as in the lag sum, on `grid` blocks
+ * of 256 threads with `unroll` (1, 2, 4 or 8) loads in flight per thread.
+ * Timing it gives the practical read bandwidth that the lag sum's roofline
+ * fraction is set against (Sec. IV names the retarded potential and the
+ * memory it needs as the main cost of a step).  buf: device, 16-byte aligned, bytes a
+ * multiple of 16.  sink: device, grid * 256 uint32 (one folded word per
+ * thread, written; the caller owns both).  Asynchronous on hip_stream (NULL:
+ * the null stream); no allocation.  RP_ERR_ARG on a null pointer, a bad size,
+ * alignment, grid (1 .. 2^20) or unroll; RP_ERR_DEVICE if the launch fails. */
+rp_status rp_read_stream(const void *buf, size_t bytes, uint32_t *sink, int32_t grid, int32_t unroll,
+                         void *hip_stream);
+
 /* Release the host plan (the workspace stays the caller's). */
 rp_status rp_plan_destroy(rp_plan plan);
 

@@ -23,7 +23,7 @@ EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_set
            "rp_osc_create", "rp_osc_workspace_bytes", "rp_osc_bind", "rp_osc_set_state", "rp_osc_sources",
            "rp_osc_step", "rp_osc_state", "rp_osc_destroy", "rp_osc_last_error", "rp_history_split",
            "rp_history_host", "rp_history_host_bytes", "rp_bind_history_host",
-           "rp_class_info", "rp_set_class_tuning", "rp_get_class_tuning"]
+           "rp_class_info", "rp_set_class_tuning", "rp_get_class_tuning", "rp_read_stream"]
 TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2, "fft_lds": 4}
 
 
@@ -59,6 +59,7 @@ def load():
     lib.rp_plan_domains.argtypes = [P(vp), i32, P(i32), P(ctypes.c_double), P(i32), ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_int, vp]
     lib.rp_workspace_bytes.argtypes = [vp, P(sz)]
+    lib.rp_read_stream.argtypes = [vp, sz, vp, i32, i32, vp]
     lib.rp_bind_workspace.argtypes = [vp, vp, sz]
     lib.rp_set_green_kernels.argtypes = [vp]
     lib.rp_push_sources.argtypes = [vp, i64, P(vp)]

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "librpot.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["plan.cpp", "surrogate.cpp", "fft.hip", "lagsum.hip", "history.hip", "mlp.hip", "surrogate.hip",
-           "coupling.hip"]
+           "coupling.hip", "calib.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
