@@ -526,7 +526,12 @@ def bench_coupled(args):
                        "lagsum_ms": lag_ms / launches, "shape_bytes_per_step": osc_bytes,
                        "max_abs_q": [float(np.max(np.abs(q[:16]))), float(np.max(np.abs(q[16:])))],
                        "autotune": tuned},
-            "roofline": None, "cpu_baseline": None}
+            "roofline": {"bound": "hbm", "achieved": round(st["lagsum_bytes"] / (lag_ms / launches * 1e-3) / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(st["lagsum_bytes"] / (lag_ms / launches * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": None, "kernel": "k_lagsum", "kernel_ms": round(lag_ms / launches, 4),
+                         "algorithmic_bytes_per_launch": st["lagsum_bytes"]},
+            "cpu_baseline": None}
     print(json.dumps(line), flush=True)
     osc.close()
     plan.close()
