@@ -33,6 +33,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+class SourceGen:
+    """Sources of step l, [4][Nx][Ny][Nz] per domain, on the GPU from the
+    separable factors (FP64 product, then the path's dtype)."""
+
+    def __init__(self, system, dtype):
+        import torch
+        from synth.sources import spatial_factors
+        self.system, self.dtype = system, dtype
+        self.B = []
+        for d in system.domains:
+            b = spatial_factors(d, system.h, system.c)
+            self.B.append(torch.from_numpy(b.reshape(b.shape[0], -1)).to("cuda"))
+
+    def __call__(self, l):
+        import torch
+        from synth.sources import time_factors
+        out = []
+        for d, B in zip(self.system.domains, self.B):
+            A = torch.from_numpy(time_factors(d, self.system.dt, [l])).to("cuda")
+            out.append((A @ B).reshape((4,) + tuple(d.dims)).to(self.dtype).contiguous())
+        return out
+
+
 def make_sources(system, steps, dtype):
     """Per-step sources [4][Nx][Ny][Nz] on the GPU from the separable factors."""
     import torch
@@ -65,52 +88,78 @@ def traffic_from_profiles(workload, precision):
     return ent.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(system, target_seconds):
+def cpu_baseline(system, target_seconds, l, gpu_values):
     """The oracle (FP64 direct sum) on a bounded sample of the same workload:
-    grid points of target domain 0 at one step, all 8 source domains."""
+    grid points of every target domain at step l (each update sums over all
+    source domains), timed on the host cores.  The same oracle values give the
+    error of the GPU's step-l output at those points (gpu_values(s, idx) ->
+    [4][len(idx)]), max and RMS over the sampled points divided by the largest
+    |oracle| value, per component."""
     import numpy as np
     import oracle
     from synth.sources import spatial_factors, time_factors
-    l = 200
     t = l * system.dt
-    dom0 = system.domains[0]
-    cache = {}
-    for n, d in enumerate(system.domains):
-        rmin, rmax = oracle.box_distance_range(dom0, d, system.h)
-        j0, j1 = oracle.needed_sample_range(t, rmin, rmax, system.dt, system.c, self_cell=(n == 0))
-        B = spatial_factors(d, system.h, system.c)
-        nt = B.shape[0]
-        js = np.arange(j0, j1 + 1)
-        A = time_factors(d, system.dt, np.concatenate([[0], js]))
-        S = (A @ B.reshape(nt, -1)).reshape(len(js) + 1, 4, -1)
-        cache[n] = (j0, S)
+    B = [spatial_factors(d, system.h, system.c) for d in system.domains]
 
-    def fn(n, a, b):
-        j0, S = cache[n]
-        if a == 0 and b == 0:
-            return S[:1]
-        return S[1 + a - j0: 2 + b - j0]
+    def windows(s):
+        """Source samples every source domain needs for target s at step l."""
+        cache = {}
+        for n, d in enumerate(system.domains):
+            rmin, rmax = oracle.box_distance_range(system.domains[s], d, system.h)
+            j0, j1 = oracle.needed_sample_range(t, rmin, rmax, system.dt, system.c, self_cell=(n == s))
+            nt = B[n].shape[0]
+            js = np.arange(j0, j1 + 1)
+            A = time_factors(d, system.dt, np.concatenate([[0], js]))
+            cache[n] = (j0, (A @ B[n].reshape(nt, -1)).reshape(len(js) + 1, 4, -1))
+
+        def fn(n, a, b):
+            j0, S = cache[n]
+            if a == 0 and b == 0:
+                return S[:1]
+            return S[1 + a - j0: 2 + b - j0]
+        return fn
 
     rng = np.random.default_rng(0)
     c1 = oracle.self_cell_c1()
     from oracle.ref import threads
     cores = threads()
-    npts = 8
-    while True:
-        idx = np.sort(rng.choice(dom0.n_points, size=npts, replace=False))
+    n_dom = len(system.domains)
+    dims = [d.dims for d in system.domains]
+    # rate on a small sample of domain 0, then an equal share of the time per domain
+    fn0 = windows(0)
+    idx = np.sort(rng.choice(system.domains[0].n_points, size=64, replace=False))
+    t0 = time.perf_counter()
+    oracle.potential_points(system, 0, idx, l, fn0, c1=c1)
+    rate = len(idx) / (time.perf_counter() - t0)
+    n_per = int(min(system.domains[0].n_points, max(64, rate * target_seconds / n_dom)))
+    el, npts, got, ref = 0.0, 0, [], []
+    for s in range(n_dom):
+        fn = fn0 if s == 0 else windows(s)
+        nx, ny, nz = dims[s]
+        corners = [(i * ny + j) * nz + k for i in (0, nx - 1) for j in (0, ny - 1) for k in (0, nz - 1)]
+        idx = np.unique(np.concatenate([corners, rng.choice(system.domains[s].n_points, size=n_per,
+                                                             replace=False)]))
         t0 = time.perf_counter()
-        oracle.potential_points(system, 0, idx, l, fn, c1=c1)
-        el = time.perf_counter() - t0
-        if el >= 0.5 * target_seconds or npts >= dom0.n_points:
-            break
-        npts = min(dom0.n_points, int(npts * min(64.0, max(2.0, target_seconds / max(el, 1e-3)))))
-    # one thread on a proportionally smaller sample
-    n1 = max(1, npts // max(cores, 1))
-    idx1 = np.sort(rng.choice(dom0.n_points, size=n1, replace=False))
+        r = oracle.potential_points(system, s, idx, l, fn, c1=c1)
+        el += time.perf_counter() - t0
+        npts += len(idx)
+        ref.append(r.T)
+        got.append(gpu_values(s, idx))
+        del fn
+    g = np.concatenate(got, axis=1)
+    r = np.concatenate(ref, axis=1)
+    scale = np.max(np.abs(r), axis=1)
+    err = {"step": l, "points": npts, "components": ["v", "Ax", "Ay", "Az"],
+           "max": [float(v) for v in np.max(np.abs(g - r), axis=1) / scale],
+           "rms": [float(v) for v in np.sqrt(np.mean((g - r) ** 2, axis=1)) / scale]}
+    # one thread on a proportionally smaller sample of domain 0
+    n1 = max(1, n_per // max(cores, 1))
+    idx1 = np.sort(rng.choice(system.domains[0].n_points, size=n1, replace=False))
+    fn0 = windows(0)
     threads(1)
     try:
         t0 = time.perf_counter()
-        oracle.potential_points(system, 0, idx1, l, fn, c1=c1)
+        oracle.potential_points(system, 0, idx1, l, fn0, c1=c1)
         el1 = time.perf_counter() - t0
     finally:
         threads(cores)
@@ -122,11 +171,14 @@ def cpu_baseline(system, target_seconds):
                 break
     except OSError:
         pass
-    return {"value": npts / el, "unit": "grid-point updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{npts} grid points of domain 0 (all 8 source domains, 2,097,152 source points each "
-                      f"update) at step {l}; {el:.1f} s of oracle time",
-            "seconds": el, "single_thread_value": n1 / el1, "single_thread_sample_points": n1,
-            "cpu_model": model}
+    src_pts = sum(d.n_points for d in system.domains)
+    cpu = {"value": npts / el, "unit": "grid-point updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"{npts} grid points spread over all {n_dom} target domains (corners included; "
+                     f"{src_pts:,} source points each update) at step {l}, the last timed step; "
+                     f"{el:.1f} s of oracle time",
+           "seconds": el, "single_thread_value": n1 / el1, "single_thread_sample_points": n1,
+           "cpu_model": model}
+    return cpu, err
 
 
 def bench_batched(args):
@@ -721,12 +773,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", default=None, choices=["fp32", "fp32_ring_fp16", "fp32_ring_bf16", "fp64"],
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp32_ring_fp16", "fp32_ring_bf16", "fp32_ring_i16", "fp64"],
                     help="default: fp32 (scale, small: fp64 always, sweep, coupled, paper); "
                          "fp32_ring_fp16 for the batched and surrogate workloads")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fill", action="store_true",
+                    help="scale workload: time from step 1 on instead of after the history fill")
     ap.add_argument("--lagsum-unroll", type=int, default=None, choices=[1, 2, 4])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default lag-sum schedule")
     ap.add_argument("--workload", default="scale", choices=["scale", "batched", "surrogate", "small", "sweep", "coupled", "paper"],
@@ -759,9 +813,10 @@ def main():
               "domain with one reduce-scatter per step) is not built", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2311_15429_amd import plan_for_system
-    from synth.sources import config2, config4
+    from synth.sources import config2
 
     if args.workload == "batched":
         return bench_batched(args)
@@ -797,25 +852,35 @@ def main():
 
     W, K = args.warmup, args.steps
     dtype = plan.dtype
-    src = make_sources(system, range(W + K + 1), dtype)
+    # fill the history: run every step up to the deepest ring slot first, so
+    # that the timed steps read real history in every (target, source, lag)
+    # triple (the kernel's bytes and schedule do not depend on it)
+    F = 0 if args.no_fill else max(plan.info(n, n)[3] for n in range(plan.n_dom))
+    gen = SourceGen(system, dtype)
     outs = [torch.empty((4,) + d, dtype=dtype, device="cuda") for d in plan.dims]
+    t0 = time.perf_counter()
+    for l in range(0, F + 1):
+        plan.push_sources(l, gen(l))
+        plan.retarded_step(l, outs)
+    torch.cuda.synchronize()
+    log(f"history fill: steps 0..{F} in {time.perf_counter() - t0:.1f} s")
+    src = [gen(l) for l in range(F + 1, F + W + K + 1)]
     torch.cuda.synchronize()
 
-    plan.push_sources(0, src[0])
-    plan.retarded_step(0, outs)
-    for l in range(1, W + 1):
-        plan.push_sources(l, src[l])
+    for l in range(F + 1, F + W + 1):
+        plan.push_sources(l, src[l - F - 1])
         plan.retarded_step(l, outs)
     torch.cuda.synchronize()
     plan.lagsum_time()
     plan.profile_lagsum(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for l in range(W + 1, W + K + 1):
-        plan.push_sources(l, src[l])
+    for l in range(F + W + 1, F + W + K + 1):
+        plan.push_sources(l, src[l - F - 1])
         plan.retarded_step(l, outs)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    last = F + W + K
     plan.profile_lagsum(False)
     lag_ms, launches = plan.lagsum_time()
     assert launches == K
@@ -852,13 +917,20 @@ def main():
     log(f"read stream: {rs:.0f} GB/s ({rs / HBM_PEAK_GBS:.1%} of peak, unroll {rs_cfg[0]}, "
         f"{rs_cfg[1]} blocks per CU); the lag sum runs at {achieved / rs:.1%} of it")
 
-    cpu = None
+    cpu, err = None, None
     if not args.no_cpu_baseline:
         del src
         torch.cuda.empty_cache()
-        log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(system, args.cpu_seconds)
+        log(f"cpu baseline (oracle) at step {last} ...")
+
+        def gpu_values(s, idx):
+            sel = torch.from_numpy(np.asarray(idx, dtype=np.int64)).to("cuda")
+            return outs[s].reshape(4, -1)[:, sel].double().cpu().numpy()
+
+        cpu, err = cpu_baseline(system, args.cpu_seconds, last, gpu_values)
         log(f"cpu baseline: {cpu['value']:.1f} updates/s on {cpu['cores']} cores")
+        log(f"rel err vs FP64 oracle at step {last} ({err['points']} points): max "
+            + " ".join(f"{v:.2e}" for v in err["max"]) + ", rms " + " ".join(f"{v:.2e}" for v in err["rms"]))
 
     dtype_name = {"fp64": "f64"}.get(args.precision, "f32")
     line = {
@@ -868,6 +940,7 @@ def main():
         "config": {"workload": workload, "precision": args.precision, "sub_domains": 8, "grid": [64, 64, 64],
                    "h_bohr": 0.3, "dt_au": 0.01, "c_au": 137.036, "seed": args.seed,
                    "triples_per_step": st["n_triples"], "ring_reads_per_step": st["n_entries"],
+                   "history_fill_steps": F, "timed_steps": [F + W + 1, last],
                    "green_setup_s": round(t_green, 3),
                    "lagsum_unroll": plan.get_tuning("lagsum_unroll"),
                    "lagsum_persistent": plan.get_tuning("lagsum_persistent"),
@@ -875,6 +948,7 @@ def main():
                    "autotuned": tuned is not None},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "rel_err_vs_fp64_sampled": err,
     }
     print(json.dumps(line), flush=True)
 

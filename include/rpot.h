@@ -69,8 +69,26 @@ typedef enum {
     RP_FP64 = 0,            /* FP64 sources, FFTs, history and accumulation        */
     RP_FP32 = 1,            /* FP32 sources, FFTs, history and accumulation        */
     RP_FP32_RING_FP16 = 2,  /* FP32, history spectra stored as scaled FP16          */
-    RP_FP32_RING_BF16 = 3   /* FP32, history spectra stored as scaled BF16          */
+    RP_FP32_RING_BF16 = 3,  /* FP32, history spectra stored as scaled BF16          */
+    RP_FP32_RING_I16 = 4    /* FP32, history spectra stored as 16-bit integers with
+                               one FP32 scale per (snapshot, tile of 256
+                               frequencies, component): block floating point     */
 } rp_precision;
+
+/*
+ * Reduced-precision history (the ring formats 2-4) keeps FP32 FFTs and FP32
+ * accumulation; only the stored source spectra dS^(k) of the lag sum are
+ * rounded, to 16 bits per real number (half the bytes of the FP32 ring).
+ *   FP16/BF16: each value rounded to FP16 (11 significant bits) or BF16 (8)
+ *     after division by one power-of-two scale per (snapshot, component).
+ *   I16: the ring of every source is cut into tiles of 256 consecutive
+ *     frequencies; per (snapshot, tile, component) the largest |Re|, |Im|
+ *     M maps to 32767 and every value is rounded to the nearest integer
+ *     multiple of M / 32767.  The rounding error of a value is at most
+ *     M / 65534, an absolute bound shared by the tile, so the large,
+ *     low-frequency values that carry the potential keep about 15
+ *     significant bits, where FP16 keeps 11.
+ */
 
 /*
  * Plan the multi-domain evaluation (host only; makes no HIP call).

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "librpot.so")
 RP_OK = 0
 STATUS = {0: "RP_OK", 1: "RP_ERR_ARG", 2: "RP_ERR_GEOMETRY", 3: "RP_ERR_NOMEM",
           4: "RP_ERR_STATE", 5: "RP_ERR_DEVICE", 6: "RP_ERR_UNSUPPORTED"}
-PRECISION = {"fp64": 0, "fp32": 1, "fp32_ring_fp16": 2, "fp32_ring_bf16": 3}
+PRECISION = {"fp64": 0, "fp32": 1, "fp32_ring_fp16": 2, "fp32_ring_bf16": 3, "fp32_ring_i16": 4}
 
 EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_set_green_kernels",
            "rp_push_sources", "rp_retarded_step", "rp_plan_info", "rp_plan_stats",

@@ -109,6 +109,22 @@ struct RingLoad<float, RING_BF16> {
     }
 };
 
+template <>
+struct RingLoad<float, RING_I16> {
+    static constexpr int row_bytes = kTile * 4 * 4;
+    __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *sc, Cx<float> (&x)[4]) {
+        const nu4 v = ld128(r, lane * 16);
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            // (re, im) as sign-extended 16-bit halves, times the tile's scale
+            const float re = float(int(w[mu] << 16) >> 16);
+            const float im = float(int(w[mu]) >> 16);
+            x[mu] = {re * sc[mu], im * sc[mu]};
+        }
+    }
+};
+
 template <typename T>
 __device__ __forceinline__ Cx<T> load_spec(__amdgpu_buffer_rsrc_t r, int lane);
 template <>
@@ -163,7 +179,7 @@ __device__ __forceinline__ uint32_t load_lag(const K2Args &a, const char *ring_t
     constexpr int64_t spec_row = int64_t(kTile) * int64_t(sizeof(Cx<T>));
     if (mk) {
         float sc[4] = {1.f, 1.f, 1.f, 1.f};
-        if (FMT == RING_F16 || FMT == RING_BF16) {
+        if (FMT == RING_F16 || FMT == RING_BF16 || FMT == RING_I16) {
             const float *s4 = a.scales + scale_off + int64_t(slot) * 4;
             sc[0] = s4[0];
             sc[1] = s4[1];
@@ -212,6 +228,7 @@ __device__ __forceinline__ void lagsum_item(const K2Args &a, int item_index) {
         const char *ring_tile = ring + (R.ring_off * esz + int64_t(tile) * depth * ring_row);
         int64_t scale_off = 0;
         if (FMT == RING_F16 || FMT == RING_BF16) scale_off = a.doms[R.n].scale_off;
+        if (FMT == RING_I16) scale_off = a.doms[R.n].scale_off + int64_t(tile) * depth * 4;
         // the ring's newest snapshot (at the head) has lag m_base
         int32_t slot = a.head[R.n] - (m_min - R.m_base);
         if (slot < 0) slot += depth;
@@ -316,6 +333,8 @@ void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, int unroll
         launch_tg<float, RING_F16>(a, tg, unroll, grid_persist, st);
     } else if (ring_fmt == RING_BF16) {
         launch_tg<float, RING_BF16>(a, tg, unroll, grid_persist, st);
+    } else if (ring_fmt == RING_I16) {
+        launch_tg<float, RING_I16>(a, tg, unroll, grid_persist, st);
     } else {
         launch_tg<float, RING_F32>(a, tg, unroll, grid_persist, st);
     }
@@ -334,6 +353,8 @@ int lagsum_blocks_per_cu(int prec64, int ring_fmt, int tg, int unroll) {
                         : unroll == 4 ? RPOT_K2_FN(float, RING_F16, G, 4) : RPOT_K2_FN(float, RING_F16, G, 2);
         else if (ring_fmt == RING_BF16) f = unroll == 1 ? RPOT_K2_FN(float, RING_BF16, G, 1)
                         : unroll == 4 ? RPOT_K2_FN(float, RING_BF16, G, 4) : RPOT_K2_FN(float, RING_BF16, G, 2);
+        else if (ring_fmt == RING_I16) f = unroll == 1 ? RPOT_K2_FN(float, RING_I16, G, 1)
+                        : unroll == 4 ? RPOT_K2_FN(float, RING_I16, G, 4) : RPOT_K2_FN(float, RING_I16, G, 2);
         else f = unroll == 1 ? RPOT_K2_FN(float, RING_F32, G, 1)
                  : unroll == 4 ? RPOT_K2_FN(float, RING_F32, G, 4) : RPOT_K2_FN(float, RING_F32, G, 2);
     };
@@ -371,6 +392,57 @@ __global__ void k_ring_scale(ScaleArgs a) {
 void launch_ring_scale(const ScaleArgs &a, hipStream_t st) {
     if (a.n_jobs == 0) return;
     hipLaunchKernelGGL(k_ring_scale, dim3(a.n_jobs), dim3(64), 0, st, a);
+}
+
+// Block floating point: one block per (tile, job), one lane per frequency.
+__device__ __forceinline__ uint32_t pack_i16(float re, float im) {
+    const int a = int(rintf(fminf(fmaxf(re, -32767.f), 32767.f)));
+    const int b = int(rintf(fminf(fmaxf(im, -32767.f), 32767.f)));
+    return (uint32_t(a) & 0xffffu) | (uint32_t(b) << 16);
+}
+
+__global__ __launch_bounds__(256) void k_quant_i16(QuantArgs a) {
+    const QuantJob &j = a.jobs[blockIdx.y];
+    const int tile = blockIdx.x;
+    if (tile >= j.n_tiles) return;
+    const int lane = threadIdx.x;
+    const int64_t k = int64_t(tile) * kTile + lane;
+    const float4 *row = reinterpret_cast<const float4 *>(j.stage) + int64_t(tile) * (2 * kTile);
+    float4 c01 = {0.f, 0.f, 0.f, 0.f}, c23 = {0.f, 0.f, 0.f, 0.f};
+    if (k < j.C) {
+        c01 = row[lane];            // (re0, im0, re1, im1)
+        c23 = row[kTile + lane];    // (re2, im2, re3, im3)
+    }
+    float m[4] = {fmaxf(fabsf(c01.x), fabsf(c01.y)), fmaxf(fabsf(c01.z), fabsf(c01.w)),
+                  fmaxf(fabsf(c23.x), fabsf(c23.y)), fmaxf(fabsf(c23.z), fabsf(c23.w))};
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        for (int o = 32; o > 0; o >>= 1) m[c] = fmaxf(m[c], __shfl_xor(m[c], o));
+    __shared__ float wmax[kTile / 64][4];
+    if ((lane & 63) == 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) wmax[lane >> 6][c] = m[c];
+    __syncthreads();
+    float inv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float mx = wmax[0][c];
+#pragma unroll
+        for (int w = 1; w < kTile / 64; ++w) mx = fmaxf(mx, wmax[w][c]);
+        m[c] = mx;
+        inv[c] = mx > 0.f ? 32767.f / mx : 0.f;
+    }
+    const int32_t slot = *j.head;
+    const int64_t r = int64_t(tile) * j.depth + slot;
+    const uint4 q = {pack_i16(c01.x * inv[0], c01.y * inv[0]), pack_i16(c01.z * inv[1], c01.w * inv[1]),
+                     pack_i16(c23.x * inv[2], c23.y * inv[2]), pack_i16(c23.z * inv[3], c23.w * inv[3])};
+    reinterpret_cast<uint4 *>(j.ring)[r * kTile + lane] = q;
+    if (lane < 4) j.scales[r * 4 + lane] = m[lane] / 32767.f;
+}
+
+void launch_quant_i16(const QuantArgs &a, hipStream_t st) {
+    if (a.n_jobs == 0 || a.max_tiles == 0) return;
+    hipLaunchKernelGGL(k_quant_i16, dim3(unsigned(a.max_tiles), unsigned(a.n_jobs)), dim3(kTile), 0, st, a);
 }
 
 // acc[k][mu] += g[k] * s[k][mu]  (FP64; static potential)

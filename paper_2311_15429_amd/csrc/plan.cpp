@@ -442,6 +442,16 @@ void plan_tables(rp_plan p) {
     }
 }
 
+// Ring formats with per-snapshot scales (FP16/BF16: [depth][4] floats) or
+// per-snapshot-and-tile scales (I16: [tile][depth][4] floats).
+bool ring_scaled(rp_plan p) {
+    return p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16 || p->ring_fmt == RING_I16;
+}
+size_t scale_bytes(rp_plan p, int depth, int64_t Cpad) {
+    const size_t rows = p->ring_fmt == RING_I16 ? size_t(depth) * size_t(Cpad / kTile) : size_t(depth);
+    return (rows * 4 * sizeof(float) + 15) / 16 * 16;
+}
+
 void plan_layout(rp_plan p) {
     size_t off = 0;
     auto alloc = [&](size_t bytes) {
@@ -479,15 +489,16 @@ void plan_layout(rp_plan p) {
     for (const SystemP &S : p->sys) spec_elems += S.spec_elems;
     p->off_spec = alloc(size_t(spec_elems) * p->spec_csz);
 
-    const bool quant = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
+    const bool quant = ring_scaled(p);
+    const bool zq = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
     size_t max_gtmp = 0, max_C = 0, max_t1 = 0, max_t2 = 0, max_pts = 0;
     for (DomainP &d : p->dom) {
         const SystemP &S = p->sys[d.sys];
         const size_t t1 = size_t(d.N[0]) * d.N[1] * S.Hz * 4;
         const size_t t2 = size_t(d.N[0]) * S.P[1] * S.Hz * 4;
         d.off_ring = alloc(size_t(d.depth) * S.Cpad * 4 * p->ring_esz);
-        d.off_scales = quant ? alloc(size_t(d.depth) * 4 * sizeof(float)) : 0;
-        d.off_zmax = quant ? alloc(size_t(d.zblocks) * 4 * sizeof(float)) : 0;
+        d.off_scales = quant ? alloc(scale_bytes(p, d.depth, S.Cpad)) : 0;
+        d.off_zmax = zq ? alloc(size_t(d.zblocks) * 4 * sizeof(float)) : 0;
         d.off_s0 = alloc(size_t(4) * d.npts * p->tsz);
         d.off_p0 = alloc(size_t(4) * d.npts * p->tsz);
         d.off_acc = alloc(size_t(S.C) * 4 * p->csz);
@@ -504,8 +515,8 @@ void plan_layout(rp_plan p) {
         const DomainP &d = p->dom[v.n];
         const SystemP &S = p->sys[d.sys];
         v.off_ring = alloc(size_t(v.W) * S.Cpad * 4 * p->ring_esz);
-        v.off_scales = quant ? alloc(size_t(v.W) * 4 * sizeof(float)) : 0;
-        v.off_zmax = quant ? alloc(size_t(d.zblocks) * 4 * sizeof(float)) : 0;
+        v.off_scales = quant ? alloc(scale_bytes(p, v.W, S.Cpad)) : 0;
+        v.off_zmax = zq ? alloc(size_t(d.zblocks) * 4 * sizeof(float)) : 0;
         v.off_t1 = alloc(size_t(d.N[0]) * d.N[1] * S.Hz * 4 * p->csz);
         v.off_t2 = alloc(size_t(d.N[0]) * S.P[1] * S.Hz * 4 * p->csz);
         v.off_stage = p->hist_host ? alloc(size_t(4) * d.npts * p->tsz) : 0;
@@ -523,6 +534,18 @@ void plan_layout(rp_plan p) {
         } else {
             d.off_hist = alloc(size_t(d.d1) * snap);
         }
+    }
+    // I16 ring: FP32 staging of the forward transforms of one ingest launch
+    // (one row per frequency tile), quantised from there into the rings
+    p->off_qstage = 0;
+    if (p->ring_fmt == RING_I16) {
+        size_t q = 0;
+        for (const ClassP &K : p->cls) {
+            size_t jobs = K.doms.size();
+            for (int n : K.doms) jobs += p->dom[n].vr.size();
+            q = std::max(q, std::min<size_t>(kMaxJobs, jobs) * size_t(p->sys[p->dom[K.doms[0]].sys].Cpad) * 4 * 8);
+        }
+        p->off_qstage = alloc(q);
     }
     p->off_gtmp = alloc(size_t(kGreenChunk) * max_gtmp * 16);
     p->off_accd = alloc(max_C * 4 * 16);
@@ -843,11 +866,12 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
     }
     for (const DomainP &d : p->dom) {
         launch_fill_zero(p->ws + d.off_ring, size_t(d.depth) * p->sys[d.sys].Cpad * 4 * p->ring_esz, st);
-        if (d.off_scales) launch_fill_zero(p->ws + d.off_scales, (size_t(d.depth) * 16 + 15) / 16 * 16, st);
+        if (d.off_scales) launch_fill_zero(p->ws + d.off_scales, scale_bytes(p, d.depth, p->sys[d.sys].Cpad), st);
     }
     for (const VRingP &v : p->vring) {
         launch_fill_zero(p->ws + v.off_ring, size_t(v.W) * p->sys[p->dom[v.n].sys].Cpad * 4 * p->ring_esz, st);
-        if (v.off_scales) launch_fill_zero(p->ws + v.off_scales, (size_t(v.W) * 16 + 15) / 16 * 16, st);
+        if (v.off_scales)
+            launch_fill_zero(p->ws + v.off_scales, scale_bytes(p, v.W, p->sys[p->dom[v.n].sys].Cpad), st);
     }
     if (p->sur.on) sur_bind(p);
     check_launch();
@@ -958,6 +982,7 @@ int cls_lds(rp_plan p, const ClassP &K) { return K.fft_lds ? K.fft_lds : p->fft_
 
 void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
     const bool quant = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
+    const bool i16 = (p->ring_fmt == RING_I16);
     const int32_t *dhead = p->at<int32_t>(p->off_head);
     for (const ClassP &K : p->cls) {
         // jobs: every domain of the class (newest sources into its ring, and a
@@ -972,14 +997,20 @@ void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
             LinePass y = fwd_y(p, K.N, K.P, K.Hz, p->p64);
             LinePass x = fwd_x(p, K.N, K.P, K.Hz, p->p64);
             y.lds_elems = x.lds_elems = cls_lds(p, K);
-            x.out_fmt = p->ring_fmt;
+            // I16: the x pass writes FP32 rows into the staging area, which
+            // the quantiser then scales per tile into the ring
+            x.out_fmt = i16 ? RING_F32 : p->ring_fmt;
             x.tile_comp = 4;
             // lanes in the order of a ring row: [c/2][k][c%2] (FP32), [c][k]
             // (FP64), [k][c] (FP16/BF16)
-            x.out_group = p->ring_fmt == RING_F32 ? 2 : (p->ring_fmt == RING_F64 ? 1 : 4);
+            x.out_group = x.out_fmt == RING_F32 ? 2 : (x.out_fmt == RING_F64 ? 1 : 4);
             ScaleArgs sa{};
+            QuantArgs qa{};
             z.n_jobs = y.n_jobs = x.n_jobs = cnt;
             sa.n_jobs = quant ? cnt : 0;
+            qa.n_jobs = i16 ? cnt : 0;
+            const int64_t Cpad = p->sys[p->dom[K.doms[0]].sys].Cpad;
+            qa.max_tiles = int(Cpad / kTile);
             for (int j = 0; j < cnt; ++j) {
                 const int code = jobs[j0 + j];
                 const bool split = code < 0;
@@ -1020,6 +1051,21 @@ void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
                 x.jobs[j].slot_stride = int64_t(kTile) * 4;
                 x.jobs[j].tile_stride = int64_t(depth) * kTile * 4;
                 x.jobs[j].qscale = quant ? p->at<float>(off_scales) : nullptr;
+                if (i16) {
+                    float *stage = p->at<float>(p->off_qstage + size_t(j) * size_t(Cpad) * 4 * 8);
+                    x.jobs[j].out = stage;
+                    x.jobs[j].head = nullptr;
+                    x.jobs[j].slot_stride = 0;
+                    x.jobs[j].tile_stride = int64_t(kTile) * 4;
+                    QuantJob &q = qa.jobs[j];
+                    q.stage = stage;
+                    q.ring = p->ws + off_ring;
+                    q.scales = p->at<float>(off_scales);
+                    q.head = dhead + ring_idx;
+                    q.C = p->sys[d.sys].C;
+                    q.depth = depth;
+                    q.n_tiles = int(Cpad / kTile);
+                }
                 if (quant) {
                     sa.jobs[j].zmax = p->at<float>(off_zmax);
                     sa.jobs[j].scales = p->at<float>(off_scales);
@@ -1032,6 +1078,7 @@ void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
             launch_ring_scale(sa, st);
             launch_line_pass(y, p->p64, st);
             launch_line_pass(x, p->p64, st);
+            launch_quant_i16(qa, st);
             check_launch();
         }
     }
@@ -1048,7 +1095,7 @@ K2Args k2_args(rp_plan p, const K2Tables &T, const K2Dev &D, const int32_t *head
     k.doms = p->at<DomDev>(p->off_domdev);
     k.spectra = p->ws + p->off_spec;
     k.ring = p->ws + p->dom[0].off_ring;
-    k.scales = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16) ? p->at<float>(p->dom[0].off_scales) : nullptr;
+    k.scales = ring_scaled(p) ? p->at<float>(p->dom[0].off_scales) : nullptr;
     k.acc = p->ws + p->dom[0].off_acc;
     k.head = head;
     k.counter = p->at<int>(p->off_counter);
@@ -1434,7 +1481,7 @@ rp_status rp_plan_domains(rp_plan *out, int32_t n_dom, const int32_t *dims, cons
         if (!(h > 0) || !std::isfinite(h)) fail(RP_ERR_ARG, "h must be positive and finite");
         if (!(dt > 0) || !std::isfinite(dt)) fail(RP_ERR_ARG, "dt must be positive and finite");
         if (!(c > 0)) fail(RP_ERR_ARG, "c must be positive (or +INFINITY)");
-        if (prec < RP_FP64 || prec > RP_FP32_RING_BF16) fail(RP_ERR_ARG, "unknown precision");
+        if (prec < RP_FP64 || prec > RP_FP32_RING_I16) fail(RP_ERR_ARG, "unknown precision");
         p = new rp_plan_s();
         p->n_dom = n_dom;
         p->h = h;
@@ -1445,7 +1492,8 @@ rp_status rp_plan_domains(rp_plan *out, int32_t n_dom, const int32_t *dims, cons
         p->p64 = (prec == RP_FP64);
         p->ring_fmt = prec == RP_FP64 ? RING_F64
                       : prec == RP_FP32  ? RING_F32
-                      : prec == RP_FP32_RING_FP16 ? RING_F16 : RING_BF16;
+                      : prec == RP_FP32_RING_FP16 ? RING_F16
+                      : prec == RP_FP32_RING_BF16 ? RING_BF16 : RING_I16;
         p->tsz = p->p64 ? 8 : 4;
         p->csz = p->p64 ? 16 : 8;
         p->spec_csz = p->csz;

@@ -203,6 +203,7 @@ struct rp_plan_s {
     std::map<int, size_t> tw64, tw32;   // FFT length -> byte offset of its twiddles
     size_t off_state = 0, off_head = 0, off_prev_head = 0, off_domdev = 0, off_counter = 0;
     size_t off_spec = 0, off_gtmp = 0, off_accd = 0, off_gstat = 0, off_t1d = 0, off_t2d = 0;
+    size_t off_qstage = 0;   // I16 ring: FP32 staging of one ingest launch
     size_t off_s0d = 0, off_p0d = 0;
     size_t ws_bytes = 0;
     char *ws = nullptr;

@@ -47,7 +47,8 @@ constexpr int kFftThreads = 256;
 constexpr int kTile = 256;
 
 // Ring storage formats of the source-spectrum history.
-enum RingFmt : int { RING_F64 = 0, RING_F32 = 1, RING_F16 = 2, RING_BF16 = 3 };
+// RING_I16: 16-bit integers, one scale per (slot, frequency tile, component).
+enum RingFmt : int { RING_F64 = 0, RING_F32 = 1, RING_F16 = 2, RING_BF16 = 3, RING_I16 = 4 };
 
 // ---------------------------------------------------------------------------
 // Generic strided line FFT (complex to complex).  A line is addressed as
@@ -193,7 +194,8 @@ struct K2Item {
 struct DomDev {
     int64_t ring_off;      // element offset (complex) of the domain's ring [tile][slot][kTile][4]
     int64_t acc_off;       // element offset (complex) of the domain's accumulator
-    int64_t scale_off;     // float offset of the ring's scales [depth][4]
+    int64_t scale_off;     // float offset of the ring's scales: [depth][4] (FP16/BF16),
+                           // [tile][depth][4] (I16)
     int32_t depth;
     int32_t pad;
 };
@@ -242,6 +244,28 @@ struct ScaleArgs {
     ScaleJob jobs[kMaxJobs];
 };
 void launch_ring_scale(const ScaleArgs &a, hipStream_t st);
+// Block-floating-point quantisation of freshly transformed source spectra
+// into a 16-bit integer ring (RING_I16).  stage holds the spectrum as FP32
+// rows [tile][c/2][kTile][c%2] (the FP32 ring row order, one row per tile);
+// frequencies k >= C are ignored.  Per tile and component the largest |Re|,
+// |Im| M gives the scale M / 32767; the row [kTile][c] of int16 (re, im)
+// pairs goes to slot *head of the ring [tile][depth][kTile][4], the scales to
+// scales[(tile * depth + slot) * 4 + c].
+struct QuantJob {
+    const float *stage;
+    void *ring;
+    float *scales;
+    const int32_t *head;
+    int64_t C;
+    int32_t depth;
+    int32_t n_tiles;
+};
+struct QuantArgs {
+    int n_jobs;
+    int max_tiles;
+    QuantJob jobs[kMaxJobs];
+};
+void launch_quant_i16(const QuantArgs &a, hipStream_t st);
 void launch_static_mac(void *acc, const void *g, const void *s, int64_t C, hipStream_t st);
 void launch_convert(void *dst, int dst64, const void *src, int src64, int64_t n, hipStream_t st);
 void launch_fill_zero(void *dst, size_t bytes, hipStream_t st);

@@ -19,7 +19,8 @@ class Plan:
 
     dims [n][3] and origins [n][3] (bohr) describe the sub-domain grids, h/dt/c
     the grid step, time step and speed of light (c may be math.inf).
-    precision: "fp64", "fp32", "fp32_ring_fp16" or "fp32_ring_bf16".
+    precision: "fp64", "fp32", "fp32_ring_fp16", "fp32_ring_bf16" or
+    "fp32_ring_i16" (the history ring's storage, rpot.h rp_precision).
     """
 
     def __init__(self, dims, origins, h, dt, c, precision="fp32", system_id=None, stream=None):

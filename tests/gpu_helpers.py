@@ -90,3 +90,42 @@ def cpu_sample_fn(system):
         return (A @ B[n].reshape(nt, -1)).reshape(j1 - j0 + 1, 4, -1)
 
     return fn
+
+
+def pick_points(dims, n_pts, rng):
+    """Flat indices ([4][Nx][Ny][Nz] layout, z fastest) of n_pts grid points of a
+    box: its 8 corners, 6 face centres and 12 edge midpoints, then random
+    points on random faces (a quarter of the rest) and random points inside."""
+    nx, ny, nz = (int(v) for v in dims)
+    hi = (nx - 1, ny - 1, nz - 1)
+    mid = (nx // 2, ny // 2, nz // 2)
+    pts = set()
+    for i in (0, hi[0]):
+        for j in (0, hi[1]):
+            for k in (0, hi[2]):
+                pts.add((i, j, k))
+    for a in range(3):
+        for side in (0, hi[a]):
+            p = list(mid)
+            p[a] = side
+            pts.add(tuple(p))
+    for a in range(3):                      # edges along axis a
+        b, c = [x for x in range(3) if x != a]
+        for vb in (0, hi[b]):
+            for vc in (0, hi[c]):
+                p = [0, 0, 0]
+                p[a], p[b], p[c] = mid[a], vb, vc
+                pts.add(tuple(p))
+    n_face = max(0, (n_pts - len(pts)) // 4)
+    total = nx * ny * nz
+    guard = 0
+    while len(pts) < min(n_pts, total) and guard < 100 * n_pts:
+        guard += 1
+        p = [int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(0, nz))]
+        if n_face > 0:
+            a = int(rng.integers(0, 3))
+            p[a] = 0 if rng.random() < 0.5 else hi[a]
+            n_face -= 1
+        pts.add(tuple(p))
+    idx = np.array(sorted((i * ny + j) * nz + k for i, j, k in pts), dtype=np.int64)
+    return idx[:n_pts] if len(idx) > n_pts else idx

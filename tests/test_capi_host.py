@@ -292,3 +292,31 @@ def test_history_host_tier_plans_host_rings_and_staging():
     assert lib.rp_bind_history_host(r._h, None, 0) == 0         # nothing split: no-op
     for x in (dev, p, q, r):
         x.close()
+
+
+def test_i16_ring_plans_like_fp16_with_tile_scales():
+    """The block-floating-point ring stores 4 bytes per complex value like the
+    FP16 ring: the same ring and lag-sum bytes, a workspace larger only by the
+    per-tile scales and the FP32 staging of one ingest launch."""
+    s = sy.config2(0, n_dom=3, n=16)
+    f16 = Plan(s.dims, s.origins, s.h, s.dt, s.c, precision="fp32_ring_fp16")
+    i16 = Plan(s.dims, s.origins, s.h, s.dt, s.c, precision="fp32_ring_i16")
+    a, b = f16.stats(), i16.stats()
+    for key in ("n_triples", "n_entries", "lagsum_bytes", "ring_bytes", "spectra_bytes"):
+        assert a[key] == b[key], key
+    pad = f16.info(0, 0)[2]
+    cpad = -(-pad[0] * pad[1] * (pad[2] // 2 + 1) // 256) * 256
+    depth = sum(f16.info(n, n)[3] for n in range(3))
+    extra = i16.workspace_bytes - f16.workspace_bytes
+    # per-tile scales ([tile][depth][4] floats instead of [depth][4]) plus
+    # staging of 3 transforms of [Cpad][4] complex FP32, less the z-pass maxima
+    assert 3 * cpad * 32 <= extra <= 3 * cpad * 32 + depth * (cpad // 256) * 16 + 64 * 1024
+    # the precision enum ends at RP_FP32_RING_I16
+    lib = load()
+    h = ctypes.c_void_p()
+    dims = np.ascontiguousarray(s.dims, dtype=np.int32)
+    org = np.ascontiguousarray(s.origins, dtype=np.float64)
+    code = lib.rp_plan_domains(ctypes.byref(h), 3, dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               org.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None,
+                               ctypes.c_double(s.h), ctypes.c_double(s.dt), ctypes.c_double(s.c), 5, None)
+    assert code == 1 and not h.value

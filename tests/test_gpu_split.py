@@ -31,7 +31,7 @@ def _three():
     return sy.System(h, 0.01, sy.C_AU, doms)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_ring_fp16", "fp32_ring_bf16"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_ring_fp16", "fp32_ring_bf16", "fp32_ring_i16"])
 def test_split_history_is_bitwise_identical(precision):
     system = _pair()
     L = 60
@@ -66,7 +66,7 @@ def test_split_history_three_domains_matches_oracle_fp64():
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_ring_fp16"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_ring_fp16", "fp32_ring_i16"])
 def test_host_tier_is_bitwise_identical(precision):
     system = _pair()
     L = 60
@@ -157,7 +157,8 @@ def test_host_tier_needs_a_pinned_buffer():
     p.close()
 
 
-@pytest.mark.parametrize("precision,host", [("fp32", False), ("fp32", True), ("fp32_ring_fp16", True)])
+@pytest.mark.parametrize("precision,host", [("fp32", False), ("fp32", True), ("fp32_ring_fp16", True),
+                                            ("fp32_ring_i16", True)])
 def test_split_history_graph_replay_is_bitwise_identical(precision, host):
     from paper_2311_15429_amd import plan_for_system
     system = _pair()

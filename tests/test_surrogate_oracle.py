@@ -188,3 +188,22 @@ def test_multipole_field_in_the_radiation_zone():
     mp = sr.multipole_field(system, S, 0, 1, L, pts)
     e = np.max(np.abs(mp - ref), axis=1) / np.max(np.abs(ref), axis=1)
     assert e[0] < 8e-5 and np.all(e[1:] < 2e-5), e
+
+
+def test_cubic_weights_reproduce_cubics_and_derivatives():
+    """The cubic Lagrange weights on the samples at -1, 0, 1, 2 reproduce any
+    cubic polynomial and its first three derivatives exactly at every u in
+    [0, 1), and a quartic's value not (the interpolant is cubic)."""
+    rng = np.random.default_rng(3)
+    x = np.array([-1.0, 0.0, 1.0, 2.0])
+    for _ in range(20):
+        a = rng.normal(size=4)                       # a0 + a1 u + a2 u^2 + a3 u^3
+        p = np.polynomial.Polynomial(a)
+        samples = p(x)
+        for u in rng.uniform(0.0, 1.0, size=8):
+            w, d1, d2, d3 = sr._cubic_weights(u)
+            for weights, ref in ((w, p(u)), (d1, p.deriv(1)(u)), (d2, p.deriv(2)(u)), (d3, p.deriv(3)(u))):
+                assert abs(weights @ samples - ref) <= 1e-12 * (1.0 + abs(ref))
+    q = np.polynomial.Polynomial([0.0, 0.0, 0.0, 0.0, 1.0])
+    w, _, _, _ = sr._cubic_weights(0.5)
+    assert abs(w @ q(x) - q(0.5)) > 1e-3
