@@ -128,6 +128,28 @@ rp_status rp_workspace_bytes(rp_plan plan, size_t *bytes);
 rp_status rp_bind_workspace(rp_plan plan, void *dev_ptr, size_t bytes);
 
 /*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: bind the plan
+ * to a fixed array of RP_STATIC_WORKSPACE_BYTES (64 MiB) that the library holds
+ * in device memory, once per device it runs on, until the process ends,
+ * instead of to a caller-allocated workspace.  Otherwise the same as
+ * rp_bind_workspace (uploads the tables, zeroes the history, resets the step
+ * sequence; may synchronise the stream), on the current device.  Allocates
+ * nothing: no hipMalloc, hipFree or other allocating call.
+ * RP_ERR_NOMEM (nothing changed) if rp_workspace_bytes exceeds the array; the
+ * FP64 plan of two 16^3 sub-domains needs 52 MiB.
+ * The array is shared by every plan on its device and keeps the contents the
+ * last plan left: the bind clears what must start at zero.  Binding a plan
+ * takes the array over; from then on the calls that use the workspace of a
+ * plan bound to it before on the same device fail with RP_ERR_STATE until that
+ * plan is bound again (its step sequence then restarts).  Work of two plans on
+ * the array that overlaps in time races.  rp_bind_workspace or
+ * rp_plan_destroy releases the array.
+ */
+#define RP_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+rp_status rp_bind_workspace_static(rp_plan plan);
+
+/*
  * Generate the sampled Green's-function spectra of every (target, source, lag)
  * triple in FP64 (Eq. "retardation space-time sampled green interpolation",
  * with h^3 as the quadrature weight and the exact self-cell integral for the

@@ -12,7 +12,8 @@ STATUS = {0: "RP_OK", 1: "RP_ERR_ARG", 2: "RP_ERR_GEOMETRY", 3: "RP_ERR_NOMEM",
           4: "RP_ERR_STATE", 5: "RP_ERR_DEVICE", 6: "RP_ERR_UNSUPPORTED"}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_ring_fp16": 2, "fp32_ring_bf16": 3, "fp32_ring_i16": 4}
 
-EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_set_green_kernels",
+EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_bind_workspace_static",
+           "rp_set_green_kernels",
            "rp_push_sources", "rp_retarded_step", "rp_plan_info", "rp_plan_stats",
            "rp_profile_lagsum", "rp_lagsum_time", "rp_set_tuning", "rp_get_tuning",
            "rp_autotune", "rp_capture_step", "rp_launch_step", "rp_mlp_create", "rp_mlp_workspace_bytes",
@@ -61,6 +62,7 @@ def load():
     lib.rp_workspace_bytes.argtypes = [vp, P(sz)]
     lib.rp_read_stream.argtypes = [vp, sz, vp, i32, i32, vp]
     lib.rp_bind_workspace.argtypes = [vp, vp, sz]
+    lib.rp_bind_workspace_static.argtypes = [vp]
     lib.rp_set_green_kernels.argtypes = [vp]
     lib.rp_push_sources.argtypes = [vp, i64, P(vp)]
     lib.rp_retarded_step.argtypes = [vp, i64, P(vp)]

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 
 using namespace rpot;
@@ -882,8 +883,74 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
     release_graph(p);
 }
 
-void do_green(rp_plan p) {
+// ---------------------------------------------------------------------------
+// Fixed device workspace for callers that cannot allocate device memory
+// (rp_bind_workspace_static).  The array exists once per device the library
+// runs on and stays until the process ends.  In host code `scratch` names a
+// host-side stand-in: its device address is taken once per device with
+// hipGetSymbolAddress and only that address is used.
+constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
+static_assert(kStaticWorkspaceBytes == RP_STATIC_WORKSPACE_BYTES, "rpot.h and the array disagree");
+static __device__ __align__(256) char scratch[kStaticWorkspaceBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char *g_static_ptr[kMaxDevices] = {};      // device address of the array, per device
+rp_plan g_static_owner[kMaxDevices] = {};  // the plan bound to it last, per device
+}  // namespace
+
+void need_ws(rp_plan p) {
     if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    if (p->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_owner[p->static_dev] != p)
+            fail(RP_ERR_STATE, "the fixed workspace array was bound to another plan since "
+                               "(rp_bind_workspace_static); bind this plan again");
+    }
+}
+
+void release_static(rp_plan p) {
+    if (p->static_dev < 0) return;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_owner[p->static_dev] == p) g_static_owner[p->static_dev] = nullptr;
+    p->static_dev = -1;
+}
+
+void do_bind_static(rp_plan p) {
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(RP_ERR_UNSUPPORTED, "device index beyond the fixed workspace table");
+    if (p->ws_bytes > kStaticWorkspaceBytes) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf,
+                      "the plan needs %zu bytes of workspace; the fixed array holds %zu "
+                      "(use rp_bind_workspace)", p->ws_bytes, kStaticWorkspaceBytes);
+        fail(RP_ERR_NOMEM, buf);
+    }
+    char *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (!g_static_ptr[dev]) {
+            void *a = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !a)
+                fail(RP_ERR_DEVICE, std::string("hipGetSymbolAddress of the fixed workspace: ") + hipGetErrorString(e));
+            g_static_ptr[dev] = static_cast<char *>(a);
+        }
+        ptr = g_static_ptr[dev];
+    }
+    release_static(p);
+    // the bind zeroes everything that must start at zero (history, heads,
+    // step counter); the rest of the array is written before it is read
+    do_bind(p, ptr, kStaticWorkspaceBytes);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    g_static_owner[dev] = p;
+    p->static_dev = dev;
+}
+
+void do_green(rp_plan p) {
+    need_ws(p);
     const int fmt = p->p64 ? RING_F64 : RING_F32;
     for (const SystemP &S : p->sys) {
         for (size_t a = 0; a < S.doms.size(); ++a) {
@@ -1233,7 +1300,7 @@ void check_ptrs(rp_plan p, const void *const *ptrs, const char *what) {
 }
 
 void do_push(rp_plan p, int64_t step, const void *const *src) {
-    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    need_ws(p);
     if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
     check_ptrs(p, src, "src");
     if (tier_active(p) && !p->host_dev) fail(RP_ERR_STATE, "the host history is not bound (rp_bind_history_host)");
@@ -1267,7 +1334,7 @@ void do_push(rp_plan p, int64_t step, const void *const *src) {
 }
 
 void do_step(rp_plan p, int64_t step, void *const *out) {
-    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    need_ws(p);
     check_ptrs(p, out, "out");
     if (step != p->next_step || !p->pushed) {
         char buf[128];
@@ -1301,7 +1368,7 @@ void do_step(rp_plan p, int64_t step, void *const *out) {
 // Record one whole step (ingest + lag sum + inverse + advance) for fixed
 // source and output buffers as a HIP graph.
 void do_capture(rp_plan p, const void *const *src, void *const *out) {
-    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    need_ws(p);
     if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
     check_ptrs(p, src, "src");
     check_ptrs(p, out, "out");
@@ -1331,6 +1398,7 @@ void do_capture(rp_plan p, const void *const *src, void *const *out) {
 }
 
 void do_launch_graph(rp_plan p, int64_t step) {
+    need_ws(p);
     if (!p->graph_exec) fail(RP_ERR_STATE, "no captured step (rp_capture_step)");
     if (step < 1 || step != p->next_step || p->pushed) {
         char buf[128];
@@ -1372,7 +1440,7 @@ void enqueue_inverse_xy(rp_plan p, hipStream_t st, int only_cls = -1) {
 // current ring and spectra; only the accumulator and FFT temporaries are
 // written) and keep the fastest.
 void do_autotune(rp_plan p, int iters, int32_t *best_unroll, int32_t *best_persist, double *best_ms) {
-    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    need_ws(p);
     if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
     if (iters < 1) fail(RP_ERR_ARG, "iters must be >= 1");
     hipStream_t st = p->stream;
@@ -1543,7 +1611,14 @@ rp_status rp_workspace_bytes(rp_plan plan, size_t *bytes) {
 }
 
 rp_status rp_bind_workspace(rp_plan plan, void *dev_ptr, size_t bytes) {
-    return guarded(plan, [&] { do_bind(plan, dev_ptr, bytes); });
+    return guarded(plan, [&] {
+        release_static(plan);
+        do_bind(plan, dev_ptr, bytes);
+    });
+}
+
+rp_status rp_bind_workspace_static(rp_plan plan) {
+    return guarded(plan, [&] { do_bind_static(plan); });
 }
 
 rp_status rp_set_green_kernels(rp_plan plan) {
@@ -1795,6 +1870,7 @@ rp_status rp_surrogate_readmit(rp_plan plan, double factor) {
 
 rp_status rp_plan_destroy(rp_plan plan) {
     if (!plan) return RP_ERR_ARG;
+    release_static(plan);
     for (hipEvent_t ev : plan->events) (void)hipEventDestroy(ev);
     release_graph(plan);
     if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);

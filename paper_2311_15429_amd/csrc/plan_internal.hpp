@@ -212,6 +212,7 @@ struct rp_plan_s {
     std::vector<hipEvent_t> events;   // begin/end pairs of recorded lag-sum launches
     size_t n_recorded = 0;
 
+    int static_dev = -1;     // device whose fixed workspace array the plan is bound to (-1: none)
     bool green_ready = false;
     int64_t next_step = 0;
     bool pushed = false;
@@ -238,6 +239,9 @@ void build_k2(rp_plan p, int sys, const std::vector<K2Member> &members, K2Tables
 void finish_k2(rp_plan p, K2Tables &T);
 void plan_tables(rp_plan p);
 void plan_layout(rp_plan p);
+// A bound workspace, and for a plan on the fixed array of rp_bind_workspace_static
+// that no later bind on its device has taken the array over (RP_ERR_STATE otherwise).
+void need_ws(rp_plan p);
 void plan_stats(rp_plan p);
 void release_graph(rp_plan p);
 void upload_k2(rp_plan p, const K2Tables &T, const K2Dev &D, hipStream_t st);

@@ -251,7 +251,7 @@ float *jfield(rp_plan p, int j) { return p->at<float>(p->sur.off_jF + size_t(j) 
 
 void need_ready(rp_plan p) {
     if (!p->sur.on) fail(RP_ERR_STATE, "surrogate not configured (rp_surrogate_configure)");
-    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    need_ws(p);
     if (p->next_step < 1 || p->pushed) fail(RP_ERR_STATE, "no completed step to evaluate");
 }
 
@@ -586,7 +586,7 @@ void sur_configure(rp_plan p, double far_factor, int n_lags, const int32_t *audi
 void sur_attach(rp_plan p, rp_mlp mlp, const float *in_scale, const float *out_scale) {
     SurrogateH &U = p->sur;
     if (!U.on) fail(RP_ERR_STATE, "surrogate not configured (rp_surrogate_configure)");
-    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    need_ws(p);
     release_graph(p);
     if (!mlp) {
         U.mlp = nullptr;
@@ -609,7 +609,7 @@ void sur_attach(rp_plan p, rp_mlp mlp, const float *in_scale, const float *out_s
 void sur_multipole(rp_plan p, int enable) {
     SurrogateH &U = p->sur;
     if (!U.on) fail(RP_ERR_STATE, "surrogate not configured (rp_surrogate_configure)");
-    if (!p->ws) fail(RP_ERR_STATE, "workspace not bound");
+    need_ws(p);
     if (enable < 0 || enable > 2) fail(RP_ERR_ARG, "enable must be 0, 1 or 2");
     release_graph(p);
     U.multipole = enable;

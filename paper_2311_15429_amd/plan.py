@@ -114,6 +114,12 @@ class Plan:
                 self._h, ctypes.c_void_p(host_history.data_ptr()), ctypes.c_size_t(host_history.numel())))
         return workspace
 
+    def bind_static(self):
+        """Bind the plan to the library's fixed device array
+        (rp_bind_workspace_static): no device memory is allocated."""
+        self._ws = None
+        _lib.check(self._lib, self._h, self._lib.rp_bind_workspace_static(self._h))
+
     def set_green_kernels(self):
         _lib.check(self._lib, self._h, self._lib.rp_set_green_kernels(self._h))
 
