@@ -182,8 +182,153 @@ def cpu_baseline(system, target_seconds, l, gpu_values):
 
 
 def bench_batched(args):
+    """The batched workload as drawn: 64 independent systems of 2-16
+    sub-domains with grids from {32, 48, 64, 96}^3 (FP32 by default).  Its
+    history and spectra (24 TB in FP32) cannot sit on one device at once, so
+    the targets are grouped into units (the targets of one grid shape of one
+    system, halved until the unit's plan fits, each with every domain of its
+    system as a source, its own pad and a split history) and the units are
+    packed into waves of at most the free device memory.  Each wave is one
+    batched plan: bind, Green spectra, step 0, a captured step, W warm-up
+    replays, K timed replays (sources already in device memory), then E eager
+    steps that time the lag sum.  Throughput = every target point x K over the
+    summed timed replays of all waves; one step of the whole workload takes
+    the sum of the waves' step times."""
+    import numpy as np
+    import torch
+    from paper_2311_15429_amd import waves as WV
+    from synth.sources import System, TorchSources, config4
+    precision = args.precision or "fp32"
+    system = config4(args.seed)
+    stream = torch.cuda.current_stream()
+    free, total = torch.cuda.mem_get_info()
+    reserve = 16e9          # sources of the timed steps, outputs, graph buffers, source fields
+    budget = int(0.97 * (free - reserve))
+    if args.wave_gb:
+        budget = min(budget, int(args.wave_gb * 1e9))
+    t0 = time.perf_counter()
+    units = WV.plan_units(system.dims, system.origins, system.system_id, system.h, system.dt, system.c,
+                          precision, budget, split_gap=args.split_gap)
+    waves = WV.pack_waves(units, budget)
+    t_plan = time.perf_counter() - t0
+    lag_total = sum(u.lagsum_bytes for u in units)
+    pts_total = sum(u.points for u in units)
+    log(f"config 4: {len(set(system.system_id))} systems, {len(system.domains)} domains, {pts_total} target points; "
+        f"{len(units)} units in {len(waves)} waves of <= {budget / 1e9:.0f} GB (device free {free / 1e9:.0f} of "
+        f"{total / 1e9:.0f} GB); lag-sum bytes per step {lag_total / 1e12:.2f} TB; host planning {t_plan:.1f} s")
+    W, K, E = args.warmup, args.steps, 1
+    t_timed = t_setup = lag_s = 0.0
+    lag_bytes = 0.0
+    updates = 0
+    ws_total = 0
+    n_launch = 0
+    phases = {"plan": 0.0, "bind": 0.0, "green": 0.0, "sources": 0.0, "capture_warmup": 0.0}
+    # one workspace allocation serves every wave
+    ws_max = max(w.workspace for w in waves) + (1 << 20)
+    workspace = torch.empty(ws_max, dtype=torch.uint8, device="cuda")
+    wall0 = time.perf_counter()
+
+    def lap(key, t):
+        torch.cuda.synchronize()
+        now = time.perf_counter()
+        phases[key] += now - t
+        return now
+
+    for wi, wave in enumerate(waves):
+        ts = t = time.perf_counter()
+        plan, doms, targets = WV.wave_plan(wave, system.dims, system.origins, system.h, system.dt, system.c,
+                                           precision, split_gap=args.split_gap, stream=stream)
+        plan.set_tuning("lagsum_persistent", 1)
+        st = plan.stats()
+        ws_total += plan.workspace_bytes
+        if plan.workspace_bytes + 256 > ws_max:
+            raise RuntimeError("wave workspace above the packing estimate")
+        t = lap("plan", t)
+        plan.bind(workspace=workspace)
+        t = lap("bind", t)
+        plan.set_green_kernels()
+        t = lap("green", t)
+        dt = plan.dtype
+        wsys = System(system.h, system.dt, system.c, [system.domains[g] for g in doms])
+        gen = TorchSources(wsys, "cuda")
+        src = [gen.step(l, dt) for l in range(W + K + E + 1)]
+        del gen
+        t = lap("sources", t)
+        tset = set(targets)
+        outs = [torch.empty((4,) + plan.dims[i], dtype=dt, device="cuda") if i in tset else None
+                for i in range(plan.n_dom)]
+        buf = [torch.empty_like(x) for x in src[0]]
+        plan.push_sources(0, src[0])
+        plan.retarded_step(0, outs)
+        plan.capture_step(buf, outs)
+        for l in range(1, W + 1):
+            torch._foreach_copy_(buf, src[l])
+            plan.launch_step(l)
+        lap("capture_warmup", t)
+        t_setup += time.perf_counter() - ts
+        t1 = time.perf_counter()
+        for l in range(W + 1, W + K + 1):
+            torch._foreach_copy_(buf, src[l])
+            plan.launch_step(l)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        t_timed += el
+        updates += st["points"] * K
+        plan.lagsum_time()
+        plan.profile_lagsum(True)
+        for l in range(W + K + 1, W + K + E + 1):
+            plan.push_sources(l, src[l])
+            plan.retarded_step(l, outs)
+        torch.cuda.synchronize()
+        plan.profile_lagsum(False)
+        ms, n = plan.lagsum_time()
+        lag_s += ms / 1e3
+        lag_bytes += st["lagsum_bytes"] * n
+        n_launch += n
+        if not all(bool(torch.isfinite(o).all()) for o in outs if o is not None):
+            raise RuntimeError(f"non-finite output in wave {wi}")
+        log(f"wave {wi + 1}/{len(waves)}: {len(wave.units)} units, {len(targets)} targets, workspace "
+            f"{plan.workspace_bytes / 1e9:.0f} GB, step {1e3 * el / K:.1f} ms, lag sum {ms / max(n, 1):.1f} ms "
+            f"({st['lagsum_bytes'] / (ms / max(n, 1) / 1e3) / 1e9:.0f} GB/s); setup so far "
+            + ", ".join(f"{k} {v:.0f} s" for k, v in phases.items()))
+        plan.close()
+        del plan, src, outs, buf
+    del workspace
+    torch.cuda.empty_cache()
+    wall = time.perf_counter() - wall0
+    value = updates / t_timed
+    ms_step = 1e3 * t_timed / K
+    achieved = lag_bytes / lag_s / 1e9
+    log(f"config 4 in {len(waves)} waves: {ms_step:.0f} ms per step of the whole workload, {value / 1e6:.2f} M "
+        f"updates/s; lag sum {achieved:.0f} GB/s over {n_launch} launches; wall {wall:.0f} s "
+        f"(setup {t_setup:.0f} s)")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_lagsum",
+            "kernel_ms": round(1e3 * lag_s / max(n_launch, 1), 4),
+            "algorithmic_bytes_per_launch": lag_bytes / max(n_launch, 1),
+            "timed_on": f"{E} eager step(s) per wave after its timed graph replays, all waves"}
+    line = {"metric": METRIC, "value": value, "unit": "grid-point updates/s", "n_gpus": 1, "steps": K,
+            "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "64 independent systems, 2-16 sub-domains each with grids drawn from "
+                                   "{32,48,64,96}^3, h=0.3 bohr, separations 20-300 bohr, dt=0.01, run in waves of "
+                                   "target groups (one graph launch per step per wave)",
+                       "precision": precision, "systems": len(set(system.system_id)),
+                       "domains": len(system.domains), "target_points": pts_total,
+                       "units": len(units), "waves": len(waves), "wave_budget_bytes": budget,
+                       "workspace_bytes_all_waves": ws_total, "lagsum_bytes_per_step": lag_total,
+                       "split_gap": args.split_gap, "steps_per_wave": {"warmup": W, "timed": K, "eager": E},
+                       "setup_s": round(t_setup, 1), "setup_phases_s": {k: round(v, 1) for k, v in phases.items()},
+                       "wall_s": round(wall, 1)},
+            "roofline": roof, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
+def bench_batched_scaled(args):
     """64 independent systems with uneven domain counts and grid sizes in one
-    plan; each step is one replay of the captured graph."""
+    plan (the batched recipe at reduced sizes: 2-8 sub-domains of 16^3, 24^3
+    or 32^3 points, so that every system fits at once); each step is one
+    replay of the captured graph."""
     import torch
     from paper_2311_15429_amd import plan_for_system
     from synth.sources import config4
@@ -243,8 +388,9 @@ def bench_batched(args):
     line = {"metric": METRIC, "value": updates, "unit": "grid-point updates/s", "n_gpus": 1, "steps": K,
             "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "64 independent systems, 2-8 sub-domains each of 16^3/24^3/32^3 points, "
-                                   "h=0.3 bohr, separations 20-300 bohr, dt=0.01, one graph launch per step",
+            "config": {"workload": "batched recipe at reduced sizes (not the drawn shapes): 64 independent "
+                                   "systems, 2-8 sub-domains each of 16^3/24^3/32^3 points, h=0.3 bohr, "
+                                   "separations 20-300 bohr, dt=0.01, one graph launch per step",
                        "precision": precision, "domains": len(system.domains),
                        "triples_per_step": st["n_triples"], "lagsum_bytes": st["lagsum_bytes"],
                        "workspace_bytes": plan.workspace_bytes, "autotune": tuned},
@@ -783,9 +929,11 @@ def main():
                     help="scale workload: time from step 1 on instead of after the history fill")
     ap.add_argument("--lagsum-unroll", type=int, default=None, choices=[1, 2, 4])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default lag-sum schedule")
-    ap.add_argument("--workload", default="scale", choices=["scale", "batched", "surrogate", "small", "sweep", "coupled", "paper"],
+    ap.add_argument("--workload", default="scale",
+                    choices=["scale", "batched", "batched_scaled", "surrogate", "small", "sweep", "coupled", "paper"],
                     help="scale: 8 x 64^3 (the metric's workload); batched: 64 independent systems "
-                         "(2-8 domains of 16^3/24^3/32^3) in one plan, one graph launch per step; "
+                         "(2-16 domains of 32^3-96^3) in waves of target groups; batched_scaled: the batched "
+                         "recipe at 16^3-32^3 and 2-8 domains in one plan, one graph launch per step; "
                          "surrogate: 32 x 48^3 in a 2000-bohr box with the learned far-pair surrogate; "
                          "small: 2 x 16^3 in FP64 beside the oracle's full run; "
                          "sweep: two 32x32x128 domains vs the box enclosing both, over the distance; "
@@ -801,10 +949,14 @@ def main():
                     help="surrogate workload: re-admission factor of fallen-back pairs (0: never)")
     ap.add_argument("--oracle-targets", type=int, default=3)
     ap.add_argument("--oracle-points", type=int, default=24)
+    ap.add_argument("--wave-gb", type=float, default=0.0,
+                    help="batched workload: cap of a wave's workspace in GB (default: the free device memory)")
+    ap.add_argument("--split-gap", type=int, default=8,
+                    help="batched workload: history split gap of the wave plans (lags)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
-    if args.precision is None and args.workload not in ("batched", "surrogate"):
+    if args.precision is None and args.workload not in ("batched", "batched_scaled", "surrogate"):
         args.precision = "fp32"
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -820,6 +972,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "batched_scaled":
+        return bench_batched_scaled(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
     if args.workload == "small":

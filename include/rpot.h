@@ -117,6 +117,27 @@ rp_status rp_plan_domains(rp_plan *out, int32_t n_dom, const int32_t *dims,
                           double h, double dt, double c, rp_precision prec,
                           void *hip_stream);
 
+/*
+ * Evaluate the potentials of a subset of the sub-domains only (host only):
+ * targets [n_targets] are domain indices; every sub-domain stays a source of
+ * the targets of its system, and only the pairs (target <- source) are formed
+ * (windows, Green spectra, history and lag sum).  A system's FFT pad then
+ * covers its largest target plus its largest source, and with a split history
+ * each source keeps only the windows of the pairs into the targets.  This is
+ * how a workload too large for one device runs in pieces (waves of target
+ * groups, each its own plan): the sum over sources of Eq. "multi domain ...
+ * convolution" is per target, so the targets' results do not depend on which
+ * other targets share the plan.  rp_retarded_step (and rp_capture_step) then
+ * write only the targets' outputs; out[n] of a non-target may be NULL.
+ * Before rp_workspace_bytes / rp_bind_workspace (RP_ERR_STATE after).
+ * n_targets <= 0 or targets NULL: every sub-domain is a target (the default).
+ * RP_ERR_ARG on an index out of range or a system left without a target;
+ * RP_ERR_UNSUPPORTED together with the far-pair surrogate.  Re-plans pads,
+ * ring depths, spectra, schedules, shape classes (their tuning is reset) and
+ * the workspace size.
+ */
+rp_status rp_plan_targets(rp_plan plan, const int32_t *targets, int32_t n_targets);
+
 /* Device workspace the plan needs, in bytes (host only). */
 rp_status rp_workspace_bytes(rp_plan plan, size_t *bytes);
 
@@ -304,7 +325,10 @@ const char *rp_mlp_last_error(rp_mlp mlp);
  * spectral ring holds every lag from 0 to the largest m_hi of its pairs, but
  * far pairs read only narrow windows of it.  With min_gap > 0 the windows of
  * a source's pairs are merged where they are less than min_gap lags apart;
- * every window after the first then gets a spectral ring of its own width,
+ * every window after the first then gets a spectral ring of its own width
+ * (and so does the first when it starts min_gap or more lags after lag 0, as
+ * for a source that is not a target, rp_plan_targets: the source's own ring
+ * then keeps lag 0 alone),
  * fed each step by transforming again the sources of `window start` steps
  * ago, which the source keeps in a real-space ring (source precision,
  * window start + 1 slots).  A source is split only where the spectra saved

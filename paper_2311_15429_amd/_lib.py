@@ -12,7 +12,7 @@ STATUS = {0: "RP_OK", 1: "RP_ERR_ARG", 2: "RP_ERR_GEOMETRY", 3: "RP_ERR_NOMEM",
           4: "RP_ERR_STATE", 5: "RP_ERR_DEVICE", 6: "RP_ERR_UNSUPPORTED"}
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_ring_fp16": 2, "fp32_ring_bf16": 3, "fp32_ring_i16": 4}
 
-EXPORTS = ["rp_plan_domains", "rp_workspace_bytes", "rp_bind_workspace", "rp_bind_workspace_static",
+EXPORTS = ["rp_plan_domains", "rp_plan_targets", "rp_workspace_bytes", "rp_bind_workspace", "rp_bind_workspace_static",
            "rp_set_green_kernels",
            "rp_push_sources", "rp_retarded_step", "rp_plan_info", "rp_plan_stats",
            "rp_profile_lagsum", "rp_lagsum_time", "rp_set_tuning", "rp_get_tuning",
@@ -60,6 +60,7 @@ def load():
     lib.rp_plan_domains.argtypes = [P(vp), i32, P(i32), P(ctypes.c_double), P(i32), ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_int, vp]
     lib.rp_workspace_bytes.argtypes = [vp, P(sz)]
+    lib.rp_plan_targets.argtypes = [vp, P(i32), i32]
     lib.rp_read_stream.argtypes = [vp, sz, vp, i32, i32, vp]
     lib.rp_bind_workspace.argtypes = [vp, vp, sz]
     lib.rp_bind_workspace_static.argtypes = [vp]

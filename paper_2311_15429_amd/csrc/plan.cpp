@@ -78,7 +78,54 @@ void pair_distance(const DomainP &s, const DomainP &n, double h, double &rmin, d
     rmax = std::sqrt(mx2);
 }
 
-// Domains, systems, FFT pads, lag windows and shape classes.
+// FFT pads of every system and the shape classes.  A pair (target s <- source
+// n) is a linear convolution of length N_s + N_n - 1 per axis, and only the
+// targets take sources: the pad covers the largest target plus the largest
+// source of the system.
+void plan_pads(rp_plan p) {
+    for (SystemP &S : p->sys) {
+        for (int a = 0; a < 3; ++a) {
+            int mt = 1, mn = 1;
+            for (int i : S.doms) {
+                mn = std::max(mn, p->dom[i].N[a]);
+                if (is_target(p, i)) mt = std::max(mt, p->dom[i].N[a]);
+            }
+            S.P[a] = smooth_even(mt + mn - 1);
+            if (S.P[a] > kMaxPad) fail(RP_ERR_UNSUPPORTED, "FFT pad above 512 points");
+        }
+        S.Hz = S.P[2] / 2 + 1;
+        S.C = int64_t(S.P[0]) * S.P[1] * S.Hz;
+        S.Cpad = (S.C + kTile - 1) / kTile * kTile;
+    }
+
+    // shape classes (same dims and pads) for batched FFT launches
+    p->cls.clear();
+    for (int i = 0; i < p->n_dom; ++i) {
+        const DomainP &d = p->dom[i];
+        const SystemP &S = p->sys[d.sys];
+        int found = -1;
+        for (size_t c = 0; c < p->cls.size(); ++c) {
+            const ClassP &K = p->cls[c];
+            if (std::equal(K.N, K.N + 3, d.N) && std::equal(K.P, K.P + 3, S.P)) found = int(c);
+        }
+        if (found < 0) {
+            ClassP K{};
+            std::copy(d.N, d.N + 3, K.N);
+            std::copy(S.P, S.P + 3, K.P);
+            K.Hz = S.Hz;
+            K.C = S.C;
+            p->cls.push_back(K);
+            found = int(p->cls.size()) - 1;
+        }
+        p->cls[found].doms.push_back(i);
+        if (is_target(p, i)) p->cls[found].tdoms.push_back(i);
+        p->dom[i].cls = found;
+        const int lpb = zfwd_lines_per_block(S.P[2], p->p64);
+        p->dom[i].zblocks = (4 * ((d.N[0] * d.N[1] + 1) / 2) + lpb - 1) / lpb;
+    }
+}
+
+// Domains, systems, lag windows, FFT pads and shape classes.
 void plan_geometry(rp_plan p, const int32_t *dims, const double *origins, const int32_t *system_id) {
     const int nd = p->n_dom;
     p->dom.resize(nd);
@@ -100,19 +147,6 @@ void plan_geometry(rp_plan p, const int32_t *dims, const double *origins, const 
         }
         d.sys = it->second;
         p->sys[d.sys].doms.push_back(i);
-    }
-
-    // pads: every pair of a system is a linear convolution of length N_s + N_n - 1
-    for (SystemP &S : p->sys) {
-        for (int a = 0; a < 3; ++a) {
-            int mx = 1;
-            for (int i : S.doms) mx = std::max(mx, p->dom[i].N[a]);
-            S.P[a] = smooth_even(2 * mx - 1);
-            if (S.P[a] > kMaxPad) fail(RP_ERR_UNSUPPORTED, "FFT pad above 512 points");
-        }
-        S.Hz = S.P[2] / 2 + 1;
-        S.C = int64_t(S.P[0]) * S.P[1] * S.Hz;
-        S.Cpad = (S.C + kTile - 1) / kTile * kTile;
     }
 
     // windows
@@ -143,34 +177,13 @@ void plan_geometry(rp_plan p, const int32_t *dims, const double *origins, const 
         }
     }
 
-    // shape classes (same dims and pads) for batched FFT launches
-    for (int i = 0; i < nd; ++i) {
-        const DomainP &d = p->dom[i];
-        const SystemP &S = p->sys[d.sys];
-        int found = -1;
-        for (size_t c = 0; c < p->cls.size(); ++c) {
-            const ClassP &K = p->cls[c];
-            if (std::equal(K.N, K.N + 3, d.N) && std::equal(K.P, K.P + 3, S.P)) found = int(c);
-        }
-        if (found < 0) {
-            ClassP K{};
-            std::copy(d.N, d.N + 3, K.N);
-            std::copy(S.P, S.P + 3, K.P);
-            K.Hz = S.Hz;
-            K.C = S.C;
-            p->cls.push_back(K);
-            found = int(p->cls.size()) - 1;
-        }
-        p->cls[found].doms.push_back(i);
-        p->dom[i].cls = found;
-        const int lpb = zfwd_lines_per_block(S.P[2], p->p64);
-        p->dom[i].zblocks = (4 * ((d.N[0] * d.N[1] + 1) / 2) + lpb - 1) / lpb;
-    }
+    plan_pads(p);
 }
 
 // A pair whose plain lag sum may run: every near pair, and a far pair whose
 // source keeps its history (it can be judged and can fall back).
 bool keeps_history(rp_plan p, int s, int n) {
+    if (!is_target(p, s)) return false;
     const SurrogateH &S = p->sur;
     if (!S.on) return true;
     const int f = S.far_index[size_t(s) * p->n_dom + n];
@@ -179,6 +192,7 @@ bool keeps_history(rp_plan p, int s, int n) {
 
 // A pair summed by the plain lag sum at every step.
 bool plain_pair(rp_plan p, int s, int n) {
+    if (!is_target(p, s)) return false;
     const SurrogateH &S = p->sur;
     if (!S.on) return true;
     const int f = S.far_index[size_t(s) * p->n_dom + n];
@@ -308,6 +322,7 @@ void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int)) {
     for (size_t si = 0; si < p->sys.size(); ++si) {
         std::vector<K2Member> members;
         for (int s : p->sys[si].doms) {
+            if (!is_target(p, s)) continue;
             K2Member M{s, s, {}};
             for (int n : p->sys[si].doms)
                 if (pred(p, s, n)) M.srcs.push_back(n);
@@ -336,9 +351,13 @@ void plan_tables(rp_plan p) {
         d.d1 = 0;
         d.t1_idx = -1;
         if (p->split_gap <= 0 || iv.empty()) continue;
-        // merge the pairs' windows; a gap of split_gap lags or more starts a new ring
+        // merge the pairs' windows; a gap of split_gap lags or more starts a new
+        // ring.  The main ring holds lag 0 (the ingest writes there); when the
+        // first window starts split_gap or more lags later (a source that is
+        // not a target reaches only other domains), it keeps lag 0 alone
         std::sort(iv.begin(), iv.end());
         std::vector<std::pair<int, int>> win{{0, iv[0].second}};
+        if (iv[0].first - 1 >= p->split_gap) win = {{0, 0}, iv[0]};
         for (size_t i = 1; i < iv.size(); ++i) {
             if (iv[i].first - win.back().second - 1 >= p->split_gap) win.push_back(iv[i]);
             else win.back().second = std::max(win.back().second, iv[i].second);
@@ -613,7 +632,8 @@ void plan_stats(rp_plan p) {
                 if (plain_pair(p, s, n)) st.n_triples += p->pr(s, n).m_hi - p->pr(s, n).m_lo + 1;
     for (const SystemP &S : p->sys) st.n_spectra += S.n_spec;
     st.n_entries = int64_t(p->k2.entries.size());
-    for (const DomainP &d : p->dom) st.points += d.npts;
+    for (int n = 0; n < p->n_dom; ++n)
+        if (is_target(p, n)) st.points += p->dom[n].npts;
     st.lagsum_bytes = k2_bytes(p, p->k2);
     for (const DomainP &d : p->dom) st.ring_bytes += double(d.depth) * p->sys[d.sys].Cpad * 4 * p->ring_esz;
     for (const VRingP &v : p->vring) st.ring_bytes += double(v.W) * p->sys[p->dom[v.n].sys].Cpad * 4 * p->ring_esz;
@@ -1005,6 +1025,7 @@ void do_static(rp_plan p, const void *const *src) {
             check_launch();
         }
         for (int s : S.doms) {
+            if (!is_target(p, s)) continue;
             const DomainP &d = p->dom[s];
             launch_fill_zero(p->ws + p->off_accd, size_t(S.C) * 4 * 16, st);
             for (int n : S.doms) {
@@ -1186,8 +1207,8 @@ void enqueue_lagsum(rp_plan p, hipStream_t st, int unroll, int persist) {
 // domain, add P(0), write the caller's output; then advance the step.
 void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st) {
     for (const ClassP &K : p->cls) {
-        for (size_t j0 = 0; j0 < K.doms.size(); j0 += kMaxJobs) {
-            const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
+        for (size_t j0 = 0; j0 < K.tdoms.size(); j0 += kMaxJobs) {
+            const int cnt = int(std::min<size_t>(kMaxJobs, K.tdoms.size() - j0));
             LinePass x = inv_x(p, K.N, K.P, K.Hz, p->p64);
             LinePass y = inv_y(p, K.N, K.P, K.Hz, p->p64);
             x.lds_elems = y.lds_elems = cls_lds(p, K);
@@ -1201,7 +1222,7 @@ void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st) {
             zi.rp = make_radix(K.P[2]);
             x.n_jobs = y.n_jobs = zi.n_jobs = cnt;
             for (int j = 0; j < cnt; ++j) {
-                const int s = K.doms[j0 + j];
+                const int s = K.tdoms[j0 + j];
                 const DomainP &d = p->dom[s];
                 x.jobs[j].in = p->ws + d.off_acc;
                 x.jobs[j].out = p->ws + d.off_t2;
@@ -1293,10 +1314,11 @@ void tier_join(rp_plan p, hipStream_t st) {
     p->tier_open = false;
 }
 
-void check_ptrs(rp_plan p, const void *const *ptrs, const char *what) {
+// Every domain's pointer (targets_only: every target's; the others may be null).
+void check_ptrs(rp_plan p, const void *const *ptrs, const char *what, bool targets_only = false) {
     if (!ptrs) fail(RP_ERR_ARG, std::string(what) + " is null");
     for (int n = 0; n < p->n_dom; ++n)
-        if (!ptrs[n]) fail(RP_ERR_ARG, std::string("a ") + what + " pointer is null");
+        if (!ptrs[n] && (!targets_only || is_target(p, n))) fail(RP_ERR_ARG, std::string("a ") + what + " pointer is null");
 }
 
 void do_push(rp_plan p, int64_t step, const void *const *src) {
@@ -1335,7 +1357,7 @@ void do_push(rp_plan p, int64_t step, const void *const *src) {
 
 void do_step(rp_plan p, int64_t step, void *const *out) {
     need_ws(p);
-    check_ptrs(p, out, "out");
+    check_ptrs(p, out, "out", true);
     if (step != p->next_step || !p->pushed) {
         char buf[128];
         std::snprintf(buf, sizeof buf, "rp_retarded_step(%lld) out of order (expected step %lld%s)",
@@ -1371,7 +1393,7 @@ void do_capture(rp_plan p, const void *const *src, void *const *out) {
     need_ws(p);
     if (!p->green_ready) fail(RP_ERR_STATE, "rp_set_green_kernels has not been called");
     check_ptrs(p, src, "src");
-    check_ptrs(p, out, "out");
+    check_ptrs(p, out, "out", true);
     if (p->tier_open) fail(RP_ERR_STATE, "capture a step after rp_retarded_step, not between push and step");
     if (tier_active(p) && !p->host_dev) fail(RP_ERR_STATE, "the host history is not bound (rp_bind_history_host)");
     release_graph(p);
@@ -1416,14 +1438,14 @@ void enqueue_inverse_xy(rp_plan p, hipStream_t st, int only_cls = -1) {
     for (size_t ci = 0; ci < p->cls.size(); ++ci) {
         if (only_cls >= 0 && int(ci) != only_cls) continue;
         const ClassP &K = p->cls[ci];
-        for (size_t j0 = 0; j0 < K.doms.size(); j0 += kMaxJobs) {
-            const int cnt = int(std::min<size_t>(kMaxJobs, K.doms.size() - j0));
+        for (size_t j0 = 0; j0 < K.tdoms.size(); j0 += kMaxJobs) {
+            const int cnt = int(std::min<size_t>(kMaxJobs, K.tdoms.size() - j0));
             LinePass x = inv_x(p, K.N, K.P, K.Hz, p->p64);
             LinePass y = inv_y(p, K.N, K.P, K.Hz, p->p64);
             x.lds_elems = y.lds_elems = cls_lds(p, K);
             x.n_jobs = y.n_jobs = cnt;
             for (int j = 0; j < cnt; ++j) {
-                const DomainP &d = p->dom[K.doms[j0 + j]];
+                const DomainP &d = p->dom[K.tdoms[j0 + j]];
                 x.jobs[j].in = p->ws + d.off_acc;
                 x.jobs[j].out = p->ws + d.off_t2;
                 y.jobs[j].in = p->ws + d.off_t2;
@@ -1475,6 +1497,7 @@ void do_autotune(rp_plan p, int iters, int32_t *best_unroll, int32_t *best_persi
     try {
         for (size_t ci = 0; ci < p->cls.size(); ++ci) {
             ClassP &K = p->cls[ci];
+            if (K.tdoms.empty()) continue;   // no inverse transforms to time
             double bt = 1e300;
             int bf = K.fft_lds;
             for (int e : {2048, 4096, 6144}) {
@@ -1638,8 +1661,9 @@ rp_status rp_plan_info(rp_plan plan, int32_t s, int32_t n, int32_t *m_lo, int32_
     return guarded(plan, [&] {
         if (s < 0 || n < 0 || s >= plan->n_dom || n >= plan->n_dom) fail(RP_ERR_ARG, "domain index out of range");
         const PairP &q = plan->pr(s, n);
-        if (m_lo) *m_lo = q.m_lo;
-        if (m_hi) *m_hi = q.m_hi;
+        const bool formed = is_target(plan, s);
+        if (m_lo) *m_lo = formed ? q.m_lo : -1;
+        if (m_hi) *m_hi = formed ? q.m_hi : -1;
         if (pad)
             for (int a = 0; a < 3; ++a) pad[a] = plan->sys[plan->dom[s].sys].P[a];
         if (depth) *depth = plan->dom[n].depth;
@@ -1761,6 +1785,32 @@ rp_status rp_launch_step(rp_plan plan, int64_t step) {
 rp_status rp_surrogate_configure(rp_plan plan, double far_factor, int32_t n_lags, const int32_t *audit,
                                  int32_t n_audit) {
     return guarded(plan, [&] { sur_configure(plan, far_factor, n_lags, audit, n_audit); });
+}
+
+rp_status rp_plan_targets(rp_plan plan, const int32_t *targets, int32_t n_targets) {
+    return guarded(plan, [&] {
+        if (plan->ws) fail(RP_ERR_STATE, "choose the targets before rp_bind_workspace");
+        if (plan->sur.on) fail(RP_ERR_UNSUPPORTED, "the surrogate and a target subset do not combine");
+        std::vector<char> t;
+        if (targets && n_targets > 0) {
+            t.assign(size_t(plan->n_dom), 0);
+            for (int i = 0; i < n_targets; ++i) {
+                if (targets[i] < 0 || targets[i] >= plan->n_dom) fail(RP_ERR_ARG, "target index out of range");
+                t[size_t(targets[i])] = 1;
+            }
+            for (size_t si = 0; si < plan->sys.size(); ++si) {
+                bool any = false;
+                for (int n : plan->sys[si].doms) any = any || t[size_t(n)];
+                if (!any) fail(RP_ERR_ARG, "every system needs at least one target");
+            }
+        }
+        plan->target = std::move(t);
+        plan_pads(plan);
+        plan_tables(plan);
+        plan_layout(plan);
+        plan_stats(plan);
+        release_graph(plan);
+    });
 }
 
 rp_status rp_history_split(rp_plan plan, int32_t min_gap) {

@@ -86,6 +86,7 @@ struct ClassP {
     int Hz;
     int64_t C;
     std::vector<int> doms;
+    std::vector<int> tdoms;  // the targets among doms (potentials evaluated)
     int fft_lds = 0;         // this class's line-pass tile (0: the plan's)
 };
 
@@ -213,6 +214,7 @@ struct rp_plan_s {
     size_t n_recorded = 0;
 
     int static_dev = -1;     // device whose fixed workspace array the plan is bound to (-1: none)
+    std::vector<char> target;   // per domain: potentials evaluated (empty: every domain)
     bool green_ready = false;
     int64_t next_step = 0;
     bool pushed = false;
@@ -239,6 +241,8 @@ void build_k2(rp_plan p, int sys, const std::vector<K2Member> &members, K2Tables
 void finish_k2(rp_plan p, K2Tables &T);
 void plan_tables(rp_plan p);
 void plan_layout(rp_plan p);
+// Domain s is a target: its potential is evaluated (rp_plan_targets).
+inline bool is_target(rp_plan p, int s) { return p->target.empty() || p->target[size_t(s)] != 0; }
 // A bound workspace, and for a plan on the fixed array of rp_bind_workspace_static
 // that no later bind on its device has taken the array over (RP_ERR_STATE otherwise).
 void need_ws(rp_plan p);

@@ -53,6 +53,7 @@ class Plan:
             float(h), float(dt), float(c), _lib.PRECISION[precision], stream_ptr)
         _lib.check(self._lib, None, code)
         self._h = handle
+        self.targets = list(range(self.n_dom))
         self._ws = None
         self._host_hist = None
 
@@ -123,10 +124,22 @@ class Plan:
     def set_green_kernels(self):
         _lib.check(self._lib, self._h, self._lib.rp_set_green_kernels(self._h))
 
-    def _ptrs(self, tensors):
+    def _ptrs(self, tensors, allow_none=False):
+        """Device pointers of one tensor per domain (allow_none: None for a
+        domain that is not a target gives a null pointer)."""
         import torch
         if len(tensors) != self.n_dom:
             raise ValueError(f"expected {self.n_dom} tensors")
+        if allow_none and any(t is None for t in tensors):
+            for n, t in enumerate(tensors):
+                if t is None and n in self.targets:
+                    raise ValueError(f"domain {n} is a target and needs an output")
+            live = [(t, d) for t, d in zip(tensors, self.dims) if t is not None]
+            for t, d in live:
+                if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != self.dtype \
+                        or tuple(t.shape) != (4, *d) or not t.is_contiguous():
+                    raise ValueError(f"output tensors must be contiguous {self.dtype} CUDA tensors [4][Nx][Ny][Nz]")
+            return (ctypes.c_void_p * self.n_dom)(*[t.data_ptr() if t is not None else None for t in tensors])
         for t, d in zip(tensors, self.dims):
             if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
                 raise ValueError("tensors must be CUDA tensors")
@@ -141,7 +154,7 @@ class Plan:
         _lib.check(self._lib, self._h, self._lib.rp_push_sources(self._h, int(step), arr))
 
     def retarded_step(self, step, outputs):
-        arr = self._ptrs(outputs)
+        arr = self._ptrs(outputs, allow_none=True)
         _lib.check(self._lib, self._h, self._lib.rp_retarded_step(self._h, int(step), arr))
 
     def profile_lagsum(self, enable=True):
@@ -232,7 +245,7 @@ class Plan:
     def capture_step(self, sources, outputs):
         """Record one whole step for these fixed buffers as a HIP graph."""
         s_arr = self._ptrs(sources)
-        o_arr = self._ptrs(outputs)
+        o_arr = self._ptrs(outputs, allow_none=True)
         self._graph_bufs = (list(sources), list(outputs))
         _lib.check(self._lib, self._h, self._lib.rp_capture_step(self._h, s_arr, o_arr))
 
@@ -241,6 +254,14 @@ class Plan:
         _lib.check(self._lib, self._h, self._lib.rp_launch_step(self._h, int(step)))
 
     # -- far-pair surrogate --------------------------------------------------
+    def set_targets(self, targets=None):
+        """Evaluate only the sub-domains `targets` (indices; every sub-domain
+        stays a source).  None or empty: every sub-domain.  Call before bind()."""
+        t = np.ascontiguousarray(list(targets or []), dtype=np.int32)
+        ptr = t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if t.size else None
+        _lib.check(self._lib, self._h, self._lib.rp_plan_targets(self._h, ptr, int(t.size)))
+        self.targets = [int(v) for v in t] if t.size else list(range(self.n_dom))
+
     def history_split(self, min_gap):
         """Split each source's history at lag gaps of at least min_gap lags
         (later windows in spectral rings of their own, fed from a real-space

@@ -367,3 +367,91 @@ def paper_pair(d: float, seed: int = 0, n_pairs: int = 8) -> System:
         _random_pairs(rng, dm, h, n_pairs)
     return System(h, 0.04134, C_AU, doms, name=f"paper pair d={d:g}")
 
+
+
+# ----------------------------------------------------------------------------
+# The same sources evaluated with torch (any device), in compact form
+# ----------------------------------------------------------------------------
+
+class TorchSources:
+    """Sources of the domains of `system` (or of `domains`, a list of indices)
+    evaluated with torch on `device` in FP64, from the same seeded charges as
+    spatial_factors / time_factors.  Each charge contributes its density
+    field to component 0 and, for a pair, its tube field times (c+ - c-)/c to
+    components 1-3, so a domain keeps one or two fields per charge instead of
+    four components per term.  step(l, dtype) -> list of [4][Nx][Ny][Nz]."""
+
+    def __init__(self, system: System, device, domains=None):
+        import torch
+        self.torch = torch
+        self.system = system
+        self.device = torch.device(device)
+        self.doms = list(range(len(system.domains))) if domains is None else list(domains)
+        self.fields = {}
+        for i in self.doms:
+            self.fields[i] = self._fields(system.domains[i])
+
+    def _fields(self, dom: Domain):
+        torch = self.torch
+        h, c = self.system.h, self.system.c
+        nx, ny, nz = dom.dims
+        f64 = dict(dtype=torch.float64, device=self.device)
+        ax = [dom.origin[a] + h * torch.arange(n, **f64) for a, n in enumerate((nx, ny, nz))]
+        X, Y, Z = torch.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
+        pts = torch.stack([X.reshape(-1), Y.reshape(-1), Z.reshape(-1)], dim=1)
+
+        def gauss(centre, s):
+            d2 = torch.sum((pts - torch.as_tensor(centre, **f64)[None, :]) ** 2, dim=1)
+            return (math.pi * s * s) ** -1.5 * torch.exp(-d2 / (s * s))
+
+        rho, cur, dvec = [], [], []
+        for ch in dom.charges:
+            if ch.kind == "pair":
+                rho.append(gauss(ch.cp, ch.s) - gauss(ch.cm, ch.s))
+                d = np.asarray(ch.cp, dtype=np.float64) - np.asarray(ch.cm, dtype=np.float64)
+                L = float(np.linalg.norm(d))
+                if L == 0.0 or not math.isfinite(c):
+                    cur.append(torch.zeros(len(pts), **f64))
+                else:
+                    dh = torch.as_tensor(d / L, **f64)
+                    rel = pts - torch.as_tensor(ch.cm, **f64)[None, :]
+                    xi = rel @ dh
+                    rp2 = torch.clamp(torch.sum(rel * rel, dim=1) - xi * xi, min=0.0)
+                    s = ch.s
+                    cur.append((math.pi * s * s) ** -1.5 * torch.exp(-rp2 / (s * s))
+                               * (math.sqrt(math.pi) * s / (2.0 * L))
+                               * (torch.special.erf(xi / s) - torch.special.erf((xi - L) / s)))
+                dvec.append(d / c if math.isfinite(c) else np.zeros(3))
+            elif ch.kind == "single":
+                rho.append(gauss(ch.cp, ch.s))
+                cur.append(None)
+                dvec.append(np.zeros(3))
+            else:
+                raise ValueError(ch.kind)
+        n = len(pts)
+        R = torch.stack(rho) if rho else torch.zeros((0, n), **f64)
+        pairs = [i for i, cf in enumerate(cur) if cf is not None]
+        J = torch.stack([cur[i] for i in pairs]) if pairs else torch.zeros((0, n), **f64)
+        D = torch.as_tensor(np.array([dvec[i] for i in pairs]).reshape(-1, 3), **f64)
+        return R, J, D, pairs
+
+    def step(self, l, dtype=None):
+        torch = self.torch
+        out = []
+        for i in self.doms:
+            dom = self.system.domains[i]
+            R, J, D, pairs = self.fields[i]
+            j = np.array([l], dtype=np.int64)
+            t = j.astype(np.float64) * self.system.dt
+            q = np.array([_profile(ch.profile, t, j)[0][0] for ch in dom.charges])
+            qd = np.array([_profile(ch.profile, t, j)[1][0] for ch in dom.charges])
+            S = torch.empty((4, R.shape[1]), dtype=torch.float64, device=self.device)
+            S[0] = torch.as_tensor(q, dtype=torch.float64, device=self.device) @ R if len(q) else 0.0
+            if pairs:
+                w = torch.as_tensor(qd[pairs], dtype=torch.float64, device=self.device)[:, None] * D   # [pairs][3]
+                S[1:] = w.T @ J
+            else:
+                S[1:] = 0.0
+            S = S.reshape((4,) + tuple(dom.dims))
+            out.append(S if dtype is None else S.to(dtype).contiguous())
+        return out

@@ -68,3 +68,19 @@ def test_wire_pair_and_enclosing_domain():
         assert np.allclose(pts[b].reshape(-1, 3), sy.grid_points(dm, s.h))
     with pytest.raises(ValueError):
         sy.wire_pair(W=8, L=24, d=15)
+
+
+def test_torch_sources_equal_the_separable_samples():
+    """The torch evaluation of the sources (compact fields) gives the samples
+    A[l] @ B of spatial_factors / time_factors."""
+    torch = pytest.importorskip("torch")
+    s = sy.config5(3, n_dom=3, n=9, box=300.0)
+    gen = sy.TorchSources(s, "cpu")
+    S = sy.sample_sources(s, [0, 7, 40])
+    for k, l in enumerate([0, 7, 40]):
+        got = gen.step(l)
+        for n in range(3):
+            ref = S[n][k]
+            g = got[n].numpy().reshape(4, -1)
+            for c in range(4):             # each component against its own scale
+                assert np.max(np.abs(g[c] - ref[c])) <= 1e-13 * np.max(np.abs(ref[c])), (l, n, c)
