@@ -181,42 +181,16 @@ def cpu_baseline(system, target_seconds, l, gpu_values):
     return cpu, err
 
 
-def bench_batched(args):
-    """The batched workload as drawn: 64 independent systems of 2-16
-    sub-domains with grids from {32, 48, 64, 96}^3 (FP32 by default).  Its
-    history and spectra (24 TB in FP32) cannot sit on one device at once, so
-    the targets are grouped into units (the targets of one grid shape of one
-    system, halved until the unit's plan fits, each with every domain of its
-    system as a source, its own pad and a split history) and the units are
-    packed into waves of at most the free device memory.  Each wave is one
-    batched plan: bind, Green spectra, step 0, a captured step, W warm-up
-    replays, K timed replays (sources already in device memory), then E eager
-    steps that time the lag sum.  Throughput = every target point x K over the
-    summed timed replays of all waves; one step of the whole workload takes
-    the sum of the waves' step times."""
-    import numpy as np
+def run_waves(system, precision, waves, W, K, E, split_gap, label="wave"):
+    """Run every wave of target groups (waves.py) of `system`: per wave one
+    batched plan (pads, split history), bound to one shared workspace, Green
+    spectra, step 0, a captured step, W warm-up replays, K timed replays
+    (sources in device memory before the timed region), E eager steps timing
+    the lag sum.  Returns the summed timings and counts."""
     import torch
     from paper_2311_15429_amd import waves as WV
-    from synth.sources import System, TorchSources, config4
-    precision = args.precision or "fp32"
-    system = config4(args.seed)
+    from synth.sources import System, TorchSources
     stream = torch.cuda.current_stream()
-    free, total = torch.cuda.mem_get_info()
-    reserve = 16e9          # sources of the timed steps, outputs, graph buffers, source fields
-    budget = int(0.97 * (free - reserve))
-    if args.wave_gb:
-        budget = min(budget, int(args.wave_gb * 1e9))
-    t0 = time.perf_counter()
-    units = WV.plan_units(system.dims, system.origins, system.system_id, system.h, system.dt, system.c,
-                          precision, budget, split_gap=args.split_gap)
-    waves = WV.pack_waves(units, budget)
-    t_plan = time.perf_counter() - t0
-    lag_total = sum(u.lagsum_bytes for u in units)
-    pts_total = sum(u.points for u in units)
-    log(f"config 4: {len(set(system.system_id))} systems, {len(system.domains)} domains, {pts_total} target points; "
-        f"{len(units)} units in {len(waves)} waves of <= {budget / 1e9:.0f} GB (device free {free / 1e9:.0f} of "
-        f"{total / 1e9:.0f} GB); lag-sum bytes per step {lag_total / 1e12:.2f} TB; host planning {t_plan:.1f} s")
-    W, K, E = args.warmup, args.steps, 1
     t_timed = t_setup = lag_s = 0.0
     lag_bytes = 0.0
     updates = 0
@@ -237,7 +211,7 @@ def bench_batched(args):
     for wi, wave in enumerate(waves):
         ts = t = time.perf_counter()
         plan, doms, targets = WV.wave_plan(wave, system.dims, system.origins, system.h, system.dt, system.c,
-                                           precision, split_gap=args.split_gap, stream=stream)
+                                           precision, split_gap=split_gap, stream=stream)
         plan.set_tuning("lagsum_persistent", 1)
         st = plan.stats()
         ws_total += plan.workspace_bytes
@@ -287,7 +261,7 @@ def bench_batched(args):
         n_launch += n
         if not all(bool(torch.isfinite(o).all()) for o in outs if o is not None):
             raise RuntimeError(f"non-finite output in wave {wi}")
-        log(f"wave {wi + 1}/{len(waves)}: {len(wave.units)} units, {len(targets)} targets, workspace "
+        log(f"{label} {wi + 1}/{len(waves)}: {len(wave.units)} units, {len(targets)} targets, workspace "
             f"{plan.workspace_bytes / 1e9:.0f} GB, step {1e3 * el / K:.1f} ms, lag sum {ms / max(n, 1):.1f} ms "
             f"({st['lagsum_bytes'] / (ms / max(n, 1) / 1e3) / 1e9:.0f} GB/s); setup so far "
             + ", ".join(f"{k} {v:.0f} s" for k, v in phases.items()))
@@ -295,6 +269,47 @@ def bench_batched(args):
         del plan, src, outs, buf
     del workspace
     torch.cuda.empty_cache()
+    return {"t_timed": t_timed, "t_setup": t_setup, "updates": updates, "phases": phases, "lag_bytes": lag_bytes,
+            "lag_s": lag_s, "n_launch": n_launch, "ws_total": ws_total, "wall0": wall0}
+
+
+def bench_batched(args):
+    """The batched workload as drawn: 64 independent systems of 2-16
+    sub-domains with grids from {32, 48, 64, 96}^3 (FP32 by default).  Its
+    history and spectra (24 TB in FP32) cannot sit on one device at once, so
+    the targets are grouped into units (the targets of one grid shape of one
+    system, halved until the unit's plan fits, each with every domain of its
+    system as a source, its own pad and a split history) and the units are
+    packed into waves of at most the free device memory.  Each wave is one
+    batched plan: bind, Green spectra, step 0, a captured step, W warm-up
+    replays, K timed replays (sources already in device memory), then E eager
+    steps that time the lag sum.  Throughput = every target point x K over the
+    summed timed replays of all waves; one step of the whole workload takes
+    the sum of the waves' step times."""
+    import torch
+    from paper_2311_15429_amd import waves as WV
+    from synth.sources import config4
+    precision = args.precision or "fp32"
+    system = config4(args.seed)
+    free, total = torch.cuda.mem_get_info()
+    reserve = 16e9          # sources of the timed steps, outputs, graph buffers, source fields
+    budget = int(0.97 * (free - reserve))
+    if args.wave_gb:
+        budget = min(budget, int(args.wave_gb * 1e9))
+    t0 = time.perf_counter()
+    units = WV.plan_units(system.dims, system.origins, system.system_id, system.h, system.dt, system.c,
+                          precision, budget, split_gap=args.split_gap)
+    waves = WV.pack_waves(units, budget)
+    t_plan = time.perf_counter() - t0
+    lag_total = sum(u.lagsum_bytes for u in units)
+    pts_total = sum(u.points for u in units)
+    log(f"config 4: {len(set(system.system_id))} systems, {len(system.domains)} domains, {pts_total} target points; "
+        f"{len(units)} units in {len(waves)} waves of <= {budget / 1e9:.0f} GB (device free {free / 1e9:.0f} of "
+        f"{total / 1e9:.0f} GB); lag-sum bytes per step {lag_total / 1e12:.2f} TB; host planning {t_plan:.1f} s")
+    W, K, E = args.warmup, args.steps, 1
+    r = run_waves(system, precision, waves, W, K, E, args.split_gap)
+    t_timed, t_setup, updates, phases = r["t_timed"], r["t_setup"], r["updates"], r["phases"]
+    lag_bytes, lag_s, n_launch, ws_total, wall0 = r["lag_bytes"], r["lag_s"], r["n_launch"], r["ws_total"], r["wall0"]
     wall = time.perf_counter() - wall0
     value = updates / t_timed
     ms_step = 1e3 * t_timed / K
@@ -468,7 +483,7 @@ def bench_surrogate(args):
     from synth.sources import config5, spatial_factors, time_factors
 
     FAR, NL, T_STEPS, JUDGE_EVERY, TOL = 10.0, 64, 3000, 100, 1e-4
-    precision = args.precision or "fp32_ring_fp16"
+    precision = args.precision or "fp32_ring_i16"
     stream = torch.cuda.current_stream()
 
     class Gen:
@@ -623,6 +638,36 @@ def bench_surrogate(args):
     log(f"oracle at {len(targets)} x {args.oracle_points} points: rel err {np.array2string(err_s, precision=2)}; "
         f"far pairs left out would give {np.array2string(err_d, precision=2)} ({t_oracle:.0f} s)")
 
+    # the plain FP32 method on the same workload, measured: its history (824
+    # GB) does not fit one device, so it runs as waves of target groups (each
+    # a plan of some targets with every domain as a source and a split
+    # history); a step of the whole workload takes the sum of the waves' steps
+    plain_meas = None
+    plan.surrogate_attach(None)
+    plan.close()
+    del plan, outs, src
+    torch.cuda.empty_cache()
+    if args.plain_baseline:
+        from paper_2311_15429_amd import waves as WV
+        free, _ = torch.cuda.mem_get_info()
+        budget = int(0.97 * (free - 16e9))
+        units = WV.plan_units(system.dims, system.origins, None, system.h, system.dt, system.c, "fp32", budget,
+                              split_gap=args.split_gap)
+        pwaves = WV.pack_waves(units, budget)
+        log(f"plain FP32 baseline: {len(units)} target groups in {len(pwaves)} waves")
+        r = run_waves(system, "fp32", pwaves, 1, 3, 1, args.split_gap, label="plain wave")
+        plain_ms = 1e3 * r["t_timed"] / 3
+        plain_meas = {"ms_per_step": plain_ms, "updates_per_s": r["updates"] / r["t_timed"],
+                      "lagsum_ms_per_step": 1e3 * r["lag_s"] / max(r["n_launch"], 1) * len(pwaves),
+                      "lagsum_gbs": r["lag_bytes"] / r["lag_s"] / 1e9, "waves": len(pwaves),
+                      "target_groups": [len(u.targets) for u in units],
+                      "method": "the plain FP32 method (every pair by the lag sum, FP32 ring) run as waves of "
+                                "target groups, each a plan of some targets with every sub-domain as a source and "
+                                "a split history, one after the other on this device; 3 timed graph replays per "
+                                "wave; a step of the whole workload takes the sum of the waves' step times"}
+        log(f"plain FP32 measured: {plain_ms:.1f} ms per step ({plain_meas['updates_per_s'] / 1e6:.1f} M updates/s); "
+            f"surrogate step {ms_step:.2f} ms: {plain_ms / ms_step:.1f}x")
+
     line = {"metric": METRIC, "value": updates, "unit": "grid-point updates/s", "n_gpus": 1, "steps": K,
             "warmup": W, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -641,6 +686,8 @@ def bench_surrogate(args):
                        "plain_fp32_lagsum_bytes": pst["lagsum_bytes"],
                        "plain_fp32_lagsum_ms_modelled": plain_lag_ms,
                        "speedup_vs_plain_lagsum_alone_modelled": plain_lag_ms / ms_step,
+                       "plain_fp32_measured": plain_meas,
+                       "speedup_vs_plain_fp32_measured": (plain_meas["ms_per_step"] / ms_step) if plain_meas else None,
                        "teacher_samples": n_samples, "teacher_s": round(t_data, 1), "train_s": round(t_train, 1),
                        "train_rel_rms": train_rms, "autotune": tuned},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -648,8 +695,6 @@ def bench_surrogate(args):
                          "kernel_ms": round(lag_s * 1e3, 4), "algorithmic_bytes_per_launch": st["lagsum_bytes"]},
             "cpu_baseline": None}
     print(json.dumps(line), flush=True)
-    plan.surrogate_attach(None)
-    plan.close()
 
 
 def bench_coupled(args):
@@ -920,8 +965,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default=None, choices=["fp32", "fp32_ring_fp16", "fp32_ring_bf16", "fp32_ring_i16", "fp64"],
-                    help="default: fp32 (scale, small: fp64 always, sweep, coupled, paper); "
-                         "fp32_ring_fp16 for the batched and surrogate workloads")
+                    help="default: fp32 (scale, batched, small: fp64 always, sweep, coupled, paper); "
+                         "fp32_ring_i16 for the surrogate workload, fp32_ring_fp16 for batched_scaled")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -951,6 +996,8 @@ def main():
     ap.add_argument("--oracle-points", type=int, default=24)
     ap.add_argument("--wave-gb", type=float, default=0.0,
                     help="batched workload: cap of a wave's workspace in GB (default: the free device memory)")
+    ap.add_argument("--no-plain-baseline", dest="plain_baseline", action="store_false",
+                    help="surrogate workload: skip the measured plain FP32 run (waves of target groups)")
     ap.add_argument("--split-gap", type=int, default=8,
                     help="batched workload: history split gap of the wave plans (lags)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,

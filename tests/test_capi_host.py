@@ -320,3 +320,74 @@ def test_i16_ring_plans_like_fp16_with_tile_scales():
                                org.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None,
                                ctypes.c_double(s.h), ctypes.c_double(s.dt), ctypes.c_double(s.c), 5, None)
     assert code == 1 and not h.value
+
+
+def test_target_subset_forms_only_pairs_into_the_targets():
+    """rp_plan_targets: only (target <- source) pairs are formed, the pad
+    covers the largest target plus the largest source, the updates are the
+    targets' points, and every system needs a target."""
+    h, dt = 0.5, 0.02
+    doms = [sy.Domain((8, 8, 8), np.array([0.0, 0, 0])), sy.Domain((16, 16, 16), np.array([30.0, 0, 0])),
+            sy.Domain((8, 8, 8), np.array([0.0, 40.0, 0]))]
+    args = ([d.dims for d in doms], [d.origin for d in doms], h, dt, C_AU)
+    full = Plan(*args, precision="fp32")
+    assert full.info(0, 0)[2] == (32, 32, 32)            # 2 x 16 - 1 -> 32
+    sub = Plan(*args, precision="fp32")
+    sub.set_targets([0, 2])
+    assert sub.info(0, 0)[2] == (24, 24, 24)              # 8 + 16 - 1 -> 24
+    assert sub.info(1, 0)[:2] == (-1, -1) and sub.info(0, 1)[:2] == full.info(0, 1)[:2]
+    a, b = full.stats(), sub.stats()
+    assert b["points"] == 2 * 8 ** 3
+    assert b["n_triples"] == sum(full.info(s, n)[1] - full.info(s, n)[0] + 1 for s in (0, 2) for n in range(3))
+    assert b["lagsum_bytes"] < a["lagsum_bytes"] and sub.workspace_bytes < full.workspace_bytes
+    sub.set_targets(None)                                  # back to every domain
+    assert sub.stats() == a
+    with pytest.raises(RpotError):
+        sub.set_targets([3])
+    two = Plan(*args, precision="fp32", system_id=[0, 0, 1])
+    with pytest.raises(RpotError):
+        two.set_targets([0, 1])                           # system 1 left without a target
+
+
+def test_split_history_drops_the_lags_before_a_non_target_window():
+    """A source that is not a target reaches the targets only from its window
+    on: with a split history its own ring keeps lag 0 alone and the window
+    sits in a split ring."""
+    h, dt = 0.5, 0.02
+    doms = [sy.Domain((8, 8, 8), np.array([0.0, 0, 0])), sy.Domain((8, 8, 8), np.array([60.0, 0, 0]))]
+    p = Plan([d.dims for d in doms], [d.origin for d in doms], h, dt, C_AU, precision="fp32")
+    p.set_targets([0])
+    lo, hi = p.info(0, 1)[:2]
+    assert lo >= 8 and p.info(1, 1)[3] == hi + 1           # unsplit: lags 0 .. hi of source 1
+    plain = p.stats()
+    p.history_split(4)
+    st = p.stats()
+    assert p.info(1, 1)[3] == 1 and st["split_rings"] == 1
+    assert st["lagsum_bytes"] == plain["lagsum_bytes"] and st["ring_bytes"] < 0.5 * plain["ring_bytes"]
+
+
+def test_waves_cover_every_target_once_within_the_budget():
+    from paper_2311_15429_amd import waves as W
+    s = sy.config4(1, n_systems=5, sizes=(8, 12, 16), n_dom_range=(2, 6))
+    big = W.plan_units(s.dims, s.origins, s.system_id, s.h, s.dt, s.c, "fp32", budget=1 << 60)
+    sid = np.asarray(s.system_id)
+    single = 0
+    for k in set(sid.tolist()):
+        doms = np.where(sid == k)[0].tolist()
+        for t in range(len(doms)):
+            p = W._unit_plan(s.dims[doms], s.origins[doms], s.h, s.dt, s.c, "fp32", [t], 8)
+            single = max(single, p.workspace_bytes)
+            p.close()
+    budget = max(single, int(0.6 * max(u.workspace for u in big)))
+    units = W.plan_units(s.dims, s.origins, s.system_id, s.h, s.dt, s.c, "fp32", budget=budget)
+    waves = W.pack_waves(units, budget)
+    assert sorted(t for u in units for t in u.targets) == list(range(len(s.domains)))
+    assert len(units) > len(big) and all(u.workspace <= budget for u in units)
+    for u in units:                       # a unit's targets share a system and a grid shape
+        assert set(sid[u.targets]) == {u.system} and len({s.domains[t].dims for t in u.targets}) == 1
+        assert sorted(u.domains) == sorted(np.where(sid == u.system)[0].tolist())
+    for w in waves:
+        p, doms, targets = W.wave_plan(w, s.dims, s.origins, s.h, s.dt, s.c, "fp32")
+        assert w.workspace <= budget and p.workspace_bytes <= w.workspace
+        assert p.stats()["points"] == sum(s.domains[doms[t]].n_points for t in targets)
+        p.close()
