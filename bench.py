@@ -973,6 +973,9 @@ def main():
     ap.add_argument("--no-fill", action="store_true",
                     help="scale workload: time from step 1 on instead of after the history fill")
     ap.add_argument("--lagsum-unroll", type=int, default=None, choices=[1, 2, 4])
+    ap.add_argument("--lagsum-steps", type=int, default=8, choices=[1, 2, 4, 8],
+                    help="scale workload: steps of the lag sum per pass over the history (1: every step "
+                         "reads the whole history)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default lag-sum schedule")
     ap.add_argument("--workload", default="scale",
                     choices=["scale", "batched", "batched_scaled", "surrogate", "small", "sweep", "coupled", "paper"],
@@ -1035,6 +1038,8 @@ def main():
     workload = "8 sub-domains of 64^3 points, h=0.3 bohr, 400-bohr box, dt=0.01, FFT pad 128^3"
     stream = torch.cuda.current_stream()
     plan = plan_for_system(system, args.precision, stream=stream)
+    if args.lagsum_steps > 1:
+        plan.set_tuning("lagsum_steps", args.lagsum_steps)
     st = plan.stats()
     log(f"plan: triples/step {st['n_triples']}, spectra {st['n_spectra']}, ring reads/step {st['n_entries']}, "
         f"workspace {plan.workspace_bytes / 1e9:.1f} GB, lag-sum bytes/launch {st['lagsum_bytes'] / 1e9:.2f} GB")
@@ -1084,7 +1089,8 @@ def main():
     last = F + W + K
     plan.profile_lagsum(False)
     lag_ms, launches = plan.lagsum_time()
-    assert launches == K
+    kb = plan.get_tuning("lagsum_steps")
+    assert launches == (K if kb == 1 else sum(1 for l in range(F + W + 1, F + W + K + 1) if (l - 1) % kb == 0))
     if not all(bool(torch.isfinite(o).all()) for o in outs):
         raise RuntimeError("non-finite output")
 
@@ -1101,11 +1107,14 @@ def main():
     updates = st["points"] * K / el
     lag_avg_s = lag_ms / launches / 1e3
     achieved = st["lagsum_bytes"] / lag_avg_s / 1e9
-    traffic = traffic_from_profiles("config2", args.precision)
+    traffic = traffic_from_profiles("config2" if kb == 1 else f"config2_blocked{kb}", args.precision)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_lagsum", "kernel_ms": round(lag_avg_s * 1e3, 4),
             "algorithmic_bytes_per_launch": st["lagsum_bytes"]}
+    if kb > 1:
+        roof["kernel"] = f"k_lagsum_block ({kb} steps per pass)"
+        roof["lagsum_bytes_per_step"] = st["lagsum_bytes"] / kb
     log(f"step {ms_step:.3f} ms, lag-sum {lag_avg_s * 1e3:.3f} ms ({achieved:.0f} GB/s), "
         f"{updates / 1e6:.2f} M updates/s")
     # the practical read bandwidth of this device (a plain read stream of 4
@@ -1143,6 +1152,7 @@ def main():
                    "triples_per_step": st["n_triples"], "ring_reads_per_step": st["n_entries"],
                    "history_fill_steps": F, "timed_steps": [F + W + 1, last],
                    "green_setup_s": round(t_green, 3),
+                   "lagsum_steps_per_pass": kb,
                    "lagsum_unroll": plan.get_tuning("lagsum_unroll"),
                    "lagsum_persistent": plan.get_tuning("lagsum_persistent"),
                    "fft_lds": plan.get_tuning("fft_lds"),

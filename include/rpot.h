@@ -249,9 +249,45 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
  *                              (half as many in FP64); 0 = default (2048 for
  *                              FP32 plans, 4096 for FP64 plans).  Also per
  *                              shape class (below).
+ *   RP_TUNE_LAGSUM_STEPS       steps of the lag sum per pass over the history:
+ *                              1 (default), 2, 4 or 8.  The potential of step
+ *                              l + i depends on the sources of steps after l
+ *                              only through its lags m < i (Eq. "retardation
+ *                              space-time sampled lorentz four vector
+ *                              potential": lag m reads the sources of step
+ *                              l + i - m).  With kb steps per pass, steps are
+ *                              grouped into blocks starting at steps 1, 1 + kb,
+ *                              ...: the block's first step reads every
+ *                              snapshot and Green spectrum of the windows once
+ *                              and sums the lags m >= i of each of its kb steps
+ *                              i = 0 .. kb-1; step i of the block adds its lags
+ *                              m < i once its own sources are pushed.  Each
+ *                              step returns exactly its own potential from the
+ *                              sources pushed so far (a coupled loop may
+ *                              compute step l + 1's sources from step l's
+ *                              output); only the order of the sums changes.
+ *                              The history is read about 1/kb as often.  FP32
+ *                              plans only (RP_ERR_UNSUPPORTED for RP_FP64, with
+ *                              a split history or with the far-pair surrogate);
+ *                              set before rp_bind_workspace (RP_ERR_STATE
+ *                              after): it re-plans the workspace (kb
+ *                              accumulators per target).  rp_capture_step then
+ *                              records one graph per step of a block, and
+ *                              rp_launch_step replays the one of its step;
+ *                              rp_profile_lagsum times the passes of the
+ *                              blocks' first steps; rp_plan_stats gives the
+ *                              bytes of that pass as lagsum_bytes.
+ *   RP_TUNE_LAGSUM_CACHED      blocked pass: 1 loads through the caches, 0
+ *                              (default) non-temporal loads.  Its items (one
+ *                              target and frequency tile each) of one tile read
+ *                              the same source rows for different targets.
+ *   RP_TUNE_LAGSUM_TILE_MAJOR  blocked pass work order: 1 the items of one
+ *                              frequency tile next to each other, 0 (default)
+ *                              the costliest target first.
  * Setting a knob discards a captured step (rp_capture_step).
  */
-enum { RP_TUNE_LAGSUM_UNROLL = 1, RP_TUNE_LAGSUM_PERSISTENT = 2, RP_TUNE_FFT_LDS = 4 };
+enum { RP_TUNE_LAGSUM_UNROLL = 1, RP_TUNE_LAGSUM_PERSISTENT = 2, RP_TUNE_FFT_LDS = 4, RP_TUNE_LAGSUM_STEPS = 8,
+       RP_TUNE_LAGSUM_CACHED = 16, RP_TUNE_LAGSUM_TILE_MAJOR = 32 };
 rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value);
 /*
  * Shape classes: sub-domains with the same grid and FFT pad share their
@@ -268,7 +304,8 @@ rp_status rp_get_class_tuning(rp_plan plan, int32_t cls, int32_t knob, int32_t *
 rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value);
 
 /*
- * Autotuner: times every lag-sum schedule (unroll x persistent) `iters` times
+ * Autotuner: times every lag-sum schedule (unroll x persistent; with blocked
+ * steps the blocked pass, between blocks only) `iters` times
  * on the bound plan (after rp_set_green_kernels; only accumulator and FFT
  * scratch are written, the step sequence is untouched), keeps the fastest and
  * returns it with its mean kernel time; then times the inverse line passes at

@@ -25,7 +25,8 @@ EXPORTS = ["rp_plan_domains", "rp_plan_targets", "rp_workspace_bytes", "rp_bind_
            "rp_osc_step", "rp_osc_state", "rp_osc_destroy", "rp_osc_last_error", "rp_history_split",
            "rp_history_host", "rp_history_host_bytes", "rp_bind_history_host",
            "rp_class_info", "rp_set_class_tuning", "rp_get_class_tuning", "rp_read_stream"]
-TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2, "fft_lds": 4}
+TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2, "fft_lds": 4, "lagsum_steps": 8, "lagsum_cached": 16,
+        "lagsum_tile_major": 32}
 
 
 class RpotError(RuntimeError):

@@ -48,20 +48,23 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const char *base, int
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(base), (short)0, bytes, kRsrcWord3);
 }
 
+template <int AUX = kLoadAux>
 __device__ __forceinline__ nu4 ld128(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(nu4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kLoadAux));
+    return __builtin_bit_cast(nu4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX));
 }
+template <int AUX = kLoadAux>
 __device__ __forceinline__ nu2 ld64(__amdgpu_buffer_rsrc_t r, int off) {
-    return __builtin_bit_cast(nu2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kLoadAux));
+    return __builtin_bit_cast(nu2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
 }
 
 template <>
 struct RingLoad<double, RING_F64> {
     static constexpr int row_bytes = kTile * 4 * 16;
+    template <int AUX = kLoadAux>
     __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *, Cx<double> (&x)[4]) {
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
-            const nu4 v = ld128(r, (mu * kTile + lane) * 16);   // row [c][k]
+            const nu4 v = ld128<AUX>(r, (mu * kTile + lane) * 16);   // row [c][k]
             x[mu] = {__builtin_bit_cast(double, nu2{v.x, v.y}), __builtin_bit_cast(double, nu2{v.z, v.w})};
         }
     }
@@ -69,9 +72,10 @@ struct RingLoad<double, RING_F64> {
 template <>
 struct RingLoad<float, RING_F32> {
     static constexpr int row_bytes = kTile * 4 * 8;
+    template <int AUX = kLoadAux>
     __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *, Cx<float> (&x)[4]) {
-        const nu4 a = ld128(r, lane * 16);                 // row [c/2][k][c%2]
-        const nu4 b = ld128(r, (kTile + lane) * 16);
+        const nu4 a = ld128<AUX>(r, lane * 16);                 // row [c/2][k][c%2]
+        const nu4 b = ld128<AUX>(r, (kTile + lane) * 16);
         x[0] = {__uint_as_float(a.x), __uint_as_float(a.y)};
         x[1] = {__uint_as_float(a.z), __uint_as_float(a.w)};
         x[2] = {__uint_as_float(b.x), __uint_as_float(b.y)};
@@ -81,8 +85,9 @@ struct RingLoad<float, RING_F32> {
 template <>
 struct RingLoad<float, RING_F16> {
     static constexpr int row_bytes = kTile * 4 * 4;
+    template <int AUX = kLoadAux>
     __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *sc, Cx<float> (&x)[4]) {
-        const nu4 v = ld128(r, lane * 16);
+        const nu4 v = ld128<AUX>(r, lane * 16);
         const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
@@ -96,8 +101,9 @@ struct RingLoad<float, RING_F16> {
 template <>
 struct RingLoad<float, RING_BF16> {
     static constexpr int row_bytes = kTile * 4 * 4;
+    template <int AUX = kLoadAux>
     __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *sc, Cx<float> (&x)[4]) {
-        const nu4 v = ld128(r, lane * 16);
+        const nu4 v = ld128<AUX>(r, lane * 16);
         const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
@@ -112,8 +118,9 @@ struct RingLoad<float, RING_BF16> {
 template <>
 struct RingLoad<float, RING_I16> {
     static constexpr int row_bytes = kTile * 4 * 4;
+    template <int AUX = kLoadAux>
     __device__ static void get(__amdgpu_buffer_rsrc_t r, int lane, const float *sc, Cx<float> (&x)[4]) {
-        const nu4 v = ld128(r, lane * 16);
+        const nu4 v = ld128<AUX>(r, lane * 16);
         const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
@@ -125,17 +132,15 @@ struct RingLoad<float, RING_I16> {
     }
 };
 
-template <typename T>
-__device__ __forceinline__ Cx<T> load_spec(__amdgpu_buffer_rsrc_t r, int lane);
-template <>
-__device__ __forceinline__ Cx<float> load_spec<float>(__amdgpu_buffer_rsrc_t r, int lane) {
-    const nu2 v = ld64(r, lane * 8);
-    return {__uint_as_float(v.x), __uint_as_float(v.y)};
-}
-template <>
-__device__ __forceinline__ Cx<double> load_spec<double>(__amdgpu_buffer_rsrc_t r, int lane) {
-    const nu4 v = ld128(r, lane * 16);
-    return {__builtin_bit_cast(double, nu2{v.x, v.y}), __builtin_bit_cast(double, nu2{v.z, v.w})};
+template <typename T, int AUX = kLoadAux>
+__device__ __forceinline__ Cx<T> load_spec(__amdgpu_buffer_rsrc_t r, int lane) {
+    if constexpr (sizeof(T) == 4) {
+        const nu2 v = ld64<AUX>(r, lane * 8);
+        return {__uint_as_float(v.x), __uint_as_float(v.y)};
+    } else {
+        const nu4 v = ld128<AUX>(r, lane * 16);
+        return {__builtin_bit_cast(double, nu2{v.x, v.y}), __builtin_bit_cast(double, nu2{v.z, v.w})};
+    }
 }
 
 template <typename T, int TG>
@@ -261,10 +266,156 @@ __device__ __forceinline__ void lagsum_item(const K2Args &a, int item_index) {
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
         if (t < g.n_members) {
-            Cx<T> *o = out + a.doms[g.member[t]].acc_off + k * 4;
+            const DomDev &D = a.doms[g.member[t]];
+            Cx<T> *o = out + D.acc_off + int64_t(a.acc_set) * D.acc_set_stride + k * 4;
+            if (a.accumulate) {
 #pragma unroll
-            for (int mu = 0; mu < 4; ++mu) o[mu] = acc[t][mu];
+                for (int mu = 0; mu < 4; ++mu) o[mu] = {o[mu].x + acc[t][mu].x, o[mu].y + acc[t][mu].y};
+            } else {
+#pragma unroll
+                for (int mu = 0; mu < 4; ++mu) o[mu] = acc[t][mu];
+            }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lag sum of KB steps in one pass (temporal blocking).
+//
+// At the first step l of a block every source snapshot dS(l - d) (age d) is
+// read once and feeds the KB accumulators of the target:
+//   acc_i += G_{d+i} dS(l - d),   i = 0 .. KB-1,  d + i in the pair's window,
+// so acc_i holds the part of step l + i that needs sources up to step l only
+// (the lags m = d + i >= i).  Steps l + i (i >= 1) add their lags m < i once
+// their own sources are in the ring (the plain kernel in accumulate mode on
+// set i), so every step gets exactly its own sum; the ring rows and spectrum
+// rows of the window are read once per KB steps instead of once per step.
+// One member per thread.  The thread keeps the spectra of KB consecutive lags
+// in a circular register window: lag m sits at (m - d0) mod KB, d0 being the
+// first age of the walk, so with the walk unrolled by KB every index is a
+// compile-time constant.
+template <int FMT, int KB, int U, int AUX>
+__device__ __forceinline__ void lagsum_block_item(const K2Args &a, int item_index) {
+    constexpr int esz = RingEsz<FMT>::v;
+    constexpr int64_t ring_row = int64_t(kTile) * 4 * esz;
+    constexpr int64_t spec_row = int64_t(kTile) * int64_t(sizeof(Cx<float>));
+    static_assert(KB % U == 0, "snapshots per load batch must divide the block");
+    const K2Item item = a.items[item_index];
+    const K2Group &g = a.groups[item.group];
+    const int lane = threadIdx.x;
+    const int64_t k = int64_t(item.k0) + lane;
+    if (k >= g.C) return;
+    const int32_t tile = item.k0 / kTile;
+    const char *spec = reinterpret_cast<const char *>(a.spectra) + g.spec_base * int64_t(sizeof(Cx<float>));
+    const char *ring = reinterpret_cast<const char *>(a.ring);
+
+    Cx<float> acc[KB][4];
+#pragma unroll
+    for (int i = 0; i < KB; ++i)
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) acc[i][mu] = {0.f, 0.f};
+
+    for (int si = g.src_begin; si < g.src_end; ++si) {
+        const K2Src &R = a.srcs[si];
+        const int m_lo = R.m_min, m_hi = R.m_max, depth = R.depth;
+        if (m_hi < m_lo) continue;
+        const bool conj = R.conj & 1u;
+        const K2Pair &Q = a.pairs[si * 8];
+        const char *srow = spec + int64_t(Q.row0 + tile * Q.w) * spec_row;   // + m * spec_row: lag m
+        const char *ring_tile = ring + (R.ring_off * esz + int64_t(tile) * depth * ring_row);
+        int64_t scale_off = 0;
+        if (FMT == RING_F16 || FMT == RING_BF16) scale_off = a.doms[R.n].scale_off;
+        if (FMT == RING_I16) scale_off = a.doms[R.n].scale_off + int64_t(tile) * depth * 4;
+        const int d0 = max(0, m_lo - (KB - 1));
+        const int n_it = m_hi - d0 + 1;
+        // age d sits in slot head - d (mod depth): the ring holds lags from 0
+        int32_t slot = a.head[R.n] - d0;
+        if (slot < 0) slot += depth;
+
+        auto load_g = [&](int m) -> Cx<float> {
+            if (m < m_lo || m > m_hi) return {0.f, 0.f};
+            Cx<float> v = load_spec<float, AUX>(row_rsrc(srow + int64_t(m) * spec_row, int(spec_row)), lane);
+            if (conj) v.y = -v.y;
+            return v;
+        };
+        Cx<float> gw[KB];
+#pragma unroll
+        for (int j = 0; j < KB - 1; ++j) gw[j] = load_g(d0 + j);
+        gw[KB - 1] = {0.f, 0.f};
+
+        for (int t0 = 0; t0 < n_it; t0 += KB) {
+#pragma unroll
+            for (int u0 = 0; u0 < KB; u0 += U) {
+                if (t0 + u0 >= n_it) break;
+                // loads of U snapshots first: ring rows, and the newest lag of
+                // each one's window into gn (the slot it takes in gw still
+                // holds a lag the previous snapshot needs)
+                Cx<float> x[U][4];
+                Cx<float> gn[U];
+#pragma unroll
+                for (int v = 0; v < U; ++v) {
+                    const int t = t0 + u0 + v;
+                    if (t < n_it) {
+                        gn[v] = load_g(d0 + t + KB - 1);
+                        float sc[4] = {1.f, 1.f, 1.f, 1.f};
+                        if (FMT == RING_F16 || FMT == RING_BF16 || FMT == RING_I16) {
+                            const float *s4 = a.scales + scale_off + int64_t(slot) * 4;
+                            sc[0] = s4[0];
+                            sc[1] = s4[1];
+                            sc[2] = s4[2];
+                            sc[3] = s4[3];
+                        }
+                        RingLoad<float, FMT>::template get<AUX>(row_rsrc(ring_tile + slot * ring_row, int(ring_row)),
+                                                                lane, sc, x[v]);
+                        slot = (slot == 0) ? depth - 1 : slot - 1;
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < U; ++v) {
+                    if (t0 + u0 + v < n_it) {
+                        gw[(u0 + v + KB - 1) % KB] = gn[v];   // replaces lag d0 + t - 1
+#pragma unroll
+                        for (int i = 0; i < KB; ++i) {
+                            const Cx<float> gv = gw[(u0 + v + i) % KB];
+#pragma unroll
+                            for (int mu = 0; mu < 4; ++mu) {
+                                acc[i][mu].x = fmaf(gv.x, x[v][mu].x, acc[i][mu].x);
+                                acc[i][mu].x = fmaf(-gv.y, x[v][mu].y, acc[i][mu].x);
+                                acc[i][mu].y = fmaf(gv.x, x[v][mu].y, acc[i][mu].y);
+                                acc[i][mu].y = fmaf(gv.y, x[v][mu].x, acc[i][mu].y);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    const DomDev &D = a.doms[g.member[0]];
+    Cx<float> *__restrict__ out = reinterpret_cast<Cx<float> *>(a.acc) + D.acc_off + k * 4;
+#pragma unroll
+    for (int i = 0; i < KB; ++i)
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) out[int64_t(i) * D.acc_set_stride + mu] = acc[i][mu];
+}
+
+// AUX: cache policy of the loads (kLoadAux: non-temporal; 0: cached, so that
+// the items of one frequency tile, which read the same source rows for
+// different targets, can share them through the caches).
+template <int FMT, int KB, int U, bool PERSIST, int AUX>
+__global__ __launch_bounds__(256) void k_lagsum_block(K2Args a) {
+    if (!PERSIST) {
+        lagsum_block_item<FMT, KB, U, AUX>(a, blockIdx.x);
+        return;
+    }
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= a.n_items) break;
+        lagsum_block_item<FMT, KB, U, AUX>(a, it);
     }
 }
 
@@ -338,6 +489,80 @@ void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, int unroll
     } else {
         launch_tg<float, RING_F32>(a, tg, unroll, grid_persist, st);
     }
+}
+
+template <int FMT, int KB, int U, int AUX>
+static void launch_block_pa(const K2Args &a, int grid_persist, hipStream_t st) {
+    if (grid_persist > 0) {
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, st, a.counter);
+        hipLaunchKernelGGL((k_lagsum_block<FMT, KB, U, true, AUX>), dim3(std::min(grid_persist, a.n_items)),
+                           dim3(256), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_lagsum_block<FMT, KB, U, false, AUX>), dim3(a.n_items), dim3(256), 0, st, a);
+    }
+}
+template <int FMT, int KB, int U>
+static void launch_block_p(const K2Args &a, int grid_persist, hipStream_t st) {
+    if (a.cached) launch_block_pa<FMT, KB, U, 0>(a, grid_persist, st);
+    else launch_block_pa<FMT, KB, U, kLoadAux>(a, grid_persist, st);
+}
+
+// snapshots per load batch: 1, 2 or 4, at most the block
+template <int KB>
+constexpr int block_u(int u) { return u == 1 ? 1 : (u == 4 && KB >= 4 ? 4 : 2); }
+
+template <int FMT, int KB>
+static void launch_block_u(const K2Args &a, int unroll, int grid_persist, hipStream_t st) {
+    switch (block_u<KB>(unroll)) {
+    case 1: launch_block_p<FMT, KB, 1>(a, grid_persist, st); break;
+    case 4: launch_block_p<FMT, KB, (KB >= 4 ? 4 : 2)>(a, grid_persist, st); break;
+    default: launch_block_p<FMT, KB, 2>(a, grid_persist, st); break;
+    }
+}
+
+template <int FMT>
+static void launch_block_kb(const K2Args &a, int kb, int unroll, int grid_persist, hipStream_t st) {
+    switch (kb) {
+    case 2: launch_block_u<FMT, 2>(a, unroll, grid_persist, st); break;
+    case 4: launch_block_u<FMT, 4>(a, unroll, grid_persist, st); break;
+    default: launch_block_u<FMT, 8>(a, unroll, grid_persist, st); break;
+    }
+}
+
+void launch_lagsum_block(const K2Args &a, int ring_fmt, int kb, int unroll, int grid_persist, hipStream_t st) {
+    if (a.n_items == 0) return;
+    switch (ring_fmt) {
+    case RING_F16: launch_block_kb<RING_F16>(a, kb, unroll, grid_persist, st); break;
+    case RING_BF16: launch_block_kb<RING_BF16>(a, kb, unroll, grid_persist, st); break;
+    case RING_I16: launch_block_kb<RING_I16>(a, kb, unroll, grid_persist, st); break;
+    default: launch_block_kb<RING_F32>(a, kb, unroll, grid_persist, st); break;
+    }
+}
+
+int lagsum_block_blocks_per_cu(int ring_fmt, int kb, int unroll) {
+    int n = 0;
+    const void *f = nullptr;
+    auto pick = [&](auto fmtc) {
+        constexpr int F = decltype(fmtc)::value;
+        auto pu = [&](auto kbc) {
+            constexpr int KB = decltype(kbc)::value;
+            const int u = block_u<KB>(unroll);
+            f = u == 1 ? reinterpret_cast<const void *>(&k_lagsum_block<F, KB, 1, true, kLoadAux>)
+                : u == 4 ? reinterpret_cast<const void *>(&k_lagsum_block<F, KB, (KB >= 4 ? 4 : 2), true, kLoadAux>)
+                         : reinterpret_cast<const void *>(&k_lagsum_block<F, KB, 2, true, kLoadAux>);
+        };
+        if (kb == 2) pu(std::integral_constant<int, 2>{});
+        else if (kb == 4) pu(std::integral_constant<int, 4>{});
+        else pu(std::integral_constant<int, 8>{});
+    };
+    switch (ring_fmt) {
+    case RING_F16: pick(std::integral_constant<int, RING_F16>{}); break;
+    case RING_BF16: pick(std::integral_constant<int, RING_BF16>{}); break;
+    case RING_I16: pick(std::integral_constant<int, RING_I16>{}); break;
+    default: pick(std::integral_constant<int, RING_F32>{}); break;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess || n < 1) n = 1;
+    return n;
 }
 
 int lagsum_blocks_per_cu(int prec64, int ring_fmt, int tg, int unroll) {

@@ -202,13 +202,16 @@ bool plain_pair(rp_plan p, int s, int n) {
 // Lag-sum schedule of the members (accumulator slots of system si): groups of
 // up to 8 members, and per group the sources any member takes with the union
 // of their windows.
-void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables &T) {
+void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables &T, int gmax, int m_cap) {
     const SystemP &S = p->sys[si];
-    for (size_t g0 = 0; g0 < members.size(); g0 += kGroupMax) {
+    // every pair's window clipped to lags <= m_cap
+    auto lo_of = [&](const PairP &q) { return q.m_lo; };
+    auto hi_of = [&](const PairP &q) { return std::min(q.m_hi, m_cap); };
+    for (size_t g0 = 0; g0 < members.size(); g0 += size_t(gmax)) {
         K2Group G{};
         G.C = S.C;
         G.spec_base = S.spec_base;
-        G.n_members = int(std::min<size_t>(kGroupMax, members.size() - g0));
+        G.n_members = int(std::min<size_t>(size_t(gmax), members.size() - g0));
         const K2Member *mb = members.data() + g0;
         for (int t = 0; t < G.n_members; ++t) G.member[t] = mb[t].slot;
         G.entry_begin = int(T.entries.size());
@@ -216,7 +219,9 @@ void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables 
         for (int n : S.doms) {
             uint32_t takes = 0;
             for (int t = 0; t < G.n_members; ++t)
-                if (std::find(mb[t].srcs.begin(), mb[t].srcs.end(), n) != mb[t].srcs.end()) takes |= 1u << t;
+                if (std::find(mb[t].srcs.begin(), mb[t].srcs.end(), n) != mb[t].srcs.end() &&
+                    lo_of(p->pr(mb[t].s, n)) <= hi_of(p->pr(mb[t].s, n)))
+                    takes |= 1u << t;
             if (!takes) continue;
             K2Src R{};
             R.n = n;
@@ -230,8 +235,8 @@ void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables 
                     Qs[t].row0 = int32_t(q.spec0 / kTile) - q.m_lo;
                     Qs[t].w = q.m_hi - q.m_lo + 1;
                     if (q.conj) R.conj |= 1u << t;
-                    R.m_min = std::min(R.m_min, q.m_lo);
-                    R.m_max = std::max(R.m_max, q.m_hi);
+                    R.m_min = std::min(R.m_min, lo_of(q));
+                    R.m_max = std::max(R.m_max, hi_of(q));
                 }
             }
             R.mask_off = int32_t(T.masks.size());
@@ -240,7 +245,7 @@ void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables 
                 for (int t = 0; t < G.n_members; ++t) {
                     if (!((takes >> t) & 1u)) continue;
                     const PairP &q = p->pr(mb[t].s, n);
-                    if (m >= q.m_lo && m <= q.m_hi) mk |= 1u << t;
+                    if (m >= lo_of(q) && m <= hi_of(q)) mk |= 1u << t;
                 }
                 T.masks.push_back(mk);
             }
@@ -268,7 +273,7 @@ void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables 
                 for (int t = 0; t < G.n_members; ++t) {
                     if (!((takes >> t) & 1u)) continue;
                     const PairP &q = p->pr(mb[t].s, n);
-                    if (m < q.m_lo || m > q.m_hi) continue;
+                    if (m < lo_of(q) || m > hi_of(q)) continue;
                     E.mask |= 1u << t;
                     if (q.conj) E.conj |= 1u << t;
                     E.spec_tile[t] = int32_t(q.spec0 / kTile + (m - q.m_lo));
@@ -316,8 +321,9 @@ void finish_k2(rp_plan p, K2Tables &T) {
     }
 }
 
-// The plain lag sum of every domain over its plain pairs.
-void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int)) {
+// The plain lag sum of every domain over its plain pairs (groups of up to
+// gmax targets, windows clipped to lags <= m_cap).
+void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int), int gmax, int m_cap) {
     T = K2Tables{};
     for (size_t si = 0; si < p->sys.size(); ++si) {
         std::vector<K2Member> members;
@@ -328,9 +334,37 @@ void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int)) {
                 if (pred(p, s, n)) M.srcs.push_back(n);
             members.push_back(std::move(M));
         }
-        build_k2(p, int(si), members, T);
+        build_k2(p, int(si), members, T, gmax, m_cap);
     }
     finish_k2(p, T);
+}
+
+void order_k2b(rp_plan p) {
+    K2Tables &T = p->k2b;
+    std::vector<double> gcost(T.groups.size(), 0.0);
+    for (size_t gi = 0; gi < T.groups.size(); ++gi)
+        for (int e = T.groups[gi].entry_begin; e < T.groups[gi].entry_end; ++e) gcost[gi] += 1.0;
+    if (p->k2b_tile_major)
+        std::stable_sort(T.items.begin(), T.items.end(), [&](const K2Item &x, const K2Item &y) {
+            return x.k0 != y.k0 ? x.k0 < y.k0 : gcost[x.group] > gcost[y.group];
+        });
+    else
+        std::stable_sort(T.items.begin(), T.items.end(), [&](const K2Item &x, const K2Item &y) {
+            return gcost[x.group] != gcost[y.group] ? gcost[x.group] > gcost[y.group] : x.k0 < y.k0;
+        });
+    if (p->ws && !T.items.empty())
+        HIP_OK(hipMemcpyAsync(p->ws + p->k2b_dev.items, T.items.data(), T.items.size() * sizeof(K2Item),
+                              hipMemcpyHostToDevice, p->stream));
+}
+
+// Device-table capacities of a schedule (its own sizes).
+void size_k2(K2Dev &D, const K2Tables &T) {
+    D.cap_items = T.items.size();
+    D.cap_groups = T.groups.size();
+    D.cap_entries = T.entries.size();
+    D.cap_srcs = T.srcs.size();
+    D.cap_pairs = T.pairs.size();
+    D.cap_masks = T.masks.size();
 }
 
 // Ring depths, stored Green spectra and the lag-sum schedules.
@@ -427,6 +461,20 @@ void plan_tables(rp_plan p) {
     }
 
     main_k2(p, p->k2, plain_pair);
+    // temporal blocking: the pass of a block's first step and the lags m < i
+    // of its steps i = 1 .. kb-1
+    p->k2b = K2Tables{};
+    p->k2c.assign(size_t(std::max(0, p->kb - 1)), K2Tables{});
+    p->k2c_dev.assign(p->k2c.size(), K2Dev{});
+    if (p->kb > 1) {
+        main_k2(p, p->k2b, plain_pair, 1);
+        order_k2b(p);
+        size_k2(p->k2b_dev, p->k2b);
+        for (int i = 1; i < p->kb; ++i) {
+            main_k2(p, p->k2c[size_t(i - 1)], plain_pair, kGroupMax, i - 1);
+            size_k2(p->k2c_dev[size_t(i - 1)], p->k2c[size_t(i - 1)]);
+        }
+    }
     // room for the largest schedule a fallback can reach
     K2Tables cap;
     main_k2(p, cap, keeps_history);
@@ -449,7 +497,7 @@ void plan_tables(rp_plan p) {
                 if (p->dom[F.s].sys != int(si)) continue;
                 members.push_back(K2Member{nd + int(v), F.s, {F.n}});
             }
-            build_k2(p, int(si), members, U.judge);
+            build_k2(p, int(si), members, U.judge, kGroupMax, INT32_MAX);
         }
         finish_k2(p, U.judge);
         K2Dev &J = U.judge_dev;
@@ -496,6 +544,10 @@ void plan_layout(rp_plan p) {
     p->off_counter = alloc(16);
     alloc_k2(p->k2_dev);
     if (p->sur.on) alloc_k2(p->sur.judge_dev);
+    if (p->kb > 1) {
+        alloc_k2(p->k2b_dev);
+        for (K2Dev &D : p->k2c_dev) alloc_k2(D);
+    }
     p->off_domdev = alloc(n_slots * sizeof(DomDev));
     for (const SystemP &S : p->sys) {
         for (int a = 0; a < 3; ++a) {
@@ -521,7 +573,7 @@ void plan_layout(rp_plan p) {
         d.off_zmax = zq ? alloc(size_t(d.zblocks) * 4 * sizeof(float)) : 0;
         d.off_s0 = alloc(size_t(4) * d.npts * p->tsz);
         d.off_p0 = alloc(size_t(4) * d.npts * p->tsz);
-        d.off_acc = alloc(size_t(S.C) * 4 * p->csz);
+        d.off_acc = alloc(size_t(p->kb) * size_t(S.C) * 4 * p->csz);   // kb accumulator sets
         d.off_t1 = alloc(t1 * p->csz);
         d.off_t2 = alloc(t2 * p->csz);
         d.off_s0hat = alloc(size_t(S.C) * 4 * 16);
@@ -585,6 +637,7 @@ void plan_layout(rp_plan p) {
         // offsets in elements relative to the first ring / accumulator / scale
         D.ring_off = int64_t((d.off_ring - p->dom[0].off_ring) / (4 * p->ring_esz)) * 4;
         D.acc_off = int64_t((d.off_acc - p->dom[0].off_acc) / p->csz);
+        D.acc_set_stride = p->sys[d.sys].C * 4;
         D.scale_off = quant ? int64_t((d.off_scales - p->dom[0].off_scales) / sizeof(float)) : 0;
         D.depth = d.depth;
         D.pad = 0;
@@ -607,6 +660,10 @@ void plan_layout(rp_plan p) {
     }
     finish_k2(p, p->k2);
     if (p->sur.on) finish_k2(p, p->sur.judge);
+    if (p->kb > 1) {
+        finish_k2(p, p->k2b);
+        for (K2Tables &T : p->k2c) finish_k2(p, T);
+    }
 }
 
 double k2_bytes(rp_plan p, const K2Tables &T) {
@@ -623,6 +680,26 @@ double k2_bytes(rp_plan p, const K2Tables &T) {
     return bytes;
 }
 
+// Minimal bytes of the blocked pass of a block's first step: per target,
+// source and frequency, the ring rows of the ages the walk reads
+// (max(0, m_lo - kb + 1) .. m_hi) and the spectrum rows of the window, and
+// the kb accumulator sets written.
+double k2b_bytes(rp_plan p) {
+    double bytes = 0;
+    for (const K2Group &G : p->k2b.groups) {
+        double per_k = 0;
+        for (int si = G.src_begin; si < G.src_end; ++si) {
+            const K2Src &R = p->k2b.srcs[size_t(si)];
+            if (R.m_max < R.m_min) continue;
+            const int d0 = std::max(0, R.m_min - (p->kb - 1));
+            per_k += double(R.m_max - d0 + 1) * 4.0 * p->ring_esz + double(R.m_max - R.m_min + 1) * p->spec_csz;
+        }
+        per_k += double(G.n_members) * p->kb * 4 * p->csz;
+        bytes += per_k * double(G.C);
+    }
+    return bytes;
+}
+
 void plan_stats(rp_plan p) {
     rp_stats &st = p->stats;
     st = rp_stats{};
@@ -634,7 +711,7 @@ void plan_stats(rp_plan p) {
     st.n_entries = int64_t(p->k2.entries.size());
     for (int n = 0; n < p->n_dom; ++n)
         if (is_target(p, n)) st.points += p->dom[n].npts;
-    st.lagsum_bytes = k2_bytes(p, p->k2);
+    st.lagsum_bytes = p->kb > 1 ? k2b_bytes(p) : k2_bytes(p, p->k2);
     for (const DomainP &d : p->dom) st.ring_bytes += double(d.depth) * p->sys[d.sys].Cpad * 4 * p->ring_esz;
     for (const VRingP &v : p->vring) st.ring_bytes += double(v.W) * p->sys[p->dom[v.n].sys].Cpad * 4 * p->ring_esz;
     for (const DomainP &d : p->dom)
@@ -844,11 +921,17 @@ void upload_k2(rp_plan p, const K2Tables &T, const K2Dev &D, hipStream_t st) {
 }
 
 void release_graph(rp_plan p) {
-    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    p->graph_exec = nullptr;
-    p->graph = nullptr;
+    for (hipGraphExec_t e : p->graph_execs)
+        if (e) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t g : p->graphs)
+        if (g) (void)hipGraphDestroy(g);
+    p->graph_execs.clear();
+    p->graphs.clear();
 }
+
+// Phase of a step within its block of kb steps (blocks start at steps 1,
+// 1 + kb, ...; step 0 runs as a block start over the empty history).
+int lag_phase(rp_plan p, int64_t step) { return step <= 0 ? 0 : int((step - 1) % p->kb); }
 
 void do_bind(rp_plan p, void *dev, size_t bytes) {
     if (!dev) fail(RP_ERR_ARG, "workspace pointer is null");
@@ -858,6 +941,10 @@ void do_bind(rp_plan p, void *dev, size_t bytes) {
     hipStream_t st = p->stream;
     upload_k2(p, p->k2, p->k2_dev, st);
     if (p->sur.on) upload_k2(p, p->sur.judge, p->sur.judge_dev, st);
+    if (p->kb > 1) {
+        upload_k2(p, p->k2b, p->k2b_dev, st);
+        for (size_t i = 0; i < p->k2c.size(); ++i) upload_k2(p, p->k2c[i], p->k2c_dev[i], st);
+    }
     HIP_OK(hipMemcpyAsync(p->ws + p->off_domdev, p->domdev.data(), p->domdev.size() * sizeof(DomDev),
                           hipMemcpyHostToDevice, st));
     // twiddles exp(-2 pi i j / P), evaluated in FP64 on the host
@@ -1199,13 +1286,34 @@ void enqueue_k2(rp_plan p, const K2Args &a, int tg, hipStream_t st, int unroll, 
     check_launch();
 }
 
-void enqueue_lagsum(rp_plan p, hipStream_t st, int unroll, int persist) {
-    enqueue_k2(p, k2_args(p, p->k2, p->k2_dev, p->at<int32_t>(p->off_head)), p->k2.tg, st, unroll, persist);
+// The lag sum of a step of phase `phase` (0 without blocking): the plain
+// pass; with kb > 1 the blocked pass at a block's first step (all kb
+// accumulator sets) and the lags m < phase added to set `phase` otherwise.
+void enqueue_lagsum(rp_plan p, hipStream_t st, int unroll, int persist, int phase) {
+    const int32_t *head = p->at<int32_t>(p->off_head);
+    if (p->kb == 1) {
+        enqueue_k2(p, k2_args(p, p->k2, p->k2_dev, head), p->k2.tg, st, unroll, persist);
+        return;
+    }
+    if (phase == 0) {
+        K2Args a = k2_args(p, p->k2b, p->k2b_dev, head);
+        a.cached = p->k2b_cached;
+        if (a.n_items == 0) return;
+        const int grid = persist ? p->n_cu * lagsum_block_blocks_per_cu(p->ring_fmt, p->kb, unroll) : 0;
+        launch_lagsum_block(a, p->ring_fmt, p->kb, unroll, grid, st);
+        check_launch();
+        return;
+    }
+    const K2Tables &T = p->k2c[size_t(phase - 1)];
+    K2Args a = k2_args(p, T, p->k2c_dev[size_t(phase - 1)], head);
+    a.acc_set = phase;
+    a.accumulate = 1;
+    enqueue_k2(p, a, T.tg, st, 1, 0);
 }
 
 // Inverse transform of every target's accumulated spectrum, crop to the
 // domain, add P(0), write the caller's output; then advance the step.
-void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st) {
+void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st, int phase) {
     for (const ClassP &K : p->cls) {
         for (size_t j0 = 0; j0 < K.tdoms.size(); j0 += kMaxJobs) {
             const int cnt = int(std::min<size_t>(kMaxJobs, K.tdoms.size() - j0));
@@ -1224,7 +1332,7 @@ void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st) {
             for (int j = 0; j < cnt; ++j) {
                 const int s = K.tdoms[j0 + j];
                 const DomainP &d = p->dom[s];
-                x.jobs[j].in = p->ws + d.off_acc;
+                x.jobs[j].in = p->ws + d.off_acc + size_t(phase) * size_t(K.C) * 4 * p->csz;
                 x.jobs[j].out = p->ws + d.off_t2;
                 y.jobs[j].in = p->ws + d.off_t2;
                 y.jobs[j].out = p->ws + d.off_t1;
@@ -1373,14 +1481,17 @@ void do_step(rp_plan p, int64_t step, void *const *out) {
                 p->events.push_back(ev);
             }
         }
-        HIP_OK(hipEventRecord(p->events[2 * p->n_recorded], st));
     }
-    enqueue_lagsum(p, st, p->k2_unroll, p->k2_persist);
-    if (p->profile) {
+    // with blocked steps only the pass at a block's first step is timed
+    const int phase = lag_phase(p, step);
+    const bool timed = p->profile && phase == 0;
+    if (timed) HIP_OK(hipEventRecord(p->events[2 * p->n_recorded], st));
+    enqueue_lagsum(p, st, p->k2_unroll, p->k2_persist, phase);
+    if (timed) {
         HIP_OK(hipEventRecord(p->events[2 * p->n_recorded + 1], st));
         p->n_recorded += 1;
     }
-    enqueue_inverse(p, out, st);
+    enqueue_inverse(p, out, st, phase);
     tier_join(p, st);
     enqueue_finish(p, out, st);
     p->next_step += 1;
@@ -1399,36 +1510,44 @@ void do_capture(rp_plan p, const void *const *src, void *const *out) {
     release_graph(p);
     if (!p->capture_stream) HIP_OK(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
     hipStream_t cs = p->capture_stream;
-    HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    try {
-        enqueue_ingest(p, src, cs);
-        tier_fork(p, cs, true);
-        if (p->sur.on) sur_enqueue_moments(p, src, cs);
-        enqueue_lagsum(p, cs, p->k2_unroll, p->k2_persist);
-        enqueue_inverse(p, out, cs);
-        tier_join(p, cs);
-        enqueue_finish(p, out, cs);
-    } catch (...) {
-        p->tier_open = false;
+    // one graph per phase of a block (kb graphs; one without blocking)
+    for (int phase = 0; phase < p->kb; ++phase) {
+        HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_ingest(p, src, cs);
+            tier_fork(p, cs, true);
+            if (p->sur.on) sur_enqueue_moments(p, src, cs);
+            enqueue_lagsum(p, cs, p->k2_unroll, p->k2_persist, phase);
+            enqueue_inverse(p, out, cs, phase);
+            tier_join(p, cs);
+            enqueue_finish(p, out, cs);
+        } catch (...) {
+            p->tier_open = false;
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            release_graph(p);
+            throw;
+        }
         hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(cs, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
+        HIP_OK(hipStreamEndCapture(cs, &g));
+        p->graphs.push_back(g);
+        hipGraphExec_t e = nullptr;
+        HIP_OK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+        p->graph_execs.push_back(e);
     }
-    HIP_OK(hipStreamEndCapture(cs, &p->graph));
-    HIP_OK(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
 }
 
 void do_launch_graph(rp_plan p, int64_t step) {
     need_ws(p);
-    if (!p->graph_exec) fail(RP_ERR_STATE, "no captured step (rp_capture_step)");
+    if (p->graph_execs.empty()) fail(RP_ERR_STATE, "no captured step (rp_capture_step)");
     if (step < 1 || step != p->next_step || p->pushed) {
         char buf[128];
         std::snprintf(buf, sizeof buf, "rp_launch_step(%lld) out of order (expected step %lld >= 1)",
                       (long long)step, (long long)p->next_step);
         fail(RP_ERR_STATE, buf);
     }
-    HIP_OK(hipGraphLaunch(p->graph_exec, p->stream));
+    HIP_OK(hipGraphLaunch(p->graph_execs[size_t(lag_phase(p, step))], p->stream));
     p->next_step += 1;
 }
 
@@ -1469,24 +1588,45 @@ void do_autotune(rp_plan p, int iters, int32_t *best_unroll, int32_t *best_persi
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
+    // the blocked pass writes every accumulator set: only between blocks
+    if (p->kb > 1 && (p->pushed || lag_phase(p, p->next_step) != 0))
+        fail(RP_ERR_STATE, "autotune a plan with blocked steps between blocks");
     double best = 1e300;
-    int bu = p->k2_unroll, bp = p->k2_persist;
+    int bu = p->k2_unroll, bp = p->k2_persist, bc = p->k2b_cached, bo = p->k2b_tile_major;
     try {
-        for (int persist = 0; persist <= 1; ++persist) {
-            for (int unroll : {1, 2, 4}) {
-                enqueue_lagsum(p, st, unroll, persist);   // warm-up
-                HIP_OK(hipEventRecord(e0, st));
-                for (int i = 0; i < iters; ++i) enqueue_lagsum(p, st, unroll, persist);
-                HIP_OK(hipEventRecord(e1, st));
-                HIP_OK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-                if (ms / iters < best) {
-                    best = ms / iters;
-                    bu = unroll;
-                    bp = persist;
+        // the blocked pass also chooses its cache policy and work order
+        const int n_var = p->kb > 1 ? 4 : 1;
+        for (int var = 0; var < n_var; ++var) {
+            if (p->kb > 1) {
+                p->k2b_cached = var & 1;
+                if (p->k2b_tile_major != (var >> 1)) {
+                    p->k2b_tile_major = var >> 1;
+                    order_k2b(p);
                 }
             }
+            for (int persist = 0; persist <= 1; ++persist) {
+                for (int unroll : {1, 2, 4}) {
+                    enqueue_lagsum(p, st, unroll, persist, 0);   // warm-up
+                    HIP_OK(hipEventRecord(e0, st));
+                    for (int i = 0; i < iters; ++i) enqueue_lagsum(p, st, unroll, persist, 0);
+                    HIP_OK(hipEventRecord(e1, st));
+                    HIP_OK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms / iters < best) {
+                        best = ms / iters;
+                        bu = unroll;
+                        bp = persist;
+                        bc = p->k2b_cached;
+                        bo = p->k2b_tile_major;
+                    }
+                }
+            }
+        }
+        p->k2b_cached = bc;
+        if (p->k2b_tile_major != bo) {
+            p->k2b_tile_major = bo;
+            order_k2b(p);
         }
     } catch (...) {
         (void)hipEventDestroy(e0);
@@ -1715,6 +1855,28 @@ rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value) {
             plan->fft_lds = value;
             for (ClassP &K : plan->cls) K.fft_lds = 0;   // the plan's value for every class
             break;
+        case RP_TUNE_LAGSUM_CACHED:
+            if (value != 0 && value != 1) fail(RP_ERR_ARG, "cached must be 0 or 1");
+            plan->k2b_cached = value;
+            break;
+        case RP_TUNE_LAGSUM_TILE_MAJOR:
+            if (value != 0 && value != 1) fail(RP_ERR_ARG, "tile-major must be 0 or 1");
+            plan->k2b_tile_major = value;
+            if (plan->kb > 1) order_k2b(plan);
+            break;
+        case RP_TUNE_LAGSUM_STEPS:
+            if (value != 1 && value != 2 && value != 4 && value != 8)
+                fail(RP_ERR_ARG, "lag-sum steps per pass must be 1, 2, 4 or 8");
+            if (plan->ws) fail(RP_ERR_STATE, "choose the lag-sum steps per pass before rp_bind_workspace");
+            if (value > 1 && plan->p64) fail(RP_ERR_UNSUPPORTED, "blocked lag-sum steps need an FP32 plan");
+            if (value > 1 && plan->sur.on) fail(RP_ERR_UNSUPPORTED, "the surrogate and blocked steps do not combine");
+            if (value > 1 && plan->split_gap > 0)
+                fail(RP_ERR_UNSUPPORTED, "a split history and blocked steps do not combine");
+            plan->kb = value;
+            plan_tables(plan);
+            plan_layout(plan);
+            plan_stats(plan);
+            break;
         default:
             fail(RP_ERR_ARG, "unknown tuning knob");
         }
@@ -1761,6 +1923,9 @@ rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value) {
         switch (knob) {
         case RP_TUNE_LAGSUM_UNROLL: *value = plan->k2_unroll; break;
         case RP_TUNE_LAGSUM_PERSISTENT: *value = plan->k2_persist; break;
+        case RP_TUNE_LAGSUM_STEPS: *value = plan->kb; break;
+        case RP_TUNE_LAGSUM_CACHED: *value = plan->k2b_cached; break;
+        case RP_TUNE_LAGSUM_TILE_MAJOR: *value = plan->k2b_tile_major; break;
         case RP_TUNE_FFT_LDS: *value = plan->fft_lds ? plan->fft_lds : (plan->p64 ? 4096 : 2048); break;
         default: fail(RP_ERR_ARG, "unknown tuning knob");
         }
@@ -1817,6 +1982,7 @@ rp_status rp_history_split(rp_plan plan, int32_t min_gap) {
     return guarded(plan, [&] {
         if (plan->ws) fail(RP_ERR_STATE, "split the history before rp_bind_workspace");
         if (min_gap > 0 && plan->sur.on) fail(RP_ERR_UNSUPPORTED, "the surrogate and a split history do not combine");
+        if (min_gap > 0 && plan->kb > 1) fail(RP_ERR_UNSUPPORTED, "a split history and blocked steps do not combine");
         plan->split_gap = std::max(0, int(min_gap));
         plan_tables(plan);
         plan_layout(plan);

@@ -197,8 +197,19 @@ struct rp_plan_s {
     bool tier_open = false;           // host-tier copies forked and not yet joined
     int n_heads = 0;     // ring heads: domains, judge slots, split rings, real-space rings
     int n_cu = 0;        // compute units of the bound device
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    // captured steps: one graph, or one per phase of a block of kb steps
+    std::vector<hipGraph_t> graphs;
+    std::vector<hipGraphExec_t> graph_execs;
+    // temporal blocking of the lag sum: kb steps per pass (1: off).  k2b is the
+    // pass of a block's first step (one target per thread), k2c[i] adds the
+    // lags m < i of the block's step i (i = 1 .. kb-1)
+    int kb = 1;
+    int k2b_cached = 0;      // blocked pass: cached loads (else non-temporal)
+    int k2b_tile_major = 0;  // blocked pass: items of one frequency tile next to each other (else costliest first)
+    rpot_host::K2Tables k2b;
+    rpot_host::K2Dev k2b_dev;
+    std::vector<rpot_host::K2Tables> k2c;
+    std::vector<rpot_host::K2Dev> k2c_dev;
     hipStream_t capture_stream = nullptr;
 
     std::map<int, size_t> tw64, tw32;   // FFT length -> byte offset of its twiddles
@@ -237,7 +248,8 @@ RadixPlan make_radix(int P);
 const void *tw_ptr(rp_plan p, int P, bool dbl);
 LinePass inv_x(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl);
 LinePass inv_y(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl);
-void build_k2(rp_plan p, int sys, const std::vector<K2Member> &members, K2Tables &T);
+// gmax: targets per group; m_cap: every pair's window clipped to lags <= m_cap.
+void build_k2(rp_plan p, int sys, const std::vector<K2Member> &members, K2Tables &T, int gmax, int m_cap);
 void finish_k2(rp_plan p, K2Tables &T);
 void plan_tables(rp_plan p);
 void plan_layout(rp_plan p);
@@ -268,6 +280,8 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
 void sur_readmit(rp_plan p, double factor);
 void sur_multipole(rp_plan p, int enable);
 void sur_multipole_response(rp_plan p, float *coef);
-void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int));
+// The plain lag sum of every target over the pairs pred admits: groups of up
+// to gmax targets, windows clipped to lags <= m_cap.
+void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int), int gmax = kGroupMax, int m_cap = INT32_MAX);
 
 }  // namespace rpot_host

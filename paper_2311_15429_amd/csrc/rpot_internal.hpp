@@ -193,7 +193,8 @@ struct K2Item {
 
 struct DomDev {
     int64_t ring_off;      // element offset (complex) of the domain's ring [tile][slot][kTile][4]
-    int64_t acc_off;       // element offset (complex) of the domain's accumulator
+    int64_t acc_off;       // element offset (complex) of the domain's accumulator (set 0)
+    int64_t acc_set_stride;   // complex elements between the accumulator sets of a blocked lag sum
     int64_t scale_off;     // float offset of the ring's scales: [depth][4] (FP16/BF16),
                            // [tile][depth][4] (I16)
     int32_t depth;
@@ -216,6 +217,9 @@ struct K2Args {
     int *counter;          // persistent launch: next work item
     int n_items;
     int n_dom;
+    int acc_set;           // accumulator set written (0 unless steps are blocked)
+    int accumulate;        // 1: add to the accumulator set instead of overwriting it
+    int cached;            // blocked pass: cached loads instead of non-temporal ones
 };
 
 // ---------------------------------------------------------------------------
@@ -229,6 +233,11 @@ int zfwd_lines_per_block(int Pz, int prec64);
 void launch_lagsum(const K2Args &a, int prec64, int ring_fmt, int tg, int unroll, int grid_persist,
                    hipStream_t st);
 int lagsum_blocks_per_cu(int prec64, int ring_fmt, int tg, int unroll);
+// Lag sum of kb steps in one pass (FP32 paths, one target per thread, kb = 2,
+// 4 or 8): every item writes the kb accumulator sets of its target.  unroll:
+// snapshots whose loads are issued before their products (1, 2 or 4).
+void launch_lagsum_block(const K2Args &a, int ring_fmt, int kb, int unroll, int grid_persist, hipStream_t st);
+int lagsum_block_blocks_per_cu(int ring_fmt, int kb, int unroll);
 // Per-snapshot ring scales: for each job, scales[head*4 + mu] =
 // 2^(e-15) with npts * max_blocks zmax[b][mu] <= 2^e (1 when the max is 0).
 struct ScaleJob {

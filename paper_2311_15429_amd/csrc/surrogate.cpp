@@ -560,6 +560,7 @@ void sur_configure(rp_plan p, double far_factor, int n_lags, const int32_t *audi
         U = SurrogateH{};
     } else {
         if (!p->target.empty()) fail(RP_ERR_UNSUPPORTED, "the surrogate and a target subset do not combine");
+        if (p->kb > 1) fail(RP_ERR_UNSUPPORTED, "the surrogate and blocked lag-sum steps do not combine");
         if (!std::isfinite(far_factor)) fail(RP_ERR_ARG, "far_factor must be finite");
         if (p->split_gap > 0) fail(RP_ERR_UNSUPPORTED, "the surrogate and a split history do not combine");
         if (p->p64) fail(RP_ERR_UNSUPPORTED, "the surrogate runs with FP32 outputs (not RP_FP64)");

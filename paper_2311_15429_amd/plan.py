@@ -199,7 +199,8 @@ class Plan:
             pad = self.info(n, n)[2]
             classes[(d, pad)] = classes.get((d, pad), 0) + 1
         sig = ";".join(f"{d[0]}x{d[1]}x{d[2]}/{p[0]}x{p[1]}x{p[2]}*{c}" for (d, p), c in sorted(classes.items()))
-        return f"{torch.cuda.get_device_name()}|{self.precision}|{sig}|systems={self.n_systems}"
+        return (f"{torch.cuda.get_device_name()}|{self.precision}|{sig}|systems={self.n_systems}"
+                f"|steps={self.get_tuning('lagsum_steps')}")
 
     def autotune(self, iters=3, cache=None):
         """Time every lag-sum schedule and, per shape class, every line-pass
@@ -217,8 +218,9 @@ class Plan:
             except (OSError, ValueError):
                 rec = None
             if rec:
-                for k in ("lagsum_unroll", "lagsum_persistent", "fft_lds"):
-                    self.set_tuning(k, rec[k])
+                for k in ("lagsum_unroll", "lagsum_persistent", "fft_lds", "lagsum_cached", "lagsum_tile_major"):
+                    if k in rec:
+                        self.set_tuning(k, rec[k])
                 for c, v in enumerate(rec.get("fft_lds_per_class", [])):
                     self.set_class_tuning(c, "fft_lds", v)
                 return dict(rec, cached=True)
@@ -226,6 +228,8 @@ class Plan:
         _lib.check(self._lib, self._h, self._lib.rp_autotune(self._h, int(iters), ctypes.byref(u),
                                                              ctypes.byref(pe), ctypes.byref(ms)))
         res = {"lagsum_unroll": int(u.value), "lagsum_persistent": int(pe.value),
+               "lagsum_steps": self.get_tuning("lagsum_steps"), "lagsum_cached": self.get_tuning("lagsum_cached"),
+               "lagsum_tile_major": self.get_tuning("lagsum_tile_major"),
                "fft_lds": self.get_tuning("fft_lds"),
                "fft_lds_per_class": [c["fft_lds"] for c in self.classes()], "lagsum_ms": float(ms.value)}
         if cache:
