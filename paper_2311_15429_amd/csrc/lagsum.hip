@@ -326,10 +326,11 @@ __device__ __forceinline__ void lagsum_block_item(const K2Args &a, int item_inde
         int64_t scale_off = 0;
         if (FMT == RING_F16 || FMT == RING_BF16) scale_off = a.doms[R.n].scale_off;
         if (FMT == RING_I16) scale_off = a.doms[R.n].scale_off + int64_t(tile) * depth * 4;
-        const int d0 = max(0, m_lo - (KB - 1));
+        // the walk starts kb - 1 ages below the window, at the newest
+        // snapshot at the latest; age d sits in slot head - (d - m_base)
+        const int d0 = max(R.m_base, m_lo - (KB - 1));
         const int n_it = m_hi - d0 + 1;
-        // age d sits in slot head - d (mod depth): the ring holds lags from 0
-        int32_t slot = a.head[R.n] - d0;
+        int32_t slot = a.head[R.n] - (d0 - R.m_base);
         if (slot < 0) slot += depth;
 
         auto load_g = [&](int m) -> Cx<float> {

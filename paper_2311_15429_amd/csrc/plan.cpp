@@ -252,8 +252,10 @@ void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables 
             // one record per ring that holds part of the window: the source's
             // ring (lags from 0) and its split rings (lags from their start)
             const DomainP &dn = p->dom[n];
-            std::vector<std::array<int, 3>> rings{{n, 0, dn.depth - 1}};
-            for (int v : dn.vr) rings.push_back({p->vring[v].idx, p->vring[v].lo, p->vring[v].hi});
+            // (ring, first lag summed from it, last lag, age of its newest snapshot)
+            std::vector<std::array<int, 4>> rings{{n, 0, dn.depth - 1, 0}};
+            for (int v : dn.vr)
+                rings.push_back({p->vring[v].idx, p->vring[v].lag_lo, p->vring[v].hi, p->vring[v].lo});
             for (const auto &rg : rings) {
                 const int a = std::max(R.m_min, rg[1]), b = std::min(R.m_max, rg[2]);
                 if (a > b) continue;
@@ -261,7 +263,7 @@ void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables 
                 Rs.n = rg[0];
                 Rs.m_min = a;
                 Rs.m_max = b;
-                Rs.m_base = rg[1];
+                Rs.m_base = rg[3];
                 Rs.mask_off = R.mask_off + (a - R.m_min);
                 for (int t = 0; t < kGroupMax; ++t) T.pairs.push_back(Qs[t]);
                 T.srcs.push_back(Rs);
@@ -389,12 +391,21 @@ void plan_tables(rp_plan p) {
         // ring.  The main ring holds lag 0 (the ingest writes there); when the
         // first window starts split_gap or more lags later (a source that is
         // not a target reaches only other domains), it keeps lag 0 alone
+        // With kb lag-sum steps per pass a ring also stores the kb - 1 ages
+        // below its first lag (the blocked pass reads them); gaps are counted
+        // to that widened start, which stays at lag 2 or later.
         std::sort(iv.begin(), iv.end());
-        std::vector<std::pair<int, int>> win{{0, iv[0].second}};
-        if (iv[0].first - 1 >= p->split_gap) win = {{0, 0}, iv[0]};
+        const int wid = p->kb - 1;
+        struct Win {
+            int lo, hi, lag_lo;   // stored ages lo .. hi; lags summed from lag_lo
+        };
+        std::vector<Win> win{{0, iv[0].second, 0}};
+        if (iv[0].first - wid - 1 >= p->split_gap) win = {{0, 0, 0}, {iv[0].first - wid, iv[0].second, iv[0].first}};
         for (size_t i = 1; i < iv.size(); ++i) {
-            if (iv[i].first - win.back().second - 1 >= p->split_gap) win.push_back(iv[i]);
-            else win.back().second = std::max(win.back().second, iv[i].second);
+            if (iv[i].first - wid - win.back().hi - 1 >= p->split_gap)
+                win.push_back({iv[i].first - wid, iv[i].second, iv[i].first});
+            else
+                win.back().hi = std::max(win.back().hi, iv[i].second);
         }
         if (win.size() < 2) continue;
         // split only where the spectra saved outweigh the real-space ring (in
@@ -403,19 +414,20 @@ void plan_tables(rp_plan p) {
         const SystemP &S = p->sys[d.sys];
         const double spec_slot = double(S.Cpad) * 4 * p->ring_esz;
         int kept = 0;
-        for (const auto &w : win) kept += w.second - w.first + 1;
+        for (const auto &w : win) kept += w.hi - w.lo + 1;
         const double saved = double(d.span - kept) * spec_slot;
         const double scratch = double(d.N[0]) * (d.N[1] + S.P[1]) * S.Hz * 4 * p->csz;
-        const double real_slots = p->hist_host ? double(win.size()) : double(win.back().first + 1);
+        const double real_slots = p->hist_host ? double(win.size()) : double(win.back().lo + 1);
         const double cost = real_slots * 4 * double(d.npts) * p->tsz + double(win.size() - 1) * scratch;
         if (saved <= cost) continue;
-        d.depth = win[0].second + 1;
-        d.d1 = win.back().first + 1;
+        d.depth = win[0].hi + 1;
+        d.d1 = win.back().lo + 1;
         for (size_t w = 1; w < win.size(); ++w) {
             VRingP v;
             v.n = n;
-            v.lo = win[w].first;
-            v.hi = win[w].second;
+            v.lo = win[w].lo;
+            v.hi = win[w].hi;
+            v.lag_lo = win[w].lag_lo;
             v.W = v.hi - v.lo + 1;
             d.vr.push_back(int(p->vring.size()));
             p->vring.push_back(v);
@@ -691,7 +703,7 @@ double k2b_bytes(rp_plan p) {
         for (int si = G.src_begin; si < G.src_end; ++si) {
             const K2Src &R = p->k2b.srcs[size_t(si)];
             if (R.m_max < R.m_min) continue;
-            const int d0 = std::max(0, R.m_min - (p->kb - 1));
+            const int d0 = std::max(R.m_base, R.m_min - (p->kb - 1));
             per_k += double(R.m_max - d0 + 1) * 4.0 * p->ring_esz + double(R.m_max - R.m_min + 1) * p->spec_csz;
         }
         per_k += double(G.n_members) * p->kb * 4 * p->csz;
@@ -1870,8 +1882,6 @@ rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value) {
             if (plan->ws) fail(RP_ERR_STATE, "choose the lag-sum steps per pass before rp_bind_workspace");
             if (value > 1 && plan->p64) fail(RP_ERR_UNSUPPORTED, "blocked lag-sum steps need an FP32 plan");
             if (value > 1 && plan->sur.on) fail(RP_ERR_UNSUPPORTED, "the surrogate and blocked steps do not combine");
-            if (value > 1 && plan->split_gap > 0)
-                fail(RP_ERR_UNSUPPORTED, "a split history and blocked steps do not combine");
             plan->kb = value;
             plan_tables(plan);
             plan_layout(plan);
@@ -1982,7 +1992,6 @@ rp_status rp_history_split(rp_plan plan, int32_t min_gap) {
     return guarded(plan, [&] {
         if (plan->ws) fail(RP_ERR_STATE, "split the history before rp_bind_workspace");
         if (min_gap > 0 && plan->sur.on) fail(RP_ERR_UNSUPPORTED, "the surrogate and a split history do not combine");
-        if (min_gap > 0 && plan->kb > 1) fail(RP_ERR_UNSUPPORTED, "a split history and blocked steps do not combine");
         plan->split_gap = std::max(0, int(min_gap));
         plan_tables(plan);
         plan_layout(plan);

@@ -54,8 +54,12 @@ struct DomainP {
 };
 
 // A later lag window [lo, hi] of source n with its own spectral ring.
+// It stores the snapshots of ages lo .. hi (lo below lag_lo by kb - 1 with
+// blocked lag-sum steps, whose pass reads kb - 1 younger ages); the lags
+// lag_lo .. hi of the source's pairs are summed from it.
 struct VRingP {
     int n = 0, lo = 0, hi = 0, W = 1;
+    int lag_lo = 0;
     int idx = 0;             // ring / head slot index
     size_t off_ring = 0, off_scales = 0, off_zmax = 0, off_t1 = 0, off_t2 = 0;
     size_t off_stage = 0;    // host tier: the snapshot the next step transforms again

@@ -41,15 +41,17 @@ class Wave:
         return sum(u.workspace for u in self.units)
 
 
-def _unit_plan(dims, origins, h, dt, c, precision, local_targets, split_gap):
+def _unit_plan(dims, origins, h, dt, c, precision, local_targets, split_gap, lagsum_steps=1):
     p = Plan(dims, origins, h, dt, c, precision=precision)
     p.set_targets(local_targets)
+    if lagsum_steps > 1:
+        p.set_tuning("lagsum_steps", lagsum_steps)
     if split_gap > 0:
         p.history_split(split_gap)
     return p
 
 
-def plan_units(dims, origins, system_id, h, dt, c, precision, budget, split_gap=8):
+def plan_units(dims, origins, system_id, h, dt, c, precision, budget, split_gap=8, lagsum_steps=1):
     """Units of every system: its targets grouped by grid shape, a group
     halved (along the widest spread of its centres) until its plan fits
     `budget` bytes.  A single target that does not fit raises ValueError."""
@@ -67,7 +69,8 @@ def plan_units(dims, origins, system_id, h, dt, c, precision, budget, split_gap=
         todo = [shapes[key] for key in sorted(shapes)]
         while todo:
             group = todo.pop(0)
-            p = _unit_plan(dims[doms], origins[doms], h, dt, c, precision, [local[g] for g in group], split_gap)
+            p = _unit_plan(dims[doms], origins[doms], h, dt, c, precision, [local[g] for g in group], split_gap,
+                           lagsum_steps)
             ws, st = p.workspace_bytes, p.stats()
             p.close()
             if ws <= budget:
@@ -111,13 +114,16 @@ def wave_layout(wave):
     return doms, sids, targets
 
 
-def wave_plan(wave, dims, origins, h, dt, c, precision, split_gap=8, stream=None):
-    """The batched plan of one wave (targets set, history split)."""
+def wave_plan(wave, dims, origins, h, dt, c, precision, split_gap=8, stream=None, lagsum_steps=1):
+    """The batched plan of one wave (targets set, lag-sum steps per pass,
+    history split)."""
     dims = np.asarray(dims).reshape(-1, 3)
     origins = np.asarray(origins).reshape(-1, 3)
     doms, sids, targets = wave_layout(wave)
     p = Plan(dims[doms], origins[doms], h, dt, c, precision=precision, system_id=sids, stream=stream)
     p.set_targets(targets)
+    if lagsum_steps > 1:
+        p.set_tuning("lagsum_steps", lagsum_steps)
     if split_gap > 0:
         p.history_split(split_gap)
     return p, doms, targets

@@ -198,3 +198,19 @@ def test_split_history_graph_replay_is_bitwise_identical(precision, host):
         for a, b in zip(res[0], other):
             for x, y in zip(a, b):
                 assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision,kb,host", [("fp32", 4, False), ("fp32", 8, False), ("fp32_ring_i16", 8, False),
+                                               ("fp32", 8, True)])
+def test_split_history_with_blocked_steps_is_bitwise_identical(precision, kb, host):
+    """With kb lag-sum steps per pass every split ring also keeps the kb - 1
+    ages below its window; the split plan still gives the unsplit plan's bits."""
+    system = _pair()
+    L = 60
+    S = sy.sample_sources(system, range(L + 1))
+    a = run_gpu(system, precision, S, tune={"lagsum_steps": kb})
+    b = run_gpu(system, precision, S, tune={"lagsum_steps": kb}, split=8, host=host)
+    for l in a:
+        for x, y in zip(a[l], b[l]):
+            assert np.array_equal(x, y), l
+    log(f"{precision}, {kb} steps per pass{', host tier' if host else ''}: split bitwise identical")

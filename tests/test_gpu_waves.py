@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _units(system, precision, split_gap):
+def _units(system, precision, split_gap, kb=1):
     """Units and waves under a budget that halves the largest target groups
     and needs several waves (no single target above it)."""
     from paper_2311_15429_amd import waves as W
@@ -25,24 +25,26 @@ def _units(system, precision, split_gap):
     for k in sorted(set(sid.tolist())):
         doms = list(np.where(sid == k)[0])
         for t in range(len(doms)):
-            p = W._unit_plan(dims[doms], org[doms], system.h, system.dt, system.c, precision, [t], split_gap)
+            p = W._unit_plan(dims[doms], org[doms], system.h, system.dt, system.c, precision, [t], split_gap, kb)
             single = max(single, p.workspace_bytes)
             p.close()
-    big = W.plan_units(dims, org, sid, system.h, system.dt, system.c, precision, budget=1 << 60, split_gap=split_gap)
+    big = W.plan_units(dims, org, sid, system.h, system.dt, system.c, precision, budget=1 << 60, split_gap=split_gap,
+                       lagsum_steps=kb)
     groups = max(u.workspace for u in big if len(u.targets) > 1)
     budget = max(single, int(0.75 * groups))
-    units = W.plan_units(dims, org, sid, system.h, system.dt, system.c, precision, budget=budget, split_gap=split_gap)
+    units = W.plan_units(dims, org, sid, system.h, system.dt, system.c, precision, budget=budget, split_gap=split_gap,
+                         lagsum_steps=kb)
     return big, units, W.pack_waves(units, budget), budget
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
-def test_waves_of_target_groups_match_the_oracle(precision, tol):
+@pytest.mark.parametrize("precision,tol,kb", [("fp64", 1e-10, 1), ("fp32", 2e-5, 1), ("fp32", 2e-5, 4)])
+def test_waves_of_target_groups_match_the_oracle(precision, tol, kb):
     from paper_2311_15429_amd import waves as W
     system = _small_batch(3, 5)
     L = 24
     check = [6, 15, 24]
     S = sy.sample_sources(system, range(L + 1))
-    big, units, waves, budget = _units(system, precision, split_gap=2)
+    big, units, waves, budget = _units(system, precision, split_gap=2, kb=kb)
     assert len(waves) >= 2 and len(units) > len(big)       # groups were halved
     covered = sorted(t for u in units for t in u.targets)
     assert covered == list(range(len(system.domains)))
@@ -50,7 +52,7 @@ def test_waves_of_target_groups_match_the_oracle(precision, tol):
     dt = torch.float64 if precision == "fp64" else torch.float32
     for wi, wave in enumerate(waves):
         p, doms, targets = W.wave_plan(wave, system.dims, system.origins, system.h, system.dt, system.c,
-                                       precision, split_gap=2, stream=torch.cuda.current_stream())
+                                       precision, split_gap=2, stream=torch.cuda.current_stream(), lagsum_steps=kb)
         assert p.workspace_bytes <= budget
         p.bind()
         p.set_green_kernels()
@@ -85,4 +87,4 @@ def test_waves_of_target_groups_match_the_oracle(precision, tol):
             e = rel_err([got[l][i] for i in idx], r)
             worst = max(worst, float(e.max()))
             assert np.all(e <= tol), (s, l, e)
-    log(f"waves {precision}: {len(units)} units in {len(waves)} waves, worst rel err {worst:.2e}")
+    log(f"waves {precision}, {kb} steps per pass: {len(units)} units in {len(waves)} waves, worst rel err {worst:.2e}")
