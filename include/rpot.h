@@ -354,6 +354,12 @@ rp_status rp_mlp_forward(rp_mlp mlp, const float *x, int32_t batch, float *y);
 rp_status rp_mlp_loss_grad(rp_mlp mlp, const float *x, const float *t, int32_t batch, float *loss, float *grad);
 /* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch; loss of the batch before the step */
 rp_status rp_mlp_train_step(rp_mlp mlp, const float *x, const float *t, int32_t batch, float lr, float *loss);
+/* Relative RMS of the network on n rows (device x [n][n_in] as the network
+ * reads them, t [n][n_out] unscaled targets, out_scale [n_out] device):
+ * sqrt(sum (y * out_scale - t)^2 / sum t^2), FP64 sums, in chunks of
+ * max_batch.  Synchronises the stream; *rel is a host value. */
+rp_status rp_mlp_relative_rms(rp_mlp mlp, const float *x, const float *t, int64_t n, const float *out_scale,
+                              double *rel);
 rp_status rp_mlp_destroy(rp_mlp mlp);
 const char *rp_mlp_last_error(rp_mlp mlp);
 
@@ -522,6 +528,35 @@ rp_status rp_surrogate_pair_response(rp_plan plan, float *coef, float *resid);
 rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t *n_fallback, double *worst,
                              int32_t *n_readmitted);
 rp_status rp_surrogate_readmit(rp_plan plan, double factor);
+
+/*
+ * Training data of the network, from the plain method (the teacher).
+ * rp_surrogate_teacher: for the audited far pairs of the last completed step
+ *   (rows in far-pair order, as rp_surrogate_pair_response): x [n_aud][n_in]
+ *   the network inputs (as rp_surrogate_features gives them: times the
+ *   attached network's in_scale, 1 without a network), t [n_aud][80] the
+ *   targets: the least-squares frame coefficients of the plain pair field
+ *   times the centre distance |c_s - c_n| (the network's output times
+ *   out_scale reproduces them); residual != 0 subtracts the multipole terms
+ *   (rp_surrogate_multipole_response) first.  Device arrays, asynchronous.
+ * rp_surrogate_data_scales: scales of n training rows (device x [n][n_in],
+ *   t [n][80], n_in = 132 n_lags + 2): in_scale[k] = 1 / RMS of moment k over
+ *   the rows and lags of the unmodulated block H (the first 22 n_lags
+ *   inputs), out_scale[c * 20 + b] = RMS of component c's 20 coefficients over
+ *   the rows; an all-zero column gets 1.  FP64 sums in a fixed order.
+ *   in_scale [22], out_scale [80]: device arrays.  Asynchronous on hip_stream.
+ * rp_surrogate_scale_data: in place, every moment of the six input blocks
+ *   times in_scale (the two geometry inputs unchanged) and every target over
+ *   out_scale: the rows the network trains on.  x or t may be NULL (with its
+ *   scale): only the other is scaled.
+ * Both return RP_ERR_ARG on a null pointer, n < 1 or n_lags outside
+ * 1 .. 1024, RP_ERR_DEVICE if a launch fails.
+ */
+rp_status rp_surrogate_teacher(rp_plan plan, float *x, float *t, int32_t residual);
+rp_status rp_surrogate_data_scales(const float *x, const float *t, int64_t n, int32_t n_lags, float *in_scale,
+                                   float *out_scale, void *hip_stream);
+rp_status rp_surrogate_scale_data(float *x, float *t, int64_t n, int32_t n_lags, const float *in_scale,
+                                  const float *out_scale, void *hip_stream);
 
 /*
  * Model response of the sources: the steps either side of the potential

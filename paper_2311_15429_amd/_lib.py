@@ -24,7 +24,8 @@ EXPORTS = ["rp_plan_domains", "rp_plan_targets", "rp_workspace_bytes", "rp_bind_
            "rp_osc_create", "rp_osc_workspace_bytes", "rp_osc_bind", "rp_osc_set_state", "rp_osc_sources",
            "rp_osc_step", "rp_osc_state", "rp_osc_destroy", "rp_osc_last_error", "rp_history_split",
            "rp_history_host", "rp_history_host_bytes", "rp_bind_history_host",
-           "rp_class_info", "rp_set_class_tuning", "rp_get_class_tuning", "rp_read_stream"]
+           "rp_class_info", "rp_set_class_tuning", "rp_get_class_tuning", "rp_read_stream",
+           "rp_surrogate_teacher", "rp_surrogate_data_scales", "rp_surrogate_scale_data", "rp_mlp_relative_rms"]
 TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2, "fft_lds": 4, "lagsum_steps": 8, "lagsum_cached": 16,
         "lagsum_tile_major": 32}
 
@@ -65,6 +66,10 @@ def load():
     lib.rp_read_stream.argtypes = [vp, sz, vp, i32, i32, vp]
     lib.rp_bind_workspace.argtypes = [vp, vp, sz]
     lib.rp_bind_workspace_static.argtypes = [vp]
+    lib.rp_surrogate_teacher.argtypes = [vp, vp, vp, i32]
+    lib.rp_surrogate_data_scales.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    lib.rp_surrogate_scale_data.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+    lib.rp_mlp_relative_rms.argtypes = [vp, vp, vp, i64, vp, P(ctypes.c_double)]
     lib.rp_set_green_kernels.argtypes = [vp]
     lib.rp_push_sources.argtypes = [vp, i64, P(vp)]
     lib.rp_retarded_step.argtypes = [vp, i64, P(vp)]

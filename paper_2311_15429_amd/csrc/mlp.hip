@@ -163,6 +163,45 @@ __global__ void k_sum_parts(const float *part, int n, float scale, float *loss) 
     if (threadIdx.x == 0) *loss = red[0] * scale;
 }
 
+// Relative RMS of the network: per block FP64 partial sums of
+// (y * scale - t)^2 and t^2 over a chunk, then one block adds them (fixed
+// order) to the running totals tot[0], tot[1].
+__global__ void k_rms_parts(const float *y, const float *t, const float *scale, int n_out, int64_t n, double *part) {
+    __shared__ double r0[256], r1[256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        const double tv = t[i];
+        const double d = double(y[i]) * double(scale[i % n_out]) - tv;
+        a += d * d;
+        b += tv * tv;
+    }
+    r0[threadIdx.x] = a;
+    r1[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            r0[threadIdx.x] += r0[threadIdx.x + o];
+            r1[threadIdx.x] += r1[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = r0[0];
+        part[2 * blockIdx.x + 1] = r1[0];
+    }
+}
+
+__global__ void k_rms_total(const double *part, int nb, double *tot, int first) {
+    if (threadIdx.x != 0) return;
+    double a = first ? 0.0 : tot[0], b = first ? 0.0 : tot[1];
+    for (int i = 0; i < nb; ++i) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    tot[0] = a;
+    tot[1] = b;
+}
+
 // dz = dh * (1 - h^2)  (tanh derivative), in place on dh
 __global__ void k_tanh_back(float *dh, const float *h, int64_t n) {
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
@@ -208,7 +247,7 @@ struct rp_mlp_s {
     size_t ws_bytes = 0;
     int64_t n_params = 0;
     size_t off_w = 0, off_g = 0, off_m = 0, off_v = 0, off_h1 = 0, off_h2 = 0, off_y = 0, off_dy = 0, off_d2 = 0,
-           off_d1 = 0, off_part = 0, off_split = 0;
+           off_d1 = 0, off_part = 0, off_split = 0, off_rms = 0;
     int64_t step = 0;
     std::string err;
     float *W1() { return f(off_w); }
@@ -353,6 +392,7 @@ rp_status rp_mlp_create(rp_mlp *out, int32_t n_in, int32_t n_hidden, int32_t n_o
     m->off_d2 = alloc(BH);
     m->off_d1 = alloc(BH);
     m->off_part = alloc(256 * 4 + 16);
+    m->off_rms = alloc((2 * 256 + 2) * 8);
     m->off_split = alloc(size_t(kMaxSplit) * max_batch * std::max(n_hidden, n_out) * 4);
     m->ws_bytes = off;
     *out = m;
@@ -413,6 +453,33 @@ rp_status rp_mlp_forward(rp_mlp m, const float *x, int32_t batch, float *y) {
         check_batch(m, batch);
         if (!x || !y) mfail(RP_ERR_ARG, "null pointer");
         forward(m, x, batch, y, m->stream);
+    });
+}
+
+rp_status rp_mlp_relative_rms(rp_mlp m, const float *x, const float *t, int64_t n, const float *out_scale,
+                              double *rel) {
+    return mguard(m, [&] {
+        need_bound(m);
+        if (!x || !t || !out_scale || !rel) mfail(RP_ERR_ARG, "null pointer");
+        if (n < 1) mfail(RP_ERR_ARG, "n must be >= 1");
+        hipStream_t st = m->stream;
+        double *part = reinterpret_cast<double *>(m->ws + m->off_rms);
+        double *tot = part + 2 * 256;
+        float *y = m->f(m->off_y);
+        for (int64_t i0 = 0; i0 < n; i0 += m->max_batch) {
+            const int B = int(std::min<int64_t>(m->max_batch, n - i0));
+            forward(m, x + i0 * m->n_in, B, y, st);
+            const int64_t ny = int64_t(B) * m->n_out;
+            const int nb = std::min(nblocks(ny), 256);
+            hipLaunchKernelGGL(k_rms_parts, dim3(nb), dim3(256), 0, st, y, t + i0 * m->n_out, out_scale, m->n_out,
+                               ny, part);
+            hipLaunchKernelGGL(k_rms_total, dim3(1), dim3(64), 0, st, part, nb, tot, i0 == 0 ? 1 : 0);
+        }
+        double h[2] = {0.0, 0.0};
+        if (hipMemcpyAsync(h, tot, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            mfail(RP_ERR_DEVICE, "reading the relative RMS back failed");
+        *rel = std::sqrt(h[0] / std::max(h[1], 1e-300));
     });
 }
 

@@ -2089,6 +2089,10 @@ rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t
     return guarded(plan, [&] { sur_judge(plan, out, tol, n_fallback, worst, n_readmitted); });
 }
 
+rp_status rp_surrogate_teacher(rp_plan plan, float *x, float *t, int32_t residual) {
+    return guarded(plan, [&] { sur_teacher(plan, x, t, residual); });
+}
+
 rp_status rp_surrogate_readmit(rp_plan plan, double factor) {
     return guarded(plan, [&] { sur_readmit(plan, factor); });
 }

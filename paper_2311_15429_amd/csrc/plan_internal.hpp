@@ -156,6 +156,7 @@ struct SurrogateH {
     size_t off_order = 0, off_tbeg = 0, off_mats = 0, off_inscale = 0, off_outscale = 0;
     size_t off_jacc = 0, off_jt1 = 0, off_jt2 = 0, off_jF = 0, off_jcoef = 0, off_jres = 0;
     size_t off_budget = 0, off_fail = 0, off_aud = 0, off_jcb = 0;
+    size_t off_rowfar = 0, off_tcoef = 0;   // teacher rows: far-pair index per audited row, multipole terms
     size_t jt1_elems = 0, jt2_elems = 0, jF_elems = 0;
     std::vector<size_t> jacc_off;  // judge slot -> byte offset of its accumulator
     std::vector<int> synth_targets;  // domains that are the target of a far pair
@@ -284,6 +285,7 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
 void sur_readmit(rp_plan p, double factor);
 void sur_multipole(rp_plan p, int enable);
 void sur_multipole_response(rp_plan p, float *coef);
+void sur_teacher(rp_plan p, float *x, float *t, int residual);
 // The plain lag sum of every target over the pairs pred admits: groups of up
 // to gmax targets, windows clipped to lags <= m_cap.
 void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int), int gmax = kGroupMax, int m_cap = INT32_MAX);

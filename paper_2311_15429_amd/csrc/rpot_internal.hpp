@@ -444,6 +444,26 @@ struct CorrArgs {
 };
 void launch_moments(const MomentArgs &a, hipStream_t st);
 void launch_features(const FeatArgs &a, hipStream_t st);
+struct TeacherArgs {
+    const FarPair *pairs;
+    const int32_t *row_far;    // [n_rows]: far-pair index of each audited row
+    const float *x_all;        // [n_far][n_in] network inputs of every far pair
+    float *x_out;              // [n_rows][n_in]
+    float *t;                  // [n_rows][kNOut] pair coefficients in, targets out
+    const float *sub;          // [n_rows][kNOut] subtracted first, or null
+    int n_rows, n_in;
+};
+void launch_teacher(const TeacherArgs &a, hipStream_t st);
+struct ScaleDataArgs {
+    const float *x, *t;        // scales: x [n][n_in], t [n][kNOut]
+    float *in_scale, *out_scale;
+    float *x_rw, *t_rw;        // scaling in place
+    const float *in_scale_c, *out_scale_c;
+    int64_t n;
+    int n_in, n_lags;
+};
+void launch_data_scales(const ScaleDataArgs &a, hipStream_t st);
+void launch_scale_data(const ScaleDataArgs &a, hipStream_t st);
 void launch_xform(const XformArgs &a, hipStream_t st);
 void launch_coef_sum(const CoefArgs &a, hipStream_t st);
 void launch_synthesize(const SynthArgs &a, hipStream_t st);

@@ -379,6 +379,8 @@ void sur_layout(rp_plan p, size_t &off) {
     U.off_budget = alloc(nd * 4 * 4);
     U.off_fail = alloc(na * 4);
     U.off_aud = alloc(na * 4);
+    U.off_rowfar = alloc(na * 4);
+    U.off_tcoef = alloc(na * kNOut * 4);
 }
 
 void sur_bind(rp_plan p) {
@@ -410,6 +412,14 @@ void sur_bind(rp_plan p) {
         HIP_OK(hipMemcpy(p->ws + U.off_mats, U.mats.data(), U.mats.size() * 4, hipMemcpyHostToDevice));
     }
     if (!aud.empty()) HIP_OK(hipMemcpy(p->ws + U.off_aud, aud.data(), aud.size() * 4, hipMemcpyHostToDevice));
+    {
+        // the audited far pairs in far-pair order: the rows of the teacher data
+        std::vector<int32_t> rowfar;
+        for (size_t f = 0; f < U.pairs.size(); ++f)
+            if (U.pairs[f].audited) rowfar.push_back(int32_t(f));
+        if (!rowfar.empty())
+            HIP_OK(hipMemcpy(p->ws + U.off_rowfar, rowfar.data(), rowfar.size() * 4, hipMemcpyHostToDevice));
+    }
     HIP_OK(hipMemcpy(p->ws + U.off_inscale, ones.data(), kNFeat * 4, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(p->ws + U.off_outscale, ones.data(), kNOut * 4, hipMemcpyHostToDevice));
     {
@@ -648,6 +658,31 @@ void sur_multipole_response(rp_plan p, float *coef) {
     check_launch();
 }
 
+void sur_teacher(rp_plan p, float *x, float *t, int residual) {
+    need_ready(p);
+    SurrogateH &U = p->sur;
+    if (!x || !t) fail(RP_ERR_ARG, "null output");
+    if (U.aud.empty()) return;
+    hipStream_t st = p->stream;
+    // every far pair's inputs into the inference buffer, the plain pair
+    // responses (rows in far-pair order of the audited pairs) into t
+    launch_features(feat_args(p, p->at<float>(U.off_x), -1), st);
+    check_launch();
+    sur_pair_response(p, t, p->at<float>(U.off_jres));
+    if (residual) sur_multipole_response(p, p->at<float>(U.off_tcoef));
+    TeacherArgs a{};
+    a.pairs = p->at<FarPair>(U.off_fpairs);
+    a.row_far = p->at<int32_t>(U.off_rowfar);
+    a.x_all = p->at<float>(U.off_x);
+    a.x_out = x;
+    a.t = t;
+    a.sub = residual ? p->at<float>(U.off_tcoef) : nullptr;
+    a.n_rows = int(U.aud.size());
+    a.n_in = U.n_in;
+    launch_teacher(a, st);
+    check_launch();
+}
+
 void sur_features(rp_plan p, float *x) {
     need_ready(p);
     if (!x) fail(RP_ERR_ARG, "x is null");
@@ -825,3 +860,48 @@ void sur_readmit(rp_plan p, double factor) {
 }
 
 }  // namespace rpot_host
+
+extern "C" {
+
+rp_status rp_surrogate_data_scales(const float *x, const float *t, int64_t n, int32_t n_lags, float *in_scale,
+                                   float *out_scale, void *hip_stream) {
+    if (!x || !t || !in_scale || !out_scale || n < 1 || n_lags < 1 || n_lags > 1024) return RP_ERR_ARG;
+    ScaleDataArgs a{};
+    a.x = x;
+    a.t = t;
+    a.in_scale = in_scale;
+    a.out_scale = out_scale;
+    a.n = n;
+    a.n_lags = n_lags;
+    a.n_in = kNBlocks * kNFeat * n_lags + kNGeo;
+    launch_data_scales(a, static_cast<hipStream_t>(hip_stream));
+    return hipGetLastError() == hipSuccess ? RP_OK : RP_ERR_DEVICE;
+}
+
+rp_status rp_surrogate_scale_data(float *x, float *t, int64_t n, int32_t n_lags, const float *in_scale,
+                                  const float *out_scale, void *hip_stream) {
+    if ((!x && !t) || (x && !in_scale) || (t && !out_scale) || n < 1 || n_lags < 1 || n_lags > 1024)
+        return RP_ERR_ARG;
+    if (n > int64_t(65535)) {
+        // one launch row per sample: several launches of at most 65535 rows
+        for (int64_t i0 = 0; i0 < n; i0 += 65535) {
+            const rp_status s = rp_surrogate_scale_data(
+                x ? x + i0 * (int64_t(kNBlocks) * kNFeat * n_lags + kNGeo) : nullptr, t ? t + i0 * kNOut : nullptr,
+                std::min<int64_t>(65535, n - i0), n_lags, in_scale, out_scale, hip_stream);
+            if (s != RP_OK) return s;
+        }
+        return RP_OK;
+    }
+    ScaleDataArgs a{};
+    a.x_rw = x;
+    a.t_rw = t;
+    a.in_scale_c = in_scale;
+    a.out_scale_c = out_scale;
+    a.n = n;
+    a.n_lags = n_lags;
+    a.n_in = kNBlocks * kNFeat * n_lags + kNGeo;
+    launch_scale_data(a, static_cast<hipStream_t>(hip_stream));
+    return hipGetLastError() == hipSuccess ? RP_OK : RP_ERR_DEVICE;
+}
+
+}  // extern "C"

@@ -14,6 +14,8 @@
 // Legendre polynomials P, box coordinates mapped to [-1, 1]).
 #include "rpot_internal.hpp"
 
+#include <algorithm>
+
 namespace rpot {
 
 __device__ __forceinline__ void legendre4(float x, float (&p)[4]) {
@@ -537,6 +539,103 @@ void launch_budget(const BudgetArgs &a, hipStream_t st) {
 void launch_correct(const CorrArgs &a, hipStream_t st) {
     if (a.n_jobs == 0 || a.max_pts == 0) return;
     hipLaunchKernelGGL(k_correct, dim3(unsigned((a.max_pts + 255) / 256)), dim3(256), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// Training data of the network (teacher rows, scales, scaling).
+
+// Row r of the audited far pairs: inputs x_out[r] = x_all[far index of r],
+// targets t[r] = (t[r] - sub[r]) * |c_s - c_n| (sub: the multipole terms, or null).
+__global__ void k_teacher(TeacherArgs a) {
+    const int r = blockIdx.x;
+    const int f = a.row_far[r];
+    const float *src = a.x_all + int64_t(f) * a.n_in;
+    float *dst = a.x_out + int64_t(r) * a.n_in;
+    for (int j = threadIdx.x; j < a.n_in; j += blockDim.x) dst[j] = src[j];
+    if (threadIdx.x < kNOut) {
+        float *t = a.t + int64_t(r) * kNOut + threadIdx.x;
+        float v = *t;
+        if (a.sub) v -= a.sub[int64_t(r) * kNOut + threadIdx.x];
+        *t = v / a.pairs[f].inv_d;
+    }
+}
+
+void launch_teacher(const TeacherArgs &a, hipStream_t st) {
+    if (a.n_rows == 0) return;
+    hipLaunchKernelGGL(k_teacher, dim3(a.n_rows), dim3(256), 0, st, a);
+}
+
+// Scales of the training data.  Block 0: moment k of the unmodulated block H
+// (columns lag * kNFeat + k, lag < n_lags), 1 / RMS over rows and lags; block
+// 1: component c of the targets (columns c * kNBasis + b), RMS over rows and
+// the kNBasis coefficients, repeated over the component's columns.  Each
+// thread keeps one column class; the sums are FP64 in a fixed order
+// (threads stride rows, then a fixed tree over the threads of a class).
+constexpr int kScaleLanesIn = 32;    // threads per moment class (block 0: 22 x 32)
+constexpr int kScaleLanesOut = 8;    // threads per target column (block 1: 80 x 8)
+__global__ __launch_bounds__(704) void k_data_scales(ScaleDataArgs a) {
+    __shared__ double part[kNFeat * kScaleLanesIn];
+    const int t = threadIdx.x;
+    double s = 0.0;
+    if (blockIdx.x == 0) {
+        // thread t reads columns t, t + 704, ... of the block H: all of moment t % 22
+        const int cols = a.n_lags * kNFeat;
+        for (int64_t i = 0; i < a.n; ++i) {
+            const float *row = a.x + i * a.n_in;
+            for (int j = t; j < cols; j += kNFeat * kScaleLanesIn) {
+                const double v = row[j];
+                s += v * v;
+            }
+        }
+    } else if (t < kNOut * kScaleLanesOut) {
+        // thread t: column t % 80, rows t / 80, t / 80 + 8, ...
+        const int col = t % kNOut, lane = t / kNOut;
+        for (int64_t i = lane; i < a.n; i += kScaleLanesOut) {
+            const double v = a.t[i * kNOut + col];
+            s += v * v;
+        }
+    }
+    part[t] = s;
+    __syncthreads();
+    if (blockIdx.x == 0 && t < kNFeat) {
+        double tot = 0.0;
+        for (int l = 0; l < kScaleLanesIn; ++l) tot += part[t + l * kNFeat];
+        const double rms = sqrt(tot / (double(a.n) * double(a.n_lags)));
+        a.in_scale[t] = rms > 0.0 ? float(1.0 / rms) : 1.0f;
+    }
+    if (blockIdx.x == 1 && t < 4) {
+        double tot = 0.0;
+        for (int l = 0; l < kScaleLanesOut; ++l)
+            for (int b = 0; b < kNBasis; ++b) tot += part[l * kNOut + t * kNBasis + b];
+        const double rms = sqrt(tot / (double(a.n) * kNBasis));
+        const float v = rms > 0.0 ? float(rms) : 1.0f;
+        for (int b = 0; b < kNBasis; ++b) a.out_scale[t * kNBasis + b] = v;
+    }
+}
+
+void launch_data_scales(const ScaleDataArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(k_data_scales, dim3(2), dim3(kNFeat * kScaleLanesIn), 0, st, a);
+}
+
+// In place: the six moment blocks of every input row times in_scale (per
+// moment), every target row over out_scale (per column).
+__global__ void k_scale_data(ScaleDataArgs a) {
+    const int64_t i = blockIdx.y;
+    const int blocks = 6 * a.n_lags * kNFeat;
+    if (a.x_rw) {
+        float *x = a.x_rw + i * a.n_in;
+        for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < blocks; j += gridDim.x * blockDim.x)
+            x[j] *= a.in_scale_c[j % kNFeat];
+    }
+    if (a.t_rw && blockIdx.x == 0 && threadIdx.x < kNOut)
+        a.t_rw[i * kNOut + threadIdx.x] /= a.out_scale_c[threadIdx.x];
+}
+
+void launch_scale_data(const ScaleDataArgs &a, hipStream_t st) {
+    if (a.n == 0) return;
+    const int blocks = 6 * a.n_lags * kNFeat;
+    hipLaunchKernelGGL(k_scale_data, dim3(unsigned(std::max(1, std::min(8, (blocks + 255) / 256))), unsigned(a.n)),
+                       dim3(256), 0, st, a);
 }
 
 }  // namespace rpot

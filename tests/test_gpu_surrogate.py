@@ -386,3 +386,64 @@ def test_readmission_restores_the_far_terms():
     for l in res[0]:
         for x, y in zip(res[0][l], res[1][l]):
             assert np.array_equal(x, y), l
+
+
+def test_training_data_calls_match_their_definitions():
+    """rp_surrogate_teacher rows are the audited pairs' features and their
+    plain responses times the pair distance (minus the multipole terms with
+    residual); the scales, the scaling and the network's relative RMS equal
+    their definitions evaluated in numpy (FP64)."""
+    from paper_2311_15429_amd import surrogate as S
+    system = far_system(3)
+    p = make_plan(system, audit=[2, 3])
+    run(p, GpuSourceGen(system, torch.float32), 30)
+    info, pairs = p.surrogate_info(), p.surrogate_pairs()
+    aud = np.nonzero(pairs["audited"])[0]
+    assert info["n_audited"] == len(aud) > 0
+    feats = p.surrogate_features().cpu().numpy()
+    coef, _ = p.surrogate_pair_response()
+    coef = coef.cpu().numpy()
+    mpole = p.surrogate_multipole_response().cpu().numpy()
+    X = torch.empty((len(aud), info["n_in"]), dtype=torch.float32, device="cuda")
+    T = torch.empty((len(aud), 80), dtype=torch.float32, device="cuda")
+    lib = S._lib.load()
+    for residual in (0, 1):
+        assert lib.rp_surrogate_teacher(p._h, S._ptr(X), S._ptr(T), residual) == 0
+        torch.cuda.synchronize()
+        assert np.array_equal(X.cpu().numpy(), feats[aud])
+        want = (coef - (mpole if residual else 0.0)) * pairs["dist"][aud][:, None]
+        got = T.cpu().numpy()
+        assert np.max(np.abs(got - want)) <= 1e-6 * np.max(np.abs(want)), residual
+    p.close()
+
+    # scales and scaling on random rows (two lags: n_in = 266)
+    rng = np.random.default_rng(0)
+    nl, n = 2, 300
+    x = (rng.normal(size=(n, 132 * nl + 2)) * rng.uniform(0.1, 10, size=132 * nl + 2)).astype(np.float32)
+    x[:, 5::22] = 0.0                                          # an all-zero moment gets scale 1
+    t = (rng.normal(size=(n, 80)) * np.repeat([1.0, 3.0, 0.5, 2.0], 20)).astype(np.float32)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    ins, outs = S.feature_scales(xd, td, nl)
+    h = x[:, :22 * nl].astype(np.float64).reshape(n, nl, 22)
+    rms_in = np.sqrt(np.mean(h ** 2, axis=(0, 1)))
+    want_in = np.where(rms_in > 0, 1.0 / np.where(rms_in > 0, rms_in, 1.0), 1.0)
+    rms_out = np.sqrt(np.mean(t.astype(np.float64).reshape(n, 4, 20) ** 2, axis=(0, 2)))
+    assert np.allclose(ins, want_in, rtol=1e-6) and ins[5] == 1.0
+    assert np.allclose(outs, np.repeat(rms_out, 20), rtol=1e-6)
+    S.scale_data(xd, td, ins, outs, nl)
+    sx = np.ones(132 * nl + 2, np.float32)
+    sx[:132 * nl] = np.tile(ins, 6 * nl)
+    assert np.allclose(xd.cpu().numpy(), x * sx, rtol=1e-6)
+    assert np.allclose(td.cpu().numpy(), t / outs, rtol=1e-6)
+
+    # relative RMS of a small network on the raw rows
+    from paper_2311_15429_amd.mlp import Mlp
+    net = Mlp(132 * nl + 2, 16, 80, 64)
+    net.set_params(torch.from_numpy(rng.normal(scale=0.05, size=net.n_params).astype(np.float32)))
+    sur = S.TrainedSurrogate(net, ins, outs, nl, [])
+    xs = torch.from_numpy(x * sx).cuda()
+    y = torch.cat([net.forward(xs[i:i + 64]) for i in range(0, n, 64)]).double().cpu().numpy() * outs
+    want = np.sqrt(np.sum((y - t) ** 2) / np.sum(t.astype(np.float64) ** 2))
+    got = S.relative_rms(sur, torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    assert abs(got - want) <= 1e-6 * want, (got, want)
+    log(f"training-data calls: teacher rows {len(aud)}, relative RMS {got:.4f}")
