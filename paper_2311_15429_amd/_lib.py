@@ -5,7 +5,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librpot.so")
+# RPOT_LIB names another build of the same library (the host sanitizer build)
+LIB_PATH = os.environ.get("RPOT_LIB") or os.path.join(HERE, "librpot.so")
 
 RP_OK = 0
 STATUS = {0: "RP_OK", 1: "RP_ERR_ARG", 2: "RP_ERR_GEOMETRY", 3: "RP_ERR_NOMEM",
