@@ -480,7 +480,10 @@ rp_status rp_bind_history_host(rp_plan plan, void *host_ptr, size_t bytes);
  *     fallen-back audited pair whose far-pair terms are within factor x
  *     tol * M_mu / (active far pairs of s + 1) in every component returns to
  *     them from the next step on (n_readmitted, may be NULL).  Synchronises the
- *     stream.  A captured step stays valid.
+ *     stream.  A call in which a pair falls back or returns discards a
+ *     captured step (the lag-sum schedule changed); otherwise it stays valid.
+ *     With rp_surrogate_sample the same call also judges far pairs of the
+ *     other sources by sample (below).
  * rp_surrogate_readmit  the re-admission factor (>= 0; 0, the default: a pair
  *     that falls back stays with the plain lag sum).  A transient, such as the
  *     light-cone front of a source's switch-on crossing the target box, then
@@ -528,6 +531,52 @@ rp_status rp_surrogate_pair_response(rp_plan plan, float *coef, float *resid);
 rp_status rp_surrogate_judge(rp_plan plan, void *const *out, double tol, int32_t *n_fallback, double *worst,
                              int32_t *n_readmitted);
 rp_status rp_surrogate_readmit(rp_plan plan, double factor);
+
+/*
+ * Judging every far pair by sample.  Only the far pairs of audit sources keep
+ * their spectral history; rp_surrogate_sample (after rp_surrogate_configure,
+ * before the bind) lets rp_surrogate_judge check the others too:
+ * - every far source keeps a real-space history of its sources S_n in FP32,
+ *   (largest far lag m_hi of its pairs) + 2 snapshots deep, written by the
+ *   ingest of every step (4 x 4 bytes per source point and snapshot: far
+ *   sources ~1900 lags deep at 48^3 points hold 3.4 GB each);
+ * - each judge call takes the next pairs_per_judge far pairs whose source is
+ *   not an audit source (far-pair order, wrapping; 0: all of them) and
+ *   evaluates their plain pair field at the last completed step l by the
+ *   direct sum of Sec. III's sampled scheme, P(r_k) = sum_k' h^3 / R *
+ *   [(1 - f) dS_n(r_k', l - m) + f dS_n(r_k', l - m - 1)] with
+ *   R = |r_k - r_k'|, R / (c dt) = m + f (0 <= f < 1), dS = S - S(0) (zero
+ *   before step 0): the same sum as the pair's lag sum over its window, here
+ *   at 64 sample points of the target, the grid points (i_x, i_y, i_z) with
+ *   i = floor((a (N - 1) + 1) / 3), a = 0 .. 3 along each axis (corners,
+ *   edge and face thirds, the multipole path's nodes on the grid);
+ * - a sampled pair whose largest difference to its surrogate terms at those
+ *   points exceeds the budget of the audited pairs (the same tol * M_mu /
+ *   active far pairs of s) falls back: it takes one of fallback_slots
+ *   slots (each a spectral ring of its lag window, refilled from the real-space
+ *   history, and its Green spectra, computed then), and from the next step on
+ *   its lag sum runs plainly: the ingest transforms S_n(l - m_lo) again into
+ *   the slot's ring and a second lag-sum launch adds the slot pairs into their
+ *   targets.  The judge call's own outputs keep the pair's surrogate terms.
+ *   With every slot in use the pair stays on its surrogate terms (counted as
+ *   refused).  With a re-admission factor a sampled pair in a slot returns to
+ *   its far-pair terms under the audited pairs' rule and frees its slot.
+ * pairs_per_judge < 0 switches sampling off (the default).  fallback_slots in
+ * 0 .. 4096.  RP_ERR_STATE after the bind or without a configured surrogate.
+ *
+ * rp_surrogate_sample_fields: the plain pair fields of far pairs
+ *   far_pairs[0 .. n) (indices into rp_surrogate_pairs, host array) at their
+ *   64 sample points at the last completed step, out device [n][64][4]
+ *   (point p = 16 a_x + 4 a_y + a_z; component v, Ax, Ay, Az).  Any far
+ *   pair, audited or not.  Synchronises the stream.
+ * rp_surrogate_judge_stats: of the last rp_surrogate_judge call, the far pairs
+ *   judged by sample and the fallbacks refused for want of a free slot; the
+ *   slots in use now; the next pair of the rotation.  Any pointer may be NULL.
+ */
+rp_status rp_surrogate_sample(rp_plan plan, int32_t pairs_per_judge, int32_t fallback_slots);
+rp_status rp_surrogate_sample_fields(rp_plan plan, const int32_t *far_pairs, int32_t n, float *out);
+rp_status rp_surrogate_judge_stats(rp_plan plan, int32_t *sampled, int32_t *refused, int32_t *slots_used,
+                                   int32_t *next_pair);
 
 /*
  * Training data of the network, from the plain method (the teacher).

@@ -26,7 +26,8 @@ EXPORTS = ["rp_plan_domains", "rp_plan_targets", "rp_workspace_bytes", "rp_bind_
            "rp_osc_step", "rp_osc_state", "rp_osc_destroy", "rp_osc_last_error", "rp_history_split",
            "rp_history_host", "rp_history_host_bytes", "rp_bind_history_host",
            "rp_class_info", "rp_set_class_tuning", "rp_get_class_tuning", "rp_read_stream",
-           "rp_surrogate_teacher", "rp_surrogate_data_scales", "rp_surrogate_scale_data", "rp_mlp_relative_rms"]
+           "rp_surrogate_teacher", "rp_surrogate_data_scales", "rp_surrogate_scale_data", "rp_mlp_relative_rms",
+           "rp_surrogate_sample", "rp_surrogate_sample_fields", "rp_surrogate_judge_stats"]
 TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2, "fft_lds": 4, "lagsum_steps": 8, "lagsum_cached": 16,
         "lagsum_tile_major": 32}
 
@@ -109,6 +110,9 @@ def load():
     lib.rp_surrogate_pair_response.argtypes = [vp, vp, vp]
     lib.rp_surrogate_judge.argtypes = [vp, P(vp), ctypes.c_double, P(i32), dp, P(i32)]
     lib.rp_surrogate_readmit.argtypes = [vp, ctypes.c_double]
+    lib.rp_surrogate_sample.argtypes = [vp, i32, i32]
+    lib.rp_surrogate_sample_fields.argtypes = [vp, P(i32), i32, vp]
+    lib.rp_surrogate_judge_stats.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
     lib.rp_history_split.argtypes = [vp, i32]
     lib.rp_history_host.argtypes = [vp, i32]
     lib.rp_history_host_bytes.argtypes = [vp, P(ctypes.c_size_t)]

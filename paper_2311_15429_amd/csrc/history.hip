@@ -52,4 +52,18 @@ void launch_tier_copy(const TierArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_tier_copy, dim3(unsigned(nb), unsigned(a.n_jobs)), dim3(256), 0, st, a);
 }
 
+__global__ __launch_bounds__(256) void k_broadcast(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int64_t n16,
+                                                   int64_t total) {
+    for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < total; k += int64_t(gridDim.x) * 256)
+        dst[k] = src[k % n16];
+}
+
+void launch_broadcast(void *dst, const void *src, int64_t bytes, int32_t count, hipStream_t st) {
+    const int64_t n16 = bytes / 16, total = n16 * count;
+    if (total <= 0) return;
+    const int64_t nb = std::min<int64_t>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_broadcast, dim3(unsigned(nb)), dim3(256), 0, st, static_cast<uint4 *>(dst),
+                       static_cast<const uint4 *>(src), n16, total);
+}
+
 }  // namespace rpot

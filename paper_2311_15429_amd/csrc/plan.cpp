@@ -190,13 +190,14 @@ bool keeps_history(rp_plan p, int s, int n) {
     return f < 0 || S.pairs[f].audited;
 }
 
-// A pair summed by the plain lag sum at every step.
+// A pair summed by the plain lag sum of every step (a fallen-back far pair of
+// a non-audit source is summed from its fallback slot instead).
 bool plain_pair(rp_plan p, int s, int n) {
     if (!is_target(p, s)) return false;
     const SurrogateH &S = p->sur;
     if (!S.on) return true;
     const int f = S.far_index[size_t(s) * p->n_dom + n];
-    return f < 0 || S.pairs[f].plain;
+    return f < 0 || (S.pairs[f].plain && S.pairs[f].audited);
 }
 
 // Lag-sum schedule of the members (accumulator slots of system si): groups of
@@ -433,12 +434,19 @@ void plan_tables(rp_plan p) {
             p->vring.push_back(v);
         }
     }
-    // head slots: domains, judge accumulators, split rings, real-space rings
+    // judge by sample: every far source keeps a real-space history deep enough
+    // for the direct sum over its pairs' windows (retarded samples l - m and
+    // l - m - 1 with m <= m_hi)
+    if (p->sur.on && p->sur.per_judge >= 0)
+        for (const FarPairH &F : p->sur.pairs) p->dom[F.n].d1 = std::max(p->dom[F.n].d1, p->pr(F.s, F.n).m_hi + 2);
+    // head slots: domains, judge accumulators, split rings, real-space rings,
+    // fallback slots
     {
         int idx = nd + int(p->sur.on ? p->sur.aud.size() : 0);
         for (VRingP &v : p->vring) v.idx = idx++;
         for (DomainP &d : p->dom)
             if (d.d1 > 0) d.t1_idx = idx++;
+        for (SlotP &k : p->sur.slots) k.idx = idx++;
         p->n_heads = idx;
     }
 
@@ -627,6 +635,7 @@ void plan_layout(rp_plan p) {
         for (const ClassP &K : p->cls) {
             size_t jobs = K.doms.size();
             for (int n : K.doms) jobs += p->dom[n].vr.size();
+            if (!p->sur.slots.empty()) jobs = kMaxJobs;   // slot transforms and refills
             q = std::max(q, std::min<size_t>(kMaxJobs, jobs) * size_t(p->sys[p->dom[K.doms[0]].sys].Cpad) * 4 * 8);
         }
         p->off_qstage = alloc(q);
@@ -662,6 +671,7 @@ void plan_layout(rp_plan p) {
     }
     for (const DomainP &d : p->dom)
         if (d.t1_idx >= 0) p->domdev[d.t1_idx].depth = d.d1;
+    if (p->sur.on) sur_slot_tables(p);
     if (p->sur.on) {
         // judge slots: accumulators of the audited far pairs, [slot][C][4]
         for (size_t v = 0; v < p->sur.aud.size(); ++v) {
@@ -728,6 +738,15 @@ void plan_stats(rp_plan p) {
     for (const VRingP &v : p->vring) st.ring_bytes += double(v.W) * p->sys[p->dom[v.n].sys].Cpad * 4 * p->ring_esz;
     for (const DomainP &d : p->dom)
         if (d.d1 > 0) st.history_bytes += double(p->hist_host ? 1 + d.vr.size() : d.d1) * 4 * double(d.npts) * p->tsz;
+    if (p->sur.on) {
+        // fallback slots of sampled far pairs: their windows, ring rows and lag-sum bytes
+        for (const SlotP &k : p->sur.slots) {
+            if (k.f < 0) continue;
+            st.n_triples += k.W;
+            st.ring_bytes += double(k.W) * p->sur.slot_Cpad * 4 * p->ring_esz;
+        }
+        if (p->kb == 1) st.lagsum_bytes += k2_bytes(p, p->sur.k2p);
+    }
     st.split_rings = int64_t(p->vring.size());
     st.n_classes = int64_t(p->cls.size());
     for (const SystemP &S : p->sys) st.spectra_bytes += double(S.spec_elems) * p->spec_csz;
@@ -1167,107 +1186,137 @@ void do_static(rp_plan p, const void *const *src) {
 // Line-pass tile of a shape class: its own choice, else the plan's.
 int cls_lds(rp_plan p, const ClassP &K) { return K.fft_lds ? K.fft_lds : p->fft_lds; }
 
-void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
+void enqueue_ring_jobs(rp_plan p, const ClassP &K, const std::vector<RingJob> &jobs, hipStream_t st) {
     const bool quant = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
     const bool i16 = (p->ring_fmt == RING_I16);
+    const int64_t Cpad = p->sys[p->dom[K.doms[0]].sys].Cpad;
+    for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxJobs) {
+        const int cnt = int(std::min<size_t>(kMaxJobs, jobs.size() - j0));
+        ZFwd z = zfwd_common(p, 0, K.N, K.P, K.Hz, p->p64);
+        LinePass y = fwd_y(p, K.N, K.P, K.Hz, p->p64);
+        LinePass x = fwd_x(p, K.N, K.P, K.Hz, p->p64);
+        y.lds_elems = x.lds_elems = cls_lds(p, K);
+        // I16: the x pass writes FP32 rows into the staging area, which
+        // the quantiser then scales per tile into the ring
+        x.out_fmt = i16 ? RING_F32 : p->ring_fmt;
+        x.tile_comp = 4;
+        // lanes in the order of a ring row: [c/2][k][c%2] (FP32), [c][k]
+        // (FP64), [k][c] (FP16/BF16)
+        x.out_group = x.out_fmt == RING_F32 ? 2 : (x.out_fmt == RING_F64 ? 1 : 4);
+        ScaleArgs sa{};
+        QuantArgs qa{};
+        z.n_jobs = y.n_jobs = x.n_jobs = cnt;
+        sa.n_jobs = quant ? cnt : 0;
+        qa.n_jobs = i16 ? cnt : 0;
+        qa.max_tiles = int(Cpad / kTile);
+        for (int j = 0; j < cnt; ++j) {
+            const RingJob &J = jobs[j0 + j];
+            const DomainP &d = p->dom[J.n];
+            z.jobs[j].src = J.src;
+            z.jobs[j].src_head = J.src_head;
+            z.jobs[j].src_depth = J.src_depth;
+            z.jobs[j].src_lag = J.src_lag;
+            z.jobs[j].store = J.store;
+            z.jobs[j].store_head = J.store_head;
+            z.jobs[j].s0 = p->ws + d.off_s0;
+            z.jobs[j].out = J.t1;
+            z.jobs[j].zmax = quant ? J.zmax : nullptr;
+            y.jobs[j].in = J.t1;
+            y.jobs[j].out = J.t2;
+            x.jobs[j].in = J.t2;
+            x.jobs[j].out = J.ring;
+            x.jobs[j].head = J.head;
+            x.jobs[j].slot_stride = int64_t(kTile) * 4;
+            x.jobs[j].tile_stride = int64_t(J.depth) * kTile * 4;
+            x.jobs[j].qscale = quant ? J.scales : nullptr;
+            if (i16) {
+                float *stage = p->at<float>(p->off_qstage + size_t(j) * size_t(Cpad) * 4 * 8);
+                x.jobs[j].out = stage;
+                x.jobs[j].head = nullptr;
+                x.jobs[j].slot_stride = 0;
+                x.jobs[j].tile_stride = int64_t(kTile) * 4;
+                QuantJob &q = qa.jobs[j];
+                q.stage = stage;
+                q.ring = J.ring;
+                q.scales = J.scales;
+                q.head = J.head;
+                q.C = p->sys[d.sys].C;
+                q.depth = J.depth;
+                q.n_tiles = int(Cpad / kTile);
+            }
+            if (quant) {
+                sa.jobs[j].zmax = J.zmax;
+                sa.jobs[j].scales = J.scales;
+                sa.jobs[j].nblk = d.zblocks;
+                sa.jobs[j].head = J.head;
+                sa.jobs[j].npts = double(d.npts);
+            }
+        }
+        launch_zfwd(z, p->p64, st);
+        launch_ring_scale(sa, st);
+        launch_line_pass(y, p->p64, st);
+        launch_line_pass(x, p->p64, st);
+        launch_quant_i16(qa, st);
+        check_launch();
+    }
+}
+
+void enqueue_ingest(rp_plan p, const void *const *src, hipStream_t st) {
+    const bool scaled = ring_scaled(p);
+    const bool zq = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
     const int32_t *dhead = p->at<int32_t>(p->off_head);
     for (const ClassP &K : p->cls) {
         // jobs: every domain of the class (newest sources into its ring, and a
-        // copy into its real-space ring), then every split ring of those
-        // domains (the sources of lo steps ago, from the real-space ring)
-        std::vector<int> jobs(K.doms.begin(), K.doms.end());
-        for (int n : K.doms)
-            for (int v : p->dom[n].vr) jobs.push_back(-1 - v);
-        for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxJobs) {
-            const int cnt = int(std::min<size_t>(kMaxJobs, jobs.size() - j0));
-            ZFwd z = zfwd_common(p, 0, K.N, K.P, K.Hz, p->p64);
-            LinePass y = fwd_y(p, K.N, K.P, K.Hz, p->p64);
-            LinePass x = fwd_x(p, K.N, K.P, K.Hz, p->p64);
-            y.lds_elems = x.lds_elems = cls_lds(p, K);
-            // I16: the x pass writes FP32 rows into the staging area, which
-            // the quantiser then scales per tile into the ring
-            x.out_fmt = i16 ? RING_F32 : p->ring_fmt;
-            x.tile_comp = 4;
-            // lanes in the order of a ring row: [c/2][k][c%2] (FP32), [c][k]
-            // (FP64), [k][c] (FP16/BF16)
-            x.out_group = x.out_fmt == RING_F32 ? 2 : (x.out_fmt == RING_F64 ? 1 : 4);
-            ScaleArgs sa{};
-            QuantArgs qa{};
-            z.n_jobs = y.n_jobs = x.n_jobs = cnt;
-            sa.n_jobs = quant ? cnt : 0;
-            qa.n_jobs = i16 ? cnt : 0;
-            const int64_t Cpad = p->sys[p->dom[K.doms[0]].sys].Cpad;
-            qa.max_tiles = int(Cpad / kTile);
-            for (int j = 0; j < cnt; ++j) {
-                const int code = jobs[j0 + j];
-                const bool split = code < 0;
-                const VRingP *v = split ? &p->vring[size_t(-1 - code)] : nullptr;
-                const int n = split ? v->n : code;
-                const DomainP &d = p->dom[n];
-                const int ring_idx = split ? v->idx : n;
-                const int depth = split ? v->W : d.depth;
-                const size_t off_t1 = split ? v->off_t1 : d.off_t1;
-                const size_t off_t2 = split ? v->off_t2 : d.off_t2;
-                const size_t off_ring = split ? v->off_ring : d.off_ring;
-                const size_t off_zmax = split ? v->off_zmax : d.off_zmax;
-                const size_t off_scales = split ? v->off_scales : d.off_scales;
-                if (split && p->hist_host) {
-                    z.jobs[j].src = p->ws + v->off_stage;   // fetched from the host ring
-                } else if (split) {
-                    z.jobs[j].src = p->ws + d.off_hist;
-                    z.jobs[j].src_head = dhead + d.t1_idx;
-                    z.jobs[j].src_depth = d.d1;
-                    z.jobs[j].src_lag = v->lo;
-                } else {
-                    z.jobs[j].src = src[n];
-                    if (d.d1 > 0 && p->hist_host) {
-                        z.jobs[j].store = p->ws + d.off_stage;   // written to the host ring
-                    } else if (d.d1 > 0) {
-                        z.jobs[j].store = p->ws + d.off_hist;
-                        z.jobs[j].store_head = dhead + d.t1_idx;
-                    }
-                }
-                z.jobs[j].s0 = p->ws + d.off_s0;
-                z.jobs[j].out = p->ws + off_t1;
-                z.jobs[j].zmax = quant ? p->at<float>(off_zmax) : nullptr;
-                y.jobs[j].in = p->ws + off_t1;
-                y.jobs[j].out = p->ws + off_t2;
-                x.jobs[j].in = p->ws + off_t2;
-                x.jobs[j].out = p->ws + off_ring;
-                x.jobs[j].head = dhead + ring_idx;
-                x.jobs[j].slot_stride = int64_t(kTile) * 4;
-                x.jobs[j].tile_stride = int64_t(depth) * kTile * 4;
-                x.jobs[j].qscale = quant ? p->at<float>(off_scales) : nullptr;
-                if (i16) {
-                    float *stage = p->at<float>(p->off_qstage + size_t(j) * size_t(Cpad) * 4 * 8);
-                    x.jobs[j].out = stage;
-                    x.jobs[j].head = nullptr;
-                    x.jobs[j].slot_stride = 0;
-                    x.jobs[j].tile_stride = int64_t(kTile) * 4;
-                    QuantJob &q = qa.jobs[j];
-                    q.stage = stage;
-                    q.ring = p->ws + off_ring;
-                    q.scales = p->at<float>(off_scales);
-                    q.head = dhead + ring_idx;
-                    q.C = p->sys[d.sys].C;
-                    q.depth = depth;
-                    q.n_tiles = int(Cpad / kTile);
-                }
-                if (quant) {
-                    sa.jobs[j].zmax = p->at<float>(off_zmax);
-                    sa.jobs[j].scales = p->at<float>(off_scales);
-                    sa.jobs[j].nblk = d.zblocks;
-                    sa.jobs[j].head = dhead + ring_idx;
-                    sa.jobs[j].npts = double(d.npts);
-                }
+        // copy into its real-space ring), every split ring of those domains
+        // (the sources of lo steps ago, from the real-space ring), and the
+        // fallback slots of sampled far pairs with a source in the class
+        std::vector<RingJob> jobs;
+        for (int n : K.doms) {
+            const DomainP &d = p->dom[n];
+            RingJob J;
+            J.n = n;
+            J.src = src[n];
+            if (d.d1 > 0 && p->hist_host) {
+                J.store = p->ws + d.off_stage;   // written to the host ring
+            } else if (d.d1 > 0) {
+                J.store = p->ws + d.off_hist;
+                J.store_head = dhead + d.t1_idx;
             }
-            launch_zfwd(z, p->p64, st);
-            launch_ring_scale(sa, st);
-            launch_line_pass(y, p->p64, st);
-            launch_line_pass(x, p->p64, st);
-            launch_quant_i16(qa, st);
-            check_launch();
+            J.t1 = p->ws + d.off_t1;
+            J.t2 = p->ws + d.off_t2;
+            J.ring = p->ws + d.off_ring;
+            J.scales = scaled ? p->at<float>(d.off_scales) : nullptr;
+            J.zmax = zq ? p->at<float>(d.off_zmax) : nullptr;
+            J.head = dhead + n;
+            J.depth = d.depth;
+            jobs.push_back(J);
         }
+        for (int n : K.doms) {
+            const DomainP &d = p->dom[n];
+            for (int vi : d.vr) {
+                const VRingP &v = p->vring[size_t(vi)];
+                RingJob J;
+                J.n = n;
+                if (p->hist_host) {
+                    J.src = p->ws + v.off_stage;   // fetched from the host ring
+                } else {
+                    J.src = p->ws + d.off_hist;
+                    J.src_head = dhead + d.t1_idx;
+                    J.src_depth = d.d1;
+                    J.src_lag = v.lo;
+                }
+                J.t1 = p->ws + v.off_t1;
+                J.t2 = p->ws + v.off_t2;
+                J.ring = p->ws + v.off_ring;
+                J.scales = scaled ? p->at<float>(v.off_scales) : nullptr;
+                J.zmax = zq ? p->at<float>(v.off_zmax) : nullptr;
+                J.head = dhead + v.idx;
+                J.depth = v.W;
+                jobs.push_back(J);
+            }
+        }
+        if (p->sur.on) sur_ring_jobs(p, K, jobs);
+        enqueue_ring_jobs(p, K, jobs, st);
     }
 }
 
@@ -1305,6 +1354,7 @@ void enqueue_lagsum(rp_plan p, hipStream_t st, int unroll, int persist, int phas
     const int32_t *head = p->at<int32_t>(p->off_head);
     if (p->kb == 1) {
         enqueue_k2(p, k2_args(p, p->k2, p->k2_dev, head), p->k2.tg, st, unroll, persist);
+        if (p->sur.on) sur_enqueue_slots(p, head, st);
         return;
     }
     if (phase == 0) {
@@ -1459,10 +1509,11 @@ void do_push(rp_plan p, int64_t step, const void *const *src) {
             launch_convert(p->ws + d.off_s0, p->p64, src[n], p->p64, 4 * d.npts, st);
             // the real-space ring starts with S(0) in every slot: sources before
             // step 0 are S(0) (the host tier reads S(0) itself for those)
-            if (!p->hist_host)
-                for (int j = 0; j < d.d1; ++j)
-                    launch_convert(p->ws + d.off_hist + size_t(j) * 4 * d.npts * p->tsz, p->p64, src[n], p->p64,
-                                   4 * d.npts, st);
+            if (!p->hist_host && d.d1 > 0) {
+                const size_t snap = size_t(4) * d.npts * p->tsz;
+                launch_convert(p->ws + d.off_hist, p->p64, src[n], p->p64, 4 * d.npts, st);
+                launch_broadcast(p->ws + d.off_hist + snap, p->ws + d.off_hist, int64_t(snap), d.d1 - 1, st);
+            }
         }
         do_static(p, src);
         tier_fork(p, st, false);
@@ -2095,6 +2146,28 @@ rp_status rp_surrogate_teacher(rp_plan plan, float *x, float *t, int32_t residua
 
 rp_status rp_surrogate_readmit(rp_plan plan, double factor) {
     return guarded(plan, [&] { sur_readmit(plan, factor); });
+}
+
+rp_status rp_surrogate_sample(rp_plan plan, int32_t pairs_per_judge, int32_t fallback_slots) {
+    return guarded(plan, [&] { sur_sample(plan, pairs_per_judge, fallback_slots); });
+}
+
+rp_status rp_surrogate_sample_fields(rp_plan plan, const int32_t *far_pairs, int32_t n, float *out) {
+    return guarded(plan, [&] { sur_sample_fields(plan, far_pairs, n, out); });
+}
+
+rp_status rp_surrogate_judge_stats(rp_plan plan, int32_t *sampled, int32_t *refused, int32_t *slots_used,
+                                   int32_t *next_pair) {
+    return guarded(plan, [&] {
+        const SurrogateH &U = plan->sur;
+        if (!U.on) fail(RP_ERR_STATE, "surrogate not configured (rp_surrogate_configure)");
+        int used = 0;
+        for (const SlotP &k : U.slots) used += k.f >= 0;
+        if (sampled) *sampled = U.last_sampled;
+        if (refused) *refused = U.last_refused;
+        if (slots_used) *slots_used = used;
+        if (next_pair) *next_pair = U.sampled.empty() ? -1 : U.sampled[size_t(U.cursor)];
+    });
 }
 
 rp_status rp_plan_destroy(rp_plan plan) {

@@ -130,7 +130,20 @@ struct FarPairH {
     double frac = 0;         // dist / (c dt) - m_c
     bool audited = false;    // the source keeps the plain history of this pair
     bool plain = false;      // fallen back: summed by the plain lag sum
+    int slot = -1;           // fallback slot of a sampled pair (index into SurrogateH::slots)
     double rot[9] = {};      // frame axes (rows)
+};
+
+// A fallback slot of the judge by sample: a spectral ring of one far pair's
+// lag window (ages lo .. lo + W - 1 of the source), refilled from the
+// source's real-space history when the pair falls back, and the pair's Green
+// spectra; its lag sum is added into the target's accumulator.
+struct SlotP {
+    int f = -1;              // far pair in the slot, or -1
+    int idx = 0;             // ring / head slot index
+    int W = 1, lo = 0;
+    size_t off_ring = 0, off_scales = 0, off_zmax = 0, off_t1 = 0, off_t2 = 0;
+    int64_t spec_elem = 0;   // its Green spectra: element offset from the start of the spectra
 };
 
 struct SurrogateH {
@@ -166,6 +179,43 @@ struct SurrogateH {
     int multipole = 0;             // analytic multipole far-pair terms: 1 alone, 2 plus the network's correction
     double readmit = 0;            // a fallen-back pair within readmit x its budget returns (0: never)
     size_t off_pinv = 0;           // [kNBasis][64] node-to-coefficient fit
+    // judge by sample (rp_surrogate_sample)
+    int per_judge = -1;            // far pairs of non-audit sources judged per call (0: all; < 0: off)
+    int n_slots = 0;
+    std::vector<int> sampled;      // far pairs of non-audit sources (far-pair order)
+    int cursor = 0;                // next position in `sampled`
+    int last_sampled = 0, last_refused = 0;
+    std::vector<SlotP> slots;
+    int slot_W = 0;                // lag window capacity of a slot
+    int64_t slot_Cpad = 0;
+    K2Tables k2p;                  // lag sum of the slot pairs (added into the targets)
+    K2Dev k2p_dev;
+    size_t off_sjobs = 0, off_jjobs = 0, off_sfield = 0, off_sres = 0, off_sfail = 0, off_fillslots = 0;
+    size_t off_fill_t1 = 0, off_fill_t2 = 0, off_fill_zmax = 0;
+    size_t fill_t1 = 0, fill_t2 = 0, fill_zmax = 0;   // bytes per fill job
+    std::vector<SampleJob> h_sjobs;        // host copies of uploaded tables (kept until copied)
+    std::vector<SampleJudgeJob> h_jjobs;
+    std::vector<int32_t> h_fill, h_heads;
+    std::vector<DomDev> h_dd;
+};
+
+constexpr int kFillJobs = 8;       // ring refills per launch (scratch sets)
+
+// One forward transform into a spectral ring (ingest of a step, or a refill):
+// the sources (the newest, or a snapshot of a real-space ring), the scratch of
+// the passes, and the ring slot written.
+struct RingJob {
+    int n = 0;                         // source domain (shape, S(0), z blocks)
+    const void *src = nullptr;
+    const int32_t *src_head = nullptr; // src is a real-space ring: read slot (*src_head - src_lag) mod src_depth
+    int src_depth = 0, src_lag = 0;
+    void *store = nullptr;             // also copy the sources to slot *store_head of this ring (null: none)
+    const int32_t *store_head = nullptr;
+    char *t1 = nullptr, *t2 = nullptr;
+    char *ring = nullptr;
+    float *scales = nullptr, *zmax = nullptr;
+    const int32_t *head = nullptr;     // ring slot written
+    int depth = 1;
 };
 
 }  // namespace rpot_host
@@ -270,6 +320,13 @@ K2Args k2_args(rp_plan p, const K2Tables &T, const K2Dev &D, const int32_t *head
 void enqueue_k2(rp_plan p, const K2Args &a, int tg, hipStream_t st, int unroll, int persist);
 bool keeps_history(rp_plan p, int s, int n);
 bool plain_pair(rp_plan p, int s, int n);
+bool ring_scaled(rp_plan p);
+size_t scale_bytes(rp_plan p, int depth, int64_t Cpad);
+void green_spectra(rp_plan p, int s, int n, int mode, int m0, int count, void *const *outs, int out_fmt,
+                   int64_t tile_stride);
+// Forward transforms of jobs of one shape class, kMaxJobs per launch.
+void enqueue_ring_jobs(rp_plan p, const ClassP &K, const std::vector<RingJob> &jobs, hipStream_t st);
+double k2_bytes(rp_plan p, const K2Tables &T);
 
 // surrogate.cpp
 void sur_classify(rp_plan p);                 // after the windows, before plan_tables
@@ -286,6 +343,11 @@ void sur_readmit(rp_plan p, double factor);
 void sur_multipole(rp_plan p, int enable);
 void sur_multipole_response(rp_plan p, float *coef);
 void sur_teacher(rp_plan p, float *x, float *t, int residual);
+void sur_sample(rp_plan p, int per_judge, int n_slots);
+void sur_sample_fields(rp_plan p, const int32_t *far_pairs, int n, float *out);
+void sur_slot_tables(rp_plan p);                          // after plan_layout's DomDev table
+void sur_ring_jobs(rp_plan p, const ClassP &K, std::vector<RingJob> &jobs);   // the slots' per-step transforms
+void sur_enqueue_slots(rp_plan p, const int32_t *head, hipStream_t st);      // the slots' lag sum
 // The plain lag sum of every target over the pairs pred admits: groups of up
 // to gmax targets, windows clipped to lags <= m_cap.
 void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int), int gmax = kGroupMax, int m_cap = INT32_MAX);

@@ -487,6 +487,53 @@ struct MultipoleArgs {
 void launch_multipole(const MultipoleArgs &a, hipStream_t st);
 void launch_correct(const CorrArgs &a, hipStream_t st);
 
+// Judge by sample.  The plain field of a far pair (target s <- source n) at
+// 64 sample points of the target at the last completed step l, by the direct
+// sum of the sampled scheme over the source's real-space history:
+//   P(r_k) = sum_k' h^3 / R [(1 - f) dS(r_k', l - m) + f dS(r_k', l - m - 1)],
+//   R = |r_k - r_k'|, R / (c dt) = m + f, dS = S - S(0).
+// Sample point p = 16 a_x + 4 a_y + a_z sits at grid index
+// floor((a (N - 1) + 1) / 3) along each axis.
+constexpr int kSamplePts = 64;
+constexpr int kSampleGroup = 8;       // sample points per block
+struct SampleJob {
+    const float *hist;     // real-space ring of S_n [depth][4][npts_n]
+    const float *s0;       // S_n(0) [4][npts_n]
+    const int32_t *head;   // slot of S_n(l) in hist
+    float *out;            // [64][4]
+    double t0[3];          // (o_s - o_n) / h: the target origin in source grid units
+    int32_t Ns[3], Nn[3];
+    int32_t depth;
+    int32_t pad_;
+};
+struct SampleArgs {
+    const SampleJob *jobs;
+    int n_jobs;
+    double h;
+    double inv_cdt;        // 1 / (c dt)
+    float h3;
+};
+void launch_pair_sample(const SampleArgs &a, hipStream_t st);
+// Per sampled pair: max over the points of |F - surrogate| and of |F| per
+// component (resid[0..3], resid[4..7]); fail = active and any
+// resid[mu] > budget[mu].
+struct SampleJudgeJob {
+    const float *F;        // [64][4]
+    const float *pc;       // the pair's box coefficients [4][20]
+    const float *budget;   // [4] of the target
+    float *resid;          // [8]
+    int32_t *fail;
+    int32_t N[3];
+    int32_t active;
+};
+struct SampleJudgeArgs {
+    const SampleJudgeJob *jobs;
+    int n_jobs;
+};
+void launch_sample_judge(const SampleJudgeArgs &a, hipStream_t st);
+// count copies of the bytes at src (a multiple of 16) after one another at dst
+void launch_broadcast(void *dst, const void *src, int64_t bytes, int32_t count, hipStream_t st);
+
 // Network forward pass of the surrogate on a given stream (mlp.hip).
 bool mlp_dims(rp_mlp m, int *n_in, int *n_out, int *max_batch);
 void mlp_forward_on(rp_mlp m, const float *x, int batch, float *y, hipStream_t st);

@@ -10,6 +10,7 @@
 #include "plan_internal.hpp"
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -381,6 +382,125 @@ void sur_layout(rp_plan p, size_t &off) {
     U.off_aud = alloc(na * 4);
     U.off_rowfar = alloc(na * 4);
     U.off_tcoef = alloc(na * kNOut * 4);
+
+    // judge by sample: job tables, fields and flags of the sampled pairs, and
+    // the fallback slots (rings, Green spectra, transform scratch, refill scratch)
+    U.slot_W = 0;
+    U.slot_Cpad = 0;
+    if (U.per_judge < 0) return;
+    const size_t nsp = std::max<size_t>(nf, 1);
+    U.off_sjobs = alloc(nsp * sizeof(SampleJob));
+    U.off_jjobs = alloc(nsp * sizeof(SampleJudgeJob));
+    U.off_sfield = alloc(nsp * kSamplePts * 4 * 4);
+    U.off_sres = alloc(nsp * 8 * 4);
+    U.off_sfail = alloc(nsp * 4);
+    if (U.slots.empty()) return;
+    size_t t1 = 0, t2 = 0, zb = 0;
+    for (int f : U.sampled) {
+        const FarPairH &F = U.pairs[f];
+        const PairP &q = p->pr(F.s, F.n);
+        const DomainP &d = p->dom[F.n];
+        const SystemP &S = p->sys[d.sys];
+        U.slot_W = std::max(U.slot_W, q.m_hi - q.m_lo + 1);
+        U.slot_Cpad = std::max(U.slot_Cpad, S.Cpad);
+        t1 = std::max(t1, size_t(d.N[0]) * d.N[1] * S.Hz * 4 * p->csz);
+        t2 = std::max(t2, size_t(d.N[0]) * S.P[1] * S.Hz * 4 * p->csz);
+        zb = std::max(zb, size_t(d.zblocks) * 4 * sizeof(float));
+    }
+    if (U.slot_W == 0) return;
+    const bool quant = ring_scaled(p);
+    const bool zq = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
+    U.fill_t1 = t1;
+    U.fill_t2 = t2;
+    U.fill_zmax = zq ? zb : 0;
+    U.off_fillslots = alloc(U.slots.size() * size_t(U.slot_W) * 4);
+    U.off_fill_t1 = alloc(kFillJobs * t1);
+    U.off_fill_t2 = alloc(kFillJobs * t2);
+    U.off_fill_zmax = zq ? alloc(kFillJobs * zb) : 0;
+    for (SlotP &k : U.slots) {
+        k.off_ring = alloc(size_t(U.slot_W) * U.slot_Cpad * 4 * p->ring_esz);
+        k.off_scales = quant ? alloc(scale_bytes(p, U.slot_W, U.slot_Cpad)) : 0;
+        k.off_zmax = zq ? alloc(zb) : 0;
+        k.off_t1 = alloc(t1);
+        k.off_t2 = alloc(t2);
+    }
+    // Green spectra of the slots, in the spectra's element units on whole
+    // frequency tiles from the start of the spectra
+    const size_t tile_bytes = size_t(kTile) * p->spec_csz;
+    const size_t rem = (off - p->off_spec) % tile_bytes;
+    if (rem) off += tile_bytes - rem;
+    for (SlotP &k : U.slots) {
+        const size_t o = alloc(size_t(U.slot_W) * U.slot_Cpad * p->spec_csz);
+        k.spec_elem = int64_t((o - p->off_spec) / p->spec_csz);
+    }
+    // lag-sum tables of the slot pairs: one group per target, a source record
+    // and W entries per slot
+    const size_t nsl = U.slots.size();
+    size_t tiles = 0;
+    for (const SystemP &S : p->sys) tiles = std::max(tiles, size_t((S.C + kTile - 1) / kTile));
+    K2Dev &D = U.k2p_dev;
+    D.cap_groups = std::min(nsl, size_t(p->n_dom));
+    D.cap_items = D.cap_groups * tiles;
+    D.cap_srcs = nsl;
+    D.cap_pairs = nsl * kGroupMax;
+    D.cap_entries = D.cap_masks = nsl * size_t(U.slot_W);
+    D.items = alloc(D.cap_items * sizeof(K2Item));
+    D.groups = alloc(D.cap_groups * sizeof(K2Group));
+    D.entries = alloc(D.cap_entries * sizeof(K2Entry));
+    D.srcs = alloc(D.cap_srcs * sizeof(K2Src));
+    D.pairs = alloc(D.cap_pairs * sizeof(K2Pair));
+    D.masks = alloc(D.cap_masks * sizeof(uint32_t));
+}
+
+// DomDev entries of the fallback slots (ring and scale offsets; depth W while
+// a pair holds the slot).
+void sur_slot_tables(rp_plan p) {
+    const bool quant = ring_scaled(p);
+    for (const SlotP &k : p->sur.slots) {
+        DomDev &D = p->domdev[size_t(k.idx)];
+        D.ring_off = int64_t((k.off_ring - p->dom[0].off_ring) / (4 * p->ring_esz)) * 4;
+        D.scale_off = quant ? int64_t((k.off_scales - p->dom[0].off_scales) / sizeof(float)) : 0;
+        D.depth = k.f >= 0 ? k.W : 1;
+    }
+}
+
+// Per step: every occupied slot whose source is in class K transforms
+// S_n(l - lo) again from the real-space history into its ring.
+void sur_ring_jobs(rp_plan p, const ClassP &K, std::vector<RingJob> &jobs) {
+    const SurrogateH &U = p->sur;
+    const int ci = int(&K - p->cls.data());
+    const bool scaled = ring_scaled(p);
+    const bool zq = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
+    const int32_t *dhead = p->at<int32_t>(p->off_head);
+    for (const SlotP &k : U.slots) {
+        if (k.f < 0) continue;
+        const int n = U.pairs[size_t(k.f)].n;
+        const DomainP &d = p->dom[n];
+        if (d.cls != ci) continue;
+        RingJob J;
+        J.n = n;
+        J.src = p->ws + d.off_hist;
+        J.src_head = dhead + d.t1_idx;
+        J.src_depth = d.d1;
+        J.src_lag = k.lo;
+        J.t1 = p->ws + k.off_t1;
+        J.t2 = p->ws + k.off_t2;
+        J.ring = p->ws + k.off_ring;
+        J.scales = scaled ? p->at<float>(k.off_scales) : nullptr;
+        J.zmax = zq ? p->at<float>(k.off_zmax) : nullptr;
+        J.head = dhead + k.idx;
+        J.depth = k.W;
+        jobs.push_back(J);
+    }
+}
+
+// The slot pairs' lag sum, added into their targets' accumulators.
+void sur_enqueue_slots(rp_plan p, const int32_t *head, hipStream_t st) {
+    SurrogateH &U = p->sur;
+    if (U.k2p.items.empty()) return;
+    K2Args a = k2_args(p, U.k2p, U.k2p_dev, head);
+    a.accumulate = 1;
+    enqueue_k2(p, a, U.k2p.tg, st, 1, 0);
 }
 
 void sur_bind(rp_plan p) {
@@ -448,7 +568,20 @@ void sur_bind(rp_plan p) {
         const std::vector<float> Q = dual_basis(p->cls[kv.first].N);
         HIP_OK(hipMemcpy(p->ws + kv.second, Q.data(), Q.size() * 4, hipMemcpyHostToDevice));
     }
-    for (FarPairH &F : U.pairs) F.plain = false;
+    for (FarPairH &F : U.pairs) {
+        F.plain = false;
+        F.slot = -1;
+    }
+    // fallback slots start empty (a fresh bind)
+    U.cursor = 0;
+    U.k2p = K2Tables{};
+    for (SlotP &k : U.slots) {
+        k.f = -1;
+        p->domdev[size_t(k.idx)].depth = 1;
+    }
+    if (!U.slots.empty())
+        HIP_OK(hipMemcpyAsync(p->ws + p->off_domdev, p->domdev.data(), p->domdev.size() * sizeof(DomDev),
+                              hipMemcpyHostToDevice, st));
     upload_csr(p, st);
     if (!U.src_doms.empty())   // ns * depth * 96 bytes: a multiple of 16
         launch_fill_zero(p->ws + U.off_mom, U.src_doms.size() * U.mom_depth * kFeatStride * 4, st);
@@ -558,6 +691,224 @@ void sur_enqueue_infer(rp_plan p, void *const *out, hipStream_t st) {
         launch_synthesize(sa, st);
     }
     check_launch();
+}
+
+// ---------------------------------------------------------------------------
+// Fallback slots of sampled far pairs
+
+namespace {
+
+// Lag-sum tables of the occupied slots: per target one group (one member),
+// per slot one source record over the slot's ring (lags lo .. lo + W - 1,
+// newest snapshot of age lo) and its Green spectra.
+void slot_k2(rp_plan p) {
+    SurrogateH &U = p->sur;
+    K2Tables &T = U.k2p;
+    T = K2Tables{};
+    std::map<int, std::vector<int>> by_target;
+    for (size_t k = 0; k < U.slots.size(); ++k)
+        if (U.slots[k].f >= 0) by_target[U.pairs[size_t(U.slots[k].f)].s].push_back(int(k));
+    for (const auto &kv : by_target) {
+        const int s = kv.first;
+        const SystemP &S = p->sys[p->dom[s].sys];
+        K2Group G{};
+        G.C = S.C;
+        G.spec_base = S.spec_base;
+        G.n_members = 1;
+        G.member[0] = s;
+        G.entry_begin = int(T.entries.size());
+        G.src_begin = int(T.srcs.size());
+        for (int k : kv.second) {
+            const SlotP &L = U.slots[size_t(k)];
+            const int64_t spec0 = L.spec_elem - S.spec_base;   // within the system's spectra
+            if (spec0 < 0 || spec0 % kTile) fail(RP_ERR_STATE, "internal: slot spectra misplaced");
+            K2Src R{};
+            R.n = L.idx;
+            R.m_min = L.lo;
+            R.m_max = L.lo + L.W - 1;
+            R.m_base = L.lo;
+            R.mask_off = int32_t(T.masks.size());
+            for (int m = R.m_min; m <= R.m_max; ++m) T.masks.push_back(1u);
+            K2Pair Qs[kGroupMax] = {};
+            Qs[0].row0 = int32_t(spec0 / kTile) - L.lo;
+            Qs[0].w = L.W;
+            for (int t = 0; t < kGroupMax; ++t) T.pairs.push_back(Qs[t]);
+            T.srcs.push_back(R);
+            for (int m = R.m_min; m <= R.m_max; ++m) {
+                K2Entry E{};
+                E.src = L.idx;
+                E.m = m;
+                E.mask = 1u;
+                E.spec_tile[0] = int32_t(spec0 / kTile + (m - L.lo));
+                E.spec_w[0] = L.W;
+                T.entries.push_back(E);
+            }
+        }
+        G.entry_end = int(T.entries.size());
+        G.src_end = int(T.srcs.size());
+        const int gi = int(T.groups.size());
+        T.groups.push_back(G);
+        for (int64_t k0 = 0; k0 < S.C; k0 += kTile) T.items.push_back(K2Item{gi, int32_t(k0)});
+    }
+    finish_k2(p, T);
+}
+
+// Far pair f takes slot k after step l (the last completed step): the slot's
+// ring gets depth W and, for the next step, head 1 mod W; the pair's Green
+// spectra are computed into the slot; its ring is refilled with dS_n at ages
+// lo .. hi of step l from the real-space history (age a at slot -(a - lo) mod
+// W), so that the next step's ingest (age lo at head 1) continues it.
+void slot_assign(rp_plan p, int k, int f, hipStream_t st) {
+    SurrogateH &U = p->sur;
+    SlotP &L = U.slots[size_t(k)];
+    FarPairH &F = U.pairs[size_t(f)];
+    const PairP &q = p->pr(F.s, F.n);
+    const DomainP &dn = p->dom[F.n];
+    const int W = q.m_hi - q.m_lo + 1;
+    if (q.m_lo < 1 || q.m_hi + 1 >= dn.d1 || W > U.slot_W || dn.t1_idx < 0)
+        fail(RP_ERR_STATE, "internal: a fallback window outside the slot or the history");
+    L.f = f;
+    L.lo = q.m_lo;
+    L.W = W;
+    F.slot = k;
+    F.plain = true;
+    DomDev &D = p->domdev[size_t(L.idx)];
+    D.depth = W;
+    HIP_OK(hipMemcpyAsync(p->ws + p->off_domdev + size_t(L.idx) * sizeof(DomDev), &D, sizeof(DomDev),
+                          hipMemcpyHostToDevice, st));
+    U.h_heads[size_t(k)] = 1 % W;
+    HIP_OK(hipMemcpyAsync(p->ws + p->off_head + size_t(L.idx) * 4, &U.h_heads[size_t(k)], 4, hipMemcpyHostToDevice,
+                          st));
+    // Green spectra of (s <- n), lags lo .. hi, [tile][lag][kTile]
+    for (int m0 = q.m_lo; m0 <= q.m_hi; m0 += kGreenChunk) {
+        const int cnt = std::min(kGreenChunk, q.m_hi - m0 + 1);
+        void *outs[kGreenChunk];
+        for (int j = 0; j < cnt; ++j)
+            outs[j] = p->ws + p->off_spec + size_t(L.spec_elem + int64_t(m0 + j - q.m_lo) * kTile) * p->spec_csz;
+        green_spectra(p, F.s, F.n, 1, m0, cnt, outs, RING_F32, int64_t(W) * kTile);
+    }
+    // refill from the real-space history
+    int32_t *slots_h = &U.h_fill[size_t(k) * U.slot_W];
+    for (int i = 0; i < W; ++i) slots_h[i] = (W - i % W) % W;
+    const int32_t *slots_d = p->at<int32_t>(U.off_fillslots) + size_t(k) * U.slot_W;
+    HIP_OK(hipMemcpyAsync(const_cast<int32_t *>(slots_d), slots_h, size_t(W) * 4, hipMemcpyHostToDevice, st));
+    const bool scaled = ring_scaled(p);
+    const bool zq = (p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
+    for (int i0 = 0; i0 < W; i0 += kFillJobs) {
+        std::vector<RingJob> jobs;
+        for (int i = i0; i < std::min(W, i0 + kFillJobs); ++i) {
+            const int j = i - i0;
+            RingJob J;
+            J.n = F.n;
+            J.src = p->ws + dn.off_hist;
+            J.src_head = p->at<int32_t>(p->off_prev_head) + dn.t1_idx;
+            J.src_depth = dn.d1;
+            J.src_lag = q.m_lo + i;
+            J.t1 = p->ws + U.off_fill_t1 + size_t(j) * U.fill_t1;
+            J.t2 = p->ws + U.off_fill_t2 + size_t(j) * U.fill_t2;
+            J.ring = p->ws + L.off_ring;
+            J.scales = scaled ? p->at<float>(L.off_scales) : nullptr;
+            J.zmax = zq ? p->at<float>(U.off_fill_zmax + size_t(j) * U.fill_zmax) : nullptr;
+            J.head = slots_d + i;
+            J.depth = W;
+            jobs.push_back(J);
+        }
+        enqueue_ring_jobs(p, p->cls[size_t(dn.cls)], jobs, st);
+    }
+    check_launch();
+}
+
+void slot_release(rp_plan p, int k, hipStream_t st) {
+    SurrogateH &U = p->sur;
+    SlotP &L = U.slots[size_t(k)];
+    if (L.f >= 0) {
+        U.pairs[size_t(L.f)].slot = -1;
+        U.pairs[size_t(L.f)].plain = false;
+    }
+    L.f = -1;
+    DomDev &D = p->domdev[size_t(L.idx)];
+    D.depth = 1;
+    HIP_OK(hipMemcpyAsync(p->ws + p->off_domdev + size_t(L.idx) * sizeof(DomDev), &D, sizeof(DomDev),
+                          hipMemcpyHostToDevice, st));
+}
+
+// Direct-sum fields of far pairs fs at their sample points into
+// U.off_sfield (rows in the order of fs).
+void sample_fields(rp_plan p, const std::vector<int> &fs, hipStream_t st) {
+    SurrogateH &U = p->sur;
+    U.h_sjobs.assign(fs.size(), SampleJob{});
+    for (size_t i = 0; i < fs.size(); ++i) {
+        const FarPairH &F = U.pairs[size_t(fs[i])];
+        const DomainP &ds = p->dom[F.s], &dn = p->dom[F.n];
+        SampleJob &J = U.h_sjobs[i];
+        J.hist = p->at<float>(dn.off_hist);
+        J.s0 = p->at<float>(dn.off_s0);
+        J.head = p->at<int32_t>(p->off_prev_head) + dn.t1_idx;
+        J.out = p->at<float>(U.off_sfield) + i * kSamplePts * 4;
+        for (int a = 0; a < 3; ++a) {
+            J.t0[a] = (ds.o[a] - dn.o[a]) / p->h;
+            J.Ns[a] = ds.N[a];
+            J.Nn[a] = dn.N[a];
+        }
+        J.depth = dn.d1;
+    }
+    if (fs.empty()) return;
+    HIP_OK(hipMemcpyAsync(p->ws + U.off_sjobs, U.h_sjobs.data(), fs.size() * sizeof(SampleJob),
+                          hipMemcpyHostToDevice, st));
+    SampleArgs a{};
+    a.jobs = p->at<SampleJob>(U.off_sjobs);
+    a.n_jobs = int(fs.size());
+    a.h = p->h;
+    a.inv_cdt = 1.0 / (p->c * p->dt);
+    a.h3 = float(p->h * p->h * p->h);
+    launch_pair_sample(a, st);
+    check_launch();
+}
+
+}  // namespace
+
+void sur_sample(rp_plan p, int per_judge, int n_slots) {
+    SurrogateH &U = p->sur;
+    if (!U.on) fail(RP_ERR_STATE, "surrogate not configured (rp_surrogate_configure)");
+    if (p->ws) fail(RP_ERR_STATE, "call rp_surrogate_sample before rp_bind_workspace");
+    if (n_slots < 0 || n_slots > 4096) fail(RP_ERR_ARG, "fallback_slots must be in [0, 4096]");
+    if (p->hist_host) fail(RP_ERR_UNSUPPORTED, "the judge by sample keeps its history in device memory");
+    U.per_judge = per_judge < 0 ? -1 : per_judge;
+    U.slots.assign(U.per_judge < 0 ? 0 : size_t(n_slots), SlotP{});
+    U.n_slots = int(U.slots.size());
+    U.sampled.clear();
+    for (size_t f = 0; f < U.pairs.size(); ++f) {
+        U.pairs[f].slot = -1;
+        if (!U.pairs[f].audited) U.sampled.push_back(int(f));
+    }
+    U.cursor = 0;
+    U.last_sampled = U.last_refused = 0;
+    U.k2p = K2Tables{};
+    U.k2p_dev = K2Dev{};
+    plan_tables(p);
+    plan_layout(p);
+    U.h_fill.assign(U.slots.size() * size_t(std::max(U.slot_W, 1)), 0);
+    U.h_heads.assign(U.slots.size(), 0);
+    plan_stats(p);
+}
+
+void sur_sample_fields(rp_plan p, const int32_t *far_pairs, int n, float *out) {
+    need_ready(p);
+    SurrogateH &U = p->sur;
+    if (U.per_judge < 0) fail(RP_ERR_STATE, "no judge by sample (rp_surrogate_sample)");
+    if (n < 0 || (n > 0 && (!far_pairs || !out))) fail(RP_ERR_ARG, "bad pair list or output");
+    if (n > int(U.pairs.size())) fail(RP_ERR_ARG, "more pairs than far pairs");
+    std::vector<int> fs(static_cast<size_t>(n));
+    for (int i = 0; i < n; ++i) {
+        if (far_pairs[i] < 0 || far_pairs[i] >= int(U.pairs.size())) fail(RP_ERR_ARG, "far pair index out of range");
+        fs[size_t(i)] = far_pairs[i];
+    }
+    hipStream_t st = p->stream;
+    sample_fields(p, fs, st);
+    if (n > 0)
+        HIP_OK(hipMemcpyAsync(out, p->ws + U.off_sfield, size_t(n) * kSamplePts * 4 * 4, hipMemcpyDeviceToDevice,
+                              st));
+    HIP_OK(hipStreamSynchronize(st));
 }
 
 // ---------------------------------------------------------------------------
@@ -738,9 +1089,19 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
     if (!(tol > 0)) fail(RP_ERR_ARG, "tol must be positive");
     hipStream_t st = p->stream;
     const int na = int(U.aud.size());
+    // the far pairs of non-audit sources judged by sample in this call
+    std::vector<int> samp;
+    if (U.per_judge >= 0 && !U.sampled.empty()) {
+        const int ns = int(U.sampled.size());
+        const int take = U.per_judge == 0 ? ns : std::min(U.per_judge, ns);
+        for (int i = 0; i < take; ++i) samp.push_back(U.sampled[size_t((U.cursor + i) % ns)]);
+        U.cursor = (U.cursor + take) % ns;
+    }
+    U.last_sampled = int(samp.size());
+    U.last_refused = 0;
     int fell = 0, back = 0;
     double w = 0.0;
-    if (na > 0) {
+    if (na > 0 || !samp.empty()) {
         // per-pair budget: tol * (max |P_mu| over the target's system) / (active far pairs of the target),
         // so that by the triangle inequality the system's error stays within tol per component
         std::vector<int> all(p->n_dom);
@@ -765,83 +1126,146 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
         for (int i = 0; i < p->n_dom; ++i)
             for (int mu = 0; mu < 4; ++mu)
                 smax[size_t(p->dom[i].sys) * 4 + mu] = std::max(smax[size_t(p->dom[i].sys) * 4 + mu], amax[size_t(i) * 4 + mu]);
-        for (int s : U.synth_targets) {
-            const int na_s = active_far(p, s);
-            if (na_s == 0) continue;
-            for (int mu = 0; mu < 4; ++mu)
-                bud[size_t(s) * 4 + mu] = float(tol * smax[size_t(p->dom[s].sys) * 4 + mu] / na_s);
-        }
-        HIP_OK(hipMemcpy(p->ws + U.off_budget, bud.data(), bud.size() * 4, hipMemcpyHostToDevice));
-        launch_fill_zero(p->ws + U.off_fail, (size_t(na) * 4 + 15) / 16 * 16, st);
-        judge_fields(p, st, [&](const int *vs, int cnt) {
-            ProjArgs pa{};
-            CorrArgs ca{};
-            pa.n_jobs = ca.n_jobs = cnt;
-            for (int j = 0; j < cnt; ++j) {
-                const int v = vs[j], f = U.aud[v];
-                const FarPairH &F = U.pairs[f];
-                const DomainP &t = p->dom[F.s];
-                ProjJob &J = pa.jobs[j];
-                J.F = jfield(p, j);
-                J.Q = nullptr;
-                J.coef_in = p->at<float>(U.off_pc) + size_t(f) * kNOut;
-                J.coef = p->at<float>(U.off_jcb) + size_t(j) * kNOut;
-                J.resid = p->at<float>(U.off_jres) + size_t(v) * 8;
-                for (int c = 0; c < 3; ++c) J.N[c] = t.N[c];
-                J.npts = t.npts;
-                CorrJob &C = ca.jobs[j];
-                C.F = J.F;
-                C.pc = J.coef_in;
-                C.resid = J.resid;
-                C.budget = p->at<float>(U.off_budget) + size_t(F.s) * 4;
-                C.out = static_cast<float *>(out[F.s]);
-                C.fail = p->at<int32_t>(U.off_fail) + v;
-                for (int c = 0; c < 3; ++c) C.N[c] = t.N[c];
-                C.active = F.plain ? 0 : 1;
-                ca.max_pts = std::max<int64_t>(ca.max_pts, t.npts);
-            }
-            launch_project(pa, false, st);
-            launch_correct(ca, st);
-            check_launch();
-        });
-        std::vector<int32_t> flags(na);
-        std::vector<float> res(size_t(na) * 8);
-        HIP_OK(hipStreamSynchronize(st));
-        HIP_OK(hipMemcpy(flags.data(), p->ws + U.off_fail, size_t(na) * 4, hipMemcpyDeviceToHost));
-        HIP_OK(hipMemcpy(res.data(), p->ws + U.off_jres, res.size() * 4, hipMemcpyDeviceToHost));
         // active far pairs per target before this judgement (the budgets' count)
         std::vector<int> n_act(p->n_dom, 0);
         for (int s : U.synth_targets) n_act[s] = active_far(p, s);
-        for (int v = 0; v < na; ++v) {
-            FarPairH &F = U.pairs[U.aud[v]];
-            if (F.plain) {
-                // re-admission: within readmit x the budget the pair would have
-                // as one more active far pair of its target, in every component
-                if (U.readmit <= 0) continue;
-                bool ok = true;
-                for (int mu = 0; mu < 4; ++mu) {
-                    const double b = tol * smax[size_t(p->dom[F.s].sys) * 4 + mu] / (n_act[F.s] + 1);
-                    ok = ok && res[size_t(v) * 8 + mu] <= U.readmit * b;
-                }
-                if (ok) {
-                    F.plain = false;
-                    ++back;
-                }
-                continue;
+        for (int s : U.synth_targets) {
+            if (n_act[s] == 0) continue;
+            for (int mu = 0; mu < 4; ++mu)
+                bud[size_t(s) * 4 + mu] = float(tol * smax[size_t(p->dom[s].sys) * 4 + mu] / n_act[s]);
+        }
+        HIP_OK(hipMemcpy(p->ws + U.off_budget, bud.data(), bud.size() * 4, hipMemcpyHostToDevice));
+        // a fallen-back pair returns within readmit x the budget it would have
+        // as one more active far pair of its target, in every component
+        auto readmit_ok = [&](const FarPairH &F, const float *r) {
+            if (U.readmit <= 0) return false;
+            bool ok = true;
+            for (int mu = 0; mu < 4; ++mu) {
+                const double b = tol * smax[size_t(p->dom[F.s].sys) * 4 + mu] / (n_act[F.s] + 1);
+                ok = ok && r[mu] <= U.readmit * b;
             }
+            return ok;
+        };
+        auto ratio = [&](const FarPairH &F, const float *r) {
             for (int mu = 0; mu < 4; ++mu) {
                 const double b = bud[size_t(F.s) * 4 + mu];
-                const double r = res[size_t(v) * 8 + mu];
-                w = std::max(w, b > 0 ? r / b : (r > 0 ? INFINITY : 0.0));
+                w = std::max(w, b > 0 ? r[mu] / b : (r[mu] > 0 ? INFINITY : 0.0));
             }
-            if (flags[v]) {
-                F.plain = true;
+        };
+        if (na > 0) {
+            launch_fill_zero(p->ws + U.off_fail, (size_t(na) * 4 + 15) / 16 * 16, st);
+            judge_fields(p, st, [&](const int *vs, int cnt) {
+                ProjArgs pa{};
+                CorrArgs ca{};
+                pa.n_jobs = ca.n_jobs = cnt;
+                for (int j = 0; j < cnt; ++j) {
+                    const int v = vs[j], f = U.aud[v];
+                    const FarPairH &F = U.pairs[f];
+                    const DomainP &t = p->dom[F.s];
+                    ProjJob &J = pa.jobs[j];
+                    J.F = jfield(p, j);
+                    J.Q = nullptr;
+                    J.coef_in = p->at<float>(U.off_pc) + size_t(f) * kNOut;
+                    J.coef = p->at<float>(U.off_jcb) + size_t(j) * kNOut;
+                    J.resid = p->at<float>(U.off_jres) + size_t(v) * 8;
+                    for (int c = 0; c < 3; ++c) J.N[c] = t.N[c];
+                    J.npts = t.npts;
+                    CorrJob &C = ca.jobs[j];
+                    C.F = J.F;
+                    C.pc = J.coef_in;
+                    C.resid = J.resid;
+                    C.budget = p->at<float>(U.off_budget) + size_t(F.s) * 4;
+                    C.out = static_cast<float *>(out[F.s]);
+                    C.fail = p->at<int32_t>(U.off_fail) + v;
+                    for (int c = 0; c < 3; ++c) C.N[c] = t.N[c];
+                    C.active = F.plain ? 0 : 1;
+                    ca.max_pts = std::max<int64_t>(ca.max_pts, t.npts);
+                }
+                launch_project(pa, false, st);
+                launch_correct(ca, st);
+                check_launch();
+            });
+            std::vector<int32_t> flags(na);
+            std::vector<float> res(size_t(na) * 8);
+            HIP_OK(hipStreamSynchronize(st));
+            HIP_OK(hipMemcpy(flags.data(), p->ws + U.off_fail, size_t(na) * 4, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(res.data(), p->ws + U.off_jres, res.size() * 4, hipMemcpyDeviceToHost));
+            for (int v = 0; v < na; ++v) {
+                FarPairH &F = U.pairs[U.aud[v]];
+                if (F.plain) {
+                    if (readmit_ok(F, &res[size_t(v) * 8])) {
+                        F.plain = false;
+                        ++back;
+                    }
+                    continue;
+                }
+                ratio(F, &res[size_t(v) * 8]);
+                if (flags[v]) {
+                    F.plain = true;
+                    ++fell;
+                }
+            }
+        }
+        if (!samp.empty()) {
+            // plain fields at the sample points, compared with the surrogate terms
+            const int ns = int(samp.size());
+            sample_fields(p, samp, st);
+            U.h_jjobs.assign(size_t(ns), SampleJudgeJob{});
+            for (int i = 0; i < ns; ++i) {
+                const FarPairH &F = U.pairs[size_t(samp[size_t(i)])];
+                SampleJudgeJob &Q = U.h_jjobs[size_t(i)];
+                Q.F = p->at<float>(U.off_sfield) + size_t(i) * kSamplePts * 4;
+                Q.pc = p->at<float>(U.off_pc) + size_t(samp[size_t(i)]) * kNOut;
+                Q.budget = p->at<float>(U.off_budget) + size_t(F.s) * 4;
+                Q.resid = p->at<float>(U.off_sres) + size_t(i) * 8;
+                Q.fail = p->at<int32_t>(U.off_sfail) + i;
+                for (int c = 0; c < 3; ++c) Q.N[c] = p->dom[F.s].N[c];
+                Q.active = F.plain ? 0 : 1;
+            }
+            HIP_OK(hipMemcpyAsync(p->ws + U.off_jjobs, U.h_jjobs.data(), size_t(ns) * sizeof(SampleJudgeJob),
+                                  hipMemcpyHostToDevice, st));
+            SampleJudgeArgs ja{};
+            ja.jobs = p->at<SampleJudgeJob>(U.off_jjobs);
+            ja.n_jobs = ns;
+            launch_sample_judge(ja, st);
+            check_launch();
+            std::vector<int32_t> flags(static_cast<size_t>(ns));
+            std::vector<float> res(size_t(ns) * 8);
+            HIP_OK(hipStreamSynchronize(st));
+            HIP_OK(hipMemcpy(flags.data(), p->ws + U.off_sfail, size_t(ns) * 4, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(res.data(), p->ws + U.off_sres, res.size() * 4, hipMemcpyDeviceToHost));
+            for (int i = 0; i < ns; ++i) {
+                const int f = samp[size_t(i)];
+                FarPairH &F = U.pairs[size_t(f)];
+                if (F.plain) {
+                    if (F.slot >= 0 && readmit_ok(F, &res[size_t(i) * 8])) {
+                        slot_release(p, F.slot, st);
+                        ++back;
+                    }
+                    continue;
+                }
+                ratio(F, &res[size_t(i) * 8]);
+                if (!flags[size_t(i)]) continue;
+                int k = -1;
+                for (size_t j = 0; j < U.slots.size() && k < 0; ++j)
+                    if (U.slots[j].f < 0) k = int(j);
+                if (k < 0) {
+                    ++U.last_refused;
+                    continue;
+                }
+                slot_assign(p, k, f, st);
                 ++fell;
             }
         }
         if (fell || back) {
+            // the schedules changed: a captured step no longer matches them
+            release_graph(p);
             main_k2(p, p->k2, plain_pair);
             upload_k2(p, p->k2, p->k2_dev, st);
+            if (!U.slots.empty()) {
+                slot_k2(p);
+                upload_k2(p, U.k2p, U.k2p_dev, st);
+            }
             upload_csr(p, st);
             HIP_OK(hipStreamSynchronize(st));
             plan_stats(p);

@@ -542,6 +542,119 @@ void launch_correct(const CorrArgs &a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Judge by sample (see SampleJob): the plain pair field at 64 target points by
+// the direct sum over the source's real-space history, and its comparison
+// with the surrogate terms.
+
+__device__ __forceinline__ int sample_index(int a, int n) { return (a * (n - 1) + 1) / 3; }
+
+// Grid (64 / kSampleGroup, jobs): each block sums kSampleGroup target points
+// over every source point (a strided share per thread, FP32 partial sums,
+// FP64 across the block); geometry in FP64.
+__global__ __launch_bounds__(256) void k_pair_sample(SampleArgs a) {
+    const SampleJob &j = a.jobs[blockIdx.y];
+    const int p0 = blockIdx.x * kSampleGroup;
+    const int Ny = j.Nn[1], Nz = j.Nn[2];
+    const int64_t npts = int64_t(j.Nn[0]) * Ny * Nz;
+    double tx[kSampleGroup], ty[kSampleGroup], tz[kSampleGroup];
+#pragma unroll
+    for (int q = 0; q < kSampleGroup; ++q) {
+        const int p = p0 + q;
+        tx[q] = j.t0[0] + sample_index(p >> 4, j.Ns[0]);
+        ty[q] = j.t0[1] + sample_index((p >> 2) & 3, j.Ns[1]);
+        tz[q] = j.t0[2] + sample_index(p & 3, j.Ns[2]);
+    }
+    const int head = *j.head;
+    const int depth = j.depth;
+    const double lag_per_cell = a.h * a.inv_cdt;   // R / (c dt) per grid unit of distance
+    float acc[kSampleGroup][4] = {};
+    for (int64_t i = threadIdx.x; i < npts; i += 256) {
+        const int iz = int(i % Nz);
+        const int64_t r = i / Nz;
+        const int iy = int(r % Ny);
+        const int ix = int(r / Ny);
+        float s0[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) s0[mu] = j.s0[mu * npts + i];
+#pragma unroll
+        for (int q = 0; q < kSampleGroup; ++q) {
+            const double dx = tx[q] - ix, dy = ty[q] - iy, dz = tz[q] - iz;
+            const double d = sqrt(dx * dx + dy * dy + dz * dz);
+            if (!(d > 0.0)) continue;
+            const double tau = d * lag_per_cell;
+            int m = int(floor(tau));
+            const float f = float(tau - double(m));
+            m = min(m, depth - 2);          // stays in the ring (the windows keep m + 1 < depth)
+            int sa = head - m;
+            if (sa < 0) sa += depth;
+            const int sb = sa == 0 ? depth - 1 : sa - 1;
+            const float *A = j.hist + int64_t(sa) * 4 * npts + i;
+            const float *B = j.hist + int64_t(sb) * 4 * npts + i;
+            const float w = a.h3 / float(d * a.h);
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+                acc[q][mu] = fmaf(w, fmaf(1.f - f, A[mu * npts], fmaf(f, B[mu * npts], -s0[mu])), acc[q][mu]);
+        }
+    }
+    __shared__ double red[4][kSampleGroup * 4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kSampleGroup; ++q)
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            double v = acc[q][mu];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) red[wv][q * 4 + mu] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < kSampleGroup * 4) {
+        const int t = threadIdx.x;
+        j.out[int64_t(p0) * 4 + t] = float(red[0][t] + red[1][t] + red[2][t] + red[3][t]);
+    }
+}
+
+// Block per sampled pair, one thread per sample point.
+__global__ __launch_bounds__(64) void k_sample_judge(SampleJudgeArgs a) {
+    const SampleJudgeJob &j = a.jobs[blockIdx.x];
+    const int p = threadIdx.x;
+    const int ix = sample_index(p >> 4, j.N[0]), iy = sample_index((p >> 2) & 3, j.N[1]),
+              iz = sample_index(p & 3, j.N[2]);
+    float B[kNBasis];
+    basis_at((int64_t(ix) * j.N[1] + iy) * j.N[2] + iz, j.N, B);
+    __shared__ float red[64];
+    bool bad = false;
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        float v = 0.f;
+#pragma unroll
+        for (int b = 0; b < kNBasis; ++b) v = fmaf(j.pc[mu * kNBasis + b], B[b], v);
+        const float F = j.F[p * 4 + mu];
+        const float x = block_max<64>(fabsf(F - v), red);
+        const float y = block_max<64>(fabsf(F), red);
+        if (p == 0) {
+            j.resid[mu] = x;
+            j.resid[4 + mu] = y;
+        }
+        bad |= x > j.budget[mu];
+    }
+    if (p == 0) *j.fail = (j.active && bad) ? 1 : 0;
+}
+
+void launch_pair_sample(const SampleArgs &a, hipStream_t st) {
+    for (int j0 = 0; j0 < a.n_jobs; j0 += 65535) {
+        SampleArgs c = a;
+        c.jobs = a.jobs + j0;
+        c.n_jobs = std::min(65535, a.n_jobs - j0);
+        hipLaunchKernelGGL(k_pair_sample, dim3(kSamplePts / kSampleGroup, c.n_jobs), dim3(256), 0, st, c);
+    }
+}
+
+void launch_sample_judge(const SampleJudgeArgs &a, hipStream_t st) {
+    if (a.n_jobs == 0) return;
+    hipLaunchKernelGGL(k_sample_judge, dim3(a.n_jobs), dim3(64), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
 // Training data of the network (teacher rows, scales, scaling).
 
 // Row r of the audited far pairs: inputs x_out[r] = x_all[far index of r],

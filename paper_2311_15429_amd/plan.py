@@ -375,6 +375,32 @@ class Plan:
         self.last_readmitted = int(back.value)
         return int(nf.value), float(worst.value)
 
+    def surrogate_sample(self, pairs_per_judge=0, fallback_slots=16):
+        """Judge the far pairs of non-audit sources too, by the direct sum at 64
+        sample points, pairs_per_judge per judge call in turn (0: all; < 0:
+        off); a failing pair takes one of fallback_slots slots.  Before bind()."""
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_sample(self._h, int(pairs_per_judge),
+                                                                     int(fallback_slots)))
+
+    def surrogate_sample_fields(self, far_pairs, out):
+        """Plain pair fields of far pairs `far_pairs` at their 64 sample points
+        at the last completed step into the device array out [n][64][4]."""
+        import torch
+        fp = np.ascontiguousarray(np.asarray(far_pairs, dtype=np.int32).reshape(-1))
+        n = int(fp.size)
+        if n and (tuple(out.shape) != (n, 64, 4) or not out.is_contiguous() or out.dtype != torch.float32):
+            raise ValueError("out must be a contiguous float32 device array [n][64][4]")
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_sample_fields(
+            self._h, fp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n, ctypes.c_void_p(out.data_ptr() if n else 0)))
+        return out
+
+    def surrogate_judge_stats(self) -> dict:
+        """Of the last judge call: far pairs judged by sample and fallbacks
+        refused for want of a slot; slots in use; the next pair of the rotation."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        _lib.check(self._lib, self._h, self._lib.rp_surrogate_judge_stats(self._h, *[ctypes.byref(x) for x in v]))
+        return {"sampled": v[0].value, "refused": v[1].value, "slots_used": v[2].value, "next_pair": v[3].value}
+
     def surrogate_readmit(self, factor):
         """Fallen-back pairs within factor x their budget return to the far-pair
         terms at the next judgement (0: never)."""

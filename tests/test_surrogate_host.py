@@ -109,3 +109,43 @@ def test_calls_before_bind_report_state():
     assert lib.rp_surrogate_features(p._h, None) != 0
     assert b"not bound" in lib.rp_last_error(p._h) or b"null" in lib.rp_last_error(p._h)
     p.close()
+
+
+def test_judge_by_sample_plans_history_slots_and_errors():
+    """rp_surrogate_sample: every far source gets a real-space history of
+    (largest far m_hi) + 2 snapshots in FP32; the workspace grows by at least
+    that history and the slots; state and argument errors."""
+    system = _system()
+    p = plan_for_system(system, "fp32")
+    p.surrogate_configure(3.0, n_lags=16, audit=[2])
+    ws0, st0 = p.workspace_bytes, p.stats()
+    assert st0["history_bytes"] == 0
+    with pytest.raises(RpotError):
+        p.surrogate_sample(0, fallback_slots=-1)
+    with pytest.raises(RpotError):
+        p.surrogate_sample(0, fallback_slots=5000)
+    p.surrogate_sample(0, fallback_slots=3)
+    st = p.stats()
+    pairs = p.surrogate_pairs()
+    depth = {}
+    for t, n in zip(pairs["target"].tolist(), pairs["source"].tolist()):
+        depth[n] = max(depth.get(n, 0), p.info(t, n)[1] + 2)
+    npts = system.domains[0].n_points
+    want = sum(d * 4 * npts * 4 for d in depth.values())
+    assert st["history_bytes"] == want
+    # slots: three rings and Green spectra of the widest sampled window
+    wmax = max(p.info(t, n)[1] - p.info(t, n)[0] + 1
+               for t, n, a in zip(pairs["target"], pairs["source"], pairs["audited"]) if not a)
+    pad = p.info(0, 0)[2]
+    cpad = -(-(pad[0] * pad[1] * (pad[2] // 2 + 1)) // 256) * 256
+    assert p.workspace_bytes >= ws0 + want + 3 * wmax * cpad * (4 * 8 + 8)
+    # the lag-sum schedule is unchanged until a pair falls back
+    assert st["lagsum_bytes"] == st0["lagsum_bytes"] and st["n_triples"] == st0["n_triples"]
+    # switched off again: back to the plan without the history
+    p.surrogate_sample(-1, 0)
+    assert p.workspace_bytes == ws0 and p.stats()["history_bytes"] == 0
+    p.close()
+    q = plan_for_system(system, "fp32")
+    with pytest.raises(RpotError):
+        q.surrogate_sample(0, 4)                          # no surrogate configured
+    q.close()
