@@ -980,6 +980,68 @@ def bench_sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_mlp(args):
+    """The far-pair surrogate network at its config-5 shape (8450 inputs,
+    2 x 256 tanh hidden, 80 outputs, linear skip): Adam training steps at a
+    minibatch of 2048 and inference over 990 far pairs, on random inputs and
+    the training run's initial weights.  Every product runs in the library's
+    FP32 matrix-core kernel; the roofline is the products' FP32 flops over the
+    whole timed step (its other kernels included) against the FP32 MFMA peak."""
+    import numpy as np
+    import torch
+    from paper_2311_15429_amd.mlp import Mlp
+    ni, H, no, B, Bi = 8450, 256, 80, 2048, 990
+    W, K = max(args.warmup, 3), args.steps
+    stream = torch.cuda.current_stream()
+    mlp = Mlp(ni, H, no, B, stream=stream)
+    g = torch.Generator(device="cpu").manual_seed(args.seed)
+    parts = [torch.randn(ni * H, generator=g) / math.sqrt(ni), torch.zeros(H),
+             torch.randn(H * H, generator=g) / math.sqrt(H), torch.zeros(H),
+             torch.randn(H * no, generator=g) / math.sqrt(H), torch.zeros(no),
+             torch.randn(ni * no, generator=g) / math.sqrt(ni)]
+    mlp.set_params(torch.cat(parts).float())
+    x = torch.randn((B, ni), generator=g).float().cuda()
+    t = torch.randn((B, no), generator=g).float().cuda()
+    xi = x[:Bi].contiguous()
+    y = torch.empty((Bi, no), dtype=torch.float32, device="cuda")
+
+    def timed(fn, n_warm, n):
+        for _ in range(n_warm):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    ms_train = timed(lambda: mlp.train_step(x, t, 1e-4), W, K)
+    ms_infer = timed(lambda: mlp.forward(xi, out=y), W, K)
+    fl_train = 2.0 * B * (2 * ni * H + 3 * H * H + 3 * H * no + 2 * ni * no)
+    fl_infer = 2.0 * Bi * (ni * H + H * H + H * no + ni * no)
+    peak = 157.3
+    ach = fl_train / (ms_train * 1e-3) / 1e12
+    log(f"mlp: train step (batch {B}) {ms_train:.3f} ms = {ach:.1f} TFLOP/s; "
+        f"inference ({Bi} pairs) {ms_infer:.3f} ms = {fl_infer / (ms_infer * 1e-3) / 1e12:.1f} TFLOP/s")
+    line = {"metric": "surrogate network training samples/s (Adam steps on the GPU)",
+            "value": B / (ms_train * 1e-3), "unit": "samples/s", "n_gpus": 1, "steps": K, "warmup": W,
+            "ms_per_step": ms_train, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"far-pair network {ni} -> {H} -> {H} -> {no} (tanh, linear skip), "
+                                   f"minibatch {B}; inference over {Bi} far pairs",
+                       "train_gflop_per_step": fl_train / 1e9, "infer_ms": ms_infer,
+                       "infer_gflop": fl_infer / 1e9,
+                       "infer_tflops": fl_infer / (ms_infer * 1e-3) / 1e12},
+            "roofline": {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
+                         "frac": round(ach / peak, 4), "traffic": None,
+                         "kernel": "k_gemm (FP32 matrix cores); achieved over the whole step, its split-K "
+                                   "reductions, loss, tanh, column-sum and Adam kernels included"},
+            "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -999,7 +1061,7 @@ def main():
                          "reads the whole history)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default lag-sum schedule")
     ap.add_argument("--workload", default="scale",
-                    choices=["scale", "batched", "batched_scaled", "surrogate", "small", "sweep", "coupled", "paper"],
+                    choices=["scale", "batched", "batched_scaled", "surrogate", "small", "sweep", "coupled", "paper", "mlp"],
                     help="scale: 8 x 64^3 (the metric's workload); batched: 64 independent systems "
                          "(2-16 domains of 32^3-96^3) in waves of target groups; batched_scaled: the batched "
                          "recipe at 16^3-32^3 and 2-8 domains in one plan, one graph launch per step; "
@@ -1007,7 +1069,8 @@ def main():
                          "small: 2 x 16^3 in FP64 beside the oracle's full run; "
                          "sweep: two 32x32x128 domains vs the box enclosing both, over the distance; "
                          "coupled: config 2 with oscillator sources driven by the potentials; "
-                         "paper: the paper's two-molecule geometry, single and split history")
+                         "paper: the paper's two-molecule geometry, single and split history; "
+                         "mlp: the surrogate network's training and inference at its config-5 shape")
     ap.add_argument("--far", default="learned", choices=["learned", "multipole", "hybrid"],
                     help="surrogate workload: far-pair terms from the trained network, the analytic "
                          "multipole, or the multipole plus a network trained on its residual")
@@ -1041,6 +1104,8 @@ def main():
     from paper_2311_15429_amd import plan_for_system
     from synth.sources import config2
 
+    if args.workload == "mlp":
+        return bench_mlp(args)
     if args.workload == "batched":
         return bench_batched(args)
     if args.workload == "batched_scaled":

@@ -8,9 +8,10 @@
 // inputs; the two tanh layers learn the rest.  Parameters are one flat FP32
 // vector [W1 (n_in x H), b1 (H), W2 (H x H), b2 (H), W3 (H x n_out),
 // b3 (n_out), Ws (n_in x n_out)], row-major, in the bound workspace.
-// Matrix products run in one LDS-tiled FP32 kernel (64 x 64 output tile,
-// 16-deep K slices, 4 x 4 outputs per thread) with strided operands, so the
-// transposed products of the backward pass need no copies.
+// Matrix products run in one LDS-tiled kernel on the FP32 matrix cores
+// (128 x 128 output tile, 16-deep K slices, split along K when the product has
+// few output tiles) with strided operands, so the transposed products of the
+// backward pass need no copies.
 #include "rpot.h"
 #include "rpot_internal.hpp"
 
@@ -24,9 +25,14 @@ namespace rpot {
 
 namespace {
 
-constexpr int kGT = 64;   // output tile
-constexpr int kGK = 16;   // K slice
-constexpr int kMaxSplit = 16;   // K splits of a product with few output tiles
+constexpr int kMT = 128;      // output tile (rows and columns) of a block
+constexpr int kKT = 16;       // K slice staged in LDS
+constexpr int kLdsRow = kMT + 4;
+constexpr int kMaxSplit = 32;   // K splits of a product with few output tiles
+constexpr int kMinSplitK = 64;  // K columns per split at least
+constexpr int kFillBlocks = 512;   // blocks a split product aims for (two per CU)
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 struct GemmArgs {
     const float *A;        // A(i, k) = A[i * sa0 + k * sa1]
@@ -41,56 +47,96 @@ struct GemmArgs {
     float *part;           // split-K: raw partial products [split][M][N]
 };
 
+// C tile of 128 x 128 per block on the FP32 matrix cores: four waves, each a
+// 64 x 64 quarter as 2 x 2 products of v_mfma_f32_32x32x2_f32 (FP32 inputs,
+// FP32 accumulation).  K goes in slices of 16 through two LDS buffers; the
+// next slice's global loads are issued before the current slice's products.
+// A k-slice of the instruction: lane l supplies A(i0 + l % 32, k + l / 32) and
+// B(k + l / 32, j0 + l % 32); accumulator register r of lane l holds
+// C(i0 + 8 (r / 4) + 4 (l / 32) + r % 4, j0 + l % 32).
+// The tile loads follow whichever operand stride is 1, so the transposed
+// products of the backward pass read contiguous runs without copies.
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-    __shared__ float As[kGK][kGT + 4];
-    __shared__ float Bs[kGK][kGT + 4];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    const int i0 = blockIdx.y * kGT, j0 = blockIdx.x * kGT;
+    __shared__ float As[2][kKT][kLdsRow];   // As[.][k][i]
+    __shared__ float Bs[2][kKT][kLdsRow];   // Bs[.][k][j]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i0 = blockIdx.y * kMT, j0 = blockIdx.x * kMT;
     const int kb = g.ks ? int(blockIdx.z) * g.ks : 0;
     const int ke = g.ks ? min(g.K, kb + g.ks) : g.K;
-    float acc[4][4] = {};
-    for (int k0 = kb; k0 < ke; k0 += kGK) {
-        for (int e = threadIdx.x; e < kGK * kGT; e += 256) {
-            const int kk = e / kGT, ii = e % kGT;
-            const int i = i0 + ii, k = k0 + kk;
-            As[kk][ii] = (i < g.M && k < ke) ? g.A[i * g.sa0 + k * g.sa1] : 0.f;
-            const int j = j0 + ii;
-            Bs[kk][ii] = (j < g.N && k < ke) ? g.B[k * g.sb0 + j * g.sb1] : 0.f;
+    // per-thread tile coordinates of the 8 A and 8 B elements of a slice
+    const bool a_kfast = (g.sa1 == 1), b_jfast = (g.sb1 == 1);
+    const int a_i = a_kfast ? (tid >> 4) : (tid & 127), a_k = a_kfast ? (tid & 15) : (tid >> 7);
+    const int a_di = a_kfast ? 16 : 0, a_dk = a_kfast ? 0 : 2;
+    const int b_j = b_jfast ? (tid & 127) : (tid >> 4), b_k = b_jfast ? (tid >> 7) : (tid & 15);
+    const int b_dj = b_jfast ? 0 : 16, b_dk = b_jfast ? 2 : 0;
+    float ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + a_i + u * a_di, k = k0 + a_k + u * a_dk;
+            ra[u] = (i < g.M && k < ke) ? g.A[int64_t(i) * g.sa0 + int64_t(k) * g.sa1] : 0.f;
+            const int j = j0 + b_j + u * b_dj, kk = k0 + b_k + u * b_dk;
+            rb[u] = (j < g.N && kk < ke) ? g.B[int64_t(kk) * g.sb0 + int64_t(j) * g.sb1] : 0.f;
         }
-        __syncthreads();
+    };
+    auto store = [&](int buf) {
 #pragma unroll
-        for (int kk = 0; kk < kGK; ++kk) {
-            float a[4], b[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(a[r], b[c], acc[r][c]);
+        for (int u = 0; u < 8; ++u) {
+            As[buf][a_k + u * a_dk][a_i + u * a_di] = ra[u];
+            Bs[buf][b_k + u * b_dk][b_j + u * b_dj] = rb[u];
         }
+    };
+    const int wi = (w >> 1) * 64, wj = (w & 1) * 64;
+    const int lr = lane & 31, lk = lane >> 5;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+    load(kb);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kb; k0 < ke; k0 += kKT) {
+        const bool more = k0 + kKT < ke;
+        if (more) load(k0 + kKT);
+#pragma unroll
+        for (int s = 0; s < kKT; s += 2) {
+            const float a0 = As[buf][s + lk][wi + lr], a1 = As[buf][s + lk][wi + 32 + lr];
+            const float b0 = Bs[buf][s + lk][wj + lr], b1 = Bs[buf][s + lk][wj + 32 + lr];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        if (more) store(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = i0 + ty * 4 + r;
-        if (i >= g.M) continue;
+    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int j = j0 + tx * 4 + c;
+        for (int tj = 0; tj < 2; ++tj) {
+            const int j = j0 + wj + tj * 32 + lr;
             if (j >= g.N) continue;
-            if (g.part) {
-                g.part[(int64_t(blockIdx.z) * g.M + i) * g.N + j] = acc[r][c];
-                continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = i0 + wi + ti * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
+                if (i >= g.M) continue;
+                const float v0 = acc[ti][tj][r];
+                if (g.part) {
+                    g.part[(int64_t(blockIdx.z) * g.M + i) * g.N + j] = v0;
+                    continue;
+                }
+                float v = v0;
+                if (g.bias) v += g.bias[j];
+                if (g.beta != 0.f) v += g.beta * g.C[int64_t(i) * g.ldc + j];
+                if (g.act == 1) v = tanhf(v);
+                g.C[int64_t(i) * g.ldc + j] = v;
             }
-            float v = acc[r][c];
-            if (g.bias) v += g.bias[j];
-            if (g.beta != 0.f) v += g.beta * g.C[int64_t(i) * g.ldc + j];
-            if (g.act == 1) v = tanhf(v);
-            g.C[int64_t(i) * g.ldc + j] = v;
         }
-    }
 }
 
 // C = act(beta C + sum over splits of part + bias), fixed summation order
@@ -107,25 +153,29 @@ __global__ void k_splitk_reduce(GemmArgs g, int splits) {
     }
 }
 
-// C (M x N) = act(beta C + A B + bias).  With split_buf (room for
-// kMaxSplit x M x N floats) a product with few output tiles and a long K is
-// split along K over blockIdx.z, then reduced.
+// C (M x N) = act(beta C + A B + bias).  With split_buf (room for split_cap
+// floats) a product with few output tiles is split along K over blockIdx.z
+// (at most kMaxSplit parts, at least kMinSplitK K columns each, the partial
+// products within split_cap), then reduced in a fixed order.
 void gemm(hipStream_t st, const float *A, int64_t sa0, int64_t sa1, const float *B, int64_t sb0, int64_t sb1,
           float *C, int64_t ldc, int M, int N, int K, const float *bias, int act, float beta,
-          float *split_buf = nullptr) {
+          float *split_buf = nullptr, int64_t split_cap = 0) {
     GemmArgs g{A, B, C, bias, sa0, sa1, sb0, sb1, ldc, M, N, K, act, beta, 0, nullptr};
-    const int gx = (N + kGT - 1) / kGT, gy = (M + kGT - 1) / kGT;
+    const int gx = (N + kMT - 1) / kMT, gy = (M + kMT - 1) / kMT;
     int splits = 1;
-    if (split_buf) splits = std::min({kMaxSplit, std::max(1, 1024 / (gx * gy)), std::max(1, K / 256)});
+    if (split_buf) {
+        const int64_t mn = int64_t(M) * N;
+        splits = std::min({kMaxSplit, std::max(1, (kFillBlocks + gx * gy - 1) / (gx * gy)), std::max(1, K / kMinSplitK),
+                           int(std::min<int64_t>(split_cap / std::max<int64_t>(mn, 1), kMaxSplit))});
+    }
     if (splits <= 1) {
         hipLaunchKernelGGL(k_gemm, dim3(gx, gy), dim3(256), 0, st, g);
         return;
     }
-    g.ks = ((K + splits - 1) / splits + kGK - 1) / kGK * kGK;
+    g.ks = ((K + splits - 1) / splits + kKT - 1) / kKT * kKT;
     splits = (K + g.ks - 1) / g.ks;
     g.part = split_buf;
     hipLaunchKernelGGL(k_gemm, dim3(gx, gy, splits), dim3(256), 0, st, g);
-    g.part = split_buf;
     const int64_t n = int64_t(M) * N;
     hipLaunchKernelGGL(k_splitk_reduce, dim3(unsigned(std::min<int64_t>((n + 255) / 256, 4096))), dim3(256), 0, st, g,
                        splits);
@@ -208,12 +258,30 @@ __global__ void k_tanh_back(float *dh, const float *h, int64_t n) {
         dh[i] *= 1.f - h[i] * h[i];
 }
 
-// db[j] = sum_i dz[i][j]
-__global__ void k_colsum(const float *dz, int rows, int cols, float *db) {
+// db[j] = sum_i dz[i][j] in two fixed-order steps: k_colsum_part sums a
+// chunk of kColRows rows for 64 columns per block (four row groups per column,
+// then the four partials), k_colsum_final adds the chunk partials in order.
+constexpr int kColRows = 64;
+
+__global__ __launch_bounds__(256) void k_colsum_part(const float *dz, int rows, int cols, float *part) {
+    __shared__ float red[4][64];
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * kColRows, r1 = min(rows, r0 + kColRows);
+    float s = 0.f;
+    if (j < cols)
+        for (int i = r0 + g; i < r1; i += 4) s += dz[int64_t(i) * cols + j];
+    red[g][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (g == 0 && j < cols)
+        part[int64_t(blockIdx.y) * cols + j] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                                               red[3][threadIdx.x];
+}
+
+__global__ void k_colsum_final(const float *part, int chunks, int cols, float *db) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= cols) return;
     float s = 0.f;
-    for (int i = 0; i < rows; ++i) s += dz[int64_t(i) * cols + j];
+    for (int c = 0; c < chunks; ++c) s += part[int64_t(c) * cols + j];
     db[j] = s;
 }
 
@@ -235,6 +303,14 @@ __global__ void k_copy_f32(float *dst, const float *src, int64_t n) {
 
 int nblocks(int64_t n) { return int(std::min<int64_t>((n + 255) / 256, 4096)); }
 
+// db = column sums of dz (rows x cols); part holds ceil(rows / kColRows) x cols
+// floats (the split-K buffer, free between products)
+void colsum(hipStream_t st, const float *dz, int rows, int cols, float *db, float *part) {
+    const int chunks = (rows + kColRows - 1) / kColRows;
+    hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, chunks), dim3(256), 0, st, dz, rows, cols, part);
+    hipLaunchKernelGGL(k_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, st, part, chunks, cols, db);
+}
+
 }  // namespace
 }  // namespace rpot
 
@@ -248,6 +324,7 @@ struct rp_mlp_s {
     int64_t n_params = 0;
     size_t off_w = 0, off_g = 0, off_m = 0, off_v = 0, off_h1 = 0, off_h2 = 0, off_y = 0, off_dy = 0, off_d2 = 0,
            off_d1 = 0, off_part = 0, off_split = 0, off_rms = 0;
+    int64_t split_cap = 0;   // floats of the split-K partial products
     int64_t step = 0;
     std::string err;
     float *W1() { return f(off_w); }
@@ -300,10 +377,11 @@ void check_batch(rp_mlp m, int batch) {
 void forward(rp_mlp m, const float *x, int B, float *y, hipStream_t st) {
     const int H = m->H;
     float *sp = m->f(m->off_split);
-    gemm(st, x, m->n_in, 1, m->W1(), H, 1, m->f(m->off_h1), H, B, H, m->n_in, m->b1(), 1, 0.f, sp);
-    gemm(st, m->f(m->off_h1), H, 1, m->W2(), H, 1, m->f(m->off_h2), H, B, H, H, m->b2(), 1, 0.f);
-    gemm(st, m->f(m->off_h2), H, 1, m->W3(), m->n_out, 1, y, m->n_out, B, m->n_out, H, m->b3(), 0, 0.f);
-    gemm(st, x, m->n_in, 1, m->Ws(), m->n_out, 1, y, m->n_out, B, m->n_out, m->n_in, nullptr, 0, 1.f, sp);
+    const int64_t cap = m->split_cap;
+    gemm(st, x, m->n_in, 1, m->W1(), H, 1, m->f(m->off_h1), H, B, H, m->n_in, m->b1(), 1, 0.f, sp, cap);
+    gemm(st, m->f(m->off_h1), H, 1, m->W2(), H, 1, m->f(m->off_h2), H, B, H, H, m->b2(), 1, 0.f, sp, cap);
+    gemm(st, m->f(m->off_h2), H, 1, m->W3(), m->n_out, 1, y, m->n_out, B, m->n_out, H, m->b3(), 0, 0.f, sp, cap);
+    gemm(st, x, m->n_in, 1, m->Ws(), m->n_out, 1, y, m->n_out, B, m->n_out, m->n_in, nullptr, 0, 1.f, sp, cap);
 }
 
 // Loss into *loss_dev and the gradient of every parameter into grad (flat).
@@ -312,6 +390,8 @@ void loss_grad(rp_mlp m, const float *x, const float *t, int B, float *loss_dev,
     const int H = m->H, no = m->n_out, ni = m->n_in;
     float *y = m->f(m->off_y), *dy = m->f(m->off_dy), *h1 = m->f(m->off_h1), *h2 = m->f(m->off_h2);
     float *d2 = m->f(m->off_d2), *d1 = m->f(m->off_d1);
+    float *sp = m->f(m->off_split);
+    const int64_t cap = m->split_cap;
     forward(m, x, B, y, st);
     const int64_t ny = int64_t(B) * no;
     const int nb = std::min(nblocks(ny), 256);
@@ -320,20 +400,20 @@ void loss_grad(rp_mlp m, const float *x, const float *t, int B, float *loss_dev,
     float *gW1 = grad, *gb1 = gW1 + int64_t(ni) * H, *gW2 = gb1 + H, *gb2 = gW2 + int64_t(H) * H;
     float *gW3 = gb2 + H, *gb3 = gW3 + int64_t(H) * no, *gWs = gb3 + no;
     // skip: gWs = x^T dy
-    gemm(st, x, 1, ni, dy, no, 1, gWs, no, ni, no, B, nullptr, 0, 0.f);
+    gemm(st, x, 1, ni, dy, no, 1, gWs, no, ni, no, B, nullptr, 0, 0.f, sp, cap);
     // layer 3: gW3 = h2^T dy, gb3 = colsum dy, d2 = dy W3^T
-    gemm(st, h2, 1, H, dy, no, 1, gW3, no, H, no, B, nullptr, 0, 0.f);
-    hipLaunchKernelGGL(k_colsum, dim3((no + 255) / 256), dim3(256), 0, st, dy, B, no, gb3);
-    gemm(st, dy, no, 1, m->W3(), 1, no, d2, H, B, H, no, nullptr, 0, 0.f);
+    gemm(st, h2, 1, H, dy, no, 1, gW3, no, H, no, B, nullptr, 0, 0.f, sp, cap);
+    colsum(st, dy, B, no, gb3, sp);
+    gemm(st, dy, no, 1, m->W3(), 1, no, d2, H, B, H, no, nullptr, 0, 0.f, sp, cap);
     hipLaunchKernelGGL(k_tanh_back, dim3(nblocks(int64_t(B) * H)), dim3(256), 0, st, d2, h2, int64_t(B) * H);
     // layer 2
-    gemm(st, h1, 1, H, d2, H, 1, gW2, H, H, H, B, nullptr, 0, 0.f);
-    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, d2, B, H, gb2);
-    gemm(st, d2, H, 1, m->W2(), 1, H, d1, H, B, H, H, nullptr, 0, 0.f);
+    gemm(st, h1, 1, H, d2, H, 1, gW2, H, H, H, B, nullptr, 0, 0.f, sp, cap);
+    colsum(st, d2, B, H, gb2, sp);
+    gemm(st, d2, H, 1, m->W2(), 1, H, d1, H, B, H, H, nullptr, 0, 0.f, sp, cap);
     hipLaunchKernelGGL(k_tanh_back, dim3(nblocks(int64_t(B) * H)), dim3(256), 0, st, d1, h1, int64_t(B) * H);
     // layer 1
-    gemm(st, x, 1, ni, d1, H, 1, gW1, H, ni, H, B, nullptr, 0, 0.f);
-    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, d1, B, H, gb1);
+    gemm(st, x, 1, ni, d1, H, 1, gW1, H, ni, H, B, nullptr, 0, 0.f, sp, cap);
+    colsum(st, d1, B, H, gb1, sp);
 }
 
 }  // namespace
@@ -393,7 +473,8 @@ rp_status rp_mlp_create(rp_mlp *out, int32_t n_in, int32_t n_hidden, int32_t n_o
     m->off_d1 = alloc(BH);
     m->off_part = alloc(256 * 4 + 16);
     m->off_rms = alloc((2 * 256 + 2) * 8);
-    m->off_split = alloc(size_t(kMaxSplit) * max_batch * std::max(n_hidden, n_out) * 4);
+    m->split_cap = int64_t(kMaxSplit) * max_batch * std::max(n_hidden, n_out);
+    m->off_split = alloc(size_t(m->split_cap) * 4);
     m->ws_bytes = off;
     *out = m;
     return RP_OK;

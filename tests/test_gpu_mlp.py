@@ -8,14 +8,14 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _setup(n_in=70, H=48, n_out=20, B=37, seed=0):
+def _setup(n_in=70, H=48, n_out=20, B=37, seed=0, wscale=0.3):
     from paper_2311_15429_amd.mlp import Mlp
     rng = np.random.default_rng(seed)
     n = mlp_ref.n_params(n_in, H, n_out)
-    w = rng.normal(scale=0.3, size=n)
+    w = rng.normal(scale=wscale, size=n)
     x = rng.normal(size=(B, n_in))
     t = rng.normal(size=(B, n_out))
-    m = Mlp(n_in, H, n_out, max_batch=64, stream=torch.cuda.current_stream())
+    m = Mlp(n_in, H, n_out, max_batch=max(64, B), stream=torch.cuda.current_stream())
     m.set_params(torch.from_numpy(w.astype(np.float32)))
     return m, w.astype(np.float32).astype(np.float64), x.astype(np.float32), t.astype(np.float32)
 
@@ -29,9 +29,24 @@ def test_forward_matches_reference(n_in):
     assert np.max(np.abs(y - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
 
 
-@pytest.mark.parametrize("n_in", [70, 3000])
-def test_gradient_matches_reference(n_in):
-    m, w, x, t = _setup(n_in=n_in, seed=1)
+@pytest.mark.parametrize("n_in, H, n_out, B", [(300, 160, 20, 150), (8450, 256, 80, 990)])
+def test_forward_matches_reference_several_tiles(n_in, H, n_out, B):
+    """Products over several 128 x 128 output tiles with ragged edges in both
+    directions, and the surrogate network's own shape (8450 inputs, 2 x 256
+    hidden, 80 outputs) at an inference batch of 990 far pairs."""
+    m, w, x, t = _setup(n_in=n_in, H=H, n_out=n_out, B=B, seed=4, wscale=1.0 / np.sqrt(n_in))
+    y = m.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref, _ = mlp_ref.forward(w, x.astype(np.float64), m.n_in, m.n_hidden, m.n_out)
+    assert np.max(np.abs(y - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("n_in, H, n_out, B", [(70, 48, 20, 37), (3000, 48, 20, 37), (300, 160, 20, 150),
+                                               (8450, 256, 80, 300)])
+def test_gradient_matches_reference(n_in, H, n_out, B):
+    """The backward products (transposed operands, split along K) at sizes
+    from one ragged tile to the surrogate network's own shape."""
+    m, w, x, t = _setup(n_in=n_in, H=H, n_out=n_out, B=B, seed=1,
+                        wscale=0.3 if n_in < 300 else 1.0 / np.sqrt(n_in))
     loss, g = m.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
     rl, rg = mlp_ref.loss_grad(w, x.astype(np.float64), t.astype(np.float64), m.n_in, m.n_hidden, m.n_out)
     g = g.cpu().numpy()
