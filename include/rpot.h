@@ -284,10 +284,15 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
  *   RP_TUNE_LAGSUM_TILE_MAJOR  blocked pass work order: 1 the items of one
  *                              frequency tile next to each other, 0 (default)
  *                              the costliest target first.
+ *   RP_TUNE_FFT_REG            1 (default): FP32 line passes of length 32, 48,
+ *                              64, 96, 128 or 256 run register-resident (each
+ *                              line split over T threads, one LDS exchange);
+ *                              0: every line pass stages whole lines in LDS
+ *                              (RP_TUNE_FFT_LDS).  FP64 passes always stage.
  * Setting a knob discards a captured step (rp_capture_step).
  */
 enum { RP_TUNE_LAGSUM_UNROLL = 1, RP_TUNE_LAGSUM_PERSISTENT = 2, RP_TUNE_FFT_LDS = 4, RP_TUNE_LAGSUM_STEPS = 8,
-       RP_TUNE_LAGSUM_CACHED = 16, RP_TUNE_LAGSUM_TILE_MAJOR = 32 };
+       RP_TUNE_LAGSUM_CACHED = 16, RP_TUNE_LAGSUM_TILE_MAJOR = 32, RP_TUNE_FFT_REG = 64 };
 rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value);
 /*
  * Shape classes: sub-domains with the same grid and FFT pad share their

@@ -25,7 +25,7 @@ BUILD = os.path.join(HERE, "_build")
 SAN_LIB = os.path.join(HERE, "librpot_san.so")
 SAN_BUILD = os.path.join(HERE, "_build_san")
 
-SOURCES = ["plan.cpp", "surrogate.cpp", "fft.hip", "lagsum.hip", "history.hip", "mlp.hip", "surrogate.hip",
+SOURCES = ["plan.cpp", "surrogate.cpp", "fft.hip", "fft_reg.hip", "lagsum.hip", "history.hip", "mlp.hip", "surrogate.hip",
            "coupling.hip", "calib.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

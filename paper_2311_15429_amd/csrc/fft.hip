@@ -484,6 +484,7 @@ int line_pass_elems(int lds_elems, int prec64) {
 }
 
 void launch_line_pass(const LinePass &a0, int prec64, hipStream_t st) {
+    if (!prec64 && a0.reg && launch_line_reg(a0, st)) return;
     LinePass a = a0;
     const int E = line_pass_elems(a.lds_elems, prec64);
     const bool fixed = !prec64 && (E == Lds<float>::E / 2 || E == Lds<float>::E) && a.out_fmt != RING_F64 &&

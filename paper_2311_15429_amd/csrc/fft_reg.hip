@@ -1,0 +1,426 @@
+// Register-resident line passes of the 3-D transforms (FP32, fixed lengths).
+//
+// The y and x passes of the padded 3-D FFTs (Sec. IV: one 3-D FFT per time
+// slice of the zero-padded sources, and the inverse on the target domain) run
+// many independent lines of one length P.  Here a line is split as
+// P = T x E over T threads of E points each:
+//
+//   x[t + T n],  t < T, n < E          (thread t holds its E points)
+//   X[k1 + E k2] = sum_t w_T^(t k2) [ w_P^(t k1) sum_n x[t + T n] w_E^(n k1) ]
+//
+// Stage 1 is an E-point DFT in registers per thread, then the twiddle
+// w_P^(t k1) (table in LDS, index t k1 < P); one exchange through LDS; stage 2
+// is E / T DFTs of T points per thread.  The small DFTs are mixed-radix
+// (4, 2, 3) codelets unrolled at compile time, their twiddles compile-time
+// constants.  Compared with a staged radix-by-radix transform this keeps one
+// LDS round trip per pass and no per-butterfly index arithmetic; the passes
+// were bound by instruction issue, not by HBM.
+//
+// Global loads and stores go straight from and to registers.  Which thread
+// holds which (line, t) is chosen separately for the loads and the stores, so
+// that consecutive lanes touch consecutive addresses: lines fastest when
+// neighbouring lines are adjacent in memory, else groups of G lines
+// interleaved with t (G = 1, 2, 4, the element order of the pass).
+#include "rpot_internal.hpp"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+namespace rpot {
+
+namespace {
+
+using Cf = Cx<float>;
+
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+
+// sin and cos for |x| <= pi by their Taylor series (compile time)
+constexpr double taylor_sin(double x) {
+    double term = x, sum = x;
+    for (int n = 1; n < 30; ++n) {
+        term *= -x * x / double((2 * n) * (2 * n + 1));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double taylor_cos(double x) {
+    double term = 1.0, sum = 1.0;
+    for (int n = 1; n < 30; ++n) {
+        term *= -x * x / double((2 * n - 1) * (2 * n));
+        sum += term;
+    }
+    return sum;
+}
+
+// cos and sin of 2 pi j / N, j < N, rounded to FP32
+template <int N>
+struct UnitRoots {
+    float c[N], s[N];
+    constexpr UnitRoots() : c(), s() {
+        for (int j = 0; j < N; ++j) {
+            double a = 2.0 * kPiD * double(j) / double(N);
+            if (a > kPiD) a -= 2.0 * kPiD;
+            c[j] = float(taylor_cos(a));
+            s[j] = float(taylor_sin(a));
+        }
+    }
+};
+template <int N>
+constexpr UnitRoots<N> kRoots{};
+
+// v * exp(DIR 2 pi i e / N); e is a constant once the codelets are unrolled,
+// so the branches and the table reads fold away
+template <int N, int DIR>
+__device__ __forceinline__ Cf twid(Cf v, int e) {
+    e %= N;
+    if (e == 0) return v;
+    if (2 * e == N) return Cf{-v.x, -v.y};
+    if (4 * e == N) return DIR > 0 ? Cf{-v.y, v.x} : Cf{v.y, -v.x};
+    if (4 * e == 3 * N) return DIR > 0 ? Cf{v.y, -v.x} : Cf{-v.y, v.x};
+    const float c = kRoots<N>.c[e], s = float(DIR) * kRoots<N>.s[e];
+    return Cf{v.x * c - v.y * s, v.x * s + v.y * c};
+}
+
+__device__ __forceinline__ Cf add(Cf a, Cf b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ Cf sub(Cf a, Cf b) { return {a.x - b.x, a.y - b.y}; }
+// a * (DIR i)
+template <int DIR>
+__device__ __forceinline__ Cf rot(Cf a) {
+    return DIR > 0 ? Cf{-a.y, a.x} : Cf{a.y, -a.x};
+}
+
+// X[k] = sum_n x[n] exp(DIR 2 pi i n k / N), natural order in and out.
+// Composite N = R M (R = 4, else 2, else 3) by decimation in time:
+// X[k + M q] = sum_r w_R^(r q) [ w_N^(r k) DFT_M(x[R m + r])[k] ].
+template <int N, int DIR>
+__device__ __forceinline__ void dft(const Cf (&x)[N], Cf (&X)[N]) {
+    if constexpr (N == 1) {
+        X[0] = x[0];
+    } else if constexpr (N == 2) {
+        X[0] = add(x[0], x[1]);
+        X[1] = sub(x[0], x[1]);
+    } else if constexpr (N == 3) {
+        const float h = 0.86602540378443864676f;   // sin(2 pi / 3)
+        const Cf s = add(x[1], x[2]);
+        const Cf d = sub(x[1], x[2]);
+        const Cf m = {x[0].x - 0.5f * s.x, x[0].y - 0.5f * s.y};
+        const Cf e = rot<DIR>(Cf{h * d.x, h * d.y});
+        X[0] = add(x[0], s);
+        X[1] = add(m, e);
+        X[2] = sub(m, e);
+    } else if constexpr (N == 4) {
+        const Cf a = add(x[0], x[2]), b = sub(x[0], x[2]);
+        const Cf c = add(x[1], x[3]), d = rot<DIR>(sub(x[1], x[3]));
+        X[0] = add(a, c);
+        X[2] = sub(a, c);
+        X[1] = add(b, d);
+        X[3] = sub(b, d);
+    } else {
+        constexpr int R = (N % 4 == 0) ? 4 : ((N % 2 == 0) ? 2 : 3);
+        constexpr int M = N / R;
+        Cf A[R][M];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            Cf s[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) s[m] = x[R * m + r];
+            dft<M, DIR>(s, A[r]);
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            Cf u[R], U[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) u[r] = twid<N, DIR>(A[r][k], r * k);
+            dft<R, DIR>(u, U);
+#pragma unroll
+            for (int q = 0; q < R; ++q) X[k + M * q] = U[q];
+        }
+    }
+}
+
+// Zero-padded input (forward passes, x[n] = 0 for n >= N / 2): the first
+// layer of a decimation in frequency needs no butterflies,
+// X[2k] = DFT_{N/2}(x)[k], X[2k + 1] = DFT_{N/2}(x w_N^n)[k].
+template <int N, int DIR>
+__device__ __forceinline__ void dft_half_in(const Cf (&x)[N], Cf (&X)[N]) {
+    constexpr int H = N / 2;
+    Cf a[H], b[H], A[H], B[H];
+#pragma unroll
+    for (int n = 0; n < H; ++n) {
+        a[n] = x[n];
+        b[n] = twid<N, DIR>(x[n], n);
+    }
+    dft<H, DIR>(a, A);
+    dft<H, DIR>(b, B);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        X[2 * k] = A[k];
+        X[2 * k + 1] = B[k];
+    }
+}
+
+// Cropped output (inverse passes, only X[k] for k < N / 2 are kept): the last
+// layer of a decimation in time computes its first half only,
+// X[k] = DFT_{N/2}(x[2m])[k] + w_N^k DFT_{N/2}(x[2m + 1])[k].
+template <int N, int DIR>
+__device__ __forceinline__ void dft_half_out(const Cf (&x)[N], Cf (&X)[N]) {
+    constexpr int H = N / 2;
+    Cf a[H], b[H], A[H], B[H];
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+        a[m] = x[2 * m];
+        b[m] = x[2 * m + 1];
+    }
+    dft<H, DIR>(a, A);
+    dft<H, DIR>(b, B);
+#pragma unroll
+    for (int k = 0; k < H; ++k) X[k] = add(A[k], twid<N, DIR>(B[k], k));
+}
+
+// (line in block, t) of thread tid: lg < 0 lines fastest; lg = 0, 1, 2
+// groups of 2^lg lines fastest, then t, then the groups
+template <int T, int L>
+__device__ __forceinline__ void line_thread(int tid, int lg, int &li, int &t) {
+    constexpr int lgT = __builtin_ctz(T);
+    if (lg < 0) {
+        li = tid & (L - 1);
+        t = tid / L;
+    } else {
+        t = (tid >> lg) & (T - 1);
+        li = ((tid >> (lg + lgT)) << lg) | (tid & ((1 << lg) - 1));
+    }
+}
+
+constexpr int kNumXcd = 8;
+// blocks of one XCD get a contiguous range of tiles (consecutive blocks are
+// dispatched round-robin over the 8 XCDs, each with its own L2)
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int x = b % kNumXcd, i = b / kNumXcd;
+    const int q = n / kNumXcd, r = n % kNumXcd;
+    return x * q + min(x, r) + i;
+}
+
+template <int FMT>
+__device__ __forceinline__ uint32_t half2_bits(Cf v, float s) {
+    if constexpr (FMT == RING_F16) {
+        const __half2 h = __halves2half2(__float2half_rn(v.x * s), __float2half_rn(v.y * s));
+        uint32_t u;
+        __builtin_memcpy(&u, &h, 4);
+        return u;
+    } else {
+        __hip_bfloat162 h;
+        h.x = __float2bfloat16(v.x * s);
+        h.y = __float2bfloat16(v.y * s);
+        uint32_t u;
+        __builtin_memcpy(&u, &h, 4);
+        return u;
+    }
+}
+
+constexpr int kRsrcWord3 = 0x00020000;   // gfx9-family buffer descriptor word 3
+constexpr uint32_t kOutOfRange = 0x80000000u;   // beyond every input: the load returns 0
+
+// Per-pass constants the launcher derives from the LinePass.
+struct RegArgs {
+    int lg_in, lg_out;     // thread orders of the loads and stores (line_thread)
+    int in_bytes;          // extent of one job's input (buffer loads, bounds-checked)
+};
+
+// One pass over a.lines lines of length P (T threads per line, L = 256 / T
+// lines per block).  FMT: output format (FP32 complex, or scaled FP16/BF16
+// ring rows).  DIR: sign of the exponent.  HALF: the pass's zero padding
+// (forward: n_in <= P / 2) or crop (inverse: n_out <= P / 2) is pruned from
+// the DFTs at compile time.
+template <int P, int T, int FMT, int DIR, bool HALF>
+__global__ __launch_bounds__(256) void k_line_reg(LinePass a, RegArgs ra) {
+    constexpr int E = P / T;
+    constexpr int L = 256 / T;
+    constexpr int RS = P + 1;   // odd LDS row stride
+    constexpr bool HALF_IN = HALF && DIR < 0, HALF_OUT = HALF && DIR > 0;
+    static_assert(E % T == 0 && L % 4 == 0 && E % 2 == 0 && T % 2 == 0, "line split P = T x E");
+    __shared__ Cf buf[L * RS];
+    __shared__ Cf twl[P];
+    const LineJob &job = a.jobs[blockIdx.y];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < P; i += 256) twl[i] = reinterpret_cast<const Cf *>(a.tw)[i];
+    const int line0 = xcd_tile(int(blockIdx.x), int(gridDim.x)) * L;
+
+    // stage 1: loads, E-point DFT, twiddles, into LDS as row[k1 T + t]
+    {
+        int li, t;
+        line_thread<T, L>(tid, ra.lg_in, li, t);
+        const int line = line0 + li;
+        // element j = t + T n of the line sits at byte offset lane_off + n step;
+        // loads past n_in (or of a line past the last) read 0 by the bounds check
+        int nv = 0;
+        uint32_t lane_off = 0;
+        if (line < a.lines) {
+            const int outer = a.dinner.div(line);
+            const int inner = line - outer * a.n_inner;
+            lane_off = uint32_t((outer * a.in_outer + inner * a.in_inner + int64_t(t) * a.in_j) * 8);
+            nv = (a.n_in - t + T - 1) / T;
+        }
+        const uint32_t step = uint32_t(int64_t(T) * a.in_j * 8);
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(job.in), (short)0, ra.in_bytes, kRsrcWord3);
+        constexpr int NL = HALF_IN ? E / 2 : E;
+        Cf v[E];
+#pragma unroll
+        for (int n = 0; n < NL; ++n) {
+            const uint32_t off = n < nv ? lane_off + uint32_t(n) * step : kOutOfRange;
+            // the whole 8-byte value is reinterpreted at once (no per-element
+            // casts of the vector)
+            v[n] = __builtin_bit_cast(Cf, __builtin_amdgcn_raw_buffer_load_b64(rs, int(off), 0, 0));
+        }
+#pragma unroll
+        for (int n = NL; n < E; ++n) v[n] = Cf{0.f, 0.f};
+        Cf X[E];
+        if constexpr (HALF_IN) dft_half_in<E, DIR>(v, X);
+        else dft<E, DIR>(v, X);
+        __syncthreads();   // twiddle table
+        Cf *row = buf + li * RS;
+        row[t] = X[0];
+#pragma unroll
+        for (int k1 = 1; k1 < E; ++k1) {
+            Cf w = twl[t * k1];
+            if (DIR > 0) w.y = -w.y;
+            row[k1 * T + t] = Cf{X[k1].x * w.x - X[k1].y * w.y, X[k1].x * w.y + X[k1].y * w.x};
+        }
+    }
+    __syncthreads();
+
+    // stage 2: E / T DFTs of T points per thread, stores
+    int li, t;
+    line_thread<T, L>(tid, ra.lg_out, li, t);
+    const int line = line0 + li;
+    if (line >= a.lines) return;
+    const int outer = a.dinner.div(line);
+    const int inner = line - outer * a.n_inner;
+    char *obase = reinterpret_cast<char *>(job.out);
+    const float *qs = job.qscale;
+    constexpr int esz = (FMT == RING_F32) ? 8 : 4;
+    if (job.head) {
+        const int64_t slot = *job.head;
+        obase += slot * job.slot_stride * esz;
+        if (qs) qs += slot * 4;
+    }
+    float iq = 1.0f;
+    if (FMT != RING_F32) iq = 1.0f / qs[inner & 3];   // scales are powers of two: exact
+    const int64_t lbase = outer * a.out_outer + inner * a.out_inner;
+    // tiled output of a length that divides the tile: the whole line is one
+    // run of one ring row, out_j = 4 (four components per frequency)
+    constexpr bool LINE_IN_TILE = (kTile % P) == 0;
+    char *lrow = nullptr;
+    if (LINE_IN_TILE && job.tile_stride) {
+        const uint32_t kk0 = uint32_t(lbase) >> 2, c = uint32_t(lbase) & 3u, kt0 = kk0 % kTile;
+        const int64_t w0 = (FMT == RING_F32) ? int64_t((c >> 1) * (2 * kTile) + kt0 * 2 + (c & 1u)) : int64_t(kt0 * 4 + c);
+        lrow = obase + (int64_t(kk0 / kTile) * job.tile_stride + w0) * esz;
+    }
+    constexpr int kstep = (FMT == RING_F32) ? 2 : 4;   // ring-row elements between frequencies
+    const Cf *row = buf + li * RS;
+#pragma unroll
+    for (int i = 0; i < E / T; ++i) {
+        const int k1 = t + T * i;
+        Cf z[T], Z[T];
+#pragma unroll
+        for (int s = 0; s < T; ++s) z[s] = row[k1 * T + s];
+        if constexpr (HALF_OUT) dft_half_out<T, DIR>(z, Z);
+        else dft<T, DIR>(z, Z);
+#pragma unroll
+        for (int k2 = 0; k2 < (HALF_OUT ? T / 2 : T); ++k2) {
+            const int k = k1 + E * k2;
+            if (k >= a.n_out) continue;
+            if (LINE_IN_TILE && job.tile_stride) {
+                if constexpr (FMT == RING_F32) reinterpret_cast<Cf *>(lrow)[int64_t(k) * kstep] = Z[k2];
+                else reinterpret_cast<uint32_t *>(lrow)[int64_t(k) * kstep] = half2_bits<FMT>(Z[k2], iq);
+                continue;
+            }
+            int64_t idx = lbase + int64_t(k) * a.out_j;
+            if (job.tile_stride) {
+                // ring rows of kTile frequencies x 4 components: [c/2][k][c%2]
+                // (FP32) or [k][c] (FP16/BF16); one job's indices stay below 2^31
+                const uint32_t u = uint32_t(idx);
+                const uint32_t kk = u >> 2, c = u & 3u, kt = kk % kTile;
+                const uint32_t w = (FMT == RING_F32) ? (c >> 1) * (2 * kTile) + kt * 2 + (c & 1u) : kt * 4 + c;
+                idx = int64_t(kk / kTile) * job.tile_stride + int64_t(w);
+            }
+            if constexpr (FMT == RING_F32) reinterpret_cast<Cf *>(obase)[idx] = Z[k2];
+            else reinterpret_cast<uint32_t *>(obase)[idx] = half2_bits<FMT>(Z[k2], iq);
+        }
+    }
+}
+
+template <int P, int T, int FMT, bool HALF>
+void launch_reg_dir(const LinePass &a, const RegArgs &ra, dim3 grid, hipStream_t st) {
+    if (a.dir > 0) hipLaunchKernelGGL((k_line_reg<P, T, FMT, +1, HALF>), grid, dim3(256), 0, st, a, ra);
+    else hipLaunchKernelGGL((k_line_reg<P, T, FMT, -1, HALF>), grid, dim3(256), 0, st, a, ra);
+}
+
+template <int P, int T>
+void launch_reg_fmt(const LinePass &a, const RegArgs &ra, hipStream_t st) {
+    constexpr int L = 256 / T;
+    const dim3 grid((a.lines + L - 1) / L, a.n_jobs);
+    const bool half = a.dir < 0 ? 2 * a.n_in <= P : 2 * a.n_out <= P;
+    switch (a.out_fmt) {
+    case RING_F16:
+        if (half) launch_reg_dir<P, T, RING_F16, true>(a, ra, grid, st);
+        else launch_reg_dir<P, T, RING_F16, false>(a, ra, grid, st);
+        break;
+    case RING_BF16:
+        if (half) launch_reg_dir<P, T, RING_BF16, true>(a, ra, grid, st);
+        else launch_reg_dir<P, T, RING_BF16, false>(a, ra, grid, st);
+        break;
+    default:
+        if (half) launch_reg_dir<P, T, RING_F32, true>(a, ra, grid, st);
+        else launch_reg_dir<P, T, RING_F32, false>(a, ra, grid, st);
+    }
+}
+
+// byte extent of one job's input: the largest element index + 1
+int64_t input_extent(const LinePass &a) {
+    const int64_t n_outer = (a.lines + a.n_inner - 1) / a.n_inner;
+    return ((n_outer - 1) * a.in_outer + int64_t(a.n_inner - 1) * a.in_inner + int64_t(a.n_in - 1) * a.in_j + 1) * 8;
+}
+
+}  // namespace
+
+bool line_reg_supported(const LinePass &a) {
+    if (!(a.out_fmt == RING_F32 || a.out_fmt == RING_F16 || a.out_fmt == RING_BF16)) return false;
+    bool tiled = false;
+    for (int j = 0; j < a.n_jobs; ++j) tiled = tiled || a.jobs[j].tile_stride != 0;
+    if (tiled && (a.tile_comp != 4 || a.out_j != 4)) return false;
+    if (a.out_fmt != RING_F32 && !(tiled && a.jobs[0].qscale)) return false;
+    for (int g : {a.in_group, a.out_group})
+        if (g != 0 && g != 1 && g != 2 && g != 4) return false;
+    if (a.lines < 1 || a.n_in < 1 || a.lines % a.n_inner != 0) return false;
+    if (a.in_j < 0 || a.in_inner < 0 || a.in_outer < 0) return false;
+    if (input_extent(a) >= (int64_t(1) << 31)) return false;   // buffer loads with 32-bit offsets
+    switch (a.P) {
+    case 32: case 48: case 64: case 96: case 128: case 256: return true;
+    default: return false;
+    }
+}
+
+// FP32 line pass in registers; false (nothing launched) when the pass is not
+// one this kernel covers (other lengths, FP64 output, one-component tiles,
+// inputs above 2 GiB).
+bool launch_line_reg(const LinePass &a0, hipStream_t st) {
+    if (!line_reg_supported(a0)) return false;
+    LinePass a = a0;
+    a.dinner = FastDiv(uint32_t(a.n_inner));
+    RegArgs ra{};
+    ra.lg_in = a.in_group > 0 ? (a.in_group >> 1) : -1;
+    ra.lg_out = a.out_group > 0 ? (a.out_group >> 1) : -1;
+    ra.in_bytes = int(input_extent(a));
+    switch (a.P) {
+    case 32: launch_reg_fmt<32, 4>(a, ra, st); break;
+    case 48: launch_reg_fmt<48, 4>(a, ra, st); break;
+    case 64: launch_reg_fmt<64, 8>(a, ra, st); break;
+    case 96: launch_reg_fmt<96, 4>(a, ra, st); break;
+    case 128: launch_reg_fmt<128, 8>(a, ra, st); break;
+    default: launch_reg_fmt<256, 16>(a, ra, st); break;
+    }
+    return true;
+}
+
+}  // namespace rpot

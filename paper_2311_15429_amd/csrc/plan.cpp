@@ -778,6 +778,7 @@ LinePass line_pass(rp_plan p, int P, bool dbl, int dir) {
     LinePass a{};
     a.P = P;
     a.lds_elems = p->fft_lds;
+    a.reg = p->fft_reg;
     a.dir = dir;
     a.tw = tw_ptr(p, P, dbl);
     a.rp = make_radix(P);
@@ -1918,6 +1919,10 @@ rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value) {
             plan->fft_lds = value;
             for (ClassP &K : plan->cls) K.fft_lds = 0;   // the plan's value for every class
             break;
+        case RP_TUNE_FFT_REG:
+            if (value != 0 && value != 1) fail(RP_ERR_ARG, "register line passes must be 0 or 1");
+            plan->fft_reg = value;
+            break;
         case RP_TUNE_LAGSUM_CACHED:
             if (value != 0 && value != 1) fail(RP_ERR_ARG, "cached must be 0 or 1");
             plan->k2b_cached = value;
@@ -1987,6 +1992,7 @@ rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value) {
         case RP_TUNE_LAGSUM_STEPS: *value = plan->kb; break;
         case RP_TUNE_LAGSUM_CACHED: *value = plan->k2b_cached; break;
         case RP_TUNE_LAGSUM_TILE_MAJOR: *value = plan->k2b_tile_major; break;
+        case RP_TUNE_FFT_REG: *value = plan->fft_reg; break;
         case RP_TUNE_FFT_LDS: *value = plan->fft_lds ? plan->fft_lds : (plan->p64 ? 4096 : 2048); break;
         default: fail(RP_ERR_ARG, "unknown tuning knob");
         }

@@ -241,6 +241,7 @@ struct rp_plan_s {
     int k2_unroll = 1;   // lags whose loads a lag-sum thread issues together
     int k2_persist = 0;  // persistent lag-sum launch (work counter) instead of one block per item
     int fft_lds = 0;     // line-pass tile: complex elements staged per block (0: default)
+    int fft_reg = 1;     // FP32 line passes of the supported lengths in registers
     int split_gap = 0;   // split a source's history at lag gaps of at least this many lags (0: off)
     std::vector<rpot_host::VRingP> vring;
     // host tier of a split history: real-space rings in pinned host memory

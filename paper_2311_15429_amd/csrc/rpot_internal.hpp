@@ -70,6 +70,7 @@ struct LinePass {
     int L;                 // lines per block (set by the launcher)
     int lds_elems;         // complex elements staged per block: 0 (default 4096), 2048, 4096 or 6144
                            // (FP32; half of it in FP64)
+    int reg;               // 1: register-resident pass where the length allows (FP32)
     FastDiv dL, dP, dinner, dnout;   // set by the launcher
     int64_t in_j, in_inner, in_outer;
     int64_t out_j, out_inner, out_outer;
@@ -225,6 +226,9 @@ struct K2Args {
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files).
 void launch_line_pass(const LinePass &a, int prec64, hipStream_t st);
+// register-resident FP32 line pass (fft_reg.hip); false when it does not
+// cover the pass (nothing launched)
+bool launch_line_reg(const LinePass &a, hipStream_t st);
 void launch_zfwd(const ZFwd &a, int prec64, hipStream_t st);
 void launch_zinv(const ZInv &a, int prec64, hipStream_t st);
 int zfwd_lines_per_block(int Pz, int prec64);

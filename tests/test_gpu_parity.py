@@ -191,12 +191,14 @@ def test_largest_fft_length(precision, tol):
 
 
 @pytest.mark.parametrize("dims,pads", [((16, 24, 32), (32, 48, 64)), ((48, 54, 8), (96, 108, 16)),
-                                       ((64, 4, 128), (128, 8, 256))])
+                                       ((64, 4, 128), (128, 8, 256)), ((32, 128, 8), (64, 256, 16))])
 def test_fixed_length_transforms_fp32(dims, pads):
     """Pads that reach every transform length with a compile-time FP32 kernel
-    (x: 32, 96, 128; y: 48, 108; z: 64, 256) and two without one (8, 16).  At
-    the 2048 and 4096 tiles (compile-time kernels) the result is the oracle's,
-    and it agrees with the run-time kernel of the 6144 tile to FP32 rounding."""
+    (x: 32, 64, 96, 128; y: 48, 108, 256; z: 64, 256) and two without one
+    (8, 16).  The register-resident line passes (lengths 32, 48, 64, 96, 128,
+    256) and the LDS-staged passes at the 2048 and 4096 tiles (compile-time
+    kernels) give the oracle's result, and both agree with the run-time
+    kernel of the 6144 tile to FP32 rounding."""
     from paper_2311_15429_amd import plan_for_system
     h = 0.5
     rng = np.random.default_rng(sum(dims))
@@ -210,11 +212,12 @@ def test_fixed_length_transforms_fp32(dims, pads):
     p.close()
     L = 10
     S = _samples(s, L)
-    runs = {tile: run_gpu(s, "fp32", S, tune={"fft_lds": tile}) for tile in (2048, 4096, 6144)}
+    runs = {tile: run_gpu(s, "fp32", S, tune={"fft_reg": 0, "fft_lds": tile}) for tile in (2048, 4096, 6144)}
+    runs["reg"] = run_gpu(s, "fp32", S, tune={"fft_reg": 1})
     ref = oracle.potential_full(s, S, [L])[0]
-    for tile in (2048, 4096):
+    for tile in (2048, 4096, "reg"):
         e = rel_err(runs[tile][L], ref)
-        log(f"pads {pads}, tile {tile}: rel err vs oracle {np.array2string(e, precision=2)}")
+        log(f"pads {pads}, line pass {tile}: rel err vs oracle {np.array2string(e, precision=2)}")
         assert np.all(e <= FP32_TOL), (tile, e)
         for l in range(L + 1):
             d = rel_err(runs[tile][l], runs[6144][l]) if np.any(runs[6144][l][0]) else np.zeros(4)
