@@ -489,8 +489,14 @@ def bench_surrogate(args):
     from paper_2311_15429_amd import surrogate as S
     from synth.sources import config5, spatial_factors, time_factors
 
-    FAR, NL, T_STEPS, JUDGE_EVERY, TOL = 10.0, 64, 3000, 100, 1e-4
+    FAR, NL, T_STEPS, TOL = 10.0, 64, 3000, 1e-4
     precision = args.precision or "fp32_ring_i16"
+    # lag-sum steps per pass; the judge may change the plain pairs only
+    # between blocks, so it runs after the last step of a block (steps
+    # 96, 192, ...; blocks start at steps 1, 1 + kb, ...)
+    KB = args.lagsum_steps
+    JUDGE_EVERY = 96 if KB > 1 else 100
+    JUDGE_AT = 0 if KB > 1 else JUDGE_EVERY - 1
     stream = torch.cuda.current_stream()
 
     class Gen:
@@ -516,6 +522,8 @@ def bench_surrogate(args):
     for seed in (args.teacher_seeds if args.far in ("learned", "hybrid") else []):
         tsys = config5(seed)
         p = plan_for_system(tsys, "fp32", stream=stream)
+        if KB > 1:
+            p.set_tuning("lagsum_steps", KB)
         p.surrogate_configure(FAR, n_lags=NL, audit=range(args.teacher_audit))
         log(f"teacher seed {seed}: {p.surrogate_info()}, workspace {p.workspace_bytes / 1e9:.1f} GB")
         p.bind()
@@ -547,6 +555,8 @@ def bench_surrogate(args):
     pst = plain.stats()
     plain.close()
     plan = plan_for_system(system, precision, stream=stream)
+    if KB > 1:
+        plan.set_tuning("lagsum_steps", KB)
     plan.surrogate_configure(FAR, n_lags=NL, audit=list(args.audit))
     info = plan.surrogate_info()
     st = plan.stats()
@@ -573,7 +583,7 @@ def bench_surrogate(args):
     def step(l):
         plan.push_sources(l, gen(l))
         plan.retarded_step(l, outs)
-        if l % JUDGE_EVERY == JUDGE_EVERY - 1:
+        if l > 0 and l % JUDGE_EVERY == JUDGE_AT:
             judged.append(plan.surrogate_judge(outs, TOL))
             readmitted.append(plan.last_readmitted)
 
@@ -593,7 +603,7 @@ def bench_surrogate(args):
     for i, l in enumerate(range(W + 1, W + K + 1)):
         plan.push_sources(l, src[i])
         plan.retarded_step(l, outs)
-        if l % JUDGE_EVERY == JUDGE_EVERY - 1:
+        if l > 0 and l % JUDGE_EVERY == JUDGE_AT:
             judged.append(plan.surrogate_judge(outs, TOL))
             readmitted.append(plan.last_readmitted)
     torch.cuda.synchronize()
@@ -697,6 +707,7 @@ def bench_surrogate(args):
                                    + " (pairs > 10 box diagonals apart)",
                        "precision": precision, "far_pairs": info["n_far"], "audited_far_pairs": info["n_audited"],
                        "judge_every": JUDGE_EVERY, "judge_tol": TOL, "fallbacks": fell,
+                       "lagsum_steps_per_pass": KB,
                        "readmit_factor": args.readmit, "readmissions": back, "plain_pairs_at_end": plain_now,
                        "rel_err_vs_fp64_oracle_sampled": [float(v) for v in err_s],
                        "rel_err_far_pairs_left_out_sampled": [float(v) for v in err_d],
@@ -712,7 +723,8 @@ def bench_surrogate(args):
                        "teacher_samples": n_samples, "teacher_s": round(t_data, 1), "train_s": round(t_train, 1),
                        "train_rel_rms": train_rms, "autotune": tuned},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_lagsum",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "k_lagsum" if KB == 1 else f"k_lagsum_block ({KB} steps per pass)",
                          "kernel_ms": round(lag_s * 1e3, 4), "algorithmic_bytes_per_launch": st["lagsum_bytes"]},
             "cpu_baseline": None}
     print(json.dumps(line), flush=True)
@@ -1057,8 +1069,8 @@ def main():
                     help="scale workload: time from step 1 on instead of after the history fill")
     ap.add_argument("--lagsum-unroll", type=int, default=None, choices=[1, 2, 4])
     ap.add_argument("--lagsum-steps", type=int, default=8, choices=[1, 2, 4, 8],
-                    help="scale workload: steps of the lag sum per pass over the history (1: every step "
-                         "reads the whole history)")
+                    help="scale and surrogate workloads: steps of the lag sum per pass over the history (1: "
+                         "every step reads the whole history)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default lag-sum schedule")
     ap.add_argument("--workload", default="scale",
                     choices=["scale", "batched", "batched_scaled", "surrogate", "small", "sweep", "coupled", "paper", "mlp"],

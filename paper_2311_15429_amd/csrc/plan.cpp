@@ -370,6 +370,30 @@ void size_k2(K2Dev &D, const K2Tables &T) {
     D.cap_masks = T.masks.size();
 }
 
+// Capacities raised to hold schedule T as well.
+void grow_k2(K2Dev &D, const K2Tables &T) {
+    D.cap_items = std::max(D.cap_items, T.items.size());
+    D.cap_groups = std::max(D.cap_groups, T.groups.size());
+    D.cap_entries = std::max(D.cap_entries, T.entries.size());
+    D.cap_srcs = std::max(D.cap_srcs, T.srcs.size());
+    D.cap_pairs = std::max(D.cap_pairs, T.pairs.size());
+    D.cap_masks = std::max(D.cap_masks, T.masks.size());
+}
+
+// The blocked schedules rebuilt for the current plain pairs (after the
+// surrogate's judge moved pairs between the network and the plain sum) and
+// copied into their device tables.
+void rebuild_blocked(rp_plan p, hipStream_t st) {
+    if (p->kb <= 1) return;
+    main_k2(p, p->k2b, plain_pair, 1);
+    order_k2b(p);
+    upload_k2(p, p->k2b, p->k2b_dev, st);
+    for (int i = 1; i < p->kb; ++i) {
+        main_k2(p, p->k2c[size_t(i - 1)], plain_pair, kGroupMax, i - 1);
+        upload_k2(p, p->k2c[size_t(i - 1)], p->k2c_dev[size_t(i - 1)], st);
+    }
+}
+
 // Ring depths, stored Green spectra and the lag-sum schedules.
 void plan_tables(rp_plan p) {
     const int nd = p->n_dom;
@@ -493,6 +517,17 @@ void plan_tables(rp_plan p) {
         for (int i = 1; i < p->kb; ++i) {
             main_k2(p, p->k2c[size_t(i - 1)], plain_pair, kGroupMax, i - 1);
             size_k2(p->k2c_dev[size_t(i - 1)], p->k2c[size_t(i - 1)]);
+        }
+        if (p->sur.on) {
+            // room for the largest blocked schedules a fallback can reach
+            K2Tables cb;
+            main_k2(p, cb, keeps_history, 1);
+            grow_k2(p->k2b_dev, cb);
+            for (int i = 1; i < p->kb; ++i) {
+                K2Tables cc;
+                main_k2(p, cc, keeps_history, kGroupMax, i - 1);
+                grow_k2(p->k2c_dev[size_t(i - 1)], cc);
+            }
         }
     }
     // room for the largest schedule a fallback can reach
@@ -1355,23 +1390,23 @@ void enqueue_lagsum(rp_plan p, hipStream_t st, int unroll, int persist, int phas
     const int32_t *head = p->at<int32_t>(p->off_head);
     if (p->kb == 1) {
         enqueue_k2(p, k2_args(p, p->k2, p->k2_dev, head), p->k2.tg, st, unroll, persist);
-        if (p->sur.on) sur_enqueue_slots(p, head, st);
-        return;
-    }
-    if (phase == 0) {
+    } else if (phase == 0) {
         K2Args a = k2_args(p, p->k2b, p->k2b_dev, head);
         a.cached = p->k2b_cached;
-        if (a.n_items == 0) return;
-        const int grid = persist ? p->n_cu * lagsum_block_blocks_per_cu(p->ring_fmt, p->kb, unroll) : 0;
-        launch_lagsum_block(a, p->ring_fmt, p->kb, unroll, grid, st);
-        check_launch();
-        return;
+        if (a.n_items > 0) {
+            const int grid = persist ? p->n_cu * lagsum_block_blocks_per_cu(p->ring_fmt, p->kb, unroll) : 0;
+            launch_lagsum_block(a, p->ring_fmt, p->kb, unroll, grid, st);
+            check_launch();
+        }
+    } else {
+        const K2Tables &T = p->k2c[size_t(phase - 1)];
+        K2Args a = k2_args(p, T, p->k2c_dev[size_t(phase - 1)], head);
+        a.acc_set = phase;
+        a.accumulate = 1;
+        enqueue_k2(p, a, T.tg, st, 1, 0);
     }
-    const K2Tables &T = p->k2c[size_t(phase - 1)];
-    K2Args a = k2_args(p, T, p->k2c_dev[size_t(phase - 1)], head);
-    a.acc_set = phase;
-    a.accumulate = 1;
-    enqueue_k2(p, a, T.tg, st, 1, 0);
+    // the fallback slots' pairs, one step at a time, into this step's set
+    if (p->sur.on) sur_enqueue_slots(p, head, st, phase);
 }
 
 // Inverse transform of every target's accumulated spectrum, crop to the
@@ -1937,7 +1972,6 @@ rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value) {
                 fail(RP_ERR_ARG, "lag-sum steps per pass must be 1, 2, 4 or 8");
             if (plan->ws) fail(RP_ERR_STATE, "choose the lag-sum steps per pass before rp_bind_workspace");
             if (value > 1 && plan->p64) fail(RP_ERR_UNSUPPORTED, "blocked lag-sum steps need an FP32 plan");
-            if (value > 1 && plan->sur.on) fail(RP_ERR_UNSUPPORTED, "the surrogate and blocked steps do not combine");
             plan->kb = value;
             plan_tables(plan);
             plan_layout(plan);

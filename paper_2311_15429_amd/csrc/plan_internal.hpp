@@ -317,6 +317,8 @@ void need_ws(rp_plan p);
 void plan_stats(rp_plan p);
 void release_graph(rp_plan p);
 void upload_k2(rp_plan p, const K2Tables &T, const K2Dev &D, hipStream_t st);
+void rebuild_blocked(rp_plan p, hipStream_t st);   // blocked schedules for the current plain pairs
+int lag_phase(rp_plan p, int64_t step);            // phase of a step within its block of blocked steps
 K2Args k2_args(rp_plan p, const K2Tables &T, const K2Dev &D, const int32_t *head);
 void enqueue_k2(rp_plan p, const K2Args &a, int tg, hipStream_t st, int unroll, int persist);
 bool keeps_history(rp_plan p, int s, int n);
@@ -348,7 +350,7 @@ void sur_sample(rp_plan p, int per_judge, int n_slots);
 void sur_sample_fields(rp_plan p, const int32_t *far_pairs, int n, float *out);
 void sur_slot_tables(rp_plan p);                          // after plan_layout's DomDev table
 void sur_ring_jobs(rp_plan p, const ClassP &K, std::vector<RingJob> &jobs);   // the slots' per-step transforms
-void sur_enqueue_slots(rp_plan p, const int32_t *head, hipStream_t st);      // the slots' lag sum
+void sur_enqueue_slots(rp_plan p, const int32_t *head, hipStream_t st, int phase);   // the slots' lag sum
 // The plain lag sum of every target over the pairs pred admits: groups of up
 // to gmax targets, windows clipped to lags <= m_cap.
 void main_k2(rp_plan p, K2Tables &T, bool (*pred)(rp_plan, int, int), int gmax = kGroupMax, int m_cap = INT32_MAX);

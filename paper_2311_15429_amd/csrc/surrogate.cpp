@@ -494,11 +494,13 @@ void sur_ring_jobs(rp_plan p, const ClassP &K, std::vector<RingJob> &jobs) {
     }
 }
 
-// The slot pairs' lag sum, added into their targets' accumulators.
-void sur_enqueue_slots(rp_plan p, const int32_t *head, hipStream_t st) {
+// The slot pairs' lag sum, added into their targets' accumulators (set
+// `phase` of a block of blocked lag-sum steps).
+void sur_enqueue_slots(rp_plan p, const int32_t *head, hipStream_t st, int phase) {
     SurrogateH &U = p->sur;
     if (U.k2p.items.empty()) return;
     K2Args a = k2_args(p, U.k2p, U.k2p_dev, head);
+    a.acc_set = phase;
     a.accumulate = 1;
     enqueue_k2(p, a, U.k2p.tg, st, 1, 0);
 }
@@ -921,7 +923,6 @@ void sur_configure(rp_plan p, double far_factor, int n_lags, const int32_t *audi
         U = SurrogateH{};
     } else {
         if (!p->target.empty()) fail(RP_ERR_UNSUPPORTED, "the surrogate and a target subset do not combine");
-        if (p->kb > 1) fail(RP_ERR_UNSUPPORTED, "the surrogate and blocked lag-sum steps do not combine");
         if (!std::isfinite(far_factor)) fail(RP_ERR_ARG, "far_factor must be finite");
         if (p->split_gap > 0) fail(RP_ERR_UNSUPPORTED, "the surrogate and a split history do not combine");
         if (p->p64) fail(RP_ERR_UNSUPPORTED, "the surrogate runs with FP32 outputs (not RP_FP64)");
@@ -1087,6 +1088,10 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
     for (int n = 0; n < p->n_dom; ++n)
         if (!out[n]) fail(RP_ERR_ARG, "an out pointer is null");
     if (!(tol > 0)) fail(RP_ERR_ARG, "tol must be positive");
+    // blocked lag-sum steps: the block's pass has summed the plain pairs of
+    // all its steps, so the pairs may change only before a block starts
+    if (p->kb > 1 && lag_phase(p, p->next_step) != 0)
+        fail(RP_ERR_STATE, "with blocked lag-sum steps the judge runs after the last step of a block");
     hipStream_t st = p->stream;
     const int na = int(U.aud.size());
     // the far pairs of non-audit sources judged by sample in this call
@@ -1262,6 +1267,7 @@ void sur_judge(rp_plan p, void *const *out, double tol, int32_t *n_fallback, dou
             release_graph(p);
             main_k2(p, p->k2, plain_pair);
             upload_k2(p, p->k2, p->k2_dev, st);
+            rebuild_blocked(p, st);
             if (!U.slots.empty()) {
                 slot_k2(p);
                 upload_k2(p, U.k2p, U.k2p_dev, st);

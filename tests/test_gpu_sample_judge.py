@@ -30,9 +30,11 @@ def _all_arrived(p, pairs):
     return max(p.info(int(t), int(n))[0] for t, n in zip(pairs["target"], pairs["source"])) + 4
 
 
-def _plan(system, audit, per_judge, slots, precision="fp32"):
+def _plan(system, audit, per_judge, slots, precision="fp32", steps=1):
     from paper_2311_15429_amd import plan_for_system
     p = plan_for_system(system, precision, stream=torch.cuda.current_stream())
+    if steps > 1:
+        p.set_tuning("lagsum_steps", steps)
     p.surrogate_configure(FAR, n_lags=N_LAGS, audit=audit)
     p.surrogate_sample(per_judge, slots)
     p.bind()
@@ -66,17 +68,22 @@ def test_sample_fields_match_the_oracle_direct_sum():
     p.close()
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("fp32_ring_i16", 1e-4)])
-def test_non_audit_pairs_fall_back_into_slots_and_match_the_oracle(precision, tol):
+@pytest.mark.parametrize("precision,tol,steps", [("fp32", 2e-5, 1), ("fp32_ring_i16", 1e-4, 1), ("fp32", 2e-5, 4),
+                                                ("fp32_ring_i16", 1e-4, 8)])
+def test_non_audit_pairs_fall_back_into_slots_and_match_the_oracle(precision, tol, steps):
     """Multipole terms judged with a tiny tolerance: every far pair fails,
     audited ones into the plain lag sum, the others into fallback slots
     (refilled from the real-space history, Green spectra computed then).  From
-    the next step on the whole output is the plain method's."""
+    the next step on the whole output is the plain method's.  With blocked
+    lag-sum steps (4 or 8 per pass) the judge runs after the last step of a
+    block, the blocked schedules are rebuilt with the fallen-back pairs, and
+    the slots add their pairs step by step into the block's accumulators."""
     system = far_system(12)
-    p = _plan(system, audit=[2], per_judge=0, slots=32, precision=precision)
+    p = _plan(system, audit=[2], per_judge=0, slots=32, precision=precision, steps=steps)
     p.surrogate_multipole(True)
     pairs = p.surrogate_pairs()
     Lj = _all_arrived(p, pairs)
+    Lj += (-Lj) % steps                   # a block's last step (blocks start at steps 1, 1 + kb, ...)
     L = Lj + 14
     S = sy.sample_sources(system, range(L + 1))
     n_far_nonaudit = int((~pairs["audited"]).sum())
@@ -88,6 +95,9 @@ def test_non_audit_pairs_fall_back_into_slots_and_match_the_oracle(precision, to
     for l in range(L + 1):
         p.push_sources(l, gen.step(l))
         p.retarded_step(l, outs)
+        if steps > 1 and l == Lj - 1:
+            with pytest.raises(Exception, match="last step of a block"):
+                p.surrogate_judge(outs, 1e-9)
         if l == Lj:
             nf, worst = p.surrogate_judge(outs, 1e-9)
             st = p.surrogate_judge_stats()
@@ -104,7 +114,8 @@ def test_non_audit_pairs_fall_back_into_slots_and_match_the_oracle(precision, to
         e = rel_err(g, r)
         worst = max(worst, float(e.max()))
         assert np.all(e <= tol), (l, e)
-    log(f"{precision}: {n_far_nonaudit} non-audit pairs in slots; steps {Lj + 1}..{L} vs oracle {worst:.2e}")
+    log(f"{precision}, {steps} steps per pass: {n_far_nonaudit} non-audit pairs in slots; steps {Lj + 1}..{L} "
+        f"vs oracle {worst:.2e}")
     p.close()
 
 

@@ -32,9 +32,11 @@ def far_system(seed=0, n=8, h=0.5):
     return sy.System(h, 0.02, sy.C_AU, doms)
 
 
-def make_plan(system, audit=None, precision="fp32"):
+def make_plan(system, audit=None, precision="fp32", steps=1):
     from paper_2311_15429_amd import plan_for_system
     p = plan_for_system(system, precision, stream=torch.cuda.current_stream())
+    if steps > 1:
+        p.set_tuning("lagsum_steps", steps)
     p.surrogate_configure(FAR, n_lags=N_LAGS, audit=range(len(system.domains)) if audit is None else audit)
     p.bind()
     p.set_green_kernels()
@@ -137,11 +139,16 @@ def _random_mlp(n_in, n_far, scale=0.05, seed=0):
     return m
 
 
-def test_judge_falls_back_and_then_matches_the_plain_method():
+@pytest.mark.parametrize("steps", [1, 4])
+def test_judge_falls_back_and_then_matches_the_plain_method(steps):
+    """A loose judge keeps every pair on the network, a tight one sends every
+    audited pair back to the plain lag sum; from then on the output is the
+    oracle's.  With 4 lag-sum steps per pass both judgements fall on the last
+    step of a block and the blocked schedules take the pairs over."""
     system = far_system(4)
     L, Lj = 34, 24
     S = sy.sample_sources(system, range(L + 1))
-    p = make_plan(system)
+    p = make_plan(system, steps=steps)
     info = p.surrogate_info()
     mlp = _random_mlp(info["n_in"], info["n_far"])
     p.surrogate_attach(mlp, np.full(22, 1.0, np.float32), np.full(80, 1e-3, np.float32))
@@ -151,7 +158,7 @@ def test_judge_falls_back_and_then_matches_the_plain_method():
     for l in range(L + 1):
         p.push_sources(l, gen.step(l))
         p.retarded_step(l, outs)
-        if l == Lj - 1:
+        if l == Lj - steps:
             nf, worst = p.surrogate_judge(outs, 1e3)       # loose: nobody falls back
             assert nf == 0 and 0 < worst < 1
         if l == Lj:

@@ -149,3 +149,27 @@ def test_judge_by_sample_plans_history_slots_and_errors():
     with pytest.raises(RpotError):
         q.surrogate_sample(0, 4)                          # no surrogate configured
     q.close()
+
+
+def test_surrogate_with_blocked_lag_sum_steps_plans_in_either_order():
+    """The surrogate combines with blocked lag-sum steps (set before or after
+    the surrogate): the same far pairs, kb accumulator sets per target, and a
+    blocked pass that reads fewer bytes per step than one step per pass."""
+    system = _system()
+    one = plan_for_system(system, "fp32")
+    one.surrogate_configure(3.0, audit=[2])
+    a = plan_for_system(system, "fp32")
+    a.set_tuning("lagsum_steps", 8)
+    a.surrogate_configure(3.0, audit=[2])
+    b = plan_for_system(system, "fp32")
+    b.surrogate_configure(3.0, audit=[2])
+    b.set_tuning("lagsum_steps", 8)
+    for q in (a, b):
+        assert q.get_tuning("lagsum_steps") == 8
+        assert q.surrogate_info()["n_far"] == one.surrogate_info()["n_far"]
+        assert q.workspace_bytes > one.workspace_bytes
+        # the blocked pass of 8 steps, per step, against one step per pass
+        assert q.stats()["lagsum_bytes"] / 8 < one.stats()["lagsum_bytes"]
+    assert a.stats() == b.stats()
+    for q in (one, a, b):
+        q.close()
