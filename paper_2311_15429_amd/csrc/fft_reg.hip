@@ -217,6 +217,14 @@ __device__ __forceinline__ uint32_t half2_bits(Cf v, float s) {
     }
 }
 
+// 16-bit integer pair (re low, im high) of a value already scaled to
+// [-32767, 32767] (rounded to nearest, clamped)
+__device__ __forceinline__ uint32_t i16_bits(float re, float im) {
+    const int a = int(rintf(fminf(fmaxf(re, -32767.f), 32767.f)));
+    const int b = int(rintf(fminf(fmaxf(im, -32767.f), 32767.f)));
+    return (uint32_t(a) & 0xffffu) | (uint32_t(b) << 16);
+}
+
 constexpr int kRsrcWord3 = 0x00020000;   // gfx9-family buffer descriptor word 3
 constexpr uint32_t kOutOfRange = 0x80000000u;   // beyond every input: the load returns 0
 
@@ -293,19 +301,21 @@ __global__ __launch_bounds__(256) void k_line_reg(LinePass a, RegArgs ra) {
     int li, t;
     line_thread<T, L>(tid, ra.lg_out, li, t);
     const int line = line0 + li;
-    if (line >= a.lines) return;
-    const int outer = a.dinner.div(line);
-    const int inner = line - outer * a.n_inner;
+    const bool live = line < a.lines;
+    const int outer = live ? a.dinner.div(line) : 0;
+    const int inner = live ? line - outer * a.n_inner : 0;
     char *obase = reinterpret_cast<char *>(job.out);
     const float *qs = job.qscale;
     constexpr int esz = (FMT == RING_F32) ? 8 : 4;
+    int32_t slot = 0;
     if (job.head) {
-        const int64_t slot = *job.head;
-        obase += slot * job.slot_stride * esz;
-        if (qs) qs += slot * 4;
+        slot = *job.head;
+        obase += int64_t(slot) * job.slot_stride * esz;
+        if (qs && FMT != RING_I16) qs += int64_t(slot) * 4;
     }
     float iq = 1.0f;
-    if (FMT != RING_F32) iq = 1.0f / qs[inner & 3];   // scales are powers of two: exact
+    if (FMT == RING_F16 || FMT == RING_BF16)
+        if (live) iq = 1.0f / qs[inner & 3];   // scales are powers of two: exact
     const int64_t lbase = outer * a.out_outer + inner * a.out_inner;
     // tiled output of a length that divides the tile: the whole line is one
     // run of one ring row, out_j = 4 (four components per frequency)
@@ -318,6 +328,8 @@ __global__ __launch_bounds__(256) void k_line_reg(LinePass a, RegArgs ra) {
     }
     constexpr int kstep = (FMT == RING_F32) ? 2 : 4;   // ring-row elements between frequencies
     const Cf *row = buf + li * RS;
+    constexpr int NO = HALF_OUT ? T / 2 : T;
+    Cf Zs[E / T][NO];
 #pragma unroll
     for (int i = 0; i < E / T; ++i) {
         const int k1 = t + T * i;
@@ -327,12 +339,80 @@ __global__ __launch_bounds__(256) void k_line_reg(LinePass a, RegArgs ra) {
         if constexpr (HALF_OUT) dft_half_out<T, DIR>(z, Z);
         else dft<T, DIR>(z, Z);
 #pragma unroll
-        for (int k2 = 0; k2 < (HALF_OUT ? T / 2 : T); ++k2) {
+        for (int k2 = 0; k2 < NO; ++k2) Zs[i][k2] = Z[k2];
+    }
+
+    if constexpr (FMT == RING_I16) {
+        // Block floating point, fused: a block's lines (L / 4 x-lines of four
+        // components, the spectrum's x-fastest order) cover whole tiles of kTile
+        // frequencies, so the largest |Re|, |Im| per (tile, component) is
+        // reduced here, in LDS; then each value is scaled to 16 bits and
+        // written, and each (tile, component) scale once.
+        constexpr int NT = (L / 4) * P / kTile;
+        static_assert((L / 4) * P % kTile == 0, "a block must cover whole tiles");
+        __shared__ uint32_t tmax[NT][4];
+        const uint32_t kk0 = uint32_t(lbase) >> 2, c = uint32_t(lbase) & 3u;
+        const int tb = int(uint32_t(line0 / 4) * uint32_t(P) / kTile);   // the block's first tile
+        const int off = int(kk0 % kTile);                                 // the line's first frequency in its tile
+        const int tl0 = int(kk0 / kTile) - tb;                            // the line's first tile in the block
+        float m0 = 0.f, m1 = 0.f;
+#pragma unroll
+        for (int i = 0; i < E / T; ++i)
+#pragma unroll
+            for (int k2 = 0; k2 < NO; ++k2) {
+                const int k = t + T * i + E * k2;
+                const float v = fmaxf(fabsf(Zs[i][k2].x), fabsf(Zs[i][k2].y));
+                if (off + k < kTile) m0 = fmaxf(m0, v);
+                else m1 = fmaxf(m1, v);
+            }
+        // the table is cleared before any thread adds to it
+        if (tid < NT * 4) tmax[tid >> 2][tid & 3] = 0u;
+        __syncthreads();
+        if (live) {
+            // non-negative floats order like their bit patterns
+            atomicMax(&tmax[tl0][c], __float_as_uint(m0));
+            if (tl0 + 1 < NT && m1 > 0.f) atomicMax(&tmax[tl0 + 1][c], __float_as_uint(m1));
+        }
+        __syncthreads();
+        const int64_t depth = job.tile_stride / (int64_t(kTile) * 4);
+        if (tid < NT * 4) {
+            const int tg = tb + (tid >> 2);
+            if (int64_t(tg) * kTile < int64_t(a.lines / 4) * P)
+                job.qscale[(int64_t(tg) * depth + slot) * 4 + (tid & 3)] = __uint_as_float(tmax[tid >> 2][tid & 3]) / 32767.f;
+        }
+        if (!live) return;
+        const float mx0 = __uint_as_float(tmax[tl0][c]);
+        const float mx1 = tl0 + 1 < NT ? __uint_as_float(tmax[tl0 + 1][c]) : 0.f;
+        const float inv0 = mx0 > 0.f ? 32767.f / mx0 : 0.f, inv1 = mx1 > 0.f ? 32767.f / mx1 : 0.f;
+#pragma unroll
+        for (int i = 0; i < E / T; ++i)
+#pragma unroll
+            for (int k2 = 0; k2 < NO; ++k2) {
+                const int k = t + T * i + E * k2;
+                if (k >= a.n_out) continue;
+                const float s = off + k < kTile ? inv0 : inv1;
+                const uint32_t bits = i16_bits(Zs[i][k2].x * s, Zs[i][k2].y * s);
+                if (LINE_IN_TILE) {
+                    reinterpret_cast<uint32_t *>(lrow)[int64_t(k) * kstep] = bits;
+                } else {
+                    const uint32_t kk = kk0 + uint32_t(k), kt = kk % kTile;
+                    reinterpret_cast<uint32_t *>(obase)[int64_t(kk / kTile) * job.tile_stride + kt * 4 + c] = bits;
+                }
+            }
+        return;
+    }
+
+    if (!live) return;
+#pragma unroll
+    for (int i = 0; i < E / T; ++i) {
+        const int k1 = t + T * i;
+#pragma unroll
+        for (int k2 = 0; k2 < NO; ++k2) {
             const int k = k1 + E * k2;
             if (k >= a.n_out) continue;
             if (LINE_IN_TILE && job.tile_stride) {
-                if constexpr (FMT == RING_F32) reinterpret_cast<Cf *>(lrow)[int64_t(k) * kstep] = Z[k2];
-                else reinterpret_cast<uint32_t *>(lrow)[int64_t(k) * kstep] = half2_bits<FMT>(Z[k2], iq);
+                if constexpr (FMT == RING_F32) reinterpret_cast<Cf *>(lrow)[int64_t(k) * kstep] = Zs[i][k2];
+                else reinterpret_cast<uint32_t *>(lrow)[int64_t(k) * kstep] = half2_bits<FMT>(Zs[i][k2], iq);
                 continue;
             }
             int64_t idx = lbase + int64_t(k) * a.out_j;
@@ -344,8 +424,8 @@ __global__ __launch_bounds__(256) void k_line_reg(LinePass a, RegArgs ra) {
                 const uint32_t w = (FMT == RING_F32) ? (c >> 1) * (2 * kTile) + kt * 2 + (c & 1u) : kt * 4 + c;
                 idx = int64_t(kk / kTile) * job.tile_stride + int64_t(w);
             }
-            if constexpr (FMT == RING_F32) reinterpret_cast<Cf *>(obase)[idx] = Z[k2];
-            else reinterpret_cast<uint32_t *>(obase)[idx] = half2_bits<FMT>(Z[k2], iq);
+            if constexpr (FMT == RING_F32) reinterpret_cast<Cf *>(obase)[idx] = Zs[i][k2];
+            else reinterpret_cast<uint32_t *>(obase)[idx] = half2_bits<FMT>(Zs[i][k2], iq);
         }
     }
 }
@@ -370,6 +450,10 @@ void launch_reg_fmt(const LinePass &a, const RegArgs &ra, hipStream_t st) {
         if (half) launch_reg_dir<P, T, RING_BF16, true>(a, ra, grid, st);
         else launch_reg_dir<P, T, RING_BF16, false>(a, ra, grid, st);
         break;
+    case RING_I16:
+        if (half) launch_reg_dir<P, T, RING_I16, true>(a, ra, grid, st);
+        else launch_reg_dir<P, T, RING_I16, false>(a, ra, grid, st);
+        break;
     default:
         if (half) launch_reg_dir<P, T, RING_F32, true>(a, ra, grid, st);
         else launch_reg_dir<P, T, RING_F32, false>(a, ra, grid, st);
@@ -385,11 +469,21 @@ int64_t input_extent(const LinePass &a) {
 }  // namespace
 
 bool line_reg_supported(const LinePass &a) {
-    if (!(a.out_fmt == RING_F32 || a.out_fmt == RING_F16 || a.out_fmt == RING_BF16)) return false;
-    bool tiled = false;
-    for (int j = 0; j < a.n_jobs; ++j) tiled = tiled || a.jobs[j].tile_stride != 0;
+    if (!(a.out_fmt == RING_F32 || a.out_fmt == RING_F16 || a.out_fmt == RING_BF16 || a.out_fmt == RING_I16))
+        return false;
+    bool tiled = false, all_tiled = true, scaled = true;
+    for (int j = 0; j < a.n_jobs; ++j) {
+        tiled = tiled || a.jobs[j].tile_stride != 0;
+        all_tiled = all_tiled && a.jobs[j].tile_stride != 0;
+        scaled = scaled && a.jobs[j].qscale != nullptr;
+    }
     if (tiled && (a.tile_comp != 4 || a.out_j != 4)) return false;
-    if (a.out_fmt != RING_F32 && !(tiled && a.jobs[0].qscale)) return false;
+    if (a.out_fmt != RING_F32 && !(all_tiled && scaled)) return false;
+    // the fused 16-bit quantisation reduces whole tiles in a block: the x
+    // pass of a spectrum, lines (x-line, component), frequencies x fastest
+    if (a.out_fmt == RING_I16 &&
+        !(a.n_inner == 4 && a.out_inner == 1 && a.out_outer == int64_t(a.P) * 4 && a.n_out == a.P && a.dir < 0))
+        return false;
     for (int g : {a.in_group, a.out_group})
         if (g != 0 && g != 1 && g != 2 && g != 4) return false;
     if (a.lines < 1 || a.n_in < 1 || a.lines % a.n_inner != 0) return false;

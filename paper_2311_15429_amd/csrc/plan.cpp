@@ -1239,11 +1239,28 @@ void enqueue_ring_jobs(rp_plan p, const ClassP &K, const std::vector<RingJob> &j
         // lanes in the order of a ring row: [c/2][k][c%2] (FP32), [c][k]
         // (FP64), [k][c] (FP16/BF16)
         x.out_group = x.out_fmt == RING_F32 ? 2 : (x.out_fmt == RING_F64 ? 1 : 4);
+        // I16: the register x pass quantises in the same launch where it
+        // covers the pass; else FP32 rows into the staging area and the
+        // quantiser after
+        bool fused_i16 = false;
+        if (i16 && !p->p64 && x.reg) {
+            LinePass xi = x;
+            xi.out_fmt = RING_I16;
+            xi.out_group = 4;
+            xi.n_jobs = 1;
+            xi.jobs[0].tile_stride = kTile * 4;
+            xi.jobs[0].qscale = reinterpret_cast<float *>(p->ws);
+            fused_i16 = line_reg_supported(xi);
+        }
+        if (fused_i16) {
+            x.out_fmt = RING_I16;
+            x.out_group = 4;
+        }
         ScaleArgs sa{};
         QuantArgs qa{};
         z.n_jobs = y.n_jobs = x.n_jobs = cnt;
         sa.n_jobs = quant ? cnt : 0;
-        qa.n_jobs = i16 ? cnt : 0;
+        qa.n_jobs = (i16 && !fused_i16) ? cnt : 0;
         qa.max_tiles = int(Cpad / kTile);
         for (int j = 0; j < cnt; ++j) {
             const RingJob &J = jobs[j0 + j];
@@ -1265,7 +1282,10 @@ void enqueue_ring_jobs(rp_plan p, const ClassP &K, const std::vector<RingJob> &j
             x.jobs[j].slot_stride = int64_t(kTile) * 4;
             x.jobs[j].tile_stride = int64_t(J.depth) * kTile * 4;
             x.jobs[j].qscale = quant ? J.scales : nullptr;
-            if (i16) {
+            if (i16 && fused_i16) {
+                // the x pass quantises into the ring itself
+                x.jobs[j].qscale = J.scales;
+            } else if (i16) {
                 float *stage = p->at<float>(p->off_qstage + size_t(j) * size_t(Cpad) * 4 * 8);
                 x.jobs[j].out = stage;
                 x.jobs[j].head = nullptr;

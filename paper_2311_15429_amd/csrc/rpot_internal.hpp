@@ -58,7 +58,8 @@ enum RingFmt : int { RING_F64 = 0, RING_F32 = 1, RING_F16 = 2, RING_BF16 = 3, RI
 struct LineJob {
     const void *in;
     void *out;
-    const float *qscale;   // ring quantisation: scales [depth][4] of the domain, else null
+    float *qscale;         // ring quantisation: scales [depth][4] of the domain (FP16/BF16, read), or
+                           // [tile][depth][4] (16-bit integers, written by the quantising x pass); else null
     const int32_t *head;   // ring output: current slot of the domain's ring, else null
     int64_t slot_stride;   // ring output: elements per slot
     int64_t tile_stride;   // tiled output: elements per frequency tile (0: linear output)
@@ -229,6 +230,9 @@ void launch_line_pass(const LinePass &a, int prec64, hipStream_t st);
 // register-resident FP32 line pass (fft_reg.hip); false when it does not
 // cover the pass (nothing launched)
 bool launch_line_reg(const LinePass &a, hipStream_t st);
+// whether launch_line_reg covers the pass (an x pass into a 16-bit integer
+// ring then quantises in the same launch)
+bool line_reg_supported(const LinePass &a);
 void launch_zfwd(const ZFwd &a, int prec64, hipStream_t st);
 void launch_zinv(const ZInv &a, int prec64, hipStream_t st);
 int zfwd_lines_per_block(int Pz, int prec64);

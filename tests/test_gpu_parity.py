@@ -192,6 +192,33 @@ def test_largest_fft_length(precision, tol):
 
 @pytest.mark.parametrize("dims,pads", [((16, 24, 32), (32, 48, 64)), ((48, 54, 8), (96, 108, 16)),
                                        ((64, 4, 128), (128, 8, 256)), ((32, 128, 8), (64, 256, 16))])
+def test_i16_ring_quantised_by_the_x_pass(dims, pads):
+    """16-bit integer ring: the register x pass quantises each (tile of 256
+    frequencies, component) in the same launch (x lengths 32, 64, 96, 128;
+    a block's lines cover whole tiles).  Against the staged path (FP32 rows,
+    then the separate quantiser) and against the oracle at the ring's bar."""
+    h = 0.5
+    rng = np.random.default_rng(sum(dims) + 1)
+    off = np.array([h * dims[0] + 6.0, 2.0, -1.0])
+    doms = [sy.Domain(dims, np.zeros(3)), sy.Domain(dims, off)]
+    for d in doms:
+        sy._random_pairs(rng, d, h, 2)
+    s = sy.System(h, 0.02, sy.C_AU, doms, name=f"pads {pads}")
+    L = 10
+    S = _samples(s, L)
+    fused = run_gpu(s, "fp32_ring_i16", S, tune={"fft_reg": 1})
+    staged = run_gpu(s, "fp32_ring_i16", S, tune={"fft_reg": 0})
+    ref = oracle.potential_full(s, S, [L])[0]
+    e = rel_err(fused[L], ref)
+    log(f"pads {pads}, I16 ring quantised by the x pass: rel err vs oracle {np.array2string(e, precision=2)}")
+    assert np.all(e <= 1e-4), e
+    for l in range(1, L + 1):
+        d = rel_err(fused[l], staged[l])
+        assert np.all(d <= 2e-5), (l, d)
+
+
+@pytest.mark.parametrize("dims,pads", [((16, 24, 32), (32, 48, 64)), ((48, 54, 8), (96, 108, 16)),
+                                       ((64, 4, 128), (128, 8, 256)), ((32, 128, 8), (64, 256, 16))])
 def test_fixed_length_transforms_fp32(dims, pads):
     """Pads that reach every transform length with a compile-time FP32 kernel
     (x: 32, 64, 96, 128; y: 48, 108, 256; z: 64, 256) and two without one
