@@ -25,24 +25,38 @@ __device__ __forceinline__ void legendre4(float x, float (&p)[4]) {
     p[3] = 0.5f * x * (5.f * x * x - 3.f);
 }
 
-// basis index -> degrees along x, y, z (lexicographic, total degree <= 3)
-__constant__ int8_t kBasisDeg[kNBasis][3] = {
-    {0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 0, 3}, {0, 1, 0}, {0, 1, 1}, {0, 1, 2}, {0, 2, 0}, {0, 2, 1}, {0, 3, 0},
-    {1, 0, 0}, {1, 0, 1}, {1, 0, 2}, {1, 1, 0}, {1, 1, 1}, {1, 2, 0}, {2, 0, 0}, {2, 0, 1}, {2, 1, 0}, {3, 0, 0}};
+// basis index -> degrees along x, y, z (lexicographic, total degree <= 3); a
+// compile-time table, so the unrolled basis products index registers by
+// constants
+struct BasisDeg {
+    int8_t d[kNBasis][3];
+};
+constexpr BasisDeg kBasisDeg = {{{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 0, 3}, {0, 1, 0}, {0, 1, 1}, {0, 1, 2},
+                                 {0, 2, 0}, {0, 2, 1}, {0, 3, 0}, {1, 0, 0}, {1, 0, 1}, {1, 0, 2}, {1, 1, 0},
+                                 {1, 1, 1}, {1, 2, 0}, {2, 0, 0}, {2, 0, 1}, {2, 1, 0}, {3, 0, 0}}};
 
-__device__ __forceinline__ float box_coord(int i, int n) { return n > 1 ? 2.f * float(i) / float(n - 1) - 1.f : 0.f; }
+__device__ __forceinline__ float box_coord(int i, int n) { return n > 1 ? float(i) * (2.f / float(n - 1)) - 1.f : 0.f; }
+
+// (ix, iy, iz) of linear grid index i (z fastest); grids stay below 2^31
+// points, so the index arithmetic is 32-bit
+__device__ __forceinline__ void grid_xyz(int64_t i, const int (&N)[3], int &ix, int &iy, int &iz) {
+    const uint32_t u = uint32_t(i), nz = uint32_t(N[2]), ny = uint32_t(N[1]);
+    const uint32_t r = u / nz;
+    iz = int(u - r * nz);
+    ix = int(r / ny);
+    iy = int(r - uint32_t(ix) * ny);
+}
 
 // The 20 basis values at grid point i of an N[0] x N[1] x N[2] box.
 __device__ __forceinline__ void basis_at(int64_t i, const int (&N)[3], float (&B)[kNBasis]) {
-    const int iz = int(i % N[2]);
-    const int iy = int((i / N[2]) % N[1]);
-    const int ix = int(i / (int64_t(N[2]) * N[1]));
+    int ix, iy, iz;
+    grid_xyz(i, N, ix, iy, iz);
     float px[4], py[4], pz[4];
     legendre4(box_coord(ix, N[0]), px);
     legendre4(box_coord(iy, N[1]), py);
     legendre4(box_coord(iz, N[2]), pz);
 #pragma unroll
-    for (int b = 0; b < kNBasis; ++b) B[b] = px[kBasisDeg[b][0]] * py[kBasisDeg[b][1]] * pz[kBasisDeg[b][2]];
+    for (int b = 0; b < kNBasis; ++b) B[b] = px[kBasisDeg.d[b][0]] * py[kBasisDeg.d[b][1]] * pz[kBasisDeg.d[b][2]];
 }
 
 template <int NT>
@@ -82,9 +96,8 @@ __global__ __launch_bounds__(256) void k_moments_partial(MomentArgs a) {
 #pragma unroll
     for (int q = 0; q < kNMom; ++q) acc[q] = 0.f;
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < npts; i += int64_t(gridDim.x) * 256) {
-        const int iz = int(i % j.N[2]);
-        const int iy = int((i / j.N[2]) % j.N[1]);
-        const int ix = int(i / (int64_t(j.N[2]) * j.N[1]));
+        int ix, iy, iz;
+        grid_xyz(i, j.N, ix, iy, iz);
         const float r[3] = {j.o[0] + a.h * float(ix), j.o[1] + a.h * float(iy), j.o[2] + a.h * float(iz)};
         float d[4];
 #pragma unroll
@@ -120,15 +133,29 @@ __global__ __launch_bounds__(256) void k_moments_partial(MomentArgs a) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) acc[32 + 6 * c + k] = fmaf(d[1 + c], rr[k], acc[32 + 6 * c + k]);
     }
-    // wave sums, then the four waves in a fixed order
+    // Wave sums by recursive halving: at the step with lane mask m a lane
+    // keeps half of its values (the upper half when its bit m is set), sends
+    // the other half to lane ^ m and adds what that lane sent; after the six
+    // steps lane q holds the wave's sum of moment q (63 exchanges instead of
+    // 6 per moment).  Then the four waves in a fixed order.
+    static_assert(kNMom <= 64, "one moment per lane");
     __shared__ float red[4][kNMom];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float v[64];
 #pragma unroll
-    for (int q = 0; q < kNMom; ++q) {
-        float v = acc[q];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) red[wave][q] = v;
+    for (int q = 0; q < 64; ++q) v[q] = q < kNMom ? acc[q] : 0.f;
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int m = 32 >> st, h = 32 >> st;   // lane mask, values kept after the step
+        const bool up = (lane & m) != 0;
+#pragma unroll
+        for (int q = 0; q < h; ++q) {
+            const float send = up ? v[q] : v[q + h];
+            const float keep = up ? v[q + h] : v[q];
+            v[q] = keep + __shfl_xor(send, m, 64);
+        }
     }
+    if (lane < kNMom) red[wave][lane] = v[0];
     __syncthreads();
     if (threadIdx.x < kNMom) {
         const int q = threadIdx.x;
