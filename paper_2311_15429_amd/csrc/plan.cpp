@@ -360,6 +360,11 @@ void order_k2b(rp_plan p) {
                               hipMemcpyHostToDevice, p->stream));
 }
 
+// Targets per group of the additions of a blocked step (its lags m < i): one.
+// Those lags are the self pairs' (a target's own sources), so targets share no
+// source row and larger groups only raise the registers per thread.
+constexpr int kAddGroup = 1;
+
 // Device-table capacities of a schedule (its own sizes).
 void size_k2(K2Dev &D, const K2Tables &T) {
     D.cap_items = T.items.size();
@@ -389,7 +394,7 @@ void rebuild_blocked(rp_plan p, hipStream_t st) {
     order_k2b(p);
     upload_k2(p, p->k2b, p->k2b_dev, st);
     for (int i = 1; i < p->kb; ++i) {
-        main_k2(p, p->k2c[size_t(i - 1)], plain_pair, kGroupMax, i - 1);
+        main_k2(p, p->k2c[size_t(i - 1)], plain_pair, kAddGroup, i - 1);
         upload_k2(p, p->k2c[size_t(i - 1)], p->k2c_dev[size_t(i - 1)], st);
     }
 }
@@ -515,7 +520,7 @@ void plan_tables(rp_plan p) {
         order_k2b(p);
         size_k2(p->k2b_dev, p->k2b);
         for (int i = 1; i < p->kb; ++i) {
-            main_k2(p, p->k2c[size_t(i - 1)], plain_pair, kGroupMax, i - 1);
+            main_k2(p, p->k2c[size_t(i - 1)], plain_pair, kAddGroup, i - 1);
             size_k2(p->k2c_dev[size_t(i - 1)], p->k2c[size_t(i - 1)]);
         }
         if (p->sur.on) {
@@ -525,7 +530,7 @@ void plan_tables(rp_plan p) {
             grow_k2(p->k2b_dev, cb);
             for (int i = 1; i < p->kb; ++i) {
                 K2Tables cc;
-                main_k2(p, cc, keeps_history, kGroupMax, i - 1);
+                main_k2(p, cc, keeps_history, kAddGroup, i - 1);
                 grow_k2(p->k2c_dev[size_t(i - 1)], cc);
             }
         }
