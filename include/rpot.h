@@ -221,6 +221,11 @@ typedef struct {
                                  part (with the host tier: its staging snapshots)  */
     int64_t split_rings;      /* extra spectral rings of a split history           */
     int64_t n_classes;        /* shape classes (same grid and FFT pad)             */
+    int64_t fused_additions;  /* 1: with blocked lag-sum steps (RP_TUNE_LAGSUM_STEPS)
+                                 a step's own lags m < i, which only the self pairs
+                                 reach, are added by the inverse transform as it
+                                 reads the accumulated spectrum (no separate pass
+                                 over the accumulators); 0: a separate pass     */
 } rp_stats;
 
 rp_status rp_plan_stats(rp_plan plan, rp_stats *out);

@@ -45,7 +45,8 @@ class RpStats(ctypes.Structure):
                 ("lagsum_bytes", ctypes.c_double), ("ring_bytes", ctypes.c_double),
                 ("spectra_bytes", ctypes.c_double), ("fft_bytes_fwd", ctypes.c_double),
                 ("fft_bytes_inv", ctypes.c_double), ("history_bytes", ctypes.c_double),
-                ("split_rings", ctypes.c_int64), ("n_classes", ctypes.c_int64)]
+                ("split_rings", ctypes.c_int64), ("n_classes", ctypes.c_int64),
+                ("fused_additions", ctypes.c_int64)]
 
 
 _LIB = None

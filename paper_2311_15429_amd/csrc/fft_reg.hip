@@ -234,12 +234,81 @@ struct RegArgs {
     int in_bytes;          // extent of one job's input (buffer loads, bounds-checked)
 };
 
+// Lags m = 0 .. add_lags - 1 of a target's own sources, added to the
+// accumulated spectrum values of one x-line (frequencies k = yz P + x of
+// component c, x = t + T n) as the inverse x pass reads them: the terms the
+// separate additions of a blocked step would add (Eq. "retardation space-time
+// sampled lorentz four vector potential": lag m reads the sources of step
+// l - m).  Storage is tile-major, so a line of a length that does not divide
+// the tile may continue in the next tile (x >= xb).
+template <int P, int T, int AF>
+__device__ __forceinline__ void add_own_lags(const LineJob &job, int yz, int c, int t, Cf (&v)[P / T]) {
+    constexpr int E = P / T;
+    constexpr bool ONE_TILE = (kTile % P) == 0;
+    const uint32_t kk0 = uint32_t(yz) * uint32_t(P);
+    const int64_t tile0 = kk0 / kTile;
+    const int off0 = int(kk0 % kTile);
+    const int xb = kTile - off0;   // first x of the line in the next tile
+    const int64_t w = job.add_w, depth = job.add_depth;
+    const Cf *spec = reinterpret_cast<const Cf *>(job.add_spec);
+    int slot = *job.add_head;
+    for (int m = 0; m < job.add_lags; ++m) {
+        const Cf *g0 = spec + (tile0 * w + m) * kTile + off0 + t;
+        const Cf *g1 = spec + ((tile0 + 1) * w + m) * kTile + (off0 - kTile) + t;
+        const int64_t row0 = (tile0 * depth + slot) * (4 * kTile), row1 = ((tile0 + 1) * depth + slot) * (4 * kTile);
+        if constexpr (AF == RING_F32) {
+            // rows [c/2][k][c%2] of complex FP32 values
+            const Cf *ring = reinterpret_cast<const Cf *>(job.add_ring) + (c >> 1) * (2 * kTile) + (c & 1);
+            const Cf *r0 = ring + row0 + 2 * (off0 + t), *r1 = ring + row1 + 2 * (off0 - kTile + t);
+#pragma unroll
+            for (int n = 0; n < E; ++n) {
+                const bool hi = !ONE_TILE && t + T * n >= xb;
+                const Cf g = (hi ? g1 : g0)[T * n], r = (hi ? r1 : r0)[2 * T * n];
+                v[n] = Cf{v[n].x + g.x * r.x - g.y * r.y, v[n].y + g.x * r.y + g.y * r.x};
+            }
+        } else {
+            // rows [k][c] of 4-byte values: FP16 / BF16 pairs times the
+            // snapshot's scale, or 16-bit integers times the tile's scale
+            const uint32_t *ring = reinterpret_cast<const uint32_t *>(job.add_ring) + c;
+            const uint32_t *r0 = ring + row0 + 4 * (off0 + t), *r1 = ring + row1 + 4 * (off0 - kTile + t);
+            float s0, s1;
+            if constexpr (AF == RING_I16) {
+                s0 = job.add_scales[(tile0 * depth + slot) * 4 + c];
+                s1 = (!ONE_TILE && xb < P) ? job.add_scales[((tile0 + 1) * depth + slot) * 4 + c] : 0.f;
+            } else {
+                s0 = s1 = job.add_scales[int64_t(slot) * 4 + c];
+            }
+#pragma unroll
+            for (int n = 0; n < E; ++n) {
+                const bool hi = !ONE_TILE && t + T * n >= xb;
+                const Cf g = (hi ? g1 : g0)[T * n];
+                const uint32_t u = (hi ? r1 : r0)[4 * T * n];
+                const float s = hi ? s1 : s0;
+                Cf r;
+                if constexpr (AF == RING_F16) {
+                    __half2 h;
+                    __builtin_memcpy(&h, &u, 4);
+                    const float2 f = __half22float2(h);
+                    r = Cf{f.x * s, f.y * s};
+                } else if constexpr (AF == RING_BF16) {
+                    r = Cf{__uint_as_float(u << 16) * s, __uint_as_float(u & 0xffff0000u) * s};
+                } else {
+                    r = Cf{float(int(u << 16) >> 16) * s, float(int(u) >> 16) * s};
+                }
+                v[n] = Cf{v[n].x + g.x * r.x - g.y * r.y, v[n].y + g.x * r.y + g.y * r.x};
+            }
+        }
+        slot = slot == 0 ? int(depth) - 1 : slot - 1;
+    }
+}
+
 // One pass over a.lines lines of length P (T threads per line, L = 256 / T
 // lines per block).  FMT: output format (FP32 complex, or scaled FP16/BF16
 // ring rows).  DIR: sign of the exponent.  HALF: the pass's zero padding
 // (forward: n_in <= P / 2) or crop (inverse: n_out <= P / 2) is pruned from
-// the DFTs at compile time.
-template <int P, int T, int FMT, int DIR, bool HALF>
+// the DFTs at compile time.  AF != 0 (inverse x pass of a blocked lag-sum
+// step): the step's own-source lags are added to the input (add_own_lags).
+template <int P, int T, int FMT, int DIR, bool HALF, int AF = 0>
 __global__ __launch_bounds__(256) void k_line_reg(LinePass a, RegArgs ra) {
     constexpr int E = P / T;
     constexpr int L = 256 / T;
@@ -282,6 +351,9 @@ __global__ __launch_bounds__(256) void k_line_reg(LinePass a, RegArgs ra) {
         }
 #pragma unroll
         for (int n = NL; n < E; ++n) v[n] = Cf{0.f, 0.f};
+        if constexpr (AF != 0) {
+            if (line < a.lines && job.add_lags > 0) add_own_lags<P, T, AF>(job, line >> 2, line & 3, t, v);
+        }
         Cf X[E];
         if constexpr (HALF_IN) dft_half_in<E, DIR>(v, X);
         else dft<E, DIR>(v, X);
@@ -436,11 +508,26 @@ void launch_reg_dir(const LinePass &a, const RegArgs &ra, dim3 grid, hipStream_t
     else hipLaunchKernelGGL((k_line_reg<P, T, FMT, -1, HALF>), grid, dim3(256), 0, st, a, ra);
 }
 
+template <int P, int T, int AF>
+void launch_reg_add(const LinePass &a, const RegArgs &ra, dim3 grid, hipStream_t st) {
+    if (2 * a.n_out <= P) hipLaunchKernelGGL((k_line_reg<P, T, RING_F32, +1, true, AF>), grid, dim3(256), 0, st, a, ra);
+    else hipLaunchKernelGGL((k_line_reg<P, T, RING_F32, +1, false, AF>), grid, dim3(256), 0, st, a, ra);
+}
+
 template <int P, int T>
 void launch_reg_fmt(const LinePass &a, const RegArgs &ra, hipStream_t st) {
     constexpr int L = 256 / T;
     const dim3 grid((a.lines + L - 1) / L, a.n_jobs);
     const bool half = a.dir < 0 ? 2 * a.n_in <= P : 2 * a.n_out <= P;
+    if (a.add_fmt != 0) {
+        switch (a.add_fmt) {
+        case RING_F16: launch_reg_add<P, T, RING_F16>(a, ra, grid, st); break;
+        case RING_BF16: launch_reg_add<P, T, RING_BF16>(a, ra, grid, st); break;
+        case RING_I16: launch_reg_add<P, T, RING_I16>(a, ra, grid, st); break;
+        default: launch_reg_add<P, T, RING_F32>(a, ra, grid, st);
+        }
+        return;
+    }
     switch (a.out_fmt) {
     case RING_F16:
         if (half) launch_reg_dir<P, T, RING_F16, true>(a, ra, grid, st);
@@ -483,6 +570,12 @@ bool line_reg_supported(const LinePass &a) {
     // pass of a spectrum, lines (x-line, component), frequencies x fastest
     if (a.out_fmt == RING_I16 &&
         !(a.n_inner == 4 && a.out_inner == 1 && a.out_outer == int64_t(a.P) * 4 && a.n_out == a.P && a.dir < 0))
+        return false;
+    // fused lag additions: the inverse x pass of a spectrum [C][4]
+    if (a.add_fmt != 0 &&
+        !(a.dir > 0 && a.out_fmt == RING_F32 && !tiled && a.n_inner == 4 && a.in_inner == 1 && a.in_j == 4 &&
+          a.in_outer == int64_t(a.P) * 4 && a.n_in == a.P &&
+          (a.add_fmt == RING_F32 || a.add_fmt == RING_F16 || a.add_fmt == RING_BF16 || a.add_fmt == RING_I16)))
         return false;
     for (int g : {a.in_group, a.out_group})
         if (g != 0 && g != 1 && g != 2 && g != 4) return false;

@@ -397,6 +397,7 @@ void rebuild_blocked(rp_plan p, hipStream_t st) {
         main_k2(p, p->k2c[size_t(i - 1)], plain_pair, kAddGroup, i - 1);
         upload_k2(p, p->k2c[size_t(i - 1)], p->k2c_dev[size_t(i - 1)], st);
     }
+    update_fused_additions(p);
 }
 
 // Ring depths, stored Green spectra and the lag-sum schedules.
@@ -535,6 +536,7 @@ void plan_tables(rp_plan p) {
             }
         }
     }
+    update_fused_additions(p);
     // room for the largest schedule a fallback can reach
     K2Tables cap;
     main_k2(p, cap, keeps_history);
@@ -789,6 +791,7 @@ void plan_stats(rp_plan p) {
     }
     st.split_rings = int64_t(p->vring.size());
     st.n_classes = int64_t(p->cls.size());
+    st.fused_additions = p->fuse_add ? 1 : 0;
     for (const SystemP &S : p->sys) st.spectra_bytes += double(S.spec_elems) * p->spec_csz;
     for (const DomainP &d : p->dom) {
         const SystemP &S = p->sys[d.sys];
@@ -897,6 +900,31 @@ LinePass inv_y(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl) {
     a.out_inner = 1;
     a.out_outer = int64_t(N[1]) * Hz * 4;
     return a;
+}
+
+// Whether a blocked step's additions (its lags m < phase) can be left to the
+// inverse x pass (add_own_lags): they must be the self pairs' alone, every
+// other plain pair starting at lag kb - 1 or later, and every class's inverse
+// x pass must be one the register kernel covers.
+static bool fused_additions_allowed(rp_plan p) {
+    if (p->kb <= 1 || p->p64 || !p->fft_reg) return false;
+    for (const SystemP &S : p->sys)
+        for (int s : S.doms)
+            for (int n : S.doms)
+                if (s != n && is_target(p, s) && plain_pair(p, s, n) && p->pr(s, n).m_lo <= p->kb - 2) return false;
+    for (const ClassP &K : p->cls) {
+        if (K.tdoms.empty()) continue;
+        LinePass x = inv_x(p, K.N, K.P, K.Hz, false);
+        x.add_fmt = p->ring_fmt;
+        x.n_jobs = 1;
+        if (!line_reg_supported(x)) return false;
+    }
+    return true;
+}
+
+void update_fused_additions(rp_plan p) {
+    p->fuse_add = fused_additions_allowed(p);
+    p->stats.fused_additions = p->fuse_add ? 1 : 0;
 }
 
 ZFwd zfwd_common(rp_plan p, int mode, const int N[3], const int P[3], int Hz, bool dbl) {
@@ -1423,7 +1451,8 @@ void enqueue_lagsum(rp_plan p, hipStream_t st, int unroll, int persist, int phas
             launch_lagsum_block(a, p->ring_fmt, p->kb, unroll, grid, st);
             check_launch();
         }
-    } else {
+    } else if (!p->fuse_add) {
+        // (with fused additions the inverse x pass adds these lags)
         const K2Tables &T = p->k2c[size_t(phase - 1)];
         K2Args a = k2_args(p, T, p->k2c_dev[size_t(phase - 1)], head);
         a.acc_set = phase;
@@ -1452,9 +1481,23 @@ void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st, int phase) {
             zi.tw = tw_ptr(p, K.P[2], p->p64);
             zi.rp = make_radix(K.P[2]);
             x.n_jobs = y.n_jobs = zi.n_jobs = cnt;
+            const bool fused = p->fuse_add && p->kb > 1 && phase > 0;
+            if (fused) x.add_fmt = p->ring_fmt;
             for (int j = 0; j < cnt; ++j) {
                 const int s = K.tdoms[j0 + j];
                 const DomainP &d = p->dom[s];
+                if (fused) {
+                    // the step's lags 0 .. phase - 1 of the target's own sources
+                    const PairP &q = p->pr(s, s);
+                    LineJob &J = x.jobs[j];
+                    J.add_ring = p->ws + d.off_ring;
+                    J.add_scales = d.off_scales ? p->at<float>(d.off_scales) : nullptr;
+                    J.add_head = p->at<int32_t>(p->off_head) + s;
+                    J.add_spec = p->ws + p->off_spec + size_t(p->sys[d.sys].spec_base + q.spec0) * p->spec_csz;
+                    J.add_depth = d.depth;
+                    J.add_w = q.m_hi - q.m_lo + 1;
+                    J.add_lags = std::min(phase, q.m_hi + 1);   // the self window is [0, m_hi]
+                }
                 x.jobs[j].in = p->ws + d.off_acc + size_t(phase) * size_t(K.C) * 4 * p->csz;
                 x.jobs[j].out = p->ws + d.off_t2;
                 y.jobs[j].in = p->ws + d.off_t2;
@@ -1982,6 +2025,7 @@ rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value) {
         case RP_TUNE_FFT_REG:
             if (value != 0 && value != 1) fail(RP_ERR_ARG, "register line passes must be 0 or 1");
             plan->fft_reg = value;
+            update_fused_additions(plan);
             break;
         case RP_TUNE_LAGSUM_CACHED:
             if (value != 0 && value != 1) fail(RP_ERR_ARG, "cached must be 0 or 1");

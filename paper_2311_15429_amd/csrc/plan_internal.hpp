@@ -260,6 +260,7 @@ struct rp_plan_s {
     // pass of a block's first step (one target per thread), k2c[i] adds the
     // lags m < i of the block's step i (i = 1 .. kb-1)
     int kb = 1;
+    bool fuse_add = false;   // blocked steps: own-source lags added by the inverse x pass (fused_additions)
     int k2b_cached = 0;      // blocked pass: cached loads (else non-temporal)
     int k2b_tile_major = 0;  // blocked pass: items of one frequency tile next to each other (else costliest first)
     rpot_host::K2Tables k2b;
@@ -318,6 +319,7 @@ void plan_stats(rp_plan p);
 void release_graph(rp_plan p);
 void upload_k2(rp_plan p, const K2Tables &T, const K2Dev &D, hipStream_t st);
 void rebuild_blocked(rp_plan p, hipStream_t st);   // blocked schedules for the current plain pairs
+void update_fused_additions(rp_plan p);            // whether the inverse x pass adds a step's own lags
 int lag_phase(rp_plan p, int64_t step);            // phase of a step within its block of blocked steps
 K2Args k2_args(rp_plan p, const K2Tables &T, const K2Dev &D, const int32_t *head);
 void enqueue_k2(rp_plan p, const K2Args &a, int tg, hipStream_t st, int unroll, int persist);

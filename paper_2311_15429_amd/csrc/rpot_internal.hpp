@@ -63,6 +63,15 @@ struct LineJob {
     const int32_t *head;   // ring output: current slot of the domain's ring, else null
     int64_t slot_stride;   // ring output: elements per slot
     int64_t tile_stride;   // tiled output: elements per frequency tile (0: linear output)
+    // Inverse x pass of a blocked lag-sum step (LinePass::add_fmt != 0): the
+    // step's lags m < add_lags of the target's own sources (its self pair) are
+    // added to the accumulated spectrum as it is read, instead of a separate
+    // read-modify-write of the accumulator.
+    const void *add_ring;      // the target's history ring (tile-major rows)
+    const float *add_scales;   // its scales (FP16/BF16 [depth][4], I16 [tile][depth][4])
+    const int32_t *add_head;   // its head (slot of the newest snapshot, lag 0)
+    const void *add_spec;      // Green spectra of the self pair: row tile * add_w + m, kTile complex each
+    int32_t add_depth, add_w, add_lags;
 };
 
 struct LinePass {
@@ -72,6 +81,7 @@ struct LinePass {
     int lds_elems;         // complex elements staged per block: 0 (default 4096), 2048, 4096 or 6144
                            // (FP32; half of it in FP64)
     int reg;               // 1: register-resident pass where the length allows (FP32)
+    int add_fmt;           // ring format of the fused lag additions (0: none; see LineJob)
     FastDiv dL, dP, dinner, dnout;   // set by the launcher
     int64_t in_j, in_inner, in_outer;
     int64_t out_j, out_inner, out_outer;

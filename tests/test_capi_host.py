@@ -391,3 +391,27 @@ def test_waves_cover_every_target_once_within_the_budget():
         assert w.workspace <= budget and p.workspace_bytes <= w.workspace
         assert p.stats()["points"] == sum(s.domains[doms[t]].n_points for t in targets)
         p.close()
+
+
+def test_fused_additions_are_chosen_only_where_they_are_the_self_pairs():
+    """With blocked lag-sum steps the lags m < i of step i of a block are added
+    by the inverse x pass only when no cross pair reaches them and the
+    register line pass covers the transform; otherwise a separate pass."""
+    from paper_2311_15429_amd import plan_for_system
+    p = plan_for_system(sy.config2(0), "fp32")      # cross windows from lag 42 on
+    assert p.stats()["fused_additions"] == 0           # one step per pass
+    p.set_tuning("lagsum_steps", 8)
+    assert p.stats()["fused_additions"] == 1
+    p.set_tuning("fft_reg", 0)                         # LDS-staged passes: separate additions
+    assert p.stats()["fused_additions"] == 0
+    p.set_tuning("fft_reg", 1)
+    assert p.stats()["fused_additions"] == 1
+    near = plan_for_system(sy.config1(0), "fp32")     # cross windows from lag 8
+    near.set_tuning("lagsum_steps", 8)
+    assert near.stats()["fused_additions"] == 1
+    close = plan_for_system(sy.System(0.5, 0.02, sy.C_AU, [sy.Domain((8, 8, 8), np.zeros(3)),
+                                                          sy.Domain((8, 8, 8), np.array([6.0, 0, 0]))]), "fp32")
+    close.set_tuning("lagsum_steps", 8)                # cross window from lag 0: not the self pairs alone
+    assert close.info(0, 1)[0] <= 6 and close.stats()["fused_additions"] == 0
+    for q in (p, near, close):
+        q.close()

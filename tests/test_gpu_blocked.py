@@ -34,6 +34,56 @@ def test_blocked_steps_match_the_oracle_at_every_step(precision, kb, tol):
     log(f"{precision}, {kb} steps per pass, {L + 1} steps: vs oracle {worst:.2e}, vs unblocked {worst_d:.2e}")
 
 
+def _spread_system(seed=3):
+    """Three uneven domains far enough apart (cross-pair windows from lag 9 on)
+    that a blocked step's own lags m < 8 are the self pairs' alone, with x
+    pads of 48 and 96 (x-lines that cross the 256-frequency tiles)."""
+    rng = np.random.default_rng(seed)
+    h = 0.5
+    doms = [sy.Domain((20, 9, 20), np.array([0.0, 0.0, 0.0])),
+            sy.Domain((40, 8, 26), np.array([36.0, 3.0, -2.0])),
+            sy.Domain((12, 6, 14), np.array([-3.0, 34.0, 8.0]))]
+    for d in doms:
+        lo = d.origin
+        hi = d.origin + h * (np.array(d.dims) - 1)
+        for _ in range(2):
+            d.charges.append(sy.Charge("pair", rng.uniform(0.8, 1.5), rng.uniform(lo, hi), rng.uniform(lo, hi),
+                                       ("cos", rng.uniform(0.1, 1), rng.uniform(0.1, 0.5), rng.uniform(0, 6.28))))
+    return sy.System(h, 0.02, sy.C_AU, doms, name="three spread domains")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("fp32_ring_i16", 1e-4), ("fp32_ring_fp16", 2e-4),
+                                           ("fp32_ring_bf16", 2e-3)])
+def test_fused_additions_every_ring_format(precision, tol):
+    """8 steps per pass with the own-source lags of steps 2..8 of a block added
+    by the inverse x pass (no separate pass over the accumulators), for every
+    ring format: every step against the oracle and against one step per
+    pass."""
+    from paper_2311_15429_amd import plan_for_system
+    s = _spread_system()
+    p = plan_for_system(s, precision)
+    p.set_tuning("lagsum_steps", 8)
+    assert p.stats()["fused_additions"] == 1
+    assert min(p.info(a, b)[0] for a in range(3) for b in range(3) if a != b) >= 7
+    assert p.info(0, 0)[2][0] == 96
+    # self windows shorter than a block (lags 0..4): the additions stop at the window
+    assert min(p.info(a, a)[1] for a in range(3)) < 7
+    p.close()
+    L = 2 * 8 + 5
+    S = sy.sample_sources(s, range(L + 1))
+    got = run_gpu(s, precision, S, tune={"lagsum_steps": 8})
+    plain = run_gpu(s, precision, S)
+    ref = oracle.potential_full(s, S, range(L + 1))
+    worst, worst_d = 0.0, 0.0
+    for l in range(L + 1):
+        e = rel_err(got[l], ref[l])
+        d = rel_err(got[l], plain[l])
+        worst, worst_d = max(worst, float(e.max())), max(worst_d, float(d.max()))
+        assert np.all(e <= tol), (l, e)
+        assert np.all(d <= max(tol / 4, 2e-6)), (l, d)
+    log(f"{precision}, fused additions: vs oracle {worst:.2e}, vs one step per pass {worst_d:.2e}")
+
+
 def test_blocked_steps_graph_replays_interleaved_with_eager_steps():
     """Batched systems, persistent blocked pass, one graph per phase: replays
     and eager steps in an irregular order, each step against the oracle."""
