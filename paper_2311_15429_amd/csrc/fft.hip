@@ -728,6 +728,7 @@ static bool launch_zfwd_static(const ZFwd &a, dim3 grid, hipStream_t st) {
 }
 
 void launch_zfwd(const ZFwd &a0, int prec64, hipStream_t st) {
+    if (!prec64 && a0.reg && launch_zfwd_reg(a0, st)) return;
     ZFwd a = a0;
     a.dP = FastDiv(uint32_t(a.Pz));
     a.dHz = FastDiv(uint32_t(a.Hz));
@@ -856,6 +857,7 @@ static bool launch_zinv_static(const ZInv &a, dim3 grid, hipStream_t st) {
 }
 
 void launch_zinv(const ZInv &a0, int prec64, hipStream_t st) {
+    if (!prec64 && a0.reg && launch_zinv_reg(a0, st)) return;
     ZInv a = a0;
     const int L = zfwd_lines_per_block(a.Pz, prec64);
     a.dHz = FastDiv(uint32_t(a.Hz));

@@ -553,6 +553,247 @@ int64_t input_extent(const LinePass &a) {
     return ((n_outer - 1) * a.in_outer + int64_t(a.n_inner - 1) * a.in_inner + int64_t(a.n_in - 1) * a.in_j + 1) * 8;
 }
 
+// ---------------------------------------------------------------------------
+// z passes in registers.  A complex line c = pair * 4 + mu carries grid
+// positions a = 2 pair (real part) and b = a + 1 (imaginary part) of
+// component mu; the two real lines sit next to each other in memory, so a
+// line's Nz + Nz real values are one contiguous run.  Loads and stores move
+// those runs in 16-byte vectors (Nz a multiple of 4 T): vector j of thread t
+// holds z = 4 (t + T j) .. + 3, so each load instruction of a line's T threads
+// reads 16 T contiguous bytes.  The transform itself is the line passes'
+// two-stage split, with LDS rows between the contiguous and the strided
+// orders and for the real-to-complex unpack, which pairs k with P - k.
+
+// Forward: dS = S - S0 (and a copy of S into a real-space ring), R2C along z,
+// output [Nx][Ny][Hz][4].
+template <int P, int T>
+__global__ __launch_bounds__(256) void k_zfwd_reg(ZFwd a) {
+    constexpr int E = P / T, L = 256 / T, RS = P + 1, HZ = P / 2 + 1;
+    __shared__ Cf buf[L * RS];
+    __shared__ Cf twl[P];
+    const ZFwdJob &job = a.jobs[blockIdx.y];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < P; i += 256) twl[i] = reinterpret_cast<const Cf *>(a.tw)[i];
+    const int line0 = blockIdx.x * L;
+    const int npos = a.Nx * a.Ny, Nz = a.Nz;
+    const int nlines = 4 * ((npos + 1) / 2);
+    const int64_t npts = int64_t(npos) * Nz;
+    // contiguous loads: vector j of thread t of line li covers z = 4 (t + T j) .. + 3
+    {
+        const int t = tid & (T - 1), li = tid / T, c = line0 + li;
+        Cf *row = buf + li * RS;
+        if (c < nlines) {
+            const int mu = c & 3, pa = (c >> 2) * 2;
+            const bool hb = pa + 1 < npos;
+            const float *S = reinterpret_cast<const float *>(job.src);
+            if (job.src_head) {
+                int h = (*job.src_head - job.src_lag) % job.src_depth;
+                if (h < 0) h += job.src_depth;
+                S += int64_t(h) * 4 * npts;
+            }
+            const float *S0 = reinterpret_cast<const float *>(job.s0);
+            float *St = nullptr;
+            if (job.store)
+                St = reinterpret_cast<float *>(job.store) + (job.store_head ? int64_t(*job.store_head) * 4 * npts : 0);
+            const int64_t oa = mu * npts + int64_t(pa) * Nz;
+            for (int q = 4 * t; q < Nz; q += 4 * T) {
+                const float4 sa = *reinterpret_cast<const float4 *>(S + oa + q);
+                const float4 sb = hb ? *reinterpret_cast<const float4 *>(S + oa + Nz + q) : float4{0.f, 0.f, 0.f, 0.f};
+                float4 qa = {0.f, 0.f, 0.f, 0.f}, qb = {0.f, 0.f, 0.f, 0.f};
+                if (S0) {
+                    qa = *reinterpret_cast<const float4 *>(S0 + oa + q);
+                    if (hb) qb = *reinterpret_cast<const float4 *>(S0 + oa + Nz + q);
+                }
+                if (St) {
+                    *reinterpret_cast<float4 *>(St + oa + q) = sa;
+                    if (hb) *reinterpret_cast<float4 *>(St + oa + Nz + q) = sb;
+                }
+                const int z = q;
+                row[z + 0] = Cf{sa.x - qa.x, sb.x - qb.x};
+                row[z + 1] = Cf{sa.y - qa.y, sb.y - qb.y};
+                row[z + 2] = Cf{sa.z - qa.z, sb.z - qb.z};
+                row[z + 3] = Cf{sa.w - qa.w, sb.w - qb.w};
+            }
+        } else {
+            for (int z = t; z < Nz; z += T) row[z] = Cf{0.f, 0.f};
+        }
+        // zero padding up to P / 2 (the strided read takes n < E / 2)
+        for (int z = Nz + t; z < P / 2; z += T) row[z] = Cf{0.f, 0.f};
+    }
+    __syncthreads();
+    const int t = tid & (T - 1), li = tid / T;
+    Cf *row = buf + li * RS;
+    {
+        Cf v[E], X[E];
+#pragma unroll
+        for (int n = 0; n < E / 2; ++n) v[n] = row[t + T * n];
+#pragma unroll
+        for (int n = E / 2; n < E; ++n) v[n] = Cf{0.f, 0.f};
+        dft_half_in<E, -1>(v, X);
+        __syncthreads();
+        row[t] = X[0];
+#pragma unroll
+        for (int k1 = 1; k1 < E; ++k1) {
+            const Cf w = twl[t * k1];
+            row[k1 * T + t] = Cf{X[k1].x * w.x - X[k1].y * w.y, X[k1].x * w.y + X[k1].y * w.x};
+        }
+    }
+    __syncthreads();
+    {
+        Cf Zs[E / T][T];
+#pragma unroll
+        for (int i = 0; i < E / T; ++i) {
+            const int k1 = t + T * i;
+            Cf z[T];
+#pragma unroll
+            for (int s = 0; s < T; ++s) z[s] = row[k1 * T + s];
+            dft<T, -1>(z, Zs[i]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < E / T; ++i)
+#pragma unroll
+            for (int k2 = 0; k2 < T; ++k2) row[t + T * i + E * k2] = Zs[i][k2];
+    }
+    __syncthreads();
+    // unpack: X_a(k) = (Z_k + conj Z_-k) / 2, X_b(k) = (Z_k - conj Z_-k) / (2i)
+    Cf *__restrict__ out = reinterpret_cast<Cf *>(job.out);
+    const int nl = min(L, nlines - line0);
+    const int pos0 = (line0 >> 2) * 2;
+    const int np = min(2 * ((nl + 3) >> 2), npos - pos0);
+    for (int e = tid; e < np * HZ * 4; e += 256) {
+        const int mu = e & 3;
+        const int pl = (e >> 2) / HZ;
+        const int k = (e >> 2) - pl * HZ;
+        const int lq = (pl >> 1) * 4 + mu;
+        const Cf zk = buf[lq * RS + k];
+        const Cf zm = buf[lq * RS + (k == 0 ? 0 : P - k)];
+        Cf r;
+        if ((pl & 1) == 0) r = {0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
+        else r = {0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)};
+        out[(int64_t(pos0 + pl) * HZ + k) * 4 + mu] = r;
+    }
+}
+
+// Inverse: C2R along z of [Nx][Ny][Hz][4], crop to z < Nz, + add, output
+// out[mu][x][y][z].
+template <int P, int T>
+__global__ __launch_bounds__(256) void k_zinv_reg(ZInv a) {
+    constexpr int E = P / T, L = 256 / T, RS = P + 1, HZ = P / 2 + 1;
+    __shared__ Cf buf[L * RS];
+    __shared__ Cf twl[P];
+    const ZInvJob &job = a.jobs[blockIdx.y];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < P; i += 256) twl[i] = reinterpret_cast<const Cf *>(a.tw)[i];
+    const int line0 = blockIdx.x * L;
+    const int npos = a.Nx * a.Ny, Nz = a.Nz;
+    const int nlines = 4 * ((npos + 1) / 2);
+    const int64_t npts = int64_t(npos) * Nz;
+    const int nl = min(L, nlines - line0);
+    const int pos0 = (line0 >> 2) * 2;
+    const Cf *__restrict__ in = reinterpret_cast<const Cf *>(job.in);
+    // Z_k = X_a(k) + i X_b(k), Z_{P-k} = conj X_a(k) + i conj X_b(k); lines
+    // past the last read zeros
+    for (int e = tid; e < (L / 4) * HZ * 4; e += 256) {
+        const int mu = e & 3;
+        const int ppl = (e >> 2) / HZ;
+        const int k = (e >> 2) - ppl * HZ;
+        const int li = ppl * 4 + mu;
+        const int pa = pos0 + 2 * ppl;
+        Cf xa = {0.f, 0.f}, xb = {0.f, 0.f};
+        if (li < nl) {
+            xa = in[(int64_t(pa) * HZ + k) * 4 + mu];
+            if (pa + 1 < npos) xb = in[(int64_t(pa + 1) * HZ + k) * 4 + mu];
+        }
+        if (k == 0 || 2 * k == P) {
+            buf[li * RS + k] = Cf{xa.x, xb.x};
+        } else {
+            buf[li * RS + k] = Cf{xa.x - xb.y, xa.y + xb.x};
+            buf[li * RS + (P - k)] = Cf{xa.x + xb.y, xb.x - xa.y};
+        }
+    }
+    __syncthreads();
+    const int t = tid & (T - 1), li = tid / T;
+    Cf *row = buf + li * RS;
+    {
+        Cf v[E], X[E];
+#pragma unroll
+        for (int n = 0; n < E; ++n) v[n] = row[t + T * n];
+        dft<E, +1>(v, X);
+        __syncthreads();
+        row[t] = X[0];
+#pragma unroll
+        for (int k1 = 1; k1 < E; ++k1) {
+            const Cf w = twl[t * k1];
+            row[k1 * T + t] = Cf{X[k1].x * w.x + X[k1].y * w.y, X[k1].y * w.x - X[k1].x * w.y};
+        }
+    }
+    __syncthreads();
+    {
+        Cf Zs[E / T][T];
+#pragma unroll
+        for (int i = 0; i < E / T; ++i) {
+            const int k1 = t + T * i;
+            Cf z[T];
+#pragma unroll
+            for (int s = 0; s < T; ++s) z[s] = row[k1 * T + s];
+            dft_half_out<T, +1>(z, Zs[i]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < E / T; ++i)
+#pragma unroll
+            for (int k2 = 0; k2 < T / 2; ++k2) row[t + T * i + E * k2] = Zs[i][k2];
+    }
+    __syncthreads();
+    // contiguous stores: vector j of thread t covers z = 4 (t + T j) .. + 3 of both positions
+    const int c = line0 + li;
+    if (c >= nlines) return;
+    const int mu = c & 3, pa = (c >> 2) * 2;
+    const bool hb = pa + 1 < npos;
+    float *__restrict__ out = reinterpret_cast<float *>(job.out);
+    const float *__restrict__ add = reinterpret_cast<const float *>(job.add);
+    const int64_t oa = mu * npts + int64_t(pa) * Nz;
+    for (int q = 4 * t; q < Nz; q += 4 * T) {
+        const int z = q;
+        const Cf v0 = row[z], v1 = row[z + 1], v2 = row[z + 2], v3 = row[z + 3];
+        float4 ra = {v0.x, v1.x, v2.x, v3.x}, rb = {v0.y, v1.y, v2.y, v3.y};
+        if (add) {
+            const float4 da = *reinterpret_cast<const float4 *>(add + oa + q);
+            ra = float4{ra.x + da.x, ra.y + da.y, ra.z + da.z, ra.w + da.w};
+            if (hb) {
+                const float4 db = *reinterpret_cast<const float4 *>(add + oa + Nz + q);
+                rb = float4{rb.x + db.x, rb.y + db.y, rb.z + db.z, rb.w + db.w};
+            }
+        }
+        *reinterpret_cast<float4 *>(out + oa + q) = ra;
+        if (hb) *reinterpret_cast<float4 *>(out + oa + Nz + q) = rb;
+    }
+}
+
+template <int P, int T>
+void launch_zfwd_reg_p(const ZFwd &a, hipStream_t st) {
+    const int nlines = 4 * ((a.Nx * a.Ny + 1) / 2);
+    hipLaunchKernelGGL((k_zfwd_reg<P, T>), dim3((nlines + 256 / T - 1) / (256 / T), a.n_jobs), dim3(256), 0, st, a);
+}
+template <int P, int T>
+void launch_zinv_reg_p(const ZInv &a, hipStream_t st) {
+    const int nlines = 4 * ((a.Nx * a.Ny + 1) / 2);
+    hipLaunchKernelGGL((k_zinv_reg<P, T>), dim3((nlines + 256 / T - 1) / (256 / T), a.n_jobs), dim3(256), 0, st, a);
+}
+
+// T threads per z line of length P (the line passes' split).  Lengths 48
+// and 96 (E = 12, 24 points per thread) measured no faster than the staged
+// pass (config 5: 80 / 74 us against 83 / 75 us per step), so they keep it.
+int z_threads(int P) {
+    switch (P) {
+    case 32: return 4;
+    case 64: case 128: return 8;
+    case 256: return 16;
+    default: return 0;
+    }
+}
+
 }  // namespace
 
 bool line_reg_supported(const LinePass &a) {
@@ -586,6 +827,43 @@ bool line_reg_supported(const LinePass &a) {
     case 32: case 48: case 64: case 96: case 128: case 256: return true;
     default: return false;
     }
+}
+
+// FP32 z passes in registers: lengths 32, 64, 128, 256, the real data at most half the
+// padded line (Nz <= P / 2), Nz a multiple of 4 T (16-byte vectors), 16-byte
+// aligned arrays, sources only (mode 0) and no per-block maxima (FP16/BF16
+// rings keep the staged pass).  False (nothing launched) otherwise.
+bool launch_zfwd_reg(const ZFwd &a, hipStream_t st) {
+    const int T = z_threads(a.Pz);
+    if (a.mode != 0 || T == 0 || 2 * a.Nz > a.Pz || a.Nz % (4 * T) != 0) return false;
+    for (int j = 0; j < a.n_jobs; ++j) {
+        const ZFwdJob &J = a.jobs[j];
+        if (J.zmax) return false;
+        for (const void *q : {J.src, J.s0, static_cast<const void *>(J.store)})
+            if (reinterpret_cast<uintptr_t>(q) % 16) return false;
+    }
+    switch (a.Pz) {
+    case 32: launch_zfwd_reg_p<32, 4>(a, st); break;
+    case 64: launch_zfwd_reg_p<64, 8>(a, st); break;
+    case 128: launch_zfwd_reg_p<128, 8>(a, st); break;
+    default: launch_zfwd_reg_p<256, 16>(a, st); break;
+    }
+    return true;
+}
+
+bool launch_zinv_reg(const ZInv &a, hipStream_t st) {
+    const int T = z_threads(a.Pz);
+    if (T == 0 || 2 * a.Nz > a.Pz || a.Nz % (4 * T) != 0) return false;
+    for (int j = 0; j < a.n_jobs; ++j)
+        for (const void *q : {static_cast<const void *>(a.jobs[j].out), a.jobs[j].add})
+            if (reinterpret_cast<uintptr_t>(q) % 16) return false;
+    switch (a.Pz) {
+    case 32: launch_zinv_reg_p<32, 4>(a, st); break;
+    case 64: launch_zinv_reg_p<64, 8>(a, st); break;
+    case 128: launch_zinv_reg_p<128, 8>(a, st); break;
+    default: launch_zinv_reg_p<256, 16>(a, st); break;
+    }
+    return true;
 }
 
 // FP32 line pass in registers; false (nothing launched) when the pass is not

@@ -815,7 +815,10 @@ void check_launch() {
     if (e != hipSuccess) fail(RP_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
 }
 
-const void *tw_ptr(rp_plan p, int P, bool dbl) { return p->ws + (dbl ? p->tw64.at(P) : p->tw32.at(P)); }
+// (null before the bind: pass descriptors are also built to plan, unlaunched)
+const void *tw_ptr(rp_plan p, int P, bool dbl) {
+    return p->ws ? p->ws + (dbl ? p->tw64.at(P) : p->tw32.at(P)) : nullptr;
+}
 
 LinePass line_pass(rp_plan p, int P, bool dbl, int dir) {
     LinePass a{};
@@ -930,6 +933,7 @@ void update_fused_additions(rp_plan p) {
 ZFwd zfwd_common(rp_plan p, int mode, const int N[3], const int P[3], int Hz, bool dbl) {
     ZFwd a{};
     a.mode = mode;
+    a.reg = p->fft_reg;
     a.Nx = N[0];
     a.Ny = N[1];
     a.Nz = N[2];
@@ -1473,6 +1477,7 @@ void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st, int phase) {
             LinePass y = inv_y(p, K.N, K.P, K.Hz, p->p64);
             x.lds_elems = y.lds_elems = cls_lds(p, K);
             ZInv zi{};
+            zi.reg = p->fft_reg;
             zi.Nx = K.N[0];
             zi.Ny = K.N[1];
             zi.Nz = K.N[2];

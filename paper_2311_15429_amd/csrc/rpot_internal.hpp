@@ -127,6 +127,7 @@ struct ZFwdJob {
 
 struct ZFwd {
     int mode;
+    int reg;               // 1: the register-resident pass where it applies (FP32 sources)
     int Nx, Ny, Nz;        // mode 0 dims (common to every job of a launch)
     int Px, Py, Pz, Hz;
     FastDiv dP, dHz, dPy2; // set by the launcher
@@ -147,6 +148,7 @@ struct ZInvJob {
 };
 
 struct ZInv {
+    int reg;               // 1: the register-resident pass where it applies (FP32)
     int Nx, Ny, Nz;
     int Pz, Hz;
     FastDiv dHz, dNz, dnp; // set by the launcher (dnp: position pairs per block)
@@ -243,6 +245,10 @@ bool launch_line_reg(const LinePass &a, hipStream_t st);
 // whether launch_line_reg covers the pass (an x pass into a 16-bit integer
 // ring then quantises in the same launch)
 bool line_reg_supported(const LinePass &a);
+// register-resident FP32 z passes (fft_reg.hip); false when they do not cover
+// the launch (nothing launched)
+bool launch_zfwd_reg(const ZFwd &a, hipStream_t st);
+bool launch_zinv_reg(const ZInv &a, hipStream_t st);
 void launch_zfwd(const ZFwd &a, int prec64, hipStream_t st);
 void launch_zinv(const ZInv &a, int prec64, hipStream_t st);
 int zfwd_lines_per_block(int Pz, int prec64);

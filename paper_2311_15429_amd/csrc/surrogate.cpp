@@ -219,6 +219,7 @@ void judge_fields(rp_plan p, hipStream_t st, Fn &&fn) {
             LinePass x = inv_x(p, K.N, K.P, K.Hz, false);
             LinePass y = inv_y(p, K.N, K.P, K.Hz, false);
             ZInv zi{};
+            zi.reg = p->fft_reg;
             zi.Nx = K.N[0];
             zi.Ny = K.N[1];
             zi.Nz = K.N[2];

@@ -190,6 +190,37 @@ def test_largest_fft_length(precision, tol):
     _check(s, precision, 8, tol, steps=[4, 8])
 
 
+@pytest.mark.parametrize("dims_a,dims_b,pz", [((4, 4, 32), (4, 4, 24), 64), ((8, 8, 16), (8, 8, 16), 32),
+                                              ((4, 4, 64), (4, 4, 64), 128), ((2, 2, 128), (2, 2, 128), 256)])
+def test_register_z_passes(dims_a, dims_b, pz):
+    """z passes of lengths 32, 64, 128, 256 in registers (contiguous 16-byte
+    loads and stores of both real lines of a complex line; sub-domains whose
+    z extent is at most half the pad and a multiple of 4 T), beside a class
+    that keeps the staged pass: against the oracle, and against the LDS-staged
+    passes to FP32 rounding."""
+    from paper_2311_15429_amd import plan_for_system
+    h = 0.5
+    rng = np.random.default_rng(pz)
+    doms = [sy.Domain(dims_a, np.zeros(3)), sy.Domain(dims_b, np.array([h * dims_a[0] + 5.0, 1.0, -2.0]))]
+    for d in doms:
+        sy._random_pairs(rng, d, h, 2)
+    s = sy.System(h, 0.02, sy.C_AU, doms, name=f"z pad {pz}")
+    p = plan_for_system(s, "fp32")
+    assert p.info(0, 0)[2][2] == pz
+    p.close()
+    L = 8
+    S = _samples(s, L)
+    reg = run_gpu(s, "fp32", S, tune={"fft_reg": 1})
+    staged = run_gpu(s, "fp32", S, tune={"fft_reg": 0})
+    ref = oracle.potential_full(s, S, [L])[0]
+    e = rel_err(reg[L], ref)
+    log(f"z pad {pz}: register z passes vs oracle {np.array2string(e, precision=2)}")
+    assert np.all(e <= FP32_TOL), e
+    for l in range(L + 1):
+        d = rel_err(reg[l], staged[l]) if np.any(staged[l][0]) else np.zeros(4)
+        assert np.all(d <= 2e-6), (l, d)
+
+
 @pytest.mark.parametrize("dims,pads", [((16, 24, 32), (32, 48, 64)), ((48, 54, 8), (96, 108, 16)),
                                        ((64, 4, 128), (128, 8, 256)), ((32, 128, 8), (64, 256, 16))])
 def test_i16_ring_quantised_by_the_x_pass(dims, pads):
