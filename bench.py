@@ -310,8 +310,11 @@ def bench_batched(args):
     log(f"config 4: {len(set(system.system_id))} systems, {len(system.domains)} domains, {pts_total} target points; "
         f"{len(units)} units in {len(waves)} waves of <= {budget / 1e9:.0f} GB (device free {free / 1e9:.0f} of "
         f"{total / 1e9:.0f} GB); lag-sum bytes per step {lag_total / 1e12:.2f} TB; host planning {t_plan:.1f} s")
-    # E eager steps per wave hold exactly one pass of the lag sum (one block start)
-    W, K, E = args.warmup, args.steps, kb
+    # per wave: W warm-up and K timed graph replays (the timed steps' sources
+    # sit in device memory beside the wave's workspace, so K stays small: one
+    # block of kb steps by default), then E eager steps holding exactly one
+    # pass of the lag sum (one block start)
+    W, K, E = args.wave_warmup, args.wave_steps, kb
     r = run_waves(system, precision, waves, W, K, E, args.split_gap, lagsum_steps=kb)
     t_timed, t_setup, updates, phases = r["t_timed"], r["t_setup"], r["updates"], r["phases"]
     lag_bytes, lag_s, n_launch, ws_total, wall0 = r["lag_bytes"], r["lag_s"], r["n_launch"], r["ws_total"], r["wall0"]
@@ -1095,6 +1098,9 @@ def main():
                     help="surrogate workload: re-admission factor of fallen-back pairs (0: never)")
     ap.add_argument("--oracle-targets", type=int, default=3)
     ap.add_argument("--oracle-points", type=int, default=24)
+    ap.add_argument("--wave-steps", type=int, default=8,
+                    help="batched: timed graph replays per wave (default one block of 8 lag-sum steps)")
+    ap.add_argument("--wave-warmup", type=int, default=1, help="batched: warm-up replays per wave")
     ap.add_argument("--wave-gb", type=float, default=0.0,
                     help="batched workload: cap of a wave's workspace in GB (default: the free device memory)")
     ap.add_argument("--no-plain-baseline", dest="plain_baseline", action="store_false",
