@@ -40,9 +40,11 @@ def _pulse(t, T_env=0.8, w=4.0):
     return 5.0 * math.sin(math.pi * t / T_env) ** 2 * math.sin(w * t) if t < T_env else 0.0
 
 
-def _gpu_loop(system, bases, params, L, precision):
+def _gpu_loop(system, bases, params, L, precision, steps=1):
     from paper_2311_15429_amd import Oscillators, plan_for_system
     plan = plan_for_system(system, precision, stream=torch.cuda.current_stream())
+    if steps > 1:
+        plan.set_tuning("lagsum_steps", steps)
     plan.bind()
     plan.set_green_kernels()
     dt_ = plan.dtype
@@ -67,13 +69,15 @@ def _gpu_loop(system, bases, params, L, precision):
     return res
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 2e-4)])
-def test_coupled_loop_matches_the_oracle(precision, tol):
+@pytest.mark.parametrize("precision,tol,steps", [("fp64", 1e-9, 1), ("fp32", 2e-4, 1), ("fp32", 2e-4, 8)])
+def test_coupled_loop_matches_the_oracle(precision, tol, steps):
+    """The sources of step l + 1 come from the potentials of step l; with 8
+    lag-sum steps per pass every step still returns its own potential."""
     system, params = _osc_system(1)
     bases = [sy.pair_shapes(d, system.h, system.c) for d in system.domains]
     L = 60
     rec = cr.run_loop(system, bases, params, _pulse, L)
-    q, qd, _ = _gpu_loop(system, bases, params, L, precision)
+    q, qd, _ = _gpu_loop(system, bases, params, L, precision, steps)
     want_q = np.concatenate(rec["q"], axis=1)
     want_qd = np.concatenate(rec["qdot"], axis=1)
     # domain 1 is driven only through the potentials (each oscillator is
@@ -81,7 +85,8 @@ def test_coupled_loop_matches_the_oracle(precision, tol):
     assert np.max(np.abs(want_q[:, 2:])) > 1e-3 * np.max(np.abs(want_q[:, :2]))
     for got, want, name in ((q, want_q, "q"), (qd, want_qd, "qdot")):
         e = np.max(np.abs(got - want), axis=0) / np.max(np.abs(want), axis=0)
-        log(f"{precision} coupled loop, {L} steps: {name} rel err per oscillator {np.array2string(e, precision=2)}")
+        log(f"{precision} coupled loop, {L} steps, {steps} per pass: {name} rel err per oscillator "
+            f"{np.array2string(e, precision=2)}")
         assert np.all(e <= tol), (name, e)
 
 
