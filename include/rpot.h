@@ -272,8 +272,7 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
  *                              compute step l + 1's sources from step l's
  *                              output); only the order of the sums changes.
  *                              The history is read about 1/kb as often.  FP32
- *                              plans only (RP_ERR_UNSUPPORTED for RP_FP64, with
- *                              a split history or with the far-pair surrogate);
+ *                              plans only (RP_ERR_UNSUPPORTED for RP_FP64);
  *                              set before rp_bind_workspace (RP_ERR_STATE
  *                              after): it re-plans the workspace (kb
  *                              accumulators per target).  rp_capture_step then
@@ -294,10 +293,19 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
  *                              line split over T threads, one LDS exchange);
  *                              0: every line pass stages whole lines in LDS
  *                              (RP_TUNE_FFT_LDS).  FP64 passes always stage.
+ *   RP_TUNE_FFT_PLANE          1 (default): with RP_TUNE_FFT_REG, the FP32
+ *                              forward z and y passes (and the inverse y and z
+ *                              passes) of pads 32, 48, 64, 96 and 128 run as
+ *                              one launch per x slice and component, the z
+ *                              transform kept in LDS between them, where the
+ *                              grid is at most half the pad in y and z and Nz
+ *                              is a multiple of 4 (scaled FP16/BF16 rings keep
+ *                              the separate forward passes); 0: separate passes.
  * Setting a knob discards a captured step (rp_capture_step).
  */
 enum { RP_TUNE_LAGSUM_UNROLL = 1, RP_TUNE_LAGSUM_PERSISTENT = 2, RP_TUNE_FFT_LDS = 4, RP_TUNE_LAGSUM_STEPS = 8,
-       RP_TUNE_LAGSUM_CACHED = 16, RP_TUNE_LAGSUM_TILE_MAJOR = 32, RP_TUNE_FFT_REG = 64 };
+       RP_TUNE_LAGSUM_CACHED = 16, RP_TUNE_LAGSUM_TILE_MAJOR = 32, RP_TUNE_FFT_REG = 64,
+       RP_TUNE_FFT_PLANE = 128 };
 rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value);
 /*
  * Shape classes: sub-domains with the same grid and FFT pad share their

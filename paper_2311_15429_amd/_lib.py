@@ -29,7 +29,7 @@ EXPORTS = ["rp_plan_domains", "rp_plan_targets", "rp_workspace_bytes", "rp_bind_
            "rp_surrogate_teacher", "rp_surrogate_data_scales", "rp_surrogate_scale_data", "rp_mlp_relative_rms",
            "rp_surrogate_sample", "rp_surrogate_sample_fields", "rp_surrogate_judge_stats"]
 TUNE = {"lagsum_unroll": 1, "lagsum_persistent": 2, "fft_lds": 4, "lagsum_steps": 8, "lagsum_cached": 16,
-        "lagsum_tile_major": 32, "fft_reg": 64}
+        "lagsum_tile_major": 32, "fft_reg": 64, "fft_plane": 128}
 
 
 class RpotError(RuntimeError):

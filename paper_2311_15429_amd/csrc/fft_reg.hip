@@ -794,6 +794,418 @@ int z_threads(int P) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Plane passes: the z and y transforms of one x slice and one component in one
+// block, so the z-transformed array between them never goes to HBM.  Forward:
+// the Ny x Nz real sources dS = S - S0 of slice (x, mu) in, the P x Hz values
+// of the y pass out ([Nx][P][Hz][4]).  Inverse: those values in, the cropped
+// real potentials out.  Two neighbouring y rows form one complex z line (real
+// and imaginary part; unpacked by pairing k with P - k).  Both transforms are
+// the line passes' two-stage split.  One LDS buffer of Hz rows of P + 1 values
+// holds, in turn, the z lines (one row per pair of y rows), the y lines (one
+// row per z frequency, entries along y) and their exchanges.  The four
+// components of a slice are consecutive tiles of one XCD, so the 8-byte
+// accesses to the interleaved [..][4] array of the four blocks meet in its L2.
+struct PlaneJob {
+    const float *src;          // forward: S [4][Nx][Ny][Nz]; with src_head a ring of such arrays
+    const float *s0;           // forward: S0 (or null)
+    const int32_t *src_head;   // forward: read slot (*src_head - src_lag) mod src_depth
+    float *store;              // forward: copy of S into slot *store_head of this ring (or null)
+    const int32_t *store_head;
+    int32_t src_depth, src_lag;
+    Cf *yout;                  // forward: [Nx][P][Hz][4]
+    const Cf *yin;             // inverse: [Nx][P][Hz][4]
+    float *out;                // inverse: [4][Nx][Ny][Nz]
+    const float *add;          // inverse: added to the output (same layout), or null
+};
+
+struct PlanePass {
+    int Nx, Ny, Nz;
+    const void *tw;            // exp(-2 pi i j / P), j < P
+    int n_jobs;
+    PlaneJob jobs[kMaxJobs];
+};
+static_assert(sizeof(PlanePass) <= 4096, "plane-pass kernel arguments above 4 KiB");
+
+// Thread roles: the lanes of a wave take consecutive lines with one t (line
+// fastest), so that with the odd row stride a wave's 8-byte LDS accesses fall
+// in distinct banks in both stages of a transform (the t-fastest order puts
+// lines 1 and t 1 on the same bank).  z lines: groups of 32 (at most P / 4 are
+// used); y lines: groups of 256 / T, as many rounds as Hz needs.
+template <int P, int T>
+__global__ __launch_bounds__(256) void k_zy_fwd(PlanePass a) {
+    constexpr int NT = 256, E = P / T, RS = P + 1, HZ = P / 2 + 1, LPI = NT / T, H = P / 2, ZL = 32;
+    constexpr int NV = ((P / 4) * (H / 4) + NT - 1) / NT;   // (row pair, z quad) items per thread
+    constexpr int NU = ((P / 4) * HZ + NT - 1) / NT;        // unpacked (row pair, kz) per thread
+    static_assert(P / 4 <= ZL && ZL * T <= NT, "the z rows of a slice exceed one round of threads");
+    __shared__ Cf buf[HZ * RS];
+    __shared__ Cf twl[P];
+    const PlaneJob &job = a.jobs[blockIdx.y];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < P; i += NT) twl[i] = reinterpret_cast<const Cf *>(a.tw)[i];
+    const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
+    const int x = tile >> 2, mu = tile & 3;
+    const int Nx = a.Nx, Ny = a.Ny, Nz = a.Nz, NZL = (Ny + 1) / 2;
+    const int64_t npts = int64_t(Nx) * Ny * Nz;
+    const int64_t slab = (int64_t(mu) * Nx + x) * Ny * Nz;
+    // dS = S - S0 of rows y = 2p (real parts) and 2p + 1 (imaginary parts)
+    // into z row p, four z at a time (16-byte vectors, Nz % 4 == 0); a missing
+    // odd last row reads as zeros
+    {
+        const float *S = job.src;
+        if (job.src_head) {
+            int h = (*job.src_head - job.src_lag) % job.src_depth;
+            if (h < 0) h += job.src_depth;
+            S += int64_t(h) * 4 * npts;
+        }
+        float *St = job.store ? job.store + (job.store_head ? int64_t(*job.store_head) * 4 * npts : 0) : nullptr;
+        const float *S0 = job.s0;
+        const int nzq = Nz / 4, nv = NZL * nzq;
+        float4 va[NV], vb[NV], qa[NV], qb[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int e = tid + NT * j;
+            va[j] = vb[j] = qa[j] = qb[j] = float4{0.f, 0.f, 0.f, 0.f};
+            if (e < nv) {
+                const int p = e / nzq;
+                const int64_t o = slab + int64_t(2 * p) * Nz + 4 * (e - p * nzq);
+                const bool hb = 2 * p + 1 < Ny;
+                va[j] = *reinterpret_cast<const float4 *>(S + o);
+                if (hb) vb[j] = *reinterpret_cast<const float4 *>(S + o + Nz);
+                if (S0) {
+                    qa[j] = *reinterpret_cast<const float4 *>(S0 + o);
+                    if (hb) qb[j] = *reinterpret_cast<const float4 *>(S0 + o + Nz);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int e = tid + NT * j;
+            if (e < nv) {
+                const int p = e / nzq, z = 4 * (e - p * nzq);
+                const int64_t o = slab + int64_t(2 * p) * Nz + z;
+                if (St) {
+                    *reinterpret_cast<float4 *>(St + o) = va[j];
+                    if (2 * p + 1 < Ny) *reinterpret_cast<float4 *>(St + o + Nz) = vb[j];
+                }
+                Cf *r = buf + p * RS + z;
+                r[0] = Cf{va[j].x - qa[j].x, vb[j].x - qb[j].x};
+                r[1] = Cf{va[j].y - qa[j].y, vb[j].y - qb[j].y};
+                r[2] = Cf{va[j].z - qa[j].z, vb[j].z - qb[j].z};
+                r[3] = Cf{va[j].w - qa[j].w, vb[j].w - qb[j].w};
+            }
+        }
+        // zeros: z in [Nz, P / 2) of every row
+        const int nzero = H - Nz;
+        for (int e = tid; e < NZL * nzero; e += NT) {
+            const int p = e / nzero;
+            buf[p * RS + Nz + e - p * nzero] = Cf{0.f, 0.f};
+        }
+    }
+    __syncthreads();
+    // z transforms (input z < P / 2), natural order back into the rows
+    {
+        const int li = tid % ZL, t = tid / ZL;
+        const bool act = t < T && li < NZL;
+        Cf *row = buf + li * RS;
+        Cf X[E];
+        if (act) {
+            Cf v[E];
+#pragma unroll
+            for (int n = 0; n < E / 2; ++n) v[n] = row[t + T * n];
+#pragma unroll
+            for (int n = E / 2; n < E; ++n) v[n] = Cf{0.f, 0.f};
+            dft_half_in<E, -1>(v, X);
+        }
+        __syncthreads();
+        if (act) {
+            row[t] = X[0];
+#pragma unroll
+            for (int k1 = 1; k1 < E; ++k1) {
+                const Cf w = twl[t * k1];
+                row[k1 * T + t] = Cf{X[k1].x * w.x - X[k1].y * w.y, X[k1].x * w.y + X[k1].y * w.x};
+            }
+        }
+        __syncthreads();
+        Cf Zs[E / T][T];
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < E / T; ++i) {
+                const int k1 = t + T * i;
+                Cf z[T];
+#pragma unroll
+                for (int s = 0; s < T; ++s) z[s] = row[k1 * T + s];
+                dft<T, -1>(z, Zs[i]);
+            }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < E / T; ++i)
+#pragma unroll
+                for (int k2 = 0; k2 < T; ++k2) row[t + T * i + E * k2] = Zs[i][k2];
+        }
+    }
+    __syncthreads();
+    // unpack X_a(k) = (Z_k + conj Z_-k) / 2, X_b(k) = (Z_k - conj Z_-k) / (2i)
+    // into the y rows: row kz, entry y (zeros for Ny <= y < P / 2)
+    {
+        Cf ua[NU], ub[NU];
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            const int e = tid + NT * j;
+            const int p = e / HZ, k = e - p * HZ;
+            ua[j] = ub[j] = Cf{0.f, 0.f};
+            if (p < NZL) {
+                const Cf zk = buf[p * RS + k], zm = buf[p * RS + (k == 0 ? 0 : P - k)];
+                ua[j] = Cf{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
+                ub[j] = Cf{0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)};
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            const int e = tid + NT * j;
+            const int p = e / HZ, k = e - p * HZ;
+            if (p < NZL) {
+                buf[k * RS + 2 * p] = ua[j];
+                if (2 * p + 1 < Ny) buf[k * RS + 2 * p + 1] = ub[j];
+            }
+        }
+        const int nzero = H - Ny;
+        for (int e = tid; e < HZ * nzero; e += NT) {
+            const int k = e / nzero;
+            buf[k * RS + Ny + e - k * nzero] = Cf{0.f, 0.f};
+        }
+    }
+    __syncthreads();
+    // y transforms (input y < P / 2), stored from registers:
+    // yout[x][k][kz][mu] for every k < P
+    Cf *__restrict__ yo = job.yout + int64_t(x) * P * HZ * 4 + mu;
+    for (int base = 0; base < HZ; base += LPI) {
+        const int li = tid % LPI, t = tid / LPI, kz = base + li;
+        const bool act = kz < HZ;
+        Cf *row = buf + kz * RS;
+        Cf X[E];
+        if (act) {
+            Cf v[E];
+#pragma unroll
+            for (int n = 0; n < E / 2; ++n) v[n] = row[t + T * n];
+#pragma unroll
+            for (int n = E / 2; n < E; ++n) v[n] = Cf{0.f, 0.f};
+            dft_half_in<E, -1>(v, X);
+        }
+        __syncthreads();
+        if (act) {
+            row[t] = X[0];
+#pragma unroll
+            for (int k1 = 1; k1 < E; ++k1) {
+                const Cf w = twl[t * k1];
+                row[k1 * T + t] = Cf{X[k1].x * w.x - X[k1].y * w.y, X[k1].x * w.y + X[k1].y * w.x};
+            }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < E / T; ++i) {
+                const int k1 = t + T * i;
+                Cf z[T], Z[T];
+#pragma unroll
+                for (int s = 0; s < T; ++s) z[s] = row[k1 * T + s];
+                dft<T, -1>(z, Z);
+#pragma unroll
+                for (int k2 = 0; k2 < T; ++k2) yo[(int64_t(k1 + E * k2) * HZ + kz) * 4] = Z[k2];
+            }
+        }
+    }
+}
+
+template <int P, int T>
+__global__ __launch_bounds__(256) void k_yz_inv(PlanePass a) {
+    constexpr int NT = 256, E = P / T, RS = P + 1, HZ = P / 2 + 1, LPI = NT / T, H = P / 2, ZL = 32;
+    constexpr int NV = ((P / 4) * (H / 4) + NT - 1) / NT;
+    constexpr int NU = ((P / 4) * HZ + NT - 1) / NT;
+    static_assert(P / 4 <= ZL && ZL * T <= NT, "the z rows of a slice exceed one round of threads");
+    __shared__ Cf buf[HZ * RS];
+    __shared__ Cf twl[P];
+    const PlaneJob &job = a.jobs[blockIdx.y];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < P; i += NT) twl[i] = reinterpret_cast<const Cf *>(a.tw)[i];
+    const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
+    const int x = tile >> 2, mu = tile & 3;
+    const int Nx = a.Nx, Ny = a.Ny, Nz = a.Nz, NZL = (Ny + 1) / 2;
+    __syncthreads();
+    // y transforms of rows kz < Hz (all P inputs; outputs y < P / 2 back into the rows)
+    const Cf *__restrict__ yi = job.yin + int64_t(x) * P * HZ * 4 + mu;
+    for (int base = 0; base < HZ; base += LPI) {
+        const int li = tid % LPI, t = tid / LPI, kz = base + li;
+        const bool act = kz < HZ;
+        Cf *row = buf + kz * RS;
+        if (act) {
+            Cf v[E], X[E];
+#pragma unroll
+            for (int n = 0; n < E; ++n) v[n] = yi[(int64_t(t + T * n) * HZ + kz) * 4];
+            dft<E, +1>(v, X);
+            row[t] = X[0];
+#pragma unroll
+            for (int k1 = 1; k1 < E; ++k1) {
+                const Cf w = twl[t * k1];
+                row[k1 * T + t] = Cf{X[k1].x * w.x + X[k1].y * w.y, X[k1].y * w.x - X[k1].x * w.y};
+            }
+        }
+        __syncthreads();
+        Cf Zs[E / T][T];
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < E / T; ++i) {
+                const int k1 = t + T * i;
+                Cf z[T];
+#pragma unroll
+                for (int s = 0; s < T; ++s) z[s] = row[k1 * T + s];
+                dft_half_out<T, +1>(z, Zs[i]);
+            }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < E / T; ++i)
+#pragma unroll
+                for (int k2 = 0; k2 < T / 2; ++k2) row[t + T * i + E * k2] = Zs[i][k2];
+        }
+    }
+    __syncthreads();
+    // z lines: Z_k = X_a(k) + i X_b(k), Z_{P-k} = conj X_a(k) + i conj X_b(k)
+    // with a = y row 2p, b = 2p + 1 (zero past Ny)
+    {
+        Cf ua[NU], ub[NU];
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            const int e = tid + NT * j;
+            const int p = e / HZ, k = e - p * HZ;
+            ua[j] = ub[j] = Cf{0.f, 0.f};
+            if (p < NZL) {
+                ua[j] = buf[k * RS + 2 * p];
+                if (2 * p + 1 < Ny) ub[j] = buf[k * RS + 2 * p + 1];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            const int e = tid + NT * j;
+            const int p = e / HZ, k = e - p * HZ;
+            if (p < NZL) {
+                const Cf xa = ua[j], xb = ub[j];
+                if (k == 0 || 2 * k == P) {
+                    buf[p * RS + k] = Cf{xa.x, xb.x};
+                } else {
+                    buf[p * RS + k] = Cf{xa.x - xb.y, xa.y + xb.x};
+                    buf[p * RS + (P - k)] = Cf{xa.x + xb.y, xb.x - xa.y};
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // z transforms, outputs z < P / 2 back into the rows
+    {
+        const int li = tid % ZL, t = tid / ZL;
+        const bool act = t < T && li < NZL;
+        Cf *row = buf + li * RS;
+        Cf X[E];
+        if (act) {
+            Cf v[E];
+#pragma unroll
+            for (int n = 0; n < E; ++n) v[n] = row[t + T * n];
+            dft<E, +1>(v, X);
+        }
+        __syncthreads();
+        if (act) {
+            row[t] = X[0];
+#pragma unroll
+            for (int k1 = 1; k1 < E; ++k1) {
+                const Cf w = twl[t * k1];
+                row[k1 * T + t] = Cf{X[k1].x * w.x + X[k1].y * w.y, X[k1].y * w.x - X[k1].x * w.y};
+            }
+        }
+        __syncthreads();
+        Cf Zs[E / T][T];
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < E / T; ++i) {
+                const int k1 = t + T * i;
+                Cf z[T];
+#pragma unroll
+                for (int s = 0; s < T; ++s) z[s] = row[k1 * T + s];
+                dft_half_out<T, +1>(z, Zs[i]);
+            }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < E / T; ++i)
+#pragma unroll
+                for (int k2 = 0; k2 < T / 2; ++k2) row[t + T * i + E * k2] = Zs[i][k2];
+        }
+    }
+    __syncthreads();
+    // rows y = 2p (real parts) and 2p + 1 (imaginary parts) of z row p into
+    // out[mu][x][y][z], four z at a time (+ add)
+    {
+        const int64_t slab = (int64_t(mu) * Nx + x) * Ny * Nz;
+        const int nzq = Nz / 4, nv = NZL * nzq;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int e = tid + NT * j;
+            if (e < nv) {
+                const int p = e / nzq, z = 4 * (e - p * nzq);
+                const int64_t o = slab + int64_t(2 * p) * Nz + z;
+                const bool hb = 2 * p + 1 < Ny;
+                const Cf *r = buf + p * RS + z;
+                const Cf r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+                float4 va = {r0.x, r1.x, r2.x, r3.x}, vb = {r0.y, r1.y, r2.y, r3.y};
+                if (job.add) {
+                    const float4 da = *reinterpret_cast<const float4 *>(job.add + o);
+                    va = float4{va.x + da.x, va.y + da.y, va.z + da.z, va.w + da.w};
+                    if (hb) {
+                        const float4 db = *reinterpret_cast<const float4 *>(job.add + o + Nz);
+                        vb = float4{vb.x + db.x, vb.y + db.y, vb.z + db.z, vb.w + db.w};
+                    }
+                }
+                *reinterpret_cast<float4 *>(job.out + o) = va;
+                if (hb) *reinterpret_cast<float4 *>(job.out + o + Nz) = vb;
+            }
+        }
+    }
+}
+
+// Threads per line of a plane pass (T * T divides P); 0: no plane pass
+int plane_threads(int P) {
+    switch (P) {
+    case 32: case 48: case 96: return 4;
+    case 64: case 128: return 8;
+    default: return 0;
+    }
+}
+
+template <int P>
+void launch_plane(const PlanePass &pp, bool fwd, hipStream_t st) {
+    constexpr int T = (P == 64 || P == 128) ? 8 : 4;
+    const dim3 grid(4 * pp.Nx, pp.n_jobs);
+    if (fwd) hipLaunchKernelGGL((k_zy_fwd<P, T>), grid, dim3(256), 0, st, pp);
+    else hipLaunchKernelGGL((k_yz_inv<P, T>), grid, dim3(256), 0, st, pp);
+}
+
+void launch_plane_p(int P, const PlanePass &pp, bool fwd, hipStream_t st) {
+    switch (P) {
+    case 32: launch_plane<32>(pp, fwd, st); break;
+    case 48: launch_plane<48>(pp, fwd, st); break;
+    case 64: launch_plane<64>(pp, fwd, st); break;
+    case 96: launch_plane<96>(pp, fwd, st); break;
+    default: launch_plane<128>(pp, fwd, st); break;
+    }
+}
+
+bool aligned16(const void *q) { return reinterpret_cast<uintptr_t>(q) % 16 == 0; }
+
 }  // namespace
 
 bool line_reg_supported(const LinePass &a) {
@@ -885,6 +1297,80 @@ bool launch_line_reg(const LinePass &a0, hipStream_t st) {
     case 128: launch_reg_fmt<128, 8>(a, ra, st); break;
     default: launch_reg_fmt<256, 16>(a, ra, st); break;
     }
+    return true;
+}
+
+bool plane_shape(int Py, int Pz, int Ny, int Nz) {
+    return Py == Pz && plane_threads(Pz) != 0 && Ny >= 1 && 2 * Ny <= Pz && Nz >= 4 && 2 * Nz <= Pz && Nz % 4 == 0;
+}
+
+// Forward z and y passes of the same jobs as one plane pass.  False (nothing
+// launched) where it does not apply: other lengths, unequal z and y pads, Ny
+// or Nz above P / 2, Nz not a multiple of 4, per-block maxima (the scaled
+// 16-bit float rings), Green's functions, misaligned arrays, or a y pass of
+// another layout than [Nx][Ny][Hz][4] -> [Nx][P][Hz][4].
+bool launch_zy_fwd_plane(const ZFwd &z, const LinePass &y, hipStream_t st) {
+    const int P = z.Pz;
+    if (z.mode != 0 || !plane_shape(z.Py, P, z.Ny, z.Nz) || y.P != P || z.Hz != P / 2 + 1 || z.Nx < 1) return false;
+    const int64_t hz4 = int64_t(z.Hz) * 4;
+    if (!(y.dir < 0 && y.n_in == z.Ny && y.n_out == P && y.lines == z.Nx * hz4 && y.n_inner == hz4 &&
+          y.in_j == hz4 && y.in_inner == 1 && y.in_outer == z.Ny * hz4 && y.out_j == hz4 && y.out_inner == 1 &&
+          y.out_outer == P * hz4 && y.out_fmt == RING_F32 && y.add_fmt == 0 && y.n_jobs == z.n_jobs))
+        return false;
+    PlanePass pp{};
+    pp.Nx = z.Nx;
+    pp.Ny = z.Ny;
+    pp.Nz = z.Nz;
+    pp.tw = z.tw;
+    pp.n_jobs = z.n_jobs;
+    for (int j = 0; j < z.n_jobs; ++j) {
+        const ZFwdJob &J = z.jobs[j];
+        const LineJob &Y = y.jobs[j];
+        if (J.zmax || Y.in != J.out || Y.tile_stride != 0 || Y.head || Y.qscale) return false;
+        if (!aligned16(J.src) || !aligned16(J.s0) || !aligned16(J.store) || reinterpret_cast<uintptr_t>(Y.out) % 8)
+            return false;
+        PlaneJob &Q = pp.jobs[j];
+        Q.src = static_cast<const float *>(J.src);
+        Q.s0 = static_cast<const float *>(J.s0);
+        Q.src_head = J.src_head;
+        Q.src_depth = J.src_depth;
+        Q.src_lag = J.src_lag;
+        Q.store = static_cast<float *>(J.store);
+        Q.store_head = J.store_head;
+        Q.yout = static_cast<Cf *>(Y.out);
+    }
+    launch_plane_p(P, pp, true, st);
+    return true;
+}
+
+// Inverse y and z passes of the same jobs as one plane pass; false (nothing
+// launched) where it does not apply (as above, for a y pass
+// [Nx][P][Hz][4] -> [Nx][Ny][Hz][4]).
+bool launch_yz_inv_plane(const LinePass &y, const ZInv &zi, hipStream_t st) {
+    const int P = zi.Pz;
+    if (!plane_shape(y.P, P, zi.Ny, zi.Nz) || zi.Hz != P / 2 + 1 || zi.Nx < 1) return false;
+    const int64_t hz4 = int64_t(zi.Hz) * 4;
+    if (!(y.dir > 0 && y.n_in == P && y.n_out == zi.Ny && y.lines == zi.Nx * hz4 && y.n_inner == hz4 &&
+          y.in_j == hz4 && y.in_inner == 1 && y.in_outer == P * hz4 && y.out_j == hz4 && y.out_inner == 1 &&
+          y.out_outer == zi.Ny * hz4 && y.out_fmt == RING_F32 && y.add_fmt == 0 && y.n_jobs == zi.n_jobs))
+        return false;
+    PlanePass pp{};
+    pp.Nx = zi.Nx;
+    pp.Ny = zi.Ny;
+    pp.Nz = zi.Nz;
+    pp.tw = zi.tw;
+    pp.n_jobs = zi.n_jobs;
+    for (int j = 0; j < zi.n_jobs; ++j) {
+        const ZInvJob &J = zi.jobs[j];
+        const LineJob &Y = y.jobs[j];
+        if (Y.out != J.in || Y.tile_stride != 0 || Y.head || Y.qscale) return false;
+        if (!aligned16(J.out) || !aligned16(J.add) || reinterpret_cast<uintptr_t>(Y.in) % 8) return false;
+        PlaneJob &Q = pp.jobs[j];
+        Q.yin = static_cast<const Cf *>(Y.in);
+        Q.out = static_cast<float *>(J.out);
+        Q.add = static_cast<const float *>(J.add);
+    }
+    launch_plane_p(P, pp, false, st);
     return true;
 }
 

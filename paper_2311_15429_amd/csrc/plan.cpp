@@ -800,10 +800,15 @@ void plan_stats(rp_plan p) {
         const double ring = double(S.C) * 4 * p->ring_esz;
         const double acc = double(S.C) * 4 * p->csz;
         const double real = double(d.npts) * 4 * p->tsz;
-        st.fft_bytes_fwd += 2 * real + t1 + t1 + t2 + t2 + ring;
-        st.fft_bytes_inv += acc + t2 + t2 + t1 + t1 + 2 * real;
+        // plane passes keep the z-transformed array (t1) in LDS; the forward
+        // ones do not run with the scaled 16-bit float rings
+        const bool pl = plane_ok(p) && plane_shape(S.P[1], S.P[2], d.N[1], d.N[2]);
+        const bool plf = pl && !(p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
+        const double fwd = 2 * real + (plf ? 0.0 : t1 + t1) + t2 + t2 + ring;
+        st.fft_bytes_fwd += fwd;
+        st.fft_bytes_inv += acc + t2 + t2 + (pl ? 0.0 : t1 + t1) + 2 * real;
         // a split history also stores the sources, and transforms them again per extra ring
-        if (d.d1 > 0) st.fft_bytes_fwd += real + double(d.vr.size()) * (2 * real + t1 + t1 + t2 + t2 + ring);
+        if (d.d1 > 0) st.fft_bytes_fwd += real + double(d.vr.size()) * fwd;
     }
 }
 
@@ -819,6 +824,10 @@ void check_launch() {
 const void *tw_ptr(rp_plan p, int P, bool dbl) {
     return p->ws ? p->ws + (dbl ? p->tw64.at(P) : p->tw32.at(P)) : nullptr;
 }
+
+// whether the FP32 plane passes (z and y in one launch) may replace the
+// separate passes; each launch still checks its own shapes
+bool plane_ok(rp_plan p) { return !p->p64 && p->fft_reg && p->fft_plane; }
 
 LinePass line_pass(rp_plan p, int P, bool dbl, int dir) {
     LinePass a{};
@@ -1345,9 +1354,11 @@ void enqueue_ring_jobs(rp_plan p, const ClassP &K, const std::vector<RingJob> &j
                 sa.jobs[j].npts = double(d.npts);
             }
         }
-        launch_zfwd(z, p->p64, st);
-        launch_ring_scale(sa, st);
-        launch_line_pass(y, p->p64, st);
+        if (!(plane_ok(p) && launch_zy_fwd_plane(z, y, st))) {
+            launch_zfwd(z, p->p64, st);
+            launch_ring_scale(sa, st);
+            launch_line_pass(y, p->p64, st);
+        }
         launch_line_pass(x, p->p64, st);
         launch_quant_i16(qa, st);
         check_launch();
@@ -1512,8 +1523,10 @@ void enqueue_inverse(rp_plan p, void *const *out, hipStream_t st, int phase) {
                 zi.jobs[j].add = p->ws + d.off_p0;
             }
             launch_line_pass(x, p->p64, st);
-            launch_line_pass(y, p->p64, st);
-            launch_zinv(zi, p->p64, st);
+            if (!(plane_ok(p) && launch_yz_inv_plane(y, zi, st))) {
+                launch_line_pass(y, p->p64, st);
+                launch_zinv(zi, p->p64, st);
+            }
             check_launch();
         }
     }
@@ -2031,6 +2044,12 @@ rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value) {
             if (value != 0 && value != 1) fail(RP_ERR_ARG, "register line passes must be 0 or 1");
             plan->fft_reg = value;
             update_fused_additions(plan);
+            plan_stats(plan);
+            break;
+        case RP_TUNE_FFT_PLANE:
+            if (value != 0 && value != 1) fail(RP_ERR_ARG, "plane passes must be 0 or 1");
+            plan->fft_plane = value;
+            plan_stats(plan);
             break;
         case RP_TUNE_LAGSUM_CACHED:
             if (value != 0 && value != 1) fail(RP_ERR_ARG, "cached must be 0 or 1");
@@ -2101,6 +2120,7 @@ rp_status rp_get_tuning(rp_plan plan, int32_t knob, int32_t *value) {
         case RP_TUNE_LAGSUM_CACHED: *value = plan->k2b_cached; break;
         case RP_TUNE_LAGSUM_TILE_MAJOR: *value = plan->k2b_tile_major; break;
         case RP_TUNE_FFT_REG: *value = plan->fft_reg; break;
+        case RP_TUNE_FFT_PLANE: *value = plan->fft_plane; break;
         case RP_TUNE_FFT_LDS: *value = plan->fft_lds ? plan->fft_lds : (plan->p64 ? 4096 : 2048); break;
         default: fail(RP_ERR_ARG, "unknown tuning knob");
         }

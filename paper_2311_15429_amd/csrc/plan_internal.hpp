@@ -242,6 +242,7 @@ struct rp_plan_s {
     int k2_persist = 0;  // persistent lag-sum launch (work counter) instead of one block per item
     int fft_lds = 0;     // line-pass tile: complex elements staged per block (0: default)
     int fft_reg = 1;     // FP32 line passes of the supported lengths in registers
+    int fft_plane = 1;   // FP32 forward z+y and inverse y+z passes as plane passes where they apply
     int split_gap = 0;   // split a source's history at lag gaps of at least this many lags (0: off)
     std::vector<rpot_host::VRingP> vring;
     // host tier of a split history: real-space rings in pinned host memory
@@ -303,6 +304,7 @@ namespace rpot_host {
 void check_launch();
 RadixPlan make_radix(int P);
 const void *tw_ptr(rp_plan p, int P, bool dbl);
+bool plane_ok(rp_plan p);
 LinePass inv_x(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl);
 LinePass inv_y(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl);
 // gmax: targets per group; m_cap: every pair's window clipped to lags <= m_cap.

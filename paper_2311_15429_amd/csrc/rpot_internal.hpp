@@ -249,6 +249,13 @@ bool line_reg_supported(const LinePass &a);
 // the launch (nothing launched)
 bool launch_zfwd_reg(const ZFwd &a, hipStream_t st);
 bool launch_zinv_reg(const ZInv &a, hipStream_t st);
+// FP32 plane passes (fft_reg.hip): the forward z and y passes, or the inverse
+// y and z passes, of the same jobs in one launch; false when they do not cover
+// the pair of passes (nothing launched)
+bool launch_zy_fwd_plane(const ZFwd &z, const LinePass &y, hipStream_t st);
+bool launch_yz_inv_plane(const LinePass &y, const ZInv &zi, hipStream_t st);
+// whether a grid of Ny x Nz (y, z) points with pads Py, Pz has plane passes
+bool plane_shape(int Py, int Pz, int Ny, int Nz);
 void launch_zfwd(const ZFwd &a, int prec64, hipStream_t st);
 void launch_zinv(const ZInv &a, int prec64, hipStream_t st);
 int zfwd_lines_per_block(int Pz, int prec64);

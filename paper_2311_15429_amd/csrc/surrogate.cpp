@@ -241,8 +241,10 @@ void judge_fields(rp_plan p, hipStream_t st, Fn &&fn) {
                 zi.jobs[j].add = nullptr;
             }
             launch_line_pass(x, 0, st);
-            launch_line_pass(y, 0, st);
-            launch_zinv(zi, 0, st);
+            if (!(plane_ok(p) && launch_yz_inv_plane(y, zi, st))) {
+                launch_line_pass(y, 0, st);
+                launch_zinv(zi, 0, st);
+            }
             check_launch();
             fn(&vs[j0], cnt);
         }

@@ -221,6 +221,41 @@ def test_register_z_passes(dims_a, dims_b, pz):
         assert np.all(d <= 2e-6), (l, d)
 
 
+@pytest.mark.parametrize("dims_a,dims_b,pad", [((5, 48, 48), (3, 47, 44), 96), ((4, 32, 32), (2, 31, 28), 64),
+                                               ((2, 64, 64), (3, 60, 40), 128), ((3, 16, 16), (2, 15, 12), 32),
+                                               ((2, 24, 24), (2, 23, 20), 48)])
+@pytest.mark.parametrize("ring", ["fp32", "fp32_ring_fp16"])
+def test_plane_passes(dims_a, dims_b, pad, ring):
+    """The z and y transforms of an x slice and component in one launch
+    (forward: sources to the y-transformed array; inverse: back to the cropped
+    potentials), pads 32 to 128, an odd y extent and a z extent below half the
+    pad in the second domain.  With the scaled FP16 ring the forward passes stay
+    separate (per-block maxima) and the inverse ones are fused.  Against the
+    oracle, and against the separate passes to FP32 rounding."""
+    from paper_2311_15429_amd import plan_for_system
+    h = 0.5
+    rng = np.random.default_rng(pad + len(ring))
+    doms = [sy.Domain(dims_a, np.zeros(3)), sy.Domain(dims_b, np.array([h * dims_a[0] + 4.0, 1.0, -2.0]))]
+    for d in doms:
+        sy._random_pairs(rng, d, h, 2)
+    s = sy.System(h, 0.02, sy.C_AU, doms, name=f"plane pad {pad}")
+    p = plan_for_system(s, "fp32")
+    assert tuple(p.info(0, 0)[2][1:]) == (pad, pad)
+    p.close()
+    L = 8
+    S = _samples(s, L)
+    plane = run_gpu(s, ring, S, tune={"fft_plane": 1})
+    sep = run_gpu(s, ring, S, tune={"fft_plane": 0})
+    ref = oracle.potential_full(s, S, [L])[0]
+    e = rel_err(plane[L], ref)
+    bar = FP32_TOL if ring == "fp32" else 2e-4
+    log(f"plane passes, pad {pad}, {ring}: vs oracle {np.array2string(e, precision=2)}")
+    assert np.all(e <= bar), e
+    for l in range(L + 1):
+        d = rel_err(plane[l], sep[l]) if np.any(sep[l][0]) else np.zeros(4)
+        assert np.all(d <= 2e-6), (l, d)
+
+
 @pytest.mark.parametrize("dims,pads", [((16, 24, 32), (32, 48, 64)), ((48, 54, 8), (96, 108, 16)),
                                        ((64, 4, 128), (128, 8, 256)), ((32, 128, 8), (64, 256, 16))])
 def test_i16_ring_quantised_by_the_x_pass(dims, pads):
