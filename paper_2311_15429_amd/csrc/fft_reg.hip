@@ -250,11 +250,13 @@ __device__ __forceinline__ void add_own_lags(const LineJob &job, int yz, int c, 
     const int off0 = int(kk0 % kTile);
     const int xb = kTile - off0;   // first x of the line in the next tile
     const int64_t w = job.add_w, depth = job.add_depth;
-    const Cf *spec = reinterpret_cast<const Cf *>(job.add_spec);
+    // the self pair's spectra are real: rows of kTile floats at the start of
+    // each row's place (2 kTile floats apart)
+    const float *spec = reinterpret_cast<const float *>(job.add_spec);
     int slot = *job.add_head;
     for (int m = 0; m < job.add_lags; ++m) {
-        const Cf *g0 = spec + (tile0 * w + m) * kTile + off0 + t;
-        const Cf *g1 = spec + ((tile0 + 1) * w + m) * kTile + (off0 - kTile) + t;
+        const float *g0 = spec + (tile0 * w + m) * (2 * kTile) + off0 + t;
+        const float *g1 = spec + ((tile0 + 1) * w + m) * (2 * kTile) + (off0 - kTile) + t;
         const int64_t row0 = (tile0 * depth + slot) * (4 * kTile), row1 = ((tile0 + 1) * depth + slot) * (4 * kTile);
         if constexpr (AF == RING_F32) {
             // rows [c/2][k][c%2] of complex FP32 values
@@ -263,8 +265,9 @@ __device__ __forceinline__ void add_own_lags(const LineJob &job, int yz, int c, 
 #pragma unroll
             for (int n = 0; n < E; ++n) {
                 const bool hi = !ONE_TILE && t + T * n >= xb;
-                const Cf g = (hi ? g1 : g0)[T * n], r = (hi ? r1 : r0)[2 * T * n];
-                v[n] = Cf{v[n].x + g.x * r.x - g.y * r.y, v[n].y + g.x * r.y + g.y * r.x};
+                const float g = (hi ? g1 : g0)[T * n];
+                const Cf r = (hi ? r1 : r0)[2 * T * n];
+                v[n] = Cf{v[n].x + g * r.x, v[n].y + g * r.y};
             }
         } else {
             // rows [k][c] of 4-byte values: FP16 / BF16 pairs times the
@@ -281,7 +284,7 @@ __device__ __forceinline__ void add_own_lags(const LineJob &job, int yz, int c, 
 #pragma unroll
             for (int n = 0; n < E; ++n) {
                 const bool hi = !ONE_TILE && t + T * n >= xb;
-                const Cf g = (hi ? g1 : g0)[T * n];
+                const float g = (hi ? g1 : g0)[T * n];
                 const uint32_t u = (hi ? r1 : r0)[4 * T * n];
                 const float s = hi ? s1 : s0;
                 Cf r;
@@ -295,7 +298,7 @@ __device__ __forceinline__ void add_own_lags(const LineJob &job, int yz, int c, 
                 } else {
                     r = Cf{float(int(u << 16) >> 16) * s, float(int(u) >> 16) * s};
                 }
-                v[n] = Cf{v[n].x + g.x * r.x - g.y * r.y, v[n].y + g.x * r.y + g.y * r.x};
+                v[n] = Cf{v[n].x + g * r.x, v[n].y + g * r.y};
             }
         }
         slot = slot == 0 ? int(depth) - 1 : slot - 1;

@@ -56,6 +56,10 @@ template <int AUX = kLoadAux>
 __device__ __forceinline__ nu2 ld64(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(nu2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
 }
+template <int AUX = kLoadAux>
+__device__ __forceinline__ float ld32f(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+}
 
 template <>
 struct RingLoad<double, RING_F64> {
@@ -143,13 +147,23 @@ __device__ __forceinline__ Cx<T> load_spec(__amdgpu_buffer_rsrc_t r, int lane) {
     }
 }
 
+// Members with a real spectrum (self pairs of FP32 plans) take two
+// multiply-adds per component instead of four.
 template <typename T, int TG>
-__device__ __forceinline__ void mac_entry(Cx<T> (&acc)[TG][4], uint32_t mask, uint32_t conj, const Cx<T> (&g)[TG],
-                                          const Cx<T> (&x)[4]) {
+__device__ __forceinline__ void mac_entry(Cx<T> (&acc)[TG][4], uint32_t mask, uint32_t conj, uint32_t real,
+                                          const Cx<T> (&g)[TG], const Cx<T> (&x)[4]) {
 #pragma unroll
     for (int t = 0; t < TG; ++t) {
         if (mask & (1u << t)) {
             const T gx = g[t].x;
+            if ((real >> t) & 1u) {
+#pragma unroll
+                for (int mu = 0; mu < 4; ++mu) {
+                    acc[t][mu].x = fma(gx, x[mu].x, acc[t][mu].x);
+                    acc[t][mu].y = fma(gx, x[mu].y, acc[t][mu].y);
+                }
+                continue;
+            }
             const T gy = ((conj >> t) & 1u) ? -g[t].y : g[t].y;
 #pragma unroll
             for (int mu = 0; mu < 4; ++mu) {
@@ -178,8 +192,8 @@ struct RingEsz {
 // accumulated.
 template <typename T, int FMT, int TG>
 __device__ __forceinline__ uint32_t load_lag(const K2Args &a, const char *ring_tile, int32_t slot, int64_t scale_off,
-                                             const char *spec, const int32_t (&r)[TG], uint32_t mk, int m, int lane,
-                                             Cx<T> (&x)[4], Cx<T> (&gv)[TG]) {
+                                             const char *spec, const int32_t (&r)[TG], uint32_t mk, uint32_t real,
+                                             int m, int lane, Cx<T> (&x)[4], Cx<T> (&gv)[TG]) {
     constexpr int64_t ring_row = int64_t(kTile) * 4 * RingEsz<FMT>::v;
     constexpr int64_t spec_row = int64_t(kTile) * int64_t(sizeof(Cx<T>));
     if (mk) {
@@ -193,8 +207,17 @@ __device__ __forceinline__ uint32_t load_lag(const K2Args &a, const char *ring_t
         }
         RingLoad<T, FMT>::get(row_rsrc(ring_tile + slot * ring_row, int(ring_row)), lane, sc, x);
 #pragma unroll
-        for (int t = 0; t < TG; ++t)
-            if (mk & (1u << t)) gv[t] = load_spec<T>(row_rsrc(spec + int64_t(r[t] + m) * spec_row, int(spec_row)), lane);
+        for (int t = 0; t < TG; ++t) {
+            if (!(mk & (1u << t))) continue;
+            const __amdgpu_buffer_rsrc_t rs = row_rsrc(spec + int64_t(r[t] + m) * spec_row, int(spec_row));
+            if constexpr (sizeof(T) == 4) {
+                if ((real >> t) & 1u) {
+                    gv[t] = {ld32f(rs, lane * 4), 0.f};
+                    continue;
+                }
+            }
+            gv[t] = load_spec<T>(rs, lane);
+        }
     }
     return mk;
 }
@@ -222,7 +245,7 @@ __device__ __forceinline__ void lagsum_item(const K2Args &a, int item_index) {
         const K2Src &R = a.srcs[si];
         const int m_min = R.m_min, m_max = R.m_max, depth = R.depth;
         if (m_max < m_min) continue;
-        const uint32_t conj = R.conj;
+        const uint32_t conj = R.conj, real = R.real;
         const uint32_t *masks = a.masks + R.mask_off - m_min;
         int32_t r[TG];
 #pragma unroll
@@ -245,19 +268,20 @@ __device__ __forceinline__ void lagsum_item(const K2Args &a, int item_index) {
             uint32_t mask[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                mask[u] = load_lag<T, FMT, TG>(a, ring_tile, slot, scale_off, spec, r, masks[m + u], m + u, lane,
-                                               x[u], gv[u]);
+                mask[u] = load_lag<T, FMT, TG>(a, ring_tile, slot, scale_off, spec, r, masks[m + u], real, m + u,
+                                               lane, x[u], gv[u]);
                 slot = (slot == 0) ? depth - 1 : slot - 1;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (mask[u]) mac_entry<T, TG>(acc, mask[u], conj, gv[u], x[u]);
+                if (mask[u]) mac_entry<T, TG>(acc, mask[u], conj, real, gv[u], x[u]);
         }
         for (; m <= m_max; ++m) {
             Cx<T> x[4];
             Cx<T> gv[TG];
-            const uint32_t mk = load_lag<T, FMT, TG>(a, ring_tile, slot, scale_off, spec, r, masks[m], m, lane, x, gv);
-            if (mk) mac_entry<T, TG>(acc, mk, conj, gv, x);
+            const uint32_t mk =
+                load_lag<T, FMT, TG>(a, ring_tile, slot, scale_off, spec, r, masks[m], real, m, lane, x, gv);
+            if (mk) mac_entry<T, TG>(acc, mk, conj, real, gv, x);
             slot = (slot == 0) ? depth - 1 : slot - 1;
         }
     }
@@ -294,6 +318,98 @@ __device__ __forceinline__ void lagsum_item(const K2Args &a, int item_index) {
 // in a circular register window: lag m sits at (m - d0) mod KB, d0 being the
 // first age of the walk, so with the walk unrolled by KB every index is a
 // compile-time constant.
+// One source of a blocked item: the walk over its snapshots.  REAL: the
+// pair's spectrum is real (a self pair), read as floats, two multiply-adds per
+// component and accumulator set instead of four.
+template <int FMT, int KB, int U, int AUX, bool REAL>
+__device__ __forceinline__ void block_src(const K2Args &a, const K2Src &R, const char *srow, const char *ring_tile,
+                                          int64_t scale_off, int lane, Cx<float> (&acc)[KB][4]) {
+    constexpr int esz = RingEsz<FMT>::v;
+    constexpr int64_t ring_row = int64_t(kTile) * 4 * esz;
+    constexpr int64_t spec_row = int64_t(kTile) * int64_t(sizeof(Cx<float>));
+    const int m_lo = R.m_min, m_hi = R.m_max, depth = R.depth;
+    const bool conj = R.conj & 1u;
+    // the walk starts kb - 1 ages below the window, at the newest snapshot
+    // at the latest; age d sits in slot head - (d - m_base)
+    const int d0 = max(R.m_base, m_lo - (KB - 1));
+    const int n_it = m_hi - d0 + 1;
+    int32_t slot = a.head[R.n] - (d0 - R.m_base);
+    if (slot < 0) slot += depth;
+
+    auto load_g = [&](int m) -> Cx<float> {
+        if (m < m_lo || m > m_hi) return {0.f, 0.f};
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc(srow + int64_t(m) * spec_row, int(spec_row));
+        if constexpr (REAL) return {ld32f<AUX>(rs, lane * 4), 0.f};
+        Cx<float> v = load_spec<float, AUX>(rs, lane);
+        if (conj) v.y = -v.y;
+        return v;
+    };
+    Cx<float> gw[KB];
+#pragma unroll
+    for (int j = 0; j < KB - 1; ++j) gw[j] = load_g(d0 + j);
+    gw[KB - 1] = {0.f, 0.f};
+
+    for (int t0 = 0; t0 < n_it; t0 += KB) {
+#pragma unroll
+        for (int u0 = 0; u0 < KB; u0 += U) {
+            if (t0 + u0 >= n_it) break;
+            // loads of U snapshots first: ring rows, and the newest lag of
+            // each one's window into gn (the slot it takes in gw still
+            // holds a lag the previous snapshot needs)
+            Cx<float> x[U][4];
+            Cx<float> gn[U];
+#pragma unroll
+            for (int v = 0; v < U; ++v) {
+                const int t = t0 + u0 + v;
+                if (t < n_it) {
+                    gn[v] = load_g(d0 + t + KB - 1);
+                    float sc[4] = {1.f, 1.f, 1.f, 1.f};
+                    if (FMT == RING_F16 || FMT == RING_BF16 || FMT == RING_I16) {
+                        const float *s4 = a.scales + scale_off + int64_t(slot) * 4;
+                        sc[0] = s4[0];
+                        sc[1] = s4[1];
+                        sc[2] = s4[2];
+                        sc[3] = s4[3];
+                    }
+                    RingLoad<float, FMT>::template get<AUX>(row_rsrc(ring_tile + slot * ring_row, int(ring_row)),
+                                                            lane, sc, x[v]);
+                    slot = (slot == 0) ? depth - 1 : slot - 1;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < U; ++v) {
+                if (t0 + u0 + v < n_it) {
+                    gw[(u0 + v + KB - 1) % KB] = gn[v];   // replaces lag d0 + t - 1
+                    // opaque per snapshot, so the branch is not hoisted out of the walk
+                    if constexpr (REAL) {
+#pragma unroll
+                        for (int i = 0; i < KB; ++i) {
+                            const float gx = gw[(u0 + v + i) % KB].x;
+#pragma unroll
+                            for (int mu = 0; mu < 4; ++mu) {
+                                acc[i][mu].x = fmaf(gx, x[v][mu].x, acc[i][mu].x);
+                                acc[i][mu].y = fmaf(gx, x[v][mu].y, acc[i][mu].y);
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < KB; ++i) {
+                            const Cx<float> gv = gw[(u0 + v + i) % KB];
+#pragma unroll
+                            for (int mu = 0; mu < 4; ++mu) {
+                                acc[i][mu].x = fmaf(gv.x, x[v][mu].x, acc[i][mu].x);
+                                acc[i][mu].x = fmaf(-gv.y, x[v][mu].y, acc[i][mu].x);
+                                acc[i][mu].y = fmaf(gv.x, x[v][mu].y, acc[i][mu].y);
+                                acc[i][mu].y = fmaf(gv.y, x[v][mu].x, acc[i][mu].y);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <int FMT, int KB, int U, int AUX>
 __device__ __forceinline__ void lagsum_block_item(const K2Args &a, int item_index) {
     constexpr int esz = RingEsz<FMT>::v;
@@ -315,82 +431,24 @@ __device__ __forceinline__ void lagsum_block_item(const K2Args &a, int item_inde
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) acc[i][mu] = {0.f, 0.f};
 
-    for (int si = g.src_begin; si < g.src_end; ++si) {
-        const K2Src &R = a.srcs[si];
-        const int m_lo = R.m_min, m_hi = R.m_max, depth = R.depth;
-        if (m_hi < m_lo) continue;
-        const bool conj = R.conj & 1u;
-        const K2Pair &Q = a.pairs[si * 8];
-        const char *srow = spec + int64_t(Q.row0 + tile * Q.w) * spec_row;   // + m * spec_row: lag m
-        const char *ring_tile = ring + (R.ring_off * esz + int64_t(tile) * depth * ring_row);
-        int64_t scale_off = 0;
-        if (FMT == RING_F16 || FMT == RING_BF16) scale_off = a.doms[R.n].scale_off;
-        if (FMT == RING_I16) scale_off = a.doms[R.n].scale_off + int64_t(tile) * depth * 4;
-        // the walk starts kb - 1 ages below the window, at the newest
-        // snapshot at the latest; age d sits in slot head - (d - m_base)
-        const int d0 = max(R.m_base, m_lo - (KB - 1));
-        const int n_it = m_hi - d0 + 1;
-        int32_t slot = a.head[R.n] - (d0 - R.m_base);
-        if (slot < 0) slot += depth;
-
-        auto load_g = [&](int m) -> Cx<float> {
-            if (m < m_lo || m > m_hi) return {0.f, 0.f};
-            Cx<float> v = load_spec<float, AUX>(row_rsrc(srow + int64_t(m) * spec_row, int(spec_row)), lane);
-            if (conj) v.y = -v.y;
-            return v;
-        };
-        Cx<float> gw[KB];
-#pragma unroll
-        for (int j = 0; j < KB - 1; ++j) gw[j] = load_g(d0 + j);
-        gw[KB - 1] = {0.f, 0.f};
-
-        for (int t0 = 0; t0 < n_it; t0 += KB) {
-#pragma unroll
-            for (int u0 = 0; u0 < KB; u0 += U) {
-                if (t0 + u0 >= n_it) break;
-                // loads of U snapshots first: ring rows, and the newest lag of
-                // each one's window into gn (the slot it takes in gw still
-                // holds a lag the previous snapshot needs)
-                Cx<float> x[U][4];
-                Cx<float> gn[U];
-#pragma unroll
-                for (int v = 0; v < U; ++v) {
-                    const int t = t0 + u0 + v;
-                    if (t < n_it) {
-                        gn[v] = load_g(d0 + t + KB - 1);
-                        float sc[4] = {1.f, 1.f, 1.f, 1.f};
-                        if (FMT == RING_F16 || FMT == RING_BF16 || FMT == RING_I16) {
-                            const float *s4 = a.scales + scale_off + int64_t(slot) * 4;
-                            sc[0] = s4[0];
-                            sc[1] = s4[1];
-                            sc[2] = s4[2];
-                            sc[3] = s4[3];
-                        }
-                        RingLoad<float, FMT>::template get<AUX>(row_rsrc(ring_tile + slot * ring_row, int(ring_row)),
-                                                                lane, sc, x[v]);
-                        slot = (slot == 0) ? depth - 1 : slot - 1;
-                    }
-                }
-#pragma unroll
-                for (int v = 0; v < U; ++v) {
-                    if (t0 + u0 + v < n_it) {
-                        gw[(u0 + v + KB - 1) % KB] = gn[v];   // replaces lag d0 + t - 1
-#pragma unroll
-                        for (int i = 0; i < KB; ++i) {
-                            const Cx<float> gv = gw[(u0 + v + i) % KB];
-#pragma unroll
-                            for (int mu = 0; mu < 4; ++mu) {
-                                acc[i][mu].x = fmaf(gv.x, x[v][mu].x, acc[i][mu].x);
-                                acc[i][mu].x = fmaf(-gv.y, x[v][mu].y, acc[i][mu].x);
-                                acc[i][mu].y = fmaf(gv.x, x[v][mu].y, acc[i][mu].y);
-                                acc[i][mu].y = fmaf(gv.y, x[v][mu].x, acc[i][mu].y);
-                            }
-                        }
-                    }
-                }
-            }
+    // the complex spectra first, then the real ones: two walks in sequence
+    // (one walk with a run-time choice between them costs hipcc 60 registers)
+    auto sources = [&](auto real_tag) {
+        constexpr bool REAL = decltype(real_tag)::value;
+        for (int si = g.src_begin; si < g.src_end; ++si) {
+            const K2Src &R = a.srcs[si];
+            if (R.m_max < R.m_min || bool(R.real & 1u) != REAL) continue;
+            const K2Pair &Q = a.pairs[si * 8];
+            const char *srow = spec + int64_t(Q.row0 + tile * Q.w) * spec_row;   // + m * spec_row: lag m
+            const char *ring_tile = ring + (R.ring_off * esz + int64_t(tile) * R.depth * ring_row);
+            int64_t scale_off = 0;
+            if (FMT == RING_F16 || FMT == RING_BF16) scale_off = a.doms[R.n].scale_off;
+            if (FMT == RING_I16) scale_off = a.doms[R.n].scale_off + int64_t(tile) * R.depth * 4;
+            block_src<FMT, KB, U, AUX, REAL>(a, R, srow, ring_tile, scale_off, lane, acc);
         }
-    }
+    };
+    sources(std::false_type{});
+    sources(std::true_type{});
 
     const DomDev &D = a.doms[g.member[0]];
     Cx<float> *__restrict__ out = reinterpret_cast<Cx<float> *>(a.acc) + D.acc_off + k * 4;
@@ -398,6 +456,26 @@ __device__ __forceinline__ void lagsum_block_item(const K2Args &a, int item_inde
     for (int i = 0; i < KB; ++i)
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) out[int64_t(i) * D.acc_set_stride + mu] = acc[i][mu];
+}
+
+// Self-pair Green spectra are real: the kernel of a sub-domain on itself
+// depends on |r| only, so on the padded grid it is even under r -> -r and the
+// imaginary parts of its transform are rounding residue.  Each row of kTile
+// complex values is rewritten in place as kTile floats (the real parts) in the
+// first half of its place; the lag sum then reads 4 bytes per frequency and
+// multiplies real by complex.  One block per row; every value of the row is
+// read (and parked in LDS) before the barrier, every float written after it.
+__global__ __launch_bounds__(kTile) void k_spec_real(Cx<float> *rows) {
+    __shared__ float re[kTile];
+    Cx<float> *row = rows + int64_t(blockIdx.x) * kTile;
+    re[threadIdx.x] = row[threadIdx.x].x;
+    __syncthreads();
+    reinterpret_cast<float *>(row)[threadIdx.x] = re[threadIdx.x];
+}
+
+void launch_spec_real(void *rows, int64_t n_rows, hipStream_t st) {
+    if (n_rows <= 0) return;
+    hipLaunchKernelGGL(k_spec_real, dim3(uint32_t(n_rows)), dim3(kTile), 0, st, static_cast<Cx<float> *>(rows));
 }
 
 // AUX: cache policy of the loads (kLoadAux: non-temporal; 0: cached, so that

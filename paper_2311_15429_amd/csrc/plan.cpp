@@ -236,6 +236,7 @@ void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables 
                     Qs[t].row0 = int32_t(q.spec0 / kTile) - q.m_lo;
                     Qs[t].w = q.m_hi - q.m_lo + 1;
                     if (q.conj) R.conj |= 1u << t;
+                    if (real_spec(p, mb[t].s, n)) R.real |= 1u << t;
                     R.m_min = std::min(R.m_min, lo_of(q));
                     R.m_max = std::max(R.m_max, hi_of(q));
                 }
@@ -279,6 +280,7 @@ void build_k2(rp_plan p, int si, const std::vector<K2Member> &members, K2Tables 
                     if (m < lo_of(q) || m > hi_of(q)) continue;
                     E.mask |= 1u << t;
                     if (q.conj) E.conj |= 1u << t;
+                    if (real_spec(p, mb[t].s, n)) E.real |= 1u << t;
                     E.spec_tile[t] = int32_t(q.spec0 / kTile + (m - q.m_lo));
                     E.spec_w[t] = q.m_hi - q.m_lo + 1;
                 }
@@ -736,7 +738,8 @@ double k2_bytes(rp_plan p, const K2Tables &T) {
         double per_k = 0;
         for (int e = G.entry_begin; e < G.entry_end; ++e) {
             const K2Entry &E = T.entries[e];
-            per_k += 4.0 * p->ring_esz + double(__builtin_popcount(E.mask)) * p->spec_csz;
+            per_k += 4.0 * p->ring_esz + double(__builtin_popcount(E.mask & ~E.real)) * p->spec_csz +
+                     double(__builtin_popcount(E.mask & E.real)) * 0.5 * p->spec_csz;
         }
         per_k += double(G.n_members) * 4 * p->csz;   // accumulator write
         bytes += per_k * double(G.C);
@@ -756,7 +759,8 @@ double k2b_bytes(rp_plan p) {
             const K2Src &R = p->k2b.srcs[size_t(si)];
             if (R.m_max < R.m_min) continue;
             const int d0 = std::max(R.m_base, R.m_min - (p->kb - 1));
-            per_k += double(R.m_max - d0 + 1) * 4.0 * p->ring_esz + double(R.m_max - R.m_min + 1) * p->spec_csz;
+            per_k += double(R.m_max - d0 + 1) * 4.0 * p->ring_esz +
+                     double(R.m_max - R.m_min + 1) * p->spec_csz * ((R.real & 1u) ? 0.5 : 1.0);
         }
         per_k += double(G.n_members) * p->kb * 4 * p->csz;
         bytes += per_k * double(G.C);
@@ -828,6 +832,9 @@ const void *tw_ptr(rp_plan p, int P, bool dbl) {
 // whether the FP32 plane passes (z and y in one launch) may replace the
 // separate passes; each launch still checks its own shapes
 bool plane_ok(rp_plan p) { return !p->p64 && p->fft_reg && p->fft_plane; }
+
+// Self pairs of FP32 plans keep their (real) spectra as rows of floats.
+bool real_spec(rp_plan p, int s, int n) { return s == n && !p->p64; }
 
 LinePass line_pass(rp_plan p, int P, bool dbl, int dir) {
     LinePass a{};
@@ -1187,9 +1194,13 @@ void do_green(rp_plan p) {
                                   size_t(S.spec_base + q.spec0 + int64_t(m0 + j - q.m_lo) * kTile) * p->spec_csz;
                     green_spectra(p, s, n, 1, m0, cnt, outs, fmt, W * kTile);
                 }
+                if (real_spec(p, s, n))
+                    launch_spec_real(p->ws + p->off_spec + size_t(S.spec_base + q.spec0) * p->spec_csz,
+                                     int64_t(q.m_hi - q.m_lo + 1) * (S.Cpad / kTile), p->stream);
             }
         }
     }
+    check_launch();
     HIP_OK(hipStreamSynchronize(p->stream));
     p->green_ready = true;
 }

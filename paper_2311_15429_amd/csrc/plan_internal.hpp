@@ -305,6 +305,7 @@ void check_launch();
 RadixPlan make_radix(int P);
 const void *tw_ptr(rp_plan p, int P, bool dbl);
 bool plane_ok(rp_plan p);
+bool real_spec(rp_plan p, int s, int n);
 LinePass inv_x(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl);
 LinePass inv_y(rp_plan p, const int N[3], const int P[3], int Hz, bool dbl);
 // gmax: targets per group; m_cap: every pair's window clipped to lags <= m_cap.

@@ -70,7 +70,8 @@ struct LineJob {
     const void *add_ring;      // the target's history ring (tile-major rows)
     const float *add_scales;   // its scales (FP16/BF16 [depth][4], I16 [tile][depth][4])
     const int32_t *add_head;   // its head (slot of the newest snapshot, lag 0)
-    const void *add_spec;      // Green spectra of the self pair: row tile * add_w + m, kTile complex each
+    const void *add_spec;      // Green spectra of the self pair: row tile * add_w + m, real (kTile
+                               // floats at the start of each row's place of kTile complex values)
     int32_t add_depth, add_w, add_lags;
 };
 
@@ -167,7 +168,7 @@ struct K2Entry {
     uint32_t conj;         // members that use the conjugate of the stored spectrum
     int64_t ring_off;      // the source's ring (complex elements from the first ring)
     int32_t depth;         // the source's ring depth
-    int32_t pad_;
+    uint32_t real;         // members whose spectra are real (K2Src::real)
     int32_t spec_tile[8];  // per member: (pair base + lag * kTile) / kTile within the system
     int32_t spec_w[8];     // per member: lags of the pair (spectrum tile stride / kTile)
 };
@@ -181,6 +182,8 @@ struct K2Src {
     uint32_t conj;         // members that use the conjugate of the stored spectra
     int32_t mask_off;      // masks[mask_off + m - m_min]: members whose window holds lag m
     int32_t m_base;        // lag of the ring's newest snapshot (0, or a split ring's first lag)
+    uint32_t real;         // members whose spectra are real: rows of kTile floats (the first
+                           // half of the row's place), for the self pairs of FP32 plans
 };
 
 // Per (group, source, member): where the pair's spectra sit.  They are stored
@@ -268,6 +271,9 @@ int lagsum_blocks_per_cu(int prec64, int ring_fmt, int tg, int unroll);
 // 4 or 8): every item writes the kb accumulator sets of its target.  unroll:
 // snapshots whose loads are issued before their products (1, 2 or 4).
 void launch_lagsum_block(const K2Args &a, int ring_fmt, int kb, int unroll, int grid_persist, hipStream_t st);
+// Self-pair spectra to real rows: each of n_rows rows of kTile complex FP32
+// values becomes kTile floats (the real parts) in the first half of its place.
+void launch_spec_real(void *rows, int64_t n_rows, hipStream_t st);
 int lagsum_block_blocks_per_cu(int ring_fmt, int kb, int unroll);
 // Per-snapshot ring scales: for each job, scales[head*4 + mu] =
 // 2^(e-15) with npts * max_blocks zmax[b][mu] <= 2^e (1 when the max is 0).
