@@ -89,49 +89,79 @@ __device__ __forceinline__ float block_max(float v, float *red) {
 // Moments.  Grid (kMomChunks, jobs): each block reduces a strided share of the
 // points into partial[chunk][kNFeat]; a second launch sums the chunks in a
 // fixed order (deterministic) into the ring slot of the current step.
+// The moments of one grid point (position r, source differences d) added to acc.
+__device__ __forceinline__ void point_moments(float (&acc)[kNMom], const float (&d)[4], const float (&r)[3]) {
+    // second-moment products x_a x_b (xx yy zz xy xz yz)
+    const float rr[6] = {r[0] * r[0], r[1] * r[1], r[2] * r[2], r[0] * r[1], r[0] * r[2], r[1] * r[2]};
+    acc[0] += d[0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[1 + c] = fmaf(d[0], r[c], acc[1 + c]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[4 + k] = fmaf(d[0], rr[k], acc[4 + k]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[10 + c] += d[1 + c];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) acc[13 + 3 * c + e] = fmaf(d[1 + c], r[e], acc[13 + 3 * c + e]);
+    }
+    // third moments of the charge: xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz
+    const float dr0 = d[0] * r[0], dr1 = d[0] * r[1], dr2 = d[0] * r[2];
+    acc[22] = fmaf(dr0, rr[0], acc[22]);
+    acc[23] = fmaf(dr1, rr[1], acc[23]);
+    acc[24] = fmaf(dr2, rr[2], acc[24]);
+    acc[25] = fmaf(dr1, rr[0], acc[25]);
+    acc[26] = fmaf(dr2, rr[0], acc[26]);
+    acc[27] = fmaf(dr0, rr[1], acc[27]);
+    acc[28] = fmaf(dr2, rr[1], acc[28]);
+    acc[29] = fmaf(dr0, rr[2], acc[29]);
+    acc[30] = fmaf(dr1, rr[2], acc[30]);
+    acc[31] = fmaf(dr0, rr[5], acc[31]);
+    // second moments of the current: N_i,ab
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[32 + 6 * c + k] = fmaf(d[1 + c], rr[k], acc[32 + 6 * c + k]);
+}
+
 __global__ __launch_bounds__(256) void k_moments_partial(MomentArgs a) {
     const MomentJob &j = a.jobs[blockIdx.y];
     const int64_t npts = int64_t(j.N[0]) * j.N[1] * j.N[2];
     float acc[kNMom];
 #pragma unroll
     for (int q = 0; q < kNMom; ++q) acc[q] = 0.f;
-    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < npts; i += int64_t(gridDim.x) * 256) {
-        int ix, iy, iz;
-        grid_xyz(i, j.N, ix, iy, iz);
-        const float r[3] = {j.o[0] + a.h * float(ix), j.o[1] + a.h * float(iy), j.o[2] + a.h * float(iz)};
-        float d[4];
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    if ((j.N[2] & 3) == 0 && ((reinterpret_cast<uintptr_t>(j.src) | reinterpret_cast<uintptr_t>(j.s0)) & 15) == 0) {
+        // four consecutive z of one (x, y) per thread: 16-byte loads, all
+        // eight issued before the products
+        for (int64_t i = (int64_t(blockIdx.x) * 256 + threadIdx.x) * 4; i < npts; i += stride * 4) {
+            float4 sv[4], qv[4];
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu) d[mu] = j.src[mu * npts + i] - j.s0[mu * npts + i];
-        // second-moment products x_a x_b (xx yy zz xy xz yz)
-        const float rr[6] = {r[0] * r[0], r[1] * r[1], r[2] * r[2], r[0] * r[1], r[0] * r[2], r[1] * r[2]};
-        acc[0] += d[0];
+            for (int mu = 0; mu < 4; ++mu) {
+                sv[mu] = *reinterpret_cast<const float4 *>(j.src + mu * npts + i);
+                qv[mu] = *reinterpret_cast<const float4 *>(j.s0 + mu * npts + i);
+            }
+            int ix, iy, iz;
+            grid_xyz(i, j.N, ix, iy, iz);
+            const float dd[4][4] = {{sv[0].x - qv[0].x, sv[1].x - qv[1].x, sv[2].x - qv[2].x, sv[3].x - qv[3].x},
+                                    {sv[0].y - qv[0].y, sv[1].y - qv[1].y, sv[2].y - qv[2].y, sv[3].y - qv[3].y},
+                                    {sv[0].z - qv[0].z, sv[1].z - qv[1].z, sv[2].z - qv[2].z, sv[3].z - qv[3].z},
+                                    {sv[0].w - qv[0].w, sv[1].w - qv[1].w, sv[2].w - qv[2].w, sv[3].w - qv[3].w}};
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[1 + c] = fmaf(d[0], r[c], acc[1 + c]);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) acc[4 + k] = fmaf(d[0], rr[k], acc[4 + k]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            acc[10 + c] += d[1 + c];
-#pragma unroll
-            for (int e = 0; e < 3; ++e) acc[13 + 3 * c + e] = fmaf(d[1 + c], r[e], acc[13 + 3 * c + e]);
+            for (int e = 0; e < 4; ++e) {
+                const float r[3] = {j.o[0] + a.h * float(ix), j.o[1] + a.h * float(iy), j.o[2] + a.h * float(iz + e)};
+                point_moments(acc, dd[e], r);
+            }
         }
-        // third moments of the charge: xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz
-        const float dr0 = d[0] * r[0], dr1 = d[0] * r[1], dr2 = d[0] * r[2];
-        acc[22] = fmaf(dr0, rr[0], acc[22]);
-        acc[23] = fmaf(dr1, rr[1], acc[23]);
-        acc[24] = fmaf(dr2, rr[2], acc[24]);
-        acc[25] = fmaf(dr1, rr[0], acc[25]);
-        acc[26] = fmaf(dr2, rr[0], acc[26]);
-        acc[27] = fmaf(dr0, rr[1], acc[27]);
-        acc[28] = fmaf(dr2, rr[1], acc[28]);
-        acc[29] = fmaf(dr0, rr[2], acc[29]);
-        acc[30] = fmaf(dr1, rr[2], acc[30]);
-        acc[31] = fmaf(dr0, rr[5], acc[31]);
-        // second moments of the current: N_i,ab
+    } else {
+        for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < npts; i += stride) {
+            int ix, iy, iz;
+            grid_xyz(i, j.N, ix, iy, iz);
+            const float r[3] = {j.o[0] + a.h * float(ix), j.o[1] + a.h * float(iy), j.o[2] + a.h * float(iz)};
+            float d[4];
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int k = 0; k < 6; ++k) acc[32 + 6 * c + k] = fmaf(d[1 + c], rr[k], acc[32 + 6 * c + k]);
+            for (int mu = 0; mu < 4; ++mu) d[mu] = j.src[mu * npts + i] - j.s0[mu * npts + i];
+            point_moments(acc, d, r);
+        }
     }
     // Wave sums by recursive halving: at the step with lane mask m a lane
     // keeps half of its values (the upper half when its bit m is set), sends
@@ -309,7 +339,54 @@ __global__ __launch_bounds__(256) void k_synthesize(SynthArgs a) {
     __shared__ float c[kNOut];
     if (threadIdx.x < kNOut) c[threadIdx.x] = j.coef[threadIdx.x];
     __syncthreads();
-    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < npts; i += int64_t(gridDim.x) * 256) {
+    if ((j.N[2] & 3) == 0 && (reinterpret_cast<uintptr_t>(j.out) & 15) == 0) {
+        // four consecutive z of one (x, y) per thread: 16-byte loads and
+        // stores.  The four points share x and y, so the x-y factors of the
+        // basis fold into W[mu][dz] = sum over b with z degree dz of
+        // c[mu][b] P_dx(x) P_dy(y), and each point takes sum_dz P_dz(z) W[mu][dz].
+        // One quad per thread (the grid covers the largest job): a loop here
+        // would hold all 80 coefficients in registers.
+        const int64_t i = (int64_t(blockIdx.x) * 256 + threadIdx.x) * 4;
+        if (i < npts) {
+            float4 o[4];
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu) o[mu] = *reinterpret_cast<const float4 *>(j.out + mu * npts + i);
+            int ix, iy, iz;
+            grid_xyz(i, j.N, ix, iy, iz);
+            float px[4], py[4];
+            legendre4(box_coord(ix, j.N[0]), px);
+            legendre4(box_coord(iy, j.N[1]), py);
+            float W[4][4];
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+                for (int dz = 0; dz < 4; ++dz) W[mu][dz] = 0.f;
+#pragma unroll
+            for (int b = 0; b < kNBasis; ++b) {
+                const float xy = px[kBasisDeg.d[b][0]] * py[kBasisDeg.d[b][1]];
+#pragma unroll
+                for (int mu = 0; mu < 4; ++mu)
+                    W[mu][kBasisDeg.d[b][2]] = fmaf(c[mu * kNBasis + b], xy, W[mu][kBasisDeg.d[b][2]]);
+            }
+            float v[4][4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float pz[4];
+                legendre4(box_coord(iz + e, j.N[2]), pz);
+#pragma unroll
+                for (int mu = 0; mu < 4; ++mu)
+                    v[mu][e] = fmaf(pz[3], W[mu][3], fmaf(pz[2], W[mu][2], fmaf(pz[1], W[mu][1], pz[0] * W[mu][0])));
+            }
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+                *reinterpret_cast<float4 *>(j.out + mu * npts + i) =
+                    float4{o[mu].x + v[mu][0], o[mu].y + v[mu][1], o[mu].z + v[mu][2], o[mu].w + v[mu][3]};
+        }
+        return;
+    }
+    // one point per thread
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < npts) {
         float B[kNBasis];
         basis_at(i, j.N, B);
 #pragma unroll
@@ -549,7 +626,15 @@ void launch_coef_sum(const CoefArgs &a, hipStream_t st) {
 
 void launch_synthesize(const SynthArgs &a, hipStream_t st) {
     if (a.n_jobs == 0) return;
-    hipLaunchKernelGGL(k_synthesize, dim3(128, a.n_jobs), dim3(256), 0, st, a);
+    // one quad of points per thread on the 16-byte path, else one point
+    int64_t blocks = 1;
+    for (int q = 0; q < a.n_jobs; ++q) {
+        const SynthJob &J = a.jobs[q];
+        const int64_t n = int64_t(J.N[0]) * J.N[1] * J.N[2];
+        const bool quad = (J.N[2] & 3) == 0 && (reinterpret_cast<uintptr_t>(J.out) & 15) == 0;
+        blocks = std::max(blocks, quad ? (n + 1023) / 1024 : (n + 255) / 256);
+    }
+    hipLaunchKernelGGL(k_synthesize, dim3(uint32_t(blocks), a.n_jobs), dim3(256), 0, st, a);
 }
 
 void launch_project(const ProjArgs &a, bool fit, hipStream_t st) {
