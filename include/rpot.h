@@ -289,7 +289,7 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
  *                              frequency tile next to each other, 0 (default)
  *                              the costliest target first.
  *   RP_TUNE_FFT_REG            1 (default): FP32 line passes of length 32, 48,
- *                              64, 96, 128 or 256 run register-resident (each
+ *                              64, 96, 128, 192 or 256 run register-resident (each
  *                              line split over T threads, one LDS exchange);
  *                              0: every line pass stages whole lines in LDS
  *                              (RP_TUNE_FFT_LDS).  FP64 passes always stage.

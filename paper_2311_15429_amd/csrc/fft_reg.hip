@@ -791,7 +791,7 @@ void launch_zinv_reg_p(const ZInv &a, hipStream_t st) {
 int z_threads(int P) {
     switch (P) {
     case 32: return 4;
-    case 64: case 128: return 8;
+    case 64: case 128: case 192: return 8;
     case 256: return 16;
     default: return 0;
     }
@@ -1239,12 +1239,12 @@ bool line_reg_supported(const LinePass &a) {
     if (a.in_j < 0 || a.in_inner < 0 || a.in_outer < 0) return false;
     if (input_extent(a) >= (int64_t(1) << 31)) return false;   // buffer loads with 32-bit offsets
     switch (a.P) {
-    case 32: case 48: case 64: case 96: case 128: case 256: return true;
+    case 32: case 48: case 64: case 96: case 128: case 192: case 256: return true;
     default: return false;
     }
 }
 
-// FP32 z passes in registers: lengths 32, 64, 128, 256, the real data at most half the
+// FP32 z passes in registers: lengths 32, 64, 128, 192, 256, the real data at most half the
 // padded line (Nz <= P / 2), Nz a multiple of 4 T (16-byte vectors), 16-byte
 // aligned arrays, sources only (mode 0) and no per-block maxima (FP16/BF16
 // rings keep the staged pass).  False (nothing launched) otherwise.
@@ -1261,6 +1261,7 @@ bool launch_zfwd_reg(const ZFwd &a, hipStream_t st) {
     case 32: launch_zfwd_reg_p<32, 4>(a, st); break;
     case 64: launch_zfwd_reg_p<64, 8>(a, st); break;
     case 128: launch_zfwd_reg_p<128, 8>(a, st); break;
+    case 192: launch_zfwd_reg_p<192, 8>(a, st); break;
     default: launch_zfwd_reg_p<256, 16>(a, st); break;
     }
     return true;
@@ -1276,6 +1277,7 @@ bool launch_zinv_reg(const ZInv &a, hipStream_t st) {
     case 32: launch_zinv_reg_p<32, 4>(a, st); break;
     case 64: launch_zinv_reg_p<64, 8>(a, st); break;
     case 128: launch_zinv_reg_p<128, 8>(a, st); break;
+    case 192: launch_zinv_reg_p<192, 8>(a, st); break;
     default: launch_zinv_reg_p<256, 16>(a, st); break;
     }
     return true;
@@ -1297,6 +1299,7 @@ bool launch_line_reg(const LinePass &a0, hipStream_t st) {
     case 48: launch_reg_fmt<48, 4>(a, ra, st); break;
     case 64: launch_reg_fmt<64, 8>(a, ra, st); break;
     case 96: launch_reg_fmt<96, 4>(a, ra, st); break;
+    case 192: launch_reg_fmt<192, 8>(a, ra, st); break;
     case 128: launch_reg_fmt<128, 8>(a, ra, st); break;
     default: launch_reg_fmt<256, 16>(a, ra, st); break;
     }

@@ -191,9 +191,10 @@ def test_largest_fft_length(precision, tol):
 
 
 @pytest.mark.parametrize("dims_a,dims_b,pz", [((4, 4, 32), (4, 4, 24), 64), ((8, 8, 16), (8, 8, 16), 32),
-                                              ((4, 4, 64), (4, 4, 64), 128), ((2, 2, 128), (2, 2, 128), 256)])
+                                              ((4, 4, 64), (4, 4, 64), 128), ((2, 2, 128), (2, 2, 128), 256),
+                                              ((2, 3, 96), (3, 2, 64), 192)])
 def test_register_z_passes(dims_a, dims_b, pz):
-    """z passes of lengths 32, 64, 128, 256 in registers (contiguous 16-byte
+    """z passes of lengths 32, 64, 128, 192, 256 in registers (contiguous 16-byte
     loads and stores of both real lines of a complex line; sub-domains whose
     z extent is at most half the pad and a multiple of 4 T), beside a class
     that keeps the staged pass: against the oracle, and against the LDS-staged
@@ -257,7 +258,8 @@ def test_plane_passes(dims_a, dims_b, pad, ring):
 
 
 @pytest.mark.parametrize("dims,pads", [((16, 24, 32), (32, 48, 64)), ((48, 54, 8), (96, 108, 16)),
-                                       ((64, 4, 128), (128, 8, 256)), ((32, 128, 8), (64, 256, 16))])
+                                       ((64, 4, 128), (128, 8, 256)), ((32, 128, 8), (64, 256, 16)),
+                                       ((96, 6, 8), (192, 12, 16))])
 def test_i16_ring_quantised_by_the_x_pass(dims, pads):
     """16-bit integer ring: the register x pass quantises each (tile of 256
     frequencies, component) in the same launch (x lengths 32, 64, 96, 128;
@@ -284,14 +286,15 @@ def test_i16_ring_quantised_by_the_x_pass(dims, pads):
 
 
 @pytest.mark.parametrize("dims,pads", [((16, 24, 32), (32, 48, 64)), ((48, 54, 8), (96, 108, 16)),
-                                       ((64, 4, 128), (128, 8, 256)), ((32, 128, 8), (64, 256, 16))])
+                                       ((64, 4, 128), (128, 8, 256)), ((32, 128, 8), (64, 256, 16)),
+                                       ((96, 6, 8), (192, 12, 16)), ((6, 96, 8), (12, 192, 16))])
 def test_fixed_length_transforms_fp32(dims, pads):
     """Pads that reach every transform length with a compile-time FP32 kernel
-    (x: 32, 64, 96, 128; y: 48, 108, 256; z: 64, 256) and two without one
-    (8, 16).  The register-resident line passes (lengths 32, 48, 64, 96, 128,
-    256) and the LDS-staged passes at the 2048 and 4096 tiles (compile-time
-    kernels) give the oracle's result, and both agree with the run-time
-    kernel of the 6144 tile to FP32 rounding."""
+    (x: 32, 64, 96, 128; y: 48, 108, 256; z: 64, 256) and some without one
+    (8, 12, 16, 192).  The register-resident line passes (lengths 32, 48, 64,
+    96, 128, 192, 256) and the LDS-staged passes at the 2048 and 4096 tiles
+    give the oracle's result, and both agree with the run-time kernel of the
+    6144 tile to FP32 rounding."""
     from paper_2311_15429_amd import plan_for_system
     h = 0.5
     rng = np.random.default_rng(sum(dims))
