@@ -1239,7 +1239,7 @@ bool line_reg_supported(const LinePass &a) {
     if (a.in_j < 0 || a.in_inner < 0 || a.in_outer < 0) return false;
     if (input_extent(a) >= (int64_t(1) << 31)) return false;   // buffer loads with 32-bit offsets
     switch (a.P) {
-    case 32: case 48: case 64: case 96: case 128: case 192: case 256: return true;
+    case 32: case 48: case 64: case 96: case 128: case 144: case 192: case 256: return true;
     default: return false;
     }
 }
@@ -1299,6 +1299,7 @@ bool launch_line_reg(const LinePass &a0, hipStream_t st) {
     case 48: launch_reg_fmt<48, 4>(a, ra, st); break;
     case 64: launch_reg_fmt<64, 8>(a, ra, st); break;
     case 96: launch_reg_fmt<96, 4>(a, ra, st); break;
+    case 144: launch_reg_fmt<144, 4>(a, ra, st); break;
     case 192: launch_reg_fmt<192, 8>(a, ra, st); break;
     case 128: launch_reg_fmt<128, 8>(a, ra, st); break;
     default: launch_reg_fmt<256, 16>(a, ra, st); break;
