@@ -1082,7 +1082,7 @@ def main():
     ap.add_argument("--no-fill", action="store_true",
                     help="scale workload: time from step 1 on instead of after the history fill")
     ap.add_argument("--lagsum-unroll", type=int, default=None, choices=[1, 2, 4])
-    ap.add_argument("--lagsum-steps", type=int, default=8, choices=[1, 2, 4, 8],
+    ap.add_argument("--lagsum-steps", type=int, default=8, choices=[1, 2, 4, 8, 16],
                     help="scale and surrogate workloads: steps of the lag sum per pass over the history (1: "
                          "every step reads the whole history)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default lag-sum schedule")

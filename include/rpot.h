@@ -255,7 +255,7 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
  *                              FP32 plans, 4096 for FP64 plans).  Also per
  *                              shape class (below).
  *   RP_TUNE_LAGSUM_STEPS       steps of the lag sum per pass over the history:
- *                              1 (default), 2, 4 or 8.  The potential of step
+ *                              1 (default), 2, 4, 8 or 16.  The potential of step
  *                              l + i depends on the sources of steps after l
  *                              only through its lags m < i (Eq. "retardation
  *                              space-time sampled lorentz four vector

@@ -604,6 +604,7 @@ static void launch_block_kb(const K2Args &a, int kb, int unroll, int grid_persis
     switch (kb) {
     case 2: launch_block_u<FMT, 2>(a, unroll, grid_persist, st); break;
     case 4: launch_block_u<FMT, 4>(a, unroll, grid_persist, st); break;
+    case 16: launch_block_u<FMT, 16>(a, unroll, grid_persist, st); break;
     default: launch_block_u<FMT, 8>(a, unroll, grid_persist, st); break;
     }
 }
@@ -632,6 +633,7 @@ int lagsum_block_blocks_per_cu(int ring_fmt, int kb, int unroll) {
         };
         if (kb == 2) pu(std::integral_constant<int, 2>{});
         else if (kb == 4) pu(std::integral_constant<int, 4>{});
+        else if (kb == 16) pu(std::integral_constant<int, 16>{});
         else pu(std::integral_constant<int, 8>{});
     };
     switch (ring_fmt) {

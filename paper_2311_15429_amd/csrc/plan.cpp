@@ -2072,8 +2072,8 @@ rp_status rp_set_tuning(rp_plan plan, int32_t knob, int32_t value) {
             if (plan->kb > 1) order_k2b(plan);
             break;
         case RP_TUNE_LAGSUM_STEPS:
-            if (value != 1 && value != 2 && value != 4 && value != 8)
-                fail(RP_ERR_ARG, "lag-sum steps per pass must be 1, 2, 4 or 8");
+            if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+                fail(RP_ERR_ARG, "lag-sum steps per pass must be 1, 2, 4, 8 or 16");
             if (plan->ws) fail(RP_ERR_STATE, "choose the lag-sum steps per pass before rp_bind_workspace");
             if (value > 1 && plan->p64) fail(RP_ERR_UNSUPPORTED, "blocked lag-sum steps need an FP32 plan");
             plan->kb = value;

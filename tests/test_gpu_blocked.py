@@ -16,7 +16,8 @@ torch = pytest.importorskip("torch")
 
 
 @pytest.mark.parametrize("precision,kb,tol", [("fp32", 2, 2e-5), ("fp32", 4, 2e-5), ("fp32", 8, 2e-5),
-                                               ("fp32_ring_i16", 8, 1e-4)])
+                                               ("fp32", 16, 2e-5), ("fp32_ring_i16", 8, 1e-4),
+                                               ("fp32_ring_i16", 16, 1e-4)])
 def test_blocked_steps_match_the_oracle_at_every_step(precision, kb, tol):
     from test_gpu_parity import _uneven_system
     s = _uneven_system(8)
@@ -145,17 +146,18 @@ def test_blocked_steps_state_rules():
 
 
 @pytest.mark.timeout(900)
-def test_blocked_steps_config2_full_size_past_the_deepest_lag():
-    """Config 2 in FP32 with 8 steps per pass: sampled points of every domain
-    at steps of every phase, the last ones past the deepest lag."""
+@pytest.mark.parametrize("kb", [8, 16])
+def test_blocked_steps_config2_full_size_past_the_deepest_lag(kb):
+    """Config 2 in FP32 with 8 or 16 steps per pass: sampled points of every
+    domain at steps of many phases, the last ones past the deepest lag."""
     from paper_2311_15429_amd import plan_for_system
     from gpu_helpers import cpu_sample_fn
     system = sy.config2(0)
-    steps_out = [43, 230, 383, 386, 390, 401]            # phases 2, 5, 6, 1, 5, 0
+    steps_out = [43, 230, 383, 386, 390, 401]            # phases 2, 5, 6, 1, 5, 0 (of 8)
     rng = np.random.default_rng(11)
     picks = {s: pick_points(d.dims, 24, rng) for s, d in enumerate(system.domains)}
     plan = plan_for_system(system, "fp32", stream=torch.cuda.current_stream())
-    plan.set_tuning("lagsum_steps", 8)
+    plan.set_tuning("lagsum_steps", kb)
     plan.bind()
     plan.set_green_kernels()
     gen = GpuSourceGen(system, plan.dtype)
@@ -174,5 +176,5 @@ def test_blocked_steps_config2_full_size_past_the_deepest_lag():
         ref = [oracle.potential_points(system, s, picks[s], l, fn).T for s in range(8)]
         g, r = np.concatenate(got[l], axis=1), np.concatenate(ref, axis=1)
         e = np.max(np.abs(g - r), axis=1) / np.max(np.abs(r), axis=1)
-        log(f"  blocked x8, step {l} (phase {(l - 1) % 8}): max rel err " + " ".join(f"{x:.2e}" for x in e))
+        log(f"  blocked x{kb}, step {l} (phase {(l - 1) % kb}): max rel err " + " ".join(f"{x:.2e}" for x in e))
         assert np.all(e <= 2e-5), (l, e)
