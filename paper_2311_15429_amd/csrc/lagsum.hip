@@ -380,7 +380,6 @@ __device__ __forceinline__ void block_src(const K2Args &a, const K2Src &R, const
             for (int v = 0; v < U; ++v) {
                 if (t0 + u0 + v < n_it) {
                     gw[(u0 + v + KB - 1) % KB] = gn[v];   // replaces lag d0 + t - 1
-                    // opaque per snapshot, so the branch is not hoisted out of the walk
                     if constexpr (REAL) {
 #pragma unroll
                         for (int i = 0; i < KB; ++i) {
