@@ -17,7 +17,8 @@ least one of them:
   space-time sampled lorentz four vector potential" with the sampled Green's
   function of Eq. "retardation space-time sampled green interpolation") on
   tiny inputs, a different formula from the oracle's interpolated direct sum;
-* step response -> static Coulomb sum; static + dynamic split; exact symmetries.
+* step response -> static Coulomb sum; static + dynamic split; exact symmetries;
+  the self pair's sampled kernel is even, so its padded DFT is real.
 """
 import math
 
@@ -264,6 +265,42 @@ def test_oracle_equals_lag_sum_bruteforce():
     # the history really is retarded: early steps differ from the instantaneous sum
     inst = oracle.potential_full(System(h, dt, math.inf, doms), S, [L])
     assert np.max(np.abs(inst[0][1] - got[L][1])) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("c,dt", [(C_AU, 0.002), (10.0, 0.03)])
+def test_self_pair_kernel_is_even_so_its_spectrum_is_real(c, dt):
+    """The sampled Green's function of a domain on itself at every lag m (the
+    response at step m + 1 to a unit source difference at step 1 in the centre
+    point, self cell included) is even under r -> -r, so its DFT on a padded
+    grid (offset r at index r mod P) is real: the FP32 path keeps only the real
+    parts of the self pairs' spectra."""
+    h, n, P = 0.25, 9, 20
+    dom = centred((0.0, 0.0, 0.0), n, h)
+    sy = System(h, dt, c, [dom])
+    L = 12
+    centre = (n // 2) * (n * n + n + 1)
+    S = np.zeros((L + 1, 4, dom.n_points))
+    S[1, 0, centre] = 1.0
+    got = oracle.potential_full(sy, [S], range(2, L + 1))
+    nonzero = 0
+    for l, per in zip(range(2, L + 1), got):
+        g = per[0][0].reshape(n, n, n)
+        scale = np.max(np.abs(g))
+        if scale == 0.0:
+            continue
+        nonzero += 1
+        for axes in ((0,), (1,), (2,), (0, 1, 2)):
+            np.testing.assert_allclose(g, np.flip(g, axis=axes), rtol=0, atol=1e-14 * scale)
+        pad = np.zeros((P, P, P))
+        idx = (np.arange(n) - n // 2) % P
+        pad[np.ix_(idx, idx, idx)] = g
+        spec = np.fft.fftn(pad)
+        assert np.max(np.abs(spec.imag)) <= 1e-13 * np.max(np.abs(spec.real)), l
+        # a kernel shifted off the centre (a cross pair) is not even
+        shifted = np.fft.fftn(np.roll(pad, 1, axis=0))
+        assert np.max(np.abs(shifted.imag)) > 1e-3 * np.max(np.abs(shifted.real))
+    assert nonzero >= 3
 
 
 # ---------------------------------------------------------------------------
