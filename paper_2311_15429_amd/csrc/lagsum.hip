@@ -349,7 +349,11 @@ __device__ __forceinline__ void block_src(const K2Args &a, const K2Src &R, const
     for (int j = 0; j < KB - 1; ++j) gw[j] = load_g(d0 + j);
     gw[KB - 1] = {0.f, 0.f};
 
-    for (int t0 = 0; t0 < n_it; t0 += KB) {
+    // one chunk of KB snapshots from t0.  HEAD: the first chunk of a walk
+    // that starts kb - 1 ages below its window, where snapshot t feeds steps
+    // i >= kb - 1 - t only; the skipped products are known at compile time.
+    auto chunk = [&](int t0, auto head_tag) {
+        constexpr bool HEAD = decltype(head_tag)::value;
 #pragma unroll
         for (int u0 = 0; u0 < KB; u0 += U) {
             if (t0 + u0 >= n_it) break;
@@ -383,6 +387,7 @@ __device__ __forceinline__ void block_src(const K2Args &a, const K2Src &R, const
                     if constexpr (REAL) {
 #pragma unroll
                         for (int i = 0; i < KB; ++i) {
+                            if (HEAD && i < KB - 1 - (u0 + v)) continue;
                             const float gx = gw[(u0 + v + i) % KB].x;
 #pragma unroll
                             for (int mu = 0; mu < 4; ++mu) {
@@ -393,6 +398,7 @@ __device__ __forceinline__ void block_src(const K2Args &a, const K2Src &R, const
                     } else {
 #pragma unroll
                         for (int i = 0; i < KB; ++i) {
+                            if (HEAD && i < KB - 1 - (u0 + v)) continue;
                             const Cx<float> gv = gw[(u0 + v + i) % KB];
 #pragma unroll
                             for (int mu = 0; mu < 4; ++mu) {
@@ -406,7 +412,13 @@ __device__ __forceinline__ void block_src(const K2Args &a, const K2Src &R, const
                 }
             }
         }
+    };
+    int t0 = 0;
+    if (m_lo - d0 == KB - 1) {
+        chunk(0, std::true_type{});
+        t0 = KB;
     }
+    for (; t0 < n_it; t0 += KB) chunk(t0, std::false_type{});
 }
 
 template <int FMT, int KB, int U, int AUX>
