@@ -224,13 +224,13 @@ def test_register_z_passes(dims_a, dims_b, pz):
 
 @pytest.mark.parametrize("dims_a,dims_b,pad", [((5, 48, 48), (3, 47, 44), 96), ((4, 32, 32), (2, 31, 28), 64),
                                                ((2, 64, 64), (3, 60, 40), 128), ((3, 16, 16), (2, 15, 12), 32),
-                                               ((2, 24, 24), (2, 23, 20), 48)])
+                                               ((2, 24, 24), (2, 23, 20), 48), ((2, 16, 16), (3, 1, 4), 32)])
 @pytest.mark.parametrize("ring", ["fp32", "fp32_ring_fp16"])
 def test_plane_passes(dims_a, dims_b, pad, ring):
     """The z and y transforms of an x slice and component in one launch
     (forward: sources to the y-transformed array; inverse: back to the cropped
     potentials), pads 32 to 128, an odd y extent and a z extent below half the
-    pad in the second domain.  With the scaled FP16 ring the forward passes stay
+    pad in the second domain (down to one y row and four z points).  With the scaled FP16 ring the forward passes stay
     separate (per-block maxima) and the inverse ones are fused.  Against the
     oracle, and against the separate passes to FP32 rounding."""
     from paper_2311_15429_amd import plan_for_system
