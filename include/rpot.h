@@ -299,8 +299,7 @@ rp_status rp_lagsum_time(rp_plan plan, double *total_ms, int64_t *launches);
  *                              one launch per x slice and component, the z
  *                              transform kept in LDS between them, where the
  *                              grid is at most half the pad in y and z and Nz
- *                              is a multiple of 4 (scaled FP16/BF16 rings keep
- *                              the separate forward passes); 0: separate passes.
+ *                              is a multiple of 4; 0: separate passes.
  * Setting a knob discards a captured step (rp_capture_step).
  */
 enum { RP_TUNE_LAGSUM_UNROLL = 1, RP_TUNE_LAGSUM_PERSISTENT = 2, RP_TUNE_FFT_LDS = 4, RP_TUNE_LAGSUM_STEPS = 8,

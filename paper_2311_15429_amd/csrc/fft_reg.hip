@@ -817,6 +817,7 @@ struct PlaneJob {
     const int32_t *store_head;
     int32_t src_depth, src_lag;
     Cf *yout;                  // forward: [Nx][P][Hz][4]
+    float *zmax;               // forward: largest |Re|, |Im| of dS per (x, component), [Nx][4], or null
     const Cf *yin;             // inverse: [Nx][P][Hz][4]
     float *out;                // inverse: [4][Nx][Ny][Nz]
     const float *add;          // inverse: added to the output (same layout), or null
@@ -843,6 +844,7 @@ __global__ __launch_bounds__(256) void k_zy_fwd(PlanePass a) {
     static_assert(P / 4 <= ZL && ZL * T <= NT, "the z rows of a slice exceed one round of threads");
     __shared__ Cf buf[HZ * RS];
     __shared__ Cf twl[P];
+    __shared__ float red[NT / 64];
     const PlaneJob &job = a.jobs[blockIdx.y];
     const int tid = threadIdx.x;
     for (int i = tid; i < P; i += NT) twl[i] = reinterpret_cast<const Cf *>(a.tw)[i];
@@ -851,6 +853,7 @@ __global__ __launch_bounds__(256) void k_zy_fwd(PlanePass a) {
     const int Nx = a.Nx, Ny = a.Ny, Nz = a.Nz, NZL = (Ny + 1) / 2;
     const int64_t npts = int64_t(Nx) * Ny * Nz;
     const int64_t slab = (int64_t(mu) * Nx + x) * Ny * Nz;
+    float mx = 0.f;   // largest |dS| of the slab (scaled 16-bit float rings)
     // dS = S - S0 of rows y = 2p (real parts) and 2p + 1 (imaginary parts)
     // into z row p, four z at a time (16-byte vectors, Nz % 4 == 0); a missing
     // odd last row reads as zeros
@@ -892,11 +895,19 @@ __global__ __launch_bounds__(256) void k_zy_fwd(PlanePass a) {
                     if (2 * p + 1 < Ny) *reinterpret_cast<float4 *>(St + o + Nz) = vb[j];
                 }
                 Cf *r = buf + p * RS + z;
-                r[0] = Cf{va[j].x - qa[j].x, vb[j].x - qb[j].x};
-                r[1] = Cf{va[j].y - qa[j].y, vb[j].y - qb[j].y};
-                r[2] = Cf{va[j].z - qa[j].z, vb[j].z - qb[j].z};
-                r[3] = Cf{va[j].w - qa[j].w, vb[j].w - qb[j].w};
+                const Cf d0 = {va[j].x - qa[j].x, vb[j].x - qb[j].x}, d1 = {va[j].y - qa[j].y, vb[j].y - qb[j].y};
+                const Cf d2 = {va[j].z - qa[j].z, vb[j].z - qb[j].z}, d3 = {va[j].w - qa[j].w, vb[j].w - qb[j].w};
+                r[0] = d0;
+                r[1] = d1;
+                r[2] = d2;
+                r[3] = d3;
+                mx = fmaxf(mx, fmaxf(fmaxf(fabsf(d0.x), fabsf(d0.y)), fmaxf(fabsf(d1.x), fabsf(d1.y))));
+                mx = fmaxf(mx, fmaxf(fmaxf(fabsf(d2.x), fabsf(d2.y)), fmaxf(fabsf(d3.x), fabsf(d3.y))));
             }
+        }
+        if (job.zmax) {
+            for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+            if ((tid & 63) == 0) red[tid >> 6] = mx;
         }
         // zeros: z in [Nz, P / 2) of every row
         const int nzero = H - Nz;
@@ -906,6 +917,11 @@ __global__ __launch_bounds__(256) void k_zy_fwd(PlanePass a) {
         }
     }
     __syncthreads();
+    if (job.zmax && tid == 0) {
+        float m = red[0];
+        for (int w = 1; w < NT / 64; ++w) m = fmaxf(m, red[w]);
+        job.zmax[x * 4 + mu] = m;
+    }
     // z transforms (input z < P / 2), natural order back into the rows
     {
         const int li = tid % ZL, t = tid / ZL;
@@ -1313,9 +1329,10 @@ bool plane_shape(int Py, int Pz, int Ny, int Nz) {
 
 // Forward z and y passes of the same jobs as one plane pass.  False (nothing
 // launched) where it does not apply: other lengths, unequal z and y pads, Ny
-// or Nz above P / 2, Nz not a multiple of 4, per-block maxima (the scaled
-// 16-bit float rings), Green's functions, misaligned arrays, or a y pass of
-// another layout than [Nx][Ny][Hz][4] -> [Nx][P][Hz][4].
+// or Nz above P / 2, Nz not a multiple of 4, Green's functions, misaligned
+// arrays, or a y pass of another layout than [Nx][Ny][Hz][4] -> [Nx][P][Hz][4].
+// A job's zmax (scaled 16-bit float rings) receives one maximum per
+// (x, component), Nx blocks of 4: the caller sizes it and the ring scales.
 bool launch_zy_fwd_plane(const ZFwd &z, const LinePass &y, hipStream_t st) {
     const int P = z.Pz;
     if (z.mode != 0 || !plane_shape(z.Py, P, z.Ny, z.Nz) || y.P != P || z.Hz != P / 2 + 1 || z.Nx < 1) return false;
@@ -1333,7 +1350,7 @@ bool launch_zy_fwd_plane(const ZFwd &z, const LinePass &y, hipStream_t st) {
     for (int j = 0; j < z.n_jobs; ++j) {
         const ZFwdJob &J = z.jobs[j];
         const LineJob &Y = y.jobs[j];
-        if (J.zmax || Y.in != J.out || Y.tile_stride != 0 || Y.head || Y.qscale) return false;
+        if (Y.in != J.out || Y.tile_stride != 0 || Y.head || Y.qscale) return false;
         if (!aligned16(J.src) || !aligned16(J.s0) || !aligned16(J.store) || reinterpret_cast<uintptr_t>(Y.out) % 8)
             return false;
         PlaneJob &Q = pp.jobs[j];
@@ -1345,6 +1362,7 @@ bool launch_zy_fwd_plane(const ZFwd &z, const LinePass &y, hipStream_t st) {
         Q.store = static_cast<float *>(J.store);
         Q.store_head = J.store_head;
         Q.yout = static_cast<Cf *>(Y.out);
+        Q.zmax = J.zmax;
     }
     launch_plane_p(P, pp, true, st);
     return true;

@@ -634,7 +634,8 @@ void plan_layout(rp_plan p) {
         const size_t t2 = size_t(d.N[0]) * S.P[1] * S.Hz * 4;
         d.off_ring = alloc(size_t(d.depth) * S.Cpad * 4 * p->ring_esz);
         d.off_scales = quant ? alloc(scale_bytes(p, d.depth, S.Cpad)) : 0;
-        d.off_zmax = zq ? alloc(size_t(d.zblocks) * 4 * sizeof(float)) : 0;
+        // per-block maxima of the staged z pass, or one per x slice of the plane pass
+        d.off_zmax = zq ? alloc(size_t(std::max(d.zblocks, d.N[0])) * 4 * sizeof(float)) : 0;
         d.off_s0 = alloc(size_t(4) * d.npts * p->tsz);
         d.off_p0 = alloc(size_t(4) * d.npts * p->tsz);
         d.off_acc = alloc(size_t(p->kb) * size_t(S.C) * 4 * p->csz);   // kb accumulator sets
@@ -652,7 +653,7 @@ void plan_layout(rp_plan p) {
         const SystemP &S = p->sys[d.sys];
         v.off_ring = alloc(size_t(v.W) * S.Cpad * 4 * p->ring_esz);
         v.off_scales = quant ? alloc(scale_bytes(p, v.W, S.Cpad)) : 0;
-        v.off_zmax = zq ? alloc(size_t(d.zblocks) * 4 * sizeof(float)) : 0;
+        v.off_zmax = zq ? alloc(size_t(std::max(d.zblocks, d.N[0])) * 4 * sizeof(float)) : 0;
         v.off_t1 = alloc(size_t(d.N[0]) * d.N[1] * S.Hz * 4 * p->csz);
         v.off_t2 = alloc(size_t(d.N[0]) * S.P[1] * S.Hz * 4 * p->csz);
         v.off_stage = p->hist_host ? alloc(size_t(4) * d.npts * p->tsz) : 0;
@@ -804,11 +805,9 @@ void plan_stats(rp_plan p) {
         const double ring = double(S.C) * 4 * p->ring_esz;
         const double acc = double(S.C) * 4 * p->csz;
         const double real = double(d.npts) * 4 * p->tsz;
-        // plane passes keep the z-transformed array (t1) in LDS; the forward
-        // ones do not run with the scaled 16-bit float rings
+        // plane passes keep the z-transformed array (t1) in LDS
         const bool pl = plane_ok(p) && plane_shape(S.P[1], S.P[2], d.N[1], d.N[2]);
-        const bool plf = pl && !(p->ring_fmt == RING_F16 || p->ring_fmt == RING_BF16);
-        const double fwd = 2 * real + (plf ? 0.0 : t1 + t1) + t2 + t2 + ring;
+        const double fwd = 2 * real + (pl ? 0.0 : t1 + t1) + t2 + t2 + ring;
         st.fft_bytes_fwd += fwd;
         st.fft_bytes_inv += acc + t2 + t2 + (pl ? 0.0 : t1 + t1) + 2 * real;
         // a split history also stores the sources, and transforms them again per extra ring
@@ -1365,7 +1364,11 @@ void enqueue_ring_jobs(rp_plan p, const ClassP &K, const std::vector<RingJob> &j
                 sa.jobs[j].npts = double(d.npts);
             }
         }
-        if (!(plane_ok(p) && launch_zy_fwd_plane(z, y, st))) {
+        if (plane_ok(p) && launch_zy_fwd_plane(z, y, st)) {
+            // the plane pass wrote one maximum per x slice and component
+            for (int j = 0; j < sa.n_jobs; ++j) sa.jobs[j].nblk = K.N[0];
+            launch_ring_scale(sa, st);
+        } else {
             launch_zfwd(z, p->p64, st);
             launch_ring_scale(sa, st);
             launch_line_pass(y, p->p64, st);

@@ -230,9 +230,11 @@ def test_plane_passes(dims_a, dims_b, pad, ring):
     """The z and y transforms of an x slice and component in one launch
     (forward: sources to the y-transformed array; inverse: back to the cropped
     potentials), pads 32 to 128, an odd y extent and a z extent below half the
-    pad in the second domain (down to one y row and four z points).  With the scaled FP16 ring the forward passes stay
-    separate (per-block maxima) and the inverse ones are fused.  Against the
-    oracle, and against the separate passes to FP32 rounding."""
+    pad in the second domain (down to one y row and four z points).  With the
+    scaled FP16 ring the forward pass also gives one maximum per x slice and
+    component for the ring scales.  Against the oracle, and against the
+    separate passes: to FP32 rounding (FP32 ring), and within the FP16 ring's
+    quantisation of inputs that differ by FP32 rounding."""
     from paper_2311_15429_amd import plan_for_system
     h = 0.5
     rng = np.random.default_rng(pad + len(ring))
@@ -252,9 +254,10 @@ def test_plane_passes(dims_a, dims_b, pad, ring):
     bar = FP32_TOL if ring == "fp32" else 2e-4
     log(f"plane passes, pad {pad}, {ring}: vs oracle {np.array2string(e, precision=2)}")
     assert np.all(e <= bar), e
+    agree = 2e-6 if ring == "fp32" else 1e-4
     for l in range(L + 1):
         d = rel_err(plane[l], sep[l]) if np.any(sep[l][0]) else np.zeros(4)
-        assert np.all(d <= 2e-6), (l, d)
+        assert np.all(d <= agree), (l, d)
 
 
 @pytest.mark.parametrize("dims,pads", [((16, 24, 32), (32, 48, 64)), ((48, 54, 8), (96, 108, 16)),
