@@ -408,7 +408,8 @@ void sur_layout(rp_plan p, size_t &off) {
         U.slot_Cpad = std::max(U.slot_Cpad, S.Cpad);
         t1 = std::max(t1, size_t(d.N[0]) * d.N[1] * S.Hz * 4 * p->csz);
         t2 = std::max(t2, size_t(d.N[0]) * S.P[1] * S.Hz * 4 * p->csz);
-        zb = std::max(zb, size_t(d.zblocks) * 4 * sizeof(float));
+        // per-block maxima of the staged z pass, or one per x slice of the plane pass
+        zb = std::max(zb, size_t(std::max(d.zblocks, d.N[0])) * 4 * sizeof(float));
     }
     if (U.slot_W == 0) return;
     const bool quant = ring_scaled(p);
