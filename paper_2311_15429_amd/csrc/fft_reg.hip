@@ -315,7 +315,12 @@ template <int P, int T, int FMT, int DIR, bool HALF, int AF = 0>
 __global__ __launch_bounds__(256) void k_line_reg(LinePass a, RegArgs ra) {
     constexpr int E = P / T;
     constexpr int L = 256 / T;
-    constexpr int RS = P + 1;   // odd LDS row stride
+    // odd LDS row stride; P + 3 rather than P + 1 spreads the exchange writes
+    // of lines grouped by four (the inverse x pass: the four components of a
+    // frequency on neighbouring lanes) over twice as many banks (length 96:
+    // 1.5 instead of 4.4 conflict cycles per LDS instruction), at the same
+    // blocks per CU
+    constexpr int RS = P + 3;
     constexpr bool HALF_IN = HALF && DIR < 0, HALF_OUT = HALF && DIR > 0;
     static_assert(E % T == 0 && L % 4 == 0 && E % 2 == 0 && T % 2 == 0, "line split P = T x E");
     __shared__ Cf buf[L * RS];
