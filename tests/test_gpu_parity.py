@@ -291,11 +291,12 @@ def test_i16_ring_quantised_by_the_x_pass(dims, pads):
 @pytest.mark.parametrize("dims,pads", [((16, 24, 32), (32, 48, 64)), ((48, 54, 8), (96, 108, 16)),
                                        ((64, 4, 128), (128, 8, 256)), ((32, 128, 8), (64, 256, 16)),
                                        ((96, 6, 8), (192, 12, 16)), ((6, 96, 8), (12, 192, 16)),
-                                       ((72, 6, 8), (144, 12, 16))])
+                                       ((72, 6, 8), (144, 12, 16)), ((24, 6, 8), (48, 12, 16)),
+                                       ((128, 6, 8), (256, 12, 16))])
 def test_fixed_length_transforms_fp32(dims, pads):
     """Pads that reach every transform length with a compile-time FP32 kernel
-    (x: 32, 64, 96, 128; y: 48, 108, 256; z: 64, 256) and some without one
-    (8, 12, 16, 144, 192).  The register-resident line passes (lengths 32, 48,
+    (x: 32, 48, 64, 96, 128, 256; y: 48, 108, 256; z: 64, 256) and some without
+    one (8, 12, 16, 144, 192).  The register-resident line passes (lengths 32, 48,
     64, 96, 128, 144, 192, 256) and the LDS-staged passes at the 2048 and 4096 tiles
     give the oracle's result, and both agree with the run-time kernel of the
     6144 tile to FP32 rounding."""
