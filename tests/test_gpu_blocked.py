@@ -85,6 +85,44 @@ def test_fused_additions_every_ring_format(precision, tol):
     log(f"{precision}, fused additions: vs oracle {worst:.2e}, vs one step per pass {worst_d:.2e}")
 
 
+@pytest.mark.parametrize("dims,pad", [((72, 6, 8), 144), ((96, 6, 8), 192)])
+def test_fused_additions_at_the_lengths_of_the_batched_recipe(dims, pad):
+    """x-lines of 144 and 192 frequencies (pads of the larger grids of the
+    batched recipe), which cross the 256-frequency tiles: 8 steps per pass
+    with the own lags added by the inverse x pass, every step against the
+    oracle and against one step per pass (FP32)."""
+    from paper_2311_15429_amd import plan_for_system
+    rng = np.random.default_rng(11)
+    h = 0.5
+    doms = [sy.Domain(dims, np.array([0.0, 0.0, 0.0])), sy.Domain(dims, np.array([-4.0, 40.0, 3.0]))]
+    for d in doms:
+        lo = d.origin
+        hi = d.origin + h * (np.array(d.dims) - 1)
+        for _ in range(2):
+            d.charges.append(sy.Charge("pair", rng.uniform(0.8, 1.5), rng.uniform(lo, hi), rng.uniform(lo, hi),
+                                       ("cos", rng.uniform(0.1, 1), rng.uniform(0.1, 0.5), rng.uniform(0, 6.28))))
+    s = sy.System(h, 0.02, sy.C_AU, doms, name=f"x pad {pad}")
+    p = plan_for_system(s, "fp32")
+    p.set_tuning("lagsum_steps", 8)
+    assert p.stats()["fused_additions"] == 1
+    assert p.info(0, 0)[2][0] == pad and p.info(1, 1)[2][0] == pad
+    assert min(p.info(0, 1)[0], p.info(1, 0)[0]) >= 7
+    p.close()
+    L = 2 * 8 + 5
+    S = sy.sample_sources(s, range(L + 1))
+    got = run_gpu(s, "fp32", S, tune={"lagsum_steps": 8})
+    plain = run_gpu(s, "fp32", S)
+    ref = oracle.potential_full(s, S, range(L + 1))
+    worst, worst_d = 0.0, 0.0
+    for l in range(L + 1):
+        e = rel_err(got[l], ref[l])
+        d = rel_err(got[l], plain[l])
+        worst, worst_d = max(worst, float(e.max())), max(worst_d, float(d.max()))
+        assert np.all(e <= 2e-5), (l, e)
+        assert np.all(d <= 5e-6), (l, d)
+    log(f"x pad {pad}, fused additions: vs oracle {worst:.2e}, vs one step per pass {worst_d:.2e}")
+
+
 def test_blocked_steps_graph_replays_interleaved_with_eager_steps():
     """Batched systems, persistent blocked pass, one graph per phase: replays
     and eager steps in an irregular order, each step against the oracle."""
